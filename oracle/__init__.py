@@ -1,0 +1,245 @@
+"""FP64 CPU oracle for the BatchLayout force step (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product (the HIP library and its
+Python binding) never imports, links or executes anything here.
+
+The arithmetic lives in ``bl_oracle.c`` (plain C, FP64, compiled with
+``-O2 -fno-fast-math -ffp-contract=off``); this module only marshals numpy
+arrays through ctypes.  Every function cites the passage of the paper it
+follows in the C source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bl_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    lib = C.CDLL(_LIB_PATH)
+    lib.orc_forces_exact.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int,
+                                     C.c_double, C.c_double, C.c_int,
+                                     _f64p, _f64p, _f64p, _f64p, _f64p]
+    lib.orc_step_at.argtypes = [C.c_double, C.c_double, C.c_int]
+    lib.orc_step_at.restype = C.c_double
+    lib.orc_layout_exact.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
+                                     C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                     C.c_int, _f64p]
+    lib.orc_tree_build.argtypes = [C.c_int, _f64p, _f64p]
+    lib.orc_tree_build.restype = C.c_void_p
+    lib.orc_tree_free.argtypes = [C.c_void_p]
+    lib.orc_tree_nnodes.argtypes = [C.c_void_p]
+    lib.orc_tree_width.argtypes = [C.c_void_p]
+    lib.orc_tree_width.restype = C.c_double
+    lib.orc_tree_node.argtypes = [C.c_void_p, C.c_int] + [C.POINTER(C.c_int)] * 4 + \
+        [C.POINTER(C.c_int * 4), C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.orc_tree_order.argtypes = [C.c_void_p, _i32p, _u32p]
+    lib.orc_forces_bh.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_void_p, C.c_int, C.c_int,
+                                  C.c_double, C.c_double, C.c_double, C.c_int,
+                                  _f64p, _f64p, _f64p, _f64p, _f64p, _i64p, _i32p]
+    lib.orc_layout_bh.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
+                                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                  C.c_int, C.c_int, _f64p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(C.c_long)]
+    lib.orc_edge_energy.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_double]
+    lib.orc_edge_energy.restype = C.c_double
+    lib.orc_edge_uniformity.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p]
+    lib.orc_edge_uniformity.restype = C.c_double
+    lib.orc_stress.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_void_p,
+                               C.POINTER(C.c_double)]
+    lib.orc_stress.restype = C.c_double
+    _lib = lib
+    return lib
+
+
+def _csr(rowptr, colidx):
+    return (np.ascontiguousarray(rowptr, dtype=np.int32),
+            np.ascontiguousarray(colidx if len(colidx) else np.zeros(1, np.int32), dtype=np.int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Forces:
+    """Per-vertex attraction (ax, ay), repulsion (rx, ry), scale S_i = sum |term|."""
+
+    def __init__(self, ax, ay, rx, ry, scale, visits=None, near_tie=None):
+        self.ax, self.ay, self.rx, self.ry, self.scale = ax, ay, rx, ry, scale
+        self.visits, self.near_tie = visits, near_tie
+
+    @property
+    def fx(self):
+        return self.ax + self.rx
+
+    @property
+    def fy(self):
+        return self.ay + self.ry
+
+
+def step_at(step0: float, decay: float, k: int) -> float:
+    """Step length at iteration k (step0 times decay, once per finished iteration)."""
+    return _load().orc_step_at(step0, decay, k)
+
+
+def forces_exact(rowptr, colidx, x, y, i0, i1, K=1.0, R=1.0, repulse_adjacent=True) -> Forces:
+    """Exact net forces on vertices [i0, i1) from coordinates (x, y) (Sec. 2.2; Alg. 2)."""
+    lib = _load()
+    rp, ci = _csr(rowptr, colidx)
+    n = len(rp) - 1
+    m = i1 - i0
+    out = [np.zeros(max(m, 1)) for _ in range(5)]
+    rc = lib.orc_forces_exact(n, rp, ci, _f64(x), _f64(y), i0, i1, K, R, int(repulse_adjacent), *out)
+    if rc != 0:
+        raise ValueError("orc_forces_exact: bad arguments")
+    return Forces(*[o[:m] for o in out])
+
+
+def layout_exact(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=0.999,
+                 K=1.0, R=1.0, repulse_adjacent=True, stop_batch=-1):
+    """Exact BatchLayout (Alg. 2 semantics).  Returns (x, y, energy per iteration)."""
+    lib = _load()
+    rp, ci = _csr(rowptr, colidx)
+    n = len(rp) - 1
+    x = _f64(x0).copy()
+    y = _f64(y0).copy()
+    e = np.zeros(max(iters, 1))
+    rc = lib.orc_layout_exact(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R,
+                              int(repulse_adjacent), stop_batch, e)
+    if rc != 0:
+        raise ValueError("orc_layout_exact failed (%d)" % rc)
+    return x, y, e[:iters]
+
+
+class Tree:
+    """Quadtree of a snapshot (Alg. S1) built by the oracle."""
+
+    def __init__(self, sx, sy):
+        self._lib = _load()
+        self.n = len(sx)
+        self.h = self._lib.orc_tree_build(self.n, _f64(sx), _f64(sy))
+        if not self.h:
+            raise ValueError("orc_tree_build failed")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self._lib.orc_tree_free(self.h)
+            self.h = None
+
+    @property
+    def width(self):
+        return self._lib.orc_tree_width(self.h)
+
+    def nodes(self):
+        out = []
+        lv, lo, hi, nc, bk = (C.c_int() for _ in range(5))
+        ch = (C.c_int * 4)()
+        cx, cy = C.c_double(), C.c_double()
+        for i in range(self._lib.orc_tree_nnodes(self.h)):
+            self._lib.orc_tree_node(self.h, i, C.byref(lv), C.byref(lo), C.byref(hi), C.byref(nc),
+                                    C.byref(ch), C.byref(bk), C.byref(cx), C.byref(cy))
+            out.append(dict(level=lv.value, lo=lo.value, hi=hi.value, children=list(ch)[:nc.value],
+                            bucket=bool(bk.value), cx=cx.value, cy=cy.value))
+        return out
+
+    def order(self):
+        order = np.zeros(self.n, np.int32)
+        keys = np.zeros(self.n, np.uint32)
+        self._lib.orc_tree_order(self.h, order, keys)
+        return order, keys
+
+
+def forces_bh(rowptr, colidx, x, y, tree: Tree, i0, i1, K=1.0, R=1.0, theta=1.2,
+              leaf_live=True) -> Forces:
+    """Barnes-Hut forces on [i0, i1): CSR attraction + tree repulsion (Alg. S2, S3)."""
+    lib = _load()
+    rp, ci = _csr(rowptr, colidx)
+    n = len(rp) - 1
+    m = i1 - i0
+    out = [np.zeros(max(m, 1)) for _ in range(5)]
+    vis = np.zeros(max(m, 1), np.int64)
+    tie = np.zeros(max(m, 1), np.int32)
+    rc = lib.orc_forces_bh(n, rp, ci, _f64(x), _f64(y), tree.h, i0, i1, K, R, theta,
+                           int(leaf_live), *out, vis, tie)
+    if rc != 0:
+        raise ValueError("orc_forces_bh: bad arguments")
+    return Forces(*[o[:m] for o in out], visits=vis[:m], near_tie=tie[:m].astype(bool))
+
+
+def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=0.999,
+              K=1.0, R=1.0, theta=1.2, leaf_live=True, stop_batch=-1, want_snapshot=False):
+    """BatchLayoutBH (Alg. S3 with the step decay of Alg. 2).
+
+    Returns (x, y, energy, visits) or, with want_snapshot, also the snapshot
+    (sx, sy) taken at the start of the last iteration."""
+    lib = _load()
+    rp, ci = _csr(rowptr, colidx)
+    n = len(rp) - 1
+    x = _f64(x0).copy()
+    y = _f64(y0).copy()
+    e = np.zeros(max(iters, 1))
+    sx = np.zeros(n)
+    sy = np.zeros(n)
+    vt = C.c_long(0)
+    rc = lib.orc_layout_bh(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R, theta,
+                           int(leaf_live), stop_batch, e,
+                           sx.ctypes.data_as(C.c_void_p) if want_snapshot else None,
+                           sy.ctypes.data_as(C.c_void_p) if want_snapshot else None,
+                           C.byref(vt))
+    if rc != 0:
+        raise ValueError("orc_layout_bh failed (%d)" % rc)
+    if want_snapshot:
+        return x, y, e[:iters], vt.value, sx, sy
+    return x, y, e[:iters], vt.value
+
+
+def edge_energy(rowptr, colidx, x, y, K=1.0) -> float:
+    """Sum over undirected edges of d^3/(3K), the attractive potential."""
+    rp, ci = _csr(rowptr, colidx)
+    return _load().orc_edge_energy(len(rp) - 1, rp, ci, _f64(x), _f64(y), K)
+
+
+def edge_uniformity(rowptr, colidx, x, y) -> float:
+    """Normalised standard deviation of edge lengths (Sec. 3.7)."""
+    rp, ci = _csr(rowptr, colidx)
+    return _load().orc_edge_uniformity(len(rp) - 1, rp, ci, _f64(x), _f64(y))
+
+
+def stress(rowptr, colidx, x, y, pivots=None):
+    """Stress after optimal uniform scaling (Sec. 3.7).  Returns (stress, scale)."""
+    rp, ci = _csr(rowptr, colidx)
+    s = C.c_double()
+    if pivots is None:
+        v = _load().orc_stress(len(rp) - 1, rp, ci, _f64(x), _f64(y), 0, None, C.byref(s))
+    else:
+        pv = np.ascontiguousarray(pivots, dtype=np.int32)
+        v = _load().orc_stress(len(rp) - 1, rp, ci, _f64(x), _f64(y), len(pv),
+                               pv.ctypes.data_as(C.c_void_p), C.byref(s))
+    return v, s.value

@@ -1,0 +1,592 @@
+/*
+ * BatchLayout oracle: a plain, slow, FP64 CPU implementation of the
+ * minibatch force-directed layout step (Rahman, Sujon & Azad, "BatchLayout:
+ * A Batch-Parallel Force-Directed Graph Layout Algorithm in Shared Memory").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or helper with the HIP
+ * library.  It is written for a reader to check against the paper by eye:
+ * one vertex at a time, j ascending, no blocking, no reordering.
+ *
+ * Conventions (each is a reading of the paper, listed in the design notes):
+ *  - Force model, Sec. 2.2 (the (a,r)-energy model) with the (2,-1) instance
+ *    of Sec. 4.1: attraction magnitude d^2/K, repulsion magnitude R*K^2/d,
+ *    both applied along the unit vector (c_j - c_i)/d; repulsion with a
+ *    negative sign, so it pushes i away from j.
+ *  - A pair with d == 0 (i itself, or a coincident vertex) contributes 0.
+ *  - Repulsion runs over every j != i by default; with repulse_adjacent = 0
+ *    adjacent pairs are skipped as in Algorithms 1 and 2.
+ *  - Minibatch step, Sec. 3.3 and Algorithm 2: forces of all vertices of a
+ *    batch are computed from one set of positions, then the batch is moved;
+ *    batches are consecutive vertex ids and later batches see earlier moves.
+ *  - Update: c_i += Step * f_i / |f_i| (no move when |f_i| == 0);
+ *    Energy += |f_i|^2; Step is multiplied by the decay after each iteration.
+ *  - Barnes-Hut, Sec. 3.5 and Algorithms S1-S3: per iteration the snapshot is
+ *    quantised on a 2^16 x 2^16 Morton grid over the square bounding box
+ *    (quantisation done in float32 arithmetic), the sorted list is split
+ *    recursively into quadrants, a centroid is the FP64 mean of the members,
+ *    a cell is accepted when side < theta * distance, a cell holding i is
+ *    always opened, leaves (single vertices, or depth-16 buckets) interact
+ *    exactly using the live coordinates of their members.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_LEVELS 16
+
+/* ---------------------------------------------------------------- pair terms
+ * Attraction term on i from neighbour j (Sec. 2.2, a = 2):
+ *   f_a(i,j) * (c_j - c_i)/d = (d^2/K) * delta/d = d * delta / K. */
+static void pair_attraction(double dx, double dy, double K, double *tx, double *ty)
+{
+    double d = sqrt(dx * dx + dy * dy);
+    *tx = d * dx / K;
+    *ty = d * dy / K;
+}
+
+/* Repulsion term on i from j (Sec. 2.2, r = -1 read as force ~ 1/d):
+ *   f_r(i,j) * (c_j - c_i)/d = (-R K^2 / d) * delta/d = -R K^2 delta / d^2. */
+static void pair_repulsion(double dx, double dy, double K, double R, double *tx, double *ty)
+{
+    double d2 = dx * dx + dy * dy;
+    if (d2 == 0.0) { *tx = 0.0; *ty = 0.0; return; }
+    double c = -R * K * K / d2;
+    *tx = c * dx;
+    *ty = c * dy;
+}
+
+/* ------------------------------------------------------------- exact forces
+ * Net force on vertex i from the current coordinates (Sec. 2.2, the combined
+ * force f(i,c); Algorithm 2 walks j = 0..n-1 and the sorted CSR row in step).
+ * Outputs attraction and repulsion separately, plus the condition scale
+ * S_i = sum of |term| over all terms. */
+static void force_exact_one(int n, const int *rowptr, const int *colidx,
+                            const double *x, const double *y, int i,
+                            double K, double R, int repulse_adjacent,
+                            double *ax, double *ay, double *rx, double *ry, double *scale)
+{
+    double sax = 0, say = 0, srx = 0, sry = 0, s = 0;
+    int k = rowptr[i], kend = rowptr[i + 1];
+    for (int j = 0; j < n; ++j) {
+        double dx = x[j] - x[i], dy = y[j] - y[i];
+        int adjacent = 0;
+        while (k < kend && colidx[k] < j) ++k;
+        if (k < kend && colidx[k] == j) adjacent = 1;
+        if (adjacent) {
+            double tx, ty;
+            pair_attraction(dx, dy, K, &tx, &ty);
+            sax += tx; say += ty;
+            s += sqrt(tx * tx + ty * ty);
+        }
+        if (j == i) continue;
+        if (adjacent && !repulse_adjacent) continue;
+        double tx, ty;
+        pair_repulsion(dx, dy, K, R, &tx, &ty);
+        srx += tx; sry += ty;
+        s += sqrt(tx * tx + ty * ty);
+    }
+    *ax = sax; *ay = say; *rx = srx; *ry = sry;
+    if (scale) *scale = s;
+}
+
+int orc_forces_exact(int n, const int *rowptr, const int *colidx,
+                     const double *x, const double *y, int i0, int i1,
+                     double K, double R, int repulse_adjacent,
+                     double *ax, double *ay, double *rx, double *ry, double *scale)
+{
+    if (n < 1 || i0 < 0 || i1 > n || i0 > i1) return -1;
+    for (int i = i0; i < i1; ++i)
+        force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent,
+                        &ax[i - i0], &ay[i - i0], &rx[i - i0], &ry[i - i0],
+                        scale ? &scale[i - i0] : NULL);
+    return 0;
+}
+
+/* Move the vertices of one batch along their normalised net forces
+ * (Algorithm 2, the update loop after the parallel force loop). */
+static double move_batch(int i0, int i1, double *x, double *y,
+                         const double *fx, const double *fy, double step)
+{
+    double energy = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        double f2 = fx[i - i0] * fx[i - i0] + fy[i - i0] * fy[i - i0];
+        double norm = sqrt(f2);
+        if (norm > 0.0) {
+            x[i] += step * fx[i - i0] / norm;
+            y[i] += step * fy[i - i0] / norm;
+        }
+        energy += f2;
+    }
+    return energy;
+}
+
+/* Step length at iteration k: Step_0 multiplied by the decay once per
+ * completed iteration (Algorithm 2, Step = Step * 0.999 after each loop). */
+double orc_step_at(double step0, double decay, int k)
+{
+    double s = step0;
+    for (int t = 0; t < k; ++t) s *= decay;
+    return s;
+}
+
+/* Exact BatchLayout (Algorithm 2 without the cache blocking).
+ * Runs iterations [start_iter, start_iter + iters).  When stop_batch >= 0 the
+ * last iteration stops after that many batches (used to dump a mid-iteration
+ * state).  energy[t] receives the energy of iteration start_iter + t. */
+int orc_layout_exact(int n, const int *rowptr, const int *colidx,
+                     double *x, double *y, int bs, int iters, int start_iter,
+                     double step0, double decay, double K, double R,
+                     int repulse_adjacent, int stop_batch, double *energy)
+{
+    if (n < 1 || bs < 1 || iters < 0) return -1;
+    int nb = (n + bs - 1) / bs;
+    double *fx = malloc(sizeof(double) * bs), *fy = malloc(sizeof(double) * bs);
+    double *ax = malloc(sizeof(double) * bs), *ay = malloc(sizeof(double) * bs);
+    if (!fx || !fy || !ax || !ay) { free(fx); free(fy); free(ax); free(ay); return -2; }
+    for (int t = 0; t < iters; ++t) {
+        double step = orc_step_at(step0, decay, start_iter + t);
+        double e = 0.0;
+        int last = (t == iters - 1 && stop_batch >= 0) ? stop_batch : nb;
+        for (int b = 0; b < last; ++b) {
+            int i0 = b * bs, i1 = i0 + bs < n ? i0 + bs : n;
+            for (int i = i0; i < i1; ++i) {
+                double rx, ry;
+                force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent,
+                                &ax[i - i0], &ay[i - i0], &rx, &ry, NULL);
+                fx[i - i0] = ax[i - i0] + rx;
+                fy[i - i0] = ay[i - i0] + ry;
+            }
+            e += move_batch(i0, i1, x, y, fx, fy, step);
+        }
+        if (energy) energy[t] = e;
+    }
+    free(fx); free(fy); free(ax); free(ay);
+    return 0;
+}
+
+/* ------------------------------------------------------------- Barnes-Hut */
+
+typedef struct {
+    int level;        /* 0 = root square of side W */
+    int lo, hi;       /* members: sorted positions [lo, hi) */
+    int nchild;
+    int child[4];     /* node indices, Morton order */
+    int bucket;       /* 1: depth-16 cell holding >= 2 members */
+    double cx, cy;    /* FP64 centroid of the members' snapshot coordinates */
+} onode;
+
+typedef struct {
+    int n;
+    int nnodes, cap;
+    onode *nodes;
+    uint32_t *key;    /* key of sorted position p */
+    int *order;       /* vertex at sorted position p */
+    int *pos;         /* sorted position of vertex i */
+    double W;         /* side of the root square (float32 value) */
+    float xmin, ymin;
+    const double *sx, *sy;   /* snapshot (copied) */
+    double *sxbuf, *sybuf;
+} otree;
+
+/* Morton key of a point, quantised in float32 arithmetic on a 2^16 grid over
+ * the square [xmin, xmin+W] x [ymin, ymin+W]; bit 2b holds x bit b and bit
+ * 2b+1 holds y bit b.  Cells of the quadtree are the key prefixes (Fig. 5). */
+static uint32_t morton_key(float px, float py, float xmin, float ymin, float W)
+{
+    uint32_t qx = 0, qy = 0;
+    if (W > 0.0f) {
+        volatile float scale = 65536.0f / W;
+        volatile float ux = px - xmin, uy = py - ymin;
+        volatile float fx = ux * scale, fy = uy * scale;
+        long lx = (long)fx, ly = (long)fy;
+        if (lx < 0) lx = 0;
+        if (ly < 0) ly = 0;
+        if (lx > 65535) lx = 65535;
+        if (ly > 65535) ly = 65535;
+        qx = (uint32_t)lx; qy = (uint32_t)ly;
+    }
+    uint32_t k = 0;
+    for (int b = 0; b < 16; ++b) {
+        k |= ((qx >> b) & 1u) << (2 * b);
+        k |= ((qy >> b) & 1u) << (2 * b + 1);
+    }
+    return k;
+}
+
+static otree *g_sort_tree;
+static int cmp_sorted(const void *a, const void *b)
+{
+    int i = *(const int *)a, j = *(const int *)b;
+    /* keys stored per vertex in tree->pos temporarily */
+    uint32_t ki = (uint32_t)g_sort_tree->pos[i], kj = (uint32_t)g_sort_tree->pos[j];
+    if (ki != kj) return ki < kj ? -1 : 1;
+    return i < j ? -1 : (i > j);
+}
+
+static int new_node(otree *t)
+{
+    if (t->nnodes == t->cap) {
+        int nc = t->cap ? 2 * t->cap : 64;
+        onode *nn = realloc(t->nodes, sizeof(onode) * nc);
+        if (!nn) return -1;
+        t->nodes = nn; t->cap = nc;
+    }
+    memset(&t->nodes[t->nnodes], 0, sizeof(onode));
+    return t->nnodes++;
+}
+
+/* Algorithm S1 (constructBHT): split the Morton-sorted members of a cell into
+ * its four quadrants, build each non-empty one, then form the centroid from
+ * the children.  Recursion stops at a single member or at depth 16. */
+static int build_cell(otree *t, int lo, int hi, int level)
+{
+    int id = new_node(t);
+    if (id < 0) return -1;
+    t->nodes[id].level = level;
+    t->nodes[id].lo = lo;
+    t->nodes[id].hi = hi;
+    if (hi - lo == 1) {
+        int v = t->order[lo];
+        t->nodes[id].cx = t->sx[v];
+        t->nodes[id].cy = t->sy[v];
+        return id;
+    }
+    if (level == ORC_LEVELS) {
+        double sx = 0, sy = 0;
+        for (int p = lo; p < hi; ++p) { sx += t->sx[t->order[p]]; sy += t->sy[t->order[p]]; }
+        t->nodes[id].bucket = 1;
+        t->nodes[id].cx = sx / (hi - lo);
+        t->nodes[id].cy = sy / (hi - lo);
+        return id;
+    }
+    int shift = 2 * (ORC_LEVELS - 1 - level);
+    int start = lo;
+    int kids[4], nk = 0;
+    for (uint32_t q = 0; q < 4; ++q) {
+        int end = start;
+        while (end < hi && ((t->key[end] >> shift) & 3u) == q) ++end;
+        if (end > start) {
+            int c = build_cell(t, start, end, level + 1);
+            if (c < 0) return -1;
+            kids[nk++] = c;
+        }
+        start = end;
+    }
+    /* centroid from the children: count-weighted mean of their centroids */
+    double sx = 0, sy = 0;
+    for (int c = 0; c < nk; ++c) {
+        onode *ch = &t->nodes[kids[c]];
+        int cnt = ch->hi - ch->lo;
+        sx += cnt * ch->cx;
+        sy += cnt * ch->cy;
+    }
+    onode *nd = &t->nodes[id];
+    nd->nchild = nk;
+    for (int c = 0; c < nk; ++c) nd->child[c] = kids[c];
+    nd->cx = sx / (hi - lo);
+    nd->cy = sy / (hi - lo);
+    return id;
+}
+
+void orc_tree_free(void *tp)
+{
+    otree *t = (otree *)tp;
+    if (!t) return;
+    free(t->nodes); free(t->key); free(t->order); free(t->pos);
+    free(t->sxbuf); free(t->sybuf);
+    free(t);
+}
+
+/* Build the quadtree of a snapshot (Algorithm S3: bounding box, Morton sort,
+ * D = max extent, constructBHT).  Returns an opaque handle. */
+void *orc_tree_build(int n, const double *sx, const double *sy)
+{
+    if (n < 1) return NULL;
+    otree *t = calloc(1, sizeof(otree));
+    if (!t) return NULL;
+    t->n = n;
+    t->key = malloc(sizeof(uint32_t) * n);
+    t->order = malloc(sizeof(int) * n);
+    t->pos = malloc(sizeof(int) * n);
+    t->sxbuf = malloc(sizeof(double) * n);
+    t->sybuf = malloc(sizeof(double) * n);
+    if (!t->key || !t->order || !t->pos || !t->sxbuf || !t->sybuf) { orc_tree_free(t); return NULL; }
+    memcpy(t->sxbuf, sx, sizeof(double) * n);
+    memcpy(t->sybuf, sy, sizeof(double) * n);
+    t->sx = t->sxbuf; t->sy = t->sybuf;
+
+    float xmin = (float)sx[0], xmax = xmin, ymin = (float)sy[0], ymax = ymin;
+    for (int i = 1; i < n; ++i) {
+        float fx = (float)sx[i], fy = (float)sy[i];
+        if (fx < xmin) xmin = fx;
+        if (fx > xmax) xmax = fx;
+        if (fy < ymin) ymin = fy;
+        if (fy > ymax) ymax = fy;
+    }
+    volatile float wx = xmax - xmin, wy = ymax - ymin;
+    float W = wx > wy ? wx : wy;
+    t->xmin = xmin; t->ymin = ymin; t->W = (double)W;
+
+    for (int i = 0; i < n; ++i) {
+        t->pos[i] = (int)morton_key((float)sx[i], (float)sy[i], xmin, ymin, W);
+        t->order[i] = i;
+    }
+    g_sort_tree = t;
+    qsort(t->order, n, sizeof(int), cmp_sorted);
+    for (int p = 0; p < n; ++p) t->key[p] = (uint32_t)t->pos[t->order[p]];
+    for (int p = 0; p < n; ++p) t->pos[t->order[p]] = p;
+
+    if (build_cell(t, 0, n, 0) < 0) { orc_tree_free(t); return NULL; }
+    return t;
+}
+
+/* Tree inspection for the tests. */
+int orc_tree_nnodes(void *tp) { return ((otree *)tp)->nnodes; }
+double orc_tree_width(void *tp) { return ((otree *)tp)->W; }
+int orc_tree_node(void *tp, int id, int *level, int *lo, int *hi, int *nchild,
+                  int *child4, int *bucket, double *cx, double *cy)
+{
+    otree *t = (otree *)tp;
+    if (id < 0 || id >= t->nnodes) return -1;
+    onode *nd = &t->nodes[id];
+    *level = nd->level; *lo = nd->lo; *hi = nd->hi; *nchild = nd->nchild;
+    for (int c = 0; c < 4; ++c) child4[c] = c < nd->nchild ? nd->child[c] : -1;
+    *bucket = nd->bucket; *cx = nd->cx; *cy = nd->cy;
+    return 0;
+}
+int orc_tree_order(void *tp, int *order, uint32_t *keys)
+{
+    otree *t = (otree *)tp;
+    for (int p = 0; p < t->n; ++p) { order[p] = t->order[p]; keys[p] = t->key[p]; }
+    return 0;
+}
+
+typedef struct {
+    const otree *t;
+    const double *x, *y;     /* live coordinates */
+    int i, posi;
+    double xi, yi;
+    double K, R, theta;
+    int leaf_live;
+    double rx, ry, scale;
+    long visits;
+    int near_tie;
+} walk_ctx;
+
+static void add_rep(walk_ctx *w, double px, double py, double mult)
+{
+    double tx, ty;
+    pair_repulsion(px - w->xi, py - w->yi, w->K, w->R, &tx, &ty);
+    w->rx += mult * tx;
+    w->ry += mult * ty;
+    w->scale += mult * sqrt(tx * tx + ty * ty);
+}
+
+static void add_member(walk_ctx *w, int v)
+{
+    if (v == w->i) return;
+    const double *px = w->leaf_live ? w->x : w->t->sx;
+    const double *py = w->leaf_live ? w->y : w->t->sy;
+    add_rep(w, px[v], py[v], 1.0);
+}
+
+/* Algorithm S2 (calcRepulsiveForce): accept a cell when side < theta * d,
+ * otherwise descend into its children in Morton order; leaves interact
+ * exactly; a cell that holds i is always opened. */
+static void walk(walk_ctx *w, int id)
+{
+    const otree *t = w->t;
+    const onode *nd = &t->nodes[id];
+    w->visits++;
+    if (nd->hi - nd->lo == 1) { add_member(w, t->order[nd->lo]); return; }
+    if (nd->bucket) {
+        for (int p = nd->lo; p < nd->hi; ++p) add_member(w, t->order[p]);
+        return;
+    }
+    int holds_i = (w->posi >= nd->lo && w->posi < nd->hi);
+    if (!holds_i) {
+        double side = ldexp(t->W, -nd->level);
+        double dx = nd->cx - w->xi, dy = nd->cy - w->yi;
+        double d = sqrt(dx * dx + dy * dy);
+        if (fabs(side - w->theta * d) <= 1e-5 * w->theta * d) w->near_tie = 1;
+        if (side < w->theta * d) {
+            add_rep(w, nd->cx, nd->cy, (double)(nd->hi - nd->lo));
+            return;
+        }
+    }
+    for (int c = 0; c < nd->nchild; ++c) walk(w, nd->child[c]);
+}
+
+/* Barnes-Hut forces for vertices [i0, i1) (Algorithm S3, force loop):
+ * attraction over CSR neighbours with live coordinates, repulsion through the
+ * tree of the snapshot.  leaf_live = 1 makes leaves use live coordinates. */
+int orc_forces_bh(int n, const int *rowptr, const int *colidx,
+                  const double *x, const double *y, void *tp, int i0, int i1,
+                  double K, double R, double theta, int leaf_live,
+                  double *ax, double *ay, double *rx, double *ry, double *scale,
+                  long *visits, int *near_tie)
+{
+    otree *t = (otree *)tp;
+    if (!t || t->n != n || i0 < 0 || i1 > n || i0 > i1) return -1;
+    for (int i = i0; i < i1; ++i) {
+        double sax = 0, say = 0, s = 0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int j = colidx[k];
+            double tx, ty;
+            pair_attraction(x[j] - x[i], y[j] - y[i], K, &tx, &ty);
+            sax += tx; say += ty;
+            s += sqrt(tx * tx + ty * ty);
+        }
+        walk_ctx w;
+        memset(&w, 0, sizeof w);
+        w.t = t; w.x = x; w.y = y; w.i = i; w.posi = t->pos[i];
+        w.xi = x[i]; w.yi = y[i];
+        w.K = K; w.R = R; w.theta = theta; w.leaf_live = leaf_live;
+        walk(&w, 0);
+        ax[i - i0] = sax; ay[i - i0] = say;
+        rx[i - i0] = w.rx; ry[i - i0] = w.ry;
+        if (scale) scale[i - i0] = s + w.scale;
+        if (visits) visits[i - i0] = w.visits;
+        if (near_tie) near_tie[i - i0] = w.near_tie;
+    }
+    return 0;
+}
+
+/* BatchLayoutBH (Algorithm S3) with the step decay of Algorithm 2.
+ * When snap_x/snap_y are given they receive the snapshot of the last
+ * (possibly partial, see stop_batch) iteration.  visits_total accumulates
+ * the node visits of all force evaluations. */
+int orc_layout_bh(int n, const int *rowptr, const int *colidx,
+                  double *x, double *y, int bs, int iters, int start_iter,
+                  double step0, double decay, double K, double R, double theta,
+                  int leaf_live, int stop_batch, double *energy,
+                  double *snap_x, double *snap_y, long *visits_total)
+{
+    if (n < 1 || bs < 1 || iters < 0 || theta < 0) return -1;
+    int nb = (n + bs - 1) / bs;
+    double *ax = malloc(sizeof(double) * bs), *ay = malloc(sizeof(double) * bs);
+    double *rx = malloc(sizeof(double) * bs), *ry = malloc(sizeof(double) * bs);
+    double *fx = malloc(sizeof(double) * bs), *fy = malloc(sizeof(double) * bs);
+    long *vis = malloc(sizeof(long) * bs);
+    if (!ax || !ay || !rx || !ry || !fx || !fy || !vis) {
+        free(ax); free(ay); free(rx); free(ry); free(fx); free(fy); free(vis);
+        return -2;
+    }
+    long vt = 0;
+    int rc = 0;
+    for (int t = 0; t < iters && rc == 0; ++t) {
+        double step = orc_step_at(step0, decay, start_iter + t);
+        void *tree = orc_tree_build(n, x, y);
+        if (!tree) { rc = -2; break; }
+        if (t == iters - 1 && snap_x && snap_y) {
+            memcpy(snap_x, x, sizeof(double) * n);
+            memcpy(snap_y, y, sizeof(double) * n);
+        }
+        double e = 0.0;
+        int last = (t == iters - 1 && stop_batch >= 0) ? stop_batch : nb;
+        for (int b = 0; b < last; ++b) {
+            int i0 = b * bs, i1 = i0 + bs < n ? i0 + bs : n;
+            orc_forces_bh(n, rowptr, colidx, x, y, tree, i0, i1, K, R, theta, leaf_live,
+                          ax, ay, rx, ry, NULL, vis, NULL);
+            for (int i = i0; i < i1; ++i) {
+                fx[i - i0] = ax[i - i0] + rx[i - i0];
+                fy[i - i0] = ay[i - i0] + ry[i - i0];
+                vt += vis[i - i0];
+            }
+            e += move_batch(i0, i1, x, y, fx, fy, step);
+        }
+        if (energy) energy[t] = e;
+        orc_tree_free(tree);
+    }
+    if (visits_total) *visits_total = vt;
+    free(ax); free(ay); free(rx); free(ry); free(fx); free(fy); free(vis);
+    return rc;
+}
+
+/* ------------------------------------------------------- quality measures */
+
+/* Edge energy: the attractive potential whose gradient is the attraction
+ * term, summed once per undirected edge: sum d^3 / (3K). */
+double orc_edge_energy(int n, const int *rowptr, const int *colidx,
+                       const double *x, const double *y, double K)
+{
+    double e = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int j = colidx[k];
+            if (j <= i) continue;
+            double dx = x[j] - x[i], dy = y[j] - y[i];
+            double d = sqrt(dx * dx + dy * dy);
+            e += d * d * d / (3.0 * K);
+        }
+    return e;
+}
+
+/* Edge uniformity (Sec. 3.7): normalised standard deviation of edge lengths. */
+double orc_edge_uniformity(int n, const int *rowptr, const int *colidx,
+                           const double *x, const double *y)
+{
+    double s = 0.0;
+    long m = 0;
+    for (int i = 0; i < n; ++i)
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int j = colidx[k];
+            if (j <= i) continue;
+            s += hypot(x[j] - x[i], y[j] - y[i]);
+            m++;
+        }
+    if (m == 0) return 0.0;
+    double mean = s / m, v = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int j = colidx[k];
+            if (j <= i) continue;
+            double l = hypot(x[j] - x[i], y[j] - y[i]);
+            v += (l - mean) * (l - mean);
+        }
+    return sqrt(v / ((double)m * mean * mean));
+}
+
+/* Stress (Sec. 3.7) after the best uniform scaling of the layout:
+ *   sum w_ij (s |c_i - c_j| - d_ij)^2 with w_ij = d_ij^-2, minimised over s,
+ * d_ij = BFS hop distance, unreachable pairs skipped.  With pivots == NULL the
+ * sum runs over unordered pairs i < j; otherwise over pivot p and all j != p.
+ * The minimum over s is N - A^2/B with A = sum |.|/d, B = sum |.|^2/d^2. */
+double orc_stress(int n, const int *rowptr, const int *colidx,
+                  const double *x, const double *y, int npivots, const int *pivots,
+                  double *scale_out)
+{
+    int *dist = malloc(sizeof(int) * n), *queue = malloc(sizeof(int) * n);
+    if (!dist || !queue) { free(dist); free(queue); return -1.0; }
+    double A = 0.0, B = 0.0, N = 0.0;
+    int np = pivots ? npivots : n;
+    for (int q = 0; q < np; ++q) {
+        int p = pivots ? pivots[q] : q;
+        for (int i = 0; i < n; ++i) dist[i] = -1;
+        int head = 0, tail = 0;
+        dist[p] = 0; queue[tail++] = p;
+        while (head < tail) {
+            int u = queue[head++];
+            for (int k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+                int v = colidx[k];
+                if (dist[v] < 0) { dist[v] = dist[u] + 1; queue[tail++] = v; }
+            }
+        }
+        for (int j = 0; j < n; ++j) {
+            if (j == p || dist[j] <= 0) continue;
+            if (!pivots && j < p) continue;
+            double dij = dist[j];
+            double g = hypot(x[j] - x[p], y[j] - y[p]);
+            A += g / dij;
+            B += g * g / (dij * dij);
+            N += 1.0;
+        }
+    }
+    free(dist); free(queue);
+    if (B == 0.0) { if (scale_out) *scale_out = 0.0; return N; }
+    if (scale_out) *scale_out = A / B;
+    return N - A * A / B;
+}

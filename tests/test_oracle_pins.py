@@ -1,0 +1,544 @@
+"""Pins for the FP64 oracle: closed forms, invariants, special cases and brute force.
+
+Each test fixes the oracle to something other than itself, so that a dropped
+term, a wrong sign, a swapped index or a wrong batch order fails one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_08233_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def random_graph(n, p, seed):
+    r = I.rng(seed)
+    iu = np.triu_indices(n, 1)
+    keep = r.random(len(iu[0])) < p
+    return I.csr_from_edges(n, iu[0][keep], iu[1][keep])
+
+
+def dyadic_coords(n, seed, bits=12):
+    """Coordinates on a 2^-bits grid so that shifts, rotations and power-of-two
+    scalings are exact in FP64."""
+    r = I.rng(seed)
+    return (r.integers(-2 ** bits, 2 ** bits, n) / 2.0 ** bits,
+            r.integers(-2 ** bits, 2 ** bits, n) / 2.0 ** bits)
+
+
+# ---------------------------------------------------------------- pair terms
+
+@pytest.mark.parametrize("K,R", [(1.0, 1.0), (0.5, 2.0), (2.0, 0.25)])
+def test_two_vertex_force_closed_form(K, R):
+    """Sec. 2.2 with a=2, r=-1: |f| = |d^2/K - R K^2/d| along the line, zero at d* = K R^(1/3)."""
+    g = I.path(2)
+    for d, ang in [(0.3, 0.1), (1.7, 2.0), (K * R ** (1 / 3), -0.7)]:
+        x = np.array([0.25, 0.25 + d * math.cos(ang)])
+        y = np.array([-0.5, -0.5 + d * math.sin(ang)])
+        f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 2, K=K, R=R)
+        # force on vertex 0 is along +u (toward vertex 1) with signed magnitude d^2/K - R K^2/d
+        u = np.array([math.cos(ang), math.sin(ang)])
+        mag = d * d / K - R * K * K / d
+        assert f.fx[0] == pytest.approx(mag * u[0], abs=1e-12 * (1 + abs(mag)))
+        assert f.fy[0] == pytest.approx(mag * u[1], abs=1e-12 * (1 + abs(mag)))
+        assert f.fx[1] == pytest.approx(-mag * u[0], abs=1e-12 * (1 + abs(mag)))
+        # attraction and repulsion separately (signs)
+        assert f.ax[0] * u[0] + f.ay[0] * u[1] == pytest.approx(d * d / K, rel=1e-13)
+        assert f.rx[0] * u[0] + f.ry[0] * u[1] == pytest.approx(-R * K * K / d, rel=1e-13)
+
+
+@pytest.mark.parametrize("bs", [1, 2])
+def test_two_vertex_trajectory_and_equilibrium(bs):
+    """Normalised steps make the motion 1-D: with batch 2 both ends move by Step
+    (distance changes by 2 Step); with batch 1 the second vertex sees the first
+    one's move.  The distance settles within 2*Step_k of d* = K R^(1/3)."""
+    g = I.path(2)
+    K, R = 1.0, 1.0
+    dstar = K * R ** (1 / 3)
+    x0 = np.array([0.0, 5.0])
+    y0 = np.array([0.0, 0.0])
+    iters = 400
+    x, y, e = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, bs, iters, step0=1.0, decay=0.9)
+    # independent recurrence on the two abscissae: each end moves by Step toward
+    # the other when the gap exceeds d*, away from it when the gap is shorter
+    def pull(p, q):
+        d = abs(q - p)
+        toward = 1.0 if q > p else -1.0
+        return toward * (1.0 if d > dstar else (-1.0 if d < dstar else 0.0))
+
+    a, b = 0.0, 5.0
+    step = 1.0
+    for k in range(iters):
+        if bs == 2:
+            sa, sb = pull(a, b), pull(b, a)
+            a, b = a + step * sa, b + step * sb
+        else:
+            a = a + step * pull(a, b)
+            b = b + step * pull(b, a)
+        step *= 0.9
+    assert x[0] == pytest.approx(a, abs=1e-12) and x[1] == pytest.approx(b, abs=1e-12)
+    assert np.all(y == 0.0)
+    assert abs(abs(x[1] - x[0]) - dstar) <= 2 * 0.9 ** (iters - 1) + 1e-12
+
+
+def test_cycle_equilibrium_radius():
+    """Cycle C_k on a circle of radius rho: by symmetry forces are radial,
+    F(rho) = (k-1) R K^2 / (2 rho) - 8 rho^2 sin^3(pi/k) / K, so the
+    equilibrium radius is rho*^3 = (k-1) R K^3 / (16 sin^3(pi/k))."""
+    for k, K, R in [(5, 1.0, 1.0), (12, 0.7, 1.5), (31, 1.3, 0.4)]:
+        g = I.cycle(k)
+        rho_star = (((k - 1) * R * K ** 3) / (16 * math.sin(math.pi / k) ** 3)) ** (1 / 3)
+        for rho in [0.5 * rho_star, rho_star, 2.0 * rho_star]:
+            phi = 2 * math.pi * np.arange(k) / k
+            x, y = rho * np.cos(phi), rho * np.sin(phi)
+            f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, k, K=K, R=R)
+            radial = f.fx * np.cos(phi) + f.fy * np.sin(phi)
+            tangential = -f.fx * np.sin(phi) + f.fy * np.cos(phi)
+            expect = (k - 1) * R * K * K / (2 * rho) - 8 * rho ** 2 * math.sin(math.pi / k) ** 3 / K
+            scale = f.scale.max()
+            assert np.allclose(radial, expect, atol=1e-12 * scale)
+            assert np.abs(tangential).max() <= 1e-12 * scale
+
+
+# ------------------------------------------------------------ force invariants
+
+def test_newton_third_law():
+    """With all vertices in one batch, repulsions and attractions each sum to zero."""
+    g = random_graph(60, 0.1, 11)
+    x, y = I.uniform_coords(60, 12)
+    f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 60)
+    s = f.scale.sum()
+    assert abs(f.rx.sum()) < 1e-12 * s and abs(f.ry.sum()) < 1e-12 * s
+    assert abs(f.ax.sum()) < 1e-12 * s and abs(f.ay.sum()) < 1e-12 * s
+
+
+def test_literal_mode_skips_adjacent_repulsion():
+    """Algorithms 1/2 skip repulsion between adjacent vertices: the literal force
+    equals the all-pairs force minus the repulsion of each neighbour."""
+    g = random_graph(40, 0.15, 3)
+    x, y = I.uniform_coords(40, 4)
+    fa = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 40, repulse_adjacent=True)
+    fl = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 40, repulse_adjacent=False)
+    for i in range(40):
+        nb = g.colidx[g.rowptr[i]:g.rowptr[i + 1]]
+        dx, dy = x[nb] - x[i], y[nb] - y[i]
+        d2 = dx * dx + dy * dy
+        cx, cy = (-dx / d2).sum(), (-dy / d2).sum()
+        assert fl.fx[i] == pytest.approx(fa.fx[i] - cx, abs=1e-11 * fa.scale[i])
+        assert fl.fy[i] == pytest.approx(fa.fy[i] - cy, abs=1e-11 * fa.scale[i])
+
+
+def test_translation_invariance_bitwise():
+    g = random_graph(50, 0.1, 5)
+    x, y = dyadic_coords(50, 6)
+    f0 = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 50)
+    f1 = oracle.forces_exact(g.rowptr, g.colidx, x + 3.25, y - 0.5, 0, 50)
+    assert np.array_equal(f0.fx, f1.fx) and np.array_equal(f0.fy, f1.fy)
+
+
+def test_rotation_and_reflection_covariance_bitwise():
+    """(x,y) -> (-y,x) and x -> -x are exact in floating point, so the forces
+    transform exactly."""
+    g = random_graph(50, 0.1, 7)
+    x, y = dyadic_coords(50, 8)
+    f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 50)
+    fr = oracle.forces_exact(g.rowptr, g.colidx, -y, x, 0, 50)
+    assert np.array_equal(fr.fx, -f.fy) and np.array_equal(fr.fy, f.fx)
+    fm = oracle.forces_exact(g.rowptr, g.colidx, -x, y, 0, 50)
+    assert np.array_equal(fm.fx, -f.fx) and np.array_equal(fm.fy, f.fy)
+
+
+def test_scaling_law():
+    """c -> s c: attraction scales by s^2, repulsion by 1/s (exact for s = 2^k)."""
+    g = random_graph(40, 0.1, 9)
+    x, y = dyadic_coords(40, 10)
+    f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 40)
+    f4 = oracle.forces_exact(g.rowptr, g.colidx, 4 * x, 4 * y, 0, 40)
+    assert np.allclose(f4.ax, 16 * f.ax, rtol=0, atol=1e-14 * np.abs(16 * f.ax).max())
+    assert np.array_equal(f4.rx, f.rx / 4) and np.array_equal(f4.ry, f.ry / 4)
+
+
+def test_coincident_vertices_contribute_nothing():
+    g = I.csr_from_edges(4, np.array([0]), np.array([1]))
+    x = np.array([0.0, 0.0, 1.0, 0.0])
+    y = np.array([0.0, 0.0, 0.0, 2.0])
+    f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 4)
+    assert np.all(np.isfinite(f.fx)) and np.all(np.isfinite(f.fy))
+    # vertex 0 feels only vertices 2 and 3
+    assert f.rx[0] == pytest.approx(-1.0) and f.ry[0] == pytest.approx(-0.5)
+    assert f.ax[0] == 0.0 and f.ay[0] == 0.0
+
+
+# --------------------------------------------------------- minibatch semantics
+
+def _py_force(rp, ci, x, y, i, K=1.0, R=1.0, literal=False):
+    """Sec. 2.2 written with the paper's f_a, f_r and unit vectors."""
+    nb = set(ci[rp[i]:rp[i + 1]].tolist())
+    fx = fy = 0.0
+    for j in range(len(x)):
+        if j == i:
+            continue
+        dx, dy = x[j] - x[i], y[j] - y[i]
+        d = math.hypot(dx, dy)
+        if d == 0:
+            continue
+        if j in nb:
+            fa = d ** 2 / K
+            fx += fa * dx / d
+            fy += fa * dy / d
+            if literal:
+                continue
+        fr = -R * K * K / d
+        fx += fr * dx / d
+        fy += fr * dy / d
+    return fx, fy
+
+
+def _py_layout(rp, ci, x, y, bs, iters, literal=False, step=1.0, decay=0.999):
+    x, y = list(x), list(y)
+    n = len(x)
+    energies = []
+    for _ in range(iters):
+        e = 0.0
+        for b0 in range(0, n, bs):
+            batch = range(b0, min(b0 + bs, n))
+            forces = [_py_force(rp, ci, x, y, i, literal=literal) for i in batch]
+            for i, (fx, fy) in zip(batch, forces):
+                norm = math.hypot(fx, fy)
+                if norm > 0:
+                    x[i] += step * fx / norm
+                    y[i] += step * fy / norm
+                e += fx * fx + fy * fy
+        energies.append(e)
+        step *= decay
+    return np.array(x), np.array(y), np.array(energies)
+
+
+def test_batch_one_is_algorithm1():
+    """Batch size 1 is the sequential Algorithm 1 (literal neighbour exclusion)."""
+    g = random_graph(24, 0.2, 21)
+    x0, y0 = I.uniform_coords(24, 22)
+    xr, yr, er = _py_layout(g.rowptr, g.colidx, x0, y0, 1, 5, literal=True)
+    x, y, e = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 1, 5, repulse_adjacent=False)
+    assert np.allclose(x, xr, atol=1e-10) and np.allclose(y, yr, atol=1e-10)
+    assert np.allclose(e, er, rtol=1e-10)
+
+
+@pytest.mark.parametrize("bs", [24, 5, 7])
+def test_batch_n_is_jacobi_and_ragged_batches(bs):
+    """Batch n is a fully synchronous update; other sizes give consecutive-id
+    batches with a ragged last batch."""
+    g = random_graph(24, 0.2, 23)
+    x0, y0 = I.uniform_coords(24, 24)
+    xr, yr, er = _py_layout(g.rowptr, g.colidx, x0, y0, bs, 4)
+    x, y, e = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, bs, 4)
+    assert np.allclose(x, xr, atol=1e-10) and np.allclose(y, yr, atol=1e-10)
+    assert np.allclose(e, er, rtol=1e-10)
+
+
+def test_fig2_schedule_golden():
+    """Fig. 2: batch b's forces use the already-moved coordinates of batch b-1."""
+    gold = json.load(open(os.path.join(GOLDEN, "fig2_minibatch_schedule.json")))
+    n, bs = gold["n"], gold["batch_size"]
+    g = I.cycle(n)
+    x0, y0 = I.uniform_coords(n, 31)
+    x, y = x0.copy(), y0.copy()
+    for batch in gold["batches"]:
+        i0, i1 = batch[0], batch[-1] + 1
+        f = oracle.forces_exact(g.rowptr, g.colidx, x, y, i0, i1)
+        norm = np.hypot(f.fx, f.fy)
+        x[i0:i1] += f.fx / norm
+        y[i0:i1] += f.fy / norm
+        xs, ys, _ = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, bs, 1, stop_batch=i1 // bs)
+        assert np.allclose(xs, x, atol=1e-13) and np.allclose(ys, y, atol=1e-13)
+    assert len(gold["batches"]) == gold["steps"] == (n + bs - 1) // bs
+
+
+def test_energy_is_sum_of_squared_forces():
+    """The energy of an iteration is the sum of |f_i|^2 at the moment of each move."""
+    g = random_graph(30, 0.15, 41)
+    x0, y0 = I.uniform_coords(30, 42)
+    f = oracle.forces_exact(g.rowptr, g.colidx, x0, y0, 0, 30)
+    _, _, e = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 30, 1)
+    assert e[0] == pytest.approx(float(np.sum(f.fx ** 2 + f.fy ** 2)), rel=1e-14)
+
+
+def test_step_schedule():
+    """Step_k = Step_0 * 0.999^k (Sec. 4.3.5); resuming at iteration k continues it."""
+    assert oracle.step_at(1.0, 0.999, 0) == 1.0
+    for k in [1, 10, 599]:
+        assert oracle.step_at(1.0, 0.999, k) == pytest.approx(0.999 ** k, rel=1e-13)
+    g = random_graph(20, 0.2, 51)
+    x0, y0 = I.uniform_coords(20, 52)
+    xa, ya, ea = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 8, 6)
+    xb, yb, eb = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 8, 3)
+    xc, yc, ec = oracle.layout_exact(g.rowptr, g.colidx, xb, yb, 8, 3, start_iter=3)
+    assert np.array_equal(xa, xc) and np.array_equal(ya, yc)
+    assert np.array_equal(ea, np.concatenate([eb, ec]))
+
+
+def test_single_vertex_and_empty_graph():
+    g1 = I.csr_from_edges(1, np.array([], np.int64), np.array([], np.int64))
+    x, y, e = oracle.layout_exact(g1.rowptr, g1.colidx, [0.5], [0.25], 4, 3)
+    assert x[0] == 0.5 and y[0] == 0.25 and np.all(e == 0)
+    g0 = I.csr_from_edges(3, np.array([], np.int64), np.array([], np.int64))
+    x0 = np.array([0.0, 1.0, 0.0]); y0 = np.array([0.0, 0.0, 1.0])
+    f = oracle.forces_exact(g0.rowptr, g0.colidx, x0, y0, 0, 3)
+    assert np.all(f.ax == 0) and f.rx[0] == pytest.approx(-1.0) and f.ry[0] == pytest.approx(-1.0)
+
+
+def test_mpmath_bruteforce():
+    """Forces, one iteration and its energy against 50-digit arithmetic."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    n, bs = 12, 5
+    g = random_graph(n, 0.3, 61)
+    x0, y0 = I.uniform_coords(n, 62)
+    K, R = 0.8, 1.3
+    X = [mp.mpf(v) for v in x0]
+    Y = [mp.mpf(v) for v in y0]
+    nbs = [set(g.colidx[g.rowptr[i]:g.rowptr[i + 1]].tolist()) for i in range(n)]
+
+    def force(i):
+        fx = fy = mp.mpf(0)
+        for j in range(n):
+            if j == i:
+                continue
+            dx, dy = X[j] - X[i], Y[j] - Y[i]
+            d = mp.sqrt(dx * dx + dy * dy)
+            if j in nbs[i]:
+                fx += d * d / K * dx / d
+                fy += d * d / K * dy / d
+            fx += -R * K * K / d * dx / d
+            fy += -R * K * K / d * dy / d
+        return fx, fy
+
+    f = oracle.forces_exact(g.rowptr, g.colidx, x0, y0, 0, n, K=K, R=R)
+    for i in range(n):
+        fx, fy = force(i)
+        assert abs(f.fx[i] - float(fx)) <= 1e-13 * f.scale[i]
+        assert abs(f.fy[i] - float(fy)) <= 1e-13 * f.scale[i]
+    energy = mp.mpf(0)
+    for b0 in range(0, n, bs):
+        batch = list(range(b0, min(b0 + bs, n)))
+        fs = [force(i) for i in batch]
+        for i, (fx, fy) in zip(batch, fs):
+            nrm = mp.sqrt(fx * fx + fy * fy)
+            X[i] += fx / nrm
+            Y[i] += fy / nrm
+            energy += fx * fx + fy * fy
+    x, y, e = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, bs, 1, K=K, R=R)
+    assert np.allclose(x, [float(v) for v in X], atol=1e-12)
+    assert np.allclose(y, [float(v) for v in Y], atol=1e-12)
+    assert e[0] == pytest.approx(float(energy), rel=1e-13)
+
+
+# ---------------------------------------------------------------- Barnes-Hut
+
+def test_bh_theta_zero_is_exact():
+    """theta = 0 never accepts a cell, so the walk reaches every vertex (any batch size)."""
+    w = I.workload_grid32()
+    g = w["graph"]
+    x, y = w["x0"], w["y0"]
+    t = oracle.Tree(x, y)
+    fe = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, g.n)
+    fb = oracle.forces_bh(g.rowptr, g.colidx, x, y, t, 0, g.n, theta=0.0)
+    assert np.abs(fe.fx - fb.fx).max() <= 1e-12 * fe.scale.max()
+    assert np.abs(fe.fy - fb.fy).max() <= 1e-12 * fe.scale.max()
+    # full runs, several batch sizes: theta = 0 equals exact up to rounding order
+    gs = random_graph(40, 0.1, 71)
+    x0, y0 = I.uniform_coords(40, 72)
+    for bs in [1, 7, 40]:
+        xe, ye, ee = oracle.layout_exact(gs.rowptr, gs.colidx, x0, y0, bs, 2)
+        xb, yb, eb, _ = oracle.layout_bh(gs.rowptr, gs.colidx, x0, y0, bs, 2, theta=0.0)
+        assert np.allclose(xe, xb, atol=1e-9) and np.allclose(ee, eb, rtol=1e-11)
+
+
+def test_bh_tree_invariants():
+    r = I.rng(81)
+    n = 500
+    x = np.concatenate([r.normal(0, 1, n - 20), np.full(20, 0.75)])   # 20 coincident points
+    y = np.concatenate([r.normal(0, 2, n - 20), np.full(20, -0.25)])
+    t = oracle.Tree(x, y)
+    nodes = t.nodes()
+    order, keys = t.order()
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0)
+    assert sorted(order.tolist()) == list(range(n))
+    assert nodes[0]["lo"] == 0 and nodes[0]["hi"] == n and nodes[0]["level"] == 0
+    W = t.width
+    assert W == pytest.approx(max(x.max() - x.min(), y.max() - y.min()), rel=1e-6)
+    nb = 0
+    for nd in nodes:
+        members = order[nd["lo"]:nd["hi"]]
+        assert nd["cx"] == pytest.approx(x[members].mean(), abs=1e-14 * (1 + abs(x).max()))
+        assert nd["cy"] == pytest.approx(y[members].mean(), abs=1e-14 * (1 + abs(y).max()))
+        assert nd["level"] <= 16
+        if nd["children"]:
+            kids = [nodes[c] for c in nd["children"]]
+            assert kids[0]["lo"] == nd["lo"] and kids[-1]["hi"] == nd["hi"]
+            for a, b in zip(kids, kids[1:]):
+                assert a["hi"] == b["lo"]
+            assert all(k["level"] == nd["level"] + 1 for k in kids)
+        if nd["bucket"]:
+            nb += 1
+            assert nd["level"] == 16 and nd["hi"] - nd["lo"] >= 2
+    assert nb == 1
+
+
+def test_bh_coincident_far_cell_is_k_times_single():
+    """k vertices at one far point act as one accepted cell with k times the force."""
+    k = 7
+    x = np.array([0.0] + [10.0] * k)
+    y = np.array([0.0] + [5.0] * k)
+    g = I.csr_from_edges(len(x), np.array([], np.int64), np.array([], np.int64))
+    f = oracle.forces_bh(g.rowptr, g.colidx, x, y, oracle.Tree(x, y), 0, 1, theta=1.2)
+    assert f.visits[0] < 4          # root opened, far cell accepted without descending
+    x1, y1 = x[:2], y[:2]
+    g1 = I.csr_from_edges(2, np.array([], np.int64), np.array([], np.int64))
+    single = oracle.forces_bh(g1.rowptr, g1.colidx, x1, y1, oracle.Tree(x1, y1), 0, 1, theta=1.2)
+    assert f.rx[0] == pytest.approx(k * single.rx[0], rel=1e-14)
+    assert f.ry[0] == pytest.approx(k * single.ry[0], rel=1e-14)
+    assert single.rx[0] == pytest.approx(-10.0 / 125.0, rel=1e-14)
+
+
+def _py_bh_force(x, y, i, theta, K=1.0, R=1.0):
+    """Independent Barnes-Hut walk: cells found by recursive geometric
+    subdivision of the bounding square (no Morton keys)."""
+    xs = x.astype(np.float32).astype(np.float64)
+    ys = y.astype(np.float32).astype(np.float64)
+    x0, y0 = xs.min(), ys.min()
+    W = max(xs.max() - x0, ys.max() - y0)
+    fx = fy = 0.0
+
+    def rep(px, py, mult):
+        dx, dy = px - x[i], py - y[i]
+        d2 = dx * dx + dy * dy
+        return (-mult * R * K * K * dx / d2, -mult * R * K * K * dy / d2) if d2 > 0 else (0.0, 0.0)
+
+    def walk(members, cx0, cy0, side, level):
+        nonlocal fx, fy
+        if len(members) == 1 or level == 16:
+            for j in members:
+                if j != i:
+                    a, b = rep(x[j], y[j], 1)
+                    fx += a; fy += b
+            return
+        if i not in members:
+            cx, cy = x[members].mean(), y[members].mean()
+            if side < theta * math.hypot(cx - x[i], cy - y[i]):
+                a, b = rep(cx, cy, len(members))
+                fx += a; fy += b
+                return
+        h = side / 2
+        for qy in (0, 1):
+            for qx in (0, 1):
+                sub = [j for j in members
+                       if (xs[j] >= cx0 + qx * h or qx == 0) and (xs[j] < cx0 + h or qx == 1)
+                       and (ys[j] >= cy0 + qy * h or qy == 0) and (ys[j] < cy0 + h or qy == 1)]
+                if sub:
+                    walk(sub, cx0 + qx * h, cy0 + qy * h, h, level + 1)
+
+    walk(list(range(len(x))), x0, y0, W, 0)
+    return fx, fy
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.2, 2.5])
+def test_bh_matches_independent_geometric_walk(theta):
+    r = I.rng(91)
+    n = 60
+    x = r.uniform(-1, 1, n).astype(np.float32).astype(np.float64)
+    y = r.uniform(-1, 1, n).astype(np.float32).astype(np.float64)
+    g = I.csr_from_edges(n, np.array([], np.int64), np.array([], np.int64))
+    t = oracle.Tree(x, y)
+    f = oracle.forces_bh(g.rowptr, g.colidx, x, y, t, 0, n, theta=theta)
+    for i in range(n):
+        fx, fy = _py_bh_force(x, y, i, theta)
+        assert f.rx[i] == pytest.approx(fx, abs=1e-11 * f.scale[i])
+        assert f.ry[i] == pytest.approx(fy, abs=1e-11 * f.scale[i])
+
+
+def test_bh_error_shrinks_with_theta():
+    w = I.workload_grid32()
+    g = w["graph"]
+    x, y = w["x0"], w["y0"]
+    t = oracle.Tree(x, y)
+    fe = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, g.n)
+    errs = []
+    for theta in [2.0, 1.2, 0.8, 0.4, 0.2]:
+        fb = oracle.forces_bh(g.rowptr, g.colidx, x, y, t, 0, g.n, theta=theta)
+        errs.append(np.hypot(fb.rx - fe.rx, fb.ry - fe.ry).sum() / np.hypot(fe.rx, fe.ry).sum())
+    assert all(a > b for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-3
+
+
+def test_bh_live_leaves_vs_snapshot():
+    """Leaves use live coordinates: after one batch has moved, a later vertex's
+    force changes only through the moved vertices it reaches as leaves."""
+    g = random_graph(64, 0.05, 95)
+    x0, y0 = I.uniform_coords(64, 96)
+    x, y, _, _, sx, sy = oracle.layout_bh(g.rowptr, g.colidx, x0, y0, 16, 1, theta=0.0,
+                                          stop_batch=2, want_snapshot=True)
+    t = oracle.Tree(sx, sy)
+    live = oracle.forces_bh(g.rowptr, g.colidx, x, y, t, 32, 48, theta=0.0, leaf_live=True)
+    exact = oracle.forces_exact(g.rowptr, g.colidx, x, y, 32, 48)
+    assert np.allclose(live.fx, exact.fx, atol=1e-12 * exact.scale.max())
+    snap = oracle.forces_bh(g.rowptr, g.colidx, x, y, t, 32, 48, theta=0.0, leaf_live=False)
+    assert not np.allclose(snap.fx, exact.fx, atol=1e-6 * exact.scale.max())
+
+
+# ------------------------------------------------------------ quality measures
+
+def test_stress_zero_for_metric_layout_and_optimal_scale():
+    g = I.path(10)
+    x = np.arange(10, dtype=float) * 3.0
+    y = np.zeros(10)
+    st, s = oracle.stress(g.rowptr, g.colidx, x, y)
+    assert st == pytest.approx(0.0, abs=1e-9) and s == pytest.approx(1 / 3.0)
+    from scipy.optimize import minimize_scalar
+    g2 = random_graph(30, 0.15, 101)
+    x2, y2 = I.uniform_coords(30, 102)
+    st2, s2 = oracle.stress(g2.rowptr, g2.colidx, x2, y2)
+    # brute-force stress as a function of the scale, independent of the closed form
+    D = np.full((30, 30), -1)
+    for p in range(30):
+        D[p, p] = 0
+        frontier = [p]
+        while frontier:
+            nxt = []
+            for u in frontier:
+                for v in g2.colidx[g2.rowptr[u]:g2.rowptr[u + 1]]:
+                    if D[p, v] < 0:
+                        D[p, v] = D[p, u] + 1
+                        nxt.append(v)
+            frontier = nxt
+    iu = np.triu_indices(30, 1)
+    dd = D[iu].astype(float)
+    gg = np.hypot(x2[iu[0]] - x2[iu[1]], y2[iu[0]] - y2[iu[1]])
+    ok = dd > 0
+    fun = lambda sc: float(np.sum((sc * gg[ok] - dd[ok]) ** 2 / dd[ok] ** 2))
+    res = minimize_scalar(fun, bounds=(1e-3, 1e3), method="bounded", options=dict(xatol=1e-12))
+    assert s2 == pytest.approx(res.x, rel=1e-6)
+    assert st2 == pytest.approx(res.fun, rel=1e-9)
+
+
+def test_edge_energy_and_uniformity_closed_forms():
+    g = I.cycle(8)
+    phi = 2 * math.pi * np.arange(8) / 8
+    x, y = 2 * np.cos(phi), 2 * np.sin(phi)
+    assert oracle.edge_uniformity(g.rowptr, g.colidx, x, y) == pytest.approx(0.0, abs=1e-12)
+    side = 2 * 2 * math.sin(math.pi / 8)
+    assert oracle.edge_energy(g.rowptr, g.colidx, x, y, K=1.5) == pytest.approx(8 * side ** 3 / 4.5)
+    gp = I.path(3)
+    assert oracle.edge_uniformity(gp.rowptr, gp.colidx, np.array([0.0, 1.0, 4.0]), np.zeros(3)) == \
+        pytest.approx(math.sqrt(((1 - 2) ** 2 + (3 - 2) ** 2) / (2 * 4)))
+
+
+def test_paper_defaults_golden():
+    gold = json.load(open(os.path.join(GOLDEN, "paper_defaults.json")))
+    assert gold["step_decay"]["value"] == 0.999 and gold["theta"]["value"] == 1.2
+    assert gold["batch_size"]["value"] == 256 and gold["step0"]["value"] == 1.0
