@@ -1,0 +1,184 @@
+/*
+ * batchlayout.h -- C ABI of the MI355X (gfx950) BatchLayout force-step library.
+ *
+ * The library lays out an undirected graph in 2D with the minibatch
+ * force-directed method of Rahman, Sujon & Azad ("BatchLayout: A
+ * Batch-Parallel Force-Directed Graph Layout Algorithm in Shared Memory"):
+ * per minibatch of consecutive vertex ids it computes attraction along CSR
+ * edges and repulsion (exact over all pairs, or through a Barnes-Hut
+ * quadtree), then moves every vertex of the batch by Step along its
+ * normalised net force; Step decays geometrically per iteration.
+ *
+ * Conventions shared by every call:
+ *  - Every function returns an int status: BL_OK (0) or a negative BL_E_*
+ *    code.  No call aborts or throws.  bl_last_error() returns a message for
+ *    the last non-OK status of the calling thread.
+ *  - Graphs are CSR (Sec. 2.1 of the paper): rowptr[n+1], colidx[nnz], int32,
+ *    symmetric, rows sorted ascending, no self-loops, no duplicates.
+ *  - Coordinates cross the ABI as FP64 structure-of-arrays x[n], y[n].  The
+ *    FP32 paths round them to nearest float32 on entry; results are returned
+ *    as FP64 copies of the device values.
+ *  - Pointers are host memory unless the call's flags contain BL_DEVICE_PTRS;
+ *    then they are device pointers (for instance torch tensors' data_ptr()),
+ *    stay owned by the caller and must stay valid until the call returns.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Calls are
+ *    synchronous with respect to the host: they return after their device
+ *    work on that stream has finished.
+ *  - Host arrays are owned by the caller; the library copies what it needs
+ *    before returning (the server copies on submit).  Device state created by
+ *    a handle is owned by the library until the matching destroy/release.
+ */
+#ifndef BATCHLAYOUT_H
+#define BATCHLAYOUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define BL_OK            0
+#define BL_E_INVAL      -1   /* bad argument (see each call)                     */
+#define BL_E_NOMEM      -2   /* device or host allocation failed                 */
+#define BL_E_HIP        -3   /* a HIP runtime call failed                        */
+#define BL_E_NOTREADY   -4   /* server job still running                         */
+#define BL_E_REJECTED   -5   /* server job can never fit the HBM budget          */
+#define BL_E_NONFINITE  -6   /* a NaN or Inf force or coordinate appeared        */
+#define BL_E_TIMEOUT    -7   /* a bounded device wait ran out                    */
+
+/* ------------------------------------------------------------------ knobs */
+#define BL_EXACT 0           /* exact all-pairs repulsion (Alg. 2)               */
+#define BL_BH    1           /* Barnes-Hut repulsion (Sec. 3.5, Alg. S1-S3)      */
+
+#define BL_FP32_KAHAN 0      /* FP32 pair math, compensated per-vertex sums      */
+#define BL_FP32_PLAIN 1      /* FP32 pair math, plain FP32 sums                  */
+#define BL_FP64       2      /* FP64 pair math and sums (exact mode only)        */
+
+#define BL_DEVICE_PTRS        1u  /* array arguments are device pointers         */
+#define BL_VALIDATE           2u  /* full CSR check on the host (sorted rows,
+                                     range, no self-loops/duplicates, symmetry) */
+#define BL_BH_SNAPSHOT_LEAVES 4u  /* BH leaves use the per-iteration snapshot
+                                     instead of live coordinates                */
+
+typedef struct {
+    int32_t n;               /* vertices, >= 1                                   */
+    int64_t nnz;             /* CSR entries (2 x undirected edges), >= 0         */
+    const int32_t *rowptr;   /* [n+1], rowptr[0] = 0, non-decreasing             */
+    const int32_t *colidx;   /* [nnz]                                            */
+} bl_csr;
+
+/* Run parameters.  bl_params_init() fills the paper's defaults: batch 256
+ * (Sec. 4.3.2), 600 iterations (supplement run example), Step_0 = 1 and decay
+ * 0.999 (Alg. 2, Sec. 4.3.5), K = R = 1 (Sec. 2.2 leaves them open),
+ * theta = 1.2 (Sec. 4.1), exact mode, FP32 with compensated sums,
+ * repulsion over all pairs. */
+typedef struct {
+    int32_t batch_size;      /* >= 1; the minibatch, consecutive vertex ids      */
+    int32_t iterations;      /* >= 0                                             */
+    int32_t start_iter;      /* >= 0; Step at iteration k = step0 * decay^k      */
+    int32_t mode;            /* BL_EXACT | BL_BH                                 */
+    int32_t precision;       /* BL_FP32_KAHAN | BL_FP32_PLAIN | BL_FP64          */
+    int32_t repulse_adjacent;/* 1: repulsion over every j != i (default);
+                                0: skip neighbours as Alg. 1/2 do (exact only)  */
+    double step0;            /* > 0                                              */
+    double step_decay;       /* in (0, 1]                                        */
+    double K;                /* > 0, optimal spring length                       */
+    double R;                /* > 0, relative strength of repulsion              */
+    double theta;            /* >= 0, BH acceptance: side < theta * distance     */
+    uint32_t flags;          /* BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES              */
+    int32_t reserved[7];     /* must be zero                                     */
+} bl_params;
+
+typedef struct {
+    int32_t iters_run;       /* iterations completed                             */
+    int32_t late_overflow;   /* BH: vertices whose late-leaf list overflowed     */
+    double  energy_last;     /* energy sum |f_i|^2 of the last full iteration    */
+    double  seconds;         /* device time of the run (hipEvent)                */
+    int64_t node_visits;     /* BH: tree nodes visited by the far-field walk     */
+    int64_t nonfinite_events;/* NaN/Inf net forces seen (those vertices stay)    */
+} bl_stats;
+
+/* Fill *p with the paper's defaults (see bl_params).  Returns BL_E_INVAL for NULL. */
+int bl_params_init(bl_params *p);
+
+/* Message for the last non-OK status returned to this thread ("" if none). */
+const char *bl_last_error(void);
+
+/* Library version string. */
+const char *bl_version(void);
+
+/* Bytes of device memory a resident layout job of this size needs (CSR,
+ * coordinates, accumulators, tree and sort buffers).  0 on invalid input. */
+size_t bl_footprint_bytes(int32_t n, int64_t nnz, const bl_params *p);
+
+/* ------------------------------------------------------- one-shot layout
+ * Lay out g from (x0, y0) for p->iterations iterations (Alg. 2 in exact mode,
+ * Alg. S3 in BH mode, both with the minibatch semantics of Sec. 3.3) and write
+ * the final coordinates to (x_out, y_out), which may alias (x0, y0).
+ * energy_out (may be NULL) receives p->iterations values, the energy
+ * sum_i |f_i|^2 of each iteration (Sec. 2.2), reduced in FP64 on the GPU.
+ * stats may be NULL.  Errors: BL_E_INVAL for bad sizes/params/NULL arrays,
+ * BL_E_NONFINITE if a net force was NaN/Inf (coordinates are still written). */
+int bl_layout(const bl_csr *g, const double *x0, const double *y0, const bl_params *p,
+              void *hip_stream, double *x_out, double *y_out, double *energy_out,
+              bl_stats *stats);
+
+/* --------------------------------------------------------- one minibatch
+ * Net forces (attraction + repulsion, no update) on the vertices of batch
+ * `batch_index` (ids [b*BS, min((b+1)*BS, n))) from coordinates (x, y)
+ * (Sec. 2.2, the combined force f(i,c)).  In BH mode the quadtree is built
+ * from the snapshot (sx, sy) -- the coordinates at the start of the
+ * iteration -- or from (x, y) when sx/sy are NULL; leaves use (x, y).
+ * fx, fy receive BS (or the ragged remainder) values as FP64.
+ * Errors: BL_E_INVAL if batch_index is out of range or arguments are bad. */
+int bl_forces(const bl_csr *g, const double *x, const double *y,
+              const double *sx, const double *sy, int32_t batch_index,
+              const bl_params *p, void *hip_stream, double *fx, double *fy);
+
+/* ------------------------------------------------------ resident handle
+ * A layout job whose CSR, coordinates and work buffers live on the device
+ * between calls (used by the benchmark, the batched path and the server). */
+typedef struct bl_graph bl_graph;
+
+/* Upload g (host, or device with BL_DEVICE_PTRS in p->flags) and allocate the
+ * work buffers for parameters p.  Coordinates start at zero. */
+int bl_graph_create(const bl_csr *g, const bl_params *p, void *hip_stream, bl_graph **out);
+
+/* Replace the coordinates (FP64 arrays of length n; flags may hold BL_DEVICE_PTRS). */
+int bl_graph_set_coords(bl_graph *h, const double *x, const double *y, uint32_t flags);
+
+/* Copy the current coordinates out as FP64 (flags may hold BL_DEVICE_PTRS). */
+int bl_graph_get_coords(bl_graph *h, double *x, double *y, uint32_t flags);
+
+/* Run iterations [start_iter, start_iter + iterations) on the resident state.
+ * stop_batch < 0: run them all.  stop_batch = b >= 0: the last iteration
+ * stops after computing the forces of batch b, which are written to (fx, fy)
+ * (host FP64, BS values or the ragged remainder) without moving the batch;
+ * the coordinates then hold the state those forces were computed from.
+ * energy_out (host, may be NULL) receives one value per full iteration.
+ * Resuming is exact: run(k1) followed by run(k2, start_iter = k1) gives the
+ * same coordinates as run(k1 + k2). */
+int bl_graph_run(bl_graph *h, int32_t iterations, int32_t start_iter, int32_t stop_batch,
+                 double *energy_out, double *fx, double *fy, bl_stats *stats);
+
+/* Release the device state of h.  NULL is accepted. */
+int bl_graph_destroy(bl_graph *h);
+
+/* Per-kernel device time of this job's launches, measured with hipEvents on
+ * the job's stream.  enable != 0 switches recording on (and resets the
+ * totals); 0 switches it off.  Adds two event records per profiled launch. */
+int bl_graph_profile(bl_graph *h, int32_t enable);
+
+/* Totals since the last bl_graph_profile(h, 1) for one kernel: "rows_kernel",
+ * "panel_kernel", "finalize_kernel" (exact mode), "tree_build" (the whole
+ * quadtree build sequence), "far_kernel", "chain_kernel" (Barnes-Hut).  The
+ * name "late_entries" returns, in *launches, the number of moved-leaf entries
+ * the far-field walks listed for the chain. */
+int bl_graph_profile_read(bl_graph *h, const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BATCHLAYOUT_H */

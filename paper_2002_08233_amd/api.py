@@ -1,0 +1,216 @@
+"""Python front end of the BatchLayout HIP library (marshalling only).
+
+Arrays may be numpy (host) or torch device tensors; device tensors are passed
+as device pointers (BL_DEVICE_PTRS), host arrays are copied by the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (BL_BH, BL_BH_SNAPSHOT_LEAVES, BL_DEVICE_PTRS, BL_EXACT, BL_FP32_KAHAN,
+                   BL_FP32_PLAIN, BL_FP64, BL_VALIDATE, BLError, Params, Stats, check, load)
+
+PRECISIONS = {"fp32_kahan": BL_FP32_KAHAN, "fp32": BL_FP32_PLAIN, "fp32_plain": BL_FP32_PLAIN,
+              "fp64": BL_FP64}
+MODES = {"exact": BL_EXACT, "bh": BL_BH}
+
+
+def params(batch_size=256, iterations=600, start_iter=0, mode="exact", precision="fp32_kahan",
+           repulse_adjacent=True, step0=1.0, step_decay=0.999, K=1.0, R=1.0, theta=1.2,
+           validate=False, snapshot_leaves=False) -> Params:
+    p = Params()
+    check(load().bl_params_init(C.byref(p)))
+    p.batch_size = int(batch_size)
+    p.iterations = int(iterations)
+    p.start_iter = int(start_iter)
+    p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.repulse_adjacent = 1 if repulse_adjacent else 0
+    p.step0, p.step_decay, p.K, p.R, p.theta = step0, step_decay, K, R, theta
+    p.flags = (BL_VALIDATE if validate else 0) | (BL_BH_SNAPSHOT_LEAVES if snapshot_leaves else 0)
+    return p
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class _Keep:
+    """Holds converted arrays alive while their pointers are in use."""
+
+    def __init__(self):
+        self.items = []
+
+    def host(self, a, dtype):
+        arr = np.ascontiguousarray(a, dtype=dtype)
+        self.items.append(arr)
+        return arr.ctypes.data
+
+    def ptr(self, a, dtype):
+        if a is None:
+            return None
+        if _is_torch(a):
+            import torch
+            t = a.contiguous()
+            want = {np.float64: torch.float64, np.int32: torch.int32}[dtype]
+            if t.dtype != want:
+                t = t.to(want)
+            self.items.append(t)
+            return t.data_ptr()
+        return self.host(a, dtype)
+
+
+def _device(*arrays):
+    dev = [_is_torch(a) and a.is_cuda for a in arrays if a is not None]
+    if any(dev) and not all(dev):
+        raise ValueError("mix of device tensors and host arrays")
+    return bool(dev) and all(dev)
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _csr(graph, keep: _Keep) -> L.CSR:
+    rowptr = graph.rowptr
+    colidx = graph.colidx
+    n = (len(rowptr) - 1) if not _is_torch(rowptr) else rowptr.numel() - 1
+    nnz = (len(colidx)) if not _is_torch(colidx) else colidx.numel()
+    c = L.CSR()
+    c.n = n
+    c.nnz = nnz
+    c.rowptr = keep.ptr(rowptr, np.int32)
+    c.colidx = keep.ptr(colidx, np.int32) if nnz else None
+    return c
+
+
+def layout(graph, x0, y0, p: Params, stream=None, energy=True):
+    """Run p.iterations of the layout.  Returns (x, y, energy, stats)."""
+    lib = load()
+    keep = _Keep()
+    dev = _device(graph.rowptr, x0, y0)
+    csr = _csr(graph, keep)
+    pp = Params.from_buffer_copy(p)
+    if dev:
+        pp.flags |= BL_DEVICE_PTRS
+        import torch
+        xo = torch.empty_like(x0, dtype=torch.float64)
+        yo = torch.empty_like(y0, dtype=torch.float64)
+        xptr, yptr = xo.data_ptr(), yo.data_ptr()
+    else:
+        xo = np.empty(csr.n)
+        yo = np.empty(csr.n)
+        xptr, yptr = xo.ctypes.data, yo.ctypes.data
+    en = np.zeros(max(p.iterations, 1))
+    st = Stats()
+    check(lib.bl_layout(C.byref(csr), keep.ptr(x0, np.float64), keep.ptr(y0, np.float64), C.byref(pp),
+                        _stream(stream), xptr, yptr, en.ctypes.data if energy else None, C.byref(st)))
+    return xo, yo, en[:p.iterations], st.as_dict()
+
+
+def forces(graph, x, y, batch_index, p: Params, snapshot=None, stream=None):
+    """Net forces on one batch from (x, y); BH tree from `snapshot` (sx, sy) if given."""
+    lib = load()
+    keep = _Keep()
+    csr = _csr(graph, keep)
+    pp = Params.from_buffer_copy(p)
+    sx, sy = snapshot if snapshot is not None else (None, None)
+    if _device(graph.rowptr, x, y, sx, sy):
+        pp.flags |= BL_DEVICE_PTRS
+    R = min(p.batch_size, csr.n - batch_index * p.batch_size)
+    fx = np.zeros(max(R, 1))
+    fy = np.zeros(max(R, 1))
+    check(lib.bl_forces(C.byref(csr), keep.ptr(x, np.float64), keep.ptr(y, np.float64),
+                        keep.ptr(sx, np.float64), keep.ptr(sy, np.float64), int(batch_index), C.byref(pp),
+                        _stream(stream), fx.ctypes.data, fy.ctypes.data))
+    return fx[:R], fy[:R]
+
+
+def footprint_bytes(n, nnz, p: Params) -> int:
+    return int(load().bl_footprint_bytes(int(n), int(nnz), C.byref(p)))
+
+
+class Graph:
+    """A resident layout job (CSR, coordinates and buffers kept on the device)."""
+
+    def __init__(self, graph, p: Params, stream=None):
+        self._lib = load()
+        keep = _Keep()
+        self.p = Params.from_buffer_copy(p)
+        if _device(graph.rowptr):
+            self.p.flags |= BL_DEVICE_PTRS
+        csr = _csr(graph, keep)
+        self.n = csr.n
+        self.h = C.c_void_p()
+        check(self._lib.bl_graph_create(C.byref(csr), C.byref(self.p), _stream(stream), C.byref(self.h)))
+
+    def set_coords(self, x, y):
+        keep = _Keep()
+        flags = BL_DEVICE_PTRS if _device(x, y) else 0
+        check(self._lib.bl_graph_set_coords(self.h, keep.ptr(x, np.float64), keep.ptr(y, np.float64), flags))
+
+    def get_coords(self, out=None):
+        if out is not None:
+            x, y = out
+            check(self._lib.bl_graph_get_coords(self.h, x.data_ptr(), y.data_ptr(), BL_DEVICE_PTRS))
+            return x, y
+        x = np.empty(self.n)
+        y = np.empty(self.n)
+        check(self._lib.bl_graph_get_coords(self.h, x.ctypes.data, y.ctypes.data, 0))
+        return x, y
+
+    def run(self, iterations, start_iter=0, stop_batch=-1, energy=True):
+        """Returns (energy, stats) or, with stop_batch >= 0, (energy, stats, fx, fy)."""
+        en = np.zeros(max(iterations, 1))
+        st = Stats()
+        fx = fy = None
+        fptr = (None, None)
+        if stop_batch >= 0:
+            R = min(self.p.batch_size, self.n - stop_batch * self.p.batch_size)
+            fx = np.zeros(max(R, 1))
+            fy = np.zeros(max(R, 1))
+            fptr = (fx.ctypes.data, fy.ctypes.data)
+        check(self._lib.bl_graph_run(self.h, int(iterations), int(start_iter), int(stop_batch),
+                                     en.ctypes.data if energy else None, fptr[0], fptr[1], C.byref(st)))
+        full = iterations - 1 if stop_batch >= 0 else iterations
+        if stop_batch >= 0:
+            return en[:full], st.as_dict(), fx[:R], fy[:R]
+        return en[:full], st.as_dict()
+
+    def profile(self, enable=True):
+        check(self._lib.bl_graph_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kernel):
+        """(total_ms, launches) of one kernel since profiling was enabled."""
+        ms = C.c_double()
+        cnt = C.c_int64()
+        check(self._lib.bl_graph_profile_read(self.h, kernel.encode(), C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self._lib.bl_graph_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,143 @@
+// Host-side internals of the BatchLayout library: the resident job state and
+// the launchers each kernel file provides.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/batchlayout.h"
+
+namespace bl {
+
+void set_error(const char *fmt, ...);
+
+#define BL_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::bl::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),  \
+                            __FILE__, __LINE__);                                      \
+            return BL_E_HIP;                                                          \
+        }                                                                             \
+    } while (0)
+
+#define BL_TRY(expr)               \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != BL_OK) return rc_; \
+    } while (0)
+
+// Late-leaf list capacity per vertex (Barnes-Hut near field, see bl_bh.hip).
+constexpr int kLateCap = 96;
+
+// Device counters shared by the kernels of one job.
+struct Counters {
+    unsigned long long nonfinite;
+    unsigned long long visits;
+    unsigned long long late_overflow;
+    unsigned long long late_total;
+};
+
+// Per-kernel device time, measured with hipEvents around launches when a
+// job's profiling is on.
+enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_COUNT };
+constexpr int kProfPool = 2048;
+struct Prof {
+    bool on = false;
+    int used = 0;
+    hipEvent_t ev[2 * kProfPool] = {};
+    int kid[kProfPool] = {};
+    double ms[PK_COUNT] = {};
+    long long launches[PK_COUNT] = {};
+    long long late_total = 0;
+};
+
+// Barnes-Hut buffers of one job (all device memory).
+struct BHBuffers {
+    float *bbox;            // [6]: xmin, ymin, W, scale, pad, pad
+    float *bbox_part;       // [2 * 4 * kBBoxBlocks] block partial min/max
+    unsigned *key[2];       // Morton keys, double-buffered for the radix sort
+    int *val[2];            // vertex ids
+    int *hist;              // radix histogram [256 * tiles]
+    int tiles;
+    unsigned *mask;         // [n] per sorted position: bit l set if a kept cell of level l starts here
+    int *cellcnt;           // [n + 1] exclusive scan of popcount(mask)
+    int *scan_part;         // scan block partials
+    double *pdd;            // [4 * (n + 1)]: double-double prefix sums of sorted x, y
+    double *pdd_part;       // [4 * blocks]
+    float4 *nodeA;          // [2n]: cx, cy, side^2 (inf for buckets), count
+    int2 *nodeB;            // [2n]: skip, vertex (-1 for cells)
+    int *leafpos;           // [n]: pre-order index of each vertex's leaf
+    int *nnodes;            // [1]
+    float4 *far;            // [n]: Kahan (sx, sy, cx, cy) of the far-field sum
+    int *late_cnt;          // [n]
+    int *late_ids;          // [n * kLateCap]
+    float *snap;            // [2n] snapshot given to the one-shot force call
+    void *fbuf;             // [BS] float2 net forces of the current batch
+};
+
+// Exact-mode buffers (all device memory).
+struct ExactBuffers {
+    void *accS[2];          // [n] T2 (float2 / double2): per-row repulsion sums, by iteration parity
+    float2 *accC[2];        // [n] Kahan compensation (FP32 Kahan only)
+    void *fbuf;             // [BS] T2 net forces of the batch being finalized
+    unsigned *ticket;       // last-workgroup counter of the finalize kernel
+};
+
+}  // namespace bl
+
+// The resident layout job.
+struct bl_graph {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    bl_params p{};
+    hipStream_t stream = nullptr;
+    bool fp64 = false;
+    int nb = 0;                 // number of batches
+    int *rowptr = nullptr;      // device CSR
+    int *colidx = nullptr;
+    void *x = nullptr;          // device coordinates (float or double)
+    void *y = nullptr;
+    double *erow = nullptr;     // [n] per-vertex |f|^2 of the current iteration
+    double *energy = nullptr;   // [energy_cap] per-iteration energies
+    int energy_cap = 0;
+    double *fout = nullptr;     // [2 * BS] forces of a stopped batch (FP64)
+    double *stage = nullptr;    // [2 * n] FP64 staging for coordinate transfers
+    bl::Counters *counters = nullptr;
+    bl::ExactBuffers ex{};
+    bl::BHBuffers bh{};
+    void *owned[64] = {};       // every device allocation of this job
+    int nowned = 0;
+    bl::Prof *prof = nullptr;   // profiling state (NULL when never enabled)
+};
+
+namespace bl {
+
+int graph_alloc(bl_graph *g, void **ptr, size_t bytes);
+
+// exact mode (bl_exact.hip)
+int exact_alloc(bl_graph *g);
+int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch);
+int exact_forces(bl_graph *g, int batch);
+
+// Barnes-Hut mode (bl_bh.hip)
+int bh_alloc(bl_graph *g);
+int bh_run(bl_graph *g, int iters, int start_iter, int stop_batch);
+int bh_forces(bl_graph *g, int batch, const double *snap_x, const double *snap_y);
+size_t bh_footprint(int n);
+
+// shared kernels (bl_common.hip)
+int energy_sum(bl_graph *g, int k);
+int convert_coords_in(bl_graph *g, const double *x, const double *y);   // device FP64 -> state
+int convert_coords_out(bl_graph *g, double *x, double *y);              // state -> device FP64
+int convert_to_float(bl_graph *g, const double *x, const double *y, float *ox, float *oy);
+
+double step_at(const bl_params &p, int k);
+
+// Profiling around launches (no-ops unless enabled on the job).
+int prof_begin(bl_graph *g, int kid, int *slot);
+int prof_end(bl_graph *g, int slot);
+int prof_collect(bl_graph *g);
+
+}  // namespace bl

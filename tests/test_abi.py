@@ -1,0 +1,104 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host (no device work is started by these calls)."""
+import ctypes as C
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "batchlayout.h")).read()
+    return sorted(set(re.findall(r"\b(bl_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2002_08233_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_2002_08233_amd import _lib
+    names = _declared()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def test_params_defaults_are_the_papers(lib):
+    from paper_2002_08233_amd import api
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_defaults.json")))
+    p = api.Params()
+    assert lib.bl_params_init(C.byref(p)) == 0
+    assert p.batch_size == gold["batch_size"]["value"]
+    assert p.iterations == gold["iterations"]["value"]
+    assert p.step0 == gold["step0"]["value"] and p.step_decay == gold["step_decay"]["value"]
+    assert p.theta == gold["theta"]["value"]
+    assert p.mode == api.BL_EXACT and p.repulse_adjacent == 1 and p.K == 1.0 and p.R == 1.0
+
+
+def _call_layout(lib, g, p):
+    from paper_2002_08233_amd import _lib as L
+    csr = L.CSR()
+    csr.n = g.n
+    csr.nnz = g.nnz
+    rp = np.ascontiguousarray(g.rowptr, np.int32)
+    ci = np.ascontiguousarray(g.colidx, np.int32)
+    csr.rowptr = rp.ctypes.data
+    csr.colidx = ci.ctypes.data if g.nnz else None
+    x = np.zeros(g.n)
+    return lib.bl_layout(C.byref(csr), x.ctypes.data, x.ctypes.data, C.byref(p), None,
+                         x.ctypes.data, x.ctypes.data, None, None)
+
+
+@pytest.mark.parametrize("field,value", [("batch_size", 0), ("iterations", -1), ("K", 0.0), ("R", -1.0),
+                                         ("theta", -0.5), ("step_decay", 1.5), ("mode", 7),
+                                         ("precision", 9), ("step0", 0.0)])
+def test_bad_params_rejected(lib, field, value):
+    from paper_2002_08233_amd import api, inputs
+    p = api.params(iterations=1)
+    setattr(p, field, value)
+    assert _call_layout(lib, inputs.path(5), p) == api.BL_BH * 0 - 1
+    assert lib.bl_last_error()
+
+
+def test_bad_csr_rejected(lib):
+    from paper_2002_08233_amd import api, inputs
+    g = inputs.path(6)
+    bad = inputs.Graph(6, g.rowptr.copy(), g.colidx.copy())
+    bad.colidx[3] = 99                       # out of range: always checked
+    assert _call_layout(lib, bad, api.params(iterations=1)) == -1
+    bad2 = inputs.Graph(6, g.rowptr.copy(), g.colidx.copy())
+    bad2.rowptr[3] = bad2.rowptr[2] - 1      # decreasing row pointer
+    assert _call_layout(lib, bad2, api.params(iterations=1)) == -1
+    bad3 = inputs.Graph(6, g.rowptr.copy(), g.colidx.copy())
+    bad3.colidx[0] = 0                       # self loop: caught with BL_VALIDATE
+    assert _call_layout(lib, bad3, api.params(iterations=1, validate=True)) == -1
+    one = inputs.Graph(0, np.zeros(1, np.int32), np.zeros(0, np.int32))
+    assert _call_layout(lib, one, api.params(iterations=1)) == -1
+
+
+def test_bh_rejects_fp64_and_literal(lib):
+    from paper_2002_08233_amd import api, inputs
+    assert _call_layout(lib, inputs.path(5), api.params(iterations=1, mode="bh", precision="fp64")) == -1
+    assert _call_layout(lib, inputs.path(5), api.params(iterations=1, mode="bh", repulse_adjacent=False)) == -1
+
+
+def test_footprint_grows_with_size(lib):
+    from paper_2002_08233_amd import api
+    p = api.params(mode="bh")
+    a = api.footprint_bytes(1000, 8000, p)
+    b = api.footprint_bytes(100000, 800000, p)
+    assert 0 < a < b
+    assert api.footprint_bytes(0, 0, p) == 0
+    e = api.footprint_bytes(100000, 800000, api.params(mode="exact"))
+    assert 0 < e < b

@@ -1,0 +1,150 @@
+"""Exact-mode parity: the HIP path against the FP64 oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_08233_amd import api, inputs as I
+from _parity import (RUN_TOL, SETTLING, assert_forces, assert_within_oracle_spread, force_errors,
+                     near_grid_init, quality)
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(a):
+    return I.to_f32_representable(a)
+
+
+def _rand_graph(n, p, seed):
+    r = I.rng(seed)
+    iu = np.triu_indices(n, 1)
+    keep = r.random(len(iu[0])) < p
+    return I.csr_from_edges(n, iu[0][keep], iu[1][keep])
+
+
+@pytest.fixture(scope="module")
+def grid32():
+    w = I.workload_grid32()
+    w["x0"], w["y0"] = _f32(w["x0"]), _f32(w["y0"])
+    return w
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp32", "fp64"])
+@pytest.mark.parametrize("batch", [0, 3, 7])
+def test_one_shot_forces(grid32, precision, batch):
+    g, x, y = grid32["graph"], grid32["x0"], grid32["y0"]
+    p = api.params(batch_size=128, iterations=1, precision=precision)
+    fx, fy = api.forces(g, x, y, batch, p)
+    ref = oracle.forces_exact(g.rowptr, g.colidx, x, y, batch * 128, batch * 128 + 128)
+    r = assert_forces(fx, fy, ref, what=precision)
+    if precision == "fp64":
+        assert r["rel_max"] < 1e-12
+
+
+@pytest.mark.parametrize("iters,stop", [(1, 1), (1, 5), (2, 0), (3, 6)])
+def test_pipeline_step_forces(grid32, iters, stop):
+    """Forces of batch `stop` after the pipelined panels of earlier steps,
+    checked on the exact state they were computed from."""
+    g = grid32["graph"]
+    p = api.params(batch_size=128, iterations=iters)
+    with api.Graph(g, p) as h:
+        h.set_coords(grid32["x0"], grid32["y0"])
+        _, _, fx, fy = h.run(iters, stop_batch=stop)
+        xs, ys = h.get_coords()
+    ref = oracle.forces_exact(g.rowptr, g.colidx, xs, ys, stop * 128, stop * 128 + 128)
+    assert_forces(fx, fy, ref, what="pipeline k=%d b=%d" % (iters - 1, stop))
+
+
+@pytest.mark.parametrize("n,bs,lit", [(1000, 96, True), (257, 64, False), (300, 512, True), (40, 1, True),
+                                      (130, 7, False)])
+def test_ragged_and_literal(n, bs, lit):
+    g = _rand_graph(n, 6.0 / n, n + bs)
+    x0, y0 = I.uniform_coords(n, 3)
+    x0, y0 = _f32(x0), _f32(y0)
+    nb = (n + bs - 1) // bs
+    stop = nb - 1                       # the ragged last batch
+    p = api.params(batch_size=bs, iterations=2, repulse_adjacent=lit)
+    with api.Graph(g, p) as h:
+        h.set_coords(x0, y0)
+        _, _, fx, fy = h.run(2, stop_batch=stop)
+        xs, ys = h.get_coords()
+    ref = oracle.forces_exact(g.rowptr, g.colidx, xs, ys, stop * bs, n, repulse_adjacent=lit)
+    assert len(fx) == n - stop * bs
+    assert_forces(fx, fy, ref)
+
+
+def test_single_vertex_and_no_edges():
+    g1 = I.csr_from_edges(1, np.array([], np.int64), np.array([], np.int64))
+    x, y, e, st = api.layout(g1, np.array([0.5]), np.array([-0.25]), api.params(batch_size=4, iterations=3))
+    assert x[0] == 0.5 and y[0] == -0.25 and np.all(e == 0)
+    g0 = I.csr_from_edges(50, np.array([], np.int64), np.array([], np.int64))
+    x0, y0 = I.uniform_coords(50, 9)
+    x0, y0 = _f32(x0), _f32(y0)
+    fx, fy = api.forces(g0, x0, y0, 0, api.params(batch_size=50))
+    ref = oracle.forces_exact(g0.rowptr, g0.colidx, x0, y0, 0, 50)
+    assert_forces(fx, fy, ref)
+
+
+def test_full_run_fp64_tracks_oracle():
+    """FP64 on the GPU against the FP64 oracle, the paper's schedule, 100 iterations."""
+    g = I.grid(32, 32)
+    x0, y0 = near_grid_init(32, 32)
+    xg, yg, eg, st = api.layout(g, x0, y0, api.params(batch_size=128, iterations=100, precision="fp64"))
+    xo, yo, eo = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 128, 100)
+    qg, qo = quality(oracle, g, xg, yg), quality(oracle, g, xo, yo)
+    assert abs(qg[0] / qo[0] - 1) <= 1e-6 and abs(qg[1] / qo[1] - 1) <= 1e-6, (qg, qo)
+    assert np.allclose(eg, eo, rtol=1e-8)
+    assert st["iters_run"] == 100 and st["nonfinite_events"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp32"])
+def test_full_run_settling_schedule_within_one_percent(precision):
+    """FP32 run on a schedule that settles: stress and edge energy within 1%."""
+    g = I.grid(32, 32)
+    x0, y0 = near_grid_init(32, 32)
+    p = api.params(batch_size=128, iterations=100, precision=precision, **SETTLING)
+    xg, yg, eg, st = api.layout(g, x0, y0, p)
+    xo, yo, eo = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 128, 100, step0=SETTLING["step0"],
+                                     decay=SETTLING["step_decay"])
+    qg, qo = quality(oracle, g, xg, yg), quality(oracle, g, xo, yo)
+    assert abs(qg[0] / qo[0] - 1) <= RUN_TOL and abs(qg[1] / qo[1] - 1) <= RUN_TOL, (qg, qo)
+    assert np.allclose(eg, eo, rtol=1e-3)
+
+
+def test_full_run_random_start_within_oracle_spread(grid32):
+    """The 32x32 grid workload (random start, 100 iterations, batch 128)."""
+    g = grid32["graph"]
+    x0, y0 = grid32["x0"], grid32["y0"]
+    xg, yg, eg, st = api.layout(g, x0, y0, api.params(batch_size=128, iterations=100))
+    rep = assert_within_oracle_spread(
+        oracle, g, xg, yg, lambda a, b: oracle.layout_exact(g.rowptr, g.colidx, a, b, 128, 100)[:2], x0, y0)
+    print("grid32 exact full run:", rep)
+    _, _, eo = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 128, 100)
+    assert abs(eg[0] / eo[0] - 1) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp64"])
+def test_resume_is_bitwise_and_runs_repeat(grid32, precision):
+    g = grid32["graph"]
+    p = api.params(batch_size=128, iterations=10, precision=precision)
+    xa, ya, ea, _ = api.layout(g, grid32["x0"], grid32["y0"], p)
+    xb, yb, eb, _ = api.layout(g, grid32["x0"], grid32["y0"], p)
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+    with api.Graph(g, p) as h:
+        h.set_coords(grid32["x0"], grid32["y0"])
+        e1, _ = h.run(4, start_iter=0)
+        e2, _ = h.run(6, start_iter=4)
+        xc, yc = h.get_coords()
+    assert np.array_equal(xa, xc) and np.array_equal(ya, yc)
+    assert np.array_equal(ea, np.concatenate([e1, e2]))
+
+
+def test_device_pointer_path(grid32):
+    import torch
+    g = grid32["graph"]
+    dev = I.Graph(g.n, torch.as_tensor(g.rowptr, device="cuda"), torch.as_tensor(g.colidx, device="cuda"))
+    x0 = torch.as_tensor(grid32["x0"], device="cuda")
+    y0 = torch.as_tensor(grid32["y0"], device="cuda")
+    p = api.params(batch_size=128, iterations=5)
+    xd, yd, ed, _ = api.layout(dev, x0, y0, p)
+    xh, yh, eh, _ = api.layout(g, grid32["x0"], grid32["y0"], p)
+    assert np.array_equal(xd.cpu().numpy(), xh) and np.array_equal(yd.cpu().numpy(), yh)

@@ -448,11 +448,21 @@ def _py_bh_force(x, y, i, theta, K=1.0, R=1.0):
 
 
 @pytest.mark.parametrize("theta", [0.5, 1.2, 2.5])
-def test_bh_matches_independent_geometric_walk(theta):
+@pytest.mark.parametrize("clustered", [False, True])
+def test_bh_matches_independent_geometric_walk(theta, clustered):
+    """Also with groups of distinct points inside one finest cell: the cells
+    above such a group hold the same members and may be accepted."""
     r = I.rng(91)
     n = 60
-    x = r.uniform(-1, 1, n).astype(np.float32).astype(np.float64)
-    y = r.uniform(-1, 1, n).astype(np.float32).astype(np.float64)
+    x = r.uniform(-1, 1, n)
+    y = r.uniform(-1, 1, n)
+    if clustered:
+        x[:8] = 0.3 + np.arange(8) * 2e-7
+        y[:8] = -0.4
+        x[8:12] = -0.7
+        y[8:12] = 0.1 + np.arange(4) * 3e-7
+    x = x.astype(np.float32).astype(np.float64)
+    y = y.astype(np.float32).astype(np.float64)
     g = I.csr_from_edges(n, np.array([], np.int64), np.array([], np.int64))
     t = oracle.Tree(x, y)
     f = oracle.forces_bh(g.rowptr, g.colidx, x, y, t, 0, n, theta=theta)
