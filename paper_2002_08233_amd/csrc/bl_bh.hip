@@ -592,173 +592,401 @@ __global__ __launch_bounds__(256) void far_kernel(WalkArgs a, const int *__restr
     }
 }
 
+// ------------------------------------------------------- early attraction
+// Neighbours j in batches >= batch(i) have not moved when batch(i) comes up,
+// so their attraction terms (Sec. 2.2, a = 2: d * delta / K) can be summed
+// for all vertices at once from the snapshot.  Sorted CSR rows make the moved
+// ("late") neighbours a prefix of each row; its length is fixed per graph.
+constexpr int kHeavyRow = 256;   // early entries above which a whole workgroup sums the row
+
+__global__ void late_prefix_kernel(int n, int BS, const int *__restrict__ rowptr,
+                                   const int *__restrict__ colidx, int *__restrict__ late_att,
+                                   int *__restrict__ heavy, int *__restrict__ nheavy) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int bstart = (i / BS) * BS;
+    int lo = rowptr[i], hi = rowptr[i + 1];   // first entry with colidx >= bstart
+    const int end = hi;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (colidx[mid] < bstart) lo = mid + 1;
+        else hi = mid;
+    }
+    late_att[i] = lo - rowptr[i];
+    if (end - lo > kHeavyRow) heavy[atomicAdd(nheavy, 1)] = i;
+}
+
+// Light rows: 8 lanes per row.
+__global__ __launch_bounds__(256) void att_early_kernel(int n, float invK, const int *__restrict__ rowptr,
+                                                        const int *__restrict__ colidx,
+                                                        const int *__restrict__ late_att,
+                                                        const float *__restrict__ x,
+                                                        const float *__restrict__ y,
+                                                        float2 *__restrict__ atte) {
+    const int g8 = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int sub = threadIdx.x & 7;
+    const int i = g8;
+    if (i >= n) return;
+    const int e0 = rowptr[i] + late_att[i], e1 = rowptr[i + 1];
+    if (e1 - e0 > kHeavyRow) return;     // summed by att_heavy_kernel
+    const float xi = x[i], yi = y[i];
+    float ax = 0.f, ay = 0.f;
+    for (int e = e0 + sub; e < e1; e += 8) {
+        const int j = colidx[e];
+        const float dx = x[j] - xi, dy = y[j] - yi;
+        const float d = sqrtf(dx * dx + dy * dy) * invK;
+        ax = fmaf(d, dx, ax);
+        ay = fmaf(d, dy, ay);
+    }
+    ax = group_sum<8>(ax);
+    ay = group_sum<8>(ay);
+    if (sub == 0) atte[i] = float2{ax, ay};
+}
+
+// Heavy rows: one workgroup per row, reduced in a fixed order.
+__global__ __launch_bounds__(256) void att_heavy_kernel(const int *__restrict__ heavy, const int *__restrict__ nheavy,
+                                                        float invK, const int *__restrict__ rowptr,
+                                                        const int *__restrict__ colidx,
+                                                        const int *__restrict__ late_att,
+                                                        const float *__restrict__ x,
+                                                        const float *__restrict__ y,
+                                                        float2 *__restrict__ atte) {
+    __shared__ float wsx[4], wsy[4];
+    for (int h = blockIdx.x; h < *nheavy; h += gridDim.x) {
+        const int i = heavy[h];
+        const int e0 = rowptr[i] + late_att[i], e1 = rowptr[i + 1];
+        const float xi = x[i], yi = y[i];
+        float ax = 0.f, ay = 0.f;
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+            const int j = colidx[e];
+            const float dx = x[j] - xi, dy = y[j] - yi;
+            const float d = sqrtf(dx * dx + dy * dy) * invK;
+            ax = fmaf(d, dx, ax);
+            ay = fmaf(d, dy, ay);
+        }
+        ax = wave_sum(ax);
+        ay = wave_sum(ay);
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            wsx[threadIdx.x / kWave] = ax;
+            wsy[threadIdx.x / kWave] = ay;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atte[i] = float2{((wsx[0] + wsx[1]) + wsx[2]) + wsx[3], ((wsy[0] + wsy[1]) + wsy[2]) + wsy[3]};
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- chain
+// ------------------------------------------------------- late entry lists
+// Everything a minibatch step needs that does not depend on moves is laid out
+// before the chain starts: per batch, the "late" entries -- moved neighbours
+// (the CSR prefix) and listed moved leaves -- of all its rows, row by row, as
+// (row in batch << 32 | vertex) words, plus each row's offset in that list.
+constexpr int kMaxChainRows = 2048;   // batch-size limit of the Barnes-Hut chain
+constexpr int kEnt = 8;               // late entries per thread per pass (held in registers)
+
+__device__ __forceinline__ int late_leaf_count(int lc) { return lc > kLateCap ? 0 : lc; }
+
+// Per batch: entry counts of its rows -> exclusive offsets within the batch.
+__global__ __launch_bounds__(1024) void batch_offsets_kernel(int n, int BS, const int *__restrict__ late_att,
+                                                              const int *__restrict__ rowptr,
+                                                              const int *__restrict__ late_cnt,
+                                                              int all_late, int *__restrict__ roff,
+                                                              int *__restrict__ btot) {
+    __shared__ int ws[16];
+    const int b = blockIdx.x;
+    const int R = min(BS, n - b * BS);
+    int carry = 0;
+    for (int r0 = 0; r0 < R; r0 += 1024) {
+        const int r = r0 + (int)threadIdx.x;
+        int c = 0;
+        if (r < R) {
+            const int i = b * BS + r;
+            const int la = all_late ? rowptr[i + 1] - rowptr[i] : late_att[i];
+            c = la + late_leaf_count(late_cnt[i]);
+        }
+        int tot;
+        const int off = block_excl_scan(c, ws, &tot);
+        if (r < R) roff[b * BS + r] = carry + off;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) btot[b] = carry;
+}
+
+// 8 lanes per row copy its late entries into the batch list; listed leaves
+// (repulsion terms) carry bit 31 of the vertex word, moved neighbours
+// (attraction terms) do not.
+__global__ __launch_bounds__(256) void late_fill_kernel(int n, int BS, const int *__restrict__ late_att,
+                                                        const int *__restrict__ rowptr,
+                                                        const int *__restrict__ colidx,
+                                                        const int *__restrict__ late_cnt,
+                                                        const int *__restrict__ late_ids, int all_late,
+                                                        const int *__restrict__ roff,
+                                                        const int *__restrict__ bbase,
+                                                        unsigned long long *__restrict__ ent) {
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int sub = threadIdx.x & 7;
+    if (i >= n) return;
+    const int b = i / BS;
+    const unsigned long long rbits = (unsigned long long)(i - b * BS) << 32;
+    const size_t base = (size_t)bbase[b] + roff[i];
+    const int rs = rowptr[i];
+    const int la = all_late ? rowptr[i + 1] - rs : late_att[i];
+    for (int k = sub; k < la; k += 8) ent[base + k] = rbits | (unsigned)colidx[rs + k];
+    const int ll = late_leaf_count(late_cnt[i]);
+    const int *lid = late_ids + (size_t)i * kLateCap;
+    for (int k = sub; k < ll; k += 8) ent[base + la + k] = rbits | 0x80000000u | (unsigned)lid[k];
+}
+
 // ---------------------------------------------------------------- chain
 struct ChainArgs {
     WalkArgs w;
     int nb_run;          // batches to process with updates
     int stop_batch;      // batch whose forces go to fout without update (-1: none)
     int first_batch;     // usually 0; the force call processes only `stop_batch`
-    const int *rowptr, *colidx;
     float *x, *y;
     const float4 *far;
-    const int *late_cnt, *late_ids;
-    float2 *fbuf;        // [BS]
+    const float2 *atte;  // early attraction (NULL: none)
+    const int *late_cnt;
+    const int *roff;     // [n] offset of each row's entries in its batch list
+    const int *bbase;    // [nb+1] start of each batch list in ent
+    const unsigned long long *ent;
+    size_t ent_cap;      // entries allocated in ent
     double *fout;        // [2*BS]
     double *energy_k;
     Counters *ctr;
     float step;
 };
 
-// Net forces of the rows [r0, r0 + R) of batch b into fbuf: entries (CSR
-// neighbours, then listed late leaves) are split evenly over the threads
-// (merge-path), each thread sums its run row by row, and rows cut by thread
-// boundaries are completed from the per-thread carries in thread order.
-__device__ void chain_rows(const ChainArgs &a, int b, int r0, int R, int *s_off, int *s_row,
-                           int *s_deg, int *s_lat, float2 *s_sum, float2 *s_cf, float2 *s_cl, int *ws) {
-    const int tid = threadIdx.x;
-    const int BS = a.w.BS;
-    int cnt = 0, rs = 0, lc = 0;
-    if (tid < R) {
-        const int i = b * BS + r0 + tid;
-        rs = a.rowptr[i];
-        const int deg = a.rowptr[i + 1] - rs;
-        lc = a.late_cnt[i];
-        if (lc > kLateCap) lc = -1;   // overflowed: full walk below
-        cnt = deg + (lc > 0 ? lc : 0);
-        s_row[tid] = rs;
-        s_deg[tid] = deg;
-        s_lat[tid] = lc;
-    }
-    int E;
-    const int off = block_excl_scan(cnt, ws, &E);
-    if (tid < R) s_off[tid] = off;
-    if (tid == 0) s_off[R] = E;
-    __syncthreads();
-    const int chunk = (E + kChainThreads - 1) / kChainThreads;
-    const int e0 = min(tid * chunk, E), e1 = min(e0 + chunk, E);
-    if (e0 < e1) {
-        int lo = 0, hi = R - 1;   // last r with s_off[r] <= e0
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= e0) lo = mid;
-            else hi = mid - 1;
-        }
-        int r = lo;
-        int i = b * BS + r0 + r;
-        float xi = a.x[i], yi = a.y[i];
-        float ax = 0.f, ay = 0.f;
-        bool first = true;
-        for (int e = e0; e < e1; ++e) {
-            while (e >= s_off[r + 1]) {
-                const bool full = s_off[r] >= e0 && s_off[r + 1] <= e1;
-                if (full) s_sum[r] = float2{ax, ay};
-                else if (first) s_cf[tid] = float2{ax, ay};
-                else s_cl[tid] = float2{ax, ay};
-                first = false;
-                ax = ay = 0.f;
-                ++r;
-                i = b * BS + r0 + r;
-                xi = a.x[i];
-                yi = a.y[i];
-            }
-            const int loc = e - s_off[r];
-            const int deg = s_deg[r];
-            if (loc < deg) {
-                const int j = a.colidx[s_row[r] + loc];
-                const float dx = a.x[j] - xi, dy = a.y[j] - yi;
-                const float d = sqrtf(dx * dx + dy * dy) * a.w.invK;
-                ax = fmaf(d, dx, ax);
-                ay = fmaf(d, dy, ay);
-            } else {
-                const int j = a.late_ids[(size_t)i * kLateCap + (loc - deg)];
-                const float dx = a.x[j] - xi, dy = a.y[j] - yi;
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-                const float inv = __builtin_amdgcn_rcpf(d2) * a.w.negRK2;
-                ax = fmaf(dx, inv, ax);
-                ay = fmaf(dy, inv, ay);
-            }
-        }
-        const bool full = s_off[r] >= e0 && s_off[r + 1] <= e1;
-        if (full) s_sum[r] = float2{ax, ay};
-        else if (first) s_cf[tid] = float2{ax, ay};
-        else s_cl[tid] = float2{ax, ay};
-    }
-    __syncthreads();
-    if (tid < R) {
-        const int o0 = s_off[tid], o1 = s_off[tid + 1];
-        float2 s{0.f, 0.f};
-        if (o1 > o0 && chunk > 0) {
-            const int t0 = o0 / chunk, t1 = (o1 - 1) / chunk;
-            if (t0 == t1) {
-                s = s_sum[tid];
-            } else {
-                s = (o0 == t0 * chunk) ? s_cf[t0] : s_cl[t0];
-                for (int t = t0 + 1; t <= t1; ++t) {
-                    s.x += s_cf[t].x;
-                    s.y += s_cf[t].y;
-                }
-            }
-        }
-        const int i = b * BS + r0 + tid;
-        float4 fr;
-        if (s_lat[tid] < 0) {
-            // late list overflowed: walk the whole tree with live leaves
-            int dummy = 0;
-            (void)bh_walk(a.w, i, a.x[i], a.y[i], 0, a.x, a.y, fr, nullptr, dummy, 0);
-        } else {
-            fr = a.far[i];
-        }
-        const float rx = fr.x - fr.z, ry = fr.y - fr.w;
-        a.fbuf[r0 + tid] = float2{s.x + a.w.negRK2 * rx, s.y + a.w.negRK2 * ry};
-    }
-    __syncthreads();
+// Per-row data of a step, requested one step ahead.  Loads are unconditional
+// with clamped indices so that a step's prefetch is straight-line code.
+struct ChainRow {
+    int o0, o1;          // entry range of the row in its batch list
+    int ovf;             // late-leaf list overflowed: walk the whole tree live
+    float x, y;
+    float4 far;
+    float2 atte;
+};
+
+__device__ __forceinline__ ChainRow chain_row(const ChainArgs &a, int b, int r, int R) {
+    ChainRow d;
+    const int rc = min(r, R - 1);
+    const int i = b * a.w.BS + rc;
+    const int E = a.bbase[b + 1] - a.bbase[b];
+    d.o0 = a.roff[i];
+    const int nxt = a.roff[min(i + 1, a.w.n - 1)];
+    d.o1 = (rc + 1 < R) ? nxt : E;
+    d.ovf = a.late_cnt[i] > kLateCap;
+    d.x = a.x[i];
+    d.y = a.y[i];
+    d.far = a.far[i];
+    d.atte = a.atte ? a.atte[i] : float2{0.f, 0.f};
+    return d;
 }
 
+struct ChainShared {
+    int off[2][kMaxChainRows + 1];
+    float px[2][kMaxChainRows];
+    float py[2][kMaxChainRows];
+    float2 sum[kMaxChainRows];   // rows complete inside one thread's run
+    float2 cf[kChainThreads];    // first (partial) row of each thread's run
+    float2 cl[kChainThreads];    // last (partial) row of each thread's run
+    double wsd[16];
+};
+
+// The minibatch chain: one workgroup walks the batches in order.  Per step b:
+//   - each thread gathers the live positions of the first late entries of its
+//     run (entry words were loaded one step ahead), then requests the next
+//     step's row data and entry words (they do not depend on this step's
+//     moves; issued after the gathers so that waiting for the gathers does
+//     not wait for them), then sums its run row by row;
+//   - rows cut by thread boundaries are completed from per-thread carries in
+//     thread order; early attraction and the far field are added, and the
+//     thread owning the row moves it (Alg. 2 update loop; Jacobi within the
+//     batch because every gather of the batch precedes the barrier).
 __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
-    __shared__ int s_off[kChainThreads + 1];
-    __shared__ int s_row[kChainThreads];
-    __shared__ int s_deg[kChainThreads];
-    __shared__ int s_lat[kChainThreads];
-    __shared__ float2 s_sum[kChainThreads];
-    __shared__ float2 s_cf[kChainThreads];
-    __shared__ float2 s_cl[kChainThreads];
-    __shared__ int ws[16];
-    __shared__ double wsd[16];
+    __shared__ ChainShared S;
+    const int tid = threadIdx.x;
     const int BS = a.w.BS, n = a.w.n;
     const int last = a.stop_batch >= 0 ? a.stop_batch : a.nb_run - 1;
-    for (int b = a.first_batch; b <= last; ++b) {
+    const float invK = a.w.invK, negRK2 = a.w.negRK2;
+    constexpr int RPT = kMaxChainRows / kChainThreads;   // rows per thread
+    const size_t entmax = a.ent_cap - 1;
+
+    ChainRow rowd[RPT];
+    unsigned long long pe[kEnt];
+    auto fetch_regs = [&](int b) {
         const int R = min(BS, n - b * BS);
-        for (int r0 = 0; r0 < R; r0 += kChainThreads)
-            chain_rows(a, b, r0, min(kChainThreads, R - r0), s_off, s_row, s_deg, s_lat, s_sum, s_cf,
-                       s_cl, ws);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k)
+            if (tid + k * kChainThreads < R) rowd[k] = chain_row(a, b, tid + k * kChainThreads, R);
+        const int E = a.bbase[b + 1] - a.bbase[b];
+        const int chunk = (E + kChainThreads - 1) / kChainThreads;
+        const int e0 = min(tid * chunk, E), e1 = min(e0 + chunk, E);
+        const size_t gb = (size_t)a.bbase[b];
+#pragma unroll
+        for (int q = 0; q < kEnt; ++q)
+            if (e0 + q < e1) pe[q] = a.ent[min(gb + (size_t)(e0 + q), entmax)];
+    };
+    auto fetch_lds = [&](int b, int slot) {
+        const int R = min(BS, n - b * BS);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int r = tid + k * kChainThreads;
+            if (r < R) {
+                S.off[slot][r] = rowd[k].o0;
+                S.px[slot][r] = rowd[k].x;
+                S.py[slot][r] = rowd[k].y;
+            }
+        }
+        if (tid == 0) S.off[slot][R] = a.bbase[b + 1] - a.bbase[b];
+    };
+    if (a.first_batch <= last) {
+        fetch_regs(a.first_batch);
+        fetch_lds(a.first_batch, a.first_batch & 1);
+    }
+    __syncthreads();
+
+    double e_iter = 0.0;
+    unsigned long long bad = 0;
+    for (int b = a.first_batch; b <= last; ++b) {
+        const int slot = b & 1;
+        const int R = min(BS, n - b * BS);
+        const int E = S.off[slot][R];
+        const int chunk = (E + kChainThreads - 1) / kChainThreads;
+        const int e0 = min(tid * chunk, E), e1 = min(e0 + chunk, E);
+        ChainRow cur[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) cur[k] = rowd[k];
+        unsigned long long ce[kEnt];
+#pragma unroll
+        for (int q = 0; q < kEnt; ++q) ce[q] = pe[q];
+
+        // gathers of the first pass (only real entries: every lane's gather
+        // costs a cache-line lookup in this CU's address unit)
+        const int m0 = min(kEnt, e1 - e0);
+        float xj[kEnt], yj[kEnt];
+#pragma unroll
+        for (int q = 0; q < kEnt; ++q) {
+            xj[q] = 0.f;
+            yj[q] = 0.f;
+            if (q < m0) {
+                const int j = (int)((unsigned)ce[q] & 0x7fffffffu);
+                xj[q] = a.x[j];
+                yj[q] = a.y[j];
+            }
+        }
+        // next step's data (clamped to the last batch on the final step)
+        fetch_regs(min(b + 1, last));
+
+        if (e0 < e1) {
+            const unsigned long long *src = a.ent + a.bbase[b];
+            int r = (int)(ce[0] >> 32);
+            float ax = 0.f, ay = 0.f;
+            bool first = true;
+            for (int base = e0; base < e1; base += kEnt) {
+                const int m = min(kEnt, e1 - base);
+                if (base != e0) {
+#pragma unroll
+                    for (int q = 0; q < kEnt; ++q)
+                        if (q < m) ce[q] = src[base + q];
+#pragma unroll
+                    for (int q = 0; q < kEnt; ++q) {
+                        if (q < m) {
+                            const int j = (int)((unsigned)ce[q] & 0x7fffffffu);
+                            xj[q] = a.x[j];
+                            yj[q] = a.y[j];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kEnt; ++q) {
+                    if (q < m) {
+                        const int rq = (int)(ce[q] >> 32);
+                        if (rq != r) {
+                            const bool full = S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1;
+                            if (full) S.sum[r] = float2{ax, ay};
+                            else if (first) S.cf[tid] = float2{ax, ay};
+                            else S.cl[tid] = float2{ax, ay};
+                            first = false;
+                            ax = ay = 0.f;
+                            r = rq;
+                        }
+                        const float dx = xj[q] - S.px[slot][r], dy = yj[q] - S.py[slot][r];
+                        if (((unsigned)ce[q] & 0x80000000u) == 0u) {
+                            // moved neighbour: attraction d * delta / K
+                            const float d = sqrtf(dx * dx + dy * dy) * invK;
+                            ax = fmaf(d, dx, ax);
+                            ay = fmaf(d, dy, ay);
+                        } else {
+                            // moved leaf: repulsion -R K^2 delta / d^2
+                            const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+                            const float inv = __builtin_amdgcn_rcpf(d2) * negRK2;
+                            ax = fmaf(dx, inv, ax);
+                            ay = fmaf(dy, inv, ay);
+                        }
+                    }
+                }
+            }
+            const bool full = S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1;
+            if (full) S.sum[r] = float2{ax, ay};
+            else if (first) S.cf[tid] = float2{ax, ay};
+            else S.cl[tid] = float2{ax, ay};
+        }
+        __syncthreads();
+
+        // complete my rows, add early attraction and far field, move them
         const bool stop = (b == a.stop_batch);
-        double e = 0.0;
-        unsigned long long bad = 0;
-        for (int q = threadIdx.x; q < R; q += kChainThreads) {
-            const float2 f = a.fbuf[q];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int r = tid + k * kChainThreads;
+            if (r >= R) continue;
+            const int o0 = cur[k].o0, o1 = cur[k].o1;
+            float2 sm{0.f, 0.f};
+            if (o1 > o0) {
+                const int t0 = o0 / chunk, t1 = (o1 - 1) / chunk;
+                if (t0 == t1) {
+                    sm = S.sum[r];
+                } else {
+                    sm = (o0 == t0 * chunk) ? S.cf[t0] : S.cl[t0];
+                    for (int t = t0 + 1; t <= t1; ++t) {
+                        sm.x += S.cf[t].x;
+                        sm.y += S.cf[t].y;
+                    }
+                }
+            }
+            const int i = b * BS + r;
+            float4 fr = cur[k].far;
+            if (cur[k].ovf) {
+                int dummy = 0;
+                (void)bh_walk(a.w, i, cur[k].x, cur[k].y, 0, a.x, a.y, fr, nullptr, dummy, 0);
+            }
+            const float fx = (sm.x + cur[k].atte.x) + negRK2 * (fr.x - fr.z);
+            const float fy = (sm.y + cur[k].atte.y) + negRK2 * (fr.y - fr.w);
             if (stop) {
-                a.fout[2 * q] = (double)f.x;
-                a.fout[2 * q + 1] = (double)f.y;
+                a.fout[2 * r] = (double)fx;
+                a.fout[2 * r + 1] = (double)fy;
                 continue;
             }
-            const double f2 = (double)f.x * f.x + (double)f.y * f.y;
+            const double f2 = (double)fx * fx + (double)fy * fy;
             if (!isfinite(f2)) {
                 ++bad;
                 continue;
             }
-            e += f2;
+            e_iter += f2;
             if (f2 > 0.0) {
-                const int i = b * BS + q;
-                const float sc = a.step / sqrtf(f.x * f.x + f.y * f.y);
-                a.x[i] = a.x[i] + sc * f.x;
-                a.y[i] = a.y[i] + sc * f.y;
+                const float sc = a.step / sqrtf(fx * fx + fy * fy);
+                a.x[i] = cur[k].x + sc * fx;
+                a.y[i] = cur[k].y + sc * fy;
             }
         }
-        if (bad) atomicAdd(&a.ctr->nonfinite, bad);
-        e = block_sum_fixed(e, wsd);
-        if (threadIdx.x == 0 && !stop && a.energy_k) *a.energy_k = (b == 0 ? 0.0 : *a.energy_k) + e;
+        if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1);
         __syncthreads();
     }
+    if (bad) atomicAdd(&a.ctr->nonfinite, bad);
+    const double e = block_sum_fixed(e_iter, S.wsd);
+    if (tid == 0 && a.energy_k) *a.energy_k = e;
 }
 
 // ------------------------------------------------------------- host side
@@ -815,6 +1043,26 @@ WalkArgs walk_args(bl_graph *g) {
     return w;
 }
 
+// Moved-neighbour prefix lengths (once per job) and the early attraction.
+int early_pass(bl_graph *g) {
+    BHBuffers &h = g->bh;
+    const int n = g->n;
+    if (!h.prefix_ready) {
+        BL_HIP(hipMemsetAsync(h.nheavy, 0, sizeof(int), g->stream));
+        hipLaunchKernelGGL(late_prefix_kernel, dim3((n + 255) / 256), dim3(256), 0, g->stream, n,
+                           g->p.batch_size, g->rowptr, g->colidx, h.late_att, h.heavy, h.nheavy);
+        BL_HIP(hipGetLastError());
+        h.prefix_ready = true;
+    }
+    const float invK = (float)(1.0 / g->p.K);
+    hipLaunchKernelGGL(att_early_kernel, dim3((n + 31) / 32), dim3(256), 0, g->stream, n, invK, g->rowptr,
+                       g->colidx, h.late_att, (const float *)g->x, (const float *)g->y, h.atte);
+    hipLaunchKernelGGL(att_heavy_kernel, dim3(256), dim3(256), 0, g->stream, h.heavy, h.nheavy, invK,
+                       g->rowptr, g->colidx, h.late_att, (const float *)g->x, (const float *)g->y, h.atte);
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
 // Far-field walks of all vertices; (px, py) are the vertices' own positions.
 int far_pass(bl_graph *g, const WalkArgs &w, const float *px, const float *py, int all_live) {
     const int snap = (g->p.flags & BL_BH_SNAPSHOT_LEAVES) ? 1 : 0;
@@ -826,21 +1074,37 @@ int far_pass(bl_graph *g, const WalkArgs &w, const float *px, const float *py, i
     return prof_end(g, slot);
 }
 
+// Late entry lists of all batches (needs the far pass's late-leaf counts).
+int late_lists(bl_graph *g, bool all_late) {
+    BHBuffers &h = g->bh;
+    const int n = g->n, BS = g->p.batch_size, nb = g->nb;
+    hipLaunchKernelGGL(batch_offsets_kernel, dim3(nb), dim3(1024), 0, g->stream, n, BS, h.late_att, g->rowptr,
+                       h.late_cnt, all_late ? 1 : 0, h.roff, h.bbase);
+    BL_HIP(hipMemsetAsync(h.bbase + nb, 0, sizeof(int), g->stream));
+    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, g->stream, h.bbase, nb + 1);
+    hipLaunchKernelGGL(late_fill_kernel, dim3((n + 31) / 32), dim3(256), 0, g->stream, n, BS, h.late_att,
+                       g->rowptr, g->colidx, h.late_cnt, h.late_ids, all_late ? 1 : 0, h.roff, h.bbase,
+                       h.ent);
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
 int chain(bl_graph *g, const WalkArgs &w, int first_batch, int nb_run, int stop_batch, int k,
-          double *energy_k) {
+          double *energy_k, bool early) {
     ChainArgs a;
     a.w = w;
     a.nb_run = nb_run;
     a.stop_batch = stop_batch;
     a.first_batch = first_batch;
-    a.rowptr = g->rowptr;
-    a.colidx = g->colidx;
     a.x = (float *)g->x;
     a.y = (float *)g->y;
     a.far = g->bh.far;
+    a.atte = early ? g->bh.atte : nullptr;
     a.late_cnt = g->bh.late_cnt;
-    a.late_ids = g->bh.late_ids;
-    a.fbuf = (float2 *)g->bh.fbuf;
+    a.roff = g->bh.roff;
+    a.bbase = g->bh.bbase;
+    a.ent = g->bh.ent;
+    a.ent_cap = (size_t)g->nnz + (size_t)g->n * kLateCap;
     a.fout = g->fout;
     a.energy_k = energy_k;
     a.ctr = g->counters;
@@ -860,7 +1124,7 @@ size_t bh_footprint(int n) {
     const size_t sblocks = (N + kScanTile - 1) / kScanTile;
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
-           4 * N * kLateCap + 8 * N + 8 * 1024;
+           4 * N * kLateCap + 8 * N + 8 * 1024 + 16 * N + 16 + 4 * N + 4 * N + 8 * N * kLateCap;
 }
 
 int bh_alloc(bl_graph *g) {
@@ -889,6 +1153,14 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.late_ids, 4 * N * kLateCap));
     BL_TRY(graph_alloc(g, (void **)&h.snap, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.fbuf, 8 * (size_t)g->p.batch_size));
+    BL_TRY(graph_alloc(g, (void **)&h.late_att, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.heavy, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.nheavy, 16));
+    BL_TRY(graph_alloc(g, (void **)&h.atte, 8 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.roff, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.bbase, 4 * ((size_t)g->nb + 1)));
+    BL_TRY(graph_alloc(g, (void **)&h.ent, 8 * ((size_t)g->nnz + N * kLateCap)));
+    h.prefix_ready = false;
     BL_HIP(hipMemsetAsync(h.bbox, 0, 64, g->stream));
     return BL_OK;
 }
@@ -901,8 +1173,10 @@ int bh_run(bl_graph *g, int iters, int start, int stop_batch) {
         BL_TRY(build_tree(g, x, y));
         const WalkArgs w = walk_args(g);
         BL_TRY(far_pass(g, w, x, y, 0));
+        BL_TRY(early_pass(g));
+        BL_TRY(late_lists(g, false));
         const int stop = (last && stop_batch >= 0) ? stop_batch : -1;
-        BL_TRY(chain(g, w, 0, stop >= 0 ? stop : g->nb, stop, k, stop >= 0 ? nullptr : g->energy + t));
+        BL_TRY(chain(g, w, 0, stop >= 0 ? stop : g->nb, stop, k, stop >= 0 ? nullptr : g->energy + t, true));
     }
     return BL_OK;
 }
@@ -919,7 +1193,9 @@ int bh_forces(bl_graph *g, int batch, const double *snap_x, const double *snap_y
     BL_TRY(build_tree(g, sx, sy));
     const WalkArgs w = walk_args(g);
     BL_TRY(far_pass(g, w, (const float *)g->x, (const float *)g->y, 1));
-    return chain(g, w, batch, batch + 1, batch, 0, nullptr);
+    if (!g->bh.prefix_ready) BL_TRY(early_pass(g));
+    BL_TRY(late_lists(g, true));
+    return chain(g, w, batch, batch + 1, batch, 0, nullptr, false);
 }
 
 }  // namespace bl

@@ -75,6 +75,14 @@ struct BHBuffers {
     int *late_ids;          // [n * kLateCap]
     float *snap;            // [2n] snapshot given to the one-shot force call
     void *fbuf;             // [BS] float2 net forces of the current batch
+    int *late_att;          // [n] length of the moved-neighbour prefix of each CSR row
+    int *heavy;             // [n] rows with many early neighbours (first *nheavy used)
+    int *nheavy;            // [1]
+    float2 *atte;           // [n] early attraction (neighbours not yet moved)
+    int *roff;              // [n] offset of each row's late entries within its batch list
+    int *bbase;             // [nb + 1] start of each batch's late entry list
+    unsigned long long *ent;// late entries (row in batch << 32 | vertex, bit 31: leaf)
+    bool prefix_ready;      // late_att/heavy computed for this job
 };
 
 // Exact-mode buffers (all device memory).
