@@ -37,14 +37,14 @@ constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 values per tile
 constexpr int kChainThreads = 1024;
 
 // ------------------------------------------------------------------ bbox
-__global__ __launch_bounds__(256) void bbox_kernel(int n, const float *__restrict__ x,
-                                                   const float *__restrict__ y, float *part,
+__global__ __launch_bounds__(256) void bbox_kernel(int n, const float2 *__restrict__ pos, float *part,
                                                    unsigned *ticket, float *bbox) {
     __shared__ float s[4][256 / kWave];
     __shared__ int s_last;
     float mnx = FLT_MAX, mny = FLT_MAX, mxx = -FLT_MAX, mxy = -FLT_MAX;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const float a = x[i], b = y[i];
+        const float2 c = pos[i];
+        const float a = c.x, b = c.y;
         mnx = fminf(mnx, a);
         mxx = fmaxf(mxx, a);
         mny = fminf(mny, b);
@@ -117,7 +117,7 @@ __device__ __forceinline__ unsigned quantise(float v, float vmin, float scale) {
     return (unsigned)q;
 }
 
-__global__ void morton_kernel(int n, const float *__restrict__ x, const float *__restrict__ y,
+__global__ void morton_kernel(int n, const float2 *__restrict__ pos,
                               const float *__restrict__ bbox, unsigned *__restrict__ key,
                               int *__restrict__ val) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -125,8 +125,9 @@ __global__ void morton_kernel(int n, const float *__restrict__ x, const float *_
     const float xmin = bbox[0], ymin = bbox[1], scale = bbox[3];
     unsigned qx = 0, qy = 0;
     if (scale > 0.f) {
-        qx = quantise(x[i], xmin, scale);
-        qy = quantise(y[i], ymin, scale);
+        const float2 c = pos[i];
+        qx = quantise(c.x, xmin, scale);
+        qy = quantise(c.y, ymin, scale);
     }
     key[i] = spread16(qx) | (spread16(qy) << 1);
     val[i] = i;
@@ -367,8 +368,7 @@ __device__ dd2 block_excl_scan_dd2(dd2 v, dd2 *ws, dd2 *total) {
 }
 
 __global__ __launch_bounds__(kScanThreads) void coord_tile_kernel(int n, const int *__restrict__ order,
-                                                                  const float *__restrict__ x,
-                                                                  const float *__restrict__ y,
+                                                                  const float2 *__restrict__ pos,
                                                                   double *part) {
     __shared__ dd2 ws[16];
     const int p0 = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
@@ -377,7 +377,8 @@ __global__ __launch_bounds__(kScanThreads) void coord_tile_kernel(int n, const i
     for (int q = 0; q < kScanItems; ++q)
         if (p0 + q < n) {
             const int v = order[p0 + q];
-            s = dd2_add(s, dd2{{(double)x[v], 0}, {(double)y[v], 0}});
+            const float2 c = pos[v];
+            s = dd2_add(s, dd2{{(double)c.x, 0}, {(double)c.y, 0}});
         }
     dd2 total;
     (void)block_excl_scan_dd2(s, ws, &total);
@@ -404,8 +405,7 @@ __global__ void coord_part_scan_kernel(int blocks, double *part) {
 
 // pdd layout: [4][n+1] -> xhi, xlo, yhi, ylo;  pdd[.][p] = sum of sorted coords < p.
 __global__ __launch_bounds__(kScanThreads) void coord_apply_kernel(int n, const int *__restrict__ order,
-                                                                   const float *__restrict__ x,
-                                                                   const float *__restrict__ y,
+                                                                   const float2 *__restrict__ pos,
                                                                    const double *__restrict__ part,
                                                                    double *pdd) {
     __shared__ dd2 ws[16];
@@ -417,7 +417,8 @@ __global__ __launch_bounds__(kScanThreads) void coord_apply_kernel(int n, const 
         v[q] = dd2{{0, 0}, {0, 0}};
         if (p0 + q < n) {
             const int id = order[p0 + q];
-            v[q] = dd2{{(double)x[id], 0}, {(double)y[id], 0}};
+            const float2 c = pos[id];
+            v[q] = dd2{{(double)c.x, 0}, {(double)c.y, 0}};
         }
         s = dd2_add(s, v[q]);
     }
@@ -450,8 +451,8 @@ __global__ __launch_bounds__(kScanThreads) void coord_apply_kernel(int n, const 
 // its last position + 1 begin, which gives the skip link.
 __global__ void emit_kernel(int n, const unsigned *__restrict__ keys, const int *__restrict__ order,
                             const unsigned *__restrict__ mask, const int *__restrict__ cellcnt,
-                            const double *__restrict__ pdd, const float *__restrict__ x,
-                            const float *__restrict__ y, const float *__restrict__ bbox,
+                            const double *__restrict__ pdd, const float2 *__restrict__ pos,
+                            const float *__restrict__ bbox,
                             float4 *__restrict__ nodeA, int2 *__restrict__ nodeB,
                             int *__restrict__ leafpos, int *nnodes) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -492,7 +493,8 @@ __global__ void emit_kernel(int n, const unsigned *__restrict__ keys, const int 
         ++v;
     }
     const int vert = order[p];
-    nodeA[v] = float4{x[vert], y[vert], 0.f, 1.f};
+    const float2 pv = pos[vert];
+    nodeA[v] = float4{pv.x, pv.y, 0.f, 1.f};
     nodeB[v] = int2{v + 1, vert};
     leafpos[vert] = v;
     if (p == n - 1) *nnodes = v + 1;
@@ -520,10 +522,9 @@ __device__ __forceinline__ void rep_add(float dx, float dy, float mult, float &s
 // Walk of the tree for vertex i in pre-order with skip links (Alg. S2 order).
 // live == nullptr: far-field mode -- leaves of vertices j with id < late_below
 // (already moved this iteration) are appended to late[] instead of summed.
-// live != nullptr: every leaf uses live coordinates (lx, ly).
+// live != nullptr: every leaf uses live coordinates.
 __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_below,
-                       const float *lx, const float *ly, float4 &acc, int *late, int &nlate,
-                       int cap) {
+                       const float2 *live, float4 &acc, int *late, int &nlate, int cap) {
     const int Li = a.leafpos[i];
     const int total = *a.total;
     float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f;
@@ -536,8 +537,9 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
         if (B.y >= 0) {
             const int j = B.y;
             if (j != i) {
-                if (lx) {
-                    rep_add(lx[j] - xi, ly[j] - yi, 1.f, sx, cx, sy, cy);
+                if (live) {
+                    const float2 pj = live[j];
+                    rep_add(pj.x - xi, pj.y - yi, 1.f, sx, cx, sy, cy);
                 } else if (j < late_below) {
                     if (nlate < cap) late[nlate] = j;
                     ++nlate;
@@ -564,8 +566,7 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
 }
 
 __global__ __launch_bounds__(256) void far_kernel(WalkArgs a, const int *__restrict__ order,
-                                                  const float *__restrict__ x,
-                                                  const float *__restrict__ y, int all_live,
+                                                  const float2 *__restrict__ pos, int all_live,
                                                   int snapshot_leaves, float4 *__restrict__ far,
                                                   int *__restrict__ late_cnt,
                                                   int *__restrict__ late_ids, Counters *ctr) {
@@ -576,7 +577,8 @@ __global__ __launch_bounds__(256) void far_kernel(WalkArgs a, const int *__restr
         const int late_below = snapshot_leaves ? 0 : (all_live ? a.n : (i / a.BS) * a.BS);
         float4 acc;
         int nlate = 0;
-        visits = bh_walk(a, i, x[i], y[i], late_below, nullptr, nullptr, acc,
+        const float2 pi = pos[i];
+        visits = bh_walk(a, i, pi.x, pi.y, late_below, nullptr, acc,
                          late_ids + (size_t)i * kLateCap, nlate, kLateCap);
         far[i] = acc;
         late_cnt[i] = nlate;
@@ -620,8 +622,7 @@ __global__ void late_prefix_kernel(int n, int BS, const int *__restrict__ rowptr
 __global__ __launch_bounds__(256) void att_early_kernel(int n, float invK, const int *__restrict__ rowptr,
                                                         const int *__restrict__ colidx,
                                                         const int *__restrict__ late_att,
-                                                        const float *__restrict__ x,
-                                                        const float *__restrict__ y,
+                                                        const float2 *__restrict__ pos,
                                                         float2 *__restrict__ atte) {
     const int g8 = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
     const int sub = threadIdx.x & 7;
@@ -629,11 +630,12 @@ __global__ __launch_bounds__(256) void att_early_kernel(int n, float invK, const
     if (i >= n) return;
     const int e0 = rowptr[i] + late_att[i], e1 = rowptr[i + 1];
     if (e1 - e0 > kHeavyRow) return;     // summed by att_heavy_kernel
-    const float xi = x[i], yi = y[i];
+    const float2 pi = pos[i];
+    const float xi = pi.x, yi = pi.y;
     float ax = 0.f, ay = 0.f;
     for (int e = e0 + sub; e < e1; e += 8) {
-        const int j = colidx[e];
-        const float dx = x[j] - xi, dy = y[j] - yi;
+        const float2 pj = pos[colidx[e]];
+        const float dx = pj.x - xi, dy = pj.y - yi;
         const float d = sqrtf(dx * dx + dy * dy) * invK;
         ax = fmaf(d, dx, ax);
         ay = fmaf(d, dy, ay);
@@ -648,18 +650,18 @@ __global__ __launch_bounds__(256) void att_heavy_kernel(const int *__restrict__ 
                                                         float invK, const int *__restrict__ rowptr,
                                                         const int *__restrict__ colidx,
                                                         const int *__restrict__ late_att,
-                                                        const float *__restrict__ x,
-                                                        const float *__restrict__ y,
+                                                        const float2 *__restrict__ pos,
                                                         float2 *__restrict__ atte) {
     __shared__ float wsx[4], wsy[4];
     for (int h = blockIdx.x; h < *nheavy; h += gridDim.x) {
         const int i = heavy[h];
         const int e0 = rowptr[i] + late_att[i], e1 = rowptr[i + 1];
-        const float xi = x[i], yi = y[i];
+        const float2 pi = pos[i];
+        const float xi = pi.x, yi = pi.y;
         float ax = 0.f, ay = 0.f;
         for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
-            const int j = colidx[e];
-            const float dx = x[j] - xi, dy = y[j] - yi;
+            const float2 pj = pos[colidx[e]];
+            const float dx = pj.x - xi, dy = pj.y - yi;
             const float d = sqrtf(dx * dx + dy * dy) * invK;
             ax = fmaf(d, dx, ax);
             ay = fmaf(d, dy, ay);
@@ -745,7 +747,7 @@ struct ChainArgs {
     int nb_run;          // batches to process with updates
     int stop_batch;      // batch whose forces go to fout without update (-1: none)
     int first_batch;     // usually 0; the force call processes only `stop_batch`
-    float *x, *y;
+    float2 *pos;
     const float4 *far;
     const float2 *atte;  // early attraction (NULL: none)
     const int *late_cnt;
@@ -778,8 +780,9 @@ __device__ __forceinline__ ChainRow chain_row(const ChainArgs &a, int b, int r, 
     const int nxt = a.roff[min(i + 1, a.w.n - 1)];
     d.o1 = (rc + 1 < R) ? nxt : E;
     d.ovf = a.late_cnt[i] > kLateCap;
-    d.x = a.x[i];
-    d.y = a.y[i];
+    const float2 pi = a.pos[i];
+    d.x = pi.x;
+    d.y = pi.y;
     d.far = a.far[i];
     d.atte = a.atte ? a.atte[i] : float2{0.f, 0.f};
     return d;
@@ -872,9 +875,9 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
             xj[q] = 0.f;
             yj[q] = 0.f;
             if (q < m0) {
-                const int j = (int)((unsigned)ce[q] & 0x7fffffffu);
-                xj[q] = a.x[j];
-                yj[q] = a.y[j];
+                const float2 pj = a.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
+                xj[q] = pj.x;
+                yj[q] = pj.y;
             }
         }
         // next step's data (clamped to the last batch on the final step)
@@ -894,9 +897,9 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
 #pragma unroll
                     for (int q = 0; q < kEnt; ++q) {
                         if (q < m) {
-                            const int j = (int)((unsigned)ce[q] & 0x7fffffffu);
-                            xj[q] = a.x[j];
-                            yj[q] = a.y[j];
+                            const float2 pj = a.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
+                            xj[q] = pj.x;
+                            yj[q] = pj.y;
                         }
                     }
                 }
@@ -960,7 +963,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
             float4 fr = cur[k].far;
             if (cur[k].ovf) {
                 int dummy = 0;
-                (void)bh_walk(a.w, i, cur[k].x, cur[k].y, 0, a.x, a.y, fr, nullptr, dummy, 0);
+                (void)bh_walk(a.w, i, cur[k].x, cur[k].y, 0, a.pos, fr, nullptr, dummy, 0);
             }
             const float fx = (sm.x + cur[k].atte.x) + negRK2 * (fr.x - fr.z);
             const float fy = (sm.y + cur[k].atte.y) + negRK2 * (fr.y - fr.w);
@@ -977,8 +980,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
             e_iter += f2;
             if (f2 > 0.0) {
                 const float sc = a.step / sqrtf(fx * fx + fy * fy);
-                a.x[i] = cur[k].x + sc * fx;
-                a.y[i] = cur[k].y + sc * fy;
+                a.pos[i] = float2{cur[k].x + sc * fx, cur[k].y + sc * fy};
             }
         }
         if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1);
@@ -990,15 +992,15 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
 }
 
 // ------------------------------------------------------------- host side
-int build_tree(bl_graph *g, const float *sx, const float *sy) {
+int build_tree(bl_graph *g, const float2 *sp) {
     BHBuffers &h = g->bh;
     const int n = g->n;
     hipStream_t s = g->stream;
     int slot;
     BL_TRY(prof_begin(g, PK_TREE, &slot));
-    hipLaunchKernelGGL(bbox_kernel, dim3(kBBoxBlocks), dim3(256), 0, s, n, sx, sy, h.bbox_part,
+    hipLaunchKernelGGL(bbox_kernel, dim3(kBBoxBlocks), dim3(256), 0, s, n, sp, h.bbox_part,
                        (unsigned *)(h.bbox + 8), h.bbox);
-    hipLaunchKernelGGL(morton_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, sx, sy, h.bbox,
+    hipLaunchKernelGGL(morton_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, sp, h.bbox,
                        h.key[0], h.val[0]);
     int cur = 0;
     for (int shift = 0; shift < 32; shift += 8) {
@@ -1019,12 +1021,12 @@ int build_tree(bl_graph *g, const float *sx, const float *sy) {
     hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, s, h.scan_part, sblocks);
     hipLaunchKernelGGL(count_apply_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, h.mask, h.scan_part,
                        h.cellcnt);
-    hipLaunchKernelGGL(coord_tile_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, order, sx, sy, h.pdd_part);
+    hipLaunchKernelGGL(coord_tile_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, order, sp, h.pdd_part);
     hipLaunchKernelGGL(coord_part_scan_kernel, dim3(1), dim3(64), 0, s, sblocks, h.pdd_part);
-    hipLaunchKernelGGL(coord_apply_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, order, sx, sy,
+    hipLaunchKernelGGL(coord_apply_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, order, sp,
                        h.pdd_part, h.pdd);
     hipLaunchKernelGGL(emit_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, keys, order, h.mask,
-                       h.cellcnt, h.pdd, sx, sy, h.bbox, h.nodeA, h.nodeB, h.leafpos, h.nnodes);
+                       h.cellcnt, h.pdd, sp, h.bbox, h.nodeA, h.nodeB, h.leafpos, h.nnodes);
     BL_HIP(hipGetLastError());
     return prof_end(g, slot);
 }
@@ -1056,19 +1058,19 @@ int early_pass(bl_graph *g) {
     }
     const float invK = (float)(1.0 / g->p.K);
     hipLaunchKernelGGL(att_early_kernel, dim3((n + 31) / 32), dim3(256), 0, g->stream, n, invK, g->rowptr,
-                       g->colidx, h.late_att, (const float *)g->x, (const float *)g->y, h.atte);
+                       g->colidx, h.late_att, (const float2 *)g->x, h.atte);
     hipLaunchKernelGGL(att_heavy_kernel, dim3(256), dim3(256), 0, g->stream, h.heavy, h.nheavy, invK,
-                       g->rowptr, g->colidx, h.late_att, (const float *)g->x, (const float *)g->y, h.atte);
+                       g->rowptr, g->colidx, h.late_att, (const float2 *)g->x, h.atte);
     BL_HIP(hipGetLastError());
     return BL_OK;
 }
 
 // Far-field walks of all vertices; (px, py) are the vertices' own positions.
-int far_pass(bl_graph *g, const WalkArgs &w, const float *px, const float *py, int all_live) {
+int far_pass(bl_graph *g, const WalkArgs &w, const float2 *pp, int all_live) {
     const int snap = (g->p.flags & BL_BH_SNAPSHOT_LEAVES) ? 1 : 0;
     int slot;
     BL_TRY(prof_begin(g, PK_FAR, &slot));
-    hipLaunchKernelGGL(far_kernel, dim3((g->n + 255) / 256), dim3(256), 0, g->stream, w, g->bh.val[0], px, py,
+    hipLaunchKernelGGL(far_kernel, dim3((g->n + 255) / 256), dim3(256), 0, g->stream, w, g->bh.val[0], pp,
                        all_live, snap && !all_live, g->bh.far, g->bh.late_cnt, g->bh.late_ids, g->counters);
     BL_HIP(hipGetLastError());
     return prof_end(g, slot);
@@ -1096,8 +1098,7 @@ int chain(bl_graph *g, const WalkArgs &w, int first_batch, int nb_run, int stop_
     a.nb_run = nb_run;
     a.stop_batch = stop_batch;
     a.first_batch = first_batch;
-    a.x = (float *)g->x;
-    a.y = (float *)g->y;
+    a.pos = (float2 *)g->x;
     a.far = g->bh.far;
     a.atte = early ? g->bh.atte : nullptr;
     a.late_cnt = g->bh.late_cnt;
@@ -1166,13 +1167,13 @@ int bh_alloc(bl_graph *g) {
 }
 
 int bh_run(bl_graph *g, int iters, int start, int stop_batch) {
-    const float *x = (const float *)g->x, *y = (const float *)g->y;
+    const float2 *pos = (const float2 *)g->x;
     for (int t = 0; t < iters; ++t) {
         const int k = start + t;
         const bool last = (t == iters - 1);
-        BL_TRY(build_tree(g, x, y));
+        BL_TRY(build_tree(g, pos));
         const WalkArgs w = walk_args(g);
-        BL_TRY(far_pass(g, w, x, y, 0));
+        BL_TRY(far_pass(g, w, pos, 0));
         BL_TRY(early_pass(g));
         BL_TRY(late_lists(g, false));
         const int stop = (last && stop_batch >= 0) ? stop_batch : -1;
@@ -1184,15 +1185,14 @@ int bh_run(bl_graph *g, int iters, int start, int stop_batch) {
 // Forces of one batch from coordinates (x, y) with the tree of the snapshot
 // (snap_x, snap_y); every leaf uses (x, y).
 int bh_forces(bl_graph *g, int batch, const double *snap_x, const double *snap_y) {
-    float *sx = (float *)g->x, *sy = (float *)g->y;
+    const float2 *sp = (const float2 *)g->x;
     if (snap_x) {
-        sx = g->bh.snap;
-        sy = g->bh.snap + g->n;
-        BL_TRY(convert_to_float(g, snap_x, snap_y, sx, sy));
+        BL_TRY(convert_to_float2(g, snap_x, snap_y, (float2 *)g->bh.snap));
+        sp = (const float2 *)g->bh.snap;
     }
-    BL_TRY(build_tree(g, sx, sy));
+    BL_TRY(build_tree(g, sp));
     const WalkArgs w = walk_args(g);
-    BL_TRY(far_pass(g, w, (const float *)g->x, (const float *)g->y, 1));
+    BL_TRY(far_pass(g, w, (const float2 *)g->x, 1));
     if (!g->bh.prefix_ready) BL_TRY(early_pass(g));
     BL_TRY(late_lists(g, true));
     return chain(g, w, batch, batch + 1, batch, 0, nullptr, false);

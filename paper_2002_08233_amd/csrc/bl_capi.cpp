@@ -185,6 +185,7 @@ int bl_graph_create(const bl_csr *csr, const bl_params *p, void *hip_stream, bl_
     g->p = *p;
     g->stream = s;
     g->fp64 = (p->precision == BL_FP64);
+    g->aos = (p->mode == BL_BH);
     g->nb = (g->n + p->batch_size - 1) / p->batch_size;
     const size_t N = (size_t)g->n, T = g->fp64 ? 8 : 4;
     int rc = BL_OK;
@@ -193,7 +194,7 @@ int bl_graph_create(const bl_csr *csr, const bl_params *p, void *hip_stream, bl_
     };
     A((void **)&g->rowptr, 4 * (N + 1));
     A((void **)&g->colidx, 4 * (size_t)std::max<int64_t>(g->nnz, 1));
-    A(&g->x, T * N);
+    A(&g->x, 2 * T * N);
     A(&g->y, T * N);
     A((void **)&g->stage, 16 * N);
     A((void **)&g->erow, 8 * N);
@@ -209,7 +210,7 @@ int bl_graph_create(const bl_csr *csr, const bl_params *p, void *hip_stream, bl_
     hipError_t e = hipMemcpyAsync(g->rowptr, csr->rowptr, 4 * (N + 1), kind, s);
     if (e == hipSuccess && g->nnz)
         e = hipMemcpyAsync(g->colidx, csr->colidx, 4 * (size_t)g->nnz, kind, s);
-    if (e == hipSuccess) e = hipMemsetAsync(g->x, 0, T * N, s);
+    if (e == hipSuccess) e = hipMemsetAsync(g->x, 0, 2 * T * N, s);
     if (e == hipSuccess) e = hipMemsetAsync(g->y, 0, T * N, s);
     if (e == hipSuccess) e = hipMemsetAsync(g->counters, 0, sizeof(Counters), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

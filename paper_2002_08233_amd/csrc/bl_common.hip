@@ -26,6 +26,22 @@ __global__ void coords_out_kernel(int n, const T *__restrict__ x, const T *__res
     }
 }
 
+__global__ void coords_in_aos_kernel(int n, const double *__restrict__ x, const double *__restrict__ y,
+                                     float2 *__restrict__ o) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = float2{(float)x[i], (float)y[i]};
+}
+
+__global__ void coords_out_aos_kernel(int n, const float2 *__restrict__ p, double *__restrict__ ox,
+                                      double *__restrict__ oy) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const float2 c = p[i];
+        ox[i] = (double)c.x;
+        oy[i] = (double)c.y;
+    }
+}
+
 }  // namespace
 
 // Step length of iteration k: step0 multiplied by the decay once per finished
@@ -38,7 +54,9 @@ double step_at(const bl_params &p, int k) {
 
 int convert_coords_in(bl_graph *g, const double *x, const double *y) {
     const int blocks = (g->n + 255) / 256;
-    if (g->fp64)
+    if (g->aos)
+        hipLaunchKernelGGL(coords_in_aos_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n, x, y, (float2 *)g->x);
+    else if (g->fp64)
         hipLaunchKernelGGL(coords_in_kernel<double>, dim3(blocks), dim3(256), 0, g->stream, g->n, x, y,
                            (double *)g->x, (double *)g->y);
     else
@@ -50,7 +68,10 @@ int convert_coords_in(bl_graph *g, const double *x, const double *y) {
 
 int convert_coords_out(bl_graph *g, double *x, double *y) {
     const int blocks = (g->n + 255) / 256;
-    if (g->fp64)
+    if (g->aos)
+        hipLaunchKernelGGL(coords_out_aos_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n,
+                           (const float2 *)g->x, x, y);
+    else if (g->fp64)
         hipLaunchKernelGGL(coords_out_kernel<double>, dim3(blocks), dim3(256), 0, g->stream, g->n,
                            (const double *)g->x, (const double *)g->y, x, y);
     else
@@ -94,9 +115,9 @@ int prof_collect(bl_graph *g) {
     return BL_OK;
 }
 
-int convert_to_float(bl_graph *g, const double *x, const double *y, float *ox, float *oy) {
+int convert_to_float2(bl_graph *g, const double *x, const double *y, float2 *o) {
     const int blocks = (g->n + 255) / 256;
-    hipLaunchKernelGGL(coords_in_kernel<float>, dim3(blocks), dim3(256), 0, g->stream, g->n, x, y, ox, oy);
+    hipLaunchKernelGGL(coords_in_aos_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n, x, y, o);
     BL_HIP(hipGetLastError());
     return BL_OK;
 }

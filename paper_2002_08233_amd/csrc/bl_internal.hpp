@@ -102,11 +102,12 @@ struct bl_graph {
     bl_params p{};
     hipStream_t stream = nullptr;
     bool fp64 = false;
+    bool aos = false;           // coordinates stored as interleaved float2 (Barnes-Hut)
     int nb = 0;                 // number of batches
     int *rowptr = nullptr;      // device CSR
     int *colidx = nullptr;
-    void *x = nullptr;          // device coordinates (float or double)
-    void *y = nullptr;
+    void *x = nullptr;          // device coordinates: float/double x[n] (exact), or float2 xy[n] (BH)
+    void *y = nullptr;          // y[n] (exact mode only)
     double *erow = nullptr;     // [n] per-vertex |f|^2 of the current iteration
     double *energy = nullptr;   // [energy_cap] per-iteration energies
     int energy_cap = 0;
@@ -139,7 +140,7 @@ size_t bh_footprint(int n);
 int energy_sum(bl_graph *g, int k);
 int convert_coords_in(bl_graph *g, const double *x, const double *y);   // device FP64 -> state
 int convert_coords_out(bl_graph *g, double *x, double *y);              // state -> device FP64
-int convert_to_float(bl_graph *g, const double *x, const double *y, float *ox, float *oy);
+int convert_to_float2(bl_graph *g, const double *x, const double *y, float2 *o);
 
 double step_at(const bl_params &p, int k);
 
