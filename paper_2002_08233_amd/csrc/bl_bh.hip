@@ -1,6 +1,10 @@
-// Barnes-Hut force step (Sec. 3.5; Alg. S1-S3) for gfx950.
+// Barnes-Hut force step (Sec. 3.5; Alg. S1-S3) for gfx950, for one or many
+// layout jobs at once.
 //
-// Per iteration (all on the device, no host round trip):
+// Every kernel here takes the table of resident jobs and a per-kernel prefix
+// of workgroups per job, so one launch serves all jobs: a single graph is the
+// one-job case, and a graph's result does not depend on which other jobs
+// share the launches.  Per iteration (no host round trip):
 //   1. bbox_kernel     square root cell: xmin, ymin, W = max extent (Alg. S3)
 //   2. morton_kernel   16-bit-per-axis Z-order keys, quantised in float32
 //   3. radix sort      own LSD sort of (key, id), 4 passes of 8 bits, stable
@@ -16,16 +20,20 @@
 //                      snapshot: accepted cells (side < theta*d), and leaves
 //                      whose vertex has not moved yet this iteration; leaves of
 //                      already-moved vertices are listed for the chain
-//   8. chain_kernel    one workgroup walks the batches in order: attraction
-//                      over CSR rows and the listed leaves with live
-//                      coordinates, then the batch update (Alg. 2 update loop)
+//   8. att_*_kernel    attraction from neighbours that have not moved yet
+//   9. late lists      per batch: the moved neighbours and listed moved leaves
+//  10. chain_kernel    one workgroup per job walks its batches in order: the
+//                      late entries with live coordinates, then the batch
+//                      update (Alg. 2 update loop)
+#include <algorithm>
 #include <cfloat>
+#include <cstring>
+#include <vector>
 
 #include "bl_device.hpp"
 #include "bl_internal.hpp"
 
 namespace bl {
-namespace {
 
 constexpr int kBBoxBlocks = 256;
 constexpr int kSortThreads = 256;
@@ -35,20 +43,80 @@ constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 values per tile
 constexpr int kChainThreads = 1024;
+constexpr int kHeavyRow = 256;        // early entries above which a whole workgroup sums the row
+constexpr int kHeavyBlocks = 16;      // workgroups per job for heavy rows
+constexpr int kMaxChainRows = 2048;   // batch-size limit of the Barnes-Hut chain
+constexpr int kEnt = 8;               // late entries per thread per pass (held in registers)
+
+// Device descriptor of one job (all pointers are device memory).
+struct BHJob {
+    int n, BS, nb, tiles, sblocks;
+    float theta2, negRK2, invK;
+    int snapshot_leaves;        // leaves use the snapshot (no late lists)
+    int all_live;               // one-shot force call: every leaf and neighbour is live
+    int first_batch, last_batch, stop_batch;
+    double step0, decay;
+    int *kiter;                 // [2]: current iteration, first iteration of the run
+    const int *rowptr, *colidx;
+    float2 *pos;                // live coordinates
+    const float2 *src;          // coordinates the tree is built from
+    float *bbox, *bbox_part;
+    unsigned *ticket;
+    unsigned *key0, *key1;
+    int *val0, *val1, *hist;
+    unsigned *mask;
+    int *cellcnt, *scan_part;
+    double *pdd, *pdd_part;
+    float4 *nodeA;
+    int2 *nodeB;
+    int *leafpos, *nnodes;
+    float4 *far;
+    int *late_cnt, *late_ids, *late_att, *heavy, *nheavy;
+    float2 *atte;
+    int *roff, *bbase;
+    unsigned long long *ent;
+    size_t ent_cap;
+    double *energy;             // one value per iteration of the run
+    double *fout;
+    Counters *ctr;
+};
+
+// Workgroup -> (job, workgroup within the job) for one kernel of a launch.
+struct JobBlock {
+    const BHJob *J;
+    int local, nblocks;
+};
+__device__ __forceinline__ JobBlock job_block(const BHJob *__restrict__ jobs, const int *__restrict__ pre,
+                                              int G) {
+    const int blk = blockIdx.x;
+    int lo = 0, hi = G - 1;   // last job whose first workgroup is <= blk
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return JobBlock{&jobs[lo], blk - pre[lo], pre[lo + 1] - pre[lo]};
+}
+
+#define BH_KERNEL_ARGS const BHJob *__restrict__ jobs, const int *__restrict__ pre, int G
+// The descriptor is copied into registers: stores through its pointers can
+// then not force reloads of its fields.
+#define BH_JOB()                               \
+    const JobBlock jb = job_block(jobs, pre, G); \
+    const BHJob J = *jb.J
 
 // ------------------------------------------------------------------ bbox
-__global__ __launch_bounds__(256) void bbox_kernel(int n, const float2 *__restrict__ pos, float *part,
-                                                   unsigned *ticket, float *bbox) {
+__global__ __launch_bounds__(256) void bbox_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ float s[4][256 / kWave];
     __shared__ int s_last;
     float mnx = FLT_MAX, mny = FLT_MAX, mxx = -FLT_MAX, mxy = -FLT_MAX;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const float2 c = pos[i];
-        const float a = c.x, b = c.y;
-        mnx = fminf(mnx, a);
-        mxx = fmaxf(mxx, a);
-        mny = fminf(mny, b);
-        mxy = fmaxf(mxy, b);
+    for (int i = jb.local * 256 + threadIdx.x; i < J.n; i += jb.nblocks * 256) {
+        const float2 c = J.src[i];
+        mnx = fminf(mnx, c.x);
+        mxx = fmaxf(mxx, c.x);
+        mny = fminf(mny, c.y);
+        mxy = fmaxf(mxy, c.y);
     }
     for (int o = kWave / 2; o > 0; o >>= 1) {
         mnx = fminf(mnx, __shfl_xor(mnx, o, kWave));
@@ -71,32 +139,33 @@ __global__ __launch_bounds__(256) void bbox_kernel(int n, const float2 *__restri
             s[2][0] = fminf(s[2][0], s[2][q]);
             s[3][0] = fmaxf(s[3][0], s[3][q]);
         }
-        part[4 * blockIdx.x + 0] = s[0][0];
-        part[4 * blockIdx.x + 1] = s[1][0];
-        part[4 * blockIdx.x + 2] = s[2][0];
-        part[4 * blockIdx.x + 3] = s[3][0];
+        float *part = J.bbox_part + 4 * jb.local;
+        part[0] = s[0][0];
+        part[1] = s[1][0];
+        part[2] = s[2][0];
+        part[3] = s[3][0];
         __threadfence();
-        s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
+        s_last = (atomicAdd(J.ticket, 1u) == (unsigned)jb.nblocks - 1);
     }
     __syncthreads();
     if (!s_last || threadIdx.x != 0) return;
     __threadfence();
     float a = FLT_MAX, b = -FLT_MAX, c = FLT_MAX, d = -FLT_MAX;
-    for (int q = 0; q < (int)gridDim.x; ++q) {
-        a = fminf(a, part[4 * q + 0]);
-        b = fmaxf(b, part[4 * q + 1]);
-        c = fminf(c, part[4 * q + 2]);
-        d = fmaxf(d, part[4 * q + 3]);
+    for (int q = 0; q < jb.nblocks; ++q) {
+        a = fminf(a, J.bbox_part[4 * q + 0]);
+        b = fmaxf(b, J.bbox_part[4 * q + 1]);
+        c = fminf(c, J.bbox_part[4 * q + 2]);
+        d = fmaxf(d, J.bbox_part[4 * q + 3]);
     }
     const float wx = b - a, wy = d - c;
     const float W = fmaxf(wx, wy);
-    bbox[0] = a;
-    bbox[1] = c;
-    bbox[2] = W;
+    J.bbox[0] = a;
+    J.bbox[1] = c;
+    J.bbox[2] = W;
     // 2^16 / W rounded once to float (computed in double: double rounding is
     // innocuous for a quotient of floats since 53 >= 2*24 + 2).
-    bbox[3] = W > 0.f ? (float)(65536.0 / (double)W) : 0.f;
-    *ticket = 0u;
+    J.bbox[3] = W > 0.f ? (float)(65536.0 / (double)W) : 0.f;
+    *J.ticket = 0u;
 }
 
 // ---------------------------------------------------------------- morton
@@ -117,20 +186,20 @@ __device__ __forceinline__ unsigned quantise(float v, float vmin, float scale) {
     return (unsigned)q;
 }
 
-__global__ void morton_kernel(int n, const float2 *__restrict__ pos,
-                              const float *__restrict__ bbox, unsigned *__restrict__ key,
-                              int *__restrict__ val) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float xmin = bbox[0], ymin = bbox[1], scale = bbox[3];
+__global__ void morton_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const int i = jb.local * blockDim.x + threadIdx.x;
+    if (i >= J.n) return;
+    const float xmin = J.bbox[0], ymin = J.bbox[1], scale = J.bbox[3];
     unsigned qx = 0, qy = 0;
     if (scale > 0.f) {
-        const float2 c = pos[i];
+        const float2 c = J.src[i];
         qx = quantise(c.x, xmin, scale);
         qy = quantise(c.y, ymin, scale);
     }
-    key[i] = spread16(qx) | (spread16(qy) << 1);
-    val[i] = i;
+    J.key0[i] = spread16(qx) | (spread16(qy) << 1);
+    J.val0[i] = i;
+    J.mask[i] = 0u;
 }
 
 // ----------------------------------------------------------- radix sort
@@ -151,15 +220,17 @@ __device__ __forceinline__ unsigned long long lanes_below() {
     return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const unsigned *__restrict__ keys,
-                                                                  int n, int shift, int *hist,
-                                                                  int tiles) {
+// Pass `pass` reads buffer pass&1 and writes the other one.
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(BH_KERNEL_ARGS, int pass) {
+    BH_JOB();
     __shared__ int h[256];
+    const unsigned *keys = (pass & 1) ? J.key1 : J.key0;
+    const int shift = 8 * pass, n = J.n;
     h[threadIdx.x] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int base = blockIdx.x * kSortTile + w * (kSortTile / 4);
+    const int base = jb.local * kSortTile + w * (kSortTile / 4);
     for (int g = 0; g < kSortItems; ++g) {
         const int p = base + g * kWave + lane;
         const bool valid = p < n;
@@ -168,18 +239,22 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const unsigned
         if (valid && (__ffsll((long long)m) - 1) == lane) atomicAdd(&h[d], __popcll(m));
     }
     __syncthreads();
-    hist[threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+    J.hist[threadIdx.x * J.tiles + jb.local] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
-    const unsigned *__restrict__ kin, const int *__restrict__ vin, unsigned *__restrict__ kout,
-    int *__restrict__ vout, int n, int shift, const int *__restrict__ hist, int tiles) {
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(BH_KERNEL_ARGS, int pass) {
+    BH_JOB();
     __shared__ int cnt[4][256];
+    const unsigned *kin = (pass & 1) ? J.key1 : J.key0;
+    const int *vin = (pass & 1) ? J.val1 : J.val0;
+    unsigned *kout = (pass & 1) ? J.key0 : J.key1;
+    int *vout = (pass & 1) ? J.val0 : J.val1;
+    const int shift = 8 * pass, n = J.n, tiles = J.tiles;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     for (int q = threadIdx.x; q < 4 * 256; q += kSortThreads) (&cnt[0][0])[q] = 0;
     __syncthreads();
-    const int base = blockIdx.x * kSortTile + w * (kSortTile / 4);
+    const int base = jb.local * kSortTile + w * (kSortTile / 4);
     unsigned k[kSortItems];
     int v[kSortItems];
 #pragma unroll
@@ -188,7 +263,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         k[g] = p < n ? kin[p] : 0u;
         v[g] = p < n ? vin[p] : 0;
     }
-    // pass 1: per-wave digit counts
+    // per-wave digit counts
 #pragma unroll
     for (int g = 0; g < kSortItems; ++g) {
         const bool valid = base + g * kWave + lane < n;
@@ -201,7 +276,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     // earlier waves of this tile
     {
         const int d = threadIdx.x;
-        int run = hist[d * tiles + blockIdx.x];
+        int run = J.hist[d * tiles + jb.local];
         for (int q = 0; q < 4; ++q) {
             const int c = cnt[q][d];
             cnt[q][d] = run;
@@ -225,10 +300,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     }
 }
 
-// Exclusive scan of `len` ints in place by one workgroup (used for the radix
-// histogram, len = 256 * tiles).
-__global__ __launch_bounds__(kScanThreads) void scan_single_kernel(int *data, int len) {
+// Exclusive scan in place by one workgroup per job.  which: 0 radix
+// histogram (256 * tiles), 1 cell-count tile sums (sblocks), 2 batch list
+// sizes (nb + 1).
+__global__ __launch_bounds__(kScanThreads) void scan_single_kernel(BH_KERNEL_ARGS, int which) {
+    BH_JOB();
     __shared__ int ws[16];
+    int *data = which == 0 ? J.hist : (which == 1 ? J.scan_part : J.bbase);
+    const int len = which == 0 ? 256 * J.tiles : (which == 1 ? J.sblocks : J.nb + 1);
     int running = 0;
     for (int b0 = 0; b0 < len; b0 += kScanTile) {
         int v[kScanItems];
@@ -240,11 +319,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(int *data, in
             s += v[q];
         }
         int total;
-        int pre = block_excl_scan(s, ws, &total) + running;
+        int pre_ = block_excl_scan(s, ws, &total) + running;
 #pragma unroll
         for (int q = 0; q < kScanItems; ++q) {
-            if (p0 + q < len) data[p0 + q] = pre;
-            pre += v[q];
+            if (p0 + q < len) data[p0 + q] = pre_;
+            pre_ += v[q];
         }
         running += total;
     }
@@ -283,49 +362,50 @@ __device__ __forceinline__ int cell_last(const unsigned *keys, int n, int p, int
     return lo;
 }
 
-__global__ void mark_kernel(int n, const unsigned *__restrict__ keys, unsigned *mask) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n - 1) return;
+__global__ void mark_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const int p = jb.local * blockDim.x + threadIdx.x;
+    if (p >= J.n - 1) return;
+    const unsigned *keys = J.key0;
     const int lvl = common_levels(keys[p], keys[p + 1]);
     const int s = cell_first(keys, p, lvl);
-    atomicOr(&mask[s], 1u << lvl);
+    atomicOr(&J.mask[s], 1u << lvl);
 }
 
-// Tile sums for the 3-phase scans.  Kind 0: popcount(mask) -> cellcnt.
-// Kind 1: sorted coordinates (double-double) -> pdd.
-__global__ __launch_bounds__(kScanThreads) void count_tile_kernel(int n, const unsigned *__restrict__ mask,
-                                                                  int *part) {
+// Tile sums and apply of the 3-phase scan of popcount(mask) -> cellcnt.
+__global__ __launch_bounds__(kScanThreads) void count_tile_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ int ws[16];
-    const int p0 = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    const int p0 = jb.local * kScanTile + threadIdx.x * kScanItems;
     int s = 0;
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q)
-        if (p0 + q < n) s += __popc(mask[p0 + q]);
+        if (p0 + q < J.n) s += __popc(J.mask[p0 + q]);
     int total;
     (void)block_excl_scan(s, ws, &total);
-    if (threadIdx.x == 0) part[blockIdx.x] = total;
+    if (threadIdx.x == 0) J.scan_part[jb.local] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void count_apply_kernel(int n, const unsigned *__restrict__ mask,
-                                                                   const int *__restrict__ part,
-                                                                   int *cellcnt) {
+__global__ __launch_bounds__(kScanThreads) void count_apply_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ int ws[16];
-    const int p0 = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    const int n = J.n;
+    const int p0 = jb.local * kScanTile + threadIdx.x * kScanItems;
     int v[kScanItems];
     int s = 0;
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
-        v[q] = (p0 + q < n) ? __popc(mask[p0 + q]) : 0;
+        v[q] = (p0 + q < n) ? __popc(J.mask[p0 + q]) : 0;
         s += v[q];
     }
     int total;
-    int pre = block_excl_scan(s, ws, &total) + part[blockIdx.x];
+    int pre_ = block_excl_scan(s, ws, &total) + J.scan_part[jb.local];
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
-        if (p0 + q < n) cellcnt[p0 + q] = pre;
-        pre += v[q];
+        if (p0 + q < n) J.cellcnt[p0 + q] = pre_;
+        pre_ += v[q];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) cellcnt[n] = pre;
+    if (jb.local == jb.nblocks - 1 && threadIdx.x == kScanThreads - 1) J.cellcnt[n] = pre_;
 }
 
 // Double-double block scan helpers (x and y together).
@@ -367,33 +447,34 @@ __device__ dd2 block_excl_scan_dd2(dd2 v, dd2 *ws, dd2 *total) {
     return dd2_add(base, ex);
 }
 
-__global__ __launch_bounds__(kScanThreads) void coord_tile_kernel(int n, const int *__restrict__ order,
-                                                                  const float2 *__restrict__ pos,
-                                                                  double *part) {
+__global__ __launch_bounds__(kScanThreads) void coord_tile_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ dd2 ws[16];
-    const int p0 = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    const int p0 = jb.local * kScanTile + threadIdx.x * kScanItems;
     dd2 s{{0, 0}, {0, 0}};
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q)
-        if (p0 + q < n) {
-            const int v = order[p0 + q];
-            const float2 c = pos[v];
+        if (p0 + q < J.n) {
+            const float2 c = J.src[J.val0[p0 + q]];
             s = dd2_add(s, dd2{{(double)c.x, 0}, {(double)c.y, 0}});
         }
     dd2 total;
     (void)block_excl_scan_dd2(s, ws, &total);
     if (threadIdx.x == 0) {
-        part[4 * blockIdx.x + 0] = total.x.hi;
-        part[4 * blockIdx.x + 1] = total.x.lo;
-        part[4 * blockIdx.x + 2] = total.y.hi;
-        part[4 * blockIdx.x + 3] = total.y.lo;
+        double *part = J.pdd_part + 4 * jb.local;
+        part[0] = total.x.hi;
+        part[1] = total.x.lo;
+        part[2] = total.y.hi;
+        part[3] = total.y.lo;
     }
 }
 
-__global__ void coord_part_scan_kernel(int blocks, double *part) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void coord_part_scan_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    if (threadIdx.x != 0) return;
     dd2 run{{0, 0}, {0, 0}};
-    for (int b = 0; b < blocks; ++b) {
+    double *part = J.pdd_part;
+    for (int b = 0; b < J.sblocks; ++b) {
         dd2 v{{part[4 * b], part[4 * b + 1]}, {part[4 * b + 2], part[4 * b + 3]}};
         part[4 * b + 0] = run.x.hi;
         part[4 * b + 1] = run.x.lo;
@@ -404,69 +485,66 @@ __global__ void coord_part_scan_kernel(int blocks, double *part) {
 }
 
 // pdd layout: [4][n+1] -> xhi, xlo, yhi, ylo;  pdd[.][p] = sum of sorted coords < p.
-__global__ __launch_bounds__(kScanThreads) void coord_apply_kernel(int n, const int *__restrict__ order,
-                                                                   const float2 *__restrict__ pos,
-                                                                   const double *__restrict__ part,
-                                                                   double *pdd) {
+__global__ __launch_bounds__(kScanThreads) void coord_apply_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ dd2 ws[16];
-    const int p0 = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    const int n = J.n;
+    const int p0 = jb.local * kScanTile + threadIdx.x * kScanItems;
     dd2 v[kScanItems];
     dd2 s{{0, 0}, {0, 0}};
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
         v[q] = dd2{{0, 0}, {0, 0}};
         if (p0 + q < n) {
-            const int id = order[p0 + q];
-            const float2 c = pos[id];
+            const float2 c = J.src[J.val0[p0 + q]];
             v[q] = dd2{{(double)c.x, 0}, {(double)c.y, 0}};
         }
         s = dd2_add(s, v[q]);
     }
     dd2 total;
-    dd2 pre = block_excl_scan_dd2(s, ws, &total);
-    const dd2 off{{part[4 * blockIdx.x], part[4 * blockIdx.x + 1]},
-                  {part[4 * blockIdx.x + 2], part[4 * blockIdx.x + 3]}};
-    pre = dd2_add(off, pre);
+    dd2 pre_ = block_excl_scan_dd2(s, ws, &total);
+    const double *part = J.pdd_part + 4 * jb.local;
+    pre_ = dd2_add(dd2{{part[0], part[1]}, {part[2], part[3]}}, pre_);
     const size_t N1 = (size_t)n + 1;
+    double *pdd = J.pdd;
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
         if (p0 + q < n) {
-            pdd[0 * N1 + p0 + q] = pre.x.hi;
-            pdd[1 * N1 + p0 + q] = pre.x.lo;
-            pdd[2 * N1 + p0 + q] = pre.y.hi;
-            pdd[3 * N1 + p0 + q] = pre.y.lo;
+            pdd[0 * N1 + p0 + q] = pre_.x.hi;
+            pdd[1 * N1 + p0 + q] = pre_.x.lo;
+            pdd[2 * N1 + p0 + q] = pre_.y.hi;
+            pdd[3 * N1 + p0 + q] = pre_.y.lo;
         }
-        pre = dd2_add(pre, v[q]);
+        pre_ = dd2_add(pre_, v[q]);
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
-        pdd[0 * N1 + n] = pre.x.hi;
-        pdd[1 * N1 + n] = pre.x.lo;
-        pdd[2 * N1 + n] = pre.y.hi;
-        pdd[3 * N1 + n] = pre.y.lo;
+    if (jb.local == jb.nblocks - 1 && threadIdx.x == kScanThreads - 1) {
+        pdd[0 * N1 + n] = pre_.x.hi;
+        pdd[1 * N1 + n] = pre_.x.lo;
+        pdd[2 * N1 + n] = pre_.y.hi;
+        pdd[3 * N1 + n] = pre_.y.lo;
     }
 }
 
 // Nodes in DFS pre-order.  Cells starting at sorted position p come right
 // before leaf p, shallower first; a cell's subtree ends where the nodes of
 // its last position + 1 begin, which gives the skip link.
-__global__ void emit_kernel(int n, const unsigned *__restrict__ keys, const int *__restrict__ order,
-                            const unsigned *__restrict__ mask, const int *__restrict__ cellcnt,
-                            const double *__restrict__ pdd, const float2 *__restrict__ pos,
-                            const float *__restrict__ bbox,
-                            float4 *__restrict__ nodeA, int2 *__restrict__ nodeB,
-                            int *__restrict__ leafpos, int *nnodes) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void emit_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const int n = J.n;
+    const int p = jb.local * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    const unsigned *keys = J.key0;
     const size_t N1 = (size_t)n + 1;
-    const float W = bbox[2];
-    unsigned m = mask[p];
-    int v = p + cellcnt[p];
+    const double *pdd = J.pdd;
+    const float W = J.bbox[2];
+    unsigned m = J.mask[p];
+    int v = p + J.cellcnt[p];
     while (m) {
         const int lvl = __ffs(m) - 1;
         m &= m - 1;
         const int e = cell_last(keys, n, p, lvl);
         const int cnt = e - p + 1;
-        const int skip = (e + 1) + cellcnt[e + 1];
+        const int skip = (e + 1) + J.cellcnt[e + 1];
         const dd sx = dd_add(dd{pdd[0 * N1 + e + 1], pdd[1 * N1 + e + 1]},
                              dd_neg(dd{pdd[0 * N1 + p], pdd[1 * N1 + p]}));
         const dd sy = dd_add(dd{pdd[2 * N1 + e + 1], pdd[3 * N1 + e + 1]},
@@ -488,16 +566,16 @@ __global__ void emit_kernel(int n, const unsigned *__restrict__ keys, const int 
             const float side = ldexpf(W, -lvl);
             side2 = side * side;
         }
-        nodeA[v] = float4{(float)cx, (float)cy, side2, (float)cnt};
-        nodeB[v] = int2{skip, -1};
+        J.nodeA[v] = float4{(float)cx, (float)cy, side2, (float)cnt};
+        J.nodeB[v] = int2{skip, -1};
         ++v;
     }
-    const int vert = order[p];
-    const float2 pv = pos[vert];
-    nodeA[v] = float4{pv.x, pv.y, 0.f, 1.f};
-    nodeB[v] = int2{v + 1, vert};
-    leafpos[vert] = v;
-    if (p == n - 1) *nnodes = v + 1;
+    const int vert = J.val0[p];
+    const float2 pv = J.src[vert];
+    J.nodeA[v] = float4{pv.x, pv.y, 0.f, 1.f};
+    J.nodeB[v] = int2{v + 1, vert};
+    J.leafpos[vert] = v;
+    if (p == n - 1) *J.nnodes = v + 1;
 }
 
 // --------------------------------------------------------------- walks
@@ -565,32 +643,45 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
     return visits;
 }
 
-__global__ __launch_bounds__(256) void far_kernel(WalkArgs a, const int *__restrict__ order,
-                                                  const float2 *__restrict__ pos, int all_live,
-                                                  int snapshot_leaves, float4 *__restrict__ far,
-                                                  int *__restrict__ late_cnt,
-                                                  int *__restrict__ late_ids, Counters *ctr) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    int visits = 0, ovf = 0;
+__device__ __forceinline__ WalkArgs walk_args(const BHJob &J) {
+    WalkArgs w;
+    w.n = J.n;
+    w.BS = J.BS;
+    w.total = J.nnodes;
+    w.nodeA = J.nodeA;
+    w.nodeB = J.nodeB;
+    w.leafpos = J.leafpos;
+    w.theta2 = J.theta2;
+    w.negRK2 = J.negRK2;
+    w.invK = J.invK;
+    return w;
+}
+
+__global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const WalkArgs a = walk_args(J);
+    const int p = jb.local * blockDim.x + threadIdx.x;
+    int visits = 0, ovf = 0, lat = 0;
     if (p < a.n) {
-        const int i = order[p];
-        const int late_below = snapshot_leaves ? 0 : (all_live ? a.n : (i / a.BS) * a.BS);
+        const int i = J.val0[p];
+        const int late_below = J.snapshot_leaves ? 0 : (J.all_live ? a.n : (i / a.BS) * a.BS);
         float4 acc;
         int nlate = 0;
-        const float2 pi = pos[i];
-        visits = bh_walk(a, i, pi.x, pi.y, late_below, nullptr, acc,
-                         late_ids + (size_t)i * kLateCap, nlate, kLateCap);
-        far[i] = acc;
-        late_cnt[i] = nlate;
+        const float2 pi = J.pos[i];
+        visits = bh_walk(a, i, pi.x, pi.y, late_below, nullptr, acc, J.late_ids + (size_t)i * kLateCap, nlate,
+                         kLateCap);
+        J.far[i] = acc;
+        J.late_cnt[i] = nlate;
         ovf = nlate > kLateCap;
+        lat = min(nlate, kLateCap);
     }
     unsigned long long vs = wave_sum((unsigned long long)visits);
     unsigned long long os = wave_sum((unsigned long long)ovf);
-    unsigned long long ls = wave_sum((unsigned long long)(p < a.n ? min(late_cnt[order[p]], kLateCap) : 0));
+    unsigned long long ls = wave_sum((unsigned long long)lat);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (vs) atomicAdd(&ctr->visits, vs);
-        if (os) atomicAdd(&ctr->late_overflow, os);
-        if (ls) atomicAdd(&ctr->late_total, ls);
+        if (vs) atomicAdd(&J.ctr->visits, vs);
+        if (os) atomicAdd(&J.ctr->late_overflow, os);
+        if (ls) atomicAdd(&J.ctr->late_total, ls);
     }
 }
 
@@ -598,70 +689,65 @@ __global__ __launch_bounds__(256) void far_kernel(WalkArgs a, const int *__restr
 // Neighbours j in batches >= batch(i) have not moved when batch(i) comes up,
 // so their attraction terms (Sec. 2.2, a = 2: d * delta / K) can be summed
 // for all vertices at once from the snapshot.  Sorted CSR rows make the moved
-// ("late") neighbours a prefix of each row; its length is fixed per graph.
-constexpr int kHeavyRow = 256;   // early entries above which a whole workgroup sums the row
+// ("late") neighbours a prefix of each row; its length is fixed per job.
+__global__ void heavy_reset_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    if (threadIdx.x == 0) *J.nheavy = 0;
+}
 
-__global__ void late_prefix_kernel(int n, int BS, const int *__restrict__ rowptr,
-                                   const int *__restrict__ colidx, int *__restrict__ late_att,
-                                   int *__restrict__ heavy, int *__restrict__ nheavy) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int bstart = (i / BS) * BS;
-    int lo = rowptr[i], hi = rowptr[i + 1];   // first entry with colidx >= bstart
+__global__ void late_prefix_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const int i = jb.local * blockDim.x + threadIdx.x;
+    if (i >= J.n) return;
+    const int bstart = (i / J.BS) * J.BS;
+    int lo = J.rowptr[i], hi = J.rowptr[i + 1];   // first entry with colidx >= bstart
     const int end = hi;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (colidx[mid] < bstart) lo = mid + 1;
+        if (J.colidx[mid] < bstart) lo = mid + 1;
         else hi = mid;
     }
-    late_att[i] = lo - rowptr[i];
-    if (end - lo > kHeavyRow) heavy[atomicAdd(nheavy, 1)] = i;
+    J.late_att[i] = lo - J.rowptr[i];
+    if (end - lo > kHeavyRow) J.heavy[atomicAdd(J.nheavy, 1)] = i;
 }
 
 // Light rows: 8 lanes per row.
-__global__ __launch_bounds__(256) void att_early_kernel(int n, float invK, const int *__restrict__ rowptr,
-                                                        const int *__restrict__ colidx,
-                                                        const int *__restrict__ late_att,
-                                                        const float2 *__restrict__ pos,
-                                                        float2 *__restrict__ atte) {
-    const int g8 = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+__global__ __launch_bounds__(256) void att_early_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const int i = (jb.local * blockDim.x + threadIdx.x) >> 3;
     const int sub = threadIdx.x & 7;
-    const int i = g8;
-    if (i >= n) return;
-    const int e0 = rowptr[i] + late_att[i], e1 = rowptr[i + 1];
+    if (i >= J.n) return;
+    const int e0 = J.rowptr[i] + J.late_att[i], e1 = J.rowptr[i + 1];
     if (e1 - e0 > kHeavyRow) return;     // summed by att_heavy_kernel
-    const float2 pi = pos[i];
-    const float xi = pi.x, yi = pi.y;
+    const float2 pi = J.pos[i];
+    const float invK = J.invK;
     float ax = 0.f, ay = 0.f;
     for (int e = e0 + sub; e < e1; e += 8) {
-        const float2 pj = pos[colidx[e]];
-        const float dx = pj.x - xi, dy = pj.y - yi;
+        const float2 pj = J.pos[J.colidx[e]];
+        const float dx = pj.x - pi.x, dy = pj.y - pi.y;
         const float d = sqrtf(dx * dx + dy * dy) * invK;
         ax = fmaf(d, dx, ax);
         ay = fmaf(d, dy, ay);
     }
     ax = group_sum<8>(ax);
     ay = group_sum<8>(ay);
-    if (sub == 0) atte[i] = float2{ax, ay};
+    if (sub == 0) J.atte[i] = float2{ax, ay};
 }
 
 // Heavy rows: one workgroup per row, reduced in a fixed order.
-__global__ __launch_bounds__(256) void att_heavy_kernel(const int *__restrict__ heavy, const int *__restrict__ nheavy,
-                                                        float invK, const int *__restrict__ rowptr,
-                                                        const int *__restrict__ colidx,
-                                                        const int *__restrict__ late_att,
-                                                        const float2 *__restrict__ pos,
-                                                        float2 *__restrict__ atte) {
+__global__ __launch_bounds__(256) void att_heavy_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ float wsx[4], wsy[4];
-    for (int h = blockIdx.x; h < *nheavy; h += gridDim.x) {
-        const int i = heavy[h];
-        const int e0 = rowptr[i] + late_att[i], e1 = rowptr[i + 1];
-        const float2 pi = pos[i];
-        const float xi = pi.x, yi = pi.y;
+    const int nh = *J.nheavy;
+    const float invK = J.invK;
+    for (int h = jb.local; h < nh; h += jb.nblocks) {
+        const int i = J.heavy[h];
+        const int e0 = J.rowptr[i] + J.late_att[i], e1 = J.rowptr[i + 1];
+        const float2 pi = J.pos[i];
         float ax = 0.f, ay = 0.f;
         for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
-            const float2 pj = pos[colidx[e]];
-            const float dx = pj.x - xi, dy = pj.y - yi;
+            const float2 pj = J.pos[J.colidx[e]];
+            const float dx = pj.x - pi.x, dy = pj.y - pi.y;
             const float d = sqrtf(dx * dx + dy * dy) * invK;
             ax = fmaf(d, dx, ax);
             ay = fmaf(d, dy, ay);
@@ -674,95 +760,66 @@ __global__ __launch_bounds__(256) void att_heavy_kernel(const int *__restrict__ 
         }
         __syncthreads();
         if (threadIdx.x == 0)
-            atte[i] = float2{((wsx[0] + wsx[1]) + wsx[2]) + wsx[3], ((wsy[0] + wsy[1]) + wsy[2]) + wsy[3]};
+            J.atte[i] = float2{((wsx[0] + wsx[1]) + wsx[2]) + wsx[3], ((wsy[0] + wsy[1]) + wsy[2]) + wsy[3]};
         __syncthreads();
     }
 }
 
-// ---------------------------------------------------------------- chain
 // ------------------------------------------------------- late entry lists
 // Everything a minibatch step needs that does not depend on moves is laid out
 // before the chain starts: per batch, the "late" entries -- moved neighbours
 // (the CSR prefix) and listed moved leaves -- of all its rows, row by row, as
 // (row in batch << 32 | vertex) words, plus each row's offset in that list.
-constexpr int kMaxChainRows = 2048;   // batch-size limit of the Barnes-Hut chain
-constexpr int kEnt = 8;               // late entries per thread per pass (held in registers)
-
 __device__ __forceinline__ int late_leaf_count(int lc) { return lc > kLateCap ? 0 : lc; }
 
 // Per batch: entry counts of its rows -> exclusive offsets within the batch.
-__global__ __launch_bounds__(1024) void batch_offsets_kernel(int n, int BS, const int *__restrict__ late_att,
-                                                              const int *__restrict__ rowptr,
-                                                              const int *__restrict__ late_cnt,
-                                                              int all_late, int *__restrict__ roff,
-                                                              int *__restrict__ btot) {
+__global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ int ws[16];
-    const int b = blockIdx.x;
-    const int R = min(BS, n - b * BS);
+    const int b = jb.local, BS = J.BS;
+    const int R = min(BS, J.n - b * BS);
     int carry = 0;
     for (int r0 = 0; r0 < R; r0 += 1024) {
         const int r = r0 + (int)threadIdx.x;
         int c = 0;
         if (r < R) {
             const int i = b * BS + r;
-            const int la = all_late ? rowptr[i + 1] - rowptr[i] : late_att[i];
-            c = la + late_leaf_count(late_cnt[i]);
+            const int la = J.all_live ? J.rowptr[i + 1] - J.rowptr[i] : J.late_att[i];
+            c = la + late_leaf_count(J.late_cnt[i]);
         }
         int tot;
         const int off = block_excl_scan(c, ws, &tot);
-        if (r < R) roff[b * BS + r] = carry + off;
+        if (r < R) J.roff[b * BS + r] = carry + off;
         carry += tot;
     }
-    if (threadIdx.x == 0) btot[b] = carry;
+    if (threadIdx.x == 0) {
+        J.bbase[b] = carry;
+        if (b == 0) J.bbase[J.nb] = 0;
+    }
 }
 
 // 8 lanes per row copy its late entries into the batch list; listed leaves
 // (repulsion terms) carry bit 31 of the vertex word, moved neighbours
 // (attraction terms) do not.
-__global__ __launch_bounds__(256) void late_fill_kernel(int n, int BS, const int *__restrict__ late_att,
-                                                        const int *__restrict__ rowptr,
-                                                        const int *__restrict__ colidx,
-                                                        const int *__restrict__ late_cnt,
-                                                        const int *__restrict__ late_ids, int all_late,
-                                                        const int *__restrict__ roff,
-                                                        const int *__restrict__ bbase,
-                                                        unsigned long long *__restrict__ ent) {
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+__global__ __launch_bounds__(256) void late_fill_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const int i = (jb.local * blockDim.x + threadIdx.x) >> 3;
     const int sub = threadIdx.x & 7;
-    if (i >= n) return;
-    const int b = i / BS;
-    const unsigned long long rbits = (unsigned long long)(i - b * BS) << 32;
-    const size_t base = (size_t)bbase[b] + roff[i];
-    const int rs = rowptr[i];
-    const int la = all_late ? rowptr[i + 1] - rs : late_att[i];
-    for (int k = sub; k < la; k += 8) ent[base + k] = rbits | (unsigned)colidx[rs + k];
-    const int ll = late_leaf_count(late_cnt[i]);
-    const int *lid = late_ids + (size_t)i * kLateCap;
+    if (i >= J.n) return;
+    const int b = i / J.BS;
+    const unsigned long long rbits = (unsigned long long)(i - b * J.BS) << 32;
+    const size_t base = (size_t)J.bbase[b] + J.roff[i];
+    const int rs = J.rowptr[i];
+    const int la = J.all_live ? J.rowptr[i + 1] - rs : J.late_att[i];
+    unsigned long long *ent = J.ent;
+    for (int k = sub; k < la; k += 8) ent[base + k] = rbits | (unsigned)J.colidx[rs + k];
+    const int ll = late_leaf_count(J.late_cnt[i]);
+    const int *lid = J.late_ids + (size_t)i * kLateCap;
     for (int k = sub; k < ll; k += 8) ent[base + la + k] = rbits | 0x80000000u | (unsigned)lid[k];
 }
 
 // ---------------------------------------------------------------- chain
-struct ChainArgs {
-    WalkArgs w;
-    int nb_run;          // batches to process with updates
-    int stop_batch;      // batch whose forces go to fout without update (-1: none)
-    int first_batch;     // usually 0; the force call processes only `stop_batch`
-    float2 *pos;
-    const float4 *far;
-    const float2 *atte;  // early attraction (NULL: none)
-    const int *late_cnt;
-    const int *roff;     // [n] offset of each row's entries in its batch list
-    const int *bbase;    // [nb+1] start of each batch list in ent
-    const unsigned long long *ent;
-    size_t ent_cap;      // entries allocated in ent
-    double *fout;        // [2*BS]
-    double *energy_k;
-    Counters *ctr;
-    float step;
-};
-
-// Per-row data of a step, requested one step ahead.  Loads are unconditional
-// with clamped indices so that a step's prefetch is straight-line code.
+// Per-row data of a step, requested one step ahead.
 struct ChainRow {
     int o0, o1;          // entry range of the row in its batch list
     int ovf;             // late-leaf list overflowed: walk the whole tree live
@@ -771,20 +828,18 @@ struct ChainRow {
     float2 atte;
 };
 
-__device__ __forceinline__ ChainRow chain_row(const ChainArgs &a, int b, int r, int R) {
+__device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r, int R) {
     ChainRow d;
-    const int rc = min(r, R - 1);
-    const int i = b * a.w.BS + rc;
-    const int E = a.bbase[b + 1] - a.bbase[b];
-    d.o0 = a.roff[i];
-    const int nxt = a.roff[min(i + 1, a.w.n - 1)];
-    d.o1 = (rc + 1 < R) ? nxt : E;
-    d.ovf = a.late_cnt[i] > kLateCap;
-    const float2 pi = a.pos[i];
+    const int i = b * J.BS + r;
+    const int E = J.bbase[b + 1] - J.bbase[b];
+    d.o0 = J.roff[i];
+    d.o1 = (r + 1 < R) ? J.roff[i + 1] : E;
+    d.ovf = J.late_cnt[i] > kLateCap;
+    const float2 pi = J.pos[i];
     d.x = pi.x;
     d.y = pi.y;
-    d.far = a.far[i];
-    d.atte = a.atte ? a.atte[i] : float2{0.f, 0.f};
+    d.far = J.far[i];
+    d.atte = J.all_live ? float2{0.f, 0.f} : J.atte[i];
     return d;
 }
 
@@ -796,26 +851,37 @@ struct ChainShared {
     float2 cf[kChainThreads];    // first (partial) row of each thread's run
     float2 cl[kChainThreads];    // last (partial) row of each thread's run
     double wsd[16];
+    double step;
 };
 
-// The minibatch chain: one workgroup walks the batches in order.  Per step b:
+// The minibatch chain: one workgroup per job walks its batches in order.
+// Per step b:
 //   - each thread gathers the live positions of the first late entries of its
 //     run (entry words were loaded one step ahead), then requests the next
 //     step's row data and entry words (they do not depend on this step's
-//     moves; issued after the gathers so that waiting for the gathers does
-//     not wait for them), then sums its run row by row;
+//     moves), then sums its run row by row;
 //   - rows cut by thread boundaries are completed from per-thread carries in
 //     thread order; early attraction and the far field are added, and the
 //     thread owning the row moves it (Alg. 2 update loop; Jacobi within the
 //     batch because every gather of the batch precedes the barrier).
-__global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
+// The step length of iteration k is step0 times decay k times (the host uses
+// the same product), k is read from and advanced in device memory.
+__global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
     __shared__ ChainShared S;
     const int tid = threadIdx.x;
-    const int BS = a.w.BS, n = a.w.n;
-    const int last = a.stop_batch >= 0 ? a.stop_batch : a.nb_run - 1;
-    const float invK = a.w.invK, negRK2 = a.w.negRK2;
+    const int BS = J.BS, n = J.n;
+    const int first = J.first_batch, last = J.last_batch;
+    const float invK = J.invK, negRK2 = J.negRK2;
+    const WalkArgs wa = walk_args(J);
     constexpr int RPT = kMaxChainRows / kChainThreads;   // rows per thread
-    const size_t entmax = a.ent_cap - 1;
+    const size_t entmax = J.ent_cap - 1;
+    const int k_it = J.kiter[0];
+    if (tid == 0) {
+        double st = J.step0;
+        for (int t = 0; t < k_it; ++t) st *= J.decay;
+        S.step = st;
+    }
 
     ChainRow rowd[RPT];
     unsigned long long pe[kEnt];
@@ -823,14 +889,14 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
         const int R = min(BS, n - b * BS);
 #pragma unroll
         for (int k = 0; k < RPT; ++k)
-            if (tid + k * kChainThreads < R) rowd[k] = chain_row(a, b, tid + k * kChainThreads, R);
-        const int E = a.bbase[b + 1] - a.bbase[b];
+            if (tid + k * kChainThreads < R) rowd[k] = chain_row(J, b, tid + k * kChainThreads, R);
+        const int E = J.bbase[b + 1] - J.bbase[b];
         const int chunk = (E + kChainThreads - 1) / kChainThreads;
         const int e0 = min(tid * chunk, E), e1 = min(e0 + chunk, E);
-        const size_t gb = (size_t)a.bbase[b];
+        const size_t gb = (size_t)J.bbase[b];
 #pragma unroll
         for (int q = 0; q < kEnt; ++q)
-            if (e0 + q < e1) pe[q] = a.ent[min(gb + (size_t)(e0 + q), entmax)];
+            if (e0 + q < e1) pe[q] = J.ent[min(gb + (size_t)(e0 + q), entmax)];
     };
     auto fetch_lds = [&](int b, int slot) {
         const int R = min(BS, n - b * BS);
@@ -843,17 +909,16 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
                 S.py[slot][r] = rowd[k].y;
             }
         }
-        if (tid == 0) S.off[slot][R] = a.bbase[b + 1] - a.bbase[b];
+        if (tid == 0) S.off[slot][R] = J.bbase[b + 1] - J.bbase[b];
     };
-    if (a.first_batch <= last) {
-        fetch_regs(a.first_batch);
-        fetch_lds(a.first_batch, a.first_batch & 1);
-    }
+    fetch_regs(first);
+    fetch_lds(first, first & 1);
     __syncthreads();
+    const float step = (float)S.step;
 
     double e_iter = 0.0;
     unsigned long long bad = 0;
-    for (int b = a.first_batch; b <= last; ++b) {
+    for (int b = first; b <= last; ++b) {
         const int slot = b & 1;
         const int R = min(BS, n - b * BS);
         const int E = S.off[slot][R];
@@ -875,7 +940,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
             xj[q] = 0.f;
             yj[q] = 0.f;
             if (q < m0) {
-                const float2 pj = a.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
+                const float2 pj = J.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
                 xj[q] = pj.x;
                 yj[q] = pj.y;
             }
@@ -884,10 +949,10 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
         fetch_regs(min(b + 1, last));
 
         if (e0 < e1) {
-            const unsigned long long *src = a.ent + a.bbase[b];
+            const unsigned long long *src = J.ent + J.bbase[b];
             int r = (int)(ce[0] >> 32);
             float ax = 0.f, ay = 0.f;
-            bool first = true;
+            bool firstseg = true;
             for (int base = e0; base < e1; base += kEnt) {
                 const int m = min(kEnt, e1 - base);
                 if (base != e0) {
@@ -897,7 +962,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
 #pragma unroll
                     for (int q = 0; q < kEnt; ++q) {
                         if (q < m) {
-                            const float2 pj = a.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
+                            const float2 pj = J.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
                             xj[q] = pj.x;
                             yj[q] = pj.y;
                         }
@@ -910,9 +975,9 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
                         if (rq != r) {
                             const bool full = S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1;
                             if (full) S.sum[r] = float2{ax, ay};
-                            else if (first) S.cf[tid] = float2{ax, ay};
+                            else if (firstseg) S.cf[tid] = float2{ax, ay};
                             else S.cl[tid] = float2{ax, ay};
-                            first = false;
+                            firstseg = false;
                             ax = ay = 0.f;
                             r = rq;
                         }
@@ -934,13 +999,13 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
             }
             const bool full = S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1;
             if (full) S.sum[r] = float2{ax, ay};
-            else if (first) S.cf[tid] = float2{ax, ay};
+            else if (firstseg) S.cf[tid] = float2{ax, ay};
             else S.cl[tid] = float2{ax, ay};
         }
         __syncthreads();
 
         // complete my rows, add early attraction and far field, move them
-        const bool stop = (b == a.stop_batch);
+        const bool stop = (b == J.stop_batch);
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
             const int r = tid + k * kChainThreads;
@@ -963,13 +1028,13 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
             float4 fr = cur[k].far;
             if (cur[k].ovf) {
                 int dummy = 0;
-                (void)bh_walk(a.w, i, cur[k].x, cur[k].y, 0, a.pos, fr, nullptr, dummy, 0);
+                (void)bh_walk(wa, i, cur[k].x, cur[k].y, 0, J.pos, fr, nullptr, dummy, 0);
             }
             const float fx = (sm.x + cur[k].atte.x) + negRK2 * (fr.x - fr.z);
             const float fy = (sm.y + cur[k].atte.y) + negRK2 * (fr.y - fr.w);
             if (stop) {
-                a.fout[2 * r] = (double)fx;
-                a.fout[2 * r + 1] = (double)fy;
+                J.fout[2 * r] = (double)fx;
+                J.fout[2 * r + 1] = (double)fy;
                 continue;
             }
             const double f2 = (double)fx * fx + (double)fy * fy;
@@ -979,153 +1044,249 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainArgs a) {
             }
             e_iter += f2;
             if (f2 > 0.0) {
-                const float sc = a.step / sqrtf(fx * fx + fy * fy);
-                a.pos[i] = float2{cur[k].x + sc * fx, cur[k].y + sc * fy};
+                const float sc = step / sqrtf(fx * fx + fy * fy);
+                J.pos[i] = float2{cur[k].x + sc * fx, cur[k].y + sc * fy};
             }
         }
         if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1);
         __syncthreads();
     }
-    if (bad) atomicAdd(&a.ctr->nonfinite, bad);
+    if (bad) atomicAdd(&J.ctr->nonfinite, bad);
     const double e = block_sum_fixed(e_iter, S.wsd);
-    if (tid == 0 && a.energy_k) *a.energy_k = e;
+    if (tid == 0 && J.stop_batch < 0) {
+        J.energy[k_it - J.kiter[1]] = e;
+        J.kiter[0] = k_it + 1;
+    }
 }
 
 // ------------------------------------------------------------- host side
-int build_tree(bl_graph *g, const float2 *sp) {
-    BHBuffers &h = g->bh;
-    const int n = g->n;
-    hipStream_t s = g->stream;
-    int slot;
-    BL_TRY(prof_begin(g, PK_TREE, &slot));
-    hipLaunchKernelGGL(bbox_kernel, dim3(kBBoxBlocks), dim3(256), 0, s, n, sp, h.bbox_part,
-                       (unsigned *)(h.bbox + 8), h.bbox);
-    hipLaunchKernelGGL(morton_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, sp, h.bbox,
-                       h.key[0], h.val[0]);
-    int cur = 0;
-    for (int shift = 0; shift < 32; shift += 8) {
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(h.tiles), dim3(kSortThreads), 0, s, h.key[cur], n,
-                           shift, h.hist, h.tiles);
-        hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, s, h.hist, 256 * h.tiles);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(h.tiles), dim3(kSortThreads), 0, s, h.key[cur],
-                           h.val[cur], h.key[cur ^ 1], h.val[cur ^ 1], n, shift, h.hist, h.tiles);
-        cur ^= 1;
+namespace {
+
+enum PreType { PT_BBOX = 0, PT_VERT, PT_SORT, PT_ONE, PT_MARK, PT_SCAN, PT_VERT8, PT_HEAVY, PT_BATCH, PT_COUNT };
+
+int blocks_for(int type, const BHJob &J) {
+    const int n = J.n;
+    switch (type) {
+        case PT_BBOX: return std::max(1, std::min(kBBoxBlocks, (n + 255) / 256));
+        case PT_VERT: return (n + 255) / 256;
+        case PT_SORT: return J.tiles;
+        case PT_ONE: return 1;
+        case PT_MARK: return std::max(1, (n - 1 + 255) / 256);
+        case PT_SCAN: return J.sblocks;
+        case PT_VERT8: return (n + 31) / 32;
+        case PT_HEAVY: return kHeavyBlocks;
+        case PT_BATCH: return J.nb;
     }
-    // after 4 passes the sorted data is back in buffer 0
-    const unsigned *keys = h.key[0];
-    const int *order = h.val[0];
-    BL_HIP(hipMemsetAsync(h.mask, 0, sizeof(unsigned) * n, s));
-    if (n > 1) hipLaunchKernelGGL(mark_kernel, dim3((n - 1 + 255) / 256), dim3(256), 0, s, n, keys, h.mask);
-    const int sblocks = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(count_tile_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, h.mask, h.scan_part);
-    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, s, h.scan_part, sblocks);
-    hipLaunchKernelGGL(count_apply_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, h.mask, h.scan_part,
-                       h.cellcnt);
-    hipLaunchKernelGGL(coord_tile_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, order, sp, h.pdd_part);
-    hipLaunchKernelGGL(coord_part_scan_kernel, dim3(1), dim3(64), 0, s, sblocks, h.pdd_part);
-    hipLaunchKernelGGL(coord_apply_kernel, dim3(sblocks), dim3(kScanThreads), 0, s, n, order, sp,
-                       h.pdd_part, h.pdd);
-    hipLaunchKernelGGL(emit_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, keys, order, h.mask,
-                       h.cellcnt, h.pdd, sp, h.bbox, h.nodeA, h.nodeB, h.leafpos, h.nnodes);
-    BL_HIP(hipGetLastError());
-    return prof_end(g, slot);
-}
-
-WalkArgs walk_args(bl_graph *g) {
-    WalkArgs w;
-    w.n = g->n;
-    w.BS = g->p.batch_size;
-    w.total = g->bh.nnodes;
-    w.nodeA = g->bh.nodeA;
-    w.nodeB = g->bh.nodeB;
-    w.leafpos = g->bh.leafpos;
-    w.theta2 = (float)(g->p.theta * g->p.theta);
-    w.negRK2 = (float)(-g->p.R * g->p.K * g->p.K);
-    w.invK = (float)(1.0 / g->p.K);
-    return w;
-}
-
-// Moved-neighbour prefix lengths (once per job) and the early attraction.
-int early_pass(bl_graph *g) {
-    BHBuffers &h = g->bh;
-    const int n = g->n;
-    if (!h.prefix_ready) {
-        BL_HIP(hipMemsetAsync(h.nheavy, 0, sizeof(int), g->stream));
-        hipLaunchKernelGGL(late_prefix_kernel, dim3((n + 255) / 256), dim3(256), 0, g->stream, n,
-                           g->p.batch_size, g->rowptr, g->colidx, h.late_att, h.heavy, h.nheavy);
-        BL_HIP(hipGetLastError());
-        h.prefix_ready = true;
-    }
-    const float invK = (float)(1.0 / g->p.K);
-    hipLaunchKernelGGL(att_early_kernel, dim3((n + 31) / 32), dim3(256), 0, g->stream, n, invK, g->rowptr,
-                       g->colidx, h.late_att, (const float2 *)g->x, h.atte);
-    hipLaunchKernelGGL(att_heavy_kernel, dim3(256), dim3(256), 0, g->stream, h.heavy, h.nheavy, invK,
-                       g->rowptr, g->colidx, h.late_att, (const float2 *)g->x, h.atte);
-    BL_HIP(hipGetLastError());
-    return BL_OK;
-}
-
-// Far-field walks of all vertices; (px, py) are the vertices' own positions.
-int far_pass(bl_graph *g, const WalkArgs &w, const float2 *pp, int all_live) {
-    const int snap = (g->p.flags & BL_BH_SNAPSHOT_LEAVES) ? 1 : 0;
-    int slot;
-    BL_TRY(prof_begin(g, PK_FAR, &slot));
-    hipLaunchKernelGGL(far_kernel, dim3((g->n + 255) / 256), dim3(256), 0, g->stream, w, g->bh.val[0], pp,
-                       all_live, snap && !all_live, g->bh.far, g->bh.late_cnt, g->bh.late_ids, g->counters);
-    BL_HIP(hipGetLastError());
-    return prof_end(g, slot);
-}
-
-// Late entry lists of all batches (needs the far pass's late-leaf counts).
-int late_lists(bl_graph *g, bool all_late) {
-    BHBuffers &h = g->bh;
-    const int n = g->n, BS = g->p.batch_size, nb = g->nb;
-    hipLaunchKernelGGL(batch_offsets_kernel, dim3(nb), dim3(1024), 0, g->stream, n, BS, h.late_att, g->rowptr,
-                       h.late_cnt, all_late ? 1 : 0, h.roff, h.bbase);
-    BL_HIP(hipMemsetAsync(h.bbase + nb, 0, sizeof(int), g->stream));
-    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(kScanThreads), 0, g->stream, h.bbase, nb + 1);
-    hipLaunchKernelGGL(late_fill_kernel, dim3((n + 31) / 32), dim3(256), 0, g->stream, n, BS, h.late_att,
-                       g->rowptr, g->colidx, h.late_cnt, h.late_ids, all_late ? 1 : 0, h.roff, h.bbase,
-                       h.ent);
-    BL_HIP(hipGetLastError());
-    return BL_OK;
-}
-
-int chain(bl_graph *g, const WalkArgs &w, int first_batch, int nb_run, int stop_batch, int k,
-          double *energy_k, bool early) {
-    ChainArgs a;
-    a.w = w;
-    a.nb_run = nb_run;
-    a.stop_batch = stop_batch;
-    a.first_batch = first_batch;
-    a.pos = (float2 *)g->x;
-    a.far = g->bh.far;
-    a.atte = early ? g->bh.atte : nullptr;
-    a.late_cnt = g->bh.late_cnt;
-    a.roff = g->bh.roff;
-    a.bbase = g->bh.bbase;
-    a.ent = g->bh.ent;
-    a.ent_cap = (size_t)g->nnz + (size_t)g->n * kLateCap;
-    a.fout = g->fout;
-    a.energy_k = energy_k;
-    a.ctr = g->counters;
-    a.step = (float)step_at(g->p, k);
-    int slot;
-    BL_TRY(prof_begin(g, PK_CHAIN, &slot));
-    hipLaunchKernelGGL(chain_kernel, dim3(1), dim3(kChainThreads), 0, g->stream, a);
-    BL_HIP(hipGetLastError());
-    return prof_end(g, slot);
+    return 0;
 }
 
 }  // namespace
 
-size_t bh_footprint(int n) {
+// Device tables of the resident jobs, double-buffered so that a new job set
+// can be uploaded while launches that read the previous one are in flight.
+struct BHEngine {
+    hipStream_t stream = nullptr;
+    int G = 0, cap = 0, cur = 0;
+    BHJob *d_jobs[2] = {nullptr, nullptr};
+    int *d_pre[2] = {nullptr, nullptr};
+    BHJob *h_jobs[2] = {nullptr, nullptr};   // pinned staging
+    int *h_pre[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool ev_used[2] = {false, false};
+    int total[PT_COUNT] = {};
+};
+
+int bh_engine_create(hipStream_t s, BHEngine **out) {
+    BHEngine *e = new BHEngine();
+    e->stream = s;
+    for (int q = 0; q < 2; ++q) {
+        hipError_t r = hipEventCreateWithFlags(&e->ev[q], hipEventDisableTiming);
+        if (r != hipSuccess) {
+            bh_engine_destroy(e);
+            set_error("hipEventCreate failed: %s", hipGetErrorString(r));
+            return BL_E_HIP;
+        }
+    }
+    *out = e;
+    return BL_OK;
+}
+
+void bh_engine_destroy(BHEngine *e) {
+    if (!e) return;
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    for (int q = 0; q < 2; ++q) {
+        if (e->d_jobs[q]) (void)hipFree(e->d_jobs[q]);
+        if (e->d_pre[q]) (void)hipFree(e->d_pre[q]);
+        if (e->h_jobs[q]) (void)hipHostFree(e->h_jobs[q]);
+        if (e->h_pre[q]) (void)hipHostFree(e->h_pre[q]);
+        if (e->ev[q]) (void)hipEventDestroy(e->ev[q]);
+    }
+    delete e;
+}
+
+// Descriptor of a job from its buffers.
+int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
+    BHBuffers &h = g->bh;
+    std::memset(J, 0, sizeof *J);
+    J->n = g->n;
+    J->BS = g->p.batch_size;
+    J->nb = g->nb;
+    J->tiles = (g->n + kSortTile - 1) / kSortTile;
+    J->sblocks = (g->n + kScanTile - 1) / kScanTile;
+    J->theta2 = (float)(g->p.theta * g->p.theta);
+    J->negRK2 = (float)(-g->p.R * g->p.K * g->p.K);
+    J->invK = (float)(1.0 / g->p.K);
+    J->snapshot_leaves = (g->p.flags & BL_BH_SNAPSHOT_LEAVES) ? 1 : 0;
+    J->all_live = spec.all_live;
+    J->first_batch = spec.first_batch;
+    J->last_batch = spec.last_batch;
+    J->stop_batch = spec.stop_batch;
+    J->step0 = g->p.step0;
+    J->decay = g->p.step_decay;
+    J->kiter = h.kiter;
+    J->rowptr = g->rowptr;
+    J->colidx = g->colidx;
+    J->pos = (float2 *)g->x;
+    J->src = spec.src ? spec.src : (const float2 *)g->x;
+    J->bbox = h.bbox;
+    J->bbox_part = h.bbox_part;
+    J->ticket = (unsigned *)(h.bbox + 8);
+    J->key0 = h.key[0];
+    J->key1 = h.key[1];
+    J->val0 = h.val[0];
+    J->val1 = h.val[1];
+    J->hist = h.hist;
+    J->mask = h.mask;
+    J->cellcnt = h.cellcnt;
+    J->scan_part = h.scan_part;
+    J->pdd = h.pdd;
+    J->pdd_part = h.pdd_part;
+    J->nodeA = h.nodeA;
+    J->nodeB = h.nodeB;
+    J->leafpos = h.leafpos;
+    J->nnodes = h.nnodes;
+    J->far = h.far;
+    J->late_cnt = h.late_cnt;
+    J->late_ids = h.late_ids;
+    J->late_att = h.late_att;
+    J->heavy = h.heavy;
+    J->nheavy = h.nheavy;
+    J->atte = h.atte;
+    J->roff = h.roff;
+    J->bbase = h.bbase;
+    J->ent = h.ent;
+    J->ent_cap = (size_t)g->nnz + (size_t)g->n * kLateCap;
+    J->energy = g->energy;
+    J->fout = g->fout;
+    J->ctr = g->counters;
+    return BL_OK;
+}
+
+// Make `jobs` the resident set (descriptors already filled).
+int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
+    const int s = e->cur ^ 1;
+    if (e->ev_used[s]) BL_HIP(hipEventSynchronize(e->ev[s]));
+    if (G > e->cap) {
+        BL_HIP(hipStreamSynchronize(e->stream));
+        const int cap = std::max(G, 2 * e->cap);
+        for (int q = 0; q < 2; ++q) {
+            if (e->d_jobs[q]) BL_HIP(hipFree(e->d_jobs[q]));
+            if (e->d_pre[q]) BL_HIP(hipFree(e->d_pre[q]));
+            if (e->h_jobs[q]) BL_HIP(hipHostFree(e->h_jobs[q]));
+            if (e->h_pre[q]) BL_HIP(hipHostFree(e->h_pre[q]));
+            e->d_jobs[q] = nullptr;
+            e->d_pre[q] = nullptr;
+            BL_HIP(hipMalloc((void **)&e->d_jobs[q], sizeof(BHJob) * cap));
+            BL_HIP(hipMalloc((void **)&e->d_pre[q], sizeof(int) * PT_COUNT * (cap + 1)));
+            BL_HIP(hipHostMalloc((void **)&e->h_jobs[q], sizeof(BHJob) * cap, hipHostMallocDefault));
+            BL_HIP(hipHostMalloc((void **)&e->h_pre[q], sizeof(int) * PT_COUNT * (cap + 1), hipHostMallocDefault));
+        }
+        e->cap = cap;
+        e->ev_used[0] = e->ev_used[1] = false;
+    }
+    std::memcpy(e->h_jobs[s], jobs, sizeof(BHJob) * G);
+    for (int t = 0; t < PT_COUNT; ++t) {
+        int *pre = e->h_pre[s] + t * (e->cap + 1);
+        pre[0] = 0;
+        for (int j = 0; j < G; ++j) pre[j + 1] = pre[j] + blocks_for(t, jobs[j]);
+        e->total[t] = pre[G];
+    }
+    BL_HIP(hipMemcpyAsync(e->d_jobs[s], e->h_jobs[s], sizeof(BHJob) * G, hipMemcpyHostToDevice, e->stream));
+    BL_HIP(hipMemcpyAsync(e->d_pre[s], e->h_pre[s], sizeof(int) * PT_COUNT * (e->cap + 1),
+                          hipMemcpyHostToDevice, e->stream));
+    // launches that read the previous tables are all enqueued before this point
+    BL_HIP(hipEventRecord(e->ev[e->cur], e->stream));
+    e->ev_used[e->cur] = true;
+    e->cur = s;
+    e->G = G;
+    return BL_OK;
+}
+
+#define BH_LAUNCH(kernel, type, threads, ...)                                                       \
+    do {                                                                                            \
+        if (e->total[type] > 0)                                                                     \
+            hipLaunchKernelGGL(kernel, dim3(e->total[type]), dim3(threads), 0, e->stream, jobs,     \
+                               e->d_pre[e->cur] + (type) * (e->cap + 1), e->G, ##__VA_ARGS__);      \
+    } while (0)
+
+// Once per job set: lengths of the moved-neighbour CSR prefixes, heavy rows.
+int bh_engine_setup(BHEngine *e) {
+    if (e->G == 0) return BL_OK;
+    const BHJob *jobs = e->d_jobs[e->cur];
+    BH_LAUNCH(heavy_reset_kernel, PT_ONE, 64);
+    BH_LAUNCH(late_prefix_kernel, PT_VERT, 256);
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
+// One layout iteration of every job of the set.
+int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
+    if (e->G == 0) return BL_OK;
+    const BHJob *jobs = e->d_jobs[e->cur];
+    int slot = -1;
+    if (prof) BL_TRY(prof_begin(prof, PK_TREE, &slot));
+    BH_LAUNCH(bbox_kernel, PT_BBOX, 256);
+    BH_LAUNCH(morton_kernel, PT_VERT, 256);
+    for (int pass = 0; pass < 4; ++pass) {
+        BH_LAUNCH(radix_hist_kernel, PT_SORT, kSortThreads, pass);
+        BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 0);
+        BH_LAUNCH(radix_scatter_kernel, PT_SORT, kSortThreads, pass);
+    }
+    BH_LAUNCH(mark_kernel, PT_MARK, 256);
+    BH_LAUNCH(count_tile_kernel, PT_SCAN, kScanThreads);
+    BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 1);
+    BH_LAUNCH(count_apply_kernel, PT_SCAN, kScanThreads);
+    BH_LAUNCH(coord_tile_kernel, PT_SCAN, kScanThreads);
+    BH_LAUNCH(coord_part_scan_kernel, PT_ONE, 64);
+    BH_LAUNCH(coord_apply_kernel, PT_SCAN, kScanThreads);
+    BH_LAUNCH(emit_kernel, PT_VERT, 256);
+    if (prof) BL_TRY(prof_end(prof, slot));
+    if (prof) BL_TRY(prof_begin(prof, PK_FAR, &slot));
+    BH_LAUNCH(far_kernel, PT_VERT, 256);
+    if (prof) BL_TRY(prof_end(prof, slot));
+    BH_LAUNCH(att_early_kernel, PT_VERT8, 256);
+    BH_LAUNCH(att_heavy_kernel, PT_HEAVY, 256);
+    BH_LAUNCH(batch_offsets_kernel, PT_BATCH, 1024);
+    BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 2);
+    BH_LAUNCH(late_fill_kernel, PT_VERT8, 256);
+    if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
+    BH_LAUNCH(chain_kernel, PT_ONE, kChainThreads);
+    if (prof) BL_TRY(prof_end(prof, slot));
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
+size_t bh_job_size() { return sizeof(BHJob); }
+
+size_t bh_footprint(int n, int64_t nnz, int BS) {
     const size_t N = (size_t)n;
     const size_t tiles = (N + kSortTile - 1) / kSortTile;
     const size_t sblocks = (N + kScanTile - 1) / kScanTile;
+    const size_t nb = (N + BS - 1) / BS;
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
-           4 * N * kLateCap + 8 * N + 8 * 1024 + 16 * N + 16 + 4 * N + 4 * N + 8 * N * kLateCap;
+           4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
+           8 * ((size_t)nnz + N * kLateCap) + 64;
 }
 
 int bh_alloc(bl_graph *g) {
@@ -1153,7 +1314,6 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.late_cnt, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.late_ids, 4 * N * kLateCap));
     BL_TRY(graph_alloc(g, (void **)&h.snap, 8 * N));
-    BL_TRY(graph_alloc(g, (void **)&h.fbuf, 8 * (size_t)g->p.batch_size));
     BL_TRY(graph_alloc(g, (void **)&h.late_att, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.heavy, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nheavy, 16));
@@ -1161,41 +1321,69 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.roff, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.bbase, 4 * ((size_t)g->nb + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.ent, 8 * ((size_t)g->nnz + N * kLateCap)));
-    h.prefix_ready = false;
+    BL_TRY(graph_alloc(g, (void **)&h.kiter, 16));
     BL_HIP(hipMemsetAsync(h.bbox, 0, 64, g->stream));
+    BL_HIP(hipMemsetAsync(h.kiter, 0, 16, g->stream));
+    return BL_OK;
+}
+
+// Start a run of job g at iteration k (device-side iteration counter).
+int bh_set_iteration(bl_graph *g, int k) {
+    g->bh.host_kiter[0] = k;
+    g->bh.host_kiter[1] = k;
+    BL_HIP(hipMemcpyAsync(g->bh.kiter, g->bh.host_kiter, 2 * sizeof(int), hipMemcpyHostToDevice, g->stream));
+    return BL_OK;
+}
+
+static int single_engine(bl_graph *g, const BHRunSpec &spec) {
+    if (!g->bh.engine) BL_TRY(bh_engine_create(g->stream, &g->bh.engine));
+    BHJob J;
+    BL_TRY(bh_fill_job(g, &J, spec));
+    BL_TRY(bh_engine_set(g->bh.engine, &J, 1));
     return BL_OK;
 }
 
 int bh_run(bl_graph *g, int iters, int start, int stop_batch) {
-    const float2 *pos = (const float2 *)g->x;
+    if (iters <= 0) return BL_OK;
+    BL_TRY(bh_set_iteration(g, start));
+    BHRunSpec spec;
+    spec.last_batch = g->nb - 1;
+    BL_TRY(single_engine(g, spec));
+    if (!g->bh.prefix_ready) {
+        BL_TRY(bh_engine_setup(g->bh.engine));
+        g->bh.prefix_ready = true;
+    }
     for (int t = 0; t < iters; ++t) {
-        const int k = start + t;
-        const bool last = (t == iters - 1);
-        BL_TRY(build_tree(g, pos));
-        const WalkArgs w = walk_args(g);
-        BL_TRY(far_pass(g, w, pos, 0));
-        BL_TRY(early_pass(g));
-        BL_TRY(late_lists(g, false));
-        const int stop = (last && stop_batch >= 0) ? stop_batch : -1;
-        BL_TRY(chain(g, w, 0, stop >= 0 ? stop : g->nb, stop, k, stop >= 0 ? nullptr : g->energy + t, true));
+        if (t == iters - 1 && stop_batch >= 0) {
+            BHRunSpec st;
+            st.last_batch = stop_batch;
+            st.stop_batch = stop_batch;
+            BL_TRY(single_engine(g, st));
+        }
+        BL_TRY(bh_engine_iteration(g->bh.engine, g));
     }
     return BL_OK;
 }
 
 // Forces of one batch from coordinates (x, y) with the tree of the snapshot
-// (snap_x, snap_y); every leaf uses (x, y).
+// (snap_x, snap_y); every leaf and neighbour uses (x, y).
 int bh_forces(bl_graph *g, int batch, const double *snap_x, const double *snap_y) {
-    const float2 *sp = (const float2 *)g->x;
+    BHRunSpec spec;
+    spec.all_live = 1;
+    spec.first_batch = batch;
+    spec.last_batch = batch;
+    spec.stop_batch = batch;
     if (snap_x) {
         BL_TRY(convert_to_float2(g, snap_x, snap_y, (float2 *)g->bh.snap));
-        sp = (const float2 *)g->bh.snap;
+        spec.src = (const float2 *)g->bh.snap;
     }
-    BL_TRY(build_tree(g, sp));
-    const WalkArgs w = walk_args(g);
-    BL_TRY(far_pass(g, w, (const float2 *)g->x, 1));
-    if (!g->bh.prefix_ready) BL_TRY(early_pass(g));
-    BL_TRY(late_lists(g, true));
-    return chain(g, w, batch, batch + 1, batch, 0, nullptr, false);
+    BL_TRY(bh_set_iteration(g, 0));
+    BL_TRY(single_engine(g, spec));
+    if (!g->bh.prefix_ready) {
+        BL_TRY(bh_engine_setup(g->bh.engine));
+        g->bh.prefix_ready = true;
+    }
+    return bh_engine_iteration(g->bh.engine, g);
 }
 
 }  // namespace bl

@@ -113,6 +113,7 @@ static int check_csr(const bl_csr *g, uint32_t flags, hipStream_t s) {
 
 static void free_graph(bl_graph *g) {
     if (!g) return;
+    if (g->p.mode == BL_BH && g->bh.engine) bh_engine_destroy(g->bh.engine);
     for (int q = 0; q < g->nowned; ++q) (void)hipFree(g->owned[q]);
     if (g->prof) {
         for (int q = 0; q < 2 * kProfPool; ++q)
@@ -169,7 +170,7 @@ size_t bl_footprint_bytes(int32_t n, int64_t nnz, const bl_params *p) {
     if (p->mode == BL_EXACT)
         b += 2 * (2 * T * N + 8 * N) + 2 * T * (size_t)p->batch_size + 256;
     else
-        b += bh_footprint(n);
+        b += bh_footprint(n, nnz, p->batch_size);
     return b;
 }
 

@@ -53,7 +53,10 @@ struct Prof {
     long long late_total = 0;
 };
 
-// Barnes-Hut buffers of one job (all device memory).
+struct BHEngine;
+struct BHJob;
+
+// Barnes-Hut buffers of one job (device memory unless noted).
 struct BHBuffers {
     float *bbox;            // [6]: xmin, ymin, W, scale, pad, pad
     float *bbox_part;       // [2 * 4 * kBBoxBlocks] block partial min/max
@@ -82,7 +85,17 @@ struct BHBuffers {
     int *roff;              // [n] offset of each row's late entries within its batch list
     int *bbase;             // [nb + 1] start of each batch's late entry list
     unsigned long long *ent;// late entries (row in batch << 32 | vertex, bit 31: leaf)
+    int *kiter;             // [2] current iteration, first iteration of the run
+    int host_kiter[2];      // host staging for kiter
     bool prefix_ready;      // late_att/heavy computed for this job
+    BHEngine *engine;       // one-job launch tables (host object)
+};
+
+// What one run of a Barnes-Hut job computes.
+struct BHRunSpec {
+    int all_live = 0;             // one-shot forces: all leaves and neighbours live
+    int first_batch = 0, last_batch = 0, stop_batch = -1;
+    const float2 *src = nullptr;  // tree source (NULL: the live coordinates)
 };
 
 // Exact-mode buffers (all device memory).
@@ -134,7 +147,17 @@ int exact_forces(bl_graph *g, int batch);
 int bh_alloc(bl_graph *g);
 int bh_run(bl_graph *g, int iters, int start_iter, int stop_batch);
 int bh_forces(bl_graph *g, int batch, const double *snap_x, const double *snap_y);
-size_t bh_footprint(int n);
+size_t bh_footprint(int n, int64_t nnz, int batch_size);
+int bh_set_iteration(bl_graph *g, int k);
+
+// Multi-job launches: one launch per kernel serves every job of the set.
+int bh_engine_create(hipStream_t s, BHEngine **out);
+void bh_engine_destroy(BHEngine *e);
+int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec);
+int bh_engine_set(BHEngine *e, const BHJob *jobs, int G);
+int bh_engine_setup(BHEngine *e);
+int bh_engine_iteration(BHEngine *e, bl_graph *prof);
+size_t bh_job_size();
 
 // shared kernels (bl_common.hip)
 int energy_sum(bl_graph *g, int k);
