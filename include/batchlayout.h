@@ -178,6 +178,18 @@ int bl_graph_profile(bl_graph *h, int32_t enable);
  * the far-field walks listed for the chain. */
 int bl_graph_profile_read(bl_graph *h, const char *kernel, double *total_ms, int64_t *launches);
 
+/* -------------------------------------------------- many graphs at once
+ * Lay out G independent graphs; graph i uses params[i] (iterations, batch
+ * size, mode, theta may differ).  Graphs small enough for one workgroup run
+ * in one persistent launch, one workgroup per graph; larger graphs run
+ * through the single-graph path on the same stream.  Each result equals the
+ * graph's own bl_layout result bitwise.  x_out[i] may alias x0[i].
+ * stats (may be NULL) has G entries. */
+int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const double *const *x0,
+                    const double *const *y0, const bl_params *const *params,
+                    void *hip_stream, double *const *x_out, double *const *y_out,
+                    bl_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ BL_DEVICE_PTRS, BL_VALIDATE, BL_BH_SNAPSHOT_LEAVES = 1, 2, 4
 EXPORTED = [
     "bl_params_init", "bl_last_error", "bl_version", "bl_footprint_bytes", "bl_layout", "bl_forces",
     "bl_graph_create", "bl_graph_set_coords", "bl_graph_get_coords", "bl_graph_run",
-    "bl_graph_destroy", "bl_graph_profile", "bl_graph_profile_read",
+    "bl_graph_destroy", "bl_graph_profile", "bl_graph_profile_read", "bl_layout_batch",
 ]
 
 
@@ -87,8 +87,7 @@ def load():
     lib.bl_graph_profile.argtypes = [vp, i32]
     lib.bl_graph_profile_read.argtypes = [vp, C.c_char_p, P(dbl), P(i64)]
     if hasattr(lib, "bl_layout_batch"):
-        lib.bl_layout_batch.argtypes = [i32, P(P(CSR)), P(vp), P(vp), P(P(Params)), vp, P(vp), P(vp),
-                                        P(Stats)]
+        lib.bl_layout_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp]
     if hasattr(lib, "bl_server_create"):
         lib.bl_server_create.argtypes = [C.c_size_t, i32, vp, P(vp)]
         lib.bl_server_submit.argtypes = [vp, P(CSR), vp, vp, P(Params), P(i64)]

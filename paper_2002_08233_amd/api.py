@@ -137,6 +137,27 @@ def forces(graph, x, y, batch_index, p: Params, snapshot=None, stream=None):
     return fx[:R], fy[:R]
 
 
+def layout_batch(graphs, x0s, y0s, plist, stream=None):
+    """Lay out many graphs at once (host arrays).  Returns ([(x, y)], [stats])."""
+    lib = load()
+    G = len(graphs)
+    keep = _Keep()
+    csrs = [_csr(g, keep) for g in graphs]
+    pp = [Params.from_buffer_copy(p) for p in plist]
+    CP = C.POINTER(L.CSR)
+    PP = C.POINTER(Params)
+    csr_arr = (CP * G)(*[C.pointer(c) for c in csrs])
+    par_arr = (PP * G)(*[C.pointer(p) for p in pp])
+    xin = (C.c_void_p * G)(*[keep.host(x, np.float64) for x in x0s])
+    yin = (C.c_void_p * G)(*[keep.host(y, np.float64) for y in y0s])
+    outs = [(np.empty(c.n), np.empty(c.n)) for c in csrs]
+    xo = (C.c_void_p * G)(*[o[0].ctypes.data for o in outs])
+    yo = (C.c_void_p * G)(*[o[1].ctypes.data for o in outs])
+    st = (Stats * G)()
+    check(lib.bl_layout_batch(G, csr_arr, xin, yin, par_arr, _stream(stream), xo, yo, st))
+    return outs, [st[q].as_dict() for q in range(G)]
+
+
 def footprint_bytes(n, nnz, p: Params) -> int:
     return int(load().bl_footprint_bytes(int(n), int(nnz), C.byref(p)))
 

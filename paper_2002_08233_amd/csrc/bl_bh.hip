@@ -1278,6 +1278,45 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
 
 size_t bh_job_size() { return sizeof(BHJob); }
 
+// `iters` iterations of the current job set.  With use_graph, one iteration's
+// launches are captured once into a hipGraph and replayed (the iteration
+// number lives on the device, so every replay is identical).
+int bh_engine_run(BHEngine *e, int iters, bool use_graph) {
+    if (e->G == 0 || iters <= 0) return BL_OK;
+    if (!use_graph || iters == 1) {
+        for (int t = 0; t < iters; ++t) BL_TRY(bh_engine_iteration(e, nullptr));
+        return BL_OK;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BL_HIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+    int rc = bh_engine_iteration(e, nullptr);
+    hipError_t ce = hipStreamEndCapture(e->stream, &graph);
+    if (rc != BL_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ce != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
+        return BL_E_HIP;
+    }
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+        return BL_E_HIP;
+    }
+    hipError_t le = hipSuccess;
+    for (int t = 0; t < iters && le == hipSuccess; ++t) le = hipGraphLaunch(exec, e->stream);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (le != hipSuccess) {
+        set_error("hipGraphLaunch failed: %s", hipGetErrorString(le));
+        return BL_E_HIP;
+    }
+    return BL_OK;
+}
+
 size_t bh_footprint(int n, int64_t nnz, int BS) {
     const size_t N = (size_t)n;
     const size_t tiles = (N + kSortTile - 1) / kSortTile;

@@ -45,7 +45,11 @@ int graph_alloc(bl_graph *g, void **ptr, size_t bytes) {
     return BL_OK;
 }
 
-static int check_params(const bl_params *p) {
+int check_params(const bl_params *p);
+int fail_code(int code, const char *msg) { return fail(code, "%s", msg); }
+int params_check(const bl_params *p) { return check_params(p); }
+
+int check_params(const bl_params *p) {
     if (!p) return fail(BL_E_INVAL, "params is NULL");
     if (p->batch_size < 1) return fail(BL_E_INVAL, "batch_size must be >= 1");
     if (p->iterations < 0) return fail(BL_E_INVAL, "iterations must be >= 0");
@@ -129,6 +133,24 @@ static int ensure_energy(bl_graph *g, int iters) {
     BL_TRY(graph_alloc(g, (void **)&g->energy, sizeof(double) * cap));
     g->energy_cap = cap;
     return BL_OK;
+}
+
+// Stats of a finished run of g (device counters and per-iteration energies).
+int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds) {
+    Counters c{};
+    BL_HIP(hipMemcpy(&c, g->counters, sizeof c, hipMemcpyDeviceToHost));
+    double e_last = 0.0;
+    if (iters_run > 0) BL_HIP(hipMemcpy(&e_last, g->energy + iters_run - 1, 8, hipMemcpyDeviceToHost));
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->iters_run = iters_run;
+        st->energy_last = e_last;
+        st->seconds = seconds;
+        st->node_visits = (int64_t)c.visits;
+        st->nonfinite_events = (int64_t)c.nonfinite;
+        st->late_overflow = (int32_t)c.late_overflow;
+    }
+    return c.nonfinite ? BL_E_NONFINITE : BL_OK;
 }
 
 }  // namespace bl

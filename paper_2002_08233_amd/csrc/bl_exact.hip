@@ -17,8 +17,15 @@
 // of a run and the one-shot force call), panel_kernel (the per-step panel),
 // finalize_kernel (attraction over CSR edges with live coordinates, one wave
 // per row, then the batch update by the last workgroup to finish).
+#include <vector>
+
 #include "bl_device.hpp"
 #include "bl_internal.hpp"
+
+// Only explicit fma() calls fuse: the same row arithmetic is compiled into
+// several kernels (multi-workgroup steps and the one-workgroup-per-graph
+// batch kernel), and must round identically in all of them.
+#pragma clang fp contract(off)
 
 namespace bl {
 namespace {
@@ -101,16 +108,16 @@ __device__ __forceinline__ void batch_partial(const T *__restrict__ x, const T *
     }
 }
 
-// Row sums over whole column batches.  from_own_batch = 1: batches
-// [batch(i), nb) (the run prologue: everything a row sees as "old" in its
-// first iteration); 0: all batches (one-shot forces).  Overwrites the sums.
+// Row sums over whole column batches for the rows [first, first + blockDim)
+// that are < row1.  from_own_batch = 1: batches [batch(i), nb) (the run
+// prologue: everything a row sees as "old" in its first iteration); 0: all
+// batches (one-shot forces).  Overwrites the sums.
 template <typename T, bool KAHAN>
-__global__ __launch_bounds__(kPanelThreads) void rows_kernel(
-    int n, int BS, int nb, int row0, int row1, int from_own_batch, const T *__restrict__ x,
-    const T *__restrict__ y, typename V2<T>::type *__restrict__ accS, float2 *__restrict__ accC) {
+__device__ __forceinline__ void rows_block(int n, int BS, int nb, int first, int row1, int from_own_batch,
+                                           const T *__restrict__ x, const T *__restrict__ y,
+                                           typename V2<T>::type *__restrict__ accS,
+                                           float2 *__restrict__ accC, typename V2<T>::type *cols) {
     using T2 = typename V2<T>::type;
-    __shared__ T2 cols[kTile];
-    const int first = row0 + blockIdx.x * kPanelThreads;
     const int i = first + threadIdx.x;
     const bool active = i < row1;
     const int bi = active ? i / BS : nb;
@@ -134,19 +141,29 @@ __global__ __launch_bounds__(kPanelThreads) void rows_kernel(
     }
 }
 
-// The panel of step (k, b): columns = batch b (just moved), rows = all.
 template <typename T, bool KAHAN>
-__global__ __launch_bounds__(kPanelThreads) void panel_kernel(
-    int n, int BS, int b, int do_next, const T *__restrict__ x, const T *__restrict__ y,
-    typename V2<T>::type *__restrict__ accS_cur, float2 *__restrict__ accC_cur,
-    typename V2<T>::type *__restrict__ accS_nxt, float2 *__restrict__ accC_nxt) {
+__global__ __launch_bounds__(kPanelThreads) void rows_kernel(
+    int n, int BS, int nb, int row0, int row1, int from_own_batch, const T *__restrict__ x,
+    const T *__restrict__ y, typename V2<T>::type *__restrict__ accS, float2 *__restrict__ accC) {
+    __shared__ typename V2<T>::type cols[kTile];
+    rows_block<T, KAHAN>(n, BS, nb, row0 + blockIdx.x * kPanelThreads, row1, from_own_batch, x, y, accS, accC,
+                         cols);
+}
+
+// The panel of step (k, b) for rows [first, first + blockDim): columns =
+// batch b (just moved); rows of later batches add to their iteration-k sums,
+// rows of batches <= b (when do_next) to their iteration-(k+1) sums.
+template <typename T, bool KAHAN>
+__device__ __forceinline__ void panel_block(int n, int BS, int b, int do_next, int first, const T *__restrict__ x,
+                                            const T *__restrict__ y, typename V2<T>::type *__restrict__ accS_cur,
+                                            float2 *__restrict__ accC_cur,
+                                            typename V2<T>::type *__restrict__ accS_nxt,
+                                            float2 *__restrict__ accC_nxt, typename V2<T>::type *cols) {
     using T2 = typename V2<T>::type;
-    __shared__ T2 cols[kTile];
-    const int i = blockIdx.x * kPanelThreads + threadIdx.x;
+    const int i = first + threadIdx.x;
     const int bi = i < n ? i / BS : -1;
     const bool cur = i < n && bi > b;
     const bool nxt = do_next && i < n && bi >= 0 && bi <= b;
-    if (!__syncthreads_or(cur || nxt)) return;
     T xi = 0, yi = 0;
     if (i < n) {
         xi = x[i];
@@ -166,6 +183,20 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(
     }
 }
 
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(kPanelThreads) void panel_kernel(
+    int n, int BS, int b, int do_next, const T *__restrict__ x, const T *__restrict__ y,
+    typename V2<T>::type *__restrict__ accS_cur, float2 *__restrict__ accC_cur,
+    typename V2<T>::type *__restrict__ accS_nxt, float2 *__restrict__ accC_nxt) {
+    __shared__ typename V2<T>::type cols[kTile];
+    const int first = blockIdx.x * kPanelThreads;
+    const int i = first + threadIdx.x;
+    const int bi = i < n ? i / BS : -1;
+    const bool work = i < n && (bi > b || (do_next && bi <= b));
+    if (!__syncthreads_or(work)) return;
+    panel_block<T, KAHAN>(n, BS, b, do_next, first, x, y, accS_cur, accC_cur, accS_nxt, accC_nxt, cols);
+}
+
 template <typename T>
 struct FinArgs {
     int n, BS, b;
@@ -183,64 +214,62 @@ struct FinArgs {
     int update;                    // move the batch
 };
 
-// Net force of every row of batch b, one wave per row: attraction over the
-// CSR row with live coordinates (Sec. 2.2, a = 2: d * delta / K), plus the
-// completed repulsion sum scaled by -R K^2.  The last workgroup to finish
-// then moves the batch (c_i += Step f_i/|f_i|, skipped for |f_i| = 0) and adds
-// sum |f_i|^2 to the iteration energy in a fixed order.
+// Net force of row r of batch b by one wave: attraction over the CSR row with
+// live coordinates (Sec. 2.2, a = 2: d * delta / K), plus the completed
+// repulsion sum scaled by -R K^2 (literal mode: minus the neighbours'
+// repulsion).  Lane 0 writes fbuf[r] and clears the row's sums.
 template <typename T, bool KAHAN>
-__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs<T> a) {
+__device__ __forceinline__ void row_force_wave(const FinArgs<T> &a, int r) {
     using T2 = typename V2<T>::type;
-    __shared__ int s_last;
-    __shared__ double s_ws[kFinThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const int r = (blockIdx.x * kFinThreads + threadIdx.x) / kWave;
+    const int i = a.b * a.BS + r;
+    const T xi = a.x[i], yi = a.y[i];
+    T ax = 0, ay = 0, lx = 0, ly = 0;
+    const int e1 = a.rowptr[i + 1];
+    for (int e = a.rowptr[i] + lane; e < e1; e += kWave) {
+        const int j = a.colidx[e];
+        const T dx = a.x[j] - xi, dy = a.y[j] - yi;
+        const T d2 = dx * dx + dy * dy;
+        const T d = sqrt(d2);
+        ax += d * dx;
+        ay += d * dy;
+        if (a.literal) rep_term(xi, yi, T2{a.x[j], a.y[j]}, lx, ly);
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    lx = wave_sum(lx);
+    ly = wave_sum(ly);
+    if (lane == 0) {
+        T2 s = a.accS[i];
+        T rx = s.x, ry = s.y;
+        if constexpr (KAHAN) {
+            float2 c = a.accC[i];
+            rx = s.x - c.x;
+            ry = s.y - c.y;
+            a.accC[i] = float2{0.f, 0.f};
+        }
+        a.accS[i] = T2{0, 0};
+        if (a.literal) {
+            rx -= lx;
+            ry -= ly;
+        }
+        a.fbuf[r] = T2{ax * a.invK + a.negRK2 * rx, ay * a.invK + a.negRK2 * ry};
+    }
+}
+
+// Move batch b (c_i += Step f_i/|f_i|, skipped for |f_i| = 0) and add
+// sum |f_i|^2 to the iteration energy in a fixed order.  Called by the first
+// kFinThreads threads of a workgroup (all of them must call it; the first
+// kFinThreads / kWave waves do the work).
+template <typename T>
+__device__ __forceinline__ void move_batch(const FinArgs<T> &a, double *s_ws) {
+    using T2 = typename V2<T>::type;
     const int i0 = a.b * a.BS;
     const int R = min(a.BS, a.n - i0);
-    if (r < R) {
-        const int i = i0 + r;
-        const T xi = a.x[i], yi = a.y[i];
-        T ax = 0, ay = 0, lx = 0, ly = 0;
-        const int e1 = a.rowptr[i + 1];
-        for (int e = a.rowptr[i] + lane; e < e1; e += kWave) {
-            const int j = a.colidx[e];
-            const T dx = a.x[j] - xi, dy = a.y[j] - yi;
-            const T d2 = dx * dx + dy * dy;
-            const T d = sqrt(d2);
-            ax += d * dx;
-            ay += d * dy;
-            if (a.literal) rep_term(xi, yi, T2{a.x[j], a.y[j]}, lx, ly);
-        }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        lx = wave_sum(lx);
-        ly = wave_sum(ly);
-        if (lane == 0) {
-            T2 s = a.accS[i];
-            T rx = s.x, ry = s.y;
-            if constexpr (KAHAN) {
-                float2 c = a.accC[i];
-                rx = s.x - c.x;
-                ry = s.y - c.y;
-                a.accC[i] = float2{0.f, 0.f};
-            }
-            a.accS[i] = T2{0, 0};
-            if (a.literal) {
-                rx -= lx;
-                ry -= ly;
-            }
-            a.fbuf[r] = T2{ax * a.invK + a.negRK2 * rx, ay * a.invK + a.negRK2 * ry};
-        }
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    const bool worker = threadIdx.x < kFinThreads;
     double e = 0.0;
     unsigned long long bad = 0;
-    for (int q = threadIdx.x; q < R; q += kFinThreads) {
+    for (int q = threadIdx.x; worker && q < R; q += kFinThreads) {
         const T2 f = a.fbuf[q];
         const double f2 = (double)f.x * (double)f.x + (double)f.y * (double)f.y;
         if (a.fout) {
@@ -261,10 +290,113 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs<T> a) {
         }
     }
     if (bad) atomicAdd(a.nonfinite, bad);
-    e = block_sum_fixed(e, s_ws);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    e = wave_sum(e);
+    if (lane == 0 && worker) s_ws[w] = e;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        if (a.energy_k) *a.energy_k = (a.b == 0 ? 0.0 : *a.energy_k) + e;
-        *a.ticket = 0u;
+        double t = 0.0;
+        for (int q = 0; q < kFinThreads / kWave; ++q) t += s_ws[q];
+        if (a.energy_k) *a.energy_k = (a.b == 0 ? 0.0 : *a.energy_k) + t;
+    }
+    __syncthreads();
+}
+
+// One wave per row of batch b, then the last workgroup to finish moves the
+// batch.
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs<T> a) {
+    __shared__ int s_last;
+    __shared__ double s_ws[kFinThreads / kWave];
+    const int r = (blockIdx.x * kFinThreads + threadIdx.x) / kWave;
+    const int R = min(a.BS, a.n - a.b * a.BS);
+    if (r < R) row_force_wave<T, KAHAN>(a, r);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    move_batch<T>(a, s_ws);
+    if (threadIdx.x == 0) *a.ticket = 0u;
+}
+
+// ------------------------------------------------- one workgroup per graph
+// Many small graphs in one launch: each workgroup runs the whole layout of
+// one graph (prologue, then per step the net forces and move of the batch and
+// the panel of its new coordinates), with the same row arithmetic as the
+// multi-workgroup kernels, so a graph's result does not depend on the launch.
+struct ExactJob {
+    int n, BS, nb, iters, start, literal;
+    double step0, decay, invK, negRK2;
+    const int *rowptr, *colidx;
+    void *x, *y;
+    void *accS[2];
+    float2 *accC[2];
+    void *fbuf;
+    double *energy;
+    unsigned long long *nonfinite;
+};
+
+template <typename T, bool KAHAN, int NT>
+__global__ __launch_bounds__(NT) void exact_graph_kernel(const ExactJob *__restrict__ jobs) {
+    using T2 = typename V2<T>::type;
+    __shared__ T2 cols[kTile];
+    __shared__ double s_ws[kFinThreads / kWave];
+    const ExactJob J = jobs[blockIdx.x];
+    const int n = J.n, BS = J.BS, nb = J.nb;
+    T *x = (T *)J.x, *y = (T *)J.y;
+    // prologue and the other parity's sums cleared
+    const int p0 = J.start & 1;
+    for (int first = 0; first < n; first += NT)
+        rows_block<T, KAHAN>(n, BS, nb, first, n, 1, x, y, (T2 *)J.accS[p0], J.accC[p0], cols);
+    for (int i = threadIdx.x; i < n; i += NT) {
+        ((T2 *)J.accS[p0 ^ 1])[i] = T2{0, 0};
+        if constexpr (KAHAN) J.accC[p0 ^ 1][i] = float2{0.f, 0.f};
+    }
+    __syncthreads();
+    double step = J.step0;
+    for (int t = 0; t < J.start; ++t) step *= J.decay;
+    const int lane_w = threadIdx.x / kWave;
+    for (int t = 0; t < J.iters; ++t) {
+        const int k = J.start + t;
+        const int cur = k & 1, nxt = cur ^ 1;
+        const bool last = (t == J.iters - 1);
+        FinArgs<T> a;
+        a.n = n;
+        a.BS = BS;
+        a.rowptr = J.rowptr;
+        a.colidx = J.colidx;
+        a.x = x;
+        a.y = y;
+        a.accS = (T2 *)J.accS[cur];
+        a.accC = J.accC[cur];
+        a.fbuf = (T2 *)J.fbuf;
+        a.ticket = nullptr;
+        a.energy_k = J.energy + t;
+        a.fout = nullptr;
+        a.nonfinite = J.nonfinite;
+        a.step = (T)step;
+        a.invK = (T)J.invK;
+        a.negRK2 = (T)J.negRK2;
+        a.literal = J.literal;
+        a.update = 1;
+        for (int b = 0; b < nb; ++b) {
+            a.b = b;
+            const int R = min(BS, n - b * BS);
+            for (int r = lane_w; r < R; r += NT / kWave) row_force_wave<T, KAHAN>(a, r);
+            __syncthreads();
+            move_batch<T>(a, s_ws);
+            if ((b + 1) < nb || !last) {
+                for (int first = 0; first < n; first += NT) {
+                    panel_block<T, KAHAN>(n, BS, b, last ? 0 : 1, first, x, y, (T2 *)J.accS[cur], J.accC[cur],
+                                          (T2 *)J.accS[nxt], J.accC[nxt], cols);
+                }
+                __syncthreads();
+            }
+        }
+        step *= J.decay;
     }
 }
 
@@ -361,6 +493,56 @@ struct ExactOps {
 };
 
 }  // namespace
+
+// Launch one workgroup per graph for a group of exact-mode graphs that share
+// a precision.  threads: 256, 512 or 1024 (the result does not depend on it).
+int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override) {
+    if (G == 0) return BL_OK;
+    std::vector<ExactJob> jobs(G);
+    for (int q = 0; q < G; ++q) {
+        bl_graph *g = gs[q];
+        ExactJob &J = jobs[q];
+        J.n = g->n;
+        J.BS = g->p.batch_size;
+        J.nb = g->nb;
+        J.iters = iters_override >= 0 ? iters_override : g->p.iterations;
+        J.start = g->p.start_iter;
+        J.literal = g->p.repulse_adjacent ? 0 : 1;
+        J.step0 = g->p.step0;
+        J.decay = g->p.step_decay;
+        J.invK = 1.0 / g->p.K;
+        J.negRK2 = -g->p.R * g->p.K * g->p.K;
+        J.rowptr = g->rowptr;
+        J.colidx = g->colidx;
+        J.x = g->x;
+        J.y = g->y;
+        J.accS[0] = g->ex.accS[0];
+        J.accS[1] = g->ex.accS[1];
+        J.accC[0] = g->ex.accC[0];
+        J.accC[1] = g->ex.accC[1];
+        J.fbuf = g->ex.fbuf;
+        J.energy = g->energy;
+        J.nonfinite = &g->counters->nonfinite;
+    }
+    BL_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(ExactJob) * G, hipMemcpyHostToDevice, s));
+    BL_HIP(hipStreamSynchronize(s));   // the host copy of the table is freed below
+    const bl_graph *g0 = gs[0];
+    const ExactJob *dj = (const ExactJob *)d_jobs;
+#define BL_EXACT_LAUNCH(T, K, NT) hipLaunchKernelGGL((exact_graph_kernel<T, K, NT>), dim3(G), dim3(NT), 0, s, dj)
+    const bool f64 = g0->fp64, plain = g0->p.precision == BL_FP32_PLAIN;
+    if (threads == 256) {
+        if (f64) BL_EXACT_LAUNCH(double, false, 256); else if (plain) BL_EXACT_LAUNCH(float, false, 256); else BL_EXACT_LAUNCH(float, true, 256);
+    } else if (threads == 512) {
+        if (f64) BL_EXACT_LAUNCH(double, false, 512); else if (plain) BL_EXACT_LAUNCH(float, false, 512); else BL_EXACT_LAUNCH(float, true, 512);
+    } else {
+        if (f64) BL_EXACT_LAUNCH(double, false, 1024); else if (plain) BL_EXACT_LAUNCH(float, false, 1024); else BL_EXACT_LAUNCH(float, true, 1024);
+    }
+#undef BL_EXACT_LAUNCH
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
+size_t exact_job_size() { return sizeof(ExactJob); }
 
 int exact_alloc(bl_graph *g) {
     const size_t t2 = g->fp64 ? sizeof(double2) : sizeof(float2);

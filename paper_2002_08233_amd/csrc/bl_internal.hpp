@@ -137,11 +137,16 @@ struct bl_graph {
 namespace bl {
 
 int graph_alloc(bl_graph *g, void **ptr, size_t bytes);
+int fail_code(int code, const char *msg);
+int params_check(const bl_params *p);
+int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds);
 
 // exact mode (bl_exact.hip)
 int exact_alloc(bl_graph *g);
 int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch);
 int exact_forces(bl_graph *g, int batch);
+int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override);
+size_t exact_job_size();
 
 // Barnes-Hut mode (bl_bh.hip)
 int bh_alloc(bl_graph *g);
@@ -157,6 +162,7 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec);
 int bh_engine_set(BHEngine *e, const BHJob *jobs, int G);
 int bh_engine_setup(BHEngine *e);
 int bh_engine_iteration(BHEngine *e, bl_graph *prof);
+int bh_engine_run(BHEngine *e, int iters, bool use_graph);
 size_t bh_job_size();
 
 // shared kernels (bl_common.hip)
