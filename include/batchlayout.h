@@ -190,6 +190,34 @@ int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const double *const 
                     void *hip_stream, double *const *x_out, double *const *y_out,
                     bl_stats *stats);
 
+/* ------------------------------------------------------------- server
+ * Continuous batching of layout jobs: a host scheduler thread admits queued
+ * jobs while their bl_footprint_bytes fits the remaining HBM budget and a
+ * slot is free, keeps admitted jobs' state on the device, and interleaves
+ * their iterations on the device.  A job's result equals its alone result
+ * bitwise. */
+typedef struct bl_server bl_server;
+
+/* hbm_budget_bytes > 0; 1 <= max_slots <= 4096.  The server runs on the
+ * current device on its own stream (hip_stream is reserved, may be NULL). */
+int bl_server_create(size_t hbm_budget_bytes, int32_t max_slots, void *hip_stream,
+                     bl_server **out);
+/* Copies the graph and coordinates (host pointers only) and queues the job.
+ * BL_E_REJECTED if the job alone exceeds the whole budget. */
+int bl_server_submit(bl_server *s, const bl_csr *g, const double *x0, const double *y0,
+                     const bl_params *p, int64_t *job);
+/* *done = 1 when the job has finished (successfully or not). Non-blocking. */
+int bl_server_poll(bl_server *s, int64_t job, int32_t *done);
+/* Block until the job is done or timeout_s seconds passed (BL_E_TIMEOUT). */
+int bl_server_wait(bl_server *s, int64_t job, double timeout_s);
+/* Copy the result out; BL_E_NOTREADY while running.  stats may be NULL; its
+ * `seconds` is the job's latency from submit to completion. */
+int bl_server_fetch(bl_server *s, int64_t job, double *x, double *y, bl_stats *stats);
+/* Forget a finished job (or cancel a queued one). */
+int bl_server_release(bl_server *s, int64_t job);
+/* Stop the scheduler, cancel pending work, free everything.  NULL accepted. */
+int bl_server_destroy(bl_server *s);
+
 #ifdef __cplusplus
 }
 #endif

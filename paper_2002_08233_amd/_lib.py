@@ -25,6 +25,8 @@ EXPORTED = [
     "bl_params_init", "bl_last_error", "bl_version", "bl_footprint_bytes", "bl_layout", "bl_forces",
     "bl_graph_create", "bl_graph_set_coords", "bl_graph_get_coords", "bl_graph_run",
     "bl_graph_destroy", "bl_graph_profile", "bl_graph_profile_read", "bl_layout_batch",
+    "bl_server_create", "bl_server_submit", "bl_server_poll", "bl_server_wait", "bl_server_fetch",
+    "bl_server_release", "bl_server_destroy",
 ]
 
 

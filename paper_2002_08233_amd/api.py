@@ -235,3 +235,59 @@ class Graph:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Server:
+    """Continuous-batching layout server (host arrays in and out)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=256, stream=None):
+        self._lib = load()
+        self.h = C.c_void_p()
+        check(self._lib.bl_server_create(C.c_size_t(int(hbm_budget_bytes)), int(max_slots), None,
+                                         C.byref(self.h)))
+        self.n = {}
+
+    def submit(self, graph, x0, y0, p: Params) -> int:
+        keep = _Keep()
+        csr = _csr(graph, keep)
+        job = C.c_int64()
+        check(self._lib.bl_server_submit(self.h, C.byref(csr), keep.host(x0, np.float64),
+                                         keep.host(y0, np.float64), C.byref(p), C.byref(job)))
+        self.n[job.value] = csr.n
+        return job.value
+
+    def poll(self, job) -> bool:
+        d = C.c_int32()
+        check(self._lib.bl_server_poll(self.h, C.c_int64(job), C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, job, timeout=600.0):
+        check(self._lib.bl_server_wait(self.h, C.c_int64(job), C.c_double(timeout)))
+
+    def fetch(self, job):
+        n = self.n[job]
+        x = np.empty(n)
+        y = np.empty(n)
+        st = Stats()
+        check(self._lib.bl_server_fetch(self.h, C.c_int64(job), x.ctypes.data, y.ctypes.data, C.byref(st)))
+        return x, y, st.as_dict()
+
+    def release(self, job):
+        check(self._lib.bl_server_release(self.h, C.c_int64(job)))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self._lib.bl_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

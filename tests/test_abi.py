@@ -28,7 +28,7 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     from paper_2002_08233_amd import _lib
     names = _declared()
-    assert len(names) >= 14
+    assert len(names) >= 21
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(_lib.EXPORTED)
@@ -102,3 +102,20 @@ def test_footprint_grows_with_size(lib):
     assert api.footprint_bytes(0, 0, p) == 0
     e = api.footprint_bytes(100000, 800000, api.params(mode="exact"))
     assert 0 < e < b
+
+
+def test_server_argument_checks(lib):
+    import ctypes as C
+    from paper_2002_08233_amd import api
+    h = C.c_void_p()
+    assert lib.bl_server_create(C.c_size_t(0), 4, None, C.byref(h)) == api.BL_BH * 0 - 1
+    assert lib.bl_server_create(C.c_size_t(1 << 30), 0, None, C.byref(h)) == -1
+    assert lib.bl_server_create(C.c_size_t(1 << 30), 5000, None, C.byref(h)) == -1
+    assert lib.bl_server_destroy(None) == 0
+
+
+def test_batch_argument_checks(lib):
+    import ctypes as C
+    assert lib.bl_layout_batch(0, None, None, None, None, None, None, None, None) == 0
+    assert lib.bl_layout_batch(-1, None, None, None, None, None, None, None, None) == -1
+    assert lib.bl_layout_batch(2, None, None, None, None, None, None, None, None) == -1

@@ -1,0 +1,91 @@
+"""Continuous-batching server: a job's result equals its alone run bitwise
+whatever else is resident, admission respects the HBM budget, oversized jobs
+are rejected, and released jobs are dropped (needs an MI355X)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2002_08233_amd import api, inputs as I
+from paper_2002_08233_amd._lib import BL_E_INVAL, BL_E_REJECTED, BL_E_TIMEOUT
+
+pytestmark = pytest.mark.gpu
+
+
+def _job(kind, n, seed, mode, iters, bs=64, theta=1.0, precision="fp32_kahan"):
+    g = I.erdos_renyi(n, 8.0, seed) if kind == "er" else I.barabasi_albert(n, 4, seed)
+    x, y = I.uniform_coords(g.n, seed + 11)
+    p = api.params(batch_size=bs, iterations=iters, mode=mode, theta=theta, precision=precision)
+    return g, I.to_f32_representable(x), I.to_f32_representable(y), p
+
+
+MIX = [
+    ("er", 400, 1, "exact", 13),
+    ("ba", 3000, 2, "bh", 21, 128, 1.2),
+    ("er", 900, 3, "exact", 5, 128, 1.0, "fp64"),
+    ("ba", 5000, 4, "bh", 9, 256, 0.8),
+    ("er", 2500, 5, "bh", 30, 100, 1.0),
+    ("ba", 700, 6, "exact", 17, 64, 1.0, "fp32_plain"),
+    ("er", 6000, 7, "bh", 3, 256, 1.2),
+]
+
+
+def _check_against_alone(srv, jobs):
+    ids = [srv.submit(*j) for j in jobs]
+    for jid, (g, x0, y0, p) in zip(ids, jobs):
+        srv.wait(jid, 300.0)
+        xs, ys, st = srv.fetch(jid)
+        xa, ya, ea, _ = api.layout(g, x0, y0, p)
+        assert np.array_equal(xs, xa) and np.array_equal(ys, ya), (g.n, p.mode, p.iterations)
+        assert st["iters_run"] == p.iterations
+        assert st["energy_last"] == ea[-1]
+        assert st["seconds"] > 0
+        srv.release(jid)
+
+
+def test_mix_matches_alone_runs_bitwise():
+    jobs = [_job(*m) for m in MIX]
+    with api.Server(8 << 30, max_slots=64) as srv:
+        _check_against_alone(srv, jobs)
+
+
+def test_small_budget_admits_in_turns():
+    jobs = [_job(*m) for m in MIX]
+    biggest = max(api.footprint_bytes(j[0].n, j[0].nnz, j[3]) for j in jobs)
+    with api.Server(biggest + 1, max_slots=2) as srv:
+        _check_against_alone(srv, jobs)
+
+
+def test_oversized_job_is_rejected():
+    g, x0, y0, p = _job("er", 2000, 9, "bh", 4)
+    need = api.footprint_bytes(g.n, g.nnz, p)
+    with api.Server(need - 1, max_slots=4) as srv:
+        with pytest.raises(api.BLError) as e:
+            srv.submit(g, x0, y0, p)
+        assert e.value.code == BL_E_REJECTED
+
+
+def test_release_cancels_and_timeout_reports():
+    g, x0, y0, p = _job("ba", 20000, 10, "bh", 200000, 256, 1.2)   # minutes unless cancelled
+    small = _job("er", 300, 12, "exact", 4)
+    with api.Server(8 << 30, max_slots=8) as srv:
+        long_id = srv.submit(g, x0, y0, p)
+        with pytest.raises(api.BLError) as e:
+            srv.wait(long_id, 0.01)
+        assert e.value.code == BL_E_TIMEOUT
+        sid = srv.submit(*small)
+        srv.wait(sid, 120.0)
+        xs, ys, _ = srv.fetch(sid)
+        xa, ya, _, _ = api.layout(*small)
+        assert np.array_equal(xs, xa) and np.array_equal(ys, ya)
+        srv.release(long_id)
+        t0 = time.time()
+        srv.wait(long_id, 120.0)
+        assert time.time() - t0 < 60.0
+        assert srv.poll(long_id)
+        with pytest.raises(api.BLError) as e:
+            srv.fetch(long_id)
+        assert e.value.code == BL_E_INVAL
+        srv.release(long_id)
+        with pytest.raises(api.BLError):
+            srv.poll(long_id)
