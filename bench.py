@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "force-updates/s (exact & BH) vs plain on 1 GPU; served p50/p99 layout latency"
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 FLOP (FMA) x 2.4 GHz, non-packed FP32
+FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X vector FP64
 # Algorithmic work per unit (see the design notes):
 BYTES_PER_VISIT = 24.0           # float4 (centroid, side^2, count) + int2 (skip, vertex) per node visit
 BYTES_PER_WALK_VERTEX = 32.0     # order id 4 + own x,y 8 + far-field sum 16 + late count 4
@@ -136,8 +137,8 @@ def main():
 
     if not args.no_profile:
         kern = {}
-        for name in ("tree_build", "far_kernel", "chain_kernel", "rows_kernel", "panel_kernel",
-                     "finalize_kernel"):
+        for name in ("tree_build", "far_kernel", "chain_kernel", "rows_kernel", "step_kernel",
+                     "finalize_kernel", "exact_graph_kernel"):
             ms, cnt = dev.profile_read(name)
             if cnt:
                 kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1e3 * ms / cnt}
@@ -164,13 +165,22 @@ def main():
         else:
             nb = (g.n + w["batch_size"] - 1) // w["batch_size"]
             pairs = float(g.n) * g.n * steps
-            panel = kern["panel_kernel"]
-            flop_per_launch = FLOP_PER_PAIR * float(g.n) * w["batch_size"]
-            panel["achieved_TFLOPs"] = flop_per_launch / (panel["avg_us"] * 1e-6) / 1e12
-            out["roofline"] = {"bound": "alu", "achieved": panel["achieved_TFLOPs"],
-                               "peak": FP32_VALU_PEAK_TFLOPS if args.precision != "fp64" else 78.6,
-                               "unit": "TFLOP/s", "frac": panel["achieved_TFLOPs"] / FP32_VALU_PEAK_TFLOPS,
-                               "traffic": None, "kernel": "panel_kernel"}
+            if "step_kernel" in kern:
+                dom_name = "step_kernel"
+                dom = kern[dom_name]
+                flop_per_launch = FLOP_PER_PAIR * float(g.n) * w["batch_size"]
+            else:   # small graph: the whole run is one launch of the one-workgroup kernel
+                dom_name = "exact_graph_kernel"
+                dom = kern[dom_name]
+                flop_per_launch = FLOP_PER_PAIR * pairs / dom["launches"]
+            dom["achieved_TFLOPs"] = flop_per_launch / (dom["avg_us"] * 1e-6) / 1e12
+            dom["flop_per_launch"] = flop_per_launch
+            peak = FP32_VALU_PEAK_TFLOPS if args.precision != "fp64" else FP64_VALU_PEAK_TFLOPS
+            out["roofline"] = {"bound": "alu", "achieved": dom["achieved_TFLOPs"], "peak": peak,
+                               "unit": "TFLOP/s", "frac": dom["achieved_TFLOPs"] / peak,
+                               "traffic": None, "kernel": dom_name,
+                               "frac_of_packed_fp32_peak": (dom["achieved_TFLOPs"] / 157.3
+                                                            if args.precision != "fp64" else None)}
             out["exact"] = {"pairs_per_s": pairs / wall, "batches_per_iteration": nb}
         out["kernels"] = kern
     out["energy_last"] = float(energy[-1]) if len(energy) else None

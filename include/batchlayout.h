@@ -61,6 +61,9 @@ extern "C" {
                                      range, no self-loops/duplicates, symmetry) */
 #define BL_BH_SNAPSHOT_LEAVES 4u  /* BH leaves use the per-iteration snapshot
                                      instead of live coordinates                */
+#define BL_EXACT_MULTI_WG     8u  /* exact mode: always use the multi-workgroup
+                                     step kernels (small graphs otherwise run in
+                                     one workgroup); the result is the same bits */
 
 typedef struct {
     int32_t n;               /* vertices, >= 1                                   */
@@ -87,7 +90,7 @@ typedef struct {
     double K;                /* > 0, optimal spring length                       */
     double R;                /* > 0, relative strength of repulsion              */
     double theta;            /* >= 0, BH acceptance: side < theta * distance     */
-    uint32_t flags;          /* BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES              */
+    uint32_t flags;          /* BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG */
     int32_t reserved[7];     /* must be zero                                     */
 } bl_params;
 

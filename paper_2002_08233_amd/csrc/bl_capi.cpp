@@ -68,7 +68,7 @@ int check_params(const bl_params *p) {
     if (!(p->K > 0) || !std::isfinite(p->K)) return fail(BL_E_INVAL, "K must be > 0");
     if (!(p->R > 0) || !std::isfinite(p->R)) return fail(BL_E_INVAL, "R must be > 0");
     if (!(p->theta >= 0) || !std::isfinite(p->theta)) return fail(BL_E_INVAL, "theta must be >= 0");
-    if (p->flags & ~(BL_DEVICE_PTRS | BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES))
+    if (p->flags & ~(BL_DEVICE_PTRS | BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG))
         return fail(BL_E_INVAL, "unknown flags 0x%x", p->flags);
     for (int q = 0; q < 7; ++q)
         if (p->reserved[q]) return fail(BL_E_INVAL, "reserved fields must be zero");
@@ -190,7 +190,7 @@ size_t bl_footprint_bytes(int32_t n, int64_t nnz, const bl_params *p) {
     b += 2 * 8 * (size_t)p->batch_size + 4096;      // forces out, counters
     b += 8 * (size_t)std::max(p->iterations, 64);   // energy per iteration
     if (p->mode == BL_EXACT)
-        b += 2 * (2 * T * N + 8 * N) + 2 * T * (size_t)p->batch_size + 256;
+        b += exact_footprint(n, nnz, p->batch_size, p->precision == BL_FP64);
     else
         b += bh_footprint(n, nnz, p->batch_size);
     return b;
@@ -241,6 +241,13 @@ int bl_graph_create(const bl_csr *csr, const bl_params *p, void *hip_stream, bl_
         set_error("graph upload failed: %s", hipGetErrorString(e));
         free_graph(g);
         return BL_E_HIP;
+    }
+    if (p->mode == BL_EXACT) {
+        rc = exact_prepare(g);
+        if (rc != BL_OK) {
+            free_graph(g);
+            return rc;
+        }
     }
     *out = g;
     return BL_OK;
@@ -345,8 +352,8 @@ int bl_graph_run(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t st
     return run_impl(g, iterations, start_iter, stop_batch, energy_out, fx, fy, st);
 }
 
-static const char *kProfNames[PK_COUNT] = {"rows_kernel", "panel_kernel", "finalize_kernel",
-                                           "tree_build", "far_kernel", "chain_kernel"};
+static const char *kProfNames[PK_COUNT] = {"rows_kernel", "step_kernel", "finalize_kernel", "tree_build",
+                                           "far_kernel", "chain_kernel", "exact_graph_kernel"};
 
 int bl_graph_profile(bl_graph *g, int32_t enable) {
     if (!g) return fail(BL_E_INVAL, "graph is NULL");

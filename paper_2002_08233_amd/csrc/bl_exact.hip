@@ -1,30 +1,47 @@
-// Exact-mode force step (Alg. 2 semantics) for gfx950.
+// Exact-mode force step (Sec. 2.2 and 3.3, Alg. 2) for gfx950.
 //
 // Dataflow.  At step (k, b) the rows of batch b need the *new* coordinates of
 // batches b' < b and the *old* ones (from iteration k-1) of batches b' >= b.
-// Both are known as soon as the batch that owns them has moved, so after the
-// update of batch b every row can consume the new coordinates of batch b at
-// once: rows of later batches add them to their iteration-k sum, rows of
-// batches <= b to their iteration-(k+1) sum (they will see batch b as "old").
-// One "panel" launch per step therefore covers all n rows x BS columns with
-// full-chip parallelism, and a row's sum is complete exactly when its batch
-// comes up.  Per-row sums are built column batch by column batch in a fixed
-// order (each batch: an FP32 partial, then one compensated add), so the
-// result does not depend on the launch shape and a resumed run reproduces a
-// continuous one bitwise.
+// Both are final as soon as the batch that owns them has moved, so once batch
+// c has moved, every row can take in its contribution from batch c at once:
+// rows of later batches add it to their iteration-k sum, rows of batches
+// <= c to their iteration-(k+1) sum (they will see batch c as "old").  The
+// contribution of a column batch to a row holds the repulsion from all of
+// its columns and the attraction from the row's neighbours inside it (their
+// positions are the same ones), so a row's net force is complete exactly
+// when its batch comes up.
 //
-// Kernels: rows_kernel (per-row sums over whole column batches: the prologue
-// of a run and the one-shot force call), panel_kernel (the per-step panel),
-// finalize_kernel (attraction over CSR edges with live coordinates, one wave
-// per row, then the batch update by the last workgroup to finish).
+// One launch per step therefore does the panel of the batch that just moved
+// over all n rows (full-chip parallelism) and, in the workgroups that hold
+// the rows of the next batch, finishes those rows and moves them: their last
+// contribution is the one this very launch adds.  The critical path of a
+// step is one launch.
+//
+// Arithmetic (the same in every kernel here, so a graph's result does not
+// depend on the launch shape, and a resumed run equals a continuous one
+// bitwise).  Per row and column batch: the repulsion of the batch's columns
+// in four interleaved partial sums (column q to sum q mod 4, ascending), the
+// attraction (and, in literal mode, the neighbour repulsion) of the row's
+// CSR entries inside the batch in entry order, combined into one partial,
+// then one compensated (Kahan) add into the row's sum.  Energy: per batch,
+// each 256-row chunk (aligned to absolute row ids) is summed by wave
+// butterflies and then its four wave sums in order; the chunk sums are added
+// in row order; iteration energies add the batch sums in batch order.
+//
+// Kernels: rows_kernel (whole-column-batch sums: the prologue of a run and
+// the one-shot force call), step_kernel (panel + fused finish of the next
+// batch), finalize_kernel (finish only: first batch of a run, probes, and
+// single-batch graphs), exact_graph_kernel (one workgroup runs a whole small
+// layout; many graphs per launch).
+#include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "bl_device.hpp"
 #include "bl_internal.hpp"
 
 // Only explicit fma() calls fuse: the same row arithmetic is compiled into
-// several kernels (multi-workgroup steps and the one-workgroup-per-graph
-// batch kernel), and must round identically in all of them.
+// several kernels and must round identically in all of them.
 #pragma clang fp contract(off)
 
 namespace bl {
@@ -41,9 +58,14 @@ struct V2<double> {
     using type = double2;
 };
 
-constexpr int kPanelThreads = 256;
-constexpr int kTile = 1024;        // columns staged in LDS per pass
-constexpr int kFinThreads = 256;   // 4 waves, one row per wave
+constexpr int kRows = 256;     // rows per workgroup of the multi-workgroup kernels (= energy chunk)
+constexpr int kTile = 1024;    // columns staged in LDS per pass
+constexpr int kSimds = 256 * 4;   // SIMDs of the chip (256 compute units x 4)
+constexpr int kPre = 4;        // CSR entries of a row prefetched per column batch
+// Graphs with n * BS up to this many pairs per step run alone in the
+// one-workgroup kernel: one compute unit finishes such a step faster than
+// a chain of full-chip launches.
+constexpr long long kOneWGPairs = 1LL << 18;
 
 // Repulsion kernel term without its constant factor -R K^2:
 //   (c_j - c_i) / |c_j - c_i|^2  (Sec. 2.2 with r = -1).
@@ -65,17 +87,54 @@ __device__ __forceinline__ void rep_term(double xi, double yi, double2 pj, doubl
     py = fma(dy, inv, py);
 }
 
-template <typename T>
-__device__ __forceinline__ void tile_sum(T xi, T yi, const typename V2<T>::type *cols, int cnt,
-                                         T &px, T &py) {
-    int q = 0;
-    for (; q + 4 <= cnt; q += 4) {
-        rep_term(xi, yi, cols[q], px, py);
-        rep_term(xi, yi, cols[q + 1], px, py);
-        rep_term(xi, yi, cols[q + 2], px, py);
-        rep_term(xi, yi, cols[q + 3], px, py);
+// One CSR entry's terms, each rounded on its own so that they can be formed
+// in any lane and then added in entry order: the attraction d * (c_j - c_i)
+// without its factor 1/K (Sec. 2.2 with a = 2: magnitude d^2 / K along the
+// unit vector), and the repulsion kernel (c_j - c_i) / d^2 that literal mode
+// takes back out for a neighbour.
+struct EntryTerms {
+    template <typename T, typename T2>
+    __device__ __forceinline__ static void att(T xi, T yi, T2 pj, T &tx, T &ty) {
+        const T dx = pj.x - xi, dy = pj.y - yi;
+        const T d = sqrt(fma(dx, dx, dy * dy));
+        tx = d * dx;
+        ty = d * dy;
     }
-    for (; q < cnt; ++q) rep_term(xi, yi, cols[q], px, py);
+    __device__ __forceinline__ static void rep(float xi, float yi, float2 pj, float &ux, float &uy) {
+        const float dx = pj.x - xi, dy = pj.y - yi;
+        const float inv = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1e-30f)));
+        ux = dx * inv;
+        uy = dy * inv;
+    }
+    __device__ __forceinline__ static void rep(double xi, double yi, double2 pj, double &ux, double &uy) {
+        const double dx = pj.x - xi, dy = pj.y - yi;
+        const double inv = 1.0 / fma(dx, dx, fma(dy, dy, 1e-300));
+        ux = dx * inv;
+        uy = dy * inv;
+    }
+};
+
+// Four interleaved repulsion partials of one row.
+template <typename T>
+struct Rep4 {
+    T x0, y0, x1, y1, x2, y2, x3, y3;
+    __device__ void zero() { x0 = y0 = x1 = y1 = x2 = y2 = x3 = y3 = 0; }
+};
+
+// Columns [lo, hi) of the staged tile (lo a multiple of 4; the tile starts at
+// a multiple of 4 columns from the batch start, so column q goes to sum q&3).
+template <typename T>
+__device__ __forceinline__ void rep_range(T xi, T yi, const typename V2<T>::type *cols, int lo, int hi, Rep4<T> &P) {
+    int q = lo;
+    for (; q + 4 <= hi; q += 4) {
+        rep_term(xi, yi, cols[q], P.x0, P.y0);
+        rep_term(xi, yi, cols[q + 1], P.x1, P.y1);
+        rep_term(xi, yi, cols[q + 2], P.x2, P.y2);
+        rep_term(xi, yi, cols[q + 3], P.x3, P.y3);
+    }
+    if (q < hi) rep_term(xi, yi, cols[q], P.x0, P.y0);
+    if (q + 1 < hi) rep_term(xi, yi, cols[q + 1], P.x1, P.y1);
+    if (q + 2 < hi) rep_term(xi, yi, cols[q + 2], P.x2, P.y2);
 }
 
 // Add one column-batch partial into a row sum.
@@ -90,251 +149,668 @@ __device__ __forceinline__ void acc_add(typename V2<T>::type &s, float2 &c, T px
     }
 }
 
-// Sum of one column batch [c0, c1) for every active row of the block, staged
-// through LDS in kTile chunks.  All threads of the block must call it.
+// Everything a kernel needs of one graph.
 template <typename T>
-__device__ __forceinline__ void batch_partial(const T *__restrict__ x, const T *__restrict__ y,
-                                              int c0, int c1, bool active, T xi, T yi,
-                                              typename V2<T>::type *cols, T &px, T &py) {
-    px = 0;
-    py = 0;
+struct GView {
+    using T2 = typename V2<T>::type;
+    int n, BS, nb, literal;
+    T invK, negRK2;
+    const int *rowptr, *colidx;
+    const int2 *segs;
+    const int *segoff;
+    int *cursor;
+    T *x, *y;
+    T2 *accS[2];
+    float2 *accC[2];
+    // by parity, without dynamic indexing (keeps a local view out of scratch)
+    __device__ __forceinline__ T2 *S(int par) const { return par ? accS[1] : accS[0]; }
+    __device__ __forceinline__ float2 *C(int par) const { return par ? accC[1] : accC[0]; }
+};
+
+// Contribution of column batch c = [c0, c1) to row i (all threads of the
+// workgroup call it; `active` rows compute).  `s` is the row's candidate
+// segment (its next unconsumed CSR run), `send` the row's segment end.  On
+// return (qx, qy) is the combined partial and `used` tells whether segment s
+// belonged to batch c.  The row's CSR segment is prefetched halfway through
+// the first column tile so that its latency hides behind the repulsion.
+template <typename T>
+__device__ __forceinline__ void batch_contrib(const GView<T> &G, int c, bool active, int i, T xi, T yi, int s,
+                                              int send, typename V2<T>::type *cols, T &qx, T &qy, bool &used) {
+    using T2 = typename V2<T>::type;
+    const int c0 = c * G.BS, c1 = min(c0 + G.BS, G.n);
+    const bool cand = active && s < send;
+    int2 sg = make_int2(-1, 0);
+    int eend = 0;
+    if (cand) {
+        sg = G.segs[s];
+        eend = (s + 1 < send) ? G.segs[s + 1].y : G.rowptr[i + 1];
+    }
+    Rep4<T> P;
+    P.zero();
+    int pre[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) pre[u] = 0;
+    int cnt = 0;
+    used = false;
     for (int t0 = c0; t0 < c1; t0 += kTile) {
-        const int cnt = min(kTile, c1 - t0);
+        const int m = min(kTile, c1 - t0);
         __syncthreads();
-        for (int q = threadIdx.x; q < cnt; q += blockDim.x)
-            cols[q] = typename V2<T>::type{x[t0 + q], y[t0 + q]};
+        for (int q = threadIdx.x; q < m; q += blockDim.x) cols[q] = T2{G.x[t0 + q], G.y[t0 + q]};
         __syncthreads();
-        if (active) tile_sum<T>(xi, yi, cols, cnt, px, py);
+        if (active) {
+            const int half = (t0 == c0) ? ((m / 2) & ~3) : 0;
+            rep_range<T>(xi, yi, cols, 0, half, P);
+            if (t0 == c0) {
+                used = cand && sg.x == c;
+                cnt = used ? eend - sg.y : 0;
+#pragma unroll
+                for (int u = 0; u < kPre; ++u)
+                    if (u < cnt) pre[u] = G.colidx[sg.y + u];
+            }
+            rep_range<T>(xi, yi, cols, half, m, P);
+        }
     }
+    T ax = 0, ay = 0, lx = 0, ly = 0;
+    if (active && cnt > 0) {
+        const bool in_lds = (c1 - c0) <= kTile;   // the whole batch is staged
+        auto one = [&](int j) {
+            const T2 pj = in_lds ? cols[j - c0] : T2{G.x[j], G.y[j]};
+            T tx, ty;
+            EntryTerms::att(xi, yi, pj, tx, ty);
+            ax += tx;
+            ay += ty;
+            if (G.literal) {
+                EntryTerms::rep(xi, yi, pj, tx, ty);
+                lx += tx;
+                ly += ty;
+            }
+        };
+#pragma unroll
+        for (int u = 0; u < kPre; ++u)
+            if (u < cnt) one(pre[u]);
+        for (int u = kPre; u < cnt; u += 4) {
+            int jj[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) jj[v] = (u + v < cnt) ? G.colidx[sg.y + u + v] : 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (u + v < cnt) one(jj[v]);
+        }
+    }
+    const T rx = (P.x0 + P.x1) + (P.x2 + P.x3);
+    const T ry = (P.y0 + P.y1) + (P.y2 + P.y3);
+    qx = G.invK * ax + G.negRK2 * (rx - lx);
+    qy = G.invK * ay + G.negRK2 * (ry - ly);
 }
 
-// Row sums over whole column batches for the rows [first, first + blockDim)
-// that are < row1.  from_own_batch = 1: batches [batch(i), nb) (the run
-// prologue: everything a row sees as "old" in its first iteration); 0: all
-// batches (one-shot forces).  Overwrites the sums.
+// First segment of row i whose column batch is >= b (binary search).
+__device__ __forceinline__ int first_seg_from(const int2 *segs, int s0, int s1, int b) {
+    while (s0 < s1) {
+        const int mid = (s0 + s1) >> 1;
+        if (segs[mid].x < b) s0 = mid + 1;
+        else s1 = mid;
+    }
+    return s0;
+}
+
+// Whole-column-batch sums for the rows [first, first + blockDim) below row1.
+// from_own = 1: batches [batch(i), nb) (the run prologue: what a row sees as
+// "old" in its first iteration); 0: all batches (one-shot forces).  Writes
+// the sums of parity p, clears parity p^1 when asked, and points each row's
+// cursor at its first segment (the next column batch to arrive is batch 0).
 template <typename T, bool KAHAN>
-__device__ __forceinline__ void rows_block(int n, int BS, int nb, int first, int row1, int from_own_batch,
-                                           const T *__restrict__ x, const T *__restrict__ y,
-                                           typename V2<T>::type *__restrict__ accS,
-                                           float2 *__restrict__ accC, typename V2<T>::type *cols) {
+__device__ __forceinline__ void rows_block(const GView<T> &G, int first, int row1, int from_own, int p, int clear_other,
+                                           typename V2<T>::type *cols) {
     using T2 = typename V2<T>::type;
     const int i = first + threadIdx.x;
-    const bool active = i < row1;
-    const int bi = active ? i / BS : nb;
+    const bool in = i < row1;
+    const int bi = in ? i / G.BS : G.nb;
     T xi = 0, yi = 0;
-    if (active) {
-        xi = x[i];
-        yi = y[i];
+    int s = 0, send = 0, srow = 0;
+    if (in) {
+        xi = G.x[i];
+        yi = G.y[i];
+        srow = G.segoff[i];
+        send = G.segoff[i + 1];
+        s = from_own ? first_seg_from(G.segs, srow, send, bi) : srow;
     }
-    T2 s{0, 0};
-    float2 c{0.f, 0.f};
-    const int bstart = from_own_batch ? first / BS : 0;
-    for (int bb = bstart; bb < nb; ++bb) {
-        const bool use = active && (!from_own_batch || bb >= bi);
-        T px, py;
-        batch_partial<T>(x, y, bb * BS, min(bb * BS + BS, n), use, xi, yi, cols, px, py);
-        if (use) acc_add<T, KAHAN>(s, c, px, py);
+    T2 acc{0, 0};
+    float2 cc{0.f, 0.f};
+    const int bstart = from_own ? min(first / G.BS, G.nb) : 0;
+    for (int bb = bstart; bb < G.nb; ++bb) {
+        const bool use = in && (!from_own || bb >= bi);
+        T qx, qy;
+        bool used;
+        batch_contrib<T>(G, bb, use, i, xi, yi, s, send, cols, qx, qy, used);
+        if (use) {
+            acc_add<T, KAHAN>(acc, cc, qx, qy);
+            if (used) ++s;
+        }
     }
-    if (active) {
-        accS[i] = s;
-        if constexpr (KAHAN) accC[i] = c;
+    if (in) {
+        G.S(p)[i] = acc;
+        if constexpr (KAHAN) G.C(p)[i] = cc;
+        if (clear_other) {
+            G.S(p ^ 1)[i] = T2{0, 0};
+            if constexpr (KAHAN) G.C(p ^ 1)[i] = float2{0.f, 0.f};
+        }
+        G.cursor[i] = srow;
     }
 }
 
-template <typename T, bool KAHAN>
-__global__ __launch_bounds__(kPanelThreads) void rows_kernel(
-    int n, int BS, int nb, int row0, int row1, int from_own_batch, const T *__restrict__ x,
-    const T *__restrict__ y, typename V2<T>::type *__restrict__ accS, float2 *__restrict__ accC) {
+// The same contribution with L lanes per row (L = 1, 2 or 4 consecutive
+// lanes; lane h holds the partial sums m = h, h + L, ... and the lead lane
+// h = 0 gets the combined partial).  The combine (P0 + P1) + (P2 + P3) and
+// the lead lane's entry-order sum of the CSR segment make the bits those of
+// batch_contrib.  The column loop runs on a wave-uniform counter.  The
+// segment's first 16 entries are prefetched by the row's lanes halfway
+// through the first tile; longer segments (hub rows) are formed by all lanes
+// of the wave, one row at a time, and added by the lead lane in order.
+template <typename T, int L>
+__device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool active, bool lead, int i, T xi, T yi,
+                                               int s, int send, typename V2<T>::type *cols, T &qx, T &qy,
+                                               bool &used) {
+    using T2 = typename V2<T>::type;
+    constexpr int A = 4 / L;               // partial sums per lane
+    constexpr int NP = 16 / L;             // prefetched entries per lane
+    const int lane = threadIdx.x & (kWave - 1);
+    const int h = threadIdx.x & (L - 1);
+    const int c0 = c * G.BS, c1 = min(c0 + G.BS, G.n);
+    const bool cand = active && s < send;
+    int2 sg = make_int2(-1, 0);
+    int eend = 0;
+    if (cand) {
+        sg = G.segs[s];
+        eend = (s + 1 < send) ? G.segs[s + 1].y : G.rowptr[i + 1];
+    }
+    T px[A], py[A];
+#pragma unroll
+    for (int t = 0; t < A; ++t) px[t] = py[t] = 0;
+    int pre[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) pre[k] = 0;
+    int big[4] = {0, 0, 0, 0};     // entries 16.. of the wave's first long segment
+    int cnt = 0, st0 = 0, ct0 = 0, src0 = -1;
+    used = false;
+    // columns [4 k0, 4 k1) of the staged tile; column 4k + h + L t -> sum t
+    auto group_range = [&](int k0, int k1) {
+        int k = k0;
+        for (; k + 2 <= k1; k += 2) {
+#pragma unroll
+            for (int t = 0; t < A; ++t) rep_term(xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
+#pragma unroll
+            for (int t = 0; t < A; ++t) rep_term(xi, yi, cols[4 * k + 4 + h + L * t], px[t], py[t]);
+        }
+        if (k < k1) {
+#pragma unroll
+            for (int t = 0; t < A; ++t) rep_term(xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
+        }
+    };
+    for (int t0 = c0; t0 < c1; t0 += kTile) {
+        const int m = min(kTile, c1 - t0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += blockDim.x) cols[q] = T2{G.x[t0 + q], G.y[t0 + q]};
+        __syncthreads();
+        const int groups = m >> 2;
+        const int hg = (t0 == c0) ? (groups >> 1) : 0;
+        if (active) group_range(0, hg);
+        if (t0 == c0) {
+            // CSR prefetch, in flight during the rest of the tile
+            used = cand && sg.x == c;
+            cnt = used ? eend - sg.y : 0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                if (h + L * k < cnt) pre[k] = G.colidx[sg.y + h + L * k];
+            const unsigned long long longm = __ballot(lead && cnt > 16);
+            if (longm) {
+                src0 = __ffsll((long long)longm) - 1;
+                st0 = __shfl(sg.y, src0, kWave);
+                ct0 = __shfl(cnt, src0, kWave);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int e = 16 + lane + kWave * k;
+                    if (e < ct0) big[k] = G.colidx[st0 + e];
+                }
+            }
+        }
+        if (active) {
+            group_range(hg, groups);
+            // the last m % 4 columns
+#pragma unroll
+            for (int t = 0; t < A; ++t) {
+                const int q = 4 * groups + h + L * t;
+                if (q < m) rep_term(xi, yi, cols[q], px[t], py[t]);
+            }
+        }
+    }
+    // (P0 + P1) + (P2 + P3)
+    T rx, ry;
+    if constexpr (L == 1) {
+        rx = (px[0] + px[1]) + (px[2] + px[3]);
+        ry = (py[0] + py[1]) + (py[2] + py[3]);
+    } else if constexpr (L == 2) {
+        const T a0 = px[0] + __shfl_xor(px[0], 1, kWave), b0 = py[0] + __shfl_xor(py[0], 1, kWave);
+        const T a1 = px[1] + __shfl_xor(px[1], 1, kWave), b1 = py[1] + __shfl_xor(py[1], 1, kWave);
+        rx = a0 + a1;
+        ry = b0 + b1;
+    } else {
+        rx = px[0] + __shfl_xor(px[0], 1, kWave);
+        ry = py[0] + __shfl_xor(py[0], 1, kWave);
+        rx += __shfl_xor(rx, 2, kWave);
+        ry += __shfl_xor(ry, 2, kWave);
+    }
+    T ax = 0, ay = 0, lx = 0, ly = 0;
+    const bool in_lds = (c1 - c0) <= kTile;
+    auto pos = [&](int j) { return in_lds ? cols[j - c0] : T2{G.x[j], G.y[j]}; };
+    // entries 0..15, held by the row's lanes (entry u in lane u % L, slot u / L)
+    const int base_lane = lane & ~(L - 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        if (!__ballot(lead && u < cnt)) break;
+        const int j = (L == 1) ? pre[u] : __shfl(pre[u / L], base_lane + (u % L), kWave);
+        if (lead && u < cnt) {
+            T tx, ty;
+            const T2 pj = pos(j);
+            EntryTerms::att(xi, yi, pj, tx, ty);
+            ax += tx;
+            ay += ty;
+            if (G.literal) {
+                EntryTerms::rep(xi, yi, pj, tx, ty);
+                lx += tx;
+                ly += ty;
+            }
+        }
+    }
+    // entries 16.. of long segments (hub rows), one row at a time: every lane
+    // of the wave forms one entry's terms, the row's lead lane adds them in
+    // entry order
+    unsigned long long longm = __ballot(lead && cnt > 16);
+    bool first_long = true;
+    while (longm) {
+        const int src = __ffsll((long long)longm) - 1;
+        longm &= longm - 1;
+        const int st = __shfl(sg.y, src, kWave), ct = __shfl(cnt, src, kWave);
+        const T rxi = __shfl(xi, src, kWave), ryi = __shfl(yi, src, kWave);
+        const bool have = first_long && src == src0;
+        first_long = false;
+        for (int b = 16; b < ct; b += 4 * kWave) {
+            int jj[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int e = b + lane + kWave * k;
+                jj[k] = have && b == 16 ? big[k] : (e < ct ? G.colidx[st + e] : c0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int e0 = b + kWave * k;
+                if (e0 >= ct) break;
+                const int e = e0 + lane;
+                const T2 pj = pos(e < ct ? jj[k] : c0);
+                T tx, ty, ux = 0, uy = 0;
+                EntryTerms::att(rxi, ryi, pj, tx, ty);
+                if (G.literal) EntryTerms::rep(rxi, ryi, pj, ux, uy);
+                const int mcount = min(kWave, ct - e0);
+                for (int u = 0; u < mcount; ++u) {
+                    const T vx = __shfl(tx, u, kWave), vy = __shfl(ty, u, kWave);
+                    if (lane == src) {
+                        ax += vx;
+                        ay += vy;
+                    }
+                    if (G.literal) {
+                        const T wx = __shfl(ux, u, kWave), wy = __shfl(uy, u, kWave);
+                        if (lane == src) {
+                            lx += wx;
+                            ly += wy;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    qx = G.invK * ax + G.negRK2 * (rx - lx);
+    qy = G.invK * ay + G.negRK2 * (ry - ly);
+}
+
+// rows_block with L lanes per row (workgroups of kRows * L; rows
+// [first, first + kRows)).
+template <typename T, bool KAHAN, int L>
+__device__ __forceinline__ void rows_blockL(const GView<T> &G, int first, int row1, int from_own, int p, int clear_other,
+                                            typename V2<T>::type *cols) {
+    using T2 = typename V2<T>::type;
+    const bool lead = (threadIdx.x & (L - 1)) == 0;
+    const int i = first + threadIdx.x / L;
+    const bool in = i < row1;
+    const int bi = in ? i / G.BS : G.nb;
+    T xi = 0, yi = 0;
+    int s = 0, send = 0, srow = 0;
+    if (in) {
+        xi = G.x[i];
+        yi = G.y[i];
+        srow = G.segoff[i];
+        send = G.segoff[i + 1];
+        s = from_own ? first_seg_from(G.segs, srow, send, bi) : srow;
+    }
+    T2 acc{0, 0};
+    float2 cc{0.f, 0.f};
+    const int bstart = from_own ? min(first / G.BS, G.nb) : 0;
+    for (int bb = bstart; bb < G.nb; ++bb) {
+        const bool use = in && (!from_own || bb >= bi);
+        T qx, qy;
+        bool used;
+        batch_contribL<T, L>(G, bb, use, lead, i, xi, yi, s, send, cols, qx, qy, used);
+        if (use) {
+            if (lead) acc_add<T, KAHAN>(acc, cc, qx, qy);
+            if (used) ++s;
+        }
+    }
+    if (in && lead) {
+        G.S(p)[i] = acc;
+        if constexpr (KAHAN) G.C(p)[i] = cc;
+        if (clear_other) {
+            G.S(p ^ 1)[i] = T2{0, 0};
+            if constexpr (KAHAN) G.C(p ^ 1)[i] = float2{0.f, 0.f};
+        }
+        G.cursor[i] = srow;
+    }
+}
+
+template <typename T, bool KAHAN, int L>
+__global__ __launch_bounds__(kRows * L) void rows_kernel(GView<T> G, int row0, int row1, int from_own, int p,
+                                                         int clear_other) {
     __shared__ typename V2<T>::type cols[kTile];
-    rows_block<T, KAHAN>(n, BS, nb, row0 + blockIdx.x * kPanelThreads, row1, from_own_batch, x, y, accS, accC,
-                         cols);
+    rows_blockL<T, KAHAN, L>(G, row0 + blockIdx.x * kRows, row1, from_own, p, clear_other, cols);
 }
 
-// The panel of step (k, b) for rows [first, first + blockDim): columns =
-// batch b (just moved); rows of later batches add to their iteration-k sums,
-// rows of batches <= b (when do_next) to their iteration-(k+1) sums.
+// The panel of column batch c for the rows [first, first + blockDim): rows of
+// later batches add it to their parity-pc sums, rows of batches <= c (when
+// do_next) to their parity-(pc^1) sums.  A row of batch `fin` keeps its
+// completed sum in (fx, fy) (and its sums are cleared) instead of storing it.
 template <typename T, bool KAHAN>
-__device__ __forceinline__ void panel_block(int n, int BS, int b, int do_next, int first, const T *__restrict__ x,
-                                            const T *__restrict__ y, typename V2<T>::type *__restrict__ accS_cur,
-                                            float2 *__restrict__ accC_cur,
-                                            typename V2<T>::type *__restrict__ accS_nxt,
-                                            float2 *__restrict__ accC_nxt, typename V2<T>::type *cols) {
+__device__ __forceinline__ void panel_rows(const GView<T> &G, int first, int c, int pc, int do_next, int fin,
+                                           typename V2<T>::type *cols, T &xi, T &yi, T &fx, T &fy) {
     using T2 = typename V2<T>::type;
     const int i = first + threadIdx.x;
-    const int bi = i < n ? i / BS : -1;
-    const bool cur = i < n && bi > b;
-    const bool nxt = do_next && i < n && bi >= 0 && bi <= b;
-    T xi = 0, yi = 0;
-    if (i < n) {
-        xi = x[i];
-        yi = y[i];
+    const int bi = i < G.n ? i / G.BS : -1;
+    const bool cur = i < G.n && bi > c;
+    const bool nxt = do_next && i < G.n && bi >= 0 && bi <= c;
+    const bool act = cur || nxt;
+    int s = 0, send = 0;
+    if (act) {
+        xi = G.x[i];
+        yi = G.y[i];
+        s = G.cursor[i];
+        send = G.segoff[i + 1];
     }
-    T px, py;
-    batch_partial<T>(x, y, b * BS, min(b * BS + BS, n), cur || nxt, xi, yi, cols, px, py);
-    if (cur || nxt) {
-        T2 *S = cur ? accS_cur : accS_nxt;
-        float2 *Cc = cur ? accC_cur : accC_nxt;
-        T2 s = S[i];
-        float2 c{0.f, 0.f};
-        if constexpr (KAHAN) c = Cc[i];
-        acc_add<T, KAHAN>(s, c, px, py);
-        S[i] = s;
-        if constexpr (KAHAN) Cc[i] = c;
+    T qx, qy;
+    bool used;
+    batch_contrib<T>(G, c, act, i, xi, yi, s, send, cols, qx, qy, used);
+    if (act) {
+        const int par = cur ? pc : (pc ^ 1);
+        T2 acc = G.S(par)[i];
+        float2 cc{0.f, 0.f};
+        if constexpr (KAHAN) cc = G.C(par)[i];
+        acc_add<T, KAHAN>(acc, cc, qx, qy);
+        if (bi == fin) {
+            fx = acc.x;
+            fy = acc.y;
+            if constexpr (KAHAN) {
+                fx = acc.x - cc.x;
+                fy = acc.y - cc.y;
+            }
+            G.S(par)[i] = T2{0, 0};
+            if constexpr (KAHAN) G.C(par)[i] = float2{0.f, 0.f};
+        } else {
+            G.S(par)[i] = acc;
+            if constexpr (KAHAN) G.C(par)[i] = cc;
+        }
+        G.cursor[i] = (c == G.nb - 1) ? G.segoff[i] : s + (used ? 1 : 0);
     }
 }
 
+// panel_rows with L lanes per row (workgroups of kRows * L, rows [first,
+// first + kRows)); the completed sum of a row of batch `fin` lands in the
+// lead lane's (fx, fy).
+template <typename T, bool KAHAN, int L>
+__device__ __forceinline__ void panel_rowsL(const GView<T> &G, int first, int c, int pc, int do_next, int fin,
+                                            typename V2<T>::type *cols, T &xi, T &yi, T &fx, T &fy) {
+    using T2 = typename V2<T>::type;
+    const bool lead = (threadIdx.x & (L - 1)) == 0;
+    const int i = first + threadIdx.x / L;
+    const int bi = i < G.n ? i / G.BS : -1;
+    const bool cur = i < G.n && bi > c;
+    const bool nxt = do_next && i < G.n && bi >= 0 && bi <= c;
+    const bool act = cur || nxt;
+    const int par = cur ? pc : (pc ^ 1);
+    int s = 0, send = 0;
+    T2 acc{0, 0};
+    float2 cc{0.f, 0.f};
+    if (act) {
+        xi = G.x[i];
+        yi = G.y[i];
+        s = G.cursor[i];
+        send = G.segoff[i + 1];
+        if (lead) {
+            acc = G.S(par)[i];
+            if constexpr (KAHAN) cc = G.C(par)[i];
+        }
+    }
+    T qx, qy;
+    bool used;
+    batch_contribL<T, L>(G, c, act, lead, i, xi, yi, s, send, cols, qx, qy, used);
+    if (act && lead) {
+        acc_add<T, KAHAN>(acc, cc, qx, qy);
+        if (bi == fin) {
+            fx = acc.x;
+            fy = acc.y;
+            if constexpr (KAHAN) {
+                fx = acc.x - cc.x;
+                fy = acc.y - cc.y;
+            }
+            G.S(par)[i] = T2{0, 0};
+            if constexpr (KAHAN) G.C(par)[i] = float2{0.f, 0.f};
+        } else {
+            G.S(par)[i] = acc;
+            if constexpr (KAHAN) G.C(par)[i] = cc;
+        }
+        G.cursor[i] = (c == G.nb - 1) ? G.segoff[i] : s + (used ? 1 : 0);
+    }
+}
+
+// Completed force of row i of the batch being finished, from memory.
 template <typename T, bool KAHAN>
-__global__ __launch_bounds__(kPanelThreads) void panel_kernel(
-    int n, int BS, int b, int do_next, const T *__restrict__ x, const T *__restrict__ y,
-    typename V2<T>::type *__restrict__ accS_cur, float2 *__restrict__ accC_cur,
-    typename V2<T>::type *__restrict__ accS_nxt, float2 *__restrict__ accC_nxt) {
-    __shared__ typename V2<T>::type cols[kTile];
-    const int first = blockIdx.x * kPanelThreads;
-    const int i = first + threadIdx.x;
-    const int bi = i < n ? i / BS : -1;
-    const bool work = i < n && (bi > b || (do_next && bi <= b));
-    if (!__syncthreads_or(work)) return;
-    panel_block<T, KAHAN>(n, BS, b, do_next, first, x, y, accS_cur, accC_cur, accS_nxt, accC_nxt, cols);
+__device__ __forceinline__ void load_force(const GView<T> &G, int i, int pf, T &fx, T &fy) {
+    using T2 = typename V2<T>::type;
+    const T2 acc = G.S(pf)[i];
+    fx = acc.x;
+    fy = acc.y;
+    if constexpr (KAHAN) {
+        const float2 cc = G.C(pf)[i];
+        fx = acc.x - cc.x;
+        fy = acc.y - cc.y;
+        G.C(pf)[i] = float2{0.f, 0.f};
+    }
+    G.S(pf)[i] = T2{0, 0};
+}
+
+// Move row i (c_i += Step f_i/|f_i|, none for |f_i| = 0; Alg. 2 update) and
+// return |f_i|^2 in FP64 (0 for a non-finite force, which is counted).
+template <typename T>
+__device__ __forceinline__ double finish_row(const GView<T> &G, int i, int r, T xi, T yi, T fx, T fy, T step,
+                                             int update, double *fout, unsigned long long &bad) {
+    const double f2 = (double)fx * (double)fx + (double)fy * (double)fy;
+    if (fout) {
+        fout[2 * r] = (double)fx;
+        fout[2 * r + 1] = (double)fy;
+    }
+    if (!isfinite(f2)) {
+        ++bad;
+        return 0.0;
+    }
+    if (update && f2 > 0.0) {
+        const T nrm = sqrt(fx * fx + fy * fy);
+        const T sc = step / nrm;
+        G.x[i] = xi + sc * fx;
+        G.y[i] = yi + sc * fy;
+    }
+    return f2;
+}
+
+// Sum over one 256-row chunk held by 4 consecutive waves: wave butterflies,
+// then the four wave sums in order.  `ws` is LDS of one double per wave;
+// `w0` the chunk's first wave.  Valid in the chunk's first thread; all
+// threads of the workgroup call it.
+__device__ __forceinline__ double chunk_sum(double e, double *ws, int w0) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    e = wave_sum(e);
+    if (lane == 0) ws[w] = e;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == w0 * kWave) r = ((ws[w0] + ws[w0 + 1]) + ws[w0 + 2]) + ws[w0 + 3];
+    __syncthreads();
+    return r;
 }
 
 template <typename T>
 struct FinArgs {
-    int n, BS, b;
-    const int *rowptr, *colidx;
-    T *x, *y;
-    typename V2<T>::type *accS;
-    float2 *accC;
-    typename V2<T>::type *fbuf;    // [BS] net forces of the batch
-    unsigned *ticket;              // last-block counter, left at 0
-    double *energy_k;              // energy of iteration k (NULL: do not record)
-    double *fout;                  // [2*BS] FP64 forces out (NULL: none)
-    unsigned long long *nonfinite;
-    T step, invK, negRK2;
-    int literal;                   // subtract neighbour repulsion (Alg. 1/2 exclusion)
-    int update;                    // move the batch
+    int fin;              // batch to finish (-1: none)
+    int pf;               // its iteration parity
+    int update;           // move it (0: forces only)
+    T step;
+    double *energy_k;     // energy of its iteration (NULL: not recorded)
+    double *fout;         // [2 * BS] FP64 forces out (NULL: none)
+    double *epart;        // chunk partials of the batch
+    unsigned *ticket;
+    unsigned long long *nonfinite_count;
 };
 
-// Net force of row r of batch b by one wave: attraction over the CSR row with
-// live coordinates (Sec. 2.2, a = 2: d * delta / K), plus the completed
-// repulsion sum scaled by -R K^2 (literal mode: minus the neighbours'
-// repulsion).  Lane 0 writes fbuf[r] and clears the row's sums.
+// Finishing of batch a.fin by the workgroup holding rows [first, first +
+// 256): each row's force (already in (fx, fy) when `have`, else from
+// memory), the move, and the batch energy, combined over the batch's chunks
+// by the last workgroup to finish.
 template <typename T, bool KAHAN>
-__device__ __forceinline__ void row_force_wave(const FinArgs<T> &a, int r) {
-    using T2 = typename V2<T>::type;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int i = a.b * a.BS + r;
-    const T xi = a.x[i], yi = a.y[i];
-    T ax = 0, ay = 0, lx = 0, ly = 0;
-    const int e1 = a.rowptr[i + 1];
-    for (int e = a.rowptr[i] + lane; e < e1; e += kWave) {
-        const int j = a.colidx[e];
-        const T dx = a.x[j] - xi, dy = a.y[j] - yi;
-        const T d2 = dx * dx + dy * dy;
-        const T d = sqrt(d2);
-        ax += d * dx;
-        ay += d * dy;
-        if (a.literal) rep_term(xi, yi, T2{a.x[j], a.y[j]}, lx, ly);
-    }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    lx = wave_sum(lx);
-    ly = wave_sum(ly);
-    if (lane == 0) {
-        T2 s = a.accS[i];
-        T rx = s.x, ry = s.y;
-        if constexpr (KAHAN) {
-            float2 c = a.accC[i];
-            rx = s.x - c.x;
-            ry = s.y - c.y;
-            a.accC[i] = float2{0.f, 0.f};
-        }
-        a.accS[i] = T2{0, 0};
-        if (a.literal) {
-            rx -= lx;
-            ry -= ly;
-        }
-        a.fbuf[r] = T2{ax * a.invK + a.negRK2 * rx, ay * a.invK + a.negRK2 * ry};
-    }
-}
-
-// Move batch b (c_i += Step f_i/|f_i|, skipped for |f_i| = 0) and add
-// sum |f_i|^2 to the iteration energy in a fixed order.  Called by the first
-// kFinThreads threads of a workgroup (all of them must call it; the first
-// kFinThreads / kWave waves do the work).
-template <typename T>
-__device__ __forceinline__ void move_batch(const FinArgs<T> &a, double *s_ws) {
-    using T2 = typename V2<T>::type;
-    const int i0 = a.b * a.BS;
-    const int R = min(a.BS, a.n - i0);
-    const bool worker = threadIdx.x < kFinThreads;
+__device__ __forceinline__ void finish_chunk(const GView<T> &G, const FinArgs<T> &a, int first, bool have, T xi, T yi,
+                                             T fx, T fy, double *ws) {
+    __shared__ int s_last;
+    const int i = first + threadIdx.x;
+    const int b0 = a.fin * G.BS, b1 = min(b0 + G.BS, G.n);
+    const bool mine = i >= b0 && i < b1;
     double e = 0.0;
     unsigned long long bad = 0;
-    for (int q = threadIdx.x; worker && q < R; q += kFinThreads) {
-        const T2 f = a.fbuf[q];
-        const double f2 = (double)f.x * (double)f.x + (double)f.y * (double)f.y;
-        if (a.fout) {
-            a.fout[2 * q] = (double)f.x;
-            a.fout[2 * q + 1] = (double)f.y;
+    if (mine) {
+        if (!have) {
+            xi = G.x[i];
+            yi = G.y[i];
+            load_force<T, KAHAN>(G, i, a.pf, fx, fy);
         }
-        if (!isfinite(f2)) {
-            ++bad;
-            continue;
-        }
-        e += f2;
-        if (a.update && f2 > 0.0) {
-            const int i = i0 + q;
-            const T nrm = sqrt(f.x * f.x + f.y * f.y);
-            const T sc = a.step / nrm;
-            a.x[i] = a.x[i] + sc * f.x;
-            a.y[i] = a.y[i] + sc * f.y;
-        }
+        e = finish_row<T>(G, i, i - b0, xi, yi, fx, fy, a.step, a.update, a.fout, bad);
     }
-    if (bad) atomicAdd(a.nonfinite, bad);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    e = wave_sum(e);
-    if (lane == 0 && worker) s_ws[w] = e;
-    __syncthreads();
+    if (bad) atomicAdd(a.nonfinite_count, bad);
+    const double cs = chunk_sum(e, ws, 0);
+    if (!a.energy_k) return;
+    const int ch0 = b0 / kRows, ch1 = (b1 - 1) / kRows, nch = ch1 - ch0 + 1;
+    if (nch == 1) {
+        if (threadIdx.x == 0) *a.energy_k = (a.fin == 0) ? cs : *a.energy_k + cs;
+        return;
+    }
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int q = 0; q < kFinThreads / kWave; ++q) t += s_ws[q];
-        if (a.energy_k) *a.energy_k = (a.b == 0 ? 0.0 : *a.energy_k) + t;
+        a.epart[first / kRows - ch0] = cs;
+        __threadfence();
+        s_last = (atomicAdd(a.ticket, 1u) == (unsigned)(nch - 1));
     }
     __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        const volatile double *ep = a.epart;
+        double bs = ep[0];
+        for (int q = 1; q < nch; ++q) bs += ep[q];
+        *a.energy_k = (a.fin == 0) ? bs : *a.energy_k + bs;
+        *a.ticket = 0u;
+    }
 }
 
-// One wave per row of batch b, then the last workgroup to finish moves the
-// batch.
-template <typename T, bool KAHAN>
-__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs<T> a) {
+// finish_chunk for the lead lanes of a kRows * L workgroup: the rows' |f|^2
+// go through LDS to the first 256 threads, which sum them with the same tree
+// as finish_chunk.
+template <typename T, bool KAHAN, int L>
+__device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T> &a, int first, T xi, T yi, T fx,
+                                              T fy, double *e2, double *ws) {
     __shared__ int s_last;
-    __shared__ double s_ws[kFinThreads / kWave];
-    const int r = (blockIdx.x * kFinThreads + threadIdx.x) / kWave;
-    const int R = min(a.BS, a.n - a.b * a.BS);
-    if (r < R) row_force_wave<T, KAHAN>(a, r);
-    __threadfence();
+    const bool lead = (threadIdx.x & (L - 1)) == 0;
+    const int r = threadIdx.x / L;
+    const int i = first + r;
+    const int b0 = a.fin * G.BS, b1 = min(b0 + G.BS, G.n);
+    const bool mine = lead && i >= b0 && i < b1;
+    unsigned long long bad = 0;
+    if (lead) e2[r] = mine ? finish_row<T>(G, i, i - b0, xi, yi, fx, fy, a.step, a.update, a.fout, bad) : 0.0;
+    if (bad) atomicAdd(a.nonfinite_count, bad);
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
+    const double cs = chunk_sum(threadIdx.x < kRows ? e2[threadIdx.x] : 0.0, ws, 0);
+    if (!a.energy_k) return;
+    const int ch0 = b0 / kRows, ch1 = (b1 - 1) / kRows, nch = ch1 - ch0 + 1;
+    if (nch == 1) {
+        if (threadIdx.x == 0) *a.energy_k = (a.fin == 0) ? cs : *a.energy_k + cs;
+        return;
+    }
+    if (threadIdx.x == 0) {
+        a.epart[first / kRows - ch0] = cs;
+        __threadfence();
+        s_last = (atomicAdd(a.ticket, 1u) == (unsigned)(nch - 1));
+    }
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    move_batch<T>(a, s_ws);
-    if (threadIdx.x == 0) *a.ticket = 0u;
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        const volatile double *ep = a.epart;
+        double bs = ep[0];
+        for (int q = 1; q < nch; ++q) bs += ep[q];
+        *a.energy_k = (a.fin == 0) ? bs : *a.energy_k + bs;
+        *a.ticket = 0u;
+    }
+}
+
+// Panel of column batch c (moved in an iteration of parity pc) over all rows,
+// fused with the finish of batch fa.fin (whose last contribution is this
+// panel's).  Needs nb > 1: the finished rows are read by no other workgroup.
+template <typename T, bool KAHAN, int L>
+__global__ __launch_bounds__(kRows * L) void step_kernel(GView<T> G, int c, int pc, int do_next, FinArgs<T> fa) {
+    __shared__ typename V2<T>::type cols[kTile];
+    __shared__ double ws[kRows * L / kWave];
+    __shared__ double e2[kRows];
+    const int first = blockIdx.x * kRows;
+    const int i = first + threadIdx.x / L;
+    const int bi = i < G.n ? i / G.BS : -1;
+    const bool work = i < G.n && (bi > c || (do_next && bi <= c));
+    const bool fin_row = fa.fin >= 0 && bi == fa.fin;
+    if (!__syncthreads_or(work || fin_row)) return;
+    T xi = 0, yi = 0, fx = 0, fy = 0;
+    panel_rowsL<T, KAHAN, L>(G, first, c, pc, do_next, fa.fin, cols, xi, yi, fx, fy);
+    if (fa.fin >= 0 && __syncthreads_or(fin_row)) finish_chunkL<T, KAHAN, L>(G, fa, first, xi, yi, fx, fy, e2, ws);
+}
+
+// Finish of batch fa.fin only (its sums are complete in memory).
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(kRows) void finalize_kernel(GView<T> G, FinArgs<T> fa) {
+    __shared__ double ws[kRows / kWave];
+    const int first = (fa.fin * G.BS) / kRows * kRows + blockIdx.x * kRows;
+    finish_chunk<T, KAHAN>(G, fa, first, false, 0, 0, 0, 0, ws);
 }
 
 // ------------------------------------------------- one workgroup per graph
 // Many small graphs in one launch: each workgroup runs the whole layout of
-// one graph (prologue, then per step the net forces and move of the batch and
-// the panel of its new coordinates), with the same row arithmetic as the
-// multi-workgroup kernels, so a graph's result does not depend on the launch.
+// one graph, the steps in order with workgroup barriers between them, in
+// passes of NT rows aligned to absolute row ids (so waves and 256-row chunks
+// cover the same rows as in the multi-workgroup kernels, and the result is
+// the same bitwise).
 struct ExactJob {
     int n, BS, nb, iters, start, literal;
     double step0, decay, invK, negRK2;
     const int *rowptr, *colidx;
+    const int2 *segs;
+    const int *segoff;
+    int *cursor;
     void *x, *y;
     void *accS[2];
     float2 *accC[2];
-    void *fbuf;
     double *energy;
     unsigned long long *nonfinite;
 };
@@ -343,143 +819,229 @@ template <typename T, bool KAHAN, int NT>
 __global__ __launch_bounds__(NT) void exact_graph_kernel(const ExactJob *__restrict__ jobs) {
     using T2 = typename V2<T>::type;
     __shared__ T2 cols[kTile];
-    __shared__ double s_ws[kFinThreads / kWave];
-    const ExactJob J = jobs[blockIdx.x];
-    const int n = J.n, BS = J.BS, nb = J.nb;
-    T *x = (T *)J.x, *y = (T *)J.y;
-    // prologue and the other parity's sums cleared
-    const int p0 = J.start & 1;
-    for (int first = 0; first < n; first += NT)
-        rows_block<T, KAHAN>(n, BS, nb, first, n, 1, x, y, (T2 *)J.accS[p0], J.accC[p0], cols);
-    for (int i = threadIdx.x; i < n; i += NT) {
-        ((T2 *)J.accS[p0 ^ 1])[i] = T2{0, 0};
-        if constexpr (KAHAN) J.accC[p0 ^ 1][i] = float2{0.f, 0.f};
-    }
+    __shared__ double ws[NT / kWave];
+    __shared__ double s_batch;
+    const ExactJob &J0 = jobs[blockIdx.x];
+    GView<T> G;
+    G.n = J0.n;
+    G.BS = J0.BS;
+    G.nb = J0.nb;
+    G.literal = J0.literal;
+    G.invK = (T)J0.invK;
+    G.negRK2 = (T)J0.negRK2;
+    G.rowptr = J0.rowptr;
+    G.colidx = J0.colidx;
+    G.segs = J0.segs;
+    G.segoff = J0.segoff;
+    G.cursor = J0.cursor;
+    G.x = (T *)J0.x;
+    G.y = (T *)J0.y;
+    G.accS[0] = (T2 *)J0.accS[0];
+    G.accS[1] = (T2 *)J0.accS[1];
+    G.accC[0] = J0.accC[0];
+    G.accC[1] = J0.accC[1];
+    const int iters = J0.iters, start = J0.start;
+    double *energy = J0.energy;
+    unsigned long long *nonfinite = J0.nonfinite;
+    if (iters <= 0) return;
+    const int n = G.n, nb = G.nb, BS = G.BS;
+    const int p0 = start & 1;
+    for (int first = 0; first < n; first += NT) rows_block<T, KAHAN>(G, first, n, 1, p0, 1, cols);
     __syncthreads();
-    double step = J.step0;
-    for (int t = 0; t < J.start; ++t) step *= J.decay;
-    const int lane_w = threadIdx.x / kWave;
-    for (int t = 0; t < J.iters; ++t) {
-        const int k = J.start + t;
-        const int cur = k & 1, nxt = cur ^ 1;
-        const bool last = (t == J.iters - 1);
-        FinArgs<T> a;
-        a.n = n;
-        a.BS = BS;
-        a.rowptr = J.rowptr;
-        a.colidx = J.colidx;
-        a.x = x;
-        a.y = y;
-        a.accS = (T2 *)J.accS[cur];
-        a.accC = J.accC[cur];
-        a.fbuf = (T2 *)J.fbuf;
-        a.ticket = nullptr;
-        a.energy_k = J.energy + t;
-        a.fout = nullptr;
-        a.nonfinite = J.nonfinite;
-        a.step = (T)step;
-        a.invK = (T)J.invK;
-        a.negRK2 = (T)J.negRK2;
-        a.literal = J.literal;
-        a.update = 1;
-        for (int b = 0; b < nb; ++b) {
-            a.b = b;
-            const int R = min(BS, n - b * BS);
-            for (int r = lane_w; r < R; r += NT / kWave) row_force_wave<T, KAHAN>(a, r);
-            __syncthreads();
-            move_batch<T>(a, s_ws);
-            if ((b + 1) < nb || !last) {
-                for (int first = 0; first < n; first += NT) {
-                    panel_block<T, KAHAN>(n, BS, b, last ? 0 : 1, first, x, y, (T2 *)J.accS[cur], J.accC[cur],
-                                          (T2 *)J.accS[nxt], J.accC[nxt], cols);
-                }
-                __syncthreads();
+    double step = J0.step0;
+    for (int t = 0; t < start; ++t) step *= J0.decay;
+    const int lastk = start + iters - 1;
+    const int w = threadIdx.x / kWave;
+    unsigned long long bad = 0;
+    // finish batch b of iteration k from memory
+    auto finish = [&](int k, int b, double stepk) {
+        const int b0 = b * BS, b1 = min(b0 + BS, n);
+        const int f0 = b0 / NT * NT;
+        for (int first = f0; first < b1; first += NT) {
+            const int i = first + threadIdx.x;
+            double e = 0.0;
+            if (i >= b0 && i < b1) {
+                T fx, fy;
+                const T xi = G.x[i], yi = G.y[i];
+                load_force<T, KAHAN>(G, i, k & 1, fx, fy);
+                e = finish_row<T>(G, i, i - b0, xi, yi, fx, fy, (T)stepk, 1, nullptr, bad);
             }
+            e = wave_sum(e);
+            if ((threadIdx.x & (kWave - 1)) == 0) ws[w] = e;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double bs = (first == f0) ? 0.0 : s_batch;
+                for (int ch = 0; ch < NT / kRows; ++ch) {
+                    const int cf = first + ch * kRows;
+                    if (cf + kRows <= b0 || cf >= b1) continue;
+                    const double cs = ((ws[4 * ch] + ws[4 * ch + 1]) + ws[4 * ch + 2]) + ws[4 * ch + 3];
+                    bs = (cf <= b0) ? cs : bs + cs;
+                }
+                s_batch = bs;
+            }
+            __syncthreads();
         }
-        step *= J.decay;
+        if (threadIdx.x == 0) {
+            double *ek = energy + (k - start);
+            *ek = (b == 0) ? s_batch : *ek + s_batch;
+        }
+    };
+    finish(start, 0, step);
+    __syncthreads();
+    for (int k = start; k <= lastk; ++k) {
+        const double stepk = step;
+        for (int b = 0; b < nb; ++b) {
+            // the panel of batch b (moved in iteration k), then the next batch
+            const bool has_next = (b + 1 < nb) || (k < lastk);
+            if (!has_next) break;
+            const int do_next = k < lastk ? 1 : 0;
+            for (int first = 0; first < n; first += NT) {
+                T xi = 0, yi = 0, fx = 0, fy = 0;
+                panel_rows<T, KAHAN>(G, first, b, k & 1, do_next, -1, cols, xi, yi, fx, fy);
+            }
+            __syncthreads();
+            if (b + 1 < nb) finish(k, b + 1, stepk);
+            else finish(k + 1, 0, stepk * J0.decay);
+            __syncthreads();
+        }
+        step *= J0.decay;
     }
+    if (bad) atomicAdd(nonfinite, bad);
 }
 
 template <typename T, bool KAHAN>
 struct ExactOps {
     using T2 = typename V2<T>::type;
 
-    static int rows(bl_graph *g, int row0, int row1, int from_own, int parity) {
+    static GView<T> view(bl_graph *g) {
+        GView<T> G;
+        G.n = g->n;
+        G.BS = g->p.batch_size;
+        G.nb = g->nb;
+        G.literal = g->p.repulse_adjacent ? 0 : 1;
+        G.invK = (T)(1.0 / g->p.K);
+        G.negRK2 = (T)(-g->p.R * g->p.K * g->p.K);
+        G.rowptr = g->rowptr;
+        G.colidx = g->colidx;
+        G.segs = g->ex.segs;
+        G.segoff = g->ex.segoff;
+        G.cursor = g->ex.cursor;
+        G.x = (T *)g->x;
+        G.y = (T *)g->y;
+        G.accS[0] = (T2 *)g->ex.accS[0];
+        G.accS[1] = (T2 *)g->ex.accS[1];
+        G.accC[0] = g->ex.accC[0];
+        G.accC[1] = g->ex.accC[1];
+        return G;
+    }
+
+    // Lanes per row of the multi-workgroup kernels: enough waves per SIMD to
+    // hide latency, as few lanes as that allows (each lane's loop overhead is
+    // shared by more pairs).  The result does not depend on it.
+    static int lanes(bl_graph *g, int rows) {
+        if (const char *e = getenv("BL_EXACT_LANES")) {
+            const int v = atoi(e);
+            if (v == 1 || v == 2 || v == 4) return v;
+        }
+        const long long waves1 = ((long long)rows + kWave - 1) / kWave;   // waves at one lane per row
+        if (waves1 >= 8LL * kSimds) return 1;
+        if (waves1 >= kSimds) return 2;
+        return 4;
+    }
+
+    static int rows(bl_graph *g, int row0, int row1, int from_own, int parity, int clear_other) {
         if (row1 <= row0) return BL_OK;
-        const int blocks = (row1 - row0 + kPanelThreads - 1) / kPanelThreads;
+        const int blocks = (row1 - row0 + kRows - 1) / kRows;
         int slot;
         BL_TRY(prof_begin(g, PK_ROWS, &slot));
-        hipLaunchKernelGGL((rows_kernel<T, KAHAN>), dim3(blocks), dim3(kPanelThreads), 0, g->stream,
-                           g->n, g->p.batch_size, g->nb, row0, row1, from_own, (const T *)g->x,
-                           (const T *)g->y, (T2 *)g->ex.accS[parity], g->ex.accC[parity]);
+        const int L = lanes(g, row1 - row0);
+        if (L == 1)
+            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 1>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), row0,
+                               row1, from_own, parity, clear_other);
+        else if (L == 2)
+            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 2>), dim3(blocks), dim3(kRows * 2), 0, g->stream, view(g),
+                               row0, row1, from_own, parity, clear_other);
+        else
+            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 4>), dim3(blocks), dim3(kRows * 4), 0, g->stream, view(g),
+                               row0, row1, from_own, parity, clear_other);
         BL_HIP(hipGetLastError());
         return prof_end(g, slot);
     }
 
-    static int panel(bl_graph *g, int b, int k, int do_next) {
-        const int cur = k & 1, nxt = cur ^ 1;
-        const int blocks = (g->n + kPanelThreads - 1) / kPanelThreads;
-        int slot;
-        BL_TRY(prof_begin(g, PK_PANEL, &slot));
-        hipLaunchKernelGGL((panel_kernel<T, KAHAN>), dim3(blocks), dim3(kPanelThreads), 0, g->stream,
-                           g->n, g->p.batch_size, b, do_next, (const T *)g->x, (const T *)g->y,
-                           (T2 *)g->ex.accS[cur], g->ex.accC[cur], (T2 *)g->ex.accS[nxt],
-                           g->ex.accC[nxt]);
-        BL_HIP(hipGetLastError());
-        return prof_end(g, slot);
-    }
-
-    static int finalize(bl_graph *g, int b, int k, double *energy_k, double *fout, int update,
-                        int parity) {
+    static FinArgs<T> fin_args(bl_graph *g, int b, int k, double *energy_k, double *fout, int update) {
         FinArgs<T> a;
-        a.n = g->n;
-        a.BS = g->p.batch_size;
-        a.b = b;
-        a.rowptr = g->rowptr;
-        a.colidx = g->colidx;
-        a.x = (T *)g->x;
-        a.y = (T *)g->y;
-        a.accS = (T2 *)g->ex.accS[parity];
-        a.accC = g->ex.accC[parity];
-        a.fbuf = (T2 *)g->ex.fbuf;
-        a.ticket = g->ex.ticket;
+        a.fin = b;
+        a.pf = k & 1;
+        a.update = update;
+        a.step = (T)step_at(g->p, k);
         a.energy_k = energy_k;
         a.fout = fout;
-        a.nonfinite = &g->counters->nonfinite;
-        a.step = (T)step_at(g->p, k);
-        a.invK = (T)(1.0 / g->p.K);
-        a.negRK2 = (T)(-g->p.R * g->p.K * g->p.K);
-        a.literal = g->p.repulse_adjacent ? 0 : 1;
-        a.update = update;
-        const int R = std::min(g->p.batch_size, g->n - b * g->p.batch_size);
-        const int blocks = (R + kFinThreads / kWave - 1) / (kFinThreads / kWave);
+        a.epart = g->ex.epart;
+        a.ticket = g->ex.ticket;
+        a.nonfinite_count = &g->counters->nonfinite;
+        return a;
+    }
+
+    static FinArgs<T> no_fin() {
+        FinArgs<T> a{};
+        a.fin = -1;
+        return a;
+    }
+
+    static int step(bl_graph *g, int c, int pc, int do_next, const FinArgs<T> &fa) {
+        const int blocks = (g->n + kRows - 1) / kRows;
         int slot;
-        BL_TRY(prof_begin(g, PK_FINALIZE, &slot));
-        hipLaunchKernelGGL((finalize_kernel<T, KAHAN>), dim3(blocks), dim3(kFinThreads), 0,
-                           g->stream, a);
+        BL_TRY(prof_begin(g, PK_PANEL, &slot));
+        const int L = lanes(g, g->n);
+        if (L == 1)
+            hipLaunchKernelGGL((step_kernel<T, KAHAN, 1>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), c, pc,
+                               do_next, fa);
+        else if (L == 2)
+            hipLaunchKernelGGL((step_kernel<T, KAHAN, 2>), dim3(blocks), dim3(kRows * 2), 0, g->stream, view(g), c,
+                               pc, do_next, fa);
+        else
+            hipLaunchKernelGGL((step_kernel<T, KAHAN, 4>), dim3(blocks), dim3(kRows * 4), 0, g->stream, view(g), c,
+                               pc, do_next, fa);
         BL_HIP(hipGetLastError());
         return prof_end(g, slot);
     }
 
+    static int finalize(bl_graph *g, const FinArgs<T> &fa) {
+        const int BS = g->p.batch_size;
+        const int b0 = fa.fin * BS, b1 = std::min(g->n, b0 + BS);
+        const int blocks = (b1 - 1) / kRows - b0 / kRows + 1;
+        int slot;
+        BL_TRY(prof_begin(g, PK_FINALIZE, &slot));
+        hipLaunchKernelGGL((finalize_kernel<T, KAHAN>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), fa);
+        BL_HIP(hipGetLastError());
+        return prof_end(g, slot);
+    }
+
+    // iters iterations from iteration `start`; with stop_batch >= 0 the last
+    // iteration ends before batch stop_batch, whose forces go to g->fout.
     static int run(bl_graph *g, int iters, int start, int stop_batch) {
         if (iters <= 0) return BL_OK;
         const int nb = g->nb;
-        const size_t accBytes = sizeof(T2) * (size_t)g->n;
-        BL_TRY(rows(g, 0, g->n, 1, start & 1));
-        BL_HIP(hipMemsetAsync(g->ex.accS[(start + 1) & 1], 0, accBytes, g->stream));
-        if (KAHAN)
-            BL_HIP(hipMemsetAsync(g->ex.accC[(start + 1) & 1], 0, sizeof(float2) * g->n, g->stream));
-        for (int t = 0; t < iters; ++t) {
-            const int k = start + t;
-            const bool last = (t == iters - 1);
-            const int upto = (last && stop_batch >= 0) ? stop_batch : nb;
-            for (int b = 0; b < upto; ++b) {
-                BL_TRY(finalize(g, b, k, g->energy + t, nullptr, 1, k & 1));
-                const bool more_rows_now = (b + 1) < nb;
-                if (more_rows_now || !last) BL_TRY(panel(g, b, k, last ? 0 : 1));
+        const long long total = (stop_batch >= 0) ? (long long)(iters - 1) * nb + stop_batch + 1
+                                                  : (long long)iters * nb;
+        const int lastk = start + iters - 1;
+        BL_TRY(rows(g, 0, g->n, 1, start & 1, 1));
+        auto fin_of = [&](long long e) {
+            const int k = start + (int)(e / nb), b = (int)(e % nb);
+            const bool probe = stop_batch >= 0 && e == total - 1;
+            return fin_args(g, b, k, probe ? nullptr : g->energy + (k - start), probe ? g->fout : nullptr,
+                            probe ? 0 : 1);
+        };
+        BL_TRY(finalize(g, fin_of(0)));
+        for (long long e = 1; e < total; ++e) {
+            const int pk = start + (int)((e - 1) / nb), pb = (int)((e - 1) % nb);
+            const int do_next = pk < lastk ? 1 : 0;
+            if (nb > 1) {
+                BL_TRY(step(g, pb, pk & 1, do_next, fin_of(e)));
+            } else {
+                BL_TRY(step(g, pb, pk & 1, do_next, no_fin()));
+                BL_TRY(finalize(g, fin_of(e)));
             }
-            if (last && stop_batch >= 0)
-                BL_TRY(finalize(g, stop_batch, k, nullptr, g->fout, 0, k & 1));
         }
         return BL_OK;
     }
@@ -487,16 +1049,62 @@ struct ExactOps {
     static int forces(bl_graph *g, int batch) {
         const int BS = g->p.batch_size;
         const int r0 = batch * BS, r1 = std::min(g->n, r0 + BS);
-        BL_TRY(rows(g, r0, r1, 0, 0));
-        return finalize(g, batch, 0, nullptr, g->fout, 0, 0);
+        BL_TRY(rows(g, r0, r1, 0, 0, 0));
+        return finalize(g, fin_args(g, batch, 0, nullptr, g->fout, 0));
     }
 };
+
+// CSR segments: per row, the runs of neighbours that fall in one column batch.
+__global__ void seg_count_kernel(int n, int BS, const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                 int *__restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0, last = -1;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int b = colidx[e] / BS;
+        if (b != last) {
+            ++c;
+            last = b;
+        }
+    }
+    cnt[i] = c;
+}
+
+// Exclusive scan of cnt[0..n) into off[0..n] by one workgroup of 1024.
+__global__ __launch_bounds__(1024) void seg_scan_kernel(int n, const int *__restrict__ cnt, int *__restrict__ off) {
+    __shared__ int wsum[16];
+    int base = 0;
+    for (int t0 = 0; t0 < n; t0 += 1024) {
+        const int i = t0 + threadIdx.x;
+        const int v = i < n ? cnt[i] : 0;
+        int tot;
+        const int ex = block_excl_scan(v, wsum, &tot);
+        if (i < n) off[i] = base + ex;
+        base += tot;
+    }
+    if (threadIdx.x == 0) off[n] = base;
+}
+
+__global__ void seg_fill_kernel(int n, int BS, const int *__restrict__ rowptr, const int *__restrict__ colidx,
+                                const int *__restrict__ off, int2 *__restrict__ segs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int s = off[i], last = -1;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int b = colidx[e] / BS;
+        if (b != last) {
+            segs[s++] = make_int2(b, e);
+            last = b;
+        }
+    }
+}
 
 }  // namespace
 
 // Launch one workgroup per graph for a group of exact-mode graphs that share
 // a precision.  threads: 256, 512 or 1024 (the result does not depend on it).
-int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override) {
+int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override,
+                       int start_override) {
     if (G == 0) return BL_OK;
     std::vector<ExactJob> jobs(G);
     for (int q = 0; q < G; ++q) {
@@ -506,7 +1114,7 @@ int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, v
         J.BS = g->p.batch_size;
         J.nb = g->nb;
         J.iters = iters_override >= 0 ? iters_override : g->p.iterations;
-        J.start = g->p.start_iter;
+        J.start = start_override >= 0 ? start_override : g->p.start_iter;
         J.literal = g->p.repulse_adjacent ? 0 : 1;
         J.step0 = g->p.step0;
         J.decay = g->p.step_decay;
@@ -514,13 +1122,15 @@ int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, v
         J.negRK2 = -g->p.R * g->p.K * g->p.K;
         J.rowptr = g->rowptr;
         J.colidx = g->colidx;
+        J.segs = g->ex.segs;
+        J.segoff = g->ex.segoff;
+        J.cursor = g->ex.cursor;
         J.x = g->x;
         J.y = g->y;
         J.accS[0] = g->ex.accS[0];
         J.accS[1] = g->ex.accS[1];
         J.accC[0] = g->ex.accC[0];
         J.accC[1] = g->ex.accC[1];
-        J.fbuf = g->ex.fbuf;
         J.energy = g->energy;
         J.nonfinite = &g->counters->nonfinite;
     }
@@ -547,17 +1157,60 @@ size_t exact_job_size() { return sizeof(ExactJob); }
 int exact_alloc(bl_graph *g) {
     const size_t t2 = g->fp64 ? sizeof(double2) : sizeof(float2);
     const size_t n = (size_t)g->n;
+    const int BS = g->p.batch_size;
     for (int q = 0; q < 2; ++q) {
         BL_TRY(graph_alloc(g, &g->ex.accS[q], t2 * n));
         BL_TRY(graph_alloc(g, (void **)&g->ex.accC[q], sizeof(float2) * n));
     }
-    BL_TRY(graph_alloc(g, &g->ex.fbuf, t2 * (size_t)g->p.batch_size));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.epart, sizeof(double) * (size_t)(BS / kRows + 2)));
     BL_TRY(graph_alloc(g, (void **)&g->ex.ticket, 256));
+    BL_TRY(graph_alloc(g, &g->ex.d_job, sizeof(ExactJob)));
     BL_HIP(hipMemsetAsync(g->ex.ticket, 0, 256, g->stream));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.segoff, sizeof(int) * (n + 1)));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.cursor, sizeof(int) * n));
     return BL_OK;
 }
 
+// CSR segments by column batch; needs the uploaded CSR.
+int exact_prepare(bl_graph *g) {
+    const size_t n = (size_t)g->n;
+    const int BS = g->p.batch_size;
+    const int blocks = (g->n + 255) / 256;
+    hipLaunchKernelGGL(seg_count_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n, BS, g->rowptr, g->colidx,
+                       g->ex.cursor);
+    hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, g->stream, g->n, g->ex.cursor, g->ex.segoff);
+    BL_HIP(hipGetLastError());
+    int nseg = 0;
+    BL_HIP(hipMemcpyAsync(&nseg, g->ex.segoff + n, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    BL_HIP(hipStreamSynchronize(g->stream));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.segs, sizeof(int2) * (size_t)std::max(nseg, 1)));
+    hipLaunchKernelGGL(seg_fill_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n, BS, g->rowptr, g->colidx,
+                       g->ex.segoff, g->ex.segs);
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
+// Segment bytes of a graph (at most one per CSR entry).
+size_t exact_footprint(int n, int64_t nnz, int BS, bool fp64) {
+    const size_t N = (size_t)n, T2 = fp64 ? 16 : 8;
+    return 2 * (T2 * N + 8 * N) + 8 * (size_t)(BS / kRows + 2) + 256 + sizeof(ExactJob) + 4 * (N + 1) + 4 * N +
+           8 * (size_t)std::max<int64_t>(nnz, 1) + 4 * 256;
+}
+
+// Small graphs run in the one-workgroup kernel (one workgroup per graph); it
+// computes the same bits as the multi-workgroup kernels.
+static bool use_one_wg(const bl_graph *g, int stop_batch) {
+    return stop_batch < 0 && !(g->p.flags & BL_EXACT_MULTI_WG) && (long long)g->n * g->p.batch_size <= kOneWGPairs;
+}
+
 int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch) {
+    if (iters > 0 && use_one_wg(g, stop_batch)) {
+        const int nt = g->n >= 1024 ? 1024 : (g->n >= 512 ? 512 : 256);
+        int slot;
+        BL_TRY(prof_begin(g, PK_GRAPH, &slot));
+        BL_TRY(exact_graph_launch(&g, 1, nt, g->stream, g->ex.d_job, iters, start_iter));
+        return prof_end(g, slot);
+    }
     if (g->fp64) return ExactOps<double, false>::run(g, iters, start_iter, stop_batch);
     if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false>::run(g, iters, start_iter, stop_batch);
     return ExactOps<float, true>::run(g, iters, start_iter, stop_batch);

@@ -41,7 +41,7 @@ struct Counters {
 
 // Per-kernel device time, measured with hipEvents around launches when a
 // job's profiling is on.
-enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_COUNT };
+enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_GRAPH, PK_COUNT };
 constexpr int kProfPool = 2048;
 struct Prof {
     bool on = false;
@@ -100,10 +100,15 @@ struct BHRunSpec {
 
 // Exact-mode buffers (all device memory).
 struct ExactBuffers {
-    void *accS[2];          // [n] T2 (float2 / double2): per-row repulsion sums, by iteration parity
+    void *accS[2];          // [n] T2 (float2 / double2): per-row force sums, by iteration parity
     float2 *accC[2];        // [n] Kahan compensation (FP32 Kahan only)
-    void *fbuf;             // [BS] T2 net forces of the batch being finalized
-    unsigned *ticket;       // last-workgroup counter of the finalize kernel
+    int2 *segs;             // CSR segments: (column batch, first entry) of each run of a row's
+                            // neighbours that fall in one batch, rows in order
+    int *segoff;            // [n + 1] first segment of each row
+    int *cursor;            // [n] next segment of each row in the column-batch cycle
+    double *epart;          // energy partials of the 256-row chunks of one batch
+    unsigned *ticket;       // last-workgroup counter of the batch finalize
+    void *d_job;            // one-job table of the one-workgroup kernel
 };
 
 }  // namespace bl
@@ -143,10 +148,13 @@ int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds);
 
 // exact mode (bl_exact.hip)
 int exact_alloc(bl_graph *g);
+int exact_prepare(bl_graph *g);   // after the CSR upload
 int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch);
 int exact_forces(bl_graph *g, int batch);
-int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override);
+int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override,
+                       int start_override = -1);
 size_t exact_job_size();
+size_t exact_footprint(int n, int64_t nnz, int BS, bool fp64);
 
 // Barnes-Hut mode (bl_bh.hip)
 int bh_alloc(bl_graph *g);

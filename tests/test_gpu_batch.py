@@ -26,6 +26,7 @@ def test_mixed_batch_matches_single_runs_bitwise():
         _job("ba", 7000, 6, "bh", 4, bs=256, theta=1.2),
         _job("er", 4500, 7, "bh", 9, bs=100, theta=0.8),
         _job("ba", 9000, 8, "exact", 2, bs=512),      # larger than one workgroup's share
+        _job("er", 3000, 9, "exact", 4, bs=128),      # one workgroup in the batch, step kernels alone
     ]
     outs, stats = api.layout_batch([j[0] for j in jobs], [j[1] for j in jobs], [j[2] for j in jobs],
                                    [j[3] for j in jobs])

@@ -148,3 +148,59 @@ def test_device_pointer_path(grid32):
     xd, yd, ed, _ = api.layout(dev, x0, y0, p)
     xh, yh, eh, _ = api.layout(g, grid32["x0"], grid32["y0"], p)
     assert np.array_equal(xd.cpu().numpy(), xh) and np.array_equal(yd.cpu().numpy(), yh)
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp32", "fp64"])
+@pytest.mark.parametrize("n,bs,lit", [(1024, 128, True), (700, 96, False), (300, 512, True), (257, 256, True)])
+def test_one_workgroup_and_multi_workgroup_paths_agree_bitwise(precision, n, bs, lit):
+    """Small graphs run in one workgroup unless forced onto the step kernels;
+    both compute the same bits (energies, coordinates), resumed or not."""
+    g = I.grid(32, 32) if n == 1024 else _rand_graph(n, 8.0 / n, n + 3)
+    x0, y0 = I.uniform_coords(g.n, 12)
+    x0, y0 = _f32(x0), _f32(y0)
+    kw = dict(batch_size=bs, iterations=7, precision=precision, repulse_adjacent=lit)
+    xa, ya, ea, sa = api.layout(g, x0, y0, api.params(**kw))
+    xb, yb, eb, sb = api.layout(g, x0, y0, api.params(multi_wg=True, **kw))
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+    with api.Graph(g, api.params(**kw)) as h:
+        h.set_coords(x0, y0)
+        e1, _ = h.run(3)
+        e2, _ = h.run(4, start_iter=3)
+        xc, yc = h.get_coords()
+    assert np.array_equal(xa, xc) and np.array_equal(ya, yc) and np.array_equal(ea, np.concatenate([e1, e2]))
+
+
+def test_multi_workgroup_full_run_within_oracle_spread():
+    """A graph above the one-workgroup size (64x64 grid, batch 256): the
+    step-kernel path over a whole run, random start, 40 iterations."""
+    g = I.grid(64, 64)
+    x0, y0 = I.uniform_coords(g.n, 21)
+    x0, y0 = _f32(x0), _f32(y0)
+    xg, yg, eg, st = api.layout(g, x0, y0, api.params(batch_size=256, iterations=40))
+    rep = assert_within_oracle_spread(
+        oracle, g, xg, yg, lambda a, b: oracle.layout_exact(g.rowptr, g.colidx, a, b, 256, 40)[:2], x0, y0,
+        members=4)
+    print("grid64 exact full run:", rep)
+    _, _, eo = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 256, 40)
+    assert abs(eg[0] / eo[0] - 1) < 1e-4
+
+
+def test_hub_rows_and_big_batches():
+    """Hubs with hundreds of neighbours in one column batch, a batch larger
+    than one LDS tile (1500 > 1024 columns), and the single-batch case."""
+    r = I.rng(77)
+    n = 3000
+    src = np.concatenate([np.zeros(900, np.int64), np.full(700, 5), r.integers(0, n, 4000)])
+    dst = np.concatenate([r.choice(np.arange(1, n), 900, replace=False), r.choice(np.arange(6, 1500), 700, replace=False),
+                          r.integers(0, n, 4000)])
+    g = I.csr_from_edges(n, src, dst)
+    x0, y0 = I.uniform_coords(n, 5)
+    x0, y0 = _f32(x0), _f32(y0)
+    for bs, stop in [(1500, 1), (256, 0), (256, 11), (3000, 0)]:
+        p = api.params(batch_size=bs, iterations=2)
+        with api.Graph(g, p) as h:
+            h.set_coords(x0, y0)
+            _, _, fx, fy = h.run(2, stop_batch=stop)
+            xs, ys = h.get_coords()
+        ref = oracle.forces_exact(g.rowptr, g.colidx, xs, ys, stop * bs, min(n, stop * bs + bs))
+        assert_forces(fx, fy, ref, what="bs=%d stop=%d" % (bs, stop))
