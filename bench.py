@@ -89,7 +89,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2-bh", choices=["c2-bh", "c2-exact", "c1", "c3"])
+    ap.add_argument("--config", default="c2-bh", choices=["c2-bh", "c2-exact", "c1", "c3", "c4", "c5"])
+    ap.add_argument("--batch-count", type=int, default=512, help="c4: graphs in the batch")
+    ap.add_argument("--plain-every", type=int, default=8, help="c4: run every k-th graph alone for the plain rate")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="c5: length of the arrival window")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="c5: arrivals per second")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel hipEvent timing")
@@ -101,11 +105,24 @@ def main():
               "MI355X; --gpus %d is not supported." % args.gpus, file=sys.stderr)
         return 2
 
+    reqs = None
+    if args.config == "c5":
+        # request graphs are generated before anything touches the GPU
+        import multiprocessing as mp
+        from paper_2002_08233_amd import inputs as I
+        stream = I.served_stream(rate=args.serve_rate, duration=args.serve_seconds)
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 4)) as pool:
+            reqs = pool.map(_served_request, stream)
+
     import torch
     from paper_2002_08233_amd import api
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.config == "c4":
+        return bench_batched(args, api)
+    if args.config == "c5":
+        return bench_served(args, api, reqs)
     w = workload(args.config)
     g = w["graph"]
     steps = args.steps if args.steps is not None else w["iterations"]
@@ -185,9 +202,166 @@ def main():
         out["kernels"] = kern
     out["energy_last"] = float(energy[-1]) if len(energy) else None
 
+    if args.config == "c3" and args.precision == "fp32_kahan":
+        out["precision"] = precision_report(api, w, dev, x0, y0, min(steps, 20))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     dev.close()
+    print(json.dumps(out))
+    return 0
+
+
+def edge_energy(g, x, y):
+    """Sum over undirected edges of d^3 / 3 (K = 1): the attractive potential."""
+    import numpy as np
+    row = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    keep = row < g.colidx
+    d = np.hypot(x[g.colidx[keep]] - x[row[keep]], y[g.colidx[keep]] - y[row[keep]])
+    return float(np.sum(d ** 3) / 3.0)
+
+
+def precision_report(api, w, dev, x0, y0, iters):
+    """The same iterations in FP32 with compensated sums, plain FP32 and FP64
+    on the GPU: throughput of each, and the FP32 results' deviation from the
+    FP64 run (final edge energy, per-iteration energy, coordinates)."""
+    import numpy as np
+    import torch
+    g = w["graph"]
+    res = {}
+    for prec in ("fp32_kahan", "fp32", "fp64"):
+        p = api.params(batch_size=w["batch_size"], iterations=iters, mode="exact", precision=prec)
+        with api.Graph(g, p) as h:
+            h.set_coords(x0, y0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            en, _ = h.run(iters)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            x, y = h.get_coords()
+        res[prec] = dict(x=x, y=y, en=en, fu_s=g.n * iters / dt)
+    ref = res["fp64"]
+    ext = max(np.ptp(ref["x"]), np.ptp(ref["y"]))
+    ee64 = edge_energy(g, ref["x"], ref["y"])
+    out = {"iterations": iters, "reference": "fp64 on the GPU"}
+    for prec in ("fp32_kahan", "fp32", "fp64"):
+        r = res[prec]
+        out[prec] = {"force_updates_per_s": r["fu_s"]}
+        if prec != "fp64":
+            out[prec].update({
+                "edge_energy_rel_dev": abs(edge_energy(g, r["x"], r["y"]) / ee64 - 1),
+                "energy_rel_dev_max": float(np.max(np.abs(r["en"] / ref["en"] - 1))),
+                "coord_rms_dev_over_extent": float(np.sqrt(np.mean((r["x"] - ref["x"]) ** 2 +
+                                                                   (r["y"] - ref["y"]) ** 2)) / ext)})
+    return out
+
+
+def bench_batched(args, api):
+    """Batched uneven graphs: all of them in one bl_layout_batch call, against
+    the same graphs run alone one after the other (a sample of them), on the
+    same GPU.  Layouts are identical bit for bit either way (so at equal
+    stress).  Device time from the library (inputs already uploaded)."""
+    import numpy as np
+    from paper_2002_08233_amd import inputs as I
+    jobs = I.workload_batched(count=args.batch_count)
+    graphs = [j["graph"] for j in jobs]
+    plist = [api.params(batch_size=j["batch_size"], iterations=j["iterations"], mode=j["mode"],
+                        theta=j["theta"] if j["mode"] == "bh" else 1.2) for j in jobs]
+    fu = float(sum(g.n * j["iterations"] for g, j in zip(graphs, jobs)))
+    api.layout_batch(graphs[:4], [j["x0"] for j in jobs[:4]], [j["y0"] for j in jobs[:4]], plist[:4])  # warm-up
+    t0 = time.perf_counter()
+    outs, stats = api.layout_batch(graphs, [j["x0"] for j in jobs], [j["y0"] for j in jobs], plist)
+    wall = time.perf_counter() - t0
+    dev_s = stats[0]["seconds"]
+    sample = list(range(0, len(jobs), max(1, args.plain_every)))
+    plain_s = 0.0
+    plain_fu = 0.0
+    same = True
+    for q in sample:
+        x, y, _, st = api.layout(graphs[q], jobs[q]["x0"], jobs[q]["y0"], plist[q], energy=False)
+        plain_s += st["seconds"]
+        plain_fu += graphs[q].n * jobs[q]["iterations"]
+        same &= bool(np.array_equal(x, outs[q][0]) and np.array_equal(y, outs[q][1]))
+    value = fu / dev_s
+    plain = plain_fu / plain_s
+    nex = sum(1 for j in jobs if j["mode"] == "exact")
+    out = {"metric": METRIC, "value": value, "unit": "force-updates/s", "n_gpus": 1, "steps": 200,
+           "warmup": 1, "ms_per_step": 1e3 * dev_s / 200, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched: %d graphs (n log-uniform in [200, 20000], ER mean degree 8 / BA m=4), "
+                                  "%d vertices, batch 128, 200 iterations, exact below 4096 vertices (%d graphs), "
+                                  "Barnes-Hut theta 1.0 above" % (len(jobs), sum(g.n for g in graphs), nex),
+                      "graphs": len(jobs), "vertices": int(sum(g.n for g in graphs))},
+           "batched": {"device_seconds": dev_s, "wall_seconds_with_transfers": wall,
+                       "force_updates_per_s_with_transfers": fu / wall},
+           "plain": {"force_updates_per_s": plain, "sample_graphs": len(sample),
+                     "note": "each sampled graph alone through bl_layout, device time summed"},
+           "speedup_vs_plain": value / plain, "equal_stress": "bitwise-identical layouts" if same else "MISMATCH",
+           "roofline": None}
+    print(json.dumps(out))
+    return 0
+
+
+def _served_request(args):
+    from paper_2002_08233_amd import inputs as I
+    t, n, seed = args
+    r = I.served_request(n, seed)
+    return t, r["graph"], r["x0"], r["y0"]
+
+
+def bench_served(args, api, reqs):
+    """Served stream: Poisson arrivals, each an RMAT graph (edge factor 8, n
+    log-uniform in [2^10, 2^20]), Barnes-Hut theta 1.2, batch 256, 300
+    iterations, submitted to the continuous-batching server at its arrival
+    time.  Reports p50/p99 latency (submit to done) and the aggregate rate,
+    and the plain rate (a sample of the same requests run alone)."""
+    import threading
+    import numpy as np
+    p = api.params(batch_size=256, iterations=300, mode="bh", theta=1.2)
+    srv = api.Server(200 << 30, max_slots=512)
+    ids = [None] * len(reqs)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for q, (t, g, x0, y0) in enumerate(reqs):
+            delay = t - (time.perf_counter() - t_start)
+            if delay > 0:
+                time.sleep(delay)
+            ids[q] = srv.submit(g, x0, y0, p)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat = []
+    for q in range(len(reqs)):
+        srv.wait(ids[q], 3600.0)
+        _, _, st = srv.fetch(ids[q])
+        lat.append(st["seconds"])
+    t_end = time.perf_counter()
+    srv.close()
+    fu = float(sum(g.n * 300 for _, g, _, _ in reqs))
+    span = t_end - t_start
+    # plain: a size-stratified sample of the same requests, each alone
+    order = np.argsort([g.n for _, g, _, _ in reqs])
+    sample = order[np.linspace(0, len(order) - 1, min(12, len(order))).astype(int)]
+    ps, pf = 0.0, 0.0
+    for q in sample:
+        _, g, x0, y0 = reqs[q]
+        _, _, _, st = api.layout(g, x0, y0, p, energy=False)
+        ps += st["seconds"]
+        pf += g.n * 300
+    lat = np.array(lat)
+    out = {"metric": METRIC, "value": fu / span, "unit": "force-updates/s", "n_gpus": 1, "steps": 300,
+           "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "served: Poisson %.0f requests/s for %.0f s (%d requests), RMAT edge factor 8, "
+                                  "n log-uniform in [2^10, 2^20], Barnes-Hut theta 1.2, batch 256, 300 iterations"
+                                  % (args.serve_rate, args.serve_seconds, len(reqs)),
+                      "requests": len(reqs), "vertices": int(sum(g.n for _, g, _, _ in reqs))},
+           "served": {"latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+                      "latency_max_s": float(lat.max()), "span_s": span},
+           "plain": {"force_updates_per_s": pf / ps, "sample_requests": int(len(sample)),
+                     "note": "sampled requests alone through bl_layout, device time summed"},
+           "speedup_vs_plain": (fu / span) / (pf / ps), "roofline": None}
     print(json.dumps(out))
     return 0
 

@@ -1094,7 +1094,19 @@ struct BHEngine {
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool ev_used[2] = {false, false};
     int total[PT_COUNT] = {};
+    hipGraph_t graph = nullptr;         // one captured iteration of the current set
+    hipGraphExec_t exec = nullptr;
 };
+
+// Drop the captured iteration (after the stream has drained).
+static void engine_drop_graph(BHEngine *e) {
+    if (!e->exec && !e->graph) return;
+    (void)hipStreamSynchronize(e->stream);
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->exec = nullptr;
+    e->graph = nullptr;
+}
 
 int bh_engine_create(hipStream_t s, BHEngine **out) {
     BHEngine *e = new BHEngine();
@@ -1113,6 +1125,7 @@ int bh_engine_create(hipStream_t s, BHEngine **out) {
 
 void bh_engine_destroy(BHEngine *e) {
     if (!e) return;
+    engine_drop_graph(e);
     if (e->stream) (void)hipStreamSynchronize(e->stream);
     for (int q = 0; q < 2; ++q) {
         if (e->d_jobs[q]) (void)hipFree(e->d_jobs[q]);
@@ -1184,6 +1197,7 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
 
 // Make `jobs` the resident set (descriptors already filled).
 int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
+    engine_drop_graph(e);
     const int s = e->cur ^ 1;
     if (e->ev_used[s]) BL_HIP(hipEventSynchronize(e->ev[s]));
     if (G > e->cap) {
@@ -1287,29 +1301,31 @@ int bh_engine_run(BHEngine *e, int iters, bool use_graph) {
         for (int t = 0; t < iters; ++t) BL_TRY(bh_engine_iteration(e, nullptr));
         return BL_OK;
     }
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    BL_HIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
-    int rc = bh_engine_iteration(e, nullptr);
-    hipError_t ce = hipStreamEndCapture(e->stream, &graph);
-    if (rc != BL_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-    }
-    if (ce != hipSuccess) {
-        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
-        return BL_E_HIP;
-    }
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ie != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
-        return BL_E_HIP;
+    if (!e->exec) {
+        BL_HIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+        int rc = bh_engine_iteration(e, nullptr);
+        hipGraph_t graph = nullptr;
+        hipError_t ce = hipStreamEndCapture(e->stream, &graph);
+        if (rc != BL_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ce != hipSuccess) {
+            set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
+            return BL_E_HIP;
+        }
+        hipGraphExec_t exec = nullptr;
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+            return BL_E_HIP;
+        }
+        e->graph = graph;
+        e->exec = exec;
     }
     hipError_t le = hipSuccess;
-    for (int t = 0; t < iters && le == hipSuccess; ++t) le = hipGraphLaunch(exec, e->stream);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    for (int t = 0; t < iters && le == hipSuccess; ++t) le = hipGraphLaunch(e->exec, e->stream);
     if (le != hipSuccess) {
         set_error("hipGraphLaunch failed: %s", hipGetErrorString(le));
         return BL_E_HIP;

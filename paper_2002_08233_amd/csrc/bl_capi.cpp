@@ -35,7 +35,7 @@ int graph_alloc(bl_graph *g, void **ptr, size_t bytes) {
         return fail(BL_E_NOMEM, "too many allocations in one job");
     if (bytes == 0) bytes = 16;
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = g->async_mem ? hipMallocAsync(&p, bytes, g->stream) : hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(BL_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
@@ -118,7 +118,10 @@ static int check_csr(const bl_csr *g, uint32_t flags, hipStream_t s) {
 static void free_graph(bl_graph *g) {
     if (!g) return;
     if (g->p.mode == BL_BH && g->bh.engine) bh_engine_destroy(g->bh.engine);
-    for (int q = 0; q < g->nowned; ++q) (void)hipFree(g->owned[q]);
+    for (int q = 0; q < g->nowned; ++q) {
+        if (g->async_mem) (void)hipFreeAsync(g->owned[q], g->stream);
+        else (void)hipFree(g->owned[q]);
+    }
     if (g->prof) {
         for (int q = 0; q < 2 * kProfPool; ++q)
             if (g->prof->ev[q]) (void)hipEventDestroy(g->prof->ev[q]);
@@ -197,12 +200,18 @@ size_t bl_footprint_bytes(int32_t n, int64_t nnz, const bl_params *p) {
 }
 
 int bl_graph_create(const bl_csr *csr, const bl_params *p, void *hip_stream, bl_graph **out) {
+    return graph_create_ex(csr, p, (hipStream_t)hip_stream, false, out);
+}
+
+}  // extern "C"
+
+int bl::graph_create_ex(const bl_csr *csr, const bl_params *p, hipStream_t s, bool async_mem, bl_graph **out) {
     if (!out) return fail(BL_E_INVAL, "out is NULL");
     *out = nullptr;
     BL_TRY(check_params(p));
-    hipStream_t s = (hipStream_t)hip_stream;
     BL_TRY(check_csr(csr, p->flags, s));
     bl_graph *g = new bl_graph();
+    g->async_mem = async_mem;
     g->n = csr->n;
     g->nnz = csr->nnz;
     g->p = *p;
@@ -252,6 +261,8 @@ int bl_graph_create(const bl_csr *csr, const bl_params *p, void *hip_stream, bl_
     *out = g;
     return BL_OK;
 }
+
+extern "C" {
 
 int bl_graph_destroy(bl_graph *g) {
     if (!g) return BL_OK;

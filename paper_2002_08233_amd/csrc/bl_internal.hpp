@@ -137,11 +137,15 @@ struct bl_graph {
     void *owned[64] = {};       // every device allocation of this job
     int nowned = 0;
     bl::Prof *prof = nullptr;   // profiling state (NULL when never enabled)
+    bool async_mem = false;     // device memory is stream-ordered (hipMallocAsync / hipFreeAsync on stream)
 };
 
 namespace bl {
 
 int graph_alloc(bl_graph *g, void **ptr, size_t bytes);
+// bl_graph_create with stream-ordered device memory when async_mem (nothing
+// in create or destroy then waits for other streams).
+int graph_create_ex(const bl_csr *csr, const bl_params *p, hipStream_t s, bool async_mem, bl_graph **out);
 int fail_code(int code, const char *msg);
 int params_check(const bl_params *p);
 int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds);

@@ -1,15 +1,19 @@
 // Continuous batching of layout jobs.
 //
 // A scheduler thread owns the device work.  Submitted jobs wait in a FIFO;
-// at every quantum boundary the scheduler admits queued jobs first-fit while
-// a slot is free and their bl_footprint_bytes fits the remaining HBM budget,
-// keeps admitted jobs' graphs, coordinates and trees resident, and advances
-// all resident Barnes-Hut jobs together through the multi-job engine (one
-// launch per kernel serves every job, so their work overlaps on the device);
-// exact-mode jobs advance by resumable runs on the same stream.  Finished
-// jobs are copied out and their memory is returned to the budget.  A job's
-// result equals its alone result bitwise: the kernels it runs and their
-// arithmetic do not depend on the other jobs, and runs resume exactly.
+// the scheduler admits queued jobs first-fit while a slot is free and their
+// bl_footprint_bytes fits the remaining HBM budget, and keeps admitted jobs'
+// graphs, coordinates and trees resident until they finish.  Resident jobs
+// are grouped into lanes by the length of their minibatch chain (batches per
+// iteration), each lane with its own stream: a lane advances all its jobs a
+// few iterations at a time (Barnes-Hut jobs of a lane share every kernel
+// launch of one replayed iteration graph; exact jobs run resumable quanta),
+// and lanes run concurrently, so short jobs are not paced by long ones and
+// the device overlaps their work.  A lane's jobs are retired and new jobs
+// joined between its quanta.  Graph memory is stream-ordered, so admission
+// and retirement never wait for other lanes.  A job's result equals its
+// alone result bitwise: the kernels it runs and their arithmetic do not
+// depend on the other jobs, and runs resume exactly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +37,15 @@ using Clock = std::chrono::steady_clock;
 
 enum JobState { JS_QUEUED = 0, JS_RUNNING, JS_DONE, JS_FAILED, JS_CANCELLED };
 
-constexpr int kQuantum = 8;   // iterations between scheduling decisions
+constexpr int kQuantum = 8;   // iterations a lane runs between scheduling decisions
+constexpr int kLanes = 4;     // lanes by batches per iteration: <= 16, <= 128, <= 1024, more
+
+int lane_of(int nb) {
+    if (nb <= 16) return 0;
+    if (nb <= 128) return 1;
+    if (nb <= 1024) return 2;
+    return 3;
+}
 
 struct Job {
     int64_t id = 0;
@@ -47,6 +59,7 @@ struct Job {
     bl_graph *g = nullptr;
     int left = 0, done_iters = 0;
     int last_q = 0;   // iterations of the job's last quantum
+    bool in_flight = false;   // part of its lane's quantum in flight
     bool cancel = false;
     Clock::time_point t_submit, t_done;
     bl_stats stats{};
@@ -54,14 +67,25 @@ struct Job {
     std::string err;
 };
 
+struct Lane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    BHEngine *eng = nullptr;
+    bool busy = false;       // a quantum is in flight
+    int q = 0;               // its iterations
+    bool set_dirty = true;   // the Barnes-Hut job set changed
+    std::vector<std::shared_ptr<Job>> jobs;
+};
+
 }  // namespace
 }  // namespace bl
 
 struct bl_server {
     size_t budget = 0, used = 0;
-    int max_slots = 0;
+    int max_slots = 0, nresident = 0;
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t setup = nullptr;     // admission uploads
+    bl::Lane lanes[bl::kLanes];
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv;        // wakes the scheduler
@@ -70,15 +94,12 @@ struct bl_server {
     int64_t next_id = 1;
     std::map<int64_t, std::shared_ptr<bl::Job>> jobs;
     std::deque<int64_t> queue;
-    std::vector<std::shared_ptr<bl::Job>> resident;
-    bl::BHEngine *eng = nullptr;
-    bool set_dirty = true;
 };
 
 namespace bl {
 namespace {
 
-void finish(bl_server *s, const std::shared_ptr<Job> &j, int rc, const char *msg) {
+void finish(const std::shared_ptr<Job> &j, int rc, const char *msg) {
     j->t_done = Clock::now();
     j->rc = rc;
     if (msg) j->err = msg;
@@ -87,11 +108,11 @@ void finish(bl_server *s, const std::shared_ptr<Job> &j, int rc, const char *msg
     j->stats.seconds = std::chrono::duration<double>(j->t_done - j->t_submit).count();
 }
 
-// Admit queued jobs first-fit (caller holds the lock; device work without it
-// would race with nothing else, the scheduler is the only device user).
+// Admit queued jobs first-fit (caller holds the lock).  Graphs are built on
+// the setup stream with stream-ordered memory, then handed to their lane.
 void admit(bl_server *s) {
     for (auto it = s->queue.begin(); it != s->queue.end();) {
-        if ((int)s->resident.size() >= s->max_slots) break;
+        if (s->nresident >= s->max_slots) break;
         auto jit = s->jobs.find(*it);
         if (jit == s->jobs.end()) {
             it = s->queue.erase(it);
@@ -99,8 +120,9 @@ void admit(bl_server *s) {
         }
         std::shared_ptr<Job> j = jit->second;
         if (j->cancel) {
-            finish(s, j, BL_OK, nullptr);
+            finish(j, BL_OK, nullptr);
             it = s->queue.erase(it);
+            s->done_cv.notify_all();
             continue;
         }
         if (s->used + j->footprint > s->budget) {
@@ -108,63 +130,79 @@ void admit(bl_server *s) {
             continue;
         }
         bl_csr csr{j->n, j->nnz, j->rowptr.data(), j->colidx.data()};
-        int rc = bl_graph_create(&csr, &j->p, s->stream, &j->g);
+        int rc = graph_create_ex(&csr, &j->p, s->setup, true, &j->g);
         if (rc == BL_OK) rc = bl_graph_set_coords(j->g, j->x0.data(), j->y0.data(), 0);
         if (rc == BL_OK && j->p.mode == BL_BH) rc = bh_set_iteration(j->g, j->p.start_iter);
+        if (rc == BL_OK && hipStreamSynchronize(s->setup) != hipSuccess)
+            rc = fail_code(BL_E_HIP, "admission upload failed");
         if (rc != BL_OK) {
             std::string m = bl_last_error();
             if (j->g) bl_graph_destroy(j->g);
             j->g = nullptr;
-            finish(s, j, rc, m.c_str());
+            finish(j, rc, m.c_str());
             it = s->queue.erase(it);
             s->done_cv.notify_all();
             continue;
         }
+        Lane &L = s->lanes[lane_of(j->g->nb)];
+        j->g->stream = L.stream;
         j->state = JS_RUNNING;
         j->left = j->p.iterations;
         s->used += j->footprint;
-        s->resident.push_back(j);
-        s->set_dirty = true;
+        ++s->nresident;
+        L.jobs.push_back(j);
+        if (j->p.mode == BL_BH) L.set_dirty = true;
         it = s->queue.erase(it);
     }
 }
 
-// One quantum of device work for all resident jobs.
-int advance(bl_server *s) {
+// Enqueue one quantum of a lane's jobs (no waiting on the device).
+int launch(Lane &L) {
     std::vector<std::shared_ptr<Job>> bh, ex;
     int q = kQuantum;
-    for (auto &j : s->resident) {
-        if (j->left <= 0) continue;
+    for (auto &j : L.jobs) {
+        if (j->left <= 0 || j->cancel) continue;
         q = std::min(q, j->left);
         (j->p.mode == BL_BH ? bh : ex).push_back(j);
     }
+    if (bh.empty() && ex.empty()) return BL_OK;
+    for (auto &j : bh) j->in_flight = true;
+    for (auto &j : ex) j->in_flight = true;
     if (!bh.empty()) {
-        if (s->set_dirty) {
+        if (L.set_dirty) {
             std::vector<char> desc(bh_job_size() * bh.size());
             for (size_t k = 0; k < bh.size(); ++k) {
                 BHRunSpec spec;
                 spec.last_batch = bh[k]->g->nb - 1;
                 BL_TRY(bh_fill_job(bh[k]->g, (BHJob *)(desc.data() + bh_job_size() * k), spec));
             }
-            BL_TRY(bh_engine_set(s->eng, (const BHJob *)desc.data(), (int)bh.size()));
-            BL_TRY(bh_engine_setup(s->eng));
-            s->set_dirty = false;
+            BL_TRY(bh_engine_set(L.eng, (const BHJob *)desc.data(), (int)bh.size()));
+            BL_TRY(bh_engine_setup(L.eng));
+            L.set_dirty = false;
         }
-        BL_TRY(bh_engine_run(s->eng, q, q > 1));
+        BL_TRY(bh_engine_run(L.eng, q, q > 1));
     }
     for (auto &j : ex) BL_TRY(exact_run(j->g, q, j->p.start_iter + j->done_iters, -1));
-    BL_HIP(hipStreamSynchronize(s->stream));
-    for (auto &j : s->resident)
-        if (j->left > 0) {
-            j->left -= q;
-            j->done_iters += q;
-            j->last_q = q;
-        }
+    BL_HIP(hipEventRecord(L.done, L.stream));
+    L.busy = true;
+    L.q = q;
     return BL_OK;
 }
 
-void retire(bl_server *s) {
-    for (auto it = s->resident.begin(); it != s->resident.end();) {
+// After a lane's quantum: progress, then retire finished or cancelled jobs
+// (caller holds the lock).
+void complete(bl_server *s, Lane &L) {
+    L.busy = false;
+    // only the jobs that took part in the quantum advance (jobs that joined
+    // the lane while it ran start with the next one)
+    for (auto &j : L.jobs)
+        if (j->in_flight) {
+            j->in_flight = false;
+            j->left -= L.q;
+            j->done_iters += L.q;
+            j->last_q = L.q;
+        }
+    for (auto it = L.jobs.begin(); it != L.jobs.end();) {
         std::shared_ptr<Job> j = *it;
         if (j->left > 0 && !j->cancel) {
             ++it;
@@ -181,15 +219,32 @@ void retire(bl_server *s) {
             if (rc == BL_OK)
                 rc = stats_fill(j->g, &j->stats, j->p.mode == BL_BH ? j->done_iters : j->last_q, 0.0);
             j->stats.iters_run = j->done_iters;
-            if (rc != BL_OK) m = bl_last_error();
+            if (rc != BL_OK && rc != BL_E_NONFINITE) m = bl_last_error();
         }
+        if (j->p.mode == BL_BH) L.set_dirty = true;
         bl_graph_destroy(j->g);
         j->g = nullptr;
         s->used -= j->footprint;
-        finish(s, j, rc, m.empty() ? nullptr : m.c_str());
-        it = s->resident.erase(it);
-        s->set_dirty = true;
+        --s->nresident;
+        finish(j, rc, m.empty() ? nullptr : m.c_str());
+        it = L.jobs.erase(it);
     }
+    s->done_cv.notify_all();
+}
+
+void fail_lane(bl_server *s, Lane &L, int rc) {
+    std::string m = bl_last_error();
+    (void)hipStreamSynchronize(L.stream);
+    L.busy = false;
+    for (auto &j : L.jobs) {
+        if (j->g) bl_graph_destroy(j->g);
+        j->g = nullptr;
+        s->used -= j->footprint;
+        --s->nresident;
+        finish(j, rc, m.c_str());
+    }
+    L.jobs.clear();
+    L.set_dirty = true;
     s->done_cv.notify_all();
 }
 
@@ -198,38 +253,64 @@ void scheduler(bl_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     while (!s->stop) {
         admit(s);
-        if (s->resident.empty()) {
+        bool any_busy = false;
+        for (auto &L : s->lanes) {
+            if (L.busy) {
+                const hipError_t q = hipEventQuery(L.done);
+                if (q == hipErrorNotReady) {
+                    any_busy = true;
+                    continue;
+                }
+                if (q != hipSuccess) {
+                    set_error("lane quantum failed: %s", hipGetErrorString(q));
+                    fail_lane(s, L, BL_E_HIP);
+                    continue;
+                }
+                complete(s, L);
+            }
+            if (!L.jobs.empty()) {
+                const int rc = launch(L);
+                if (rc != BL_OK) {
+                    fail_lane(s, L, rc);
+                    continue;
+                }
+                any_busy |= L.busy;
+            }
+        }
+        if (!any_busy) {
             s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
             continue;
         }
-        // device work without the lock: only this thread touches the
-        // resident set and the engine; submitters and pollers proceed
-        lk.unlock();
-        const int rc = advance(s);
-        lk.lock();
-        if (rc != BL_OK) {
-            std::string m = bl_last_error();
-            for (auto &j : s->resident) {
-                if (j->g) bl_graph_destroy(j->g);
-                j->g = nullptr;
-                s->used -= j->footprint;
-                finish(s, j, rc, m.c_str());
-            }
-            s->resident.clear();
-            s->set_dirty = true;
-            s->done_cv.notify_all();
-            continue;
+        // poll the lanes' events; new submissions wake us at once
+        s->cv.wait_for(lk, std::chrono::microseconds(100));
+    }
+    for (auto &L : s->lanes) {
+        (void)hipStreamSynchronize(L.stream);
+        L.busy = false;
+        for (auto &j : L.jobs) {
+            if (j->g) bl_graph_destroy(j->g);
+            j->g = nullptr;
+            s->used -= j->footprint;
+            --s->nresident;
+            j->cancel = true;
+            finish(j, BL_OK, nullptr);
         }
-        retire(s);
+        L.jobs.clear();
     }
-    for (auto &j : s->resident) {
-        if (j->g) bl_graph_destroy(j->g);
-        j->g = nullptr;
-        j->cancel = true;
-        finish(s, j, BL_OK, nullptr);
-    }
-    s->resident.clear();
     s->done_cv.notify_all();
+}
+
+void server_free(bl_server *s) {
+    for (auto &L : s->lanes) {
+        if (L.eng) bh_engine_destroy(L.eng);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.stream) {
+            (void)hipStreamSynchronize(L.stream);
+            (void)hipStreamDestroy(L.stream);
+        }
+    }
+    if (s->setup) (void)hipStreamDestroy(s->setup);
+    delete s;
 }
 
 }  // namespace
@@ -249,17 +330,22 @@ int bl_server_create(size_t hbm_budget_bytes, int32_t max_slots, void *hip_strea
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     hipError_t e = hipGetDevice(&s->device);
-    if (e == hipSuccess) e = hipStreamCreate(&s->stream);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->setup, hipStreamNonBlocking);
+    for (auto &L : s->lanes) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
-        delete s;
-        set_error("server stream: %s", hipGetErrorString(e));
+        server_free(s);
+        set_error("server streams: %s", hipGetErrorString(e));
         return BL_E_HIP;
     }
-    int rc = bh_engine_create(s->stream, &s->eng);
-    if (rc != BL_OK) {
-        (void)hipStreamDestroy(s->stream);
-        delete s;
-        return rc;
+    for (auto &L : s->lanes) {
+        const int rc = bh_engine_create(L.stream, &L.eng);
+        if (rc != BL_OK) {
+            server_free(s);
+            return rc;
+        }
     }
     s->worker = std::thread(scheduler, s);
     *out = s;
@@ -342,7 +428,7 @@ int bl_server_release(bl_server *s, int64_t job) {
         s->jobs.erase(it);
         return BL_OK;
     }
-    j->cancel = true;   // queued: dropped at admission; running: at the next quantum
+    j->cancel = true;   // queued: dropped at admission; running: after its lane's quantum
     s->cv.notify_all();
     return BL_OK;
 }
@@ -355,10 +441,7 @@ int bl_server_destroy(bl_server *s) {
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    if (s->eng) bh_engine_destroy(s->eng);
-    (void)hipStreamSynchronize(s->stream);
-    (void)hipStreamDestroy(s->stream);
-    delete s;
+    server_free(s);
     return BL_OK;
 }
 

@@ -89,3 +89,21 @@ def test_release_cancels_and_timeout_reports():
         srv.release(long_id)
         with pytest.raises(api.BLError):
             srv.poll(long_id)
+
+
+def test_jobs_joining_a_running_lane():
+    """Jobs submitted while their lane's quantum is on the device start with
+    the next quantum and still equal their alone runs."""
+    first = _job("er", 1500, 30, "bh", 60, 128, 1.0)
+    later = [_job("er", 1200 + 100 * q, 31 + q, "bh" if q % 2 else "exact", 9 + q, 128, 1.0) for q in range(5)]
+    with api.Server(8 << 30, max_slots=64) as srv:
+        ids = [srv.submit(*first)]
+        for j in later:
+            time.sleep(0.01)
+            ids.append(srv.submit(*j))
+        for jid, (g, x0, y0, p) in zip(ids, [first] + later):
+            srv.wait(jid, 120.0)
+            xs, ys, st = srv.fetch(jid)
+            xa, ya, ea, _ = api.layout(g, x0, y0, p)
+            assert np.array_equal(xs, xa) and np.array_equal(ys, ya), (g.n, p.mode)
+            assert st["iters_run"] == p.iterations and st["energy_last"] == ea[-1]
