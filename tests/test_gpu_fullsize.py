@@ -1,0 +1,84 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration
+the benchmark times, on sampled minibatches the oracle can compute one by one
+(needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_08233_amd import api, inputs as I
+from _parity import assert_forces, force_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rmat17():
+    return I.workload_rmat17(mode="bh")
+
+
+@pytest.fixture(scope="module")
+def rgg64k():
+    return I.workload_rgg64k()
+
+
+def _pipeline(w, p, k, stop):
+    """Forces of batch `stop` in iteration k (0-based), with the snapshot the
+    tree of iteration k was built from and the live coordinates."""
+    g = w["graph"]
+    with api.Graph(g, p) as h:
+        h.set_coords(w["x0"], w["y0"])
+        if k > 0:
+            h.run(k)
+        sx, sy = h.get_coords()
+        _, st, fx, fy = h.run(1, start_iter=k, stop_batch=stop)
+        xs, ys = h.get_coords()
+    return sx, sy, xs, ys, fx, fy, st
+
+
+@pytest.mark.parametrize("stop", [0, 300, 511])
+def test_rmat17_barnes_hut_pipeline(rmat17, stop):
+    """131072 vertices, theta 1.2, batch 256: hub rows (batch 0), the middle,
+    the last batch; iteration 2 (moved leaves and moved neighbours live)."""
+    w, g = rmat17, rmat17["graph"]
+    p = api.params(batch_size=256, iterations=2, mode="bh", theta=1.2)
+    sx, sy, xs, ys, fx, fy, st = _pipeline(w, p, 1, stop)
+    ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(sx, sy), stop * 256, stop * 256 + 256,
+                           theta=1.2)
+    r = assert_forces(fx, fy, ref, mask=~ref.near_tie, what="rmat17 bh batch %d" % stop)
+    print("rmat17 bh batch", stop, r, "near ties", int(ref.near_tie.sum()))
+
+
+def test_rmat17_barnes_hut_one_shot(rmat17):
+    w, g = rmat17, rmat17["graph"]
+    p = api.params(batch_size=256, iterations=1, mode="bh", theta=1.2)
+    for b in (1, 257):
+        fx, fy = api.forces(g, w["x0"], w["y0"], b, p)
+        ref = oracle.forces_bh(g.rowptr, g.colidx, w["x0"], w["y0"], oracle.Tree(w["x0"], w["y0"]),
+                               b * 256, b * 256 + 256, theta=1.2)
+        assert_forces(fx, fy, ref, mask=~ref.near_tie, what="rmat17 one-shot batch %d" % b)
+
+
+@pytest.mark.parametrize("stop", [0, 257])
+def test_rmat17_exact_pipeline(rmat17, stop):
+    """The same graph in exact mode (17.2e9 pairs per iteration): iteration 2."""
+    w, g = rmat17, rmat17["graph"]
+    p = api.params(batch_size=256, iterations=2, mode="exact")
+    _, _, xs, ys, fx, fy, _ = _pipeline(w, p, 1, stop)
+    ref = oracle.forces_exact(g.rowptr, g.colidx, xs, ys, stop * 256, stop * 256 + 256)
+    r = assert_forces(fx, fy, ref, what="rmat17 exact batch %d" % stop)
+    print("rmat17 exact batch", stop, r)
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp32", "fp64"])
+def test_rgg64k_precision_stress(rgg64k, precision):
+    """65536-vertex random geometric graph, batch 512, three precisions: the
+    per-step force error against FP64 at iteration 3, batch 64."""
+    w, g = rgg64k, rgg64k["graph"]
+    p = api.params(batch_size=512, iterations=4, mode="exact", precision=precision)
+    _, _, xs, ys, fx, fy, _ = _pipeline(w, p, 3, 64)
+    ref = oracle.forces_exact(g.rowptr, g.colidx, xs, ys, 64 * 512, 65 * 512)
+    r = force_errors(fx, fy, ref)
+    print("rgg64k", precision, r)
+    assert r["ok"], r
+    if precision == "fp64":
+        assert r["normwise"] < 1e-10
