@@ -33,6 +33,26 @@ BYTES_PER_WALK_VERTEX = 32.0     # order id 4 + own x,y 8 + far-field sum 16 + l
 BYTES_PER_ENTRY = 12.0           # CSR or moved-leaf entry: 4 B id + 8 B live x,y
 BYTES_PER_CHAIN_VERTEX = 52.0    # rowptr 8 + late count 4 + far sum 16 + x,y read 8 + write 8 + force 8
 FLOP_PER_PAIR = 10.0             # 2 sub, d^2 (2 mul + 1 add), 1 reciprocal, 2 FMA
+# HBM bytes per launch of a workload's dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (FETCH_SIZE scaled by 2.0, the factor a plain copy of known size shows; WRITE_SIZE by 1.0).
+# Valid only while the kernel's source file is the one the counters were taken on.
+MEASURED_TRAFFIC = {
+    ("c2-bh", "chain_kernel"): (23650979.0, "bl_bh.hip", "7204b5fd8d542cde"),
+    ("c2-exact", "step_kernel"): (6224705.0, "bl_exact.hip", "d969f86577c20086"),
+}
+
+
+def measured_traffic(config, kernel):
+    import hashlib
+    m = MEASURED_TRAFFIC.get((config, kernel))
+    if not m:
+        return None
+    path = os.path.join(ROOT, "paper_2002_08233_amd", "csrc", m[1])
+    try:
+        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return m[0] if digest == m[2] else None
 
 
 def workload(name):
@@ -98,6 +118,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel hipEvent timing")
     ap.add_argument("--precision", default="fp32_kahan")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -105,6 +127,8 @@ def main():
               "MI355X; --gpus %d is not supported." % args.gpus, file=sys.stderr)
         return 2
 
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     reqs = None
     if args.config == "c5":
         # request graphs are generated before anything touches the GPU
@@ -175,8 +199,9 @@ def main():
             if dom_name == "tree_build":
                 dom_name = "far_kernel"
             out["roofline"] = {"bound": "hbm", "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                               "unit": "GB/s", "frac": dom["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
-                               "kernel": dom_name}
+                               "unit": "GB/s", "frac": dom["achieved_GBs"] / HBM_PEAK_GBS,
+                               "traffic": measured_traffic(args.config, dom_name), "kernel": dom_name,
+                               "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
             out["bh"] = {"node_visits_per_vertex": visits / (g.n * steps), "late_entries_per_vertex":
                          late / (g.n * steps), "late_overflow": st["late_overflow"]}
         else:
@@ -195,7 +220,7 @@ def main():
             peak = FP32_VALU_PEAK_TFLOPS if args.precision != "fp64" else FP64_VALU_PEAK_TFLOPS
             out["roofline"] = {"bound": "alu", "achieved": dom["achieved_TFLOPs"], "peak": peak,
                                "unit": "TFLOP/s", "frac": dom["achieved_TFLOPs"] / peak,
-                               "traffic": None, "kernel": dom_name,
+                               "traffic": measured_traffic(args.config, dom_name.split("<")[0]), "kernel": dom_name,
                                "frac_of_packed_fp32_peak": (dom["achieved_TFLOPs"] / 157.3
                                                             if args.precision != "fp64" else None)}
             out["exact"] = {"pairs_per_s": pairs / wall, "batches_per_iteration": nb}
@@ -208,6 +233,19 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     dev.close()
     print(json.dumps(out))
+    return 0
+
+
+def copy_probe(mib):
+    """A plain copy of known size: reads and writes mib MiB once per launch,
+    three launches.  Its FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    import torch
+    src = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_launch": mib << 20, "launches": 3}))
     return 0
 
 

@@ -149,6 +149,23 @@ extern "C" int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const dou
             wg_idx[g->p.precision].push_back(q);
         } else big.push_back(g);
     }
+    // largest graphs first: their workgroups start at once and bound the
+    // launch, the small ones fill in behind them
+    for (int c = 0; c < 3; ++c) {
+        std::vector<size_t> ord(wg[c].size());
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            return (int64_t)wg[c][a]->n * wg[c][a]->nb > (int64_t)wg[c][b]->n * wg[c][b]->nb;
+        });
+        std::vector<bl_graph *> g2;
+        std::vector<int> i2;
+        for (size_t q : ord) {
+            g2.push_back(wg[c][q]);
+            i2.push_back(wg_idx[c][q]);
+        }
+        wg[c].swap(g2);
+        wg_idx[c].swap(i2);
+    }
     size_t maxwg = 0;
     for (int c = 0; c < 3; ++c) maxwg = std::max(maxwg, wg[c].size());
     if (maxwg) BL_HIP(hipMalloc(&B.d_jobs, exact_job_size() * maxwg));
