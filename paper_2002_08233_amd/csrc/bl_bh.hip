@@ -44,7 +44,7 @@ constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 values per tile
 constexpr int kChainThreads = 1024;
 constexpr int kHeavyRow = 256;        // early entries above which a whole workgroup sums the row
-constexpr int kHeavyBlocks = 16;      // workgroups per job for heavy rows
+constexpr int kLateHeavyRow = 256;    // moved neighbours above which a whole workgroup copies the row
 constexpr int kMaxChainRows = 2048;   // batch-size limit of the Barnes-Hut chain
 constexpr int kEnt = 8;               // late entries per thread per pass (held in registers)
 
@@ -692,7 +692,7 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
 // ("late") neighbours a prefix of each row; its length is fixed per job.
 __global__ void heavy_reset_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
-    if (threadIdx.x == 0) *J.nheavy = 0;
+    if (threadIdx.x < 2) J.nheavy[threadIdx.x] = 0;
 }
 
 __global__ void late_prefix_kernel(BH_KERNEL_ARGS) {
@@ -709,6 +709,7 @@ __global__ void late_prefix_kernel(BH_KERNEL_ARGS) {
     }
     J.late_att[i] = lo - J.rowptr[i];
     if (end - lo > kHeavyRow) J.heavy[atomicAdd(J.nheavy, 1)] = i;
+    if (lo - J.rowptr[i] > kLateHeavyRow) J.heavy[J.n + atomicAdd(J.nheavy + 1, 1)] = i;
 }
 
 // Light rows: 8 lanes per row.
@@ -812,10 +813,27 @@ __global__ __launch_bounds__(256) void late_fill_kernel(BH_KERNEL_ARGS) {
     const int rs = J.rowptr[i];
     const int la = J.all_live ? J.rowptr[i + 1] - rs : J.late_att[i];
     unsigned long long *ent = J.ent;
-    for (int k = sub; k < la; k += 8) ent[base + k] = rbits | (unsigned)J.colidx[rs + k];
+    const bool heavy = !J.all_live && la > kLateHeavyRow;   // copied by late_fill_heavy_kernel
+    if (!heavy)
+        for (int k = sub; k < la; k += 8) ent[base + k] = rbits | (unsigned)J.colidx[rs + k];
     const int ll = late_leaf_count(J.late_cnt[i]);
     const int *lid = J.late_ids + (size_t)i * kLateCap;
     for (int k = sub; k < ll; k += 8) ent[base + la + k] = rbits | 0x80000000u | (unsigned)lid[k];
+}
+
+// Rows with many moved neighbours: one workgroup per row copies them.
+__global__ __launch_bounds__(256) void late_fill_heavy_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    if (J.all_live) return;
+    const int nh = J.nheavy[1];
+    for (int h = jb.local; h < nh; h += jb.nblocks) {
+        const int i = J.heavy[J.n + h];
+        const int b = i / J.BS;
+        const unsigned long long rbits = (unsigned long long)(i - b * J.BS) << 32;
+        const size_t base = (size_t)J.bbase[b] + J.roff[i];
+        const int rs = J.rowptr[i], la = J.late_att[i];
+        for (int k = threadIdx.x; k < la; k += 256) J.ent[base + k] = rbits | (unsigned)J.colidx[rs + k];
+    }
 }
 
 // ---------------------------------------------------------------- chain
@@ -1074,7 +1092,7 @@ int blocks_for(int type, const BHJob &J) {
         case PT_MARK: return std::max(1, (n - 1 + 255) / 256);
         case PT_SCAN: return J.sblocks;
         case PT_VERT8: return (n + 31) / 32;
-        case PT_HEAVY: return kHeavyBlocks;
+        case PT_HEAVY: return std::max(16, std::min(256, n / 512));
         case PT_BATCH: return J.nb;
     }
     return 0;
@@ -1283,6 +1301,7 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     BH_LAUNCH(batch_offsets_kernel, PT_BATCH, 1024);
     BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 2);
     BH_LAUNCH(late_fill_kernel, PT_VERT8, 256);
+    BH_LAUNCH(late_fill_heavy_kernel, PT_HEAVY, 256);
     if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
     BH_LAUNCH(chain_kernel, PT_ONE, kChainThreads);
     if (prof) BL_TRY(prof_end(prof, slot));
@@ -1341,7 +1360,7 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
-           8 * ((size_t)nnz + N * kLateCap) + 64;
+           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N;
 }
 
 int bh_alloc(bl_graph *g) {
@@ -1370,7 +1389,7 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.late_ids, 4 * N * kLateCap));
     BL_TRY(graph_alloc(g, (void **)&h.snap, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.late_att, 4 * N));
-    BL_TRY(graph_alloc(g, (void **)&h.heavy, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.heavy, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nheavy, 16));
     BL_TRY(graph_alloc(g, (void **)&h.atte, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.roff, 4 * N));
