@@ -45,7 +45,7 @@ constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 values per tile
 constexpr int kChainThreads = 1024;
 constexpr int kHeavyRow = 256;        // early entries above which a whole workgroup sums the row
 constexpr int kLateHeavyRow = 256;    // moved neighbours above which a whole workgroup copies the row
-constexpr int kMaxChainRows = 2048;   // batch-size limit of the Barnes-Hut chain
+constexpr int kMaxChainRows = 1024;   // batch-size limit of the Barnes-Hut chain
 constexpr int kEnt = 8;               // late entries per thread per pass (held in registers)
 
 // Device descriptor of one job (all pointers are device memory).
@@ -56,28 +56,28 @@ struct BHJob {
     int all_live;               // one-shot force call: every leaf and neighbour is live
     int first_batch, last_batch, stop_batch;
     double step0, decay;
-    int *kiter;                 // [2]: current iteration, first iteration of the run
-    const int *rowptr, *colidx;
-    float2 *pos;                // live coordinates
-    const float2 *src;          // coordinates the tree is built from
-    float *bbox, *bbox_part;
-    unsigned *ticket;
-    unsigned *key0, *key1;
-    int *val0, *val1, *hist;
-    unsigned *mask;
-    int *cellcnt, *scan_part;
-    double *pdd, *pdd_part;
-    float4 *nodeA;
-    int2 *nodeB;
-    int *leafpos, *nnodes;
-    float4 *far;
-    int *late_cnt, *late_ids, *late_att, *heavy, *nheavy;
-    float2 *atte;
-    int *roff, *bbase;
-    unsigned long long *ent;
+    gptr<int> kiter;            // [2]: current iteration, first iteration of the run
+    gptr<const int> rowptr, colidx;
+    gptr<float2> pos;           // live coordinates
+    gptr<const float2> src;     // coordinates the tree is built from
+    gptr<float> bbox, bbox_part;
+    gptr<unsigned> ticket;
+    gptr<unsigned> key0, key1;
+    gptr<int> val0, val1, hist;
+    gptr<unsigned> mask;
+    gptr<int> cellcnt, scan_part;
+    gptr<double> pdd, pdd_part;
+    gptr<float4> nodeA;
+    gptr<int2> nodeB;
+    gptr<int> leafpos, nnodes;
+    gptr<float4> far;
+    gptr<int> late_cnt, late_ids, late_att, heavy, nheavy;
+    gptr<float2> atte;
+    gptr<int> roff, bbase;
+    gptr<unsigned long long> ent;
     size_t ent_cap;
-    double *energy;             // one value per iteration of the run
-    double *fout;
+    gptr<double> energy;        // one value per iteration of the run
+    gptr<double> fout;
     Counters *ctr;
 };
 
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void bbox_kernel(BH_KERNEL_ARGS) {
     __shared__ int s_last;
     float mnx = FLT_MAX, mny = FLT_MAX, mxx = -FLT_MAX, mxy = -FLT_MAX;
     for (int i = jb.local * 256 + threadIdx.x; i < J.n; i += jb.nblocks * 256) {
-        const float2 c = J.src[i];
+        const float2 c = ld<float2>(J.src, i);
         mnx = fminf(mnx, c.x);
         mxx = fmaxf(mxx, c.x);
         mny = fminf(mny, c.y);
@@ -139,13 +139,13 @@ __global__ __launch_bounds__(256) void bbox_kernel(BH_KERNEL_ARGS) {
             s[2][0] = fminf(s[2][0], s[2][q]);
             s[3][0] = fmaxf(s[3][0], s[3][q]);
         }
-        float *part = J.bbox_part + 4 * jb.local;
+        gptr<float> part = J.bbox_part + 4 * jb.local;
         part[0] = s[0][0];
         part[1] = s[1][0];
         part[2] = s[2][0];
         part[3] = s[3][0];
         __threadfence();
-        s_last = (atomicAdd(J.ticket, 1u) == (unsigned)jb.nblocks - 1);
+        s_last = (atomicAdd((unsigned *)J.ticket, 1u) == (unsigned)jb.nblocks - 1);
     }
     __syncthreads();
     if (!s_last || threadIdx.x != 0) return;
@@ -193,7 +193,7 @@ __global__ void morton_kernel(BH_KERNEL_ARGS) {
     const float xmin = J.bbox[0], ymin = J.bbox[1], scale = J.bbox[3];
     unsigned qx = 0, qy = 0;
     if (scale > 0.f) {
-        const float2 c = J.src[i];
+        const float2 c = ld<float2>(J.src, i);
         qx = quantise(c.x, xmin, scale);
         qy = quantise(c.y, ymin, scale);
     }
@@ -224,7 +224,7 @@ __device__ __forceinline__ unsigned long long lanes_below() {
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(BH_KERNEL_ARGS, int pass) {
     BH_JOB();
     __shared__ int h[256];
-    const unsigned *keys = (pass & 1) ? J.key1 : J.key0;
+    gptr<const unsigned> keys = (pass & 1) ? J.key1 : J.key0;
     const int shift = 8 * pass, n = J.n;
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -245,10 +245,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(BH_KERNEL_ARGS
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(BH_KERNEL_ARGS, int pass) {
     BH_JOB();
     __shared__ int cnt[4][256];
-    const unsigned *kin = (pass & 1) ? J.key1 : J.key0;
-    const int *vin = (pass & 1) ? J.val1 : J.val0;
-    unsigned *kout = (pass & 1) ? J.key0 : J.key1;
-    int *vout = (pass & 1) ? J.val0 : J.val1;
+    gptr<const unsigned> kin = (pass & 1) ? J.key1 : J.key0;
+    gptr<const int> vin = (pass & 1) ? J.val1 : J.val0;
+    gptr<unsigned> kout = (pass & 1) ? J.key0 : J.key1;
+    gptr<int> vout = (pass & 1) ? J.val0 : J.val1;
     const int shift = 8 * pass, n = J.n, tiles = J.tiles;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(BH_KERNEL_A
 __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(BH_KERNEL_ARGS, int which) {
     BH_JOB();
     __shared__ int ws[16];
-    int *data = which == 0 ? J.hist : (which == 1 ? J.scan_part : J.bbase);
+    gptr<int> data = which == 0 ? J.hist : (which == 1 ? J.scan_part : J.bbase);
     const int len = which == 0 ? 256 * J.tiles : (which == 1 ? J.sblocks : J.nb + 1);
     int running = 0;
     for (int b0 = 0; b0 < len; b0 += kScanTile) {
@@ -337,7 +337,7 @@ __device__ __forceinline__ int common_levels(unsigned a, unsigned b) {
 
 // Sorted position range [lo, hi] of the level-`lvl` cell holding sorted
 // position p (binary searches on the sorted keys).
-__device__ __forceinline__ int cell_first(const unsigned *keys, int p, int lvl) {
+__device__ __forceinline__ int cell_first(gptr<const unsigned> keys, int p, int lvl) {
     if (lvl == 0) return 0;
     const int sh = 32 - 2 * lvl;
     const unsigned pre = keys[p] >> sh;
@@ -349,7 +349,7 @@ __device__ __forceinline__ int cell_first(const unsigned *keys, int p, int lvl) 
     }
     return lo;
 }
-__device__ __forceinline__ int cell_last(const unsigned *keys, int n, int p, int lvl) {
+__device__ __forceinline__ int cell_last(gptr<const unsigned> keys, int n, int p, int lvl) {
     if (lvl == 0) return n - 1;
     const int sh = 32 - 2 * lvl;
     const unsigned pre = keys[p] >> sh;
@@ -366,10 +366,10 @@ __global__ void mark_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     const int p = jb.local * blockDim.x + threadIdx.x;
     if (p >= J.n - 1) return;
-    const unsigned *keys = J.key0;
+    gptr<const unsigned> keys = J.key0;
     const int lvl = common_levels(keys[p], keys[p + 1]);
     const int s = cell_first(keys, p, lvl);
-    atomicOr(&J.mask[s], 1u << lvl);
+    atomicOr((unsigned *)(J.mask + s), 1u << lvl);
 }
 
 // Tile sums and apply of the 3-phase scan of popcount(mask) -> cellcnt.
@@ -455,13 +455,13 @@ __global__ __launch_bounds__(kScanThreads) void coord_tile_kernel(BH_KERNEL_ARGS
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q)
         if (p0 + q < J.n) {
-            const float2 c = J.src[J.val0[p0 + q]];
+            const float2 c = ld<float2>(J.src, J.val0[p0 + q]);
             s = dd2_add(s, dd2{{(double)c.x, 0}, {(double)c.y, 0}});
         }
     dd2 total;
     (void)block_excl_scan_dd2(s, ws, &total);
     if (threadIdx.x == 0) {
-        double *part = J.pdd_part + 4 * jb.local;
+        gptr<double> part = J.pdd_part + 4 * jb.local;
         part[0] = total.x.hi;
         part[1] = total.x.lo;
         part[2] = total.y.hi;
@@ -473,7 +473,7 @@ __global__ void coord_part_scan_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     if (threadIdx.x != 0) return;
     dd2 run{{0, 0}, {0, 0}};
-    double *part = J.pdd_part;
+    gptr<double> part = J.pdd_part;
     for (int b = 0; b < J.sblocks; ++b) {
         dd2 v{{part[4 * b], part[4 * b + 1]}, {part[4 * b + 2], part[4 * b + 3]}};
         part[4 * b + 0] = run.x.hi;
@@ -496,17 +496,17 @@ __global__ __launch_bounds__(kScanThreads) void coord_apply_kernel(BH_KERNEL_ARG
     for (int q = 0; q < kScanItems; ++q) {
         v[q] = dd2{{0, 0}, {0, 0}};
         if (p0 + q < n) {
-            const float2 c = J.src[J.val0[p0 + q]];
+            const float2 c = ld<float2>(J.src, J.val0[p0 + q]);
             v[q] = dd2{{(double)c.x, 0}, {(double)c.y, 0}};
         }
         s = dd2_add(s, v[q]);
     }
     dd2 total;
     dd2 pre_ = block_excl_scan_dd2(s, ws, &total);
-    const double *part = J.pdd_part + 4 * jb.local;
+    const gptr<double> part = J.pdd_part + 4 * jb.local;
     pre_ = dd2_add(dd2{{part[0], part[1]}, {part[2], part[3]}}, pre_);
     const size_t N1 = (size_t)n + 1;
-    double *pdd = J.pdd;
+    gptr<double> pdd = J.pdd;
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
         if (p0 + q < n) {
@@ -533,9 +533,9 @@ __global__ void emit_kernel(BH_KERNEL_ARGS) {
     const int n = J.n;
     const int p = jb.local * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const unsigned *keys = J.key0;
+    gptr<const unsigned> keys = J.key0;
     const size_t N1 = (size_t)n + 1;
-    const double *pdd = J.pdd;
+    const gptr<double> pdd = J.pdd;
     const float W = J.bbox[2];
     unsigned m = J.mask[p];
     int v = p + J.cellcnt[p];
@@ -566,14 +566,14 @@ __global__ void emit_kernel(BH_KERNEL_ARGS) {
             const float side = ldexpf(W, -lvl);
             side2 = side * side;
         }
-        J.nodeA[v] = float4{(float)cx, (float)cy, side2, (float)cnt};
-        J.nodeB[v] = int2{skip, -1};
+        st<float4>(J.nodeA, v, float4{(float)cx, (float)cy, side2, (float)cnt});
+        st<int2>(J.nodeB, v, int2{skip, -1});
         ++v;
     }
     const int vert = J.val0[p];
-    const float2 pv = J.src[vert];
-    J.nodeA[v] = float4{pv.x, pv.y, 0.f, 1.f};
-    J.nodeB[v] = int2{v + 1, vert};
+    const float2 pv = ld<float2>(J.src, vert);
+    st<float4>(J.nodeA, v, float4{pv.x, pv.y, 0.f, 1.f});
+    st<int2>(J.nodeB, v, int2{v + 1, vert});
     J.leafpos[vert] = v;
     if (p == n - 1) *J.nnodes = v + 1;
 }
@@ -581,10 +581,10 @@ __global__ void emit_kernel(BH_KERNEL_ARGS) {
 // --------------------------------------------------------------- walks
 struct WalkArgs {
     int n, BS;
-    const int *total;       // node count, written by emit_kernel
-    const float4 *nodeA;
-    const int2 *nodeB;
-    const int *leafpos;
+    gptr<const int> total;  // node count, written by emit_kernel
+    gptr<const float4> nodeA;
+    gptr<const int2> nodeB;
+    gptr<const int> leafpos;
     float theta2, negRK2, invK;
 };
 
@@ -602,21 +602,21 @@ __device__ __forceinline__ void rep_add(float dx, float dy, float mult, float &s
 // (already moved this iteration) are appended to late[] instead of summed.
 // live != nullptr: every leaf uses live coordinates.
 __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_below,
-                       const float2 *live, float4 &acc, int *late, int &nlate, int cap) {
+                       gptr<const float2> live, float4 &acc, gptr<int> late, int &nlate, int cap) {
     const int Li = a.leafpos[i];
     const int total = *a.total;
     float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f;
     int visits = 0;
     int v = 0;
     while (v < total) {
-        const float4 A = a.nodeA[v];
-        const int2 B = a.nodeB[v];
+        const float4 A = ld<float4>(a.nodeA, v);
+        const int2 B = ld<int2>(a.nodeB, v);
         ++visits;
         if (B.y >= 0) {
             const int j = B.y;
             if (j != i) {
                 if (live) {
-                    const float2 pj = live[j];
+                    const float2 pj = ld<float2>(live, j);
                     rep_add(pj.x - xi, pj.y - yi, 1.f, sx, cx, sy, cy);
                 } else if (j < late_below) {
                     if (nlate < cap) late[nlate] = j;
@@ -667,10 +667,10 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
         const int late_below = J.snapshot_leaves ? 0 : (J.all_live ? a.n : (i / a.BS) * a.BS);
         float4 acc;
         int nlate = 0;
-        const float2 pi = J.pos[i];
+        const float2 pi = ld<float2>(J.pos, i);
         visits = bh_walk(a, i, pi.x, pi.y, late_below, nullptr, acc, J.late_ids + (size_t)i * kLateCap, nlate,
                          kLateCap);
-        J.far[i] = acc;
+        st<float4>(J.far, i, acc);
         J.late_cnt[i] = nlate;
         ovf = nlate > kLateCap;
         lat = min(nlate, kLateCap);
@@ -708,8 +708,8 @@ __global__ void late_prefix_kernel(BH_KERNEL_ARGS) {
         else hi = mid;
     }
     J.late_att[i] = lo - J.rowptr[i];
-    if (end - lo > kHeavyRow) J.heavy[atomicAdd(J.nheavy, 1)] = i;
-    if (lo - J.rowptr[i] > kLateHeavyRow) J.heavy[J.n + atomicAdd(J.nheavy + 1, 1)] = i;
+    if (end - lo > kHeavyRow) J.heavy[atomicAdd((int *)J.nheavy, 1)] = i;
+    if (lo - J.rowptr[i] > kLateHeavyRow) J.heavy[J.n + atomicAdd((int *)(J.nheavy + 1), 1)] = i;
 }
 
 // Light rows: 8 lanes per row.
@@ -720,11 +720,11 @@ __global__ __launch_bounds__(256) void att_early_kernel(BH_KERNEL_ARGS) {
     if (i >= J.n) return;
     const int e0 = J.rowptr[i] + J.late_att[i], e1 = J.rowptr[i + 1];
     if (e1 - e0 > kHeavyRow) return;     // summed by att_heavy_kernel
-    const float2 pi = J.pos[i];
+    const float2 pi = ld<float2>(J.pos, i);
     const float invK = J.invK;
     float ax = 0.f, ay = 0.f;
     for (int e = e0 + sub; e < e1; e += 8) {
-        const float2 pj = J.pos[J.colidx[e]];
+        const float2 pj = ld<float2>(J.pos, J.colidx[e]);
         const float dx = pj.x - pi.x, dy = pj.y - pi.y;
         const float d = sqrtf(dx * dx + dy * dy) * invK;
         ax = fmaf(d, dx, ax);
@@ -732,7 +732,7 @@ __global__ __launch_bounds__(256) void att_early_kernel(BH_KERNEL_ARGS) {
     }
     ax = group_sum<8>(ax);
     ay = group_sum<8>(ay);
-    if (sub == 0) J.atte[i] = float2{ax, ay};
+    if (sub == 0) st<float2>(J.atte, i, float2{ax, ay});
 }
 
 // Heavy rows: one workgroup per row, reduced in a fixed order.
@@ -744,10 +744,10 @@ __global__ __launch_bounds__(256) void att_heavy_kernel(BH_KERNEL_ARGS) {
     for (int h = jb.local; h < nh; h += jb.nblocks) {
         const int i = J.heavy[h];
         const int e0 = J.rowptr[i] + J.late_att[i], e1 = J.rowptr[i + 1];
-        const float2 pi = J.pos[i];
+        const float2 pi = ld<float2>(J.pos, i);
         float ax = 0.f, ay = 0.f;
         for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
-            const float2 pj = J.pos[J.colidx[e]];
+            const float2 pj = ld<float2>(J.pos, J.colidx[e]);
             const float dx = pj.x - pi.x, dy = pj.y - pi.y;
             const float d = sqrtf(dx * dx + dy * dy) * invK;
             ax = fmaf(d, dx, ax);
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(256) void att_heavy_kernel(BH_KERNEL_ARGS) {
         }
         __syncthreads();
         if (threadIdx.x == 0)
-            J.atte[i] = float2{((wsx[0] + wsx[1]) + wsx[2]) + wsx[3], ((wsy[0] + wsy[1]) + wsy[2]) + wsy[3]};
+            st<float2>(J.atte, i, float2{((wsx[0] + wsx[1]) + wsx[2]) + wsx[3], ((wsy[0] + wsy[1]) + wsy[2]) + wsy[3]});
         __syncthreads();
     }
 }
@@ -812,12 +812,12 @@ __global__ __launch_bounds__(256) void late_fill_kernel(BH_KERNEL_ARGS) {
     const size_t base = (size_t)J.bbase[b] + J.roff[i];
     const int rs = J.rowptr[i];
     const int la = J.all_live ? J.rowptr[i + 1] - rs : J.late_att[i];
-    unsigned long long *ent = J.ent;
+    gptr<unsigned long long> ent = J.ent;
     const bool heavy = !J.all_live && la > kLateHeavyRow;   // copied by late_fill_heavy_kernel
     if (!heavy)
         for (int k = sub; k < la; k += 8) ent[base + k] = rbits | (unsigned)J.colidx[rs + k];
     const int ll = late_leaf_count(J.late_cnt[i]);
-    const int *lid = J.late_ids + (size_t)i * kLateCap;
+    gptr<const int> lid = J.late_ids + (size_t)i * kLateCap;
     for (int k = sub; k < ll; k += 8) ent[base + la + k] = rbits | 0x80000000u | (unsigned)lid[k];
 }
 
@@ -846,31 +846,115 @@ struct ChainRow {
     float2 atte;
 };
 
-__device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r, int R) {
+__device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r, int R, int E) {
     ChainRow d;
     const int i = b * J.BS + r;
-    const int E = J.bbase[b + 1] - J.bbase[b];
     d.o0 = J.roff[i];
     d.o1 = (r + 1 < R) ? J.roff[i + 1] : E;
     d.ovf = J.late_cnt[i] > kLateCap;
-    const float2 pi = J.pos[i];
+    const float2 pi = ld<float2>(J.pos, i);
     d.x = pi.x;
     d.y = pi.y;
-    d.far = J.far[i];
-    d.atte = J.all_live ? float2{0.f, 0.f} : J.atte[i];
+    d.far = ld<float4>(J.far, i);
+    d.atte = J.all_live ? float2{0.f, 0.f} : ld<float2>(J.atte, i);
     return d;
 }
 
 struct ChainShared {
-    int off[2][kMaxChainRows + 1];
-    float px[2][kMaxChainRows];
+    int off[2][kMaxChainRows + 1];    // row offsets in the batch list, by step parity
+    float px[2][kMaxChainRows];       // row positions, by step parity
     float py[2][kMaxChainRows];
-    float2 sum[kMaxChainRows];   // rows complete inside one thread's run
-    float2 cf[kChainThreads];    // first (partial) row of each thread's run
-    float2 cl[kChainThreads];    // last (partial) row of each thread's run
+    float2 sum[kMaxChainRows];        // rows complete inside one thread's run
+    float2 cf[kChainThreads];         // first (partial) row of each thread's run
+    float2 cl[kChainThreads];         // last (partial) row of each thread's run
+    int mb[16];                       // list starts of batches b .. b + 15
     double wsd[16];
     double step;
 };
+
+// A thread's run [e0, e1) of a batch list (entries ordered by row): rows
+// wholly inside the run go to sum[r], the run's first and last (cut) rows to
+// cf/cl[thread].  The first min(KE, e1 - e0) entry words and their gathered
+// live positions come in (w, xj, yj).  Terms: a moved neighbour adds the
+// attraction d * delta / K, a listed leaf the repulsion -R K^2 delta / d^2
+// (Sec. 2.2).
+template <int KE>
+__device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr<const float2> pos, int e0, int e1,
+                                        unsigned long long (&w)[KE], float (&xj)[KE], float (&yj)[KE],
+                                        const int *off, const float *px, const float *py, float2 *sum,
+                                        float2 *cf, float2 *cl, float invK, float negRK2) {
+    if (e0 >= e1) return;
+    const int tid = threadIdx.x;
+    int r = (int)(w[0] >> 32);
+    float ax = 0.f, ay = 0.f;
+    bool firstseg = true;
+    for (int base = e0; base < e1; base += KE) {
+        const int m = min(KE, e1 - base);
+        if (base != e0) {
+#pragma unroll
+            for (int q = 0; q < KE; ++q)
+                if (q < m) w[q] = src[base + q];
+#pragma unroll
+            for (int q = 0; q < KE; ++q) {
+                if (q < m) {
+                    const float2 pj = ld<float2>(pos, (int)((unsigned)w[q] & 0x7fffffffu));
+                    xj[q] = pj.x;
+                    yj[q] = pj.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KE; ++q) {
+            if (q < m) {
+                const int rq = (int)(w[q] >> 32);
+                if (rq != r) {
+                    const bool full = off[r] >= e0 && off[r + 1] <= e1;
+                    if (full) sum[r] = float2{ax, ay};
+                    else if (firstseg) cf[tid] = float2{ax, ay};
+                    else cl[tid] = float2{ax, ay};
+                    firstseg = false;
+                    ax = ay = 0.f;
+                    r = rq;
+                }
+                const float dx = xj[q] - px[r], dy = yj[q] - py[r];
+                if (((unsigned)w[q] & 0x80000000u) == 0u) {
+                    const float d = sqrtf(dx * dx + dy * dy) * invK;
+                    ax = fmaf(d, dx, ax);
+                    ay = fmaf(d, dy, ay);
+                } else {
+                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+                    const float inv = __builtin_amdgcn_rcpf(d2) * negRK2;
+                    ax = fmaf(dx, inv, ax);
+                    ay = fmaf(dy, inv, ay);
+                }
+            }
+        }
+    }
+    const bool full = off[r] >= e0 && off[r + 1] <= e1;
+    if (full) sum[r] = float2{ax, ay};
+    else if (firstseg) cf[tid] = float2{ax, ay};
+    else cl[tid] = float2{ax, ay};
+}
+
+// A row's total over its entries [o0, o1) from the runs' results, runs of
+// `chunk` entries, added in thread order.
+__device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, const float2 *sum, const float2 *cf,
+                                            const float2 *cl) {
+    float2 sm{0.f, 0.f};
+    if (o1 > o0) {
+        const int t0 = o0 / chunk, t1 = (o1 - 1) / chunk;
+        if (t0 == t1) {
+            sm = sum[r];
+        } else {
+            sm = (o0 == t0 * chunk) ? cf[t0] : cl[t0];
+            for (int t = t0 + 1; t <= t1; ++t) {
+                sm.x += cf[t].x;
+                sm.y += cf[t].y;
+            }
+        }
+    }
+    return sm;
+}
 
 // The minibatch chain: one workgroup per job walks its batches in order.
 // Per step b:
@@ -882,8 +966,10 @@ struct ChainShared {
 //     thread order; early attraction and the far field are added, and the
 //     thread owning the row moves it (Alg. 2 update loop; Jacobi within the
 //     batch because every gather of the batch precedes the barrier).
-// The step length of iteration k is step0 times decay k times (the host uses
-// the same product), k is read from and advanced in device memory.
+// The list starts of the next 16 batches are kept in LDS, so no step waits on
+// a dependent load of them.  The step length of iteration k is step0 times
+// decay k times (the host uses the same product), k is read from and advanced
+// in device memory.
 __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     __shared__ ChainShared S;
@@ -892,7 +978,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
     const int first = J.first_batch, last = J.last_batch;
     const float invK = J.invK, negRK2 = J.negRK2;
     const WalkArgs wa = walk_args(J);
-    constexpr int RPT = kMaxChainRows / kChainThreads;   // rows per thread
+    static_assert(kMaxChainRows == kChainThreads, "one row per thread");
     const size_t entmax = J.ent_cap - 1;
     const int k_it = J.kiter[0];
     if (tid == 0) {
@@ -900,34 +986,40 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
         for (int t = 0; t < k_it; ++t) st *= J.decay;
         S.step = st;
     }
+    auto nrows = [&](int b) { return min(BS, n - b * BS); };
+    auto run_of = [&](int E, int &e0, int &e1) {
+        const int chunk = max(1, (E + kChainThreads - 1) / kChainThreads);
+        e0 = min(tid * chunk, E);
+        e1 = min(e0 + chunk, E);
+        return chunk;
+    };
+    if (tid < 16) {
+        const int q = first + tid;
+        if (q <= J.nb) S.mb[q & 15] = J.bbase[q];
+    }
+    __syncthreads();
 
-    ChainRow rowd[RPT];
+    ChainRow rowd;
     unsigned long long pe[kEnt];
     auto fetch_regs = [&](int b) {
-        const int R = min(BS, n - b * BS);
-#pragma unroll
-        for (int k = 0; k < RPT; ++k)
-            if (tid + k * kChainThreads < R) rowd[k] = chain_row(J, b, tid + k * kChainThreads, R);
-        const int E = J.bbase[b + 1] - J.bbase[b];
-        const int chunk = (E + kChainThreads - 1) / kChainThreads;
-        const int e0 = min(tid * chunk, E), e1 = min(e0 + chunk, E);
-        const size_t gb = (size_t)J.bbase[b];
+        const int R = nrows(b);
+        const int E = S.mb[(b + 1) & 15] - S.mb[b & 15];
+        if (tid < R) rowd = chain_row(J, b, tid, R, E);
+        int e0, e1;
+        run_of(E, e0, e1);
+        const size_t gb = (size_t)S.mb[b & 15];
 #pragma unroll
         for (int q = 0; q < kEnt; ++q)
             if (e0 + q < e1) pe[q] = J.ent[min(gb + (size_t)(e0 + q), entmax)];
     };
     auto fetch_lds = [&](int b, int slot) {
-        const int R = min(BS, n - b * BS);
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int r = tid + k * kChainThreads;
-            if (r < R) {
-                S.off[slot][r] = rowd[k].o0;
-                S.px[slot][r] = rowd[k].x;
-                S.py[slot][r] = rowd[k].y;
-            }
+        const int R = nrows(b);
+        if (tid < R) {
+            S.off[slot][tid] = rowd.o0;
+            S.px[slot][tid] = rowd.x;
+            S.py[slot][tid] = rowd.y;
         }
-        if (tid == 0) S.off[slot][R] = J.bbase[b + 1] - J.bbase[b];
+        if (tid == 0) S.off[slot][R] = S.mb[(b + 1) & 15] - S.mb[b & 15];
     };
     fetch_regs(first);
     fetch_lds(first, first & 1);
@@ -938,13 +1030,11 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
     unsigned long long bad = 0;
     for (int b = first; b <= last; ++b) {
         const int slot = b & 1;
-        const int R = min(BS, n - b * BS);
+        const int R = nrows(b);
         const int E = S.off[slot][R];
-        const int chunk = (E + kChainThreads - 1) / kChainThreads;
-        const int e0 = min(tid * chunk, E), e1 = min(e0 + chunk, E);
-        ChainRow cur[RPT];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) cur[k] = rowd[k];
+        int e0, e1;
+        const int chunk = run_of(E, e0, e1);
+        const ChainRow cur = rowd;
         unsigned long long ce[kEnt];
 #pragma unroll
         for (int q = 0; q < kEnt; ++q) ce[q] = pe[q];
@@ -958,112 +1048,49 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
             xj[q] = 0.f;
             yj[q] = 0.f;
             if (q < m0) {
-                const float2 pj = J.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
+                const float2 pj = ld<float2>(J.pos, (int)((unsigned)ce[q] & 0x7fffffffu));
                 xj[q] = pj.x;
                 yj[q] = pj.y;
             }
         }
-        // next step's data (clamped to the last batch on the final step)
+        // next step's data (clamped to the last batch on the final step),
+        // and the list start of batch b + 16
         fetch_regs(min(b + 1, last));
+        int meta = 0;
+        if (tid == 0 && b + 16 <= J.nb) meta = J.bbase[b + 16];
 
-        if (e0 < e1) {
-            const unsigned long long *src = J.ent + J.bbase[b];
-            int r = (int)(ce[0] >> 32);
-            float ax = 0.f, ay = 0.f;
-            bool firstseg = true;
-            for (int base = e0; base < e1; base += kEnt) {
-                const int m = min(kEnt, e1 - base);
-                if (base != e0) {
-#pragma unroll
-                    for (int q = 0; q < kEnt; ++q)
-                        if (q < m) ce[q] = src[base + q];
-#pragma unroll
-                    for (int q = 0; q < kEnt; ++q) {
-                        if (q < m) {
-                            const float2 pj = J.pos[(int)((unsigned)ce[q] & 0x7fffffffu)];
-                            xj[q] = pj.x;
-                            yj[q] = pj.y;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kEnt; ++q) {
-                    if (q < m) {
-                        const int rq = (int)(ce[q] >> 32);
-                        if (rq != r) {
-                            const bool full = S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1;
-                            if (full) S.sum[r] = float2{ax, ay};
-                            else if (firstseg) S.cf[tid] = float2{ax, ay};
-                            else S.cl[tid] = float2{ax, ay};
-                            firstseg = false;
-                            ax = ay = 0.f;
-                            r = rq;
-                        }
-                        const float dx = xj[q] - S.px[slot][r], dy = yj[q] - S.py[slot][r];
-                        if (((unsigned)ce[q] & 0x80000000u) == 0u) {
-                            // moved neighbour: attraction d * delta / K
-                            const float d = sqrtf(dx * dx + dy * dy) * invK;
-                            ax = fmaf(d, dx, ax);
-                            ay = fmaf(d, dy, ay);
-                        } else {
-                            // moved leaf: repulsion -R K^2 delta / d^2
-                            const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-                            const float inv = __builtin_amdgcn_rcpf(d2) * negRK2;
-                            ax = fmaf(dx, inv, ax);
-                            ay = fmaf(dy, inv, ay);
-                        }
-                    }
-                }
-            }
-            const bool full = S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1;
-            if (full) S.sum[r] = float2{ax, ay};
-            else if (firstseg) S.cf[tid] = float2{ax, ay};
-            else S.cl[tid] = float2{ax, ay};
-        }
+        run_sum<kEnt>(J.ent + S.mb[b & 15], J.pos, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot],
+                      S.sum, S.cf, S.cl, invK, negRK2);
         __syncthreads();
+        if (tid == 0) S.mb[b & 15] = meta;   // the slot of batch b now holds batch b + 16
 
-        // complete my rows, add early attraction and far field, move them
+        // complete the row of batch b, add early attraction and far field,
+        // move it
         const bool stop = (b == J.stop_batch);
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int r = tid + k * kChainThreads;
-            if (r >= R) continue;
-            const int o0 = cur[k].o0, o1 = cur[k].o1;
-            float2 sm{0.f, 0.f};
-            if (o1 > o0) {
-                const int t0 = o0 / chunk, t1 = (o1 - 1) / chunk;
-                if (t0 == t1) {
-                    sm = S.sum[r];
+        if (tid < R) {
+            const float2 sm = row_total(tid, cur.o0, cur.o1, chunk, S.sum, S.cf, S.cl);
+            const int i = b * BS + tid;
+            float4 fr = cur.far;
+            if (cur.ovf) {
+                int dummy = 0;
+                (void)bh_walk(wa, i, cur.x, cur.y, 0, J.pos, fr, nullptr, dummy, 0);
+            }
+            const float fx = (sm.x + cur.atte.x) + negRK2 * (fr.x - fr.z);
+            const float fy = (sm.y + cur.atte.y) + negRK2 * (fr.y - fr.w);
+            if (stop) {
+                J.fout[2 * tid] = (double)fx;
+                J.fout[2 * tid + 1] = (double)fy;
+            } else {
+                const double f2 = (double)fx * fx + (double)fy * fy;
+                if (!isfinite(f2)) {
+                    ++bad;
                 } else {
-                    sm = (o0 == t0 * chunk) ? S.cf[t0] : S.cl[t0];
-                    for (int t = t0 + 1; t <= t1; ++t) {
-                        sm.x += S.cf[t].x;
-                        sm.y += S.cf[t].y;
+                    e_iter += f2;
+                    if (f2 > 0.0) {
+                        const float sc = step / sqrtf(fx * fx + fy * fy);
+                        st<float2>(J.pos, i, float2{cur.x + sc * fx, cur.y + sc * fy});
                     }
                 }
-            }
-            const int i = b * BS + r;
-            float4 fr = cur[k].far;
-            if (cur[k].ovf) {
-                int dummy = 0;
-                (void)bh_walk(wa, i, cur[k].x, cur[k].y, 0, J.pos, fr, nullptr, dummy, 0);
-            }
-            const float fx = (sm.x + cur[k].atte.x) + negRK2 * (fr.x - fr.z);
-            const float fy = (sm.y + cur[k].atte.y) + negRK2 * (fr.y - fr.w);
-            if (stop) {
-                J.fout[2 * r] = (double)fx;
-                J.fout[2 * r + 1] = (double)fy;
-                continue;
-            }
-            const double f2 = (double)fx * fx + (double)fy * fy;
-            if (!isfinite(f2)) {
-                ++bad;
-                continue;
-            }
-            e_iter += f2;
-            if (f2 > 0.0) {
-                const float sc = step / sqrtf(fx * fx + fy * fy);
-                J.pos[i] = float2{cur[k].x + sc * fx, cur[k].y + sc * fy};
             }
         }
         if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1);
@@ -1159,57 +1186,57 @@ void bh_engine_destroy(BHEngine *e) {
 int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     BHBuffers &h = g->bh;
     std::memset(J, 0, sizeof *J);
-    J->n = g->n;
-    J->BS = g->p.batch_size;
-    J->nb = g->nb;
-    J->tiles = (g->n + kSortTile - 1) / kSortTile;
-    J->sblocks = (g->n + kScanTile - 1) / kScanTile;
-    J->theta2 = (float)(g->p.theta * g->p.theta);
-    J->negRK2 = (float)(-g->p.R * g->p.K * g->p.K);
-    J->invK = (float)(1.0 / g->p.K);
-    J->snapshot_leaves = (g->p.flags & BL_BH_SNAPSHOT_LEAVES) ? 1 : 0;
-    J->all_live = spec.all_live;
-    J->first_batch = spec.first_batch;
-    J->last_batch = spec.last_batch;
-    J->stop_batch = spec.stop_batch;
-    J->step0 = g->p.step0;
-    J->decay = g->p.step_decay;
-    J->kiter = h.kiter;
-    J->rowptr = g->rowptr;
-    J->colidx = g->colidx;
-    J->pos = (float2 *)g->x;
-    J->src = spec.src ? spec.src : (const float2 *)g->x;
-    J->bbox = h.bbox;
-    J->bbox_part = h.bbox_part;
-    J->ticket = (unsigned *)(h.bbox + 8);
-    J->key0 = h.key[0];
-    J->key1 = h.key[1];
-    J->val0 = h.val[0];
-    J->val1 = h.val[1];
-    J->hist = h.hist;
-    J->mask = h.mask;
-    J->cellcnt = h.cellcnt;
-    J->scan_part = h.scan_part;
-    J->pdd = h.pdd;
-    J->pdd_part = h.pdd_part;
-    J->nodeA = h.nodeA;
-    J->nodeB = h.nodeB;
-    J->leafpos = h.leafpos;
-    J->nnodes = h.nnodes;
-    J->far = h.far;
-    J->late_cnt = h.late_cnt;
-    J->late_ids = h.late_ids;
-    J->late_att = h.late_att;
-    J->heavy = h.heavy;
-    J->nheavy = h.nheavy;
-    J->atte = h.atte;
-    J->roff = h.roff;
-    J->bbase = h.bbase;
-    J->ent = h.ent;
-    J->ent_cap = (size_t)g->nnz + (size_t)g->n * kLateCap;
-    J->energy = g->energy;
-    J->fout = g->fout;
-    J->ctr = g->counters;
+    J->n = (decltype(J->n))(g->n);
+    J->BS = (decltype(J->BS))(g->p.batch_size);
+    J->nb = (decltype(J->nb))(g->nb);
+    J->tiles = (decltype(J->tiles))((g->n + kSortTile - 1) / kSortTile);
+    J->sblocks = (decltype(J->sblocks))((g->n + kScanTile - 1) / kScanTile);
+    J->theta2 = (decltype(J->theta2))((float)(g->p.theta * g->p.theta));
+    J->negRK2 = (decltype(J->negRK2))((float)(-g->p.R * g->p.K * g->p.K));
+    J->invK = (decltype(J->invK))((float)(1.0 / g->p.K));
+    J->snapshot_leaves = (decltype(J->snapshot_leaves))((g->p.flags & BL_BH_SNAPSHOT_LEAVES) ? 1 : 0);
+    J->all_live = (decltype(J->all_live))(spec.all_live);
+    J->first_batch = (decltype(J->first_batch))(spec.first_batch);
+    J->last_batch = (decltype(J->last_batch))(spec.last_batch);
+    J->stop_batch = (decltype(J->stop_batch))(spec.stop_batch);
+    J->step0 = (decltype(J->step0))(g->p.step0);
+    J->decay = (decltype(J->decay))(g->p.step_decay);
+    J->kiter = (decltype(J->kiter))(h.kiter);
+    J->rowptr = (decltype(J->rowptr))(g->rowptr);
+    J->colidx = (decltype(J->colidx))(g->colidx);
+    J->pos = (decltype(J->pos))((float2 *)g->x);
+    J->src = (decltype(J->src))(spec.src ? spec.src : (const float2 *)g->x);
+    J->bbox = (decltype(J->bbox))(h.bbox);
+    J->bbox_part = (decltype(J->bbox_part))(h.bbox_part);
+    J->ticket = (decltype(J->ticket))((unsigned *)(h.bbox + 8));
+    J->key0 = (decltype(J->key0))(h.key[0]);
+    J->key1 = (decltype(J->key1))(h.key[1]);
+    J->val0 = (decltype(J->val0))(h.val[0]);
+    J->val1 = (decltype(J->val1))(h.val[1]);
+    J->hist = (decltype(J->hist))(h.hist);
+    J->mask = (decltype(J->mask))(h.mask);
+    J->cellcnt = (decltype(J->cellcnt))(h.cellcnt);
+    J->scan_part = (decltype(J->scan_part))(h.scan_part);
+    J->pdd = (decltype(J->pdd))(h.pdd);
+    J->pdd_part = (decltype(J->pdd_part))(h.pdd_part);
+    J->nodeA = (decltype(J->nodeA))(h.nodeA);
+    J->nodeB = (decltype(J->nodeB))(h.nodeB);
+    J->leafpos = (decltype(J->leafpos))(h.leafpos);
+    J->nnodes = (decltype(J->nnodes))(h.nnodes);
+    J->far = (decltype(J->far))(h.far);
+    J->late_cnt = (decltype(J->late_cnt))(h.late_cnt);
+    J->late_ids = (decltype(J->late_ids))(h.late_ids);
+    J->late_att = (decltype(J->late_att))(h.late_att);
+    J->heavy = (decltype(J->heavy))(h.heavy);
+    J->nheavy = (decltype(J->nheavy))(h.nheavy);
+    J->atte = (decltype(J->atte))(h.atte);
+    J->roff = (decltype(J->roff))(h.roff);
+    J->bbase = (decltype(J->bbase))(h.bbase);
+    J->ent = (decltype(J->ent))(h.ent);
+    J->ent_cap = (decltype(J->ent_cap))((size_t)g->nnz + (size_t)g->n * kLateCap);
+    J->energy = (decltype(J->energy))(g->energy);
+    J->fout = (decltype(J->fout))(g->fout);
+    J->ctr = (decltype(J->ctr))(g->counters);
     return BL_OK;
 }
 

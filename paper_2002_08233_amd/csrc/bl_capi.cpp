@@ -59,8 +59,8 @@ int check_params(const bl_params *p) {
         return fail(BL_E_INVAL, "unknown precision %d", p->precision);
     if (p->mode == BL_BH && p->precision == BL_FP64)
         return fail(BL_E_INVAL, "FP64 precision is provided for exact mode only");
-    if (p->mode == BL_BH && p->batch_size > 2048)
-        return fail(BL_E_INVAL, "Barnes-Hut mode supports batch sizes up to 2048");
+    if (p->mode == BL_BH && p->batch_size > 1024)
+        return fail(BL_E_INVAL, "Barnes-Hut mode supports batch sizes up to 1024");
     if (p->mode == BL_BH && !p->repulse_adjacent)
         return fail(BL_E_INVAL, "Barnes-Hut mode repels all pairs (repulse_adjacent must be 1)");
     if (!(p->step0 > 0) || !std::isfinite(p->step0)) return fail(BL_E_INVAL, "step0 must be > 0");

@@ -7,6 +7,41 @@ namespace bl {
 
 constexpr int kWave = 64;
 
+// Pointer to device global memory.  Kernels that read pointers out of a
+// descriptor in memory would otherwise see generic pointers and emit flat
+// instructions, which also count against the LDS wait counter (so every LDS
+// wait would wait for the gathers in flight too).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <int N>
+struct RawBits;
+template <>
+struct RawBits<4> {
+    using type = unsigned;
+};
+template <>
+struct RawBits<8> {
+    using type = unsigned long long;
+};
+template <>
+struct RawBits<16> {
+    using type = unsigned __attribute__((ext_vector_type(4)));
+};
+
+// Element i of a global array of a vector type (HIP's vector types have no
+// constructors from other address spaces, so they move as raw bits).
+template <typename T>
+__device__ __forceinline__ T ld(gptr<const T> p, size_t i) {
+    using B = typename RawBits<sizeof(T)>::type;
+    return __builtin_bit_cast(T, ((gptr<const B>)p)[i]);
+}
+template <typename T>
+__device__ __forceinline__ void st(gptr<T> p, size_t i, T v) {
+    using B = typename RawBits<sizeof(T)>::type;
+    ((gptr<B>)p)[i] = __builtin_bit_cast(B, v);
+}
+
 // Kahan-compensated FP32 accumulation: (s, c) represents s - c.
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     float y = v - c;
