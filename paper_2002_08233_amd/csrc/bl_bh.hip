@@ -46,7 +46,7 @@ constexpr int kChainThreads = 1024;
 constexpr int kHeavyRow = 256;        // early entries above which a whole workgroup sums the row
 constexpr int kLateHeavyRow = 256;    // moved neighbours above which a whole workgroup copies the row
 constexpr int kMaxChainRows = 1024;   // batch-size limit of the Barnes-Hut chain
-constexpr int kEnt = 8;               // late entries per thread per pass (held in registers)
+constexpr int kEnt = 4;               // late entries per thread per pass (held in registers)
 
 // Device descriptor of one job (all pointers are device memory).
 struct BHJob {
@@ -865,8 +865,10 @@ struct ChainShared {
     float px[2][kMaxChainRows];       // row positions, by step parity
     float py[2][kMaxChainRows];
     float2 sum[kMaxChainRows];        // rows complete inside one thread's run
-    float2 cf[kChainThreads];         // first (partial) row of each thread's run
+    float2 scan[kChainThreads];       // scanned first (partial) rows of the threads' runs
     float2 cl[kChainThreads];         // last (partial) row of each thread's run
+    float2 wv[kChainThreads / kWave]; // carry scan: per-wave totals and keys
+    int wk[kChainThreads / kWave], wkf[kChainThreads / kWave];
     int mb[16];                       // list starts of batches b .. b + 15
     double wsd[16];
     double step;
@@ -882,7 +884,8 @@ template <int KE>
 __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr<const float2> pos, int e0, int e1,
                                         unsigned long long (&w)[KE], float (&xj)[KE], float (&yj)[KE],
                                         const int *off, const float *px, const float *py, float2 *sum,
-                                        float2 *cf, float2 *cl, float invK, float negRK2) {
+                                        float2 &first, float2 *cl, float invK, float negRK2) {
+    first = float2{0.f, 0.f};
     if (e0 >= e1) return;
     const int tid = threadIdx.x;
     int r = (int)(w[0] >> 32);
@@ -910,7 +913,7 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr
                 if (rq != r) {
                     const bool full = off[r] >= e0 && off[r + 1] <= e1;
                     if (full) sum[r] = float2{ax, ay};
-                    else if (firstseg) cf[tid] = float2{ax, ay};
+                    else if (firstseg) first = float2{ax, ay};
                     else cl[tid] = float2{ax, ay};
                     firstseg = false;
                     ax = ay = 0.f;
@@ -932,13 +935,51 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr
     }
     const bool full = off[r] >= e0 && off[r + 1] <= e1;
     if (full) sum[r] = float2{ax, ay};
-    else if (firstseg) cf[tid] = float2{ax, ay};
+    else if (firstseg) first = float2{ax, ay};
     else cl[tid] = float2{ax, ay};
 }
 
+// Sums of the runs' first partial rows over consecutive threads that start
+// in the same row (segmented inclusive scan in thread order: wave
+// shuffles, then the carries of earlier waves).  key: the row of the
+// thread's first entry (unique per thread when it has none); v: its first
+// partial row (0 when that row is complete inside the run).  Writes scan[t];
+// all threads call it, it holds one barrier.
+__device__ __forceinline__ void carry_scan(float2 v, int key, float2 *scan, float2 *wv, int *wk, int *wkf) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const float ux = __shfl_up(v.x, d, kWave), uy = __shfl_up(v.y, d, kWave);
+        const int uk = __shfl_up(key, d, kWave);
+        if (lane >= d && uk == key) {
+            v.x += ux;
+            v.y += uy;
+        }
+    }
+    if (lane == kWave - 1) {
+        wv[w] = v;
+        wk[w] = key;
+    }
+    if (lane == 0) wkf[w] = key;
+    __syncthreads();
+    const int K = wkf[w];
+    if (key == K) {
+        float2 c{0.f, 0.f};
+        for (int u = w - 1; u >= 0 && wk[u] == K; --u) {
+            c.x += wv[u].x;
+            c.y += wv[u].y;
+            if (wkf[u] != K) break;
+        }
+        v.x += c.x;
+        v.y += c.y;
+    }
+    scan[tid] = v;
+}
+
 // A row's total over its entries [o0, o1) from the runs' results, runs of
-// `chunk` entries, added in thread order.
-__device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, const float2 *sum, const float2 *cf,
+// `chunk` entries: one run's sum, or the part in the run it starts in plus
+// the scanned first parts of the following runs.
+__device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, const float2 *sum, const float2 *scan,
                                             const float2 *cl) {
     float2 sm{0.f, 0.f};
     if (o1 > o0) {
@@ -946,10 +987,10 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
         if (t0 == t1) {
             sm = sum[r];
         } else {
-            sm = (o0 == t0 * chunk) ? cf[t0] : cl[t0];
-            for (int t = t0 + 1; t <= t1; ++t) {
-                sm.x += cf[t].x;
-                sm.y += cf[t].y;
+            sm = scan[t1];
+            if (o0 != t0 * chunk) {
+                sm.x = cl[t0].x + sm.x;
+                sm.y = cl[t0].y + sm.y;
             }
         }
     }
@@ -1059,8 +1100,11 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
         int meta = 0;
         if (tid == 0 && b + 16 <= J.nb) meta = J.bbase[b + 16];
 
+        float2 firstp;
+        const int key0 = e0 < e1 ? (int)(ce[0] >> 32) : -1 - tid;   // row of the run's first entry
         run_sum<kEnt>(J.ent + S.mb[b & 15], J.pos, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot],
-                      S.sum, S.cf, S.cl, invK, negRK2);
+                      S.sum, firstp, S.cl, invK, negRK2);
+        carry_scan(firstp, key0, S.scan, S.wv, S.wk, S.wkf);
         __syncthreads();
         if (tid == 0) S.mb[b & 15] = meta;   // the slot of batch b now holds batch b + 16
 
@@ -1068,7 +1112,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
         // move it
         const bool stop = (b == J.stop_batch);
         if (tid < R) {
-            const float2 sm = row_total(tid, cur.o0, cur.o1, chunk, S.sum, S.cf, S.cl);
+            const float2 sm = row_total(tid, cur.o0, cur.o1, chunk, S.sum, S.scan, S.cl);
             const int i = b * BS + tid;
             float4 fr = cur.far;
             if (cur.ovf) {
