@@ -46,7 +46,7 @@ constexpr int kChainThreads = 1024;
 constexpr int kHeavyRow = 256;        // early entries above which a whole workgroup sums the row
 constexpr int kLateHeavyRow = 256;    // moved neighbours above which a whole workgroup copies the row
 constexpr int kMaxChainRows = 1024;   // batch-size limit of the Barnes-Hut chain
-constexpr int kEnt = 4;               // late entries per thread per pass (held in registers)
+constexpr int kEnt = 3;               // late entries per thread per pass (held in registers)
 
 // Device descriptor of one job (all pointers are device memory).
 struct BHJob {
