@@ -865,7 +865,8 @@ struct ChainShared {
     float px[2][kMaxChainRows];       // row positions, by step parity
     float py[2][kMaxChainRows];
     float2 sum[kMaxChainRows];        // rows complete inside one thread's run
-    float2 scan[kChainThreads];       // scanned first (partial) rows of the threads' runs
+    float2 scan[kChainThreads];       // first (partial) rows of the threads' runs, scanned within waves
+    int skey[kChainThreads];          // their rows
     float2 cl[kChainThreads];         // last (partial) row of each thread's run
     float2 wv[kChainThreads / kWave]; // carry scan: per-wave totals and keys
     int wk[kChainThreads / kWave], wkf[kChainThreads / kWave];
@@ -940,12 +941,14 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr
 }
 
 // Sums of the runs' first partial rows over consecutive threads that start
-// in the same row (segmented inclusive scan in thread order: wave
-// shuffles, then the carries of earlier waves).  key: the row of the
+// in the same row (a segmented inclusive scan in thread order), in two
+// halves around the barrier that follows: before it, each wave scans its
+// threads by shuffles and publishes its total and first/last keys; after
+// it, scan_at(t) adds the carry of earlier waves.  key: the row of the
 // thread's first entry (unique per thread when it has none); v: its first
-// partial row (0 when that row is complete inside the run).  Writes scan[t];
-// all threads call it, it holds one barrier.
-__device__ __forceinline__ void carry_scan(float2 v, int key, float2 *scan, float2 *wv, int *wk, int *wkf) {
+// partial row (0 when that row is complete inside the run).
+__device__ __forceinline__ void carry_scan_wave(float2 v, int key, float2 *loc, int *keys, float2 *wv, int *wk,
+                                                int *wkf) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -956,14 +959,21 @@ __device__ __forceinline__ void carry_scan(float2 v, int key, float2 *scan, floa
             v.y += uy;
         }
     }
+    loc[tid] = v;
+    keys[tid] = key;
     if (lane == kWave - 1) {
         wv[w] = v;
         wk[w] = key;
     }
     if (lane == 0) wkf[w] = key;
-    __syncthreads();
+}
+
+__device__ __forceinline__ float2 scan_at(int t, const float2 *loc, const int *keys, const float2 *wv, const int *wk,
+                                          const int *wkf) {
+    const int w = t / kWave;
+    float2 v = loc[t];
     const int K = wkf[w];
-    if (key == K) {
+    if (keys[t] == K) {
         float2 c{0.f, 0.f};
         for (int u = w - 1; u >= 0 && wk[u] == K; --u) {
             c.x += wv[u].x;
@@ -973,21 +983,22 @@ __device__ __forceinline__ void carry_scan(float2 v, int key, float2 *scan, floa
         v.x += c.x;
         v.y += c.y;
     }
-    scan[tid] = v;
+    return v;
 }
 
 // A row's total over its entries [o0, o1) from the runs' results, runs of
 // `chunk` entries: one run's sum, or the part in the run it starts in plus
 // the scanned first parts of the following runs.
-__device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, const float2 *sum, const float2 *scan,
-                                            const float2 *cl) {
+__device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, const float2 *sum, const float2 *cl,
+                                            const float2 *loc, const int *keys, const float2 *wv, const int *wk,
+                                            const int *wkf) {
     float2 sm{0.f, 0.f};
     if (o1 > o0) {
         const int t0 = o0 / chunk, t1 = (o1 - 1) / chunk;
         if (t0 == t1) {
             sm = sum[r];
         } else {
-            sm = scan[t1];
+            sm = scan_at(t1, loc, keys, wv, wk, wkf);
             if (o0 != t0 * chunk) {
                 sm.x = cl[t0].x + sm.x;
                 sm.y = cl[t0].y + sm.y;
@@ -1104,7 +1115,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
         const int key0 = e0 < e1 ? (int)(ce[0] >> 32) : -1 - tid;   // row of the run's first entry
         run_sum<kEnt>(J.ent + S.mb[b & 15], J.pos, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot],
                       S.sum, firstp, S.cl, invK, negRK2);
-        carry_scan(firstp, key0, S.scan, S.wv, S.wk, S.wkf);
+        carry_scan_wave(firstp, key0, S.scan, S.skey, S.wv, S.wk, S.wkf);
         __syncthreads();
         if (tid == 0) S.mb[b & 15] = meta;   // the slot of batch b now holds batch b + 16
 
@@ -1112,7 +1123,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
         // move it
         const bool stop = (b == J.stop_batch);
         if (tid < R) {
-            const float2 sm = row_total(tid, cur.o0, cur.o1, chunk, S.sum, S.scan, S.cl);
+            const float2 sm = row_total(tid, cur.o0, cur.o1, chunk, S.sum, S.cl, S.scan, S.skey, S.wv, S.wk, S.wkf);
             const int i = b * BS + tid;
             float4 fr = cur.far;
             if (cur.ovf) {
