@@ -47,6 +47,14 @@ constexpr int kHeavyRow = 256;        // early entries above which a whole workg
 constexpr int kLateHeavyRow = 256;    // moved neighbours above which a whole workgroup copies the row
 constexpr int kMaxChainRows = 1024;   // batch-size limit of the Barnes-Hut chain
 constexpr int kEnt = 3;               // late entries per thread per pass (held in registers)
+// An iteration's chain runs in up to kMaxSegments launches (one per
+// kSegBatches batches).  Before the launch of a segment, a full-chip kernel
+// sums, for every row of the segment, the late entries that refer to
+// vertices of earlier segments ("old": all moved, and final, by then); the
+// chain itself gathers only the entries that refer to its own segment.
+constexpr int kMaxSegments = 16;
+constexpr int kSegBatches = 16;
+constexpr int kEntH = 8;              // old entries per thread per pass in the segment kernel
 
 // Device descriptor of one job (all pointers are device memory).
 struct BHJob {
@@ -55,6 +63,7 @@ struct BHJob {
     int snapshot_leaves;        // leaves use the snapshot (no late lists)
     int all_live;               // one-shot force call: every leaf and neighbour is live
     int first_batch, last_batch, stop_batch;
+    int nseg;                   // chain segments per iteration (1: no old part)
     double step0, decay;
     gptr<int> kiter;            // [2]: current iteration, first iteration of the run
     gptr<const int> rowptr, colidx;
@@ -71,9 +80,10 @@ struct BHJob {
     gptr<int2> nodeB;
     gptr<int> leafpos, nnodes;
     gptr<float4> far;
-    gptr<int> late_cnt, late_ids, late_att, heavy, nheavy;
+    gptr<int> late_cnt, late_ids, late_att, old_att, heavy, nheavy;
     gptr<float2> atte;
-    gptr<int> roff, bbase;
+    gptr<int> roff, roff_old, bbase, bold;
+    gptr<float2> oldsum;        // per vertex: sum of its old entries
     gptr<unsigned long long> ent;
     size_t ent_cap;
     gptr<double> energy;        // one value per iteration of the run
@@ -690,6 +700,15 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
 // so their attraction terms (Sec. 2.2, a = 2: d * delta / K) can be summed
 // for all vertices at once from the snapshot.  Sorted CSR rows make the moved
 // ("late") neighbours a prefix of each row; its length is fixed per job.
+// Batches per chain segment, and the first vertex of batch b's segment:
+// entries of batch b that refer to vertices below it are "old".
+__device__ __forceinline__ int seg_len(const BHJob &J) { return (J.nb + J.nseg - 1) / J.nseg; }
+__device__ __forceinline__ int old_limit(const BHJob &J, int b) {
+    if (J.nseg <= 1) return 0;
+    const int L = seg_len(J);
+    return (b / L) * L * J.BS;
+}
+
 __global__ void heavy_reset_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     if (threadIdx.x < 2) J.nheavy[threadIdx.x] = 0;
@@ -708,6 +727,14 @@ __global__ void late_prefix_kernel(BH_KERNEL_ARGS) {
         else hi = mid;
     }
     J.late_att[i] = lo - J.rowptr[i];
+    const int olim = old_limit(J, i / J.BS);
+    int ol = J.rowptr[i], oh = lo;
+    while (ol < oh) {
+        const int mid = (ol + oh) >> 1;
+        if (J.colidx[mid] < olim) ol = mid + 1;
+        else oh = mid;
+    }
+    J.old_att[i] = ol - J.rowptr[i];
     if (end - lo > kHeavyRow) J.heavy[atomicAdd((int *)J.nheavy, 1)] = i;
     if (lo - J.rowptr[i] > kLateHeavyRow) J.heavy[J.n + atomicAdd((int *)(J.nheavy + 1), 1)] = i;
 }
@@ -767,58 +794,104 @@ __global__ __launch_bounds__(256) void att_heavy_kernel(BH_KERNEL_ARGS) {
 }
 
 // ------------------------------------------------------- late entry lists
+
 // Everything a minibatch step needs that does not depend on moves is laid out
 // before the chain starts: per batch, the "late" entries -- moved neighbours
 // (the CSR prefix) and listed moved leaves -- of all its rows, row by row, as
 // (row in batch << 32 | vertex) words, plus each row's offset in that list.
 __device__ __forceinline__ int late_leaf_count(int lc) { return lc > kLateCap ? 0 : lc; }
 
-// Per batch: entry counts of its rows -> exclusive offsets within the batch.
+// Per batch: the list holds first the old entries of all its rows, then the
+// others, each part row by row.  Counts of each row -> exclusive offsets
+// within each part; bold[b] = old part length, bbase[b] = list length (a scan
+// turns bbase into list starts).
 __global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     __shared__ int ws[16];
     const int b = jb.local, BS = J.BS;
     const int R = min(BS, J.n - b * BS);
-    int carry = 0;
+    const int olim = old_limit(J, b);
+    int carry_o = 0, carry_r = 0;
     for (int r0 = 0; r0 < R; r0 += 1024) {
         const int r = r0 + (int)threadIdx.x;
-        int c = 0;
+        int co = 0, cr = 0;
         if (r < R) {
             const int i = b * BS + r;
             const int la = J.all_live ? J.rowptr[i + 1] - J.rowptr[i] : J.late_att[i];
-            c = la + late_leaf_count(J.late_cnt[i]);
+            const int oa = J.all_live ? 0 : J.old_att[i];
+            const int ll = late_leaf_count(J.late_cnt[i]);
+            gptr<const int> lid = J.late_ids + (size_t)i * kLateCap;
+            int ol = 0;
+            for (int k = 0; k < ll; ++k) ol += lid[k] < olim ? 1 : 0;
+            co = oa + ol;
+            cr = (la - oa) + (ll - ol);
         }
-        int tot;
-        const int off = block_excl_scan(c, ws, &tot);
-        if (r < R) J.roff[b * BS + r] = carry + off;
-        carry += tot;
+        int tot_o, tot_r;
+        const int off_o = block_excl_scan(co, ws, &tot_o);
+        const int off_r = block_excl_scan(cr, ws, &tot_r);
+        if (r < R) {
+            J.roff_old[b * BS + r] = carry_o + off_o;
+            J.roff[b * BS + r] = carry_r + off_r;
+        }
+        carry_o += tot_o;
+        carry_r += tot_r;
     }
     if (threadIdx.x == 0) {
-        J.bbase[b] = carry;
+        J.bold[b] = carry_o;
+        J.bbase[b] = carry_o + carry_r;
         if (b == 0) J.bbase[J.nb] = 0;
     }
 }
 
 // 8 lanes per row copy its late entries into the batch list; listed leaves
 // (repulsion terms) carry bit 31 of the vertex word, moved neighbours
-// (attraction terms) do not.
+// (attraction terms) do not.  Within each part a row's entries keep their
+// order: neighbours by id, then leaves in walk order.
 __global__ __launch_bounds__(256) void late_fill_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     const int i = (jb.local * blockDim.x + threadIdx.x) >> 3;
     const int sub = threadIdx.x & 7;
-    if (i >= J.n) return;
-    const int b = i / J.BS;
-    const unsigned long long rbits = (unsigned long long)(i - b * J.BS) << 32;
-    const size_t base = (size_t)J.bbase[b] + J.roff[i];
-    const int rs = J.rowptr[i];
-    const int la = J.all_live ? J.rowptr[i + 1] - rs : J.late_att[i];
+    const bool in = i < J.n;
+    const int ii = in ? i : J.n - 1;
+    const int b = ii / J.BS;
+    const unsigned long long rbits = (unsigned long long)(ii - b * J.BS) << 32;
+    const size_t bo = (size_t)J.bbase[b] + J.roff_old[ii];
+    const size_t br = (size_t)J.bbase[b] + J.bold[b] + J.roff[ii];
+    const int rs = J.rowptr[ii];
+    const int la = J.all_live ? J.rowptr[ii + 1] - rs : J.late_att[ii];
+    const int oa = J.all_live ? 0 : J.old_att[ii];
     gptr<unsigned long long> ent = J.ent;
     const bool heavy = !J.all_live && la > kLateHeavyRow;   // copied by late_fill_heavy_kernel
-    if (!heavy)
-        for (int k = sub; k < la; k += 8) ent[base + k] = rbits | (unsigned)J.colidx[rs + k];
-    const int ll = late_leaf_count(J.late_cnt[i]);
-    gptr<const int> lid = J.late_ids + (size_t)i * kLateCap;
-    for (int k = sub; k < ll; k += 8) ent[base + la + k] = rbits | 0x80000000u | (unsigned)lid[k];
+    if (in && !heavy) {
+        for (int k = sub; k < oa; k += 8) ent[bo + k] = rbits | (unsigned)J.colidx[rs + k];
+        for (int k = oa + sub; k < la; k += 8) ent[br + (k - oa)] = rbits | (unsigned)J.colidx[rs + k];
+    }
+    // leaves: stable split by the ballot of this row's eight lanes
+    const int ll = in ? late_leaf_count(J.late_cnt[ii]) : 0;
+    const int olim = old_limit(J, b);
+    gptr<const int> lid = J.late_ids + (size_t)ii * kLateCap;
+    const int gshift = (threadIdx.x & (kWave - 1)) & ~7;
+    int no = 0, nr = 0;
+    int mx = ll;
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, kWave));
+    for (int k0 = 0; k0 < mx; k0 += 8) {
+        const int k = k0 + sub;
+        const bool have = k < ll;
+        const int v = have ? lid[k] : 0;
+        const bool isold = have && v < olim;
+        const unsigned mo = (unsigned)(__ballot(isold) >> gshift) & 0xffu;
+        const unsigned mh = (unsigned)(__ballot(have) >> gshift) & 0xffu;
+        const unsigned below = (1u << sub) - 1u;
+        const int ro = __popc(mo & below), rr = __popc(mh & ~mo & below);
+        if (have) {
+            const unsigned long long wd = rbits | 0x80000000u | (unsigned)v;
+            if (isold) ent[bo + oa + no + ro] = wd;
+            else ent[br + (la - oa) + nr + rr] = wd;
+        }
+        no += __popc(mo);
+        nr += __popc(mh & ~mo);
+    }
 }
 
 // Rows with many moved neighbours: one workgroup per row copies them.
@@ -830,9 +903,11 @@ __global__ __launch_bounds__(256) void late_fill_heavy_kernel(BH_KERNEL_ARGS) {
         const int i = J.heavy[J.n + h];
         const int b = i / J.BS;
         const unsigned long long rbits = (unsigned long long)(i - b * J.BS) << 32;
-        const size_t base = (size_t)J.bbase[b] + J.roff[i];
-        const int rs = J.rowptr[i], la = J.late_att[i];
-        for (int k = threadIdx.x; k < la; k += 256) J.ent[base + k] = rbits | (unsigned)J.colidx[rs + k];
+        const size_t bo = (size_t)J.bbase[b] + J.roff_old[i];
+        const size_t br = (size_t)J.bbase[b] + J.bold[b] + J.roff[i];
+        const int rs = J.rowptr[i], la = J.late_att[i], oa = J.old_att[i];
+        for (int k = threadIdx.x; k < la; k += 256)
+            J.ent[k < oa ? bo + k : br + (k - oa)] = rbits | (unsigned)J.colidx[rs + k];
     }
 }
 
@@ -844,6 +919,7 @@ struct ChainRow {
     float x, y;
     float4 far;
     float2 atte;
+    float2 old;          // sum of the row's old entries (segment kernel)
 };
 
 __device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r, int R, int E) {
@@ -857,6 +933,7 @@ __device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r, int 
     d.y = pi.y;
     d.far = ld<float4>(J.far, i);
     d.atte = J.all_live ? float2{0.f, 0.f} : ld<float2>(J.atte, i);
+    d.old = J.nseg <= 1 ? float2{0.f, 0.f} : ld<float2>(J.oldsum, i);
     return d;
 }
 
@@ -870,7 +947,7 @@ struct ChainShared {
     float2 cl[kChainThreads];         // last (partial) row of each thread's run
     float2 wv[kChainThreads / kWave]; // carry scan: per-wave totals and keys
     int wk[kChainThreads / kWave], wkf[kChainThreads / kWave];
-    int mb[16];                       // list starts of batches b .. b + 15
+    int mb[16], mo[16];               // list starts and old-part lengths of batches b .. b + 15
     double wsd[16];
     double step;
 };
@@ -1008,6 +1085,65 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
     return sm;
 }
 
+// Old entries of one batch of chain segment `seg` (one workgroup of 256 per
+// batch): every vertex they refer to lies in an earlier segment, so it has
+// moved in this iteration and its position is final.  The batch's old list
+// is split into equal runs, summed per row with live positions, the runs'
+// partial rows combined by the carry scan; each row's total goes to oldsum.
+__global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
+    BH_JOB();
+    __shared__ int off[kMaxChainRows + 1];
+    __shared__ float px[kMaxChainRows], py[kMaxChainRows];
+    __shared__ float2 sum[kMaxChainRows];
+    __shared__ float2 cl[256], loc[256];
+    __shared__ int keys[256];
+    __shared__ float2 wv[256 / kWave];
+    __shared__ int wk[256 / kWave], wkf[256 / kWave];
+    if (J.nseg <= 1) return;
+    const int b = seg * seg_len(J) + jb.local;
+    if (b >= J.nb) return;
+    const int tid = threadIdx.x, BS = J.BS;
+    const int R = min(BS, J.n - b * BS);
+    const int Eo = J.bold[b];
+    const size_t base = (size_t)J.bbase[b];
+    for (int r = tid; r < R; r += 256) {
+        const int i = b * BS + r;
+        off[r] = J.roff_old[i];
+        const float2 p = ld<float2>(J.pos, i);
+        px[r] = p.x;
+        py[r] = p.y;
+    }
+    if (tid == 0) off[R] = Eo;
+    const int chunk = max(1, (Eo + 255) / 256);
+    const int e0 = min(tid * chunk, Eo), e1 = min(e0 + chunk, Eo);
+    unsigned long long w[kEntH];
+    float xj[kEntH], yj[kEntH];
+    const int m0 = min(kEntH, e1 - e0);
+#pragma unroll
+    for (int q = 0; q < kEntH; ++q) {
+        w[q] = 0;
+        xj[q] = 0.f;
+        yj[q] = 0.f;
+        if (q < m0) w[q] = J.ent[base + e0 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < kEntH; ++q) {
+        if (q < m0) {
+            const float2 pj = ld<float2>(J.pos, (int)((unsigned)w[q] & 0x7fffffffu));
+            xj[q] = pj.x;
+            yj[q] = pj.y;
+        }
+    }
+    __syncthreads();
+    const int key0 = e0 < e1 ? (int)(w[0] >> 32) : -1 - tid;
+    float2 firstp;
+    run_sum<kEntH>(J.ent + base, J.pos, e0, e1, w, xj, yj, off, px, py, sum, firstp, cl, J.invK, J.negRK2);
+    carry_scan_wave(firstp, key0, loc, keys, wv, wk, wkf);
+    __syncthreads();
+    for (int r = tid; r < R; r += 256)
+        st<float2>(J.oldsum, b * BS + r, row_total(r, off[r], off[r + 1], chunk, sum, cl, loc, keys, wv, wk, wkf));
+}
+
 // The minibatch chain: one workgroup per job walks its batches in order.
 // Per step b:
 //   - each thread gathers the live positions of the first late entries of its
@@ -1022,12 +1158,23 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
 // a dependent load of them.  The step length of iteration k is step0 times
 // decay k times (the host uses the same product), k is read from and advanced
 // in device memory.
-__global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
+__global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, int seg) {
     BH_JOB();
     __shared__ ChainShared S;
     const int tid = threadIdx.x;
     const int BS = J.BS, n = J.n;
-    const int first = J.first_batch, last = J.last_batch;
+    // this launch's batches: segment `seg` of the run's range (a one-shot
+    // force call runs whole in segment 0)
+    int first = J.first_batch, last = J.last_batch;
+    if (J.nseg <= 1) {
+        if (seg != 0) return;
+    } else {
+        const int L = seg_len(J);
+        first = max(first, seg * L);
+        last = min(last, seg * L + L - 1);
+        if (first > last) return;
+    }
+    const bool first_launch = (first == J.first_batch), last_launch = (last == J.last_batch);
     const float invK = J.invK, negRK2 = J.negRK2;
     const WalkArgs wa = walk_args(J);
     static_assert(kMaxChainRows == kChainThreads, "one row per thread");
@@ -1048,6 +1195,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
     if (tid < 16) {
         const int q = first + tid;
         if (q <= J.nb) S.mb[q & 15] = J.bbase[q];
+        if (q < J.nb) S.mo[q & 15] = J.bold[q];
     }
     __syncthreads();
 
@@ -1055,11 +1203,11 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
     unsigned long long pe[kEnt];
     auto fetch_regs = [&](int b) {
         const int R = nrows(b);
-        const int E = S.mb[(b + 1) & 15] - S.mb[b & 15];
+        const int Eo = S.mo[b & 15], E = S.mb[(b + 1) & 15] - S.mb[b & 15] - Eo;
         if (tid < R) rowd = chain_row(J, b, tid, R, E);
         int e0, e1;
         run_of(E, e0, e1);
-        const size_t gb = (size_t)S.mb[b & 15];
+        const size_t gb = (size_t)S.mb[b & 15] + Eo;
 #pragma unroll
         for (int q = 0; q < kEnt; ++q)
             if (e0 + q < e1) pe[q] = J.ent[min(gb + (size_t)(e0 + q), entmax)];
@@ -1071,7 +1219,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
             S.px[slot][tid] = rowd.x;
             S.py[slot][tid] = rowd.y;
         }
-        if (tid == 0) S.off[slot][R] = S.mb[(b + 1) & 15] - S.mb[b & 15];
+        if (tid == 0) S.off[slot][R] = S.mb[(b + 1) & 15] - S.mb[b & 15] - S.mo[b & 15];
     };
     fetch_regs(first);
     fetch_lds(first, first & 1);
@@ -1108,16 +1256,22 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
         // next step's data (clamped to the last batch on the final step),
         // and the list start of batch b + 16
         fetch_regs(min(b + 1, last));
-        int meta = 0;
-        if (tid == 0 && b + 16 <= J.nb) meta = J.bbase[b + 16];
+        int meta = 0, meta_o = 0;
+        if (tid == 0) {
+            if (b + 16 <= J.nb) meta = J.bbase[b + 16];
+            if (b + 16 < J.nb) meta_o = J.bold[b + 16];
+        }
 
         float2 firstp;
         const int key0 = e0 < e1 ? (int)(ce[0] >> 32) : -1 - tid;   // row of the run's first entry
-        run_sum<kEnt>(J.ent + S.mb[b & 15], J.pos, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot],
+        run_sum<kEnt>(J.ent + S.mb[b & 15] + S.mo[b & 15], J.pos, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot],
                       S.sum, firstp, S.cl, invK, negRK2);
         carry_scan_wave(firstp, key0, S.scan, S.skey, S.wv, S.wk, S.wkf);
         __syncthreads();
-        if (tid == 0) S.mb[b & 15] = meta;   // the slot of batch b now holds batch b + 16
+        if (tid == 0) {   // the slot of batch b now holds batch b + 16
+            S.mb[b & 15] = meta;
+            S.mo[b & 15] = meta_o;
+        }
 
         // complete the row of batch b, add early attraction and far field,
         // move it
@@ -1130,8 +1284,8 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
                 int dummy = 0;
                 (void)bh_walk(wa, i, cur.x, cur.y, 0, J.pos, fr, nullptr, dummy, 0);
             }
-            const float fx = (sm.x + cur.atte.x) + negRK2 * (fr.x - fr.z);
-            const float fy = (sm.y + cur.atte.y) + negRK2 * (fr.y - fr.w);
+            const float fx = ((sm.x + cur.old.x) + cur.atte.x) + negRK2 * (fr.x - fr.z);
+            const float fy = ((sm.y + cur.old.y) + cur.atte.y) + negRK2 * (fr.y - fr.w);
             if (stop) {
                 J.fout[2 * tid] = (double)fx;
                 J.fout[2 * tid + 1] = (double)fy;
@@ -1154,15 +1308,17 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
     if (bad) atomicAdd(&J.ctr->nonfinite, bad);
     const double e = block_sum_fixed(e_iter, S.wsd);
     if (tid == 0 && J.stop_batch < 0) {
-        J.energy[k_it - J.kiter[1]] = e;
-        J.kiter[0] = k_it + 1;
+        // segments add their energies in order; the last one ends the iteration
+        const int slot_e = k_it - J.kiter[1];
+        J.energy[slot_e] = first_launch ? e : J.energy[slot_e] + e;
+        if (last_launch) J.kiter[0] = k_it + 1;
     }
 }
 
 // ------------------------------------------------------------- host side
 namespace {
 
-enum PreType { PT_BBOX = 0, PT_VERT, PT_SORT, PT_ONE, PT_MARK, PT_SCAN, PT_VERT8, PT_HEAVY, PT_BATCH, PT_COUNT };
+enum PreType { PT_BBOX = 0, PT_VERT, PT_SORT, PT_ONE, PT_MARK, PT_SCAN, PT_VERT8, PT_HEAVY, PT_BATCH, PT_SEG, PT_COUNT };
 
 int blocks_for(int type, const BHJob &J) {
     const int n = J.n;
@@ -1176,6 +1332,7 @@ int blocks_for(int type, const BHJob &J) {
         case PT_VERT8: return (n + 31) / 32;
         case PT_HEAVY: return std::max(16, std::min(256, n / 512));
         case PT_BATCH: return J.nb;
+        case PT_SEG: return J.nseg > 1 ? (J.nb + J.nseg - 1) / J.nseg : 0;
     }
     return 0;
 }
@@ -1194,6 +1351,7 @@ struct BHEngine {
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool ev_used[2] = {false, false};
     int total[PT_COUNT] = {};
+    int nseg = 1;                       // most chain segments of any job
     hipGraph_t graph = nullptr;         // one captured iteration of the current set
     hipGraphExec_t exec = nullptr;
 };
@@ -1254,6 +1412,7 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->first_batch = (decltype(J->first_batch))(spec.first_batch);
     J->last_batch = (decltype(J->last_batch))(spec.last_batch);
     J->stop_batch = (decltype(J->stop_batch))(spec.stop_batch);
+    J->nseg = (decltype(J->nseg))(spec.all_live ? 1 : std::max(1, std::min(kMaxSegments, (int)(g->nb / kSegBatches))));
     J->step0 = (decltype(J->step0))(g->p.step0);
     J->decay = (decltype(J->decay))(g->p.step_decay);
     J->kiter = (decltype(J->kiter))(h.kiter);
@@ -1282,6 +1441,10 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->late_cnt = (decltype(J->late_cnt))(h.late_cnt);
     J->late_ids = (decltype(J->late_ids))(h.late_ids);
     J->late_att = (decltype(J->late_att))(h.late_att);
+    J->old_att = (decltype(J->old_att))(h.old_att);
+    J->roff_old = (decltype(J->roff_old))(h.roff_old);
+    J->bold = (decltype(J->bold))(h.bold);
+    J->oldsum = (decltype(J->oldsum))(h.oldsum);
     J->heavy = (decltype(J->heavy))(h.heavy);
     J->nheavy = (decltype(J->nheavy))(h.nheavy);
     J->atte = (decltype(J->atte))(h.atte);
@@ -1325,6 +1488,8 @@ int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
         for (int j = 0; j < G; ++j) pre[j + 1] = pre[j] + blocks_for(t, jobs[j]);
         e->total[t] = pre[G];
     }
+    e->nseg = 1;
+    for (int j = 0; j < G; ++j) e->nseg = std::max(e->nseg, (int)jobs[j].nseg);
     BL_HIP(hipMemcpyAsync(e->d_jobs[s], e->h_jobs[s], sizeof(BHJob) * G, hipMemcpyHostToDevice, e->stream));
     BL_HIP(hipMemcpyAsync(e->d_pre[s], e->h_pre[s], sizeof(int) * PT_COUNT * (e->cap + 1),
                           hipMemcpyHostToDevice, e->stream));
@@ -1385,7 +1550,10 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     BH_LAUNCH(late_fill_kernel, PT_VERT8, 256);
     BH_LAUNCH(late_fill_heavy_kernel, PT_HEAVY, 256);
     if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
-    BH_LAUNCH(chain_kernel, PT_ONE, kChainThreads);
+    for (int seg = 0; seg < e->nseg; ++seg) {
+        BH_LAUNCH(old_sum_kernel, PT_SEG, 256, seg);
+        BH_LAUNCH(chain_kernel, PT_ONE, kChainThreads, seg);
+    }
     if (prof) BL_TRY(prof_end(prof, slot));
     BL_HIP(hipGetLastError());
     return BL_OK;
@@ -1442,7 +1610,7 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
-           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N;
+           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1);
 }
 
 int bh_alloc(bl_graph *g) {
@@ -1471,6 +1639,10 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.late_ids, 4 * N * kLateCap));
     BL_TRY(graph_alloc(g, (void **)&h.snap, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.late_att, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.old_att, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.roff_old, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.bold, 4 * ((size_t)g->nb + 1)));
+    BL_TRY(graph_alloc(g, (void **)&h.oldsum, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.heavy, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nheavy, 16));
     BL_TRY(graph_alloc(g, (void **)&h.atte, 8 * N));

@@ -79,6 +79,10 @@ struct BHBuffers {
     float *snap;            // [2n] snapshot given to the one-shot force call
     void *fbuf;             // [BS] float2 net forces of the current batch
     int *late_att;          // [n] length of the moved-neighbour prefix of each CSR row
+    int *old_att;           // [n] its part in earlier chain segments
+    int *roff_old;          // [n] offset of each row's old entries within its batch list
+    int *bold;              // [nb + 1] length of each batch list's old part
+    float2 *oldsum;         // [n] sum of each vertex's old entries
     int *heavy;             // [n] rows with many early neighbours (first *nheavy used)
     int *nheavy;            // [1]
     float2 *atte;           // [n] early attraction (neighbours not yet moved)
