@@ -55,6 +55,8 @@ constexpr int kEnt = 3;               // late entries per thread per pass (held 
 constexpr int kMaxSegments = 16;
 constexpr int kSegBatches = 16;
 constexpr int kEntH = 8;              // old entries per thread per pass in the segment kernel
+constexpr int kOldSplit = 16;         // workgroups per batch in the segment kernel
+static_assert(kMaxChainRows <= 1024, "batch_offsets_kernel takes one row per thread");
 
 // Device descriptor of one job (all pointers are device memory).
 struct BHJob {
@@ -84,6 +86,7 @@ struct BHJob {
     gptr<float2> atte;
     gptr<int> roff, roff_old, bbase, bold;
     gptr<float2> oldsum;        // per vertex: sum of its old entries
+    gptr<int> osplit;           // per batch: kOldSplit + 1 row bounds splitting its old part
     gptr<unsigned long long> ent;
     size_t ent_cap;
     gptr<double> energy;        // one value per iteration of the run
@@ -804,49 +807,53 @@ __device__ __forceinline__ int late_leaf_count(int lc) { return lc > kLateCap ? 
 // Per batch: the list holds first the old entries of all its rows, then the
 // others, each part row by row.  Counts of each row -> exclusive offsets
 // within each part; bold[b] = old part length, bbase[b] = list length (a scan
-// turns bbase into list starts).
+// turns bbase into list starts).  The old part is also cut into kOldSplit
+// row ranges of about equal entry counts: bound k is the first row that
+// starts at or after entry floor(k * bold / kOldSplit).
 __global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     __shared__ int ws[16];
-    const int b = jb.local, BS = J.BS;
-    const int R = min(BS, J.n - b * BS);
+    const int b = jb.local, BS = J.BS, r = (int)threadIdx.x;
+    const int R = min(BS, J.n - b * BS);   // at most kMaxChainRows: one row per thread
     const int olim = old_limit(J, b);
-    int carry_o = 0, carry_r = 0;
-    for (int r0 = 0; r0 < R; r0 += 1024) {
-        const int r = r0 + (int)threadIdx.x;
-        int co = 0, cr = 0;
-        if (r < R) {
-            const int i = b * BS + r;
-            const int la = J.all_live ? J.rowptr[i + 1] - J.rowptr[i] : J.late_att[i];
-            const int oa = J.all_live ? 0 : J.old_att[i];
-            const int ll = late_leaf_count(J.late_cnt[i]);
-            gptr<const int> lid = J.late_ids + (size_t)i * kLateCap;
-            int ol = 0;
-            for (int k = 0; k < ll; ++k) ol += lid[k] < olim ? 1 : 0;
-            co = oa + ol;
-            cr = (la - oa) + (ll - ol);
-        }
-        int tot_o, tot_r;
-        const int off_o = block_excl_scan(co, ws, &tot_o);
-        const int off_r = block_excl_scan(cr, ws, &tot_r);
-        if (r < R) {
-            J.roff_old[b * BS + r] = carry_o + off_o;
-            J.roff[b * BS + r] = carry_r + off_r;
-        }
-        carry_o += tot_o;
-        carry_r += tot_r;
+    int co = 0, cr = 0;
+    if (r < R) {
+        const int i = b * BS + r;
+        const int la = J.all_live ? J.rowptr[i + 1] - J.rowptr[i] : J.late_att[i];
+        const int oa = J.all_live ? 0 : J.old_att[i];
+        const int ll = late_leaf_count(J.late_cnt[i]);
+        gptr<const int> lid = J.late_ids + (size_t)i * kLateCap;
+        int ol = 0;
+        for (int k = 0; k < ll; ++k) ol += lid[k] < olim ? 1 : 0;
+        co = oa + ol;
+        cr = (la - oa) + (ll - ol);
     }
-    if (threadIdx.x == 0) {
-        J.bold[b] = carry_o;
-        J.bbase[b] = carry_o + carry_r;
+    int tot_o, tot_r;
+    const int off_o = block_excl_scan(co, ws, &tot_o);
+    const int off_r = block_excl_scan(cr, ws, &tot_r);
+    if (r < R) {
+        J.roff_old[b * BS + r] = off_o;
+        J.roff[b * BS + r] = off_r;
+    }
+    if (J.nseg > 1) {
+        gptr<int> sp = J.osplit + (size_t)b * (kOldSplit + 1);
+        for (int k = 1; k < kOldSplit; ++k) {
+            const int t = (int)(((long long)k * tot_o) / kOldSplit);
+            // the row whose entries (off_o, off_o + co] hold t ends range k - 1
+            if (r < R && co > 0 && off_o < t && t <= off_o + co) sp[k] = r + 1;
+            if (r == 0 && t == 0) sp[k] = 0;
+        }
+        if (r == 0) {
+            sp[0] = 0;
+            sp[kOldSplit] = R;
+        }
+    }
+    if (r == 0) {
+        J.bold[b] = tot_o;
+        J.bbase[b] = tot_o + tot_r;
         if (b == 0) J.bbase[J.nb] = 0;
     }
 }
-
-// 8 lanes per row copy its late entries into the batch list; listed leaves
-// (repulsion terms) carry bit 31 of the vertex word, moved neighbours
-// (attraction terms) do not.  Within each part a row's entries keep their
-// order: neighbours by id, then leaves in walk order.
 __global__ __launch_bounds__(256) void late_fill_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     const int i = (jb.local * blockDim.x + threadIdx.x) >> 3;
@@ -1085,11 +1092,12 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
     return sm;
 }
 
-// Old entries of one batch of chain segment `seg` (one workgroup of 256 per
-// batch): every vertex they refer to lies in an earlier segment, so it has
-// moved in this iteration and its position is final.  The batch's old list
-// is split into equal runs, summed per row with live positions, the runs'
-// partial rows combined by the carry scan; each row's total goes to oldsum.
+// Old entries of chain segment `seg`, kOldSplit workgroups of 256 per batch,
+// each taking one row range of the batch's old part: every vertex they refer
+// to lies in an earlier segment, so it has moved in this iteration and its
+// position is final.  The range's entries are split into equal runs, summed
+// per row with live positions, the runs' partial rows combined by the carry
+// scan; each row's total goes to oldsum.
 __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     BH_JOB();
     __shared__ int off[kMaxChainRows + 1];
@@ -1100,22 +1108,19 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     __shared__ float2 wv[256 / kWave];
     __shared__ int wk[256 / kWave], wkf[256 / kWave];
     if (J.nseg <= 1) return;
-    const int b = seg * seg_len(J) + jb.local;
+    const int b = seg * seg_len(J) + jb.local / kOldSplit, part = jb.local % kOldSplit;
     if (b >= J.nb) return;
     const int tid = threadIdx.x, BS = J.BS;
     const int R = min(BS, J.n - b * BS);
+    gptr<const int> sp = J.osplit + (size_t)b * (kOldSplit + 1);
+    const int rlo = sp[part], rhi = sp[part + 1];
+    if (rlo >= rhi) return;
+    gptr<const int> ro = J.roff_old + (size_t)b * BS;
     const int Eo = J.bold[b];
+    const int E0 = ro[rlo], E1 = rhi < R ? ro[rhi] : Eo;
     const size_t base = (size_t)J.bbase[b];
-    for (int r = tid; r < R; r += 256) {
-        const int i = b * BS + r;
-        off[r] = J.roff_old[i];
-        const float2 p = ld<float2>(J.pos, i);
-        px[r] = p.x;
-        py[r] = p.y;
-    }
-    if (tid == 0) off[R] = Eo;
-    const int chunk = max(1, (Eo + 255) / 256);
-    const int e0 = min(tid * chunk, Eo), e1 = min(e0 + chunk, Eo);
+    const int chunk = max(1, (E1 - E0 + 255) / 256);
+    const int e0 = min(E0 + tid * chunk, E1), e1 = min(e0 + chunk, E1);
     unsigned long long w[kEntH];
     float xj[kEntH], yj[kEntH];
     const int m0 = min(kEntH, e1 - e0);
@@ -1126,6 +1131,13 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
         yj[q] = 0.f;
         if (q < m0) w[q] = J.ent[base + e0 + q];
     }
+    for (int r = rlo + tid; r < rhi; r += 256) {
+        off[r] = ro[r];
+        const float2 p = ld<float2>(J.pos, b * BS + r);
+        px[r] = p.x;
+        py[r] = p.y;
+    }
+    if (tid == 0) off[rhi] = E1;
 #pragma unroll
     for (int q = 0; q < kEntH; ++q) {
         if (q < m0) {
@@ -1140,8 +1152,9 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     run_sum<kEntH>(J.ent + base, J.pos, e0, e1, w, xj, yj, off, px, py, sum, firstp, cl, J.invK, J.negRK2);
     carry_scan_wave(firstp, key0, loc, keys, wv, wk, wkf);
     __syncthreads();
-    for (int r = tid; r < R; r += 256)
-        st<float2>(J.oldsum, b * BS + r, row_total(r, off[r], off[r + 1], chunk, sum, cl, loc, keys, wv, wk, wkf));
+    for (int r = rlo + tid; r < rhi; r += 256)
+        st<float2>(J.oldsum, b * BS + r,
+                   row_total(r, off[r] - E0, off[r + 1] - E0, chunk, sum, cl, loc, keys, wv, wk, wkf));
 }
 
 // The minibatch chain: one workgroup per job walks its batches in order.
@@ -1332,7 +1345,7 @@ int blocks_for(int type, const BHJob &J) {
         case PT_VERT8: return (n + 31) / 32;
         case PT_HEAVY: return std::max(16, std::min(256, n / 512));
         case PT_BATCH: return J.nb;
-        case PT_SEG: return J.nseg > 1 ? (J.nb + J.nseg - 1) / J.nseg : 0;
+        case PT_SEG: return J.nseg > 1 ? kOldSplit * ((J.nb + J.nseg - 1) / J.nseg) : 0;
     }
     return 0;
 }
@@ -1445,6 +1458,7 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->roff_old = (decltype(J->roff_old))(h.roff_old);
     J->bold = (decltype(J->bold))(h.bold);
     J->oldsum = (decltype(J->oldsum))(h.oldsum);
+    J->osplit = (decltype(J->osplit))(h.osplit);
     J->heavy = (decltype(J->heavy))(h.heavy);
     J->nheavy = (decltype(J->nheavy))(h.nheavy);
     J->atte = (decltype(J->atte))(h.atte);
@@ -1610,7 +1624,7 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
-           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1);
+           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1);
 }
 
 int bh_alloc(bl_graph *g) {
@@ -1643,6 +1657,7 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.roff_old, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.bold, 4 * ((size_t)g->nb + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.oldsum, 8 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.osplit, 4 * (size_t)g->nb * (kOldSplit + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.heavy, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nheavy, 16));
     BL_TRY(graph_alloc(g, (void **)&h.atte, 8 * N));

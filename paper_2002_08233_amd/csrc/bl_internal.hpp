@@ -83,6 +83,7 @@ struct BHBuffers {
     int *roff_old;          // [n] offset of each row's old entries within its batch list
     int *bold;              // [nb + 1] length of each batch list's old part
     float2 *oldsum;         // [n] sum of each vertex's old entries
+    int *osplit;            // [nb * 17] row ranges of each batch's old part, one per workgroup
     int *heavy;             // [n] rows with many early neighbours (first *nheavy used)
     int *nheavy;            // [1]
     float2 *atte;           // [n] early attraction (neighbours not yet moved)
