@@ -922,7 +922,7 @@ __global__ __launch_bounds__(256) void late_fill_heavy_kernel(BH_KERNEL_ARGS) {
 // Per-row data of a step, requested one step ahead.
 struct ChainRow {
     int o0, o1;          // entry range of the row in its batch list
-    int ovf;             // late-leaf list overflowed: walk the whole tree live
+    int lc;              // late-leaf count; above kLateCap the list overflowed: walk the whole tree live
     float x, y;
     float4 far;
     float2 atte;
@@ -934,7 +934,7 @@ __device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r, int 
     const int i = b * J.BS + r;
     d.o0 = J.roff[i];
     d.o1 = (r + 1 < R) ? J.roff[i + 1] : E;
-    d.ovf = J.late_cnt[i] > kLateCap;
+    d.lc = J.late_cnt[i];
     const float2 pi = ld<float2>(J.pos, i);
     d.x = pi.x;
     d.y = pi.y;
@@ -1031,18 +1031,32 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr
 // it, scan_at(t) adds the carry of earlier waves.  key: the row of the
 // thread's first entry (unique per thread when it has none); v: its first
 // partial row (0 when that row is complete inside the run).
+// One step of the wave's segmented scan by a DPP lane move: v takes the
+// value of the source lane when that lane exists for the move and has the
+// same key (keys are sorted over the threads that have entries, and unique
+// elsewhere, so equal keys enclose only equal keys).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_dpp(float2 &v, int key) {
+    const int uk = __builtin_amdgcn_update_dpp((int)0x80000000, key, CTRL, ROWS, 0xf, false);
+    const float ux = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v.x), CTRL, ROWS, 0xf, false));
+    const float uy = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v.y), CTRL, ROWS, 0xf, false));
+    if (uk == key) {
+        v.x += ux;
+        v.y += uy;
+    }
+}
+
 __device__ __forceinline__ void carry_scan_wave(float2 v, int key, float2 *loc, int *keys, float2 *wv, int *wk,
                                                 int *wkf) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const float ux = __shfl_up(v.x, d, kWave), uy = __shfl_up(v.y, d, kWave);
-        const int uk = __shfl_up(key, d, kWave);
-        if (lane >= d && uk == key) {
-            v.x += ux;
-            v.y += uy;
-        }
-    }
+    // within rows of 16 lanes (shift right by 1, 2, 4, 8), then lane 15 of
+    // rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3
+    seg_dpp<0x111, 0xf>(v, key);
+    seg_dpp<0x112, 0xf>(v, key);
+    seg_dpp<0x114, 0xf>(v, key);
+    seg_dpp<0x118, 0xf>(v, key);
+    seg_dpp<0x142, 0xa>(v, key);
+    seg_dpp<0x143, 0xc>(v, key);
     loc[tid] = v;
     keys[tid] = key;
     if (lane == kWave - 1) {
@@ -1212,12 +1226,15 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
     }
     __syncthreads();
 
-    ChainRow rowd;
-    unsigned long long pe[kEnt];
-    auto fetch_regs = [&](int b) {
+    // Per-step registers are double-buffered (the loop is unrolled by two),
+    // so the next batch's loads are issued before this batch's gathers are
+    // waited for.
+    ChainRow rA, rB;
+    unsigned long long pA[kEnt], pB[kEnt];
+    auto fetch_regs = [&](int b, ChainRow &rd, unsigned long long (&pe)[kEnt]) {
         const int R = nrows(b);
         const int Eo = S.mo[b & 15], E = S.mb[(b + 1) & 15] - S.mb[b & 15] - Eo;
-        if (tid < R) rowd = chain_row(J, b, tid, R, E);
+        if (tid < R) rd = chain_row(J, b, tid, R, E);
         int e0, e1;
         run_of(E, e0, e1);
         const size_t gb = (size_t)S.mb[b & 15] + Eo;
@@ -1225,32 +1242,29 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         for (int q = 0; q < kEnt; ++q)
             if (e0 + q < e1) pe[q] = J.ent[min(gb + (size_t)(e0 + q), entmax)];
     };
-    auto fetch_lds = [&](int b, int slot) {
+    auto fetch_lds = [&](int b, int slot, const ChainRow &rd) {
         const int R = nrows(b);
         if (tid < R) {
-            S.off[slot][tid] = rowd.o0;
-            S.px[slot][tid] = rowd.x;
-            S.py[slot][tid] = rowd.y;
+            S.off[slot][tid] = rd.o0;
+            S.px[slot][tid] = rd.x;
+            S.py[slot][tid] = rd.y;
         }
         if (tid == 0) S.off[slot][R] = S.mb[(b + 1) & 15] - S.mb[b & 15] - S.mo[b & 15];
     };
-    fetch_regs(first);
-    fetch_lds(first, first & 1);
+    fetch_regs(first, rA, pA);
+    fetch_lds(first, first & 1, rA);
     __syncthreads();
     const float step = (float)S.step;
 
     double e_iter = 0.0;
     unsigned long long bad = 0;
-    for (int b = first; b <= last; ++b) {
+    auto chain_step = [&](int b, const ChainRow &cur, unsigned long long (&ce)[kEnt], ChainRow &nxt,
+                          unsigned long long (&ne)[kEnt]) {
         const int slot = b & 1;
         const int R = nrows(b);
         const int E = S.off[slot][R];
         int e0, e1;
         const int chunk = run_of(E, e0, e1);
-        const ChainRow cur = rowd;
-        unsigned long long ce[kEnt];
-#pragma unroll
-        for (int q = 0; q < kEnt; ++q) ce[q] = pe[q];
 
         // gathers of the first pass (only real entries: every lane's gather
         // costs a cache-line lookup in this CU's address unit)
@@ -1268,7 +1282,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         }
         // next step's data (clamped to the last batch on the final step),
         // and the list start of batch b + 16
-        fetch_regs(min(b + 1, last));
+        fetch_regs(min(b + 1, last), nxt, ne);
         int meta = 0, meta_o = 0;
         if (tid == 0) {
             if (b + 16 <= J.nb) meta = J.bbase[b + 16];
@@ -1293,7 +1307,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
             const float2 sm = row_total(tid, cur.o0, cur.o1, chunk, S.sum, S.cl, S.scan, S.skey, S.wv, S.wk, S.wkf);
             const int i = b * BS + tid;
             float4 fr = cur.far;
-            if (cur.ovf) {
+            if (cur.lc > kLateCap) {
                 int dummy = 0;
                 (void)bh_walk(wa, i, cur.x, cur.y, 0, J.pos, fr, nullptr, dummy, 0);
             }
@@ -1315,8 +1329,12 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
                 }
             }
         }
-        if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1);
+        if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1, nxt);
         __syncthreads();
+    };
+    for (int b = first; b <= last; b += 2) {
+        chain_step(b, rA, pA, rB, pB);
+        if (b + 1 <= last) chain_step(b + 1, rB, pB, rA, pA);
     }
     if (bad) atomicAdd(&J.ctr->nonfinite, bad);
     const double e = block_sum_fixed(e_iter, S.wsd);
