@@ -56,6 +56,10 @@ constexpr int kMaxSegments = 16;
 constexpr int kSegBatches = 16;
 constexpr int kEntH = 8;              // old entries per thread per pass in the segment kernel
 constexpr int kOldSplit = 16;         // workgroups per batch in the segment kernel
+// The chain keeps the positions its segment has moved in an LDS window (the
+// recent entries refer to those vertices only); a segment spans at most
+// kWindow vertices.
+constexpr int kWindow = 10240;
 static_assert(kMaxChainRows <= 1024, "batch_offsets_kernel takes one row per thread");
 
 // Device descriptor of one job (all pointers are device memory).
@@ -921,7 +925,7 @@ __global__ __launch_bounds__(256) void late_fill_heavy_kernel(BH_KERNEL_ARGS) {
 // ---------------------------------------------------------------- chain
 // Per-row data of a step, requested one step ahead.
 struct ChainRow {
-    int o0, o1;          // entry range of the row in its batch list
+    int o0;              // start of the row's entries in its batch list
     int lc;              // late-leaf count; above kLateCap the list overflowed: walk the whole tree live
     float x, y;
     float4 far;
@@ -929,11 +933,10 @@ struct ChainRow {
     float2 old;          // sum of the row's old entries (segment kernel)
 };
 
-__device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r, int R, int E) {
+__device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r) {
     ChainRow d;
     const int i = b * J.BS + r;
     d.o0 = J.roff[i];
-    d.o1 = (r + 1 < R) ? J.roff[i + 1] : E;
     d.lc = J.late_cnt[i];
     const float2 pi = ld<float2>(J.pos, i);
     d.x = pi.x;
@@ -948,6 +951,8 @@ struct ChainShared {
     int off[2][kMaxChainRows + 1];    // row offsets in the batch list, by step parity
     float px[2][kMaxChainRows];       // row positions, by step parity
     float py[2][kMaxChainRows];
+    float2 base[2][kMaxChainRows];    // row forces apart from the late entries: old sum, early attraction, far field
+    int ovf[2];                       // a row of the step takes the full walk
     float2 sum[kMaxChainRows];        // rows complete inside one thread's run
     float2 scan[kChainThreads];       // first (partial) rows of the threads' runs, scanned within waves
     int skey[kChainThreads];          // their rows
@@ -965,8 +970,20 @@ struct ChainShared {
 // live positions come in (w, xj, yj).  Terms: a moved neighbour adds the
 // attraction d * delta / K, a listed leaf the repulsion -R K^2 delta / d^2
 // (Sec. 2.2).
-template <int KE>
-__device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr<const float2> pos, int e0, int e1,
+// Where a run's gathers read positions: global memory, or the chain's LDS
+// window of the vertices its segment has moved (vertex base .. base + size).
+struct PosG {
+    gptr<const float2> p;
+    __device__ __forceinline__ float2 operator()(int j) const { return ld<float2>(p, j); }
+};
+struct PosL {
+    const float2 *w;
+    int base;
+    __device__ __forceinline__ float2 operator()(int j) const { return w[j - base]; }
+};
+
+template <int KE, typename P>
+__device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, P pos, int e0, int e1,
                                         unsigned long long (&w)[KE], float (&xj)[KE], float (&yj)[KE],
                                         const int *off, const float *px, const float *py, float2 *sum,
                                         float2 &first, float2 *cl, float invK, float negRK2) {
@@ -985,7 +1002,7 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, gptr
 #pragma unroll
             for (int q = 0; q < KE; ++q) {
                 if (q < m) {
-                    const float2 pj = ld<float2>(pos, (int)((unsigned)w[q] & 0x7fffffffu));
+                    const float2 pj = pos((int)((unsigned)w[q] & 0x7fffffffu));
                     xj[q] = pj.x;
                     yj[q] = pj.y;
                 }
@@ -1163,7 +1180,7 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     __syncthreads();
     const int key0 = e0 < e1 ? (int)(w[0] >> 32) : -1 - tid;
     float2 firstp;
-    run_sum<kEntH>(J.ent + base, J.pos, e0, e1, w, xj, yj, off, px, py, sum, firstp, cl, J.invK, J.negRK2);
+    run_sum<kEntH>(J.ent + base, PosG{J.pos}, e0, e1, w, xj, yj, off, px, py, sum, firstp, cl, J.invK, J.negRK2);
     carry_scan_wave(firstp, key0, loc, keys, wv, wk, wkf);
     __syncthreads();
     for (int r = rlo + tid; r < rhi; r += 256)
@@ -1188,6 +1205,7 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
 __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, int seg) {
     BH_JOB();
     __shared__ ChainShared S;
+    extern __shared__ float2 win[];   // dynamic: the segment's moved positions
     const int tid = threadIdx.x;
     const int BS = J.BS, n = J.n;
     // this launch's batches: segment `seg` of the run's range (a one-shot
@@ -1202,6 +1220,12 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         if (first > last) return;
     }
     const bool first_launch = (first == J.first_batch), last_launch = (last == J.last_batch);
+    // one-shot force calls gather from global memory; runs from the window,
+    // which starts at the segment's first vertex
+    const bool use_win = !J.all_live;
+    const int wbase = (J.nseg <= 1 ? 0 : seg * seg_len(J)) * BS;
+    const PosL pl{win, wbase};
+    const PosG pg{J.pos};
     const float invK = J.invK, negRK2 = J.negRK2;
     const WalkArgs wa = walk_args(J);
     static_assert(kMaxChainRows == kChainThreads, "one row per thread");
@@ -1224,17 +1248,21 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         if (q <= J.nb) S.mb[q & 15] = J.bbase[q];
         if (q < J.nb) S.mo[q & 15] = J.bold[q];
     }
+    if (tid < 2) S.ovf[tid] = 0;
+    if (use_win)   // batches of the segment moved before this launch
+        for (int v = wbase + tid; v < first * BS; v += kChainThreads) win[v - wbase] = ld<float2>(J.pos, v);
     __syncthreads();
 
-    // Per-step registers are double-buffered (the loop is unrolled by two),
-    // so the next batch's loads are issued before this batch's gathers are
-    // waited for.
-    ChainRow rA, rB;
+    // The next batch's row records are loaded during a step and moved to LDS
+    // at its end; its first entries stay in registers, double-buffered (the
+    // loop is unrolled by two) so that they are loaded before this batch's
+    // gathers are waited for.
+    ChainRow rd;
     unsigned long long pA[kEnt], pB[kEnt];
     auto fetch_regs = [&](int b, ChainRow &rd, unsigned long long (&pe)[kEnt]) {
         const int R = nrows(b);
         const int Eo = S.mo[b & 15], E = S.mb[(b + 1) & 15] - S.mb[b & 15] - Eo;
-        if (tid < R) rd = chain_row(J, b, tid, R, E);
+        if (tid < R) rd = chain_row(J, b, tid);
         int e0, e1;
         run_of(E, e0, e1);
         const size_t gb = (size_t)S.mb[b & 15] + Eo;
@@ -1248,18 +1276,28 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
             S.off[slot][tid] = rd.o0;
             S.px[slot][tid] = rd.x;
             S.py[slot][tid] = rd.y;
+            // a row whose leaf list overflowed gets its far field from a
+            // full walk when it moves
+            const bool ov = rd.lc > kLateCap;
+            float2 bs{rd.old.x + rd.atte.x, rd.old.y + rd.atte.y};
+            if (!ov) {
+                bs.x += negRK2 * (rd.far.x - rd.far.z);
+                bs.y += negRK2 * (rd.far.y - rd.far.w);
+            } else {
+                S.ovf[slot] = 1;
+            }
+            S.base[slot][tid] = bs;
         }
         if (tid == 0) S.off[slot][R] = S.mb[(b + 1) & 15] - S.mb[b & 15] - S.mo[b & 15];
     };
-    fetch_regs(first, rA, pA);
-    fetch_lds(first, first & 1, rA);
+    fetch_regs(first, rd, pA);
+    fetch_lds(first, first & 1, rd);
     __syncthreads();
     const float step = (float)S.step;
 
     double e_iter = 0.0;
     unsigned long long bad = 0;
-    auto chain_step = [&](int b, const ChainRow &cur, unsigned long long (&ce)[kEnt], ChainRow &nxt,
-                          unsigned long long (&ne)[kEnt]) {
+    auto chain_step = [&](int b, unsigned long long (&ce)[kEnt], unsigned long long (&ne)[kEnt]) {
         const int slot = b & 1;
         const int R = nrows(b);
         const int E = S.off[slot][R];
@@ -1275,14 +1313,15 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
             xj[q] = 0.f;
             yj[q] = 0.f;
             if (q < m0) {
-                const float2 pj = ld<float2>(J.pos, (int)((unsigned)ce[q] & 0x7fffffffu));
+                const int j = (int)((unsigned)ce[q] & 0x7fffffffu);
+                const float2 pj = use_win ? pl(j) : pg(j);
                 xj[q] = pj.x;
                 yj[q] = pj.y;
             }
         }
         // next step's data (clamped to the last batch on the final step),
         // and the list start of batch b + 16
-        fetch_regs(min(b + 1, last), nxt, ne);
+        fetch_regs(min(b + 1, last), rd, ne);
         int meta = 0, meta_o = 0;
         if (tid == 0) {
             if (b + 16 <= J.nb) meta = J.bbase[b + 16];
@@ -1291,9 +1330,15 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
 
         float2 firstp;
         const int key0 = e0 < e1 ? (int)(ce[0] >> 32) : -1 - tid;   // row of the run's first entry
-        run_sum<kEnt>(J.ent + S.mb[b & 15] + S.mo[b & 15], J.pos, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot],
-                      S.sum, firstp, S.cl, invK, negRK2);
+        gptr<const unsigned long long> lst = J.ent + S.mb[b & 15] + S.mo[b & 15];
+        if (use_win)
+            run_sum<kEnt>(lst, pl, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl, invK,
+                          negRK2);
+        else
+            run_sum<kEnt>(lst, pg, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl, invK,
+                          negRK2);
         carry_scan_wave(firstp, key0, S.scan, S.skey, S.wv, S.wk, S.wkf);
+        if (tid == 0) S.ovf[slot ^ 1] = 0;   // last read in the previous step
         __syncthreads();
         if (tid == 0) {   // the slot of batch b now holds batch b + 16
             S.mb[b & 15] = meta;
@@ -1304,19 +1349,24 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         // move it
         const bool stop = (b == J.stop_batch);
         if (tid < R) {
-            const float2 sm = row_total(tid, cur.o0, cur.o1, chunk, S.sum, S.cl, S.scan, S.skey, S.wv, S.wk, S.wkf);
+            const float2 sm = row_total(tid, S.off[slot][tid], S.off[slot][tid + 1], chunk, S.sum, S.cl, S.scan, S.skey,
+                                        S.wv, S.wk, S.wkf);
             const int i = b * BS + tid;
-            float4 fr = cur.far;
-            if (cur.lc > kLateCap) {
+            const float2 bs = S.base[slot][tid];
+            const float x = S.px[slot][tid], y = S.py[slot][tid];
+            float fx = sm.x + bs.x, fy = sm.y + bs.y;
+            if (S.ovf[slot] && J.late_cnt[i] > kLateCap) {
+                float4 fr;
                 int dummy = 0;
-                (void)bh_walk(wa, i, cur.x, cur.y, 0, J.pos, fr, nullptr, dummy, 0);
+                (void)bh_walk(wa, i, x, y, 0, J.pos, fr, nullptr, dummy, 0);
+                fx += negRK2 * (fr.x - fr.z);
+                fy += negRK2 * (fr.y - fr.w);
             }
-            const float fx = ((sm.x + cur.old.x) + cur.atte.x) + negRK2 * (fr.x - fr.z);
-            const float fy = ((sm.y + cur.old.y) + cur.atte.y) + negRK2 * (fr.y - fr.w);
             if (stop) {
                 J.fout[2 * tid] = (double)fx;
                 J.fout[2 * tid + 1] = (double)fy;
             } else {
+                float2 np{x, y};
                 const double f2 = (double)fx * fx + (double)fy * fy;
                 if (!isfinite(f2)) {
                     ++bad;
@@ -1324,17 +1374,19 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
                     e_iter += f2;
                     if (f2 > 0.0) {
                         const float sc = step / sqrtf(fx * fx + fy * fy);
-                        st<float2>(J.pos, i, float2{cur.x + sc * fx, cur.y + sc * fy});
+                        np = float2{x + sc * fx, y + sc * fy};
+                        st<float2>(J.pos, i, np);
                     }
                 }
+                if (use_win) win[i - wbase] = np;
             }
         }
-        if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1, nxt);
+        if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1, rd);
         __syncthreads();
     };
     for (int b = first; b <= last; b += 2) {
-        chain_step(b, rA, pA, rB, pB);
-        if (b + 1 <= last) chain_step(b + 1, rB, pB, rA, pA);
+        chain_step(b, pA, pB);
+        if (b + 1 <= last) chain_step(b + 1, pB, pA);
     }
     if (bad) atomicAdd(&J.ctr->nonfinite, bad);
     const double e = block_sum_fixed(e_iter, S.wsd);
@@ -1383,6 +1435,7 @@ struct BHEngine {
     bool ev_used[2] = {false, false};
     int total[PT_COUNT] = {};
     int nseg = 1;                       // most chain segments of any job
+    size_t win_bytes = 0;               // chain window: the largest segment of any job
     hipGraph_t graph = nullptr;         // one captured iteration of the current set
     hipGraphExec_t exec = nullptr;
 };
@@ -1407,6 +1460,14 @@ int bh_engine_create(hipStream_t s, BHEngine **out) {
             set_error("hipEventCreate failed: %s", hipGetErrorString(r));
             return BL_E_HIP;
         }
+    }
+    // the chain's window is dynamic LDS beyond the 64 KB default
+    hipError_t r = hipFuncSetAttribute((const void *)chain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(float2) * kWindow));
+    if (r != hipSuccess) {
+        bh_engine_destroy(e);
+        set_error("hipFuncSetAttribute(chain_kernel) failed: %s", hipGetErrorString(r));
+        return BL_E_HIP;
     }
     *out = e;
     return BL_OK;
@@ -1443,7 +1504,20 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->first_batch = (decltype(J->first_batch))(spec.first_batch);
     J->last_batch = (decltype(J->last_batch))(spec.last_batch);
     J->stop_batch = (decltype(J->stop_batch))(spec.stop_batch);
-    J->nseg = (decltype(J->nseg))(spec.all_live ? 1 : std::max(1, std::min(kMaxSegments, (int)(g->nb / kSegBatches))));
+    {
+        // enough segments for the window, and one per kSegBatches batches
+        // (up to kMaxSegments) to move old entries off the chain
+        int ns = 1;
+        if (!spec.all_live) {
+            const int nb = (int)g->nb, lmax = kWindow / (int)g->p.batch_size;
+            if (lmax < 1) {
+                set_error("batch size %d above the chain window", (int)g->p.batch_size);
+                return BL_E_INVAL;
+            }
+            ns = std::max(std::max(1, std::min(kMaxSegments, nb / kSegBatches)), (nb + lmax - 1) / lmax);
+        }
+        J->nseg = (decltype(J->nseg))ns;
+    }
     J->step0 = (decltype(J->step0))(g->p.step0);
     J->decay = (decltype(J->decay))(g->p.step_decay);
     J->kiter = (decltype(J->kiter))(h.kiter);
@@ -1521,7 +1595,13 @@ int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
         e->total[t] = pre[G];
     }
     e->nseg = 1;
-    for (int j = 0; j < G; ++j) e->nseg = std::max(e->nseg, (int)jobs[j].nseg);
+    e->win_bytes = 0;
+    for (int j = 0; j < G; ++j) {
+        const BHJob &J = jobs[j];
+        e->nseg = std::max(e->nseg, (int)J.nseg);
+        if (!J.all_live)
+            e->win_bytes = std::max(e->win_bytes, sizeof(float2) * (size_t)J.BS * ((J.nb + J.nseg - 1) / J.nseg));
+    }
     BL_HIP(hipMemcpyAsync(e->d_jobs[s], e->h_jobs[s], sizeof(BHJob) * G, hipMemcpyHostToDevice, e->stream));
     BL_HIP(hipMemcpyAsync(e->d_pre[s], e->h_pre[s], sizeof(int) * PT_COUNT * (e->cap + 1),
                           hipMemcpyHostToDevice, e->stream));
@@ -1584,7 +1664,9 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
     for (int seg = 0; seg < e->nseg; ++seg) {
         BH_LAUNCH(old_sum_kernel, PT_SEG, 256, seg);
-        BH_LAUNCH(chain_kernel, PT_ONE, kChainThreads, seg);
+        if (e->total[PT_ONE] > 0)
+            hipLaunchKernelGGL(chain_kernel, dim3(e->total[PT_ONE]), dim3(kChainThreads), e->win_bytes, e->stream,
+                               jobs, e->d_pre[e->cur] + PT_ONE * (e->cap + 1), e->G, seg);
     }
     if (prof) BL_TRY(prof_end(prof, slot));
     BL_HIP(hipGetLastError());
