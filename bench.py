@@ -30,8 +30,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X vector FP64
 # Algorithmic work per unit (see the design notes):
 BYTES_PER_VISIT = 24.0           # float4 (centroid, side^2, count) + int2 (skip, vertex) per node visit
 BYTES_PER_WALK_VERTEX = 32.0     # order id 4 + own x,y 8 + far-field sum 16 + late count 4
-BYTES_PER_ENTRY = 12.0           # CSR or moved-leaf entry: 4 B id + 8 B live x,y
-BYTES_PER_CHAIN_VERTEX = 52.0    # rowptr 8 + late count 4 + far sum 16 + x,y read 8 + write 8 + force 8
+BYTES_PER_LIST_WORD = 8.0        # late-list entry: row in batch << 32 | vertex (bit 31: leaf)
+BYTES_PER_GATHER = 8.0           # x,y of the vertex an entry refers to
+BYTES_PER_CHAIN_ROW = 56.0       # list offset 4 + leaf count 4 + x,y 8 + far sum 16 + early attraction 8
+                                 # + old sum 8 + x,y write 8 (recent gathers come from the LDS window)
+BYTES_PER_OLD_ROW = 20.0         # list offset 4 + x,y 8 + old sum write 8
 FLOP_PER_PAIR = 10.0             # 2 sub, d^2 (2 mul + 1 add), 1 reciprocal, 2 FMA
 # HBM bytes per launch of a workload's dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (FETCH_SIZE scaled by 2.0, the factor a plain copy of known size shows; WRITE_SIZE by 1.0).
@@ -117,6 +120,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel hipEvent timing")
+    ap.add_argument("--profile-steps", type=int, default=100, help="iterations of the per-kernel timing run")
     ap.add_argument("--precision", default="fp32_kahan")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -161,8 +165,6 @@ def main():
     if args.warmup > 0:
         dev.run(args.warmup)
     dev.set_coords(x0, y0)
-    if not args.no_profile:
-        dev.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     energy, st = dev.run(steps)
@@ -177,8 +179,16 @@ def main():
            "config": describe(w, steps)}
 
     if not args.no_profile:
+        # per-kernel hipEvent timing in a separate run from the same start (its
+        # event records between launches would slow the timed run)
+        psteps = min(steps, args.profile_steps)
+        dev.set_coords(x0, y0)
+        dev.profile(True)
+        _, st = dev.run(psteps)
+        dev.profile(False)
+        out["profiled_steps"] = psteps
         kern = {}
-        for name in ("tree_build", "far_kernel", "chain_kernel", "rows_kernel", "step_kernel",
+        for name in ("tree_build", "far_kernel", "old_sum_kernel", "chain_kernel", "rows_kernel", "step_kernel",
                      "finalize_kernel", "exact_graph_kernel"):
             ms, cnt = dev.profile_read(name)
             if cnt:
@@ -186,24 +196,26 @@ def main():
         late = dev.profile_read("late_entries")[1]
         if w["mode"] == "bh":
             visits = st["node_visits"]
-            far = kern["far_kernel"]
-            chain = kern["chain_kernel"]
-            far_bytes = (BYTES_PER_VISIT * visits + BYTES_PER_WALK_VERTEX * g.n * far["launches"]) / far["launches"]
-            chain_bytes = (BYTES_PER_ENTRY * (g.nnz * chain["launches"] + late) +
-                           BYTES_PER_CHAIN_VERTEX * g.n * chain["launches"]) / chain["launches"]
-            far["achieved_GBs"] = far_bytes / (far["avg_us"] * 1e-6) / 1e9
-            chain["achieved_GBs"] = chain_bytes / (chain["avg_us"] * 1e-6) / 1e9
-            far["bytes_per_launch"], chain["bytes_per_launch"] = far_bytes, chain_bytes
-            dom_name = max(("far_kernel", "chain_kernel", "tree_build"), key=lambda k: kern[k]["total_ms"])
-            dom = kern[dom_name] if dom_name != "tree_build" else far
-            if dom_name == "tree_build":
-                dom_name = "far_kernel"
+            old_e, recent_e = dev.profile_read("old_entries")[1], dev.profile_read("recent_entries")[1]
+            rows = float(g.n) * psteps   # every row once per iteration in each kernel below
+            work = {"far_kernel": BYTES_PER_VISIT * visits + BYTES_PER_WALK_VERTEX * rows,
+                    "chain_kernel": BYTES_PER_CHAIN_ROW * rows + BYTES_PER_LIST_WORD * recent_e,
+                    "old_sum_kernel": BYTES_PER_OLD_ROW * rows + (BYTES_PER_LIST_WORD + BYTES_PER_GATHER) * old_e}
+            for k, total in work.items():
+                if k in kern:
+                    kern[k]["bytes_per_launch"] = total / kern[k]["launches"]
+                    kern[k]["achieved_GBs"] = kern[k]["bytes_per_launch"] / (kern[k]["avg_us"] * 1e-6) / 1e9
+            dom_name = max((k for k in work if k in kern), key=lambda k: kern[k]["total_ms"])
+            dom = kern[dom_name]
             out["roofline"] = {"bound": "hbm", "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": dom["achieved_GBs"] / HBM_PEAK_GBS,
                                "traffic": measured_traffic(args.config, dom_name), "kernel": dom_name,
                                "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
-            out["bh"] = {"node_visits_per_vertex": visits / (g.n * steps), "late_entries_per_vertex":
-                         late / (g.n * steps), "late_overflow": st["late_overflow"]}
+            nb = (g.n + w["batch_size"] - 1) // w["batch_size"]
+            out["bh"] = {"node_visits_per_vertex": visits / rows, "late_entries_per_vertex": late / rows,
+                         "old_entries_per_vertex": old_e / rows, "recent_entries_per_vertex": recent_e / rows,
+                         "late_overflow": st["late_overflow"],
+                         "chain_us_per_batch": 1e3 * kern["chain_kernel"]["total_ms"] / (nb * psteps)}
         else:
             nb = (g.n + w["batch_size"] - 1) // w["batch_size"]
             pairs = float(g.n) * g.n * steps
@@ -214,7 +226,7 @@ def main():
             else:   # small graph: the whole run is one launch of the one-workgroup kernel
                 dom_name = "exact_graph_kernel"
                 dom = kern[dom_name]
-                flop_per_launch = FLOP_PER_PAIR * pairs / dom["launches"]
+                flop_per_launch = FLOP_PER_PAIR * float(g.n) * g.n * psteps / dom["launches"]
             dom["achieved_TFLOPs"] = flop_per_launch / (dom["avg_us"] * 1e-6) / 1e12
             dom["flop_per_launch"] = flop_per_launch
             peak = FP32_VALU_PEAK_TFLOPS if args.precision != "fp64" else FP64_VALU_PEAK_TFLOPS

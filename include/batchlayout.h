@@ -175,10 +175,13 @@ int bl_graph_destroy(bl_graph *h);
 int bl_graph_profile(bl_graph *h, int32_t enable);
 
 /* Totals since the last bl_graph_profile(h, 1) for one kernel: "rows_kernel",
- * "panel_kernel", "finalize_kernel" (exact mode), "tree_build" (the whole
- * quadtree build sequence), "far_kernel", "chain_kernel" (Barnes-Hut).  The
- * name "late_entries" returns, in *launches, the number of moved-leaf entries
- * the far-field walks listed for the chain. */
+ * "step_kernel", "finalize_kernel", "exact_graph_kernel" (exact mode),
+ * "tree_build" (the whole quadtree build sequence, one entry per iteration),
+ * "far_kernel", "old_sum_kernel", "chain_kernel" (Barnes-Hut, one entry per
+ * launch).  Counts instead of times, returned in *launches: "late_entries"
+ * (moved-leaf entries the far-field walks listed), "old_entries" and
+ * "recent_entries" (moved-neighbour and moved-leaf entries summed by the
+ * segment kernel and by the chain). */
 int bl_graph_profile_read(bl_graph *h, const char *kernel, double *total_ms, int64_t *launches);
 
 /* -------------------------------------------------- many graphs at once

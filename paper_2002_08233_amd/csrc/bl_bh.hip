@@ -47,6 +47,7 @@ constexpr int kHeavyRow = 256;        // early entries above which a whole workg
 constexpr int kLateHeavyRow = 256;    // moved neighbours above which a whole workgroup copies the row
 constexpr int kMaxChainRows = 1024;   // batch-size limit of the Barnes-Hut chain
 constexpr int kEnt = 3;               // late entries per thread per pass (held in registers)
+constexpr int kMinRun = 1;            // entries per thread at least (packs a step's entries into fewer waves)
 // An iteration's chain runs in up to kMaxSegments launches (one per
 // kSegBatches batches).  Before the launch of a segment, a full-chip kernel
 // sums, for every row of the segment, the late entries that refer to
@@ -165,14 +166,37 @@ __global__ __launch_bounds__(256) void bbox_kernel(BH_KERNEL_ARGS) {
         s_last = (atomicAdd((unsigned *)J.ticket, 1u) == (unsigned)jb.nblocks - 1);
     }
     __syncthreads();
-    if (!s_last || threadIdx.x != 0) return;
+    if (!s_last) return;
+    // the last workgroup combines the partial boxes, one per thread
     __threadfence();
     float a = FLT_MAX, b = -FLT_MAX, c = FLT_MAX, d = -FLT_MAX;
-    for (int q = 0; q < jb.nblocks; ++q) {
-        a = fminf(a, J.bbox_part[4 * q + 0]);
-        b = fmaxf(b, J.bbox_part[4 * q + 1]);
-        c = fminf(c, J.bbox_part[4 * q + 2]);
-        d = fmaxf(d, J.bbox_part[4 * q + 3]);
+    for (int q = threadIdx.x; q < jb.nblocks; q += 256) {
+        const float4 v = ld<float4>((gptr<const float4>)J.bbox_part, q);
+        a = fminf(a, v.x);
+        b = fmaxf(b, v.y);
+        c = fminf(c, v.z);
+        d = fmaxf(d, v.w);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        a = fminf(a, __shfl_xor(a, o, kWave));
+        b = fmaxf(b, __shfl_xor(b, o, kWave));
+        c = fminf(c, __shfl_xor(c, o, kWave));
+        d = fmaxf(d, __shfl_xor(d, o, kWave));
+    }
+    __syncthreads();   // s[] was read by thread 0 above
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        s[0][w] = a;
+        s[1][w] = b;
+        s[2][w] = c;
+        s[3][w] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int q = 1; q < 256 / kWave; ++q) {
+        a = fminf(a, s[0][q]);
+        b = fmaxf(b, s[1][q]);
+        c = fminf(c, s[2][q]);
+        d = fmaxf(d, s[3][q]);
     }
     const float wx = b - a, wy = d - c;
     const float W = fmaxf(wx, wy);
@@ -747,6 +771,30 @@ __global__ void late_prefix_kernel(BH_KERNEL_ARGS) {
 }
 
 // Light rows: 8 lanes per row.
+// Attraction terms of one lane's entries e, e + S, e + 2S, ... below e1, in
+// that order; U entries' loads are issued before their terms are added.
+template <int U, int S>
+__device__ __forceinline__ void att_run(const BHJob &J, int e, int e1, float2 pi, float invK, float &ax, float &ay) {
+    for (; e < e1; e += U * S) {
+        int c[U];
+        float2 pj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = e + u * S < e1 ? J.colidx[e + u * S] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0) pj[u] = ld<float2>(J.pos, c[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c[u] >= 0) {
+                const float dx = pj[u].x - pi.x, dy = pj[u].y - pi.y;
+                const float d = sqrtf(dx * dx + dy * dy) * invK;
+                ax = fmaf(d, dx, ax);
+                ay = fmaf(d, dy, ay);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void att_early_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     const int i = (jb.local * blockDim.x + threadIdx.x) >> 3;
@@ -757,13 +805,7 @@ __global__ __launch_bounds__(256) void att_early_kernel(BH_KERNEL_ARGS) {
     const float2 pi = ld<float2>(J.pos, i);
     const float invK = J.invK;
     float ax = 0.f, ay = 0.f;
-    for (int e = e0 + sub; e < e1; e += 8) {
-        const float2 pj = ld<float2>(J.pos, J.colidx[e]);
-        const float dx = pj.x - pi.x, dy = pj.y - pi.y;
-        const float d = sqrtf(dx * dx + dy * dy) * invK;
-        ax = fmaf(d, dx, ax);
-        ay = fmaf(d, dy, ay);
-    }
+    att_run<4, 8>(J, e0 + sub, e1, pi, invK, ax, ay);
     ax = group_sum<8>(ax);
     ay = group_sum<8>(ay);
     if (sub == 0) st<float2>(J.atte, i, float2{ax, ay});
@@ -780,13 +822,7 @@ __global__ __launch_bounds__(256) void att_heavy_kernel(BH_KERNEL_ARGS) {
         const int e0 = J.rowptr[i] + J.late_att[i], e1 = J.rowptr[i + 1];
         const float2 pi = ld<float2>(J.pos, i);
         float ax = 0.f, ay = 0.f;
-        for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
-            const float2 pj = ld<float2>(J.pos, J.colidx[e]);
-            const float dx = pj.x - pi.x, dy = pj.y - pi.y;
-            const float d = sqrtf(dx * dx + dy * dy) * invK;
-            ax = fmaf(d, dx, ax);
-            ay = fmaf(d, dy, ay);
-        }
+        att_run<8, 256>(J, e0 + (int)threadIdx.x, e1, pi, invK, ax, ay);
         ax = wave_sum(ax);
         ay = wave_sum(ay);
         if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -853,6 +889,8 @@ __global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
         }
     }
     if (r == 0) {
+        atomicAdd(&J.ctr->old_total, (unsigned long long)tot_o);
+        atomicAdd(&J.ctr->recent_total, (unsigned long long)tot_r);
         J.bold[b] = tot_o;
         J.bbase[b] = tot_o + tot_r;
         if (b == 0) J.bbase[J.nb] = 0;
@@ -917,6 +955,7 @@ __global__ __launch_bounds__(256) void late_fill_heavy_kernel(BH_KERNEL_ARGS) {
         const size_t bo = (size_t)J.bbase[b] + J.roff_old[i];
         const size_t br = (size_t)J.bbase[b] + J.bold[b] + J.roff[i];
         const int rs = J.rowptr[i], la = J.late_att[i], oa = J.old_att[i];
+#pragma unroll 4
         for (int k = threadIdx.x; k < la; k += 256)
             J.ent[k < oa ? bo + k : br + (k - oa)] = rbits | (unsigned)J.colidx[rs + k];
     }
@@ -1238,7 +1277,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
     }
     auto nrows = [&](int b) { return min(BS, n - b * BS); };
     auto run_of = [&](int E, int &e0, int &e1) {
-        const int chunk = max(1, (E + kChainThreads - 1) / kChainThreads);
+        const int chunk = max(kMinRun, (E + kChainThreads - 1) / kChainThreads);
         e0 = min(tid * chunk, E);
         e1 = min(e0 + chunk, E);
         return chunk;
@@ -1308,6 +1347,9 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         // costs a cache-line lookup in this CU's address unit)
         const int m0 = min(kEnt, e1 - e0);
         float xj[kEnt], yj[kEnt];
+        // waves past the last thread with entries have nothing to sum (the
+        // row totals read carries of earlier waves only)
+        const bool wave_busy = __builtin_amdgcn_readfirstlane(tid & ~(kWave - 1)) * chunk < E;
 #pragma unroll
         for (int q = 0; q < kEnt; ++q) {
             xj[q] = 0.f;
@@ -1331,13 +1373,15 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         float2 firstp;
         const int key0 = e0 < e1 ? (int)(ce[0] >> 32) : -1 - tid;   // row of the run's first entry
         gptr<const unsigned long long> lst = J.ent + S.mb[b & 15] + S.mo[b & 15];
-        if (use_win)
-            run_sum<kEnt>(lst, pl, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl, invK,
-                          negRK2);
-        else
-            run_sum<kEnt>(lst, pg, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl, invK,
-                          negRK2);
-        carry_scan_wave(firstp, key0, S.scan, S.skey, S.wv, S.wk, S.wkf);
+        if (wave_busy) {
+            if (use_win)
+                run_sum<kEnt>(lst, pl, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl,
+                              invK, negRK2);
+            else
+                run_sum<kEnt>(lst, pg, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl,
+                              invK, negRK2);
+            carry_scan_wave(firstp, key0, S.scan, S.skey, S.wv, S.wk, S.wkf);
+        }
         if (tid == 0) S.ovf[slot ^ 1] = 0;   // last read in the previous step
         __syncthreads();
         if (tid == 0) {   // the slot of batch b now holds batch b + 16
@@ -1661,14 +1705,18 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 2);
     BH_LAUNCH(late_fill_kernel, PT_VERT8, 256);
     BH_LAUNCH(late_fill_heavy_kernel, PT_HEAVY, 256);
-    if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
     for (int seg = 0; seg < e->nseg; ++seg) {
-        BH_LAUNCH(old_sum_kernel, PT_SEG, 256, seg);
+        if (e->total[PT_SEG] > 0) {
+            if (prof) BL_TRY(prof_begin(prof, PK_OLDSUM, &slot));
+            BH_LAUNCH(old_sum_kernel, PT_SEG, 256, seg);
+            if (prof) BL_TRY(prof_end(prof, slot));
+        }
+        if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
         if (e->total[PT_ONE] > 0)
             hipLaunchKernelGGL(chain_kernel, dim3(e->total[PT_ONE]), dim3(kChainThreads), e->win_bytes, e->stream,
                                jobs, e->d_pre[e->cur] + PT_ONE * (e->cap + 1), e->G, seg);
+        if (prof) BL_TRY(prof_end(prof, slot));
     }
-    if (prof) BL_TRY(prof_end(prof, slot));
     BL_HIP(hipGetLastError());
     return BL_OK;
 }

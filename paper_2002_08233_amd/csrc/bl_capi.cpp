@@ -344,6 +344,8 @@ static int run_impl(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t
     if (g->prof) {
         BL_TRY(prof_collect(g));
         g->prof->late_total += (long long)c.late_total;
+        g->prof->old_total += (long long)c.old_total;
+        g->prof->recent_total += (long long)c.recent_total;
     }
     if (st) {
         std::memset(st, 0, sizeof *st);
@@ -363,8 +365,9 @@ int bl_graph_run(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t st
     return run_impl(g, iterations, start_iter, stop_batch, energy_out, fx, fy, st);
 }
 
-static const char *kProfNames[PK_COUNT] = {"rows_kernel", "step_kernel", "finalize_kernel", "tree_build",
-                                           "far_kernel", "chain_kernel", "exact_graph_kernel"};
+static const char *kProfNames[PK_COUNT] = {"rows_kernel", "step_kernel",        "finalize_kernel",
+                                           "tree_build",  "far_kernel",         "chain_kernel",
+                                           "exact_graph_kernel", "old_sum_kernel"};
 
 int bl_graph_profile(bl_graph *g, int32_t enable) {
     if (!g) return fail(BL_E_INVAL, "graph is NULL");
@@ -379,6 +382,8 @@ int bl_graph_profile(bl_graph *g, int32_t enable) {
         P.launches[q] = 0;
     }
     P.late_total = 0;
+    P.old_total = 0;
+    P.recent_total = 0;
     P.on = enable != 0;
     return BL_OK;
 }
@@ -391,6 +396,14 @@ int bl_graph_profile_read(bl_graph *g, const char *kernel, double *total_ms, int
     BL_TRY(prof_collect(g));
     if (!std::strcmp(kernel, "late_entries")) {
         *launches = g->prof->late_total;
+        return BL_OK;
+    }
+    if (!std::strcmp(kernel, "old_entries")) {
+        *launches = g->prof->old_total;
+        return BL_OK;
+    }
+    if (!std::strcmp(kernel, "recent_entries")) {
+        *launches = g->prof->recent_total;
         return BL_OK;
     }
     for (int q = 0; q < PK_COUNT; ++q)

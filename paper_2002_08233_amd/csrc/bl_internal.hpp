@@ -37,12 +37,14 @@ struct Counters {
     unsigned long long visits;
     unsigned long long late_overflow;
     unsigned long long late_total;
+    unsigned long long old_total;      // late entries summed by the segment kernel
+    unsigned long long recent_total;   // late entries summed by the chain
 };
 
 // Per-kernel device time, measured with hipEvents around launches when a
 // job's profiling is on.
-enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_GRAPH, PK_COUNT };
-constexpr int kProfPool = 2048;
+enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_GRAPH, PK_OLDSUM, PK_COUNT };
+constexpr int kProfPool = 8192;
 struct Prof {
     bool on = false;
     int used = 0;
@@ -51,6 +53,7 @@ struct Prof {
     double ms[PK_COUNT] = {};
     long long launches[PK_COUNT] = {};
     long long late_total = 0;
+    long long old_total = 0, recent_total = 0;
 };
 
 struct BHEngine;
