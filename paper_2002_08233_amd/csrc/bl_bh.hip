@@ -37,8 +37,8 @@ namespace bl {
 
 constexpr int kBBoxBlocks = 256;
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 keys per tile
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;     // 2048 keys per tile
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 values per tile
