@@ -175,7 +175,7 @@ int bl_graph_destroy(bl_graph *h);
 int bl_graph_profile(bl_graph *h, int32_t enable);
 
 /* Totals since the last bl_graph_profile(h, 1) for one kernel: "rows_kernel",
- * "step_kernel", "finalize_kernel", "exact_graph_kernel" (exact mode),
+ * "step_kernel", "finalize_kernel", "exact_graph_kernel", "steps_kernel" (exact mode),
  * "tree_build" (the whole quadtree build sequence, one entry per iteration),
  * "far_kernel", "old_sum_kernel", "chain_kernel" (Barnes-Hut, one entry per
  * launch).  Counts instead of times, returned in *launches: "late_entries"

@@ -131,6 +131,7 @@ extern "C" int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const dou
     for (int q = 0; q < G; ++q) {
         const bool bh = params[q]->mode == BL_BH;
         BL_TRY(bl_graph_create(graphs[q], params[q], bh ? B.s_bh : B.s_ex, &B.gs[q]));
+        B.gs[q]->coop = false;   // runs beside the other graphs' launches
         BL_TRY(bl_graph_set_coords(B.gs[q], x0[q], y0[q], 0));
         const size_t N = (size_t)graphs[q]->n;
         xy0[q].resize(2 * N);

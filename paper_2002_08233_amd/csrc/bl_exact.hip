@@ -787,6 +787,109 @@ __global__ __launch_bounds__(kRows * L) void step_kernel(GView<T> G, int c, int 
     if (fa.fin >= 0 && __syncthreads_or(fin_row)) finish_chunkL<T, KAHAN, L>(G, fa, first, xi, yi, fx, fy, e2, ws);
 }
 
+// ------------------------------------------------- persistent whole run
+// A run as one launch of co-resident workgroups (cooperative launch).  Each
+// workgroup owns fixed 256-row chunks and walks the steps in order; a step
+// waits only until the batch whose columns it adds has moved, and the
+// workgroups holding the next batch's rows move them and count the move.
+// Every wait is for an earlier step, so the launch always progresses; a wait
+// that runs out sets a flag that makes every workgroup leave, and the run
+// reports a time-out.  The arithmetic is that of step_kernel.
+struct StepsArgs {
+    int e0, e1;            // steps [e0, e1) of the run; step e adds batch (e-1) % nb, finishes batch e % nb
+    int start, lastk;      // first and last iteration of the run
+    double step_start;     // step length of iteration `start`
+    double decay;
+    double *energy;        // energy[k - start]
+    unsigned *moved;       // [nb] chunk moves of each batch since the run started
+    unsigned long long *abort;
+    long long spin_limit;  // polls before a wait gives up
+};
+
+// Thread 0: wait until *cnt >= need (the caller then acquires).  Returns 0
+// when the launch is being abandoned.
+__device__ __forceinline__ int wait_moved(unsigned *cnt, unsigned need, unsigned long long *abort,
+                                          long long limit) {
+    for (long long it = 0;; ++it) {
+        if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return 1;
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0;
+        if (it >= limit) {
+            __hip_atomic_store(abort, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ __forceinline__ int batch_chunks(int b, int BS, int n) {
+    const int b0 = b * BS, b1 = min(b0 + BS, n);
+    return (b1 - 1) / kRows - b0 / kRows + 1;
+}
+
+template <typename T, bool KAHAN, int L>
+__global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs A, FinArgs<T> fa0) {
+    __shared__ typename V2<T>::type cols[kTile];
+    __shared__ double ws[kRows * L / kWave];
+    __shared__ double e2[kRows];
+    __shared__ int s_go;
+    const int nb = G.nb, nch = (G.n + kRows - 1) / kRows;
+    int kf_cur = A.start;
+    double st_cur = A.step_start;   // step length of iteration kf_cur (the host's sequential product)
+    for (int e = A.e0; e < A.e1; ++e) {
+        const int c = (e - 1) % nb, pk = A.start + (e - 1) / nb;
+        const int fin = e % nb, kf = A.start + e / nb;
+        const int do_next = pk < A.lastk ? 1 : 0;
+        while (kf_cur < kf) {
+            st_cur *= A.decay;
+            ++kf_cur;
+        }
+        // batch c has moved in iteration pk
+        // (thread 0's acquire invalidates the caches this workgroup reads
+        // through; the barrier orders the other waves' loads after it)
+        if (threadIdx.x == 0) {
+            const unsigned need = (unsigned)(pk - A.start + 1) * (unsigned)batch_chunks(c, G.BS, G.n);
+            s_go = wait_moved(A.moved + c, need, A.abort, A.spin_limit);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (!s_go) return;
+        const int fb0 = fin * G.BS, fb1 = min(fb0 + G.BS, G.n);
+        const int fch0 = fb0 / kRows, fch1 = (fb1 - 1) / kRows;
+        // the chunks of the batch to finish first: the next step waits for them
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int q = blockIdx.x; q < nch; q += gridDim.x) {
+                const bool is_fin = q >= fch0 && q <= fch1;
+                if ((pass == 0) != is_fin) continue;
+                const int first = q * kRows, last = min(first + kRows, G.n) - 1;
+                const bool work = last / G.BS > c || (do_next && first / G.BS <= c) || is_fin;
+                if (!work) continue;
+                T xi = 0, yi = 0, fx = 0, fy = 0;
+                panel_rowsL<T, KAHAN, L>(G, first, c, pk & 1, do_next, fin, cols, xi, yi, fx, fy);
+                if (is_fin) {
+                    FinArgs<T> fa = fa0;
+                    fa.fin = fin;
+                    fa.pf = kf & 1;
+                    fa.step = (T)st_cur;
+                    fa.energy_k = A.energy + (kf - A.start);
+                    finish_chunkL<T, KAHAN, L>(G, fa, first, xi, yi, fx, fy, e2, ws);
+                    // every wave's stores complete, then one release of them and the count
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    if (threadIdx.x == 0)
+                        __hip_atomic_fetch_add(A.moved + fin, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    }
+}
+
+// Move counters of a persistent run: batch 0 of its first iteration was
+// finished before the launch.
+__global__ void moved_init_kernel(unsigned *moved, int nb, unsigned first_chunks) {
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) moved[b] = b == 0 ? first_chunks : 0u;
+}
+
+
 // Finish of batch fa.fin only (its sums are complete in memory).
 template <typename T, bool KAHAN>
 __global__ __launch_bounds__(kRows) void finalize_kernel(GView<T> G, FinArgs<T> fa) {
@@ -1006,6 +1109,49 @@ struct ExactOps {
         return prof_end(g, slot);
     }
 
+    // Steps [e0, e1) of a run as one cooperative launch of co-resident
+    // workgroups (steps_kernel).  `launched` stays 0 when the device cannot
+    // hold a workgroup of it; the caller then launches step by step.
+    static int steps(bl_graph *g, int e0, int e1, int start, int lastk, int &launched) {
+        launched = 0;
+        const int L = lanes(g, g->n);
+        const void *f = L == 1 ? (const void *)steps_kernel<T, KAHAN, 1>
+                               : (L == 2 ? (const void *)steps_kernel<T, KAHAN, 2> : (const void *)steps_kernel<T, KAHAN, 4>);
+        int dev = 0, cus = 0, per_cu = 0;
+        BL_HIP(hipGetDevice(&dev));
+        BL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        BL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kRows * L, 0));
+        const int nch = (g->n + kRows - 1) / kRows;
+        const int grid = std::min(nch, per_cu * cus);
+        if (grid < 1) return BL_OK;
+        long long limit = 1ll << 22;   // polls of about a microsecond each
+        if (const char *v = getenv("BL_EXACT_SPIN_LIMIT")) limit = atoll(v);
+        const int BS = g->p.batch_size;
+        const unsigned first_chunks = (unsigned)((std::min(BS, g->n) - 1) / kRows + 1);
+        hipLaunchKernelGGL(moved_init_kernel, dim3(1), dim3(256), 0, g->stream, g->ex.moved, g->nb, first_chunks);
+        BL_HIP(hipGetLastError());
+        StepsArgs A;
+        A.e0 = e0;
+        A.e1 = e1;
+        A.start = start;
+        A.lastk = lastk;
+        A.step_start = step_at(g->p, start);
+        A.decay = g->p.step_decay;
+        A.energy = g->energy;
+        A.moved = g->ex.moved;
+        A.abort = &g->counters->wait_abort;
+        A.spin_limit = limit;
+        FinArgs<T> fa0 = fin_args(g, 0, start, nullptr, nullptr, 1);
+        GView<T> G = view(g);
+        void *args[] = {&G, &A, &fa0};
+        int slot;
+        BL_TRY(prof_begin(g, PK_STEPS, &slot));
+        BL_HIP(hipLaunchCooperativeKernel(f, dim3(grid), dim3(kRows * L), args, 0, g->stream));
+        BL_TRY(prof_end(g, slot));
+        launched = 1;
+        return BL_OK;
+    }
+
     static int finalize(bl_graph *g, const FinArgs<T> &fa) {
         const int BS = g->p.batch_size;
         const int b0 = fa.fin * BS, b1 = std::min(g->n, b0 + BS);
@@ -1033,6 +1179,12 @@ struct ExactOps {
                             probe ? 0 : 1);
         };
         BL_TRY(finalize(g, fin_of(0)));
+        // the rest as one persistent launch where the device may be held
+        if (stop_batch < 0 && nb > 1 && total > 1 && total < (1ll << 30) && g->coop && !getenv("BL_EXACT_STEPWISE")) {
+            int launched = 0;
+            BL_TRY(steps(g, 1, (int)total, start, lastk, launched));
+            if (launched) return BL_OK;
+        }
         for (long long e = 1; e < total; ++e) {
             const int pk = start + (int)((e - 1) / nb), pb = (int)((e - 1) % nb);
             const int do_next = pk < lastk ? 1 : 0;
@@ -1165,6 +1317,7 @@ int exact_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&g->ex.epart, sizeof(double) * (size_t)(BS / kRows + 2)));
     BL_TRY(graph_alloc(g, (void **)&g->ex.ticket, 256));
     BL_TRY(graph_alloc(g, &g->ex.d_job, sizeof(ExactJob)));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.moved, sizeof(unsigned) * (size_t)g->nb));
     BL_HIP(hipMemsetAsync(g->ex.ticket, 0, 256, g->stream));
     BL_TRY(graph_alloc(g, (void **)&g->ex.segoff, sizeof(int) * (n + 1)));
     BL_TRY(graph_alloc(g, (void **)&g->ex.cursor, sizeof(int) * n));
@@ -1193,7 +1346,8 @@ int exact_prepare(bl_graph *g) {
 // Segment bytes of a graph (at most one per CSR entry).
 size_t exact_footprint(int n, int64_t nnz, int BS, bool fp64) {
     const size_t N = (size_t)n, T2 = fp64 ? 16 : 8;
-    return 2 * (T2 * N + 8 * N) + 8 * (size_t)(BS / kRows + 2) + 256 + sizeof(ExactJob) + 4 * (N + 1) + 4 * N +
+    const size_t nb = (N + BS - 1) / BS;
+    return 2 * (T2 * N + 8 * N) + 8 * (size_t)(BS / kRows + 2) + 256 + sizeof(ExactJob) + 4 * nb + 4 * (N + 1) + 4 * N +
            8 * (size_t)std::max<int64_t>(nnz, 1) + 4 * 256;
 }
 

@@ -39,11 +39,12 @@ struct Counters {
     unsigned long long late_total;
     unsigned long long old_total;      // late entries summed by the segment kernel
     unsigned long long recent_total;   // late entries summed by the chain
+    unsigned long long wait_abort;     // a bounded device wait ran out (the launch left early)
 };
 
 // Per-kernel device time, measured with hipEvents around launches when a
 // job's profiling is on.
-enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_GRAPH, PK_OLDSUM, PK_COUNT };
+enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_GRAPH, PK_OLDSUM, PK_STEPS, PK_COUNT };
 constexpr int kProfPool = 8192;
 struct Prof {
     bool on = false;
@@ -117,6 +118,7 @@ struct ExactBuffers {
     double *epart;          // energy partials of the 256-row chunks of one batch
     unsigned *ticket;       // last-workgroup counter of the batch finalize
     void *d_job;            // one-job table of the one-workgroup kernel
+    unsigned *moved;        // [nb] chunk moves of each batch in the current persistent run
 };
 
 }  // namespace bl
@@ -146,6 +148,8 @@ struct bl_graph {
     int nowned = 0;
     bl::Prof *prof = nullptr;   // profiling state (NULL when never enabled)
     bool async_mem = false;     // device memory is stream-ordered (hipMallocAsync / hipFreeAsync on stream)
+    bool coop = true;           // may run an exact layout as one cooperative (persistent) launch; off when
+                                // the job shares the device with other work of this library
 };
 
 namespace bl {

@@ -131,6 +131,7 @@ void admit(bl_server *s) {
         }
         bl_csr csr{j->n, j->nnz, j->rowptr.data(), j->colidx.data()};
         int rc = graph_create_ex(&csr, &j->p, s->setup, true, &j->g);
+        if (rc == BL_OK) j->g->coop = false;   // shares the device with the other lanes
         if (rc == BL_OK) rc = bl_graph_set_coords(j->g, j->x0.data(), j->y0.data(), 0);
         if (rc == BL_OK && j->p.mode == BL_BH) rc = bh_set_iteration(j->g, j->p.start_iter);
         if (rc == BL_OK && hipStreamSynchronize(s->setup) != hipSuccess)

@@ -204,3 +204,38 @@ def test_hub_rows_and_big_batches():
             xs, ys = h.get_coords()
         ref = oracle.forces_exact(g.rowptr, g.colidx, xs, ys, stop * bs, min(n, stop * bs + bs))
         assert_forces(fx, fy, ref, what="bs=%d stop=%d" % (bs, stop))
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp64"])
+@pytest.mark.parametrize("n,bs", [(3000, 128), (2900, 300), (4100, 512), (1300, 256)])
+def test_persistent_run_equals_step_launches_bitwise(monkeypatch, precision, n, bs):
+    """A multi-workgroup run is one cooperative launch whose workgroups wait
+    on per-batch move counters; launching the steps one by one gives the same
+    bits.  Batch sizes below, across and above the 256-row chunks."""
+    g = _rand_graph(n, 8.0 / n, n + 11)
+    x0, y0 = I.uniform_coords(g.n, 31)
+    x0, y0 = _f32(x0), _f32(y0)
+    p = api.params(batch_size=bs, iterations=5, precision=precision, multi_wg=True)
+    xa, ya, ea, _ = api.layout(g, x0, y0, p)
+    monkeypatch.setenv("BL_EXACT_STEPWISE", "1")
+    xb, yb, eb, _ = api.layout(g, x0, y0, p)
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+
+
+def test_persistent_wait_limit_reports_timeout(monkeypatch):
+    """A spin limit of zero makes the first wait that is not already met give
+    up: every workgroup leaves, the run reports BL_E_TIMEOUT, and a new run
+    on a new job is unaffected."""
+    g = _rand_graph(4000, 8.0 / 4000, 4011)
+    x0, y0 = I.uniform_coords(g.n, 32)
+    x0, y0 = _f32(x0), _f32(y0)
+    p = api.params(batch_size=128, iterations=4, multi_wg=True)
+    monkeypatch.setenv("BL_EXACT_SPIN_LIMIT", "0")
+    with pytest.raises(api.BLError) as err:
+        api.layout(g, x0, y0, p)
+    assert err.value.code == -7
+    monkeypatch.delenv("BL_EXACT_SPIN_LIMIT")
+    xa, ya, ea, _ = api.layout(g, x0, y0, p)
+    monkeypatch.setenv("BL_EXACT_STEPWISE", "1")
+    xb, yb, eb, _ = api.layout(g, x0, y0, p)
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
