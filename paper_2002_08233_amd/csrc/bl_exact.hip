@@ -306,7 +306,16 @@ __device__ __forceinline__ void rows_block(const GView<T> &G, int first, int row
 // segment's first 16 entries are prefetched by the row's lanes halfway
 // through the first tile; longer segments (hub rows) are formed by all lanes
 // of the wave, one row at a time, and added by the lead lane in order.
-template <typename T, int L>
+// A coordinate that another workgroup of a running launch may have written:
+// an agent-scope load, coherent across the chip's L2 caches.
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// COH: the column batch was moved by another workgroup of the same launch
+// (persistent run), so its coordinates are read with agent-scope loads.
+template <typename T, int L, bool COH = false>
 __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool active, bool lead, int i, T xi, T yi,
                                                int s, int send, typename V2<T>::type *cols, T &qx, T &qy,
                                                bool &used) {
@@ -349,7 +358,10 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
     for (int t0 = c0; t0 < c1; t0 += kTile) {
         const int m = min(kTile, c1 - t0);
         __syncthreads();
-        for (int q = threadIdx.x; q < m; q += blockDim.x) cols[q] = T2{G.x[t0 + q], G.y[t0 + q]};
+        for (int q = threadIdx.x; q < m; q += blockDim.x) {
+            if constexpr (COH) cols[q] = T2{ld_agent(G.x + t0 + q), ld_agent(G.y + t0 + q)};
+            else cols[q] = T2{G.x[t0 + q], G.y[t0 + q]};
+        }
         __syncthreads();
         const int groups = m >> 2;
         const int hg = (t0 == c0) ? (groups >> 1) : 0;
@@ -401,7 +413,11 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
     }
     T ax = 0, ay = 0, lx = 0, ly = 0;
     const bool in_lds = (c1 - c0) <= kTile;
-    auto pos = [&](int j) { return in_lds ? cols[j - c0] : T2{G.x[j], G.y[j]}; };
+    auto pos = [&](int j) {
+        if (in_lds) return cols[j - c0];
+        if constexpr (COH) return T2{ld_agent(G.x + j), ld_agent(G.y + j)};
+        else return T2{G.x[j], G.y[j]};
+    };
     // entries 0..15, held by the row's lanes (entry u in lane u % L, slot u / L)
     const int base_lane = lane & ~(L - 1);
 #pragma unroll
@@ -570,7 +586,7 @@ __device__ __forceinline__ void panel_rows(const GView<T> &G, int first, int c, 
 // panel_rows with L lanes per row (workgroups of kRows * L, rows [first,
 // first + kRows)); the completed sum of a row of batch `fin` lands in the
 // lead lane's (fx, fy).
-template <typename T, bool KAHAN, int L>
+template <typename T, bool KAHAN, int L, bool COH = false>
 __device__ __forceinline__ void panel_rowsL(const GView<T> &G, int first, int c, int pc, int do_next, int fin,
                                             typename V2<T>::type *cols, T &xi, T &yi, T &fx, T &fy) {
     using T2 = typename V2<T>::type;
@@ -596,7 +612,7 @@ __device__ __forceinline__ void panel_rowsL(const GView<T> &G, int first, int c,
     }
     T qx, qy;
     bool used;
-    batch_contribL<T, L>(G, c, act, lead, i, xi, yi, s, send, cols, qx, qy, used);
+    batch_contribL<T, L, COH>(G, c, act, lead, i, xi, yi, s, send, cols, qx, qy, used);
     if (act && lead) {
         acc_add<T, KAHAN>(acc, cc, qx, qy);
         if (bi == fin) {
@@ -844,17 +860,21 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
             ++kf_cur;
         }
         // batch c has moved in iteration pk
-        // (thread 0's acquire invalidates the caches this workgroup reads
-        // through; the barrier orders the other waves' loads after it)
+        const int fb0 = fin * G.BS, fb1 = min(fb0 + G.BS, G.n);
+        const int fch0 = fb0 / kRows, fch1 = (fb1 - 1) / kRows;
+        // The moved columns are read with agent-scope loads.  A workgroup
+        // that finishes rows this step also reads what earlier finishers
+        // wrote (energy, batch partials, ticket): thread 0 acquires, and the
+        // barrier orders the other waves' loads after it.
+        bool finisher = false;
+        for (int q = blockIdx.x; q < nch; q += gridDim.x) finisher |= q >= fch0 && q <= fch1;
         if (threadIdx.x == 0) {
             const unsigned need = (unsigned)(pk - A.start + 1) * (unsigned)batch_chunks(c, G.BS, G.n);
             s_go = wait_moved(A.moved + c, need, A.abort, A.spin_limit);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (finisher) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (!s_go) return;
-        const int fb0 = fin * G.BS, fb1 = min(fb0 + G.BS, G.n);
-        const int fch0 = fb0 / kRows, fch1 = (fb1 - 1) / kRows;
         // the chunks of the batch to finish first: the next step waits for them
         for (int pass = 0; pass < 2; ++pass) {
             for (int q = blockIdx.x; q < nch; q += gridDim.x) {
@@ -864,7 +884,7 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
                 const bool work = last / G.BS > c || (do_next && first / G.BS <= c) || is_fin;
                 if (!work) continue;
                 T xi = 0, yi = 0, fx = 0, fy = 0;
-                panel_rowsL<T, KAHAN, L>(G, first, c, pk & 1, do_next, fin, cols, xi, yi, fx, fy);
+                panel_rowsL<T, KAHAN, L, true>(G, first, c, pk & 1, do_next, fin, cols, xi, yi, fx, fy);
                 if (is_fin) {
                     FinArgs<T> fa = fa0;
                     fa.fin = fin;
