@@ -442,6 +442,9 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
     // entry order
     unsigned long long longm = __ballot(lead && cnt > 16);
     bool first_long = true;
+    // per-wave staging of one group's terms (at most 16 waves per workgroup)
+    __shared__ T2 s_att[16][kWave], s_lrep[16][kWave];
+    T2 *lt = s_att[threadIdx.x / kWave], *lu = s_lrep[threadIdx.x / kWave];
     while (longm) {
         const int src = __ffsll((long long)longm) - 1;
         longm &= longm - 1;
@@ -466,20 +469,24 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
                 EntryTerms::att(rxi, ryi, pj, tx, ty);
                 if (G.literal) EntryTerms::rep(rxi, ryi, pj, ux, uy);
                 const int mcount = min(kWave, ct - e0);
-                for (int u = 0; u < mcount; ++u) {
-                    const T vx = __shfl(tx, u, kWave), vy = __shfl(ty, u, kWave);
-                    if (lane == src) {
-                        ax += vx;
-                        ay += vy;
+                lt[lane] = T2{tx, ty};
+                if (G.literal) lu[lane] = T2{ux, uy};
+                __builtin_amdgcn_wave_barrier();
+                if (lane == src) {
+                    for (int u = 0; u < mcount; ++u) {
+                        const T2 v = lt[u];
+                        ax += v.x;
+                        ay += v.y;
                     }
                     if (G.literal) {
-                        const T wx = __shfl(ux, u, kWave), wy = __shfl(uy, u, kWave);
-                        if (lane == src) {
-                            lx += wx;
-                            ly += wy;
+                        for (int u = 0; u < mcount; ++u) {
+                            const T2 v = lu[u];
+                            lx += v.x;
+                            ly += v.y;
                         }
                     }
                 }
+                __builtin_amdgcn_wave_barrier();   // the next group overwrites the staging
             }
         }
     }
@@ -748,7 +755,7 @@ __device__ __forceinline__ void finish_chunk(const GView<T> &G, const FinArgs<T>
 // finish_chunk for the lead lanes of a kRows * L workgroup: the rows' |f|^2
 // go through LDS to the first 256 threads, which sum them with the same tree
 // as finish_chunk.
-template <typename T, bool KAHAN, int L>
+template <typename T, bool KAHAN, int L, bool COH = false>
 __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T> &a, int first, T xi, T yi, T fx,
                                               T fy, double *e2, double *ws) {
     __shared__ int s_last;
@@ -764,8 +771,14 @@ __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T
     const double cs = chunk_sum(threadIdx.x < kRows ? e2[threadIdx.x] : 0.0, ws, 0);
     if (!a.energy_k) return;
     const int ch0 = b0 / kRows, ch1 = (b1 - 1) / kRows, nch = ch1 - ch0 + 1;
+    // (COH: the running energy was written by another workgroup of the
+    // same launch)
     if (nch == 1) {
-        if (threadIdx.x == 0) *a.energy_k = (a.fin == 0) ? cs : *a.energy_k + cs;
+        if (threadIdx.x == 0) {
+            double prev = 0.0;
+            if (a.fin != 0) prev = COH ? ld_agent(a.energy_k) : *a.energy_k;
+            *a.energy_k = (a.fin == 0) ? cs : prev + cs;
+        }
         return;
     }
     if (threadIdx.x == 0) {
@@ -862,16 +875,13 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
         // batch c has moved in iteration pk
         const int fb0 = fin * G.BS, fb1 = min(fb0 + G.BS, G.n);
         const int fch0 = fb0 / kRows, fch1 = (fb1 - 1) / kRows;
-        // The moved columns are read with agent-scope loads.  A workgroup
-        // that finishes rows this step also reads what earlier finishers
-        // wrote (energy, batch partials, ticket): thread 0 acquires, and the
-        // barrier orders the other waves' loads after it.
-        bool finisher = false;
-        for (int q = blockIdx.x; q < nch; q += gridDim.x) finisher |= q >= fch0 && q <= fch1;
+        // What other workgroups of this launch wrote is read with agent-scope
+        // loads: the moved columns and the running energy (the batch
+        // partials of a batch of several chunks behind a fence of their
+        // own), so no acquire has to drop this workgroup's cached rows.
         if (threadIdx.x == 0) {
             const unsigned need = (unsigned)(pk - A.start + 1) * (unsigned)batch_chunks(c, G.BS, G.n);
             s_go = wait_moved(A.moved + c, need, A.abort, A.spin_limit);
-            if (finisher) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (!s_go) return;
@@ -884,6 +894,8 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
                 const bool work = last / G.BS > c || (do_next && first / G.BS <= c) || is_fin;
                 if (!work) continue;
                 T xi = 0, yi = 0, fx = 0, fy = 0;
+                // the rows every workgroup waits for next go first on their SIMDs
+                if (is_fin) __builtin_amdgcn_s_setprio(3);
                 panel_rowsL<T, KAHAN, L, true>(G, first, c, pk & 1, do_next, fin, cols, xi, yi, fx, fy);
                 if (is_fin) {
                     FinArgs<T> fa = fa0;
@@ -891,12 +903,13 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
                     fa.pf = kf & 1;
                     fa.step = (T)st_cur;
                     fa.energy_k = A.energy + (kf - A.start);
-                    finish_chunkL<T, KAHAN, L>(G, fa, first, xi, yi, fx, fy, e2, ws);
+                    finish_chunkL<T, KAHAN, L, true>(G, fa, first, xi, yi, fx, fy, e2, ws);
                     // every wave's stores complete, then one release of them and the count
                     __builtin_amdgcn_s_waitcnt(0);
                     __syncthreads();
                     if (threadIdx.x == 0)
                         __hip_atomic_fetch_add(A.moved + fin, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_s_setprio(0);
                 }
             }
         }

@@ -239,3 +239,24 @@ def test_persistent_wait_limit_reports_timeout(monkeypatch):
     monkeypatch.setenv("BL_EXACT_STEPWISE", "1")
     xb, yb, eb, _ = api.layout(g, x0, y0, p)
     assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+
+
+@pytest.mark.parametrize("precision", ["fp32_kahan", "fp64"])
+@pytest.mark.parametrize("lit", [True, False])
+def test_hub_rows_one_workgroup_and_multi_workgroup_bitwise(precision, lit):
+    """Rows with far more than 16 neighbours in one column batch take the
+    long-segment path (terms formed across the wave, added by the row's lead
+    lane in entry order); the one-workgroup kernel adds the same terms in the
+    same order one lane per row."""
+    r = I.rng(91)
+    n = 2000
+    src = np.concatenate([np.zeros(900, np.int64), np.full(600, 7), r.integers(0, n, 3000)])
+    dst = np.concatenate([r.choice(np.arange(1, n), 900, replace=False), r.choice(np.arange(8, n), 600, replace=False),
+                          r.integers(0, n, 3000)])
+    g = I.csr_from_edges(n, src, dst)
+    x0, y0 = I.uniform_coords(n, 17)
+    x0, y0 = _f32(x0), _f32(y0)
+    kw = dict(batch_size=128, iterations=4, precision=precision, repulse_adjacent=lit)
+    xa, ya, ea, _ = api.layout(g, x0, y0, api.params(**kw))
+    xb, yb, eb, _ = api.layout(g, x0, y0, api.params(multi_wg=True, **kw))
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
