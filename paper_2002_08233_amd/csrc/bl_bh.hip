@@ -54,9 +54,9 @@ constexpr int kMinRun = 1;            // entries per thread at least (packs a st
 // vertices of earlier segments ("old": all moved, and final, by then); the
 // chain itself gathers only the entries that refer to its own segment.
 constexpr int kMaxSegments = 16;
-constexpr int kSegBatches = 16;
+constexpr int kSegBatches = 32;
 constexpr int kEntH = 8;              // old entries per thread per pass in the segment kernel
-constexpr int kOldSplit = 16;         // workgroups per batch in the segment kernel
+constexpr int kOldSplit = 16;         // most workgroups per batch in the segment kernel
 // The chain keeps the positions its segment has moved in an LDS window (the
 // recent entries refer to those vertices only); a segment spans at most
 // kWindow vertices.
@@ -71,6 +71,7 @@ struct BHJob {
     int all_live;               // one-shot force call: every leaf and neighbour is live
     int first_batch, last_batch, stop_batch;
     int nseg;                   // chain segments per iteration (1: no old part)
+    int nsplit;                 // segment-kernel workgroups per batch (<= kOldSplit)
     double step0, decay;
     gptr<int> kiter;            // [2]: current iteration, first iteration of the run
     gptr<const int> rowptr, colidx;
@@ -847,9 +848,9 @@ __device__ __forceinline__ int late_leaf_count(int lc) { return lc > kLateCap ? 
 // Per batch: the list holds first the old entries of all its rows, then the
 // others, each part row by row.  Counts of each row -> exclusive offsets
 // within each part; bold[b] = old part length, bbase[b] = list length (a scan
-// turns bbase into list starts).  The old part is also cut into kOldSplit
+// turns bbase into list starts).  The old part is also cut into J.nsplit
 // row ranges of about equal entry counts: bound k is the first row that
-// starts at or after entry floor(k * bold / kOldSplit).
+// starts at or after entry floor(k * bold / J.nsplit).
 __global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     __shared__ int ws[16];
@@ -877,15 +878,16 @@ __global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
     }
     if (J.nseg > 1) {
         gptr<int> sp = J.osplit + (size_t)b * (kOldSplit + 1);
-        for (int k = 1; k < kOldSplit; ++k) {
-            const int t = (int)(((long long)k * tot_o) / kOldSplit);
+        const int S = J.nsplit;
+        for (int k = 1; k < S; ++k) {
+            const int t = (int)(((long long)k * tot_o) / S);
             // the row whose entries (off_o, off_o + co] hold t ends range k - 1
             if (r < R && co > 0 && off_o < t && t <= off_o + co) sp[k] = r + 1;
             if (r == 0 && t == 0) sp[k] = 0;
         }
         if (r == 0) {
             sp[0] = 0;
-            sp[kOldSplit] = R;
+            sp[S] = R;
         }
     }
     if (r == 0) {
@@ -1162,7 +1164,7 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
     return sm;
 }
 
-// Old entries of chain segment `seg`, kOldSplit workgroups of 256 per batch,
+// Old entries of chain segment `seg`, J.nsplit workgroups of 256 per batch,
 // each taking one row range of the batch's old part: every vertex they refer
 // to lies in an earlier segment, so it has moved in this iteration and its
 // position is final.  The range's entries are split into equal runs, summed
@@ -1178,7 +1180,7 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     __shared__ float2 wv[256 / kWave];
     __shared__ int wk[256 / kWave], wkf[256 / kWave];
     if (J.nseg <= 1) return;
-    const int b = seg * seg_len(J) + jb.local / kOldSplit, part = jb.local % kOldSplit;
+    const int b = seg * seg_len(J) + jb.local / J.nsplit, part = jb.local % J.nsplit;
     if (b >= J.nb) return;
     const int tid = threadIdx.x, BS = J.BS;
     const int R = min(BS, J.n - b * BS);
@@ -1459,7 +1461,7 @@ int blocks_for(int type, const BHJob &J) {
         case PT_VERT8: return (n + 31) / 32;
         case PT_HEAVY: return std::max(16, std::min(256, n / 512));
         case PT_BATCH: return J.nb;
-        case PT_SEG: return J.nseg > 1 ? kOldSplit * ((J.nb + J.nseg - 1) / J.nseg) : 0;
+        case PT_SEG: return J.nseg > 1 ? J.nsplit * ((J.nb + J.nseg - 1) / J.nseg) : 0;
     }
     return 0;
 }
@@ -1561,6 +1563,9 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
             ns = std::max(std::max(1, std::min(kMaxSegments, nb / kSegBatches)), (nb + lmax - 1) / lmax);
         }
         J->nseg = (decltype(J->nseg))ns;
+        // about 256 expected old entries or more per segment-kernel workgroup
+        const double per_batch = (double)g->p.batch_size * (double)g->nnz / std::max(1, g->n);
+        J->nsplit = (decltype(J->nsplit))std::max(1, std::min(kOldSplit, (int)(per_batch / 256.0)));
     }
     J->step0 = (decltype(J->step0))(g->p.step0);
     J->decay = (decltype(J->decay))(g->p.step_decay);
