@@ -55,6 +55,7 @@ constexpr int kMinRun = 1;            // entries per thread at least (packs a st
 // chain itself gathers only the entries that refer to its own segment.
 constexpr int kMaxSegments = 16;
 constexpr int kSegBatches = 32;
+constexpr int kMinSegChain = 192;
 constexpr int kEntH = 8;              // old entries per thread per pass in the segment kernel
 constexpr int kOldSplit = 16;         // most workgroups per batch in the segment kernel
 // The chain keeps the positions its segment has moved in an LDS window (the
@@ -1551,8 +1552,10 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->last_batch = (decltype(J->last_batch))(spec.last_batch);
     J->stop_batch = (decltype(J->stop_batch))(spec.stop_batch);
     {
-        // enough segments for the window, and one per kSegBatches batches
-        // (up to kMaxSegments) to move old entries off the chain
+        // enough segments for the window, and for chains of kMinSegChain
+        // batches or more one per kSegBatches batches (up to kMaxSegments) to
+        // move old entries off the chain (shorter chains gain less than the
+        // segment launches cost)
         int ns = 1;
         if (!spec.all_live) {
             const int nb = (int)g->nb, lmax = kWindow / (int)g->p.batch_size;
@@ -1560,7 +1563,8 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
                 set_error("batch size %d above the chain window", (int)g->p.batch_size);
                 return BL_E_INVAL;
             }
-            ns = std::max(std::max(1, std::min(kMaxSegments, nb / kSegBatches)), (nb + lmax - 1) / lmax);
+            const int want = nb < kMinSegChain ? 1 : std::max(1, std::min(kMaxSegments, nb / kSegBatches));
+            ns = std::max(want, (nb + lmax - 1) / lmax);
         }
         J->nseg = (decltype(J->nseg))ns;
         // about 256 expected old entries or more per segment-kernel workgroup

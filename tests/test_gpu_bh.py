@@ -157,3 +157,29 @@ def test_repeat_runs_bitwise(grid32):
     a = api.layout(g, grid32["x0"], grid32["y0"], p)
     b = api.layout(g, grid32["x0"], grid32["y0"], p)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("iters,stop", [(1, 40), (1, 199), (2, 170)])
+def test_segmented_chain_ragged(iters, stop):
+    """A chain long enough to be cut into segments (200 batches of 64 rows,
+    ragged last batch and last segment): forces at stop batches inside later
+    segments, where most moved entries come from earlier segments."""
+    g = I.rmat(14, 8, seed=23)
+    n = 200 * 64 - 17
+    keep = (g.colidx < n)
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    sel = keep & (rows < n)
+    g = I.csr_from_edges(n, rows[sel], g.colidx[sel])
+    x0, y0 = I.uniform_coords(n, 24)
+    x0, y0 = _f32(x0), _f32(y0)
+    p = api.params(batch_size=64, iterations=iters, mode="bh", theta=1.2)
+    with api.Graph(g, p) as h:
+        h.set_coords(x0, y0)
+        if iters > 1:
+            h.run(iters - 1)
+        sx, sy = h.get_coords()
+        _, _, fx, fy = h.run(1, start_iter=iters - 1, stop_batch=stop)
+        xs, ys = h.get_coords()
+    r1 = min(n, stop * 64 + 64)
+    ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(sx, sy), stop * 64, r1, theta=1.2)
+    assert_forces(fx, fy, ref, mask=~ref.near_tie, what="stop %d" % stop)
