@@ -860,7 +860,7 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
     __shared__ typename V2<T>::type cols[kTile];
     __shared__ double ws[kRows * L / kWave];
     __shared__ double e2[kRows];
-    __shared__ int s_go;
+    __shared__ int s_go[2];   // by step parity: thread 0 cannot be two steps ahead of a wave reading it
     const int nb = G.nb, nch = (G.n + kRows - 1) / kRows;
     int kf_cur = A.start;
     double st_cur = A.step_start;   // step length of iteration kf_cur (the host's sequential product)
@@ -881,10 +881,10 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
         // own), so no acquire has to drop this workgroup's cached rows.
         if (threadIdx.x == 0) {
             const unsigned need = (unsigned)(pk - A.start + 1) * (unsigned)batch_chunks(c, G.BS, G.n);
-            s_go = wait_moved(A.moved + c, need, A.abort, A.spin_limit);
+            s_go[e & 1] = wait_moved(A.moved + c, need, A.abort, A.spin_limit);
         }
         __syncthreads();
-        if (!s_go) return;
+        if (!s_go[e & 1]) return;
         // the chunks of the batch to finish first: the next step waits for them
         for (int pass = 0; pass < 2; ++pass) {
             for (int q = blockIdx.x; q < nch; q += gridDim.x) {

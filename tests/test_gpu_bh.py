@@ -183,3 +183,25 @@ def test_segmented_chain_ragged(iters, stop):
     r1 = min(n, stop * 64 + 64)
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(sx, sy), stop * 64, r1, theta=1.2)
     assert_forces(fx, fy, ref, mask=~ref.near_tie, what="stop %d" % stop)
+
+
+@pytest.mark.parametrize("stop", [25, 29])
+def test_window_forces_segments_at_big_batches(stop):
+    """Batch 1024: the chain's LDS window holds 10 batches, so a 30-batch
+    chain is cut into 3 segments even though it is short; forces in the
+    last segment, including the ragged last batch."""
+    g = I.rmat(15, 8, seed=29)
+    n = 29 * 1024 + 300
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    sel = (g.colidx < n) & (rows < n)
+    g = I.csr_from_edges(n, rows[sel], g.colidx[sel])
+    x0, y0 = I.uniform_coords(n, 30)
+    x0, y0 = _f32(x0), _f32(y0)
+    p = api.params(batch_size=1024, iterations=1, mode="bh", theta=1.2)
+    with api.Graph(g, p) as h:
+        h.set_coords(x0, y0)
+        _, _, fx, fy = h.run(1, stop_batch=stop)
+        xs, ys = h.get_coords()
+    r1 = min(n, stop * 1024 + 1024)
+    ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), stop * 1024, r1, theta=1.2)
+    assert_forces(fx, fy, ref, mask=~ref.near_tie, what="stop %d" % stop)
