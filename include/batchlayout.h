@@ -91,7 +91,15 @@ typedef struct {
     double R;                /* > 0, relative strength of repulsion              */
     double theta;            /* >= 0, BH acceptance: side < theta * distance     */
     uint32_t flags;          /* BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG */
-    int32_t reserved[7];     /* must be zero                                     */
+    int32_t reserved0;       /* must be zero                                     */
+    double conv_tol;         /* >= 0; 0 = off.  The energy stopping rule of
+                                Sec. 4.3 read as a relative change: after an
+                                iteration k that is not the run's first, stop
+                                when |E_k - E_{k-1}| <= conv_tol * E_{k-1}; the
+                                layout is the one after iteration k and
+                                stats.iters_run counts the iterations done.
+                                Not with a stop batch, nor in the server.       */
+    int32_t reserved[4];     /* must be zero                                     */
 } bl_params;
 
 typedef struct {

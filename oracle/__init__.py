@@ -5,9 +5,10 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 Python binding) never imports, links or executes anything here.
 
 The arithmetic lives in ``bl_oracle.c`` (plain C, FP64, compiled with
-``-O2 -fno-fast-math -ffp-contract=off``); this module only marshals numpy
-arrays through ctypes.  Every function cites the passage of the paper it
-follows in the C source.
+``-O2 -fno-fast-math -ffp-contract=off``); this module marshals numpy arrays
+through ctypes and applies the energy stopping rule between iterations (one
+comparison of two energies).  Every function cites the passage of the paper
+it follows in the C source.
 """
 from __future__ import annotations
 
@@ -122,9 +123,27 @@ def forces_exact(rowptr, colidx, x, y, i0, i1, K=1.0, R=1.0, repulse_adjacent=Tr
     return Forces(*[o[:m] for o in out])
 
 
+def _converged(e, conv_tol):
+    """The energy stopping rule (Sec. 4.3), read as a relative change: after
+    an iteration that is not the run's first, stop when |E_k - E_{k-1}| <=
+    conv_tol * E_{k-1}."""
+    return conv_tol > 0 and len(e) >= 2 and abs(e[-1] - e[-2]) <= conv_tol * e[-2]
+
+
 def layout_exact(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=0.999,
-                 K=1.0, R=1.0, repulse_adjacent=True, stop_batch=-1):
-    """Exact BatchLayout (Alg. 2 semantics).  Returns (x, y, energy per iteration)."""
+                 K=1.0, R=1.0, repulse_adjacent=True, stop_batch=-1, conv_tol=0.0):
+    """Exact BatchLayout (Alg. 2 semantics).  Returns (x, y, energy per iteration);
+    with conv_tol > 0 the run ends where the energy stopping rule holds."""
+    if conv_tol > 0:
+        assert stop_batch < 0
+        x, y, es = x0, y0, []
+        for t in range(iters):
+            x, y, e = layout_exact(rowptr, colidx, x, y, bs, 1, start_iter + t, step0, decay, K, R,
+                                   repulse_adjacent)
+            es.append(e[0])
+            if _converged(es, conv_tol):
+                break
+        return _f64(x), _f64(y), np.array(es)
     lib = _load()
     rp, ci = _csr(rowptr, colidx)
     n = len(rp) - 1
@@ -194,11 +213,23 @@ def forces_bh(rowptr, colidx, x, y, tree: Tree, i0, i1, K=1.0, R=1.0, theta=1.2,
 
 
 def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=0.999,
-              K=1.0, R=1.0, theta=1.2, leaf_live=True, stop_batch=-1, want_snapshot=False):
+              K=1.0, R=1.0, theta=1.2, leaf_live=True, stop_batch=-1, want_snapshot=False, conv_tol=0.0):
     """BatchLayoutBH (Alg. S3 with the step decay of Alg. 2).
 
     Returns (x, y, energy, visits) or, with want_snapshot, also the snapshot
-    (sx, sy) taken at the start of the last iteration."""
+    (sx, sy) taken at the start of the last iteration.  With conv_tol > 0 the
+    run ends where the energy stopping rule holds."""
+    if conv_tol > 0:
+        assert stop_batch < 0 and not want_snapshot
+        x, y, es, vt = x0, y0, [], 0
+        for t in range(iters):
+            x, y, e, v = layout_bh(rowptr, colidx, x, y, bs, 1, start_iter + t, step0, decay, K, R, theta,
+                                   leaf_live)
+            es.append(e[0])
+            vt += v
+            if _converged(es, conv_tol):
+                break
+        return _f64(x), _f64(y), np.array(es), vt
     lib = _load()
     rp, ci = _csr(rowptr, colidx)
     n = len(rp) - 1

@@ -20,7 +20,7 @@ MODES = {"exact": BL_EXACT, "bh": BL_BH}
 
 def params(batch_size=256, iterations=600, start_iter=0, mode="exact", precision="fp32_kahan",
            repulse_adjacent=True, step0=1.0, step_decay=0.999, K=1.0, R=1.0, theta=1.2,
-           validate=False, snapshot_leaves=False, multi_wg=False) -> Params:
+           validate=False, snapshot_leaves=False, multi_wg=False, conv_tol=0.0) -> Params:
     p = Params()
     check(load().bl_params_init(C.byref(p)))
     p.batch_size = int(batch_size)
@@ -30,6 +30,7 @@ def params(batch_size=256, iterations=600, start_iter=0, mode="exact", precision
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.repulse_adjacent = 1 if repulse_adjacent else 0
     p.step0, p.step_decay, p.K, p.R, p.theta = step0, step_decay, K, R, theta
+    p.conv_tol = conv_tol
     p.flags = ((BL_VALIDATE if validate else 0) | (BL_BH_SNAPSHOT_LEAVES if snapshot_leaves else 0) |
                (BL_EXACT_MULTI_WG if multi_wg else 0))
     return p
@@ -117,7 +118,7 @@ def layout(graph, x0, y0, p: Params, stream=None, energy=True):
     st = Stats()
     check(lib.bl_layout(C.byref(csr), keep.ptr(x0, np.float64), keep.ptr(y0, np.float64), C.byref(pp),
                         _stream(stream), xptr, yptr, en.ctypes.data if energy else None, C.byref(st)))
-    return xo, yo, en[:p.iterations], st.as_dict()
+    return xo, yo, en[:st.iters_run], st.as_dict()
 
 
 def forces(graph, x, y, batch_index, p: Params, snapshot=None, stream=None):
@@ -205,7 +206,7 @@ class Graph:
             fptr = (fx.ctypes.data, fy.ctypes.data)
         check(self._lib.bl_graph_run(self.h, int(iterations), int(start_iter), int(stop_batch),
                                      en.ctypes.data if energy else None, fptr[0], fptr[1], C.byref(st)))
-        full = iterations - 1 if stop_batch >= 0 else iterations
+        full = iterations - 1 if stop_batch >= 0 else st.iters_run
         if stop_batch >= 0:
             return en[:full], st.as_dict(), fx[:R], fy[:R]
         return en[:full], st.as_dict()

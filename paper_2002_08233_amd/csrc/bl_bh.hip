@@ -99,6 +99,7 @@ struct BHJob {
     gptr<double> energy;        // one value per iteration of the run
     gptr<double> fout;
     Counters *ctr;
+    double conv_tol;            // energy stopping rule (0: off)
 };
 
 // Workgroup -> (job, workgroup within the job) for one kernel of a launch.
@@ -121,9 +122,11 @@ __device__ __forceinline__ JobBlock job_block(const BHJob *__restrict__ jobs, co
 #define BH_KERNEL_ARGS const BHJob *__restrict__ jobs, const int *__restrict__ pre, int G
 // The descriptor is copied into registers: stores through its pointers can
 // then not force reloads of its fields.
+// (a job whose energy stopping rule has held does nothing more)
 #define BH_JOB()                               \
     const JobBlock jb = job_block(jobs, pre, G); \
-    const BHJob J = *jb.J
+    const BHJob J = *jb.J;                       \
+    if (J.conv_tol > 0 && J.ctr->halted) return
 
 // ------------------------------------------------------------------ bbox
 __global__ __launch_bounds__(256) void bbox_kernel(BH_KERNEL_ARGS) {
@@ -1440,8 +1443,16 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
     if (tid == 0 && J.stop_batch < 0) {
         // segments add their energies in order; the last one ends the iteration
         const int slot_e = k_it - J.kiter[1];
-        J.energy[slot_e] = first_launch ? e : J.energy[slot_e] + e;
-        if (last_launch) J.kiter[0] = k_it + 1;
+        const double ek = first_launch ? e : J.energy[slot_e] + e;
+        J.energy[slot_e] = ek;
+        if (last_launch) {
+            J.kiter[0] = k_it + 1;
+            // energy stopping rule (relative change against the previous iteration of the run)
+            if (J.conv_tol > 0 && slot_e >= 1) {
+                const double ep = J.energy[slot_e - 1];
+                if (fabs(ek - ep) <= J.conv_tol * ep) J.ctr->halted = (unsigned long long)(slot_e + 1);
+            }
+        }
     }
 }
 
@@ -1614,6 +1625,7 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->energy = (decltype(J->energy))(g->energy);
     J->fout = (decltype(J->fout))(g->fout);
     J->ctr = (decltype(J->ctr))(g->counters);
+    J->conv_tol = (decltype(J->conv_tol))(spec.all_live || spec.stop_batch >= 0 ? 0.0 : g->p.conv_tol);
     return BL_OK;
 }
 

@@ -70,7 +70,9 @@ int check_params(const bl_params *p) {
     if (!(p->theta >= 0) || !std::isfinite(p->theta)) return fail(BL_E_INVAL, "theta must be >= 0");
     if (p->flags & ~(BL_DEVICE_PTRS | BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG))
         return fail(BL_E_INVAL, "unknown flags 0x%x", p->flags);
-    for (int q = 0; q < 7; ++q)
+    if (!(p->conv_tol >= 0) || !std::isfinite(p->conv_tol)) return fail(BL_E_INVAL, "conv_tol must be >= 0");
+    if (p->reserved0) return fail(BL_E_INVAL, "reserved fields must be zero");
+    for (int q = 0; q < 4; ++q)
         if (p->reserved[q]) return fail(BL_E_INVAL, "reserved fields must be zero");
     return BL_OK;
 }
@@ -142,6 +144,7 @@ static int ensure_energy(bl_graph *g, int iters) {
 int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds) {
     Counters c{};
     BL_HIP(hipMemcpy(&c, g->counters, sizeof c, hipMemcpyDeviceToHost));
+    if (c.halted) iters_run = std::min(iters_run, (int)c.halted);
     double e_last = 0.0;
     if (iters_run > 0) BL_HIP(hipMemcpy(&e_last, g->energy + iters_run - 1, 8, hipMemcpyDeviceToHost));
     if (st) {
@@ -310,6 +313,7 @@ static int run_impl(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t
     if (stop_batch >= g->nb) return fail(BL_E_INVAL, "stop_batch %d out of range (%d batches)", stop_batch, g->nb);
     if (stop_batch >= 0 && iterations < 1) return fail(BL_E_INVAL, "stop_batch needs iterations >= 1");
     if (stop_batch >= 0 && (!fx || !fy)) return fail(BL_E_INVAL, "stop_batch needs fx, fy");
+    if (stop_batch >= 0 && g->p.conv_tol > 0) return fail(BL_E_INVAL, "stop_batch cannot be combined with conv_tol");
     BL_TRY(ensure_energy(g, std::max(iterations, 1)));
     BL_HIP(hipMemsetAsync(g->counters, 0, sizeof(Counters), g->stream));
     hipEvent_t e0, e1;
@@ -326,7 +330,10 @@ static int run_impl(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t
     (void)hipEventDestroy(e1);
     if (rc != BL_OK) return rc;
     if (he != hipSuccess) return fail(BL_E_HIP, "layout run failed: %s", hipGetErrorString(he));
-    const int full = (stop_batch >= 0) ? iterations - 1 : iterations;
+    Counters c{};
+    BL_HIP(hipMemcpy(&c, g->counters, sizeof c, hipMemcpyDeviceToHost));
+    int full = (stop_batch >= 0) ? iterations - 1 : iterations;
+    if (c.halted) full = std::min(full, (int)c.halted);   // the energy stopping rule ended the run
     std::vector<double> en(std::max(full, 1));
     if (full > 0) BL_HIP(hipMemcpy(en.data(), g->energy, 8 * (size_t)full, hipMemcpyDeviceToHost));
     if (energy_out && full > 0) std::memcpy(energy_out, en.data(), 8 * (size_t)full);
@@ -340,8 +347,6 @@ static int run_impl(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t
             fy[q] = f[2 * q + 1];
         }
     }
-    Counters c{};
-    BL_HIP(hipMemcpy(&c, g->counters, sizeof c, hipMemcpyDeviceToHost));
     if (g->prof) {
         BL_TRY(prof_collect(g));
         g->prof->late_total += (long long)c.late_total;

@@ -705,7 +705,26 @@ struct FinArgs {
     double *epart;        // chunk partials of the batch
     unsigned *ticket;
     unsigned long long *nonfinite_count;
+    // energy stopping rule: applied when the run's iteration ending with this
+    // batch is not its first (energy_k > energy0)
+    double conv_tol;      // 0: off
+    const double *energy0;
+    unsigned long long *halted;
 };
+
+// After the last batch of an iteration: the energy stopping rule, relative
+// change against the run's previous iteration (COH: that energy was written
+// by another workgroup of the same launch).
+template <typename T, bool COH>
+__device__ __forceinline__ void energy_rule(const FinArgs<T> &a, int nb, double ek) {
+    if (a.conv_tol > 0 && a.fin == nb - 1 && a.energy_k > a.energy0) {
+        const double ep = COH ? ld_agent(a.energy_k - 1) : a.energy_k[-1];
+        if (fabs(ek - ep) <= a.conv_tol * ep) *a.halted = (unsigned long long)(a.energy_k - a.energy0) + 1;
+    }
+}
+__device__ __forceinline__ bool halted_run(double conv_tol, const unsigned long long *h) {
+    return conv_tol > 0 && h && *h;
+}
 
 // Finishing of batch a.fin by the workgroup holding rows [first, first +
 // 256): each row's force (already in (fx, fy) when `have`, else from
@@ -733,7 +752,11 @@ __device__ __forceinline__ void finish_chunk(const GView<T> &G, const FinArgs<T>
     if (!a.energy_k) return;
     const int ch0 = b0 / kRows, ch1 = (b1 - 1) / kRows, nch = ch1 - ch0 + 1;
     if (nch == 1) {
-        if (threadIdx.x == 0) *a.energy_k = (a.fin == 0) ? cs : *a.energy_k + cs;
+        if (threadIdx.x == 0) {
+            const double ek = (a.fin == 0) ? cs : *a.energy_k + cs;
+            *a.energy_k = ek;
+            energy_rule<T, false>(a, G.nb, ek);
+        }
         return;
     }
     if (threadIdx.x == 0) {
@@ -747,7 +770,9 @@ __device__ __forceinline__ void finish_chunk(const GView<T> &G, const FinArgs<T>
         const volatile double *ep = a.epart;
         double bs = ep[0];
         for (int q = 1; q < nch; ++q) bs += ep[q];
-        *a.energy_k = (a.fin == 0) ? bs : *a.energy_k + bs;
+        const double ek = (a.fin == 0) ? bs : *a.energy_k + bs;
+        *a.energy_k = ek;
+        energy_rule<T, false>(a, G.nb, ek);   // (after the fence above)
         *a.ticket = 0u;
     }
 }
@@ -777,7 +802,9 @@ __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T
         if (threadIdx.x == 0) {
             double prev = 0.0;
             if (a.fin != 0) prev = COH ? ld_agent(a.energy_k) : *a.energy_k;
-            *a.energy_k = (a.fin == 0) ? cs : prev + cs;
+            const double ek = (a.fin == 0) ? cs : prev + cs;
+            *a.energy_k = ek;
+            energy_rule<T, COH>(a, G.nb, ek);
         }
         return;
     }
@@ -792,7 +819,9 @@ __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T
         const volatile double *ep = a.epart;
         double bs = ep[0];
         for (int q = 1; q < nch; ++q) bs += ep[q];
-        *a.energy_k = (a.fin == 0) ? bs : *a.energy_k + bs;
+        const double ek = (a.fin == 0) ? bs : *a.energy_k + bs;
+        *a.energy_k = ek;
+        energy_rule<T, false>(a, G.nb, ek);   // (after the fence above)
         *a.ticket = 0u;
     }
 }
@@ -802,6 +831,7 @@ __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T
 // panel's).  Needs nb > 1: the finished rows are read by no other workgroup.
 template <typename T, bool KAHAN, int L>
 __global__ __launch_bounds__(kRows * L) void step_kernel(GView<T> G, int c, int pc, int do_next, FinArgs<T> fa) {
+    if (halted_run(fa.conv_tol, fa.halted)) return;   // the energy stopping rule ended the run
     __shared__ typename V2<T>::type cols[kTile];
     __shared__ double ws[kRows * L / kWave];
     __shared__ double e2[kRows];
@@ -881,7 +911,10 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
         // own), so no acquire has to drop this workgroup's cached rows.
         if (threadIdx.x == 0) {
             const unsigned need = (unsigned)(pk - A.start + 1) * (unsigned)batch_chunks(c, G.BS, G.n);
-            s_go[e & 1] = wait_moved(A.moved + c, need, A.abort, A.spin_limit);
+            int go = wait_moved(A.moved + c, need, A.abort, A.spin_limit);
+            // the energy stopping rule held at the end of the previous step
+            if (go && fa0.conv_tol > 0 && ld_agent(fa0.halted)) go = 0;
+            s_go[e & 1] = go;
         }
         __syncthreads();
         if (!s_go[e & 1]) return;
@@ -926,6 +959,7 @@ __global__ void moved_init_kernel(unsigned *moved, int nb, unsigned first_chunks
 // Finish of batch fa.fin only (its sums are complete in memory).
 template <typename T, bool KAHAN>
 __global__ __launch_bounds__(kRows) void finalize_kernel(GView<T> G, FinArgs<T> fa) {
+    if (halted_run(fa.conv_tol, fa.halted)) return;
     __shared__ double ws[kRows / kWave];
     const int first = (fa.fin * G.BS) / kRows * kRows + blockIdx.x * kRows;
     finish_chunk<T, KAHAN>(G, fa, first, false, 0, 0, 0, 0, ws);
@@ -949,6 +983,8 @@ struct ExactJob {
     float2 *accC[2];
     double *energy;
     unsigned long long *nonfinite;
+    double conv_tol;                 // energy stopping rule (0: off)
+    unsigned long long *halted;
 };
 
 template <typename T, bool KAHAN, int NT>
@@ -957,6 +993,7 @@ __global__ __launch_bounds__(NT) void exact_graph_kernel(const ExactJob *__restr
     __shared__ T2 cols[kTile];
     __shared__ double ws[NT / kWave];
     __shared__ double s_batch;
+    __shared__ int s_stop;
     const ExactJob &J0 = jobs[blockIdx.x];
     GView<T> G;
     G.n = J0.n;
@@ -1030,6 +1067,19 @@ __global__ __launch_bounds__(NT) void exact_graph_kernel(const ExactJob *__restr
             // the panel of batch b (moved in iteration k), then the next batch
             const bool has_next = (b + 1 < nb) || (k < lastk);
             if (!has_next) break;
+            if (b == nb - 1 && J0.conv_tol > 0 && k > start) {
+                // E_k is final: the energy stopping rule before batch 0 of k + 1 moves
+                if (threadIdx.x == 0) {
+                    const double ek = energy[k - start], ep = energy[k - start - 1];
+                    s_stop = fabs(ek - ep) <= J0.conv_tol * ep;
+                    if (s_stop) *J0.halted = (unsigned long long)(k - start + 1);
+                }
+                __syncthreads();
+                if (s_stop) {
+                    if (bad) atomicAdd(nonfinite, bad);
+                    return;
+                }
+            }
             const int do_next = k < lastk ? 1 : 0;
             for (int first = 0; first < n; first += NT) {
                 T xi = 0, yi = 0, fx = 0, fy = 0;
@@ -1115,6 +1165,9 @@ struct ExactOps {
         a.epart = g->ex.epart;
         a.ticket = g->ex.ticket;
         a.nonfinite_count = &g->counters->nonfinite;
+        a.conv_tol = g->p.conv_tol;
+        a.energy0 = g->energy;
+        a.halted = &g->counters->halted;
         return a;
     }
 
@@ -1318,6 +1371,8 @@ int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, v
         J.accC[1] = g->ex.accC[1];
         J.energy = g->energy;
         J.nonfinite = &g->counters->nonfinite;
+        J.conv_tol = g->p.conv_tol;
+        J.halted = &g->counters->halted;
     }
     BL_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(ExactJob) * G, hipMemcpyHostToDevice, s));
     BL_HIP(hipStreamSynchronize(s));   // the host copy of the table is freed below

@@ -40,6 +40,7 @@ struct Counters {
     unsigned long long old_total;      // late entries summed by the segment kernel
     unsigned long long recent_total;   // late entries summed by the chain
     unsigned long long wait_abort;     // a bounded device wait ran out (the launch left early)
+    unsigned long long halted;         // the energy stopping rule held after this many iterations
 };
 
 // Per-kernel device time, measured with hipEvents around launches when a

@@ -81,3 +81,21 @@ def near_grid_init(rows, cols, seed=11, noise=0.15):
     x = np.float32(gx + r.normal(0, noise, n)).astype(np.float64)
     y = np.float32(gy + r.normal(0, noise, n)).astype(np.float64)
     return x, y
+
+
+def stop_tolerance(energies, kmax=10):
+    """A tolerance for the energy stopping rule that first holds at an
+    iteration k* with a margin on both sides (so that runs whose energies
+    differ by rounding stop at the same k*): the k* in 2..kmax whose relative
+    change is furthest below all earlier ones, else k* = 1.  Returns
+    (tolerance, iterations the stopped run completes = k* + 1)."""
+    e = np.asarray(energies, float)
+    rel = np.abs(np.diff(e)) / e[:-1]          # rel[k - 1]: change at iteration k
+    best, kbest = 1.0, 1
+    for k in range(2, min(kmax, len(rel)) + 1):
+        ratio = float(np.min(rel[:k - 1])) / max(float(rel[k - 1]), 1e-300)
+        if ratio > best:
+            best, kbest = ratio, k
+    if kbest == 1 or best < 1.3:
+        return 2.0 * float(rel[0]) + 1e-12, 2
+    return float(np.sqrt(rel[kbest - 1] * np.min(rel[:kbest - 1]))), kbest + 1

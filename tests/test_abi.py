@@ -62,7 +62,8 @@ def _call_layout(lib, g, p):
 
 @pytest.mark.parametrize("field,value", [("batch_size", 0), ("iterations", -1), ("K", 0.0), ("R", -1.0),
                                          ("theta", -0.5), ("step_decay", 1.5), ("mode", 7),
-                                         ("precision", 9), ("step0", 0.0)])
+                                         ("precision", 9), ("step0", 0.0), ("conv_tol", -1.0),
+                                         ("reserved0", 3)])
 def test_bad_params_rejected(lib, field, value):
     from paper_2002_08233_amd import api, inputs
     p = api.params(iterations=1)
@@ -119,3 +120,28 @@ def test_batch_argument_checks(lib):
     assert lib.bl_layout_batch(0, None, None, None, None, None, None, None, None) == 0
     assert lib.bl_layout_batch(-1, None, None, None, None, None, None, None, None) == -1
     assert lib.bl_layout_batch(2, None, None, None, None, None, None, None, None) == -1
+
+
+def test_params_and_stats_layout_match_the_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets that a C
+    compiler gives the header's structs."""
+    import ctypes as C
+    import subprocess
+    from paper_2002_08233_amd import _lib
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in _lib.Params._fields_]
+    sfields = [f for f, _ in _lib.Stats._fields_]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "batchlayout.h"', 'int main(void) {',
+             '  printf("%zu\\n", sizeof(bl_params));']
+    lines += ['  printf("%%zu\\n", offsetof(bl_params, %s));' % f for f in fields]
+    lines += ['  printf("%zu\\n", sizeof(bl_stats));']
+    lines += ['  printf("%%zu\\n", offsetof(bl_stats, %s));' % f for f in sfields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines) + "\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [C.sizeof(_lib.Params)] + [getattr(_lib.Params, f).offset for f in fields]
+    want += [C.sizeof(_lib.Stats)] + [getattr(_lib.Stats, f).offset for f in sfields]
+    assert got == want

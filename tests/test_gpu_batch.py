@@ -44,3 +44,27 @@ def test_batch_twice_is_reproducible_and_empty_is_ok():
     for (xa, ya), (xb, yb) in zip(a, b):
         assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
     assert api.layout_batch([], [], [], []) == ([], [])
+
+
+def test_batch_with_energy_stopping_rule():
+    """conv_tol per graph in a batch (one-workgroup exact, step-kernel exact,
+    Barnes-Hut engine): each graph stops where it stops alone, with the same
+    bits."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from _parity import stop_tolerance
+    jobs = [_job("er", 600, 41, "exact", 12, bs=64), _job("ba", 9000, 42, "exact", 10, bs=512),
+            _job("er", 5000, 43, "bh", 12, bs=128), _job("ba", 700, 44, "exact", 12, bs=32)]
+    for g, x0, y0, p in jobs:
+        p.step0, p.step_decay = 0.05, 0.97
+        _, _, ef, _ = api.layout(g, x0, y0, p)
+        p.conv_tol = stop_tolerance(ef)[0]
+    outs, stats = api.layout_batch([j[0] for j in jobs], [j[1] for j in jobs], [j[2] for j in jobs],
+                                   [j[3] for j in jobs])
+    stopped = 0
+    for (g, x0, y0, p), (xb, yb), st in zip(jobs, outs, stats):
+        xs, ys, es, sts = api.layout(g, x0, y0, p)
+        assert np.array_equal(xb, xs) and np.array_equal(yb, ys), (g.n, p.mode)
+        assert st["iters_run"] == sts["iters_run"] == len(es)
+        stopped += st["iters_run"] < p.iterations
+    assert stopped == len(jobs)

@@ -5,7 +5,8 @@ import pytest
 
 import oracle
 from paper_2002_08233_amd import api, inputs as I
-from _parity import RUN_TOL, SETTLING, assert_forces, assert_within_oracle_spread, near_grid_init, quality
+from _parity import (RUN_TOL, SETTLING, assert_forces, assert_within_oracle_spread, near_grid_init, quality,
+                     stop_tolerance)
 
 pytestmark = pytest.mark.gpu
 
@@ -205,3 +206,25 @@ def test_window_forces_segments_at_big_batches(stop):
     r1 = min(n, stop * 1024 + 1024)
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), stop * 1024, r1, theta=1.2)
     assert_forces(fx, fy, ref, mask=~ref.near_tie, what="stop %d" % stop)
+
+
+@pytest.mark.parametrize("n,bs", [(3000, 128), (12783, 64)])
+def test_energy_stopping_rule(n, bs):
+    """conv_tol on the Barnes-Hut engine (one segment, and a segmented chain):
+    the run stops at the same iteration as the oracle and equals a plain run
+    of that many iterations bitwise."""
+    g = I.rmat(14, 8, seed=31)
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    sel = (g.colidx < n) & (rows < n)
+    g = I.csr_from_edges(n, rows[sel], g.colidx[sel])
+    x0, y0 = I.uniform_coords(n, 32)
+    x0, y0 = _f32(x0), _f32(y0)
+    kw = dict(batch_size=bs, mode="bh", theta=1.2, step0=0.05, step_decay=0.97)
+    _, _, ef, _ = api.layout(g, x0, y0, api.params(iterations=12, **kw))
+    tol, want = stop_tolerance(ef)
+    xs, ys, es, st = api.layout(g, x0, y0, api.params(iterations=12, conv_tol=tol, **kw))
+    assert st["iters_run"] == want and len(es) == want
+    xp, yp, ep, _ = api.layout(g, x0, y0, api.params(iterations=want, **kw))
+    assert np.array_equal(xs, xp) and np.array_equal(ys, yp) and np.array_equal(es, ep)
+    eo = oracle.layout_bh(g.rowptr, g.colidx, x0, y0, bs, 12, step0=0.05, decay=0.97, theta=1.2, conv_tol=tol)[2]
+    assert len(eo) == want

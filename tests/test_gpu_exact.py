@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from paper_2002_08233_amd import api, inputs as I
-from _parity import (RUN_TOL, SETTLING, assert_forces, assert_within_oracle_spread, force_errors,
+from _parity import (RUN_TOL, SETTLING, assert_forces, assert_within_oracle_spread, force_errors, stop_tolerance,
                      near_grid_init, quality)
 
 pytestmark = pytest.mark.gpu
@@ -260,3 +260,25 @@ def test_hub_rows_one_workgroup_and_multi_workgroup_bitwise(precision, lit):
     xa, ya, ea, _ = api.layout(g, x0, y0, api.params(**kw))
     xb, yb, eb, _ = api.layout(g, x0, y0, api.params(multi_wg=True, **kw))
     assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+
+
+@pytest.mark.parametrize("path", ["one_workgroup", "persistent", "stepwise"])
+def test_energy_stopping_rule(monkeypatch, path):
+    """conv_tol ends the run where the energy's relative change first falls to
+    the tolerance (Sec. 4.3): the same iteration as the oracle, and the same
+    bits as a plain run of that many iterations, on every exact path."""
+    g = _rand_graph(900, 8.0 / 900, 77)
+    x0, y0 = I.uniform_coords(g.n, 78)
+    x0, y0 = _f32(x0), _f32(y0)
+    multi = path != "one_workgroup"
+    if path == "stepwise":
+        monkeypatch.setenv("BL_EXACT_STEPWISE", "1")
+    kw = dict(batch_size=128, step0=0.05, step_decay=0.97, multi_wg=multi)
+    _, _, ef, _ = api.layout(g, x0, y0, api.params(iterations=14, **kw))
+    tol, want = stop_tolerance(ef)
+    xs, ys, es, st = api.layout(g, x0, y0, api.params(iterations=14, conv_tol=tol, **kw))
+    assert st["iters_run"] == want and len(es) == want
+    xp, yp, ep, _ = api.layout(g, x0, y0, api.params(iterations=want, **kw))
+    assert np.array_equal(xs, xp) and np.array_equal(ys, yp) and np.array_equal(es, ep)
+    _, _, eo = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 128, 14, step0=0.05, decay=0.97, conv_tol=tol)
+    assert len(eo) == want

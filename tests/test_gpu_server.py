@@ -65,6 +65,16 @@ def test_oversized_job_is_rejected():
         assert e.value.code == BL_E_REJECTED
 
 
+def test_energy_stopping_rule_is_rejected():
+    """The server runs jobs a fixed number of iterations in quanta."""
+    g, x0, y0, p = _job("er", 500, 13, "exact", 4)
+    p.conv_tol = 1e-3
+    with api.Server(1 << 30, max_slots=4) as srv:
+        with pytest.raises(api.BLError) as e:
+            srv.submit(g, x0, y0, p)
+        assert e.value.code == -1
+
+
 def test_release_cancels_and_timeout_reports():
     g, x0, y0, p = _job("ba", 20000, 10, "bh", 200000, 256, 1.2)   # minutes unless cancelled
     small = _job("er", 300, 12, "exact", 4)

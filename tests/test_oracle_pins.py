@@ -552,3 +552,39 @@ def test_paper_defaults_golden():
     gold = json.load(open(os.path.join(GOLDEN, "paper_defaults.json")))
     assert gold["step_decay"]["value"] == 0.999 and gold["theta"]["value"] == 1.2
     assert gold["batch_size"]["value"] == 256 and gold["step0"]["value"] == 1.0
+
+
+def _first_stop(e, tol):
+    """Iterations run under the energy stopping rule, straight from its
+    definition: the first k >= 1 with |E_k - E_{k-1}| <= tol * E_{k-1}."""
+    for k in range(1, len(e)):
+        if abs(e[k] - e[k - 1]) <= tol * e[k - 1]:
+            return k + 1
+    return len(e)
+
+
+@pytest.mark.parametrize("mode", ["exact", "bh"])
+def test_energy_stopping_rule(mode):
+    """Sec. 4.3's energy stopping rule read as a relative change (R11): the run
+    stops at the first iteration (not the run's first) whose relative energy
+    change is at or below the tolerance, and its layout is the plain run's
+    layout after that many iterations.  Tolerances taken from the plain run's
+    own changes, one that always holds, and 0 (off)."""
+    g = I.grid(6, 7)
+    x0, y0 = I.uniform_coords(g.n, 41)
+    if mode == "exact":
+        run = lambda it, tol=0.0: oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 8, it, conv_tol=tol)[:3]
+    else:
+        run = lambda it, tol=0.0: oracle.layout_bh(g.rowptr, g.colidx, x0, y0, 8, it, theta=0.7,
+                                                   conv_tol=tol)[:3]
+    xf, yf, ef = run(16)
+    rel = np.abs(np.diff(ef)) / ef[:-1]
+    assert np.all(np.isfinite(rel)) and rel.size == 15
+    tols = [10.0, 0.0] + sorted(set(float(r) * 1.0001 for r in rel[1:8]))
+    for tol in tols:
+        want = _first_stop(ef, tol) if tol > 0 else 16
+        xs, ys, es = run(16, tol)
+        assert len(es) == want, (tol, len(es), want)
+        xp, yp, ep = run(want)
+        assert np.array_equal(xs, xp) and np.array_equal(ys, yp) and np.array_equal(es, ep)
+    assert len(run(16, 10.0)[2]) == 2
