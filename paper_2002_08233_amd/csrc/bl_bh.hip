@@ -21,10 +21,15 @@
 //                      whose vertex has not moved yet this iteration; leaves of
 //                      already-moved vertices are listed for the chain
 //   8. att_*_kernel    attraction from neighbours that have not moved yet
-//   9. late lists      per batch: the moved neighbours and listed moved leaves
-//  10. chain_kernel    one workgroup per job walks its batches in order: the
-//                      late entries with live coordinates, then the batch
-//                      update (Alg. 2 update loop)
+//   9. late lists      per batch: the moved neighbours and listed moved leaves,
+//                      split into entries that refer to earlier chain segments
+//                      ("old") and to the batch's own segment ("recent")
+//  10. per segment     old_sum_kernel (full chip) sums the segment's old
+//                      entries; chain_kernel (one workgroup per job) then walks
+//                      the segment's batches in order: the recent entries with
+//                      live coordinates from an LDS window of the segment's
+//                      moved vertices, then the batch update (Alg. 2 update
+//                      loop)
 #include <algorithm>
 #include <cfloat>
 #include <cstring>

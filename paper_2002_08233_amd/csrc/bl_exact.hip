@@ -29,8 +29,11 @@
 // in row order; iteration energies add the batch sums in batch order.
 //
 // Kernels: rows_kernel (whole-column-batch sums: the prologue of a run and
-// the one-shot force call), step_kernel (panel + fused finish of the next
-// batch), finalize_kernel (finish only: first batch of a run, probes, and
+// the one-shot force call), steps_kernel (all steps of a run in one
+// cooperative launch: workgroups own fixed rows and wait only for the batch
+// whose columns they add next), step_kernel (one step: panel + fused finish
+// of the next batch; probes, and jobs that share the device),
+// finalize_kernel (finish only: first batch of a run, probes, and
 // single-batch graphs), exact_graph_kernel (one workgroup runs a whole small
 // layout; many graphs per launch).
 #include <algorithm>
