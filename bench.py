@@ -40,7 +40,7 @@ FLOP_PER_PAIR = 10.0             # 2 sub, d^2 (2 mul + 1 add), 1 reciprocal, 2 F
 # (FETCH_SIZE scaled by 2.0, the factor a plain copy of known size shows; WRITE_SIZE by 1.0).
 # Valid only while the kernel's source file is the one the counters were taken on.
 MEASURED_TRAFFIC = {
-    ("c2-bh", "chain_kernel"): (625805.6, "bl_bh.hip", "df1962213dd09b92"),
+    ("c2-bh", "chain_kernel"): (624341.6, "bl_bh.hip", "b2c4a1e59d63ff37"),
 }
 
 
@@ -134,6 +134,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel hipEvent timing")
     ap.add_argument("--profile-steps", type=int, default=100, help="iterations of the per-kernel timing run")
+    ap.add_argument("--no-end-to-end", action="store_true", help="skip the run through host arrays")
     ap.add_argument("--precision", default="fp32_kahan")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -256,6 +257,16 @@ def main():
         dev.profile(False)   # (this also clears the totals just read)
     out["energy_last"] = float(energy[-1]) if len(energy) else None
 
+    if not args.no_end_to_end:
+        # the same run through the host-array boundary: graph and coordinates
+        # uploaded, the run, coordinates copied back (never the headline value)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.layout(g, w["x0"], w["y0"], p)
+        e2e = time.perf_counter() - t0
+        out["end_to_end"] = {"force_updates_per_s": g.n * steps / e2e, "seconds": e2e,
+                             "note": "bl_layout from host arrays: CSR and coordinates uploaded, "
+                                     "device state built, the run, coordinates back"}
     if args.config == "c3" and args.precision == "fp32_kahan":
         out["precision"] = precision_report(api, w, dev, x0, y0, min(steps, 20))
     if not args.no_cpu_baseline:
