@@ -76,6 +76,7 @@ def _load():
     lib.orc_stress.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_void_p,
                                C.POINTER(C.c_double)]
     lib.orc_stress.restype = C.c_double
+    lib.orc_greedy_init.argtypes = [C.c_int, _i32p, _i32p, C.c_int, _f64p, _f64p, _f64p, _f64p, _i32p]
     _lib = lib
     return lib
 
@@ -274,3 +275,20 @@ def stress(rowptr, colidx, x, y, pivots=None):
         v = _load().orc_stress(len(rp) - 1, rp, ci, _f64(x), _f64(y), len(pv),
                                pv.ctypes.data_as(C.c_void_p), C.byref(s))
     return v, s.value
+
+
+def greedy_init(rowptr, colidx, start, xr=None, yr=None):
+    """Greedy initial layout (Sec. 3.6, Algorithm 3) from `start` at (0, 0).
+
+    Components the start cannot reach begin, lowest unvisited id first, at
+    their positions in (xr, yr) (zeros when not given).  Returns (x, y, parent).
+    """
+    rp, ci = _csr(rowptr, colidx)
+    n = len(rp) - 1
+    xr = np.zeros(n) if xr is None else _f64(xr)
+    yr = np.zeros(n) if yr is None else _f64(yr)
+    x, y, par = np.empty(n), np.empty(n), np.empty(n, np.int32)
+    rc = _load().orc_greedy_init(n, rp, ci, int(start), xr, yr, x, y, par)
+    if rc != 0:
+        raise ValueError("greedy_init: bad arguments (%d)" % rc)
+    return x, y, par

@@ -29,6 +29,10 @@
  *    a cell is accepted when side < theta * distance, a cell holding i is
  *    always opened, leaves (single vertices, or depth-16 buckets) interact
  *    exactly using the live coordinates of their members.
+ *  - Greedy initialisation, Sec. 3.6 and Algorithm 3: a stack-driven
+ *    traversal from a start vertex at (0, 0); each popped vertex places its
+ *    unvisited neighbours on the unit circle around itself, at angles that
+ *    advance by 360 / degree degrees, with the paper's constant 3.1416 for pi.
  */
 #include <math.h>
 #include <stdint.h>
@@ -589,4 +593,56 @@ double orc_stress(int n, const int *rowptr, const int *colidx,
     if (B == 0.0) { if (scale_out) *scale_out = 0.0; return N; }
     if (scale_out) *scale_out = A / B;
     return N - A * A / B;
+}
+
+/* ------------------------------------------------- greedy initialisation */
+
+/* Greedy initialisation, Sec. 3.6 and Algorithm 3.  The start vertex sits at
+ * (0, 0) and is pushed on an empty stack.  While the stack is not empty, pop
+ * U; with d = 360 / deg(U) (all neighbours counted) and D = 0, every
+ * neighbour u of U, in row order, that is not yet visited is placed at
+ * U + (cos(PI*D/180), sin(PI*D/180)) with PI = 3.1416, marked visited and
+ * pushed, and D grows by d.  Vertices the start cannot reach (the paper is
+ * silent): the lowest-id unvisited vertex starts a new traversal from its
+ * given position (xr, yr), repeated until every vertex is placed.
+ * parent[v] is the vertex that placed v (-1 for the start and the roots). */
+int orc_greedy_init(int n, const int *rowptr, const int *colidx, int start,
+                    const double *xr, const double *yr, double *x, double *y, int *parent)
+{
+    const double PI = 3.1416;
+    if (n < 1 || start < 0 || start >= n) return -1;
+    int *stack = malloc(sizeof(int) * n);
+    char *visited = calloc(n, 1);
+    if (!stack || !visited) { free(stack); free(visited); return -2; }
+    int root = start, next = 0;
+    for (;;) {
+        if (root == start) { x[root] = 0.0; y[root] = 0.0; }
+        else { x[root] = xr[root]; y[root] = yr[root]; }
+        visited[root] = 1;
+        parent[root] = -1;
+        int sp = 0;
+        stack[sp++] = root;
+        while (sp > 0) {
+            int U = stack[--sp];
+            int deg = rowptr[U + 1] - rowptr[U];
+            if (deg == 0) continue;
+            double d = 360.0 / deg;
+            double D = 0.0;
+            for (int k = rowptr[U]; k < rowptr[U + 1]; ++k) {
+                int u = colidx[k];
+                if (visited[u]) continue;
+                x[u] = x[U] + cos(PI * D / 180.0);
+                y[u] = y[U] + sin(PI * D / 180.0);
+                visited[u] = 1;
+                parent[u] = U;
+                stack[sp++] = u;
+                D = D + d;
+            }
+        }
+        while (next < n && visited[next]) ++next;
+        if (next == n) break;
+        root = next;
+    }
+    free(stack); free(visited);
+    return 0;
 }

@@ -588,3 +588,103 @@ def test_energy_stopping_rule(mode):
         xp, yp, ep = run(want)
         assert np.array_equal(xs, xp) and np.array_equal(ys, yp) and np.array_equal(es, ep)
     assert len(run(16, 10.0)[2]) == 2
+
+
+# --------------------------------------------------- greedy initialisation
+
+def _angle(dx, dy):
+    return math.atan2(dy, dx) % (2 * math.pi)
+
+
+def test_greedy_path_from_an_end_is_the_unit_line():
+    """Alg. 3 from an end of a path: every vertex is one unit further along +x (angle 0 each time)."""
+    g = I.path(9)
+    x, y, par = oracle.greedy_init(g.rowptr, g.colidx, 0)
+    assert np.array_equal(x, np.arange(9.0)) and np.array_equal(y, np.zeros(9))
+    assert list(par) == [-1] + list(range(8))
+
+
+def test_greedy_uses_the_papers_pi_and_a_stack():
+    """Path 0-1-2-3-4 from 2: vertex 1 at angle 0, vertex 3 at 180 degrees of the paper's PI = 3.1416,
+    so 3 lies sin(3.1416) = -(3.1416 - pi) + O(eps^3) below the axis; 3 is popped first (last pushed)
+    and places 4 at angle 0 from itself; then 1 places 0."""
+    g = I.path(5)
+    x, y, par = oracle.greedy_init(g.rowptr, g.colidx, 2)
+    assert (x[2], y[2]) == (0.0, 0.0)
+    assert (x[1], y[1]) == (1.0, 0.0) and (x[0], y[0]) == (2.0, 0.0)
+    eps = 3.1416 - math.pi
+    assert y[3] == pytest.approx(-eps, rel=1e-9)
+    assert x[3] == pytest.approx(-1.0 + eps * eps / 2, abs=1e-15)
+    assert x[4] == x[3] + 1.0 and y[4] == y[3]
+    assert list(par) == [1, 2, -1, 2, 3]
+
+
+def test_greedy_depth_first_not_breadth_first():
+    """Square 0-1-3-2-0 from 0: 1 and 2 are pushed in that order, 2 is popped first and places 3
+    at angle 0 from itself, next to the origin (a queue would let 1 place it, at (2, 0))."""
+    g = I.csr_from_edges(4, np.array([0, 0, 1, 2]), np.array([1, 2, 3, 3]))
+    x, y, par = oracle.greedy_init(g.rowptr, g.colidx, 0)
+    assert par[3] == 2
+    assert x[3] == x[2] + 1.0 and y[3] == y[2]
+    assert abs(x[3]) < 1e-9 and abs(y[3]) < 1e-5
+
+
+@pytest.mark.parametrize("m", [3, 7, 12])
+def test_greedy_star_angles_count_every_neighbour(m):
+    """Star with centre 0.  From the centre the leaves sit on the unit circle 2*3.1416/m radians apart
+    in row order.  From leaf 1 the centre lands at (1, 0) and places the other m - 1 leaves at the
+    same spacing: the degree counts the visited neighbour too."""
+    g = I.csr_from_edges(m + 1, np.zeros(m, np.int64), np.arange(1, m + 1))
+    step = 2 * 3.1416 / m
+    x, y, _ = oracle.greedy_init(g.rowptr, g.colidx, 0)
+    assert (x[1], y[1]) == (1.0, 0.0)
+    for k in range(1, m + 1):
+        assert math.hypot(x[k], y[k]) == pytest.approx(1.0, abs=1e-15)
+        assert _angle(x[k], y[k]) == pytest.approx((k - 1) * step % (2 * math.pi), abs=1e-12)
+    x, y, _ = oracle.greedy_init(g.rowptr, g.colidx, 1)
+    assert (x[0], y[0]) == (1.0, 0.0) and (x[2], y[2]) == (2.0, 0.0)
+    for k in range(2, m + 1):
+        assert _angle(x[k] - x[0], y[k] - y[0]) == pytest.approx((k - 2) * step % (2 * math.pi), abs=1e-12)
+
+
+def test_greedy_tree_invariants_and_components():
+    """Random graph with several components and isolated vertices: every vertex is placed once;
+    a non-root lies at distance 1 from the neighbour that placed it; the children of a vertex
+    sit at angles 0, s, 2s, ... with s = 2*3.1416/deg in row order; the start is at the origin and
+    each other component's root is its lowest id, at its given position."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    g = random_graph(300, 0.006, 41)
+    n = g.n
+    xr, yr = I.uniform_coords(n, 42)
+    start = 17
+    x, y, par = oracle.greedy_init(g.rowptr, g.colidx, start, xr, yr)
+    A = csr_matrix((np.ones(g.nnz), g.colidx, g.rowptr), shape=(n, n))
+    ncomp, lab = connected_components(A, directed=False)
+    assert ncomp > 5
+    roots = np.flatnonzero(par < 0)
+    assert len(roots) == ncomp and len(set(lab[roots])) == ncomp
+    assert (x[start], y[start]) == (0.0, 0.0)
+    for r in roots:
+        if r != start:
+            assert r == np.flatnonzero(lab == lab[r]).min()
+            assert (x[r], y[r]) == (xr[r], yr[r])
+    kids = {}
+    for v in range(n):
+        u = par[v]
+        if u < 0:
+            continue
+        assert v in g.colidx[g.rowptr[u]:g.rowptr[u + 1]]
+        assert math.hypot(x[v] - x[u], y[v] - y[u]) == pytest.approx(1.0, abs=1e-12)
+        kids.setdefault(u, []).append(v)
+    for u, vs in kids.items():
+        s = 2 * 3.1416 / (g.rowptr[u + 1] - g.rowptr[u])
+        for k, v in enumerate(sorted(vs)):
+            assert _angle(x[v] - x[u], y[v] - y[u]) == pytest.approx(k * s % (2 * math.pi), abs=1e-9)
+    # the tree is acyclic: following parents always reaches a root
+    for v in range(n):
+        seen, u = 0, v
+        while par[u] >= 0:
+            u = par[u]
+            seen += 1
+            assert seen <= n
