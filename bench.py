@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 FLOP (FMA) x 2.4 GHz, non-packed FP32
 FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X vector FP64
 # Algorithmic work per unit (see the design notes):
-BYTES_PER_VISIT = 24.0           # float4 (centroid, side^2, count) + int2 (skip, vertex) per node visit
+BYTES_PER_VISIT = 24.0           # float4 (centroid hi, side^2, count) + int2 (skip, vertex) per node visit
+BYTES_PER_CELL_TEST = 8.0        # float2 centroid remainder per cell tested by the acceptance criterion
 BYTES_PER_WALK_VERTEX = 32.0     # order id 4 + own x,y 8 + far-field sum 16 + late count 4
 BYTES_PER_LIST_WORD = 8.0        # late-list entry: row in batch << 32 | vertex (bit 31: leaf)
 BYTES_PER_GATHER = 8.0           # x,y of the vertex an entry refers to
@@ -120,6 +121,31 @@ def cpu_baseline(w, budget_s):
                       "1 thread, %.1f s" % (done, w["iterations"], el)}
 
 
+def greedy_report(api, w, p, steps, with_oracle, energy_random):
+    """The greedy initial layout (Sec. 3.6) of the workload's graph from vertex
+    0, the library's host routine timed (median of 5), and the same run as the
+    timed one started from it instead of the random start (its last energy
+    beside the random start's)."""
+    g = w["graph"]
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        xg, yg = api.greedy_init(g, 0, w["x0"], w["y0"])
+        ts.append(time.perf_counter() - t0)
+    sec = sorted(ts)[len(ts) // 2]
+    rep = {"seconds": sec, "entries_per_s": (g.n + g.nnz) / sec, "start": 0,
+           "note": "host routine; unreached components start from the random layout"}
+    _, _, en, _ = api.layout(g, xg, yg, p)
+    rep["energy_last"] = float(en[-1]) if len(en) else None
+    rep["energy_last_random_start"] = energy_random
+    if with_oracle:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.greedy_init(g.rowptr, g.colidx, 0, w["x0"], w["y0"])
+        rep["oracle_seconds"] = time.perf_counter() - t0
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +161,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel hipEvent timing")
     ap.add_argument("--profile-steps", type=int, default=100, help="iterations of the per-kernel timing run")
     ap.add_argument("--no-end-to-end", action="store_true", help="skip the run through host arrays")
+    ap.add_argument("--no-greedy", action="store_true", help="skip the greedy-initialisation report")
     ap.add_argument("--precision", default="fp32_kahan")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -210,8 +237,9 @@ def main():
         if w["mode"] == "bh":
             visits = st["node_visits"]
             old_e, recent_e = dev.profile_read("old_entries")[1], dev.profile_read("recent_entries")[1]
+            tests = dev.profile_read("cell_tests")[1]
             rows = float(g.n) * psteps   # every row once per iteration in each kernel below
-            work = {"far_kernel": BYTES_PER_VISIT * visits + BYTES_PER_WALK_VERTEX * rows,
+            work = {"far_kernel": BYTES_PER_VISIT * visits + BYTES_PER_CELL_TEST * tests + BYTES_PER_WALK_VERTEX * rows,
                     "chain_kernel": BYTES_PER_CHAIN_ROW * rows + BYTES_PER_LIST_WORD * recent_e,
                     "old_sum_kernel": BYTES_PER_OLD_ROW * rows + (BYTES_PER_LIST_WORD + BYTES_PER_GATHER) * old_e}
             for k, total in work.items():
@@ -225,7 +253,8 @@ def main():
                                "traffic": measured_traffic(args.config, dom_name), "kernel": dom_name,
                                "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
             nb = (g.n + w["batch_size"] - 1) // w["batch_size"]
-            out["bh"] = {"node_visits_per_vertex": visits / rows, "late_entries_per_vertex": late / rows,
+            out["bh"] = {"node_visits_per_vertex": visits / rows, "cell_tests_per_vertex": tests / rows,
+                         "late_entries_per_vertex": late / rows,
                          "old_entries_per_vertex": old_e / rows, "recent_entries_per_vertex": recent_e / rows,
                          "late_overflow": st["late_overflow"],
                          "chain_us_per_batch": 1e3 * kern["chain_kernel"]["total_ms"] / (nb * psteps)}
@@ -267,6 +296,9 @@ def main():
         out["end_to_end"] = {"force_updates_per_s": g.n * steps / e2e, "seconds": e2e,
                              "note": "bl_layout from host arrays: CSR and coordinates uploaded, "
                                      "device state built, the run, coordinates back"}
+    if not args.no_greedy:
+        out["greedy_init"] = greedy_report(api, w, p, steps, not args.no_cpu_baseline,
+                                           float(energy[-1]) if len(energy) else None)
     if args.config == "c3" and args.precision == "fp32_kahan":
         out["precision"] = precision_report(api, w, dev, x0, y0, min(steps, 20))
     if not args.no_cpu_baseline:

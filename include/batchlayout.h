@@ -136,6 +136,24 @@ int bl_layout(const bl_csr *g, const double *x0, const double *y0, const bl_para
               void *hip_stream, double *x_out, double *y_out, double *energy_out,
               bl_stats *stats);
 
+/* ------------------------------------------------ greedy initial layout
+ * The greedy initialisation of Sec. 3.6 (Algorithm 3): `start` is placed at
+ * (0, 0) and pushed on a stack; each popped vertex U places every neighbour
+ * that is not yet placed, in row order, on the unit circle around U, at
+ * angles 0, d, 2d, ... degrees with d = 360 / deg(U) (deg counts all of U's
+ * neighbours) and pi taken as the paper's 3.1416, and pushes it.  The paper
+ * draws `start` at random; the caller passes it.
+ * x, y (host FP64, length n) are in/out.  On entry only the entries of
+ * vertices that `start` cannot reach are read: the lowest-id vertex of each
+ * such component keeps its position and the component is placed from it the
+ * same way, components in increasing order of that id.  On return they hold
+ * the initial layout for bl_layout.  g must be host memory (no
+ * BL_DEVICE_PTRS); rows in the order the traversal should see them.
+ * Runs on the host (a sequential O(n + m) traversal), no device work.
+ * Errors: BL_E_INVAL for NULL arrays, start out of range or a malformed CSR
+ * (rowptr not monotone, colidx out of range), BL_E_NOMEM. */
+int bl_greedy_init(const bl_csr *g, int32_t start, double *x, double *y);
+
 /* --------------------------------------------------------- one minibatch
  * Net forces (attraction + repulsion, no update) on the vertices of batch
  * `batch_index` (ids [b*BS, min((b+1)*BS, n))) from coordinates (x, y)
@@ -189,7 +207,8 @@ int bl_graph_profile(bl_graph *h, int32_t enable);
  * launch).  Counts instead of times, returned in *launches: "late_entries"
  * (moved-leaf entries the far-field walks listed), "old_entries" and
  * "recent_entries" (moved-neighbour and moved-leaf entries summed by the
- * segment kernel and by the chain). */
+ * segment kernel and by the chain), "cell_tests" (cells the far-field walks
+ * tested with the acceptance criterion). */
 int bl_graph_profile_read(bl_graph *h, const char *kernel, double *total_ms, int64_t *launches);
 
 /* -------------------------------------------------- many graphs at once

@@ -121,6 +121,26 @@ def layout(graph, x0, y0, p: Params, stream=None, energy=True):
     return xo, yo, en[:st.iters_run], st.as_dict()
 
 
+def greedy_init(graph, start, x=None, y=None):
+    """Greedy initial layout (Sec. 3.6, Algorithm 3) from vertex `start` at (0, 0).
+
+    (x, y): host positions whose entries for the lowest id of each component
+    that `start` does not reach are kept as that component's origin (zeros
+    when not given).  Returns new host arrays (x, y).
+    """
+    lib = load()
+    keep = _Keep()
+    if _device(graph.rowptr, x, y):
+        raise ValueError("greedy_init takes host arrays")
+    csr = _csr(graph, keep)
+    xo = np.zeros(csr.n) if x is None else np.array(x, dtype=np.float64)
+    yo = np.zeros(csr.n) if y is None else np.array(y, dtype=np.float64)
+    if xo.shape != (csr.n,) or yo.shape != (csr.n,):
+        raise ValueError("x and y need n entries")
+    check(lib.bl_greedy_init(C.byref(csr), int(start), xo.ctypes.data, yo.ctypes.data))
+    return xo, yo
+
+
 def forces(graph, x, y, batch_index, p: Params, snapshot=None, stream=None):
     """Net forces on one batch from (x, y); BH tree from `snapshot` (sx, sy) if given."""
     lib = load()

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbatchlayout.so")
-SOURCES = ["bl_capi.cpp", "bl_common.hip", "bl_exact.hip", "bl_bh.hip", "bl_batch.hip", "bl_server.cpp"]
+SOURCES = ["bl_capi.cpp", "bl_common.hip", "bl_exact.hip", "bl_bh.hip", "bl_batch.hip", "bl_server.cpp",
+           "bl_init.cpp"]
 ARCH = os.environ.get("BL_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -92,6 +92,7 @@ struct BHJob {
     gptr<double> pdd, pdd_part;
     gptr<float4> nodeA;
     gptr<int2> nodeB;
+    gptr<float2> nodeC;
     gptr<int> leafpos, nnodes;
     gptr<float4> far;
     gptr<int> late_cnt, late_ids, late_att, old_att, heavy, nheavy;
@@ -617,8 +618,13 @@ __global__ void emit_kernel(BH_KERNEL_ARGS) {
             const float side = ldexpf(W, -lvl);
             side2 = side * side;
         }
-        st<float4>(J.nodeA, v, float4{(float)cx, (float)cy, side2, (float)cnt});
+        // the centroid as a float pair hi + lo: with hi alone its rounding
+        // (half an ulp of the coordinate) would be large next to the
+        // distance of a nearby accepted cell
+        const float hx = (float)cx, hy = (float)cy;
+        st<float4>(J.nodeA, v, float4{hx, hy, side2, (float)cnt});
         st<int2>(J.nodeB, v, int2{skip, -1});
+        st<float2>(J.nodeC, v, float2{(float)(cx - (double)hx), (float)(cy - (double)hy)});
         ++v;
     }
     const int vert = J.val0[p];
@@ -635,6 +641,7 @@ struct WalkArgs {
     gptr<const int> total;  // node count, written by emit_kernel
     gptr<const float4> nodeA;
     gptr<const int2> nodeB;
+    gptr<const float2> nodeC;
     gptr<const int> leafpos;
     float theta2, negRK2, invK;
 };
@@ -653,11 +660,12 @@ __device__ __forceinline__ void rep_add(float dx, float dy, float mult, float &s
 // (already moved this iteration) are appended to late[] instead of summed.
 // live != nullptr: every leaf uses live coordinates.
 __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_below,
-                       gptr<const float2> live, float4 &acc, gptr<int> late, int &nlate, int cap) {
+                       gptr<const float2> live, float4 &acc, gptr<int> late, int &nlate, int cap,
+                       int *tests = nullptr) {
     const int Li = a.leafpos[i];
     const int total = *a.total;
     float sx = 0.f, cx = 0.f, sy = 0.f, cy = 0.f;
-    int visits = 0;
+    int visits = 0, ntest = 0;
     int v = 0;
     while (v < total) {
         const float4 A = ld<float4>(a.nodeA, v);
@@ -680,7 +688,10 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
         } else if (v <= Li && Li < B.x) {
             ++v;   // the cell holds i: always opened
         } else {
-            const float dx = A.x - xi, dy = A.y - yi;
+            // offset to the centroid hi + lo: (hi - x_i) + lo
+            const float2 lo = ld<float2>(a.nodeC, v);
+            ++ntest;
+            const float dx = (A.x - xi) + lo.x, dy = (A.y - yi) + lo.y;
             const float d2 = dx * dx + dy * dy;
             if (A.z < a.theta2 * d2) {
                 rep_add(dx, dy, A.w, sx, cx, sy, cy);
@@ -691,6 +702,7 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
         }
     }
     acc = float4{sx, sy, cx, cy};
+    if (tests) *tests = ntest;
     return visits;
 }
 
@@ -701,6 +713,7 @@ __device__ __forceinline__ WalkArgs walk_args(const BHJob &J) {
     w.total = J.nnodes;
     w.nodeA = J.nodeA;
     w.nodeB = J.nodeB;
+    w.nodeC = J.nodeC;
     w.leafpos = J.leafpos;
     w.theta2 = J.theta2;
     w.negRK2 = J.negRK2;
@@ -712,7 +725,7 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     const WalkArgs a = walk_args(J);
     const int p = jb.local * blockDim.x + threadIdx.x;
-    int visits = 0, ovf = 0, lat = 0;
+    int visits = 0, ovf = 0, lat = 0, tests = 0;
     if (p < a.n) {
         const int i = J.val0[p];
         const int late_below = J.snapshot_leaves ? 0 : (J.all_live ? a.n : (i / a.BS) * a.BS);
@@ -720,7 +733,7 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
         int nlate = 0;
         const float2 pi = ld<float2>(J.pos, i);
         visits = bh_walk(a, i, pi.x, pi.y, late_below, nullptr, acc, J.late_ids + (size_t)i * kLateCap, nlate,
-                         kLateCap);
+                         kLateCap, &tests);
         st<float4>(J.far, i, acc);
         J.late_cnt[i] = nlate;
         ovf = nlate > kLateCap;
@@ -729,8 +742,10 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
     unsigned long long vs = wave_sum((unsigned long long)visits);
     unsigned long long os = wave_sum((unsigned long long)ovf);
     unsigned long long ls = wave_sum((unsigned long long)lat);
+    unsigned long long ts = wave_sum((unsigned long long)tests);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         if (vs) atomicAdd(&J.ctr->visits, vs);
+        if (ts) atomicAdd(&J.ctr->cell_tests, ts);
         if (os) atomicAdd(&J.ctr->late_overflow, os);
         if (ls) atomicAdd(&J.ctr->late_total, ls);
     }
@@ -1609,6 +1624,7 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->pdd_part = (decltype(J->pdd_part))(h.pdd_part);
     J->nodeA = (decltype(J->nodeA))(h.nodeA);
     J->nodeB = (decltype(J->nodeB))(h.nodeB);
+    J->nodeC = (decltype(J->nodeC))(h.nodeC);
     J->leafpos = (decltype(J->leafpos))(h.leafpos);
     J->nnodes = (decltype(J->nnodes))(h.nnodes);
     J->far = (decltype(J->far))(h.far);
@@ -1796,7 +1812,7 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
     const size_t sblocks = (N + kScanTile - 1) / kScanTile;
     const size_t nb = (N + BS - 1) / BS;
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
-           32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
+           32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
            8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1);
 }
@@ -1820,6 +1836,7 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.pdd_part, 32 * (sblocks + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.nodeA, 16 * 2 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nodeB, 8 * 2 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.nodeC, 8 * 2 * N));
     BL_TRY(graph_alloc(g, (void **)&h.leafpos, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nnodes, 16));
     BL_TRY(graph_alloc(g, (void **)&h.far, 16 * N));

@@ -80,7 +80,7 @@ int check_params(const bl_params *p) {
 // Host-side CSR checks.  Always: sizes, rowptr monotone, colidx in range (an
 // out-of-range id would make a kernel read outside its buffers).  With
 // BL_VALIDATE also: sorted rows, no self-loops or duplicates, symmetry.
-static int check_csr_host(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, bool full) {
+int check_csr_host(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, bool full) {
     if (rp[0] != 0) return fail(BL_E_INVAL, "rowptr[0] must be 0");
     for (int i = 0; i < n; ++i)
         if (rp[i + 1] < rp[i]) return fail(BL_E_INVAL, "rowptr decreases at row %d", i);
@@ -352,6 +352,7 @@ static int run_impl(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t
         g->prof->late_total += (long long)c.late_total;
         g->prof->old_total += (long long)c.old_total;
         g->prof->recent_total += (long long)c.recent_total;
+        g->prof->cell_tests += (long long)c.cell_tests;
     }
     if (st) {
         std::memset(st, 0, sizeof *st);
@@ -391,6 +392,7 @@ int bl_graph_profile(bl_graph *g, int32_t enable) {
     P.late_total = 0;
     P.old_total = 0;
     P.recent_total = 0;
+    P.cell_tests = 0;
     P.on = enable != 0;
     return BL_OK;
 }
@@ -411,6 +413,10 @@ int bl_graph_profile_read(bl_graph *g, const char *kernel, double *total_ms, int
     }
     if (!std::strcmp(kernel, "recent_entries")) {
         *launches = g->prof->recent_total;
+        return BL_OK;
+    }
+    if (!std::strcmp(kernel, "cell_tests")) {
+        *launches = g->prof->cell_tests;
         return BL_OK;
     }
     for (int q = 0; q < PK_COUNT; ++q)

@@ -41,6 +41,7 @@ struct Counters {
     unsigned long long recent_total;   // late entries summed by the chain
     unsigned long long wait_abort;     // a bounded device wait ran out (the launch left early)
     unsigned long long halted;         // the energy stopping rule held after this many iterations
+    unsigned long long cell_tests;     // far-field walks: cells tested by the acceptance criterion
 };
 
 // Per-kernel device time, measured with hipEvents around launches when a
@@ -55,7 +56,7 @@ struct Prof {
     double ms[PK_COUNT] = {};
     long long launches[PK_COUNT] = {};
     long long late_total = 0;
-    long long old_total = 0, recent_total = 0;
+    long long old_total = 0, recent_total = 0, cell_tests = 0;
 };
 
 struct BHEngine;
@@ -76,6 +77,7 @@ struct BHBuffers {
     double *pdd_part;       // [4 * blocks]
     float4 *nodeA;          // [2n]: cx, cy, side^2 (inf for buckets), count
     int2 *nodeB;            // [2n]: skip, vertex (-1 for cells)
+    float2 *nodeC;          // [2n]: cells' centroid remainders c - (float)c (the centroid is hi + lo)
     int *leafpos;           // [n]: pre-order index of each vertex's leaf
     int *nnodes;            // [1]
     float4 *far;            // [n]: Kahan (sx, sy, cx, cy) of the far-field sum
@@ -160,6 +162,9 @@ int graph_alloc(bl_graph *g, void **ptr, size_t bytes);
 // in create or destroy then waits for other streams).
 int graph_create_ex(const bl_csr *csr, const bl_params *p, hipStream_t s, bool async_mem, bl_graph **out);
 int fail_code(int code, const char *msg);
+// Host CSR checks: sizes, monotone rowptr, colidx in range; with `full` also
+// sorted rows, no self-loops or duplicates, symmetry.
+int check_csr_host(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, bool full);
 int params_check(const bl_params *p);
 int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds);
 
