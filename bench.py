@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -121,6 +123,32 @@ def cpu_baseline(w, budget_s):
                       "1 thread, %.1f s" % (done, w["iterations"], el)}
 
 
+QUALITY_PIVOTS = 1024             # BFS pivots of the stress sample at 131072 vertices
+
+
+def quality_report(api, g, x, y, with_oracle):
+    """Stress (1024 seeded pivots, or all pairs below 65536 vertices), edge
+    energy and edge uniformity of the timed run's layout (Sec. 3.7), on the
+    GPU; the oracle's evaluators timed on a 16-pivot sample."""
+    from paper_2002_08233_amd import inputs as I
+    piv = None if g.n <= 65536 else I.rng(10).integers(0, g.n, QUALITY_PIVOTS).astype(np.int32)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q = api.quality(g, x, y, piv)
+    sec = time.perf_counter() - t0
+    nsrc = g.n if piv is None else len(piv)
+    rep = dict(q, seconds=sec, sources=nsrc, pairs_per_s=q["pairs"] / sec,
+               note="bl_quality_eval from host arrays: upload, edge passes, 64-source BFS passes")
+    if with_oracle:
+        import oracle
+        sp = I.rng(11).integers(0, g.n, 16).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.stress(g.rowptr, g.colidx, x, y, sp)
+        rep["oracle_seconds_per_source"] = (time.perf_counter() - t0) / len(sp)
+    return rep
+
+
 def greedy_report(api, w, p, steps, with_oracle, energy_random):
     """The greedy initial layout (Sec. 3.6) of the workload's graph from vertex
     0, the library's host routine timed (median of 5), and the same run as the
@@ -132,7 +160,7 @@ def greedy_report(api, w, p, steps, with_oracle, energy_random):
         t0 = time.perf_counter()
         xg, yg = api.greedy_init(g, 0, w["x0"], w["y0"])
         ts.append(time.perf_counter() - t0)
-    sec = sorted(ts)[len(ts) // 2]
+    sec = float(np.median(ts))
     rep = {"seconds": sec, "entries_per_s": (g.n + g.nnz) / sec, "start": 0,
            "note": "host routine; unreached components start from the random layout"}
     _, _, en, _ = api.layout(g, xg, yg, p)
@@ -162,6 +190,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100, help="iterations of the per-kernel timing run")
     ap.add_argument("--no-end-to-end", action="store_true", help="skip the run through host arrays")
     ap.add_argument("--no-greedy", action="store_true", help="skip the greedy-initialisation report")
+    ap.add_argument("--no-quality", action="store_true", help="skip the layout-quality report")
     ap.add_argument("--precision", default="fp32_kahan")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -211,6 +240,7 @@ def main():
     energy, st = dev.run(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    xf, yf = dev.get_coords()   # the timed run's layout (quality report)
 
     value = g.n * steps / wall
     out = {"metric": METRIC, "value": value, "unit": "force-updates/s", "n_gpus": 1, "steps": steps,
@@ -296,6 +326,8 @@ def main():
         out["end_to_end"] = {"force_updates_per_s": g.n * steps / e2e, "seconds": e2e,
                              "note": "bl_layout from host arrays: CSR and coordinates uploaded, "
                                      "device state built, the run, coordinates back"}
+    if not args.no_quality:
+        out["quality"] = quality_report(api, g, xf, yf, not args.no_cpu_baseline)
     if not args.no_greedy:
         out["greedy_init"] = greedy_report(api, w, p, steps, not args.no_cpu_baseline,
                                            float(energy[-1]) if len(energy) else None)

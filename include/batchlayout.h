@@ -154,6 +154,41 @@ int bl_layout(const bl_csr *g, const double *x0, const double *y0, const bl_para
  * (rowptr not monotone, colidx out of range), BL_E_NOMEM. */
 int bl_greedy_init(const bl_csr *g, int32_t start, double *x, double *y);
 
+/* ------------------------------------------------------ layout quality
+ * The quality measures of Sec. 3.7 for the layout (x, y) of g, in FP64 on
+ * the GPU:
+ *  - stress after the best uniform scaling s: sum over pairs of
+ *    d_ij^-2 (s |c_i - c_j| - d_ij)^2, minimised over s in closed form
+ *    (N - A^2/B with A = sum |.|/d, B = sum |.|^2/d^2, N the pair count),
+ *    d_ij the BFS hop distance, pairs that cannot reach each other skipped;
+ *  - edge energy: sum over undirected edges of d^3 / (3K), the attractive
+ *    potential whose gradient is the attraction term of Sec. 2.2;
+ *  - edge uniformity: the standard deviation of edge lengths over their
+ *    mean (normalised as in Sec. 3.7).
+ * npivots = 0: stress over all unordered pairs i < j; otherwise over pairs
+ * (p, j), j != p, for each pivot p of the host array pivots[npivots]
+ * (repeats count again).  Hop distances come from a bit-parallel BFS with 64
+ * sources per pass.  With BL_DEVICE_PTRS in flags, g, x and y are device
+ * pointers (pivots stay host memory).  The work runs on hip_stream and the
+ * call returns when it is done; temporary device memory is allocated and
+ * freed inside.  Sums run in a fixed order: the same inputs give the same bits.
+ * Errors: BL_E_INVAL (NULL arrays, bad CSR, K <= 0, a pivot out of range),
+ * BL_E_NOMEM, BL_E_HIP. */
+typedef struct {
+    double  stress;          /* at the optimal scale                          */
+    double  scale;           /* the optimal s = A / B (0 when B = 0)          */
+    int64_t pairs;           /* pairs in the stress sum                       */
+    double  edge_energy;     /* sum over edges of d^3 / (3K)                  */
+    double  edge_uniformity; /* std(edge length) / mean(edge length)          */
+    int64_t edges;           /* undirected edges                              */
+    int64_t bfs_levels;      /* BFS levels launched, all passes               */
+    double  reserved[2];
+} bl_quality;
+
+int bl_quality_eval(const bl_csr *g, const double *x, const double *y, int32_t npivots,
+                    const int32_t *pivots, double K, uint32_t flags, void *hip_stream,
+                    bl_quality *out);
+
 /* --------------------------------------------------------- one minibatch
  * Net forces (attraction + repulsion, no update) on the vertices of batch
  * `batch_index` (ids [b*BS, min((b+1)*BS, n))) from coordinates (x, y)

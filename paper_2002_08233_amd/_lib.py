@@ -26,7 +26,7 @@ EXPORTED = [
     "bl_graph_create", "bl_graph_set_coords", "bl_graph_get_coords", "bl_graph_run",
     "bl_graph_destroy", "bl_graph_profile", "bl_graph_profile_read", "bl_layout_batch",
     "bl_server_create", "bl_server_submit", "bl_server_poll", "bl_server_wait", "bl_server_fetch",
-    "bl_server_release", "bl_server_destroy", "bl_greedy_init",
+    "bl_server_release", "bl_server_destroy", "bl_greedy_init", "bl_quality_eval",
 ]
 
 
@@ -56,6 +56,15 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Quality(C.Structure):
+    _fields_ = [("stress", C.c_double), ("scale", C.c_double), ("pairs", C.c_int64),
+                ("edge_energy", C.c_double), ("edge_uniformity", C.c_double), ("edges", C.c_int64),
+                ("bfs_levels", C.c_int64), ("reserved", C.c_double * 2)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 _lib = None
 
 
@@ -82,6 +91,7 @@ def load():
     lib.bl_layout.argtypes = [P(CSR), vp, vp, P(Params), vp, vp, vp, vp, P(Stats)]
     lib.bl_forces.argtypes = [P(CSR), vp, vp, vp, vp, i32, P(Params), vp, vp, vp]
     lib.bl_greedy_init.argtypes = [P(CSR), i32, vp, vp]
+    lib.bl_quality_eval.argtypes = [P(CSR), vp, vp, i32, vp, dbl, C.c_uint32, vp, P(Quality)]
     lib.bl_graph_create.argtypes = [P(CSR), P(Params), vp, P(vp)]
     lib.bl_graph_set_coords.argtypes = [vp, vp, vp, C.c_uint32]
     lib.bl_graph_get_coords.argtypes = [vp, vp, vp, C.c_uint32]

@@ -141,6 +141,26 @@ def greedy_init(graph, start, x=None, y=None):
     return xo, yo
 
 
+def quality(graph, x, y, pivots=None, K=1.0, stream=None):
+    """Stress (optimal scale, BFS hop distances), edge energy and edge
+    uniformity of the layout (x, y) (Sec. 3.7), computed on the GPU.
+
+    pivots=None: all unordered pairs; else pairs (p, j) for each pivot p.
+    Returns a dict (stress, scale, pairs, edge_energy, edge_uniformity, edges,
+    bfs_levels).
+    """
+    lib = load()
+    keep = _Keep()
+    dev = _device(graph.rowptr, x, y)
+    csr = _csr(graph, keep)
+    piv = None if pivots is None else np.ascontiguousarray(pivots, dtype=np.int32)
+    q = L.Quality()
+    check(lib.bl_quality_eval(C.byref(csr), keep.ptr(x, np.float64), keep.ptr(y, np.float64),
+                              0 if piv is None else len(piv), None if piv is None else piv.ctypes.data,
+                              float(K), BL_DEVICE_PTRS if dev else 0, _stream(stream), C.byref(q)))
+    return q.as_dict()
+
+
 def forces(graph, x, y, batch_index, p: Params, snapshot=None, stream=None):
     """Net forces on one batch from (x, y); BH tree from `snapshot` (sx, sy) if given."""
     lib = load()

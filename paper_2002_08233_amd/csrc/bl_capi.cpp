@@ -102,7 +102,7 @@ int check_csr_host(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, boo
     return BL_OK;
 }
 
-static int check_csr(const bl_csr *g, uint32_t flags, hipStream_t s) {
+int check_csr(const bl_csr *g, uint32_t flags, hipStream_t s) {
     if (!g) return fail(BL_E_INVAL, "graph is NULL");
     if (g->n < 1) return fail(BL_E_INVAL, "n must be >= 1");
     if (g->nnz < 0 || g->nnz > 0x7fffffffLL) return fail(BL_E_INVAL, "nnz out of range");

@@ -165,6 +165,8 @@ int fail_code(int code, const char *msg);
 // Host CSR checks: sizes, monotone rowptr, colidx in range; with `full` also
 // sorted rows, no self-loops or duplicates, symmetry.
 int check_csr_host(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, bool full);
+// The same checks on a graph given in host or (BL_DEVICE_PTRS) device memory.
+int check_csr(const bl_csr *g, uint32_t flags, hipStream_t s);
 int params_check(const bl_params *p);
 int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds);
 

@@ -1,0 +1,473 @@
+// Layout quality measures of Sec. 3.7 on the GPU: stress after the best
+// uniform scaling, with hop distances from a bit-parallel multi-source BFS
+// (64 sources per pass, one bit each); edge energy (the attractive potential
+// whose gradient is the attraction term); edge uniformity (normalised standard
+// deviation of edge lengths).
+//
+// Every sum runs in FP64 on a fixed grid: each thread sums its grid-stride
+// share in order, each block combines its waves in order into its own slot,
+// and one thread adds the slots in block order.  The result depends only on
+// the graph and the coordinates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bl_device.hpp"
+#include "bl_internal.hpp"
+
+namespace bl {
+namespace {
+
+using u64 = unsigned long long;
+
+constexpr int kQThreads = 256;
+constexpr int kQBlocks = 1024;
+constexpr int kSrc = 64;         // BFS sources per pass
+constexpr int kLevelGroup = 4;   // BFS levels launched between checks for an empty frontier
+
+struct Sums {
+    double s[kQBlocks][3];       // per block: stress A, B (or edge sums)
+    u64 c[kQBlocks];             // per block: pair or edge count
+};
+
+// Fixed-order sum over the block of three doubles and a count; the totals
+// land in slot blockIdx.x of S (added when `accumulate`, else stored).
+__device__ void block_slot(Sums *S, double a, double b, double c, u64 k, bool accumulate) {
+    __shared__ double ws[3][kQThreads / kWave];
+    __shared__ u64 wk[kQThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    k = wave_sum(k);
+    if (lane == 0) {
+        ws[0][w] = a;
+        ws[1][w] = b;
+        ws[2][w] = c;
+        wk[w] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        u64 tk = 0;
+        for (int q = 0; q < kQThreads / kWave; ++q) {
+            t0 += ws[0][q];
+            t1 += ws[1][q];
+            t2 += ws[2][q];
+            tk += wk[q];
+        }
+        double *d = S->s[blockIdx.x];
+        if (accumulate) {
+            d[0] += t0;
+            d[1] += t1;
+            d[2] += t2;
+            S->c[blockIdx.x] += tk;
+        } else {
+            d[0] = t0;
+            d[1] = t1;
+            d[2] = t2;
+            S->c[blockIdx.x] = tk;
+        }
+    }
+}
+
+__global__ void sums_clear_kernel(Sums *S) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < kQBlocks) {
+        S->s[b][0] = S->s[b][1] = S->s[b][2] = 0.0;
+        S->c[b] = 0;
+    }
+}
+
+// Slots added in block order by one thread: out[0..2] doubles, out[3] count.
+__global__ void sums_total_kernel(const Sums *S, double *out, u64 *count) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    u64 tk = 0;
+    for (int b = 0; b < kQBlocks; ++b) {
+        t0 += S->s[b][0];
+        t1 += S->s[b][1];
+        t2 += S->s[b][2];
+        tk += S->c[b];
+    }
+    out[0] = t0;
+    out[1] = t1;
+    out[2] = t2;
+    *count = tk;
+}
+
+__global__ void pos_kernel(int n, const double *__restrict__ x, const double *__restrict__ y, double2 *p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = double2{x[i], y[i]};
+}
+
+// Row holding CSR entry e: the largest i with rp[i] <= e (rp[n] = nnz > e).
+__device__ __forceinline__ int row_of(const int *rp, int n, int64_t e) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Edge lengths of the undirected edges (entries (i, j) with j > i).
+// pass 0: sum d^3 / (3K), sum d, count; pass 1: sum (d - mean)^2.
+__global__ __launch_bounds__(kQThreads) void edge_kernel(int n, int64_t nnz, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci, const double2 *__restrict__ p,
+                                                         double K, int pass, double mean, Sums *S) {
+    double s0 = 0.0, s1 = 0.0;
+    u64 m = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+        const int j = ci[e];
+        const int i = row_of(rp, n, e);
+        if (j <= i) continue;
+        const double2 a = p[i], b = p[j];
+        const double dx = b.x - a.x, dy = b.y - a.y;
+        const double d = sqrt(dx * dx + dy * dy);
+        if (pass == 0) {
+            s0 += d * d * d / (3.0 * K);
+            s1 += d;
+            ++m;
+        } else {
+            s0 += (d - mean) * (d - mean);
+        }
+    }
+    block_slot(S, s0, s1, 0.0, m, false);
+}
+
+__global__ void bfs_clear_kernel(int n, u64 *seen, u64 *fr) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) {
+        seen[v] = 0;
+        fr[v] = 0;
+    }
+}
+
+// Source k of the pass is src[k] (pivots) or base + k (all pairs).
+__device__ __forceinline__ int source_of(const int *src, int base, int k) { return src ? src[k] : base + k; }
+
+__global__ void bfs_sources_kernel(const int *src, int base, int ns, u64 *seen, u64 *fr) {
+    const int k = threadIdx.x;
+    if (k < ns) {
+        const int s = source_of(src, base, k);
+        atomicOr(&seen[s], 1ull << k);
+        atomicOr(&fr[s], 1ull << k);
+    }
+}
+
+__global__ void counters_clear_kernel(u64 *c, int m) {
+    if (threadIdx.x < m) c[threadIdx.x] = 0;
+}
+
+// One BFS level for the pass's sources, pulled: v is reached from source k
+// at `level` when a neighbour was in source k's frontier at level - 1 and v
+// was not reached before.  Each new (v, source) pair adds |c_v - c_s| / d and
+// |c_v - c_s|^2 / d^2 to the stress sums (for all pairs only v > s counts, so
+// each unordered pair counts once).  Rows of up to kHeavyDeg entries take a
+// group of 8 lanes (bfs_light_kernel); longer rows, the hubs of skewed
+// graphs, take a whole workgroup (bfs_heavy_kernel), so that no lane walks a
+// hub row alone.
+constexpr int kHeavyDeg = 256;
+constexpr int kGroup = 8;
+
+// OR of fin[ci[e]] over e = e0, e0 + step, ... < e1, four entries per round
+// so that their loads are in flight together.
+__device__ __forceinline__ u64 or_row(const int *__restrict__ ci, const u64 *__restrict__ fin, int e0, int e1,
+                                      int step) {
+    u64 m = 0;
+    for (int e = e0; e < e1; e += 4 * step) {
+        int c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = e + q * step < e1 ? ci[e + q * step] : -1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m |= c[q] >= 0 ? fin[c[q]] : 0ull;
+    }
+    return m;
+}
+
+struct BfsArgs {
+    int n, ns, all_pairs, level;
+    const int *rp, *ci, *src;
+    int base;
+    const double2 *p;
+    const u64 *fin;
+    u64 *fout, *seen, *newcount;
+    const int *heavy;
+    int nheavy;
+    Sums *S;
+};
+
+__device__ __forceinline__ void load_sources(const BfsArgs &a, int *ss, double2 *sp) {
+    if (threadIdx.x < a.ns) {
+        const int s = source_of(a.src, a.base, threadIdx.x);
+        ss[threadIdx.x] = s;
+        sp[threadIdx.x] = a.p[s];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void add_pair(const BfsArgs &a, int v, double2 pv, int k, const int *ss,
+                                         const double2 *sp, double &sa, double &sb, u64 &pairs) {
+    if (a.all_pairs && v < ss[k]) return;
+    const double dl = (double)a.level;
+    const double dx = pv.x - sp[k].x, dy = pv.y - sp[k].y;
+    const double g = sqrt(dx * dx + dy * dy);
+    sa += g / dl;
+    sb += g * g / (dl * dl);
+    ++pairs;
+}
+
+__global__ __launch_bounds__(kQThreads) void bfs_light_kernel(BfsArgs a) {
+    __shared__ double2 sp[kSrc];
+    __shared__ int ss[kSrc];
+    load_sources(a, ss, sp);
+    const u64 full = a.ns == kSrc ? ~0ull : ((1ull << a.ns) - 1ull);
+    const int sub = threadIdx.x & (kGroup - 1);
+    const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+    const int ngroups = gridDim.x * blockDim.x / kGroup;
+    double sa = 0.0, sb = 0.0;
+    u64 pairs = 0, fresh = 0;
+    for (int base = 0; base < a.n; base += ngroups) {   // the same trip count in every lane
+        const int v = base + gid;
+        u64 sv = 0, m = 0;
+        bool light = false;
+        if (v < a.n) {
+            sv = a.seen[v];
+            const int r0 = a.rp[v], r1 = a.rp[v + 1];
+            light = r1 - r0 <= kHeavyDeg;
+            if (light && sv != full) m = or_row(a.ci, a.fin, r0 + sub, r1, kGroup);
+        }
+        // every lane is active here: OR over the group of 8
+        m |= __shfl_xor(m, 1, kWave);
+        m |= __shfl_xor(m, 2, kWave);
+        m |= __shfl_xor(m, 4, kWave);
+        if (light) {
+            u64 nw = m & ~sv;
+            if (sub == 0) {
+                a.fout[v] = nw;
+                if (nw) a.seen[v] = sv | nw;
+                fresh += (u64)__popcll(nw);
+            }
+            if (nw) {
+                const double2 pv = a.p[v];
+                nw &= 0x0101010101010101ull << sub;   // this lane's bits: k = sub mod 8
+                while (nw) {
+                    const int k = __builtin_ctzll(nw);
+                    nw &= nw - 1ull;
+                    add_pair(a, v, pv, k, ss, sp, sa, sb, pairs);
+                }
+            }
+        }
+    }
+    block_slot(a.S, sa, sb, 0.0, pairs, true);
+    const u64 f = wave_sum(fresh);
+    if ((threadIdx.x & (kWave - 1)) == 0 && f) atomicAdd(a.newcount, f);
+}
+
+__global__ __launch_bounds__(kQThreads) void bfs_heavy_kernel(BfsArgs a) {
+    __shared__ double2 sp[kSrc];
+    __shared__ int ss[kSrc];
+    __shared__ u64 wor[kQThreads / kWave];
+    load_sources(a, ss, sp);
+    const u64 full = a.ns == kSrc ? ~0ull : ((1ull << a.ns) - 1ull);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double sa = 0.0, sb = 0.0;
+    u64 pairs = 0, fresh = 0;
+    for (int h = blockIdx.x; h < a.nheavy; h += gridDim.x) {   // uniform over the block
+        const int v = a.heavy[h];
+        const u64 sv = a.seen[v];
+        u64 m = 0;
+        if (sv != full) m = or_row(a.ci, a.fin, a.rp[v] + threadIdx.x, a.rp[v + 1], blockDim.x);
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) m |= __shfl_xor(m, o, kWave);
+        if (lane == 0) wor[w] = m;
+        __syncthreads();
+        m = 0;
+        for (int q = 0; q < kQThreads / kWave; ++q) m |= wor[q];
+        __syncthreads();
+        const u64 nw = m & ~sv;
+        if (threadIdx.x == 0) {
+            a.fout[v] = nw;
+            if (nw) a.seen[v] = sv | nw;
+            fresh += (u64)__popcll(nw);
+        }
+        if (threadIdx.x < kSrc && ((nw >> threadIdx.x) & 1ull))
+            add_pair(a, v, a.p[v], threadIdx.x, ss, sp, sa, sb, pairs);
+    }
+    block_slot(a.S, sa, sb, 0.0, pairs, true);
+    const u64 f = wave_sum(fresh);
+    if ((threadIdx.x & (kWave - 1)) == 0 && f) atomicAdd(a.newcount, f);
+}
+
+// Device buffers of one evaluation, freed on every exit path.
+struct QBuffers {
+    std::vector<void *> owned;
+    ~QBuffers() {
+        for (void *q : owned) (void)hipFree(q);
+    }
+    int alloc(void **out, size_t bytes) {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes ? bytes : 16) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail_code(BL_E_NOMEM, "hipMalloc failed in bl_quality_eval");
+        }
+        owned.push_back(q);
+        *out = q;
+        return BL_OK;
+    }
+};
+
+}  // namespace
+}  // namespace bl
+
+extern "C" int bl_quality_eval(const bl_csr *g, const double *x, const double *y, int32_t npivots,
+                               const int32_t *pivots, double K, uint32_t flags, void *hip_stream,
+                               bl_quality *out) {
+    using namespace bl;
+    if (!out) return fail_code(BL_E_INVAL, "out is NULL");
+    std::memset(out, 0, sizeof *out);
+    if (!x || !y) return fail_code(BL_E_INVAL, "coordinate arrays are NULL");
+    if (flags & ~BL_DEVICE_PTRS) return fail_code(BL_E_INVAL, "unknown flags");
+    if (!(K > 0) || !std::isfinite(K)) return fail_code(BL_E_INVAL, "K must be > 0");
+    if (npivots < 0 || (npivots > 0 && !pivots)) return fail_code(BL_E_INVAL, "bad pivot list");
+    hipStream_t s = (hipStream_t)hip_stream;
+    BL_TRY(check_csr(g, flags, s));
+    const int n = g->n;
+    const int64_t nnz = g->nnz;
+    for (int q = 0; q < npivots; ++q)
+        if (pivots[q] < 0 || pivots[q] >= n) return fail_code(BL_E_INVAL, "pivot out of range");
+    const bool dev = (flags & BL_DEVICE_PTRS) != 0;
+    const hipMemcpyKind h2d = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+
+    QBuffers B;
+    int *rp, *ci, *src = nullptr;
+    double *dx, *dy, *tot;
+    double2 *p;
+    u64 *seen, *fr[2], *cnt, *newc;
+    int *heavy;
+    Sums *S;
+    BL_TRY(B.alloc((void **)&rp, sizeof(int) * (size_t)(n + 1)));
+    BL_TRY(B.alloc((void **)&ci, sizeof(int) * (size_t)nnz));
+    BL_TRY(B.alloc((void **)&dx, sizeof(double) * (size_t)n));
+    BL_TRY(B.alloc((void **)&dy, sizeof(double) * (size_t)n));
+    BL_TRY(B.alloc((void **)&p, sizeof(double2) * (size_t)n));
+    BL_TRY(B.alloc((void **)&seen, sizeof(u64) * (size_t)n));
+    BL_TRY(B.alloc((void **)&fr[0], sizeof(u64) * (size_t)n));
+    BL_TRY(B.alloc((void **)&fr[1], sizeof(u64) * (size_t)n));
+    BL_TRY(B.alloc((void **)&S, sizeof(Sums)));
+    BL_TRY(B.alloc((void **)&tot, sizeof(double) * 4));
+    BL_TRY(B.alloc((void **)&cnt, sizeof(u64) * 2));
+    BL_TRY(B.alloc((void **)&newc, sizeof(u64) * kLevelGroup));
+    if (npivots > 0) {
+        BL_TRY(B.alloc((void **)&src, sizeof(int) * (size_t)npivots));
+        BL_HIP(hipMemcpyAsync(src, pivots, sizeof(int) * (size_t)npivots, hipMemcpyHostToDevice, s));
+    }
+    BL_HIP(hipMemcpyAsync(rp, g->rowptr, sizeof(int) * (size_t)(n + 1), h2d, s));
+    if (nnz) BL_HIP(hipMemcpyAsync(ci, g->colidx, sizeof(int) * (size_t)nnz, h2d, s));
+    BL_HIP(hipMemcpyAsync(dx, x, sizeof(double) * (size_t)n, h2d, s));
+    BL_HIP(hipMemcpyAsync(dy, y, sizeof(double) * (size_t)n, h2d, s));
+    // rows longer than kHeavyDeg, listed once for the heavy BFS kernel
+    std::vector<int32_t> rph;
+    const int32_t *rpv = g->rowptr;
+    if (dev) {
+        rph.resize((size_t)n + 1);
+        BL_HIP(hipMemcpyAsync(rph.data(), g->rowptr, sizeof(int) * (size_t)(n + 1), hipMemcpyDeviceToHost, s));
+        BL_HIP(hipStreamSynchronize(s));
+        rpv = rph.data();
+    }
+    std::vector<int32_t> hv;
+    for (int v = 0; v < n; ++v)
+        if (rpv[v + 1] - rpv[v] > kHeavyDeg) hv.push_back(v);
+    BL_TRY(B.alloc((void **)&heavy, sizeof(int) * std::max<size_t>(hv.size(), 1)));
+    if (!hv.empty()) BL_HIP(hipMemcpyAsync(heavy, hv.data(), sizeof(int) * hv.size(), hipMemcpyHostToDevice, s));
+    const int nheavy = (int)hv.size();
+    const int vb = (n + 255) / 256;
+    hipLaunchKernelGGL(pos_kernel, dim3(vb), dim3(256), 0, s, n, dx, dy, p);
+
+    // edge energy and uniformity: two passes over the entries
+    double h[4];
+    u64 hc[2];
+    hipLaunchKernelGGL(edge_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, n, nnz, rp, ci, p, K, 0, 0.0, S);
+    hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, S, tot, cnt);
+    BL_HIP(hipMemcpyAsync(h, tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    BL_HIP(hipMemcpyAsync(hc, cnt, sizeof(u64), hipMemcpyDeviceToHost, s));
+    BL_HIP(hipStreamSynchronize(s));
+    const u64 m = hc[0];
+    out->edges = (int64_t)m;
+    out->edge_energy = h[0];
+    if (m > 0) {
+        const double mean = h[1] / (double)m;
+        hipLaunchKernelGGL(edge_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, n, nnz, rp, ci, p, K, 1, mean, S);
+        hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, S, tot, cnt);
+        BL_HIP(hipMemcpyAsync(h, tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+        BL_HIP(hipStreamSynchronize(s));
+        out->edge_uniformity = mean > 0 ? std::sqrt(h[0] / ((double)m * mean * mean)) : 0.0;
+    }
+
+    // stress: sources in passes of 64
+    hipLaunchKernelGGL(sums_clear_kernel, dim3((kQBlocks + 255) / 256), dim3(256), 0, s, S);
+    const int nsrc_total = npivots > 0 ? npivots : n;
+    int levels = 0;
+    for (int base = 0; base < nsrc_total; base += kSrc) {
+        const int ns = std::min(kSrc, nsrc_total - base);
+        const int *sp = src ? src + base : nullptr;
+        hipLaunchKernelGGL(bfs_clear_kernel, dim3(vb), dim3(256), 0, s, n, seen, fr[0]);
+        hipLaunchKernelGGL(bfs_sources_kernel, dim3(1), dim3(kSrc), 0, s, sp, base, ns, seen, fr[0]);
+        int cur = 0;
+        for (int level = 1; level < n + 1; level += kLevelGroup) {
+            hipLaunchKernelGGL(counters_clear_kernel, dim3(1), dim3(kLevelGroup), 0, s, newc, kLevelGroup);
+            for (int q = 0; q < kLevelGroup; ++q) {
+                BfsArgs a;
+                a.n = n;
+                a.ns = ns;
+                a.all_pairs = npivots > 0 ? 0 : 1;
+                a.level = level + q;
+                a.rp = rp;
+                a.ci = ci;
+                a.src = sp;
+                a.base = base;
+                a.p = p;
+                a.fin = fr[cur];
+                a.fout = fr[cur ^ 1];
+                a.seen = seen;
+                a.newcount = newc + q;
+                a.heavy = heavy;
+                a.nheavy = nheavy;
+                a.S = S;
+                hipLaunchKernelGGL(bfs_light_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, a);
+                if (nheavy)
+                    hipLaunchKernelGGL(bfs_heavy_kernel, dim3(std::min(nheavy, kQBlocks)), dim3(kQThreads), 0, s, a);
+                cur ^= 1;
+            }
+            u64 nc[kLevelGroup];
+            BL_HIP(hipMemcpyAsync(nc, newc, sizeof nc, hipMemcpyDeviceToHost, s));
+            BL_HIP(hipStreamSynchronize(s));
+            levels += kLevelGroup;
+            bool done = false;
+            for (int q = 0; q < kLevelGroup; ++q) done = done || nc[q] == 0;
+            if (done) break;
+        }
+    }
+    hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, S, tot, cnt);
+    BL_HIP(hipMemcpyAsync(h, tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    BL_HIP(hipMemcpyAsync(hc, cnt, sizeof(u64), hipMemcpyDeviceToHost, s));
+    BL_HIP(hipStreamSynchronize(s));
+    BL_HIP(hipGetLastError());
+    const double A = h[0], Bs = h[1], N = (double)hc[0];
+    out->pairs = (int64_t)hc[0];
+    out->bfs_levels = levels;
+    if (Bs == 0.0) {
+        out->stress = N;
+        out->scale = 0.0;
+    } else {
+        out->stress = N - A * A / Bs;
+        out->scale = A / Bs;
+    }
+    return BL_OK;
+}

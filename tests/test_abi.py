@@ -122,7 +122,7 @@ def test_batch_argument_checks(lib):
     assert lib.bl_layout_batch(2, None, None, None, None, None, None, None, None) == -1
 
 
-def test_params_and_stats_layout_match_the_header(tmp_path):
+def test_struct_layouts_match_the_header(tmp_path):
     """The binding's ctypes structs have the sizes and field offsets that a C
     compiler gives the header's structs."""
     import ctypes as C
@@ -131,11 +131,14 @@ def test_params_and_stats_layout_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     fields = [f for f, _ in _lib.Params._fields_]
     sfields = [f for f, _ in _lib.Stats._fields_]
+    qfields = [f for f, _ in _lib.Quality._fields_]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "batchlayout.h"', 'int main(void) {',
              '  printf("%zu\\n", sizeof(bl_params));']
     lines += ['  printf("%%zu\\n", offsetof(bl_params, %s));' % f for f in fields]
     lines += ['  printf("%zu\\n", sizeof(bl_stats));']
     lines += ['  printf("%%zu\\n", offsetof(bl_stats, %s));' % f for f in sfields]
+    lines += ['  printf("%zu\\n", sizeof(bl_quality));']
+    lines += ['  printf("%%zu\\n", offsetof(bl_quality, %s));' % f for f in qfields]
     lines += ['  return 0;', '}']
     src.write_text("\n".join(lines) + "\n")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
@@ -144,4 +147,29 @@ def test_params_and_stats_layout_match_the_header(tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [C.sizeof(_lib.Params)] + [getattr(_lib.Params, f).offset for f in fields]
     want += [C.sizeof(_lib.Stats)] + [getattr(_lib.Stats, f).offset for f in sfields]
+    want += [C.sizeof(_lib.Quality)] + [getattr(_lib.Quality, f).offset for f in qfields]
     assert got == want
+
+
+def test_quality_rejects_bad_arguments(lib):
+    """Argument checks of bl_quality_eval run on the host before any device work."""
+    import ctypes as C
+    from paper_2002_08233_amd import _lib, api, inputs
+    g = inputs.path(5)
+    keep = api._Keep()
+    csr = api._csr(g, keep)
+    x = np.zeros(5)
+    q = _lib.Quality()
+    piv = np.array([0, 7], np.int32)
+    assert lib.bl_quality_eval(C.byref(csr), x.ctypes.data, x.ctypes.data, 0, None, 1.0, 0, None, None) == -1
+    assert lib.bl_quality_eval(C.byref(csr), None, x.ctypes.data, 0, None, 1.0, 0, None, C.byref(q)) == -1
+    assert lib.bl_quality_eval(C.byref(csr), x.ctypes.data, x.ctypes.data, 0, None, 0.0, 0, None, C.byref(q)) == -1
+    assert lib.bl_quality_eval(C.byref(csr), x.ctypes.data, x.ctypes.data, 2, piv.ctypes.data, 1.0, 0, None,
+                               C.byref(q)) == -1
+    assert lib.bl_quality_eval(C.byref(csr), x.ctypes.data, x.ctypes.data, 2, None, 1.0, 0, None, C.byref(q)) == -1
+    assert lib.bl_quality_eval(C.byref(csr), x.ctypes.data, x.ctypes.data, 0, None, 1.0, 64, None, C.byref(q)) == -1
+    bad = inputs.Graph(5, g.rowptr.copy(), g.colidx.copy())
+    bad.colidx[2] = 9
+    csr2 = api._csr(bad, keep)
+    assert lib.bl_quality_eval(C.byref(csr2), x.ctypes.data, x.ctypes.data, 0, None, 1.0, 0, None, C.byref(q)) == -1
+    assert lib.bl_last_error()
