@@ -92,7 +92,6 @@ struct BHJob {
     gptr<double> pdd, pdd_part;
     gptr<float4> nodeA;
     gptr<int2> nodeB;
-    gptr<float2> nodeC;
     gptr<int> leafpos, nnodes;
     gptr<float4> far;
     gptr<int> late_cnt, late_ids, late_att, old_att, heavy, nheavy;
@@ -577,6 +576,13 @@ __global__ __launch_bounds__(kScanThreads) void coord_apply_kernel(BH_KERNEL_ARG
     }
 }
 
+// Bits of the bfloat16 nearest to f (round to nearest, ties to even), in the
+// low 16 bits; f is finite.
+__device__ __forceinline__ unsigned bf16_bits(float f) {
+    const unsigned u = __builtin_bit_cast(unsigned, f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
 // Nodes in DFS pre-order.  Cells starting at sorted position p come right
 // before leaf p, shallower first; a cell's subtree ends where the nodes of
 // its last position + 1 begin, which gives the skip link.
@@ -618,13 +624,14 @@ __global__ void emit_kernel(BH_KERNEL_ARGS) {
             const float side = ldexpf(W, -lvl);
             side2 = side * side;
         }
-        // the centroid as a float pair hi + lo: with hi alone its rounding
+        // the centroid as hi + lo: with hi = (float)c alone its rounding
         // (half an ulp of the coordinate) would be large next to the
-        // distance of a nearby accepted cell
+        // distance of a nearby accepted cell; lo = c - hi goes as two
+        // bfloat16 in the fourth float, the count as -count in nodeB.y
         const float hx = (float)cx, hy = (float)cy;
-        st<float4>(J.nodeA, v, float4{hx, hy, side2, (float)cnt});
-        st<int2>(J.nodeB, v, int2{skip, -1});
-        st<float2>(J.nodeC, v, float2{(float)(cx - (double)hx), (float)(cy - (double)hy)});
+        const unsigned lo = bf16_bits((float)(cx - (double)hx)) | (bf16_bits((float)(cy - (double)hy)) << 16);
+        st<float4>(J.nodeA, v, float4{hx, hy, side2, __builtin_bit_cast(float, lo)});
+        st<int2>(J.nodeB, v, int2{skip, -(int)cnt});
         ++v;
     }
     const int vert = J.val0[p];
@@ -641,7 +648,6 @@ struct WalkArgs {
     gptr<const int> total;  // node count, written by emit_kernel
     gptr<const float4> nodeA;
     gptr<const int2> nodeB;
-    gptr<const float2> nodeC;
     gptr<const int> leafpos;
     float theta2, negRK2, invK;
 };
@@ -689,12 +695,13 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
             ++v;   // the cell holds i: always opened
         } else {
             // offset to the centroid hi + lo: (hi - x_i) + lo
-            const float2 lo = ld<float2>(a.nodeC, v);
+            const unsigned lo = __builtin_bit_cast(unsigned, A.w);
+            const float lox = __builtin_bit_cast(float, lo << 16), loy = __builtin_bit_cast(float, lo & 0xffff0000u);
             ++ntest;
-            const float dx = (A.x - xi) + lo.x, dy = (A.y - yi) + lo.y;
+            const float dx = (A.x - xi) + lox, dy = (A.y - yi) + loy;
             const float d2 = dx * dx + dy * dy;
             if (A.z < a.theta2 * d2) {
-                rep_add(dx, dy, A.w, sx, cx, sy, cy);
+                rep_add(dx, dy, (float)(-B.y), sx, cx, sy, cy);
                 v = B.x;
             } else {
                 ++v;
@@ -713,7 +720,6 @@ __device__ __forceinline__ WalkArgs walk_args(const BHJob &J) {
     w.total = J.nnodes;
     w.nodeA = J.nodeA;
     w.nodeB = J.nodeB;
-    w.nodeC = J.nodeC;
     w.leafpos = J.leafpos;
     w.theta2 = J.theta2;
     w.negRK2 = J.negRK2;
@@ -1624,7 +1630,6 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->pdd_part = (decltype(J->pdd_part))(h.pdd_part);
     J->nodeA = (decltype(J->nodeA))(h.nodeA);
     J->nodeB = (decltype(J->nodeB))(h.nodeB);
-    J->nodeC = (decltype(J->nodeC))(h.nodeC);
     J->leafpos = (decltype(J->leafpos))(h.leafpos);
     J->nnodes = (decltype(J->nnodes))(h.nnodes);
     J->far = (decltype(J->far))(h.far);
@@ -1812,7 +1817,7 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
     const size_t sblocks = (N + kScanTile - 1) / kScanTile;
     const size_t nb = (N + BS - 1) / BS;
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
-           32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8 + 8) + 4 * N + 16 + 16 * N + 4 * N +
+           32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
            8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1);
 }
@@ -1836,7 +1841,6 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.pdd_part, 32 * (sblocks + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.nodeA, 16 * 2 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nodeB, 8 * 2 * N));
-    BL_TRY(graph_alloc(g, (void **)&h.nodeC, 8 * 2 * N));
     BL_TRY(graph_alloc(g, (void **)&h.leafpos, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nnodes, 16));
     BL_TRY(graph_alloc(g, (void **)&h.far, 16 * N));

@@ -75,9 +75,8 @@ struct BHBuffers {
     int *scan_part;         // scan block partials
     double *pdd;            // [4 * (n + 1)]: double-double prefix sums of sorted x, y
     double *pdd_part;       // [4 * blocks]
-    float4 *nodeA;          // [2n]: cx, cy, side^2 (inf for buckets), count
-    int2 *nodeB;            // [2n]: skip, vertex (-1 for cells)
-    float2 *nodeC;          // [2n]: cells' centroid remainders c - (float)c (the centroid is hi + lo)
+    float4 *nodeA;          // [2n]: centroid hi x, y, side^2 (inf for buckets), centroid lo x, y as two bf16
+    int2 *nodeB;            // [2n]: skip, vertex (leaves) or -count (cells)
     int *leafpos;           // [n]: pre-order index of each vertex's leaf
     int *nnodes;            // [1]
     float4 *far;            // [n]: Kahan (sx, sy, cx, cy) of the far-field sum
