@@ -29,7 +29,7 @@ METRIC = "force-updates/s (exact & BH) vs plain on 1 GPU; served p50/p99 layout 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 FLOP (FMA) x 2.4 GHz, non-packed FP32
 FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X vector FP64
-# Algorithmic work per unit (see the design notes):
+# Algorithmic work per unit (bytes a kernel must move, or FLOP it must do, per unit of work):
 BYTES_PER_VISIT = 24.0           # float4 (centroid hi, side^2, centroid lo) + int2 (skip, vertex or count) per node visit
 BYTES_PER_WALK_VERTEX = 32.0     # order id 4 + own x,y 8 + far-field sum 16 + late count 4
 BYTES_PER_LIST_WORD = 8.0        # late-list entry: row in batch << 32 | vertex (bit 31: leaf)
@@ -99,10 +99,23 @@ def describe(w, iters):
         "iterations": iters, "init": "seeded uniform [-1,1]^2 (float32-representable)"}
 
 
-def cpu_baseline(w, budget_s):
+def cpu_baseline(w, budget_s, quality_layout=None):
     """The FP64 oracle, single-threaded, on the host: as many whole iterations of
-    the same workload as fit in the budget (at least one)."""
+    the same workload as fit in the budget (at least one).  Also times, under
+    "other", the oracle's greedy initialisation of the graph and its stress
+    evaluator per BFS source (16 sources) on `quality_layout` when given."""
     import oracle
+    g0 = w["graph"]
+    other = {}
+    t0 = time.perf_counter()
+    oracle.greedy_init(g0.rowptr, g0.colidx, 0, w["x0"], w["y0"])
+    other["greedy_init_seconds"] = time.perf_counter() - t0
+    if quality_layout is not None:
+        from paper_2002_08233_amd import inputs as I
+        sp = I.rng(11).integers(0, g0.n, 16).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.stress(g0.rowptr, g0.colidx, quality_layout[0], quality_layout[1], sp)
+        other["stress_seconds_per_source"] = (time.perf_counter() - t0) / len(sp)
     g = w["graph"]
     x, y = w["x0"].copy(), w["y0"].copy()
     done = 0
@@ -119,16 +132,16 @@ def cpu_baseline(w, budget_s):
             break
     return {"value": g.n * done / el, "unit": "force-updates/s", "cores": 1, "kind": "oracle",
             "sample": "%d of %d iterations of the same workload from the same start, FP64 C oracle, "
-                      "1 thread, %.1f s" % (done, w["iterations"], el)}
+                      "1 thread, %.1f s" % (done, w["iterations"], el), "other": other}
 
 
 QUALITY_PIVOTS = 1024             # BFS pivots of the stress sample at 131072 vertices
 
 
-def quality_report(api, g, x, y, with_oracle):
+def quality_report(api, g, x, y):
     """Stress (1024 seeded pivots, or all pairs below 65536 vertices), edge
     energy and edge uniformity of the timed run's layout (Sec. 3.7), on the
-    GPU; the oracle's evaluators timed on a 16-pivot sample."""
+    GPU."""
     from paper_2002_08233_amd import inputs as I
     piv = None if g.n <= 65536 else I.rng(10).integers(0, g.n, QUALITY_PIVOTS).astype(np.int32)
     import torch
@@ -139,16 +152,10 @@ def quality_report(api, g, x, y, with_oracle):
     nsrc = g.n if piv is None else len(piv)
     rep = dict(q, seconds=sec, sources=nsrc, pairs_per_s=q["pairs"] / sec,
                note="bl_quality_eval from host arrays: upload, edge passes, 64-source BFS passes")
-    if with_oracle:
-        import oracle
-        sp = I.rng(11).integers(0, g.n, 16).astype(np.int32)
-        t0 = time.perf_counter()
-        oracle.stress(g.rowptr, g.colidx, x, y, sp)
-        rep["oracle_seconds_per_source"] = (time.perf_counter() - t0) / len(sp)
     return rep
 
 
-def greedy_report(api, w, p, steps, with_oracle, energy_random):
+def greedy_report(api, w, p, steps, energy_random):
     """The greedy initial layout (Sec. 3.6) of the workload's graph from vertex
     0, the library's host routine timed (median of 5), and the same run as the
     timed one started from it instead of the random start (its last energy
@@ -165,11 +172,6 @@ def greedy_report(api, w, p, steps, with_oracle, energy_random):
     _, _, en, _ = api.layout(g, xg, yg, p)
     rep["energy_last"] = float(en[-1]) if len(en) else None
     rep["energy_last_random_start"] = energy_random
-    if with_oracle:
-        import oracle
-        t0 = time.perf_counter()
-        oracle.greedy_init(g.rowptr, g.colidx, 0, w["x0"], w["y0"])
-        rep["oracle_seconds"] = time.perf_counter() - t0
     return rep
 
 
@@ -326,14 +328,13 @@ def main():
                              "note": "bl_layout from host arrays: CSR and coordinates uploaded, "
                                      "device state built, the run, coordinates back"}
     if not args.no_quality:
-        out["quality"] = quality_report(api, g, xf, yf, not args.no_cpu_baseline)
+        out["quality"] = quality_report(api, g, xf, yf)
     if not args.no_greedy:
-        out["greedy_init"] = greedy_report(api, w, p, steps, not args.no_cpu_baseline,
-                                           float(energy[-1]) if len(energy) else None)
+        out["greedy_init"] = greedy_report(api, w, p, steps, float(energy[-1]) if len(energy) else None)
     if args.config == "c3" and args.precision == "fp32_kahan":
         out["precision"] = precision_report(api, w, dev, x0, y0, min(steps, 20))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, None if args.no_quality else (xf, yf))
     dev.close()
     print(json.dumps(out))
     return 0
