@@ -69,6 +69,40 @@ def test_rmat17_exact_pipeline(rmat17, stop):
     print("rmat17 exact batch", stop, r)
 
 
+def test_rmat17_exact_persistent_run_equals_step_launches(rmat17, monkeypatch):
+    """The benchmark's exact configuration (131072 vertices, batch 256) runs as
+    one cooperative launch; the step-by-step launches, which the pipeline test
+    above checks against the oracle, give the same bits over 3 iterations."""
+    w, g = rmat17, rmat17["graph"]
+    p = api.params(batch_size=256, iterations=3, mode="exact")
+    xa, ya, ea, sa = api.layout(g, w["x0"], w["y0"], p)
+    monkeypatch.setenv("BL_EXACT_STEPWISE", "1")
+    xb, yb, eb, sb = api.layout(g, w["x0"], w["y0"], p)
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+    assert sa["iters_run"] == sb["iters_run"] == 3 and sa["nonfinite_events"] == 0
+
+
+def test_rmat17_barnes_hut_benchmark_run_energies(rmat17):
+    """The benchmark's Barnes-Hut configuration as timed (resident job, graph
+    replay, 16 chain segments): the first two iterations' energies against the
+    oracle's run from the same start (the first within 1e-4; the second within
+    1e-2, as a handful of close pairs with |f| ~ 1e6 dominate the sum and FP32
+    moves them slightly differently), and a repeat of the run gives the same
+    bits."""
+    w, g = rmat17, rmat17["graph"]
+    p = api.params(batch_size=256, iterations=2, mode="bh", theta=1.2)
+    with api.Graph(g, p) as h:
+        h.set_coords(w["x0"], w["y0"])
+        ea, _ = h.run(2)
+        xa, ya = h.get_coords()
+        h.set_coords(w["x0"], w["y0"])
+        eb, _ = h.run(2)
+        xb, yb = h.get_coords()
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+    _, _, eo, _ = oracle.layout_bh(g.rowptr, g.colidx, w["x0"], w["y0"], 256, 2, theta=1.2)
+    assert abs(ea[0] / eo[0] - 1) < 1e-4 and abs(ea[1] / eo[1] - 1) < 1e-2, (ea, eo)
+
+
 @pytest.mark.parametrize("precision", ["fp32_kahan", "fp32", "fp64"])
 def test_rgg64k_precision_stress(rgg64k, precision):
     """65536-vertex random geometric graph, batch 512, three precisions: the
