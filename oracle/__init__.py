@@ -48,6 +48,12 @@ def _load():
     lib.orc_forces_exact.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int,
                                      C.c_double, C.c_double, C.c_int,
                                      _f64p, _f64p, _f64p, _f64p, _f64p]
+    lib.orc_forces_exact_ar.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int,
+                                        C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                        _f64p, _f64p, _f64p, _f64p, _f64p]
+    lib.orc_layout_exact_ar.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
+                                        C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                        C.c_int, C.c_int, C.c_int, _f64p]
     lib.orc_step_at.argtypes = [C.c_double, C.c_double, C.c_int]
     lib.orc_step_at.restype = C.c_double
     lib.orc_layout_exact.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
@@ -111,14 +117,18 @@ def step_at(step0: float, decay: float, k: int) -> float:
     return _load().orc_step_at(step0, decay, k)
 
 
-def forces_exact(rowptr, colidx, x, y, i0, i1, K=1.0, R=1.0, repulse_adjacent=True) -> Forces:
-    """Exact net forces on vertices [i0, i1) from coordinates (x, y) (Sec. 2.2; Alg. 2)."""
+def forces_exact(rowptr, colidx, x, y, i0, i1, K=1.0, R=1.0, repulse_adjacent=True, model=(2, -1)) -> Forces:
+    """Exact net forces on vertices [i0, i1) from coordinates (x, y) (Sec. 2.2; Alg. 2).
+
+    model = (a, r): attraction magnitude d^a / K, repulsion magnitude R K^2 d^r
+    (integers; (2, -1) is Fruchterman-Reingold)."""
     lib = _load()
     rp, ci = _csr(rowptr, colidx)
     n = len(rp) - 1
     m = i1 - i0
     out = [np.zeros(max(m, 1)) for _ in range(5)]
-    rc = lib.orc_forces_exact(n, rp, ci, _f64(x), _f64(y), i0, i1, K, R, int(repulse_adjacent), *out)
+    rc = lib.orc_forces_exact_ar(n, rp, ci, _f64(x), _f64(y), i0, i1, K, R, int(repulse_adjacent),
+                                 int(model[0]), int(model[1]), *out)
     if rc != 0:
         raise ValueError("orc_forces_exact: bad arguments")
     return Forces(*[o[:m] for o in out])
@@ -132,15 +142,16 @@ def _converged(e, conv_tol):
 
 
 def layout_exact(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=0.999,
-                 K=1.0, R=1.0, repulse_adjacent=True, stop_batch=-1, conv_tol=0.0):
-    """Exact BatchLayout (Alg. 2 semantics).  Returns (x, y, energy per iteration);
-    with conv_tol > 0 the run ends where the energy stopping rule holds."""
+                 K=1.0, R=1.0, repulse_adjacent=True, stop_batch=-1, conv_tol=0.0, model=(2, -1)):
+    """Exact BatchLayout (Alg. 2 semantics) with the (a, r) model of Sec. 2.2.
+    Returns (x, y, energy per iteration); with conv_tol > 0 the run ends where
+    the energy stopping rule holds."""
     if conv_tol > 0:
         assert stop_batch < 0
         x, y, es = x0, y0, []
         for t in range(iters):
             x, y, e = layout_exact(rowptr, colidx, x, y, bs, 1, start_iter + t, step0, decay, K, R,
-                                   repulse_adjacent)
+                                   repulse_adjacent, model=model)
             es.append(e[0])
             if _converged(es, conv_tol):
                 break
@@ -151,8 +162,8 @@ def layout_exact(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, dec
     x = _f64(x0).copy()
     y = _f64(y0).copy()
     e = np.zeros(max(iters, 1))
-    rc = lib.orc_layout_exact(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R,
-                              int(repulse_adjacent), stop_batch, e)
+    rc = lib.orc_layout_exact_ar(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R,
+                                 int(repulse_adjacent), int(model[0]), int(model[1]), stop_batch, e)
     if rc != 0:
         raise ValueError("orc_layout_exact failed (%d)" % rc)
     return x, y, e[:iters]

@@ -42,24 +42,51 @@
 #define ORC_LEVELS 16
 
 /* ---------------------------------------------------------------- pair terms
- * Attraction term on i from neighbour j (Sec. 2.2, a = 2):
- *   f_a(i,j) * (c_j - c_i)/d = (d^2/K) * delta/d = d * delta / K. */
-static void pair_attraction(double dx, double dy, double K, double *tx, double *ty)
+ * The (a,r)-energy model of Sec. 2.2: attraction magnitude d^a / K and
+ * repulsion magnitude R K^2 d^r (the exponent r read as the power of d in the
+ * force, so that (2,-1) is Fruchterman-Reingold), each along the unit vector
+ * (c_j - c_i)/d, the repulsion with a negative sign.  A pair with d == 0
+ * contributes 0.  (2,-1) is written out on its own. */
+
+/* Attraction term on i from neighbour j:
+ *   a = 2:   (d^2/K) * delta/d = d * delta / K;
+ *   general: (d^a/K) * delta/d. */
+static void pair_attraction_ar(double dx, double dy, double K, int a, double *tx, double *ty)
 {
     double d = sqrt(dx * dx + dy * dy);
-    *tx = d * dx / K;
-    *ty = d * dy / K;
+    if (a == 2) {
+        *tx = d * dx / K;
+        *ty = d * dy / K;
+        return;
+    }
+    if (d == 0.0) { *tx = 0.0; *ty = 0.0; return; }
+    double f = pow(d, (double)a) / K;
+    *tx = f * dx / d;
+    *ty = f * dy / d;
 }
 
-/* Repulsion term on i from j (Sec. 2.2, r = -1 read as force ~ 1/d):
- *   f_r(i,j) * (c_j - c_i)/d = (-R K^2 / d) * delta/d = -R K^2 delta / d^2. */
-static void pair_repulsion(double dx, double dy, double K, double R, double *tx, double *ty)
+/* Repulsion term on i from j:
+ *   r = -1:  (-R K^2 / d) * delta/d = -R K^2 delta / d^2;
+ *   general: (-R K^2 d^r) * delta/d. */
+static void pair_repulsion_ar(double dx, double dy, double K, double R, int r, double *tx, double *ty)
 {
     double d2 = dx * dx + dy * dy;
     if (d2 == 0.0) { *tx = 0.0; *ty = 0.0; return; }
-    double c = -R * K * K / d2;
-    *tx = c * dx;
-    *ty = c * dy;
+    if (r == -1) {
+        double c = -R * K * K / d2;
+        *tx = c * dx;
+        *ty = c * dy;
+        return;
+    }
+    double d = sqrt(d2);
+    double f = -R * K * K * pow(d, (double)r);
+    *tx = f * dx / d;
+    *ty = f * dy / d;
+}
+
+static void pair_repulsion(double dx, double dy, double K, double R, double *tx, double *ty)
+{
+    pair_repulsion_ar(dx, dy, K, R, -1, tx, ty);
 }
 
 /* ------------------------------------------------------------- exact forces
@@ -69,7 +96,7 @@ static void pair_repulsion(double dx, double dy, double K, double R, double *tx,
  * S_i = sum of |term| over all terms. */
 static void force_exact_one(int n, const int *rowptr, const int *colidx,
                             const double *x, const double *y, int i,
-                            double K, double R, int repulse_adjacent,
+                            double K, double R, int repulse_adjacent, int a, int r,
                             double *ax, double *ay, double *rx, double *ry, double *scale)
 {
     double sax = 0, say = 0, srx = 0, sry = 0, s = 0;
@@ -81,14 +108,14 @@ static void force_exact_one(int n, const int *rowptr, const int *colidx,
         if (k < kend && colidx[k] == j) adjacent = 1;
         if (adjacent) {
             double tx, ty;
-            pair_attraction(dx, dy, K, &tx, &ty);
+            pair_attraction_ar(dx, dy, K, a, &tx, &ty);
             sax += tx; say += ty;
             s += sqrt(tx * tx + ty * ty);
         }
         if (j == i) continue;
         if (adjacent && !repulse_adjacent) continue;
         double tx, ty;
-        pair_repulsion(dx, dy, K, R, &tx, &ty);
+        pair_repulsion_ar(dx, dy, K, R, r, &tx, &ty);
         srx += tx; sry += ty;
         s += sqrt(tx * tx + ty * ty);
     }
@@ -96,17 +123,26 @@ static void force_exact_one(int n, const int *rowptr, const int *colidx,
     if (scale) *scale = s;
 }
 
+int orc_forces_exact_ar(int n, const int *rowptr, const int *colidx,
+                        const double *x, const double *y, int i0, int i1,
+                        double K, double R, int repulse_adjacent, int a, int r,
+                        double *ax, double *ay, double *rx, double *ry, double *scale)
+{
+    if (n < 1 || i0 < 0 || i1 > n || i0 > i1) return -1;
+    for (int i = i0; i < i1; ++i)
+        force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent, a, r,
+                        &ax[i - i0], &ay[i - i0], &rx[i - i0], &ry[i - i0],
+                        scale ? &scale[i - i0] : NULL);
+    return 0;
+}
+
 int orc_forces_exact(int n, const int *rowptr, const int *colidx,
                      const double *x, const double *y, int i0, int i1,
                      double K, double R, int repulse_adjacent,
                      double *ax, double *ay, double *rx, double *ry, double *scale)
 {
-    if (n < 1 || i0 < 0 || i1 > n || i0 > i1) return -1;
-    for (int i = i0; i < i1; ++i)
-        force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent,
-                        &ax[i - i0], &ay[i - i0], &rx[i - i0], &ry[i - i0],
-                        scale ? &scale[i - i0] : NULL);
-    return 0;
+    return orc_forces_exact_ar(n, rowptr, colidx, x, y, i0, i1, K, R, repulse_adjacent, 2, -1,
+                               ax, ay, rx, ry, scale);
 }
 
 /* Move the vertices of one batch along their normalised net forces
@@ -140,10 +176,10 @@ double orc_step_at(double step0, double decay, int k)
  * Runs iterations [start_iter, start_iter + iters).  When stop_batch >= 0 the
  * last iteration stops after that many batches (used to dump a mid-iteration
  * state).  energy[t] receives the energy of iteration start_iter + t. */
-int orc_layout_exact(int n, const int *rowptr, const int *colidx,
-                     double *x, double *y, int bs, int iters, int start_iter,
-                     double step0, double decay, double K, double R,
-                     int repulse_adjacent, int stop_batch, double *energy)
+int orc_layout_exact_ar(int n, const int *rowptr, const int *colidx,
+                        double *x, double *y, int bs, int iters, int start_iter,
+                        double step0, double decay, double K, double R,
+                        int repulse_adjacent, int a, int r, int stop_batch, double *energy)
 {
     if (n < 1 || bs < 1 || iters < 0) return -1;
     int nb = (n + bs - 1) / bs;
@@ -158,7 +194,7 @@ int orc_layout_exact(int n, const int *rowptr, const int *colidx,
             int i0 = b * bs, i1 = i0 + bs < n ? i0 + bs : n;
             for (int i = i0; i < i1; ++i) {
                 double rx, ry;
-                force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent,
+                force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent, a, r,
                                 &ax[i - i0], &ay[i - i0], &rx, &ry, NULL);
                 fx[i - i0] = ax[i - i0] + rx;
                 fy[i - i0] = ay[i - i0] + ry;
@@ -169,6 +205,15 @@ int orc_layout_exact(int n, const int *rowptr, const int *colidx,
     }
     free(fx); free(fy); free(ax); free(ay);
     return 0;
+}
+
+int orc_layout_exact(int n, const int *rowptr, const int *colidx,
+                     double *x, double *y, int bs, int iters, int start_iter,
+                     double step0, double decay, double K, double R,
+                     int repulse_adjacent, int stop_batch, double *energy)
+{
+    return orc_layout_exact_ar(n, rowptr, colidx, x, y, bs, iters, start_iter, step0, decay, K, R,
+                               repulse_adjacent, 2, -1, stop_batch, energy);
 }
 
 /* ------------------------------------------------------------- Barnes-Hut */
@@ -440,7 +485,7 @@ int orc_forces_bh(int n, const int *rowptr, const int *colidx,
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
             int j = colidx[k];
             double tx, ty;
-            pair_attraction(x[j] - x[i], y[j] - y[i], K, &tx, &ty);
+            pair_attraction_ar(x[j] - x[i], y[j] - y[i], K, 2, &tx, &ty);
             sax += tx; say += ty;
             s += sqrt(tx * tx + ty * ty);
         }

@@ -688,3 +688,108 @@ def test_greedy_tree_invariants_and_components():
             u = par[u]
             seen += 1
             assert seen <= n
+
+
+# ------------------------------------------------------ (a, r) energy models
+
+AR_MODELS = [(1, -1), (0, -1), (3, -1), (2, -2), (1, -2), (3, 0)]
+
+
+@pytest.mark.parametrize("a,r", AR_MODELS)
+def test_ar_two_vertex_closed_form(a, r):
+    """Sec. 2.2 with general (a, r): on two vertices the force on vertex 0 is
+    (d^a/K - R K^2 d^r) along the unit vector toward vertex 1, zero at
+    d* = (R K^3)^(1/(a - r))."""
+    g = I.path(2)
+    K, R = 0.7, 1.6
+    dstar = (R * K ** 3) ** (1.0 / (a - r))
+    for d, ang in [(0.37, 0.3), (2.2, -1.1), (dstar, 2.5)]:
+        x = np.array([-0.25, -0.25 + d * math.cos(ang)])
+        y = np.array([0.5, 0.5 + d * math.sin(ang)])
+        f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 2, K=K, R=R, model=(a, r))
+        u = np.array([math.cos(ang), math.sin(ang)])
+        mag = d ** a / K - R * K * K * d ** r
+        tol = 1e-12 * (d ** a / K + R * K * K * d ** r)
+        assert f.fx[0] == pytest.approx(mag * u[0], abs=tol) and f.fy[0] == pytest.approx(mag * u[1], abs=tol)
+        assert f.fx[1] == pytest.approx(-mag * u[0], abs=tol) and f.fy[1] == pytest.approx(-mag * u[1], abs=tol)
+        assert np.hypot(f.ax[0], f.ay[0]) == pytest.approx(d ** a / K, rel=1e-12)
+        assert np.hypot(f.rx[0], f.ry[0]) == pytest.approx(R * K * K * d ** r, rel=1e-12)
+    # the attraction points toward the neighbour, the repulsion away from it
+    assert f.ax[0] * u[0] + f.ay[0] * u[1] > 0 and f.rx[0] * u[0] + f.ry[0] * u[1] < 0
+
+
+@pytest.mark.parametrize("a,r", AR_MODELS)
+def test_ar_newton_third_law(a, r):
+    """At BS = n every pair term appears with both signs: the attraction and
+    the repulsion each sum to zero over all vertices."""
+    g = random_graph(60, 0.1, 71)
+    x, y = I.uniform_coords(60, 72)
+    f = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 60, model=(a, r))
+    s = f.scale.sum()
+    assert abs(f.ax.sum()) < 1e-12 * s and abs(f.ay.sum()) < 1e-12 * s
+    assert abs(f.rx.sum()) < 1e-12 * s and abs(f.ry.sum()) < 1e-12 * s
+
+
+@pytest.mark.parametrize("a,r", AR_MODELS)
+def test_ar_scaling_law_and_literal_identity(a, r):
+    """c -> 2c scales the attraction by 2^a and the repulsion by 2^r; literal
+    mode is the default force minus the neighbours' repulsion terms."""
+    g = random_graph(40, 0.15, 73)
+    x, y = dyadic_coords(40, 74)
+    f1 = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 40, model=(a, r))
+    f2 = oracle.forces_exact(g.rowptr, g.colidx, 2 * x, 2 * y, 0, 40, model=(a, r))
+    np.testing.assert_allclose(f2.ax, 2.0 ** a * f1.ax, rtol=1e-13, atol=1e-13 * 2.0 ** a * f1.scale.max())
+    np.testing.assert_allclose(f2.rx, 2.0 ** r * f1.rx, rtol=1e-13, atol=1e-13 * 2.0 ** r * f1.scale.max())
+    lit = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 40, repulse_adjacent=False, model=(a, r))
+    for i in range(40):
+        cx = cy = 0.0
+        for j in g.colidx[g.rowptr[i]:g.rowptr[i + 1]]:
+            dx, dy = x[j] - x[i], y[j] - y[i]
+            d = math.hypot(dx, dy)
+            cx += -(d ** r) * dx / d
+            cy += -(d ** r) * dy / d
+        assert lit.rx[i] == pytest.approx(f1.rx[i] - cx, abs=1e-12 * f1.scale[i])
+        assert lit.ry[i] == pytest.approx(f1.ry[i] - cy, abs=1e-12 * f1.scale[i])
+
+
+@pytest.mark.parametrize("a,r", [(1, -1), (0, -2), (3, 0)])
+def test_ar_mpmath_bruteforce(a, r):
+    """Forces and one iteration under (a, r) against 50-digit arithmetic."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    n, bs = 11, 4
+    g = random_graph(n, 0.35, 75)
+    x0, y0 = I.uniform_coords(n, 76)
+    K, R = 1.3, 0.6
+    nbs = [set(g.colidx[g.rowptr[i]:g.rowptr[i + 1]].tolist()) for i in range(n)]
+
+    def forces(X, Y, i):
+        fx = fy = mp.mpf(0)
+        for j in range(n):
+            if j == i:
+                continue
+            dx, dy = X[j] - X[i], Y[j] - Y[i]
+            d = mp.sqrt(dx * dx + dy * dy)
+            m = -R * K * K * d ** r + (d ** a / K if j in nbs[i] else 0)
+            fx += m * dx / d
+            fy += m * dy / d
+        return fx, fy
+
+    X = [mp.mpf(v) for v in x0]
+    Y = [mp.mpf(v) for v in y0]
+    f = oracle.forces_exact(g.rowptr, g.colidx, x0, y0, 0, n, K=K, R=R, model=(a, r))
+    for i in range(n):
+        fx, fy = forces(X, Y, i)
+        assert abs(f.fx[i] - float(fx)) <= 1e-13 * f.scale[i]
+        assert abs(f.fy[i] - float(fy)) <= 1e-13 * f.scale[i]
+    # one iteration of the minibatch schedule, step 1
+    for b0 in range(0, n, bs):
+        batch = list(range(b0, min(b0 + bs, n)))
+        fs = [forces(X, Y, i) for i in batch]
+        for i, (fx, fy) in zip(batch, fs):
+            nrm = mp.sqrt(fx * fx + fy * fy)
+            X[i] += fx / nrm
+            Y[i] += fy / nrm
+    x1, y1, e = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, bs, 1, K=K, R=R, model=(a, r))
+    for i in range(n):
+        assert x1[i] == pytest.approx(float(X[i]), abs=1e-12) and y1[i] == pytest.approx(float(Y[i]), abs=1e-12)
