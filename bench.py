@@ -38,6 +38,18 @@ BYTES_PER_CHAIN_ROW = 56.0       # list offset 4 + leaf count 4 + x,y 8 + far su
                                  # + old sum 8 + x,y write 8 (recent gathers come from the LDS window)
 BYTES_PER_OLD_ROW = 20.0         # list offset 4 + x,y 8 + old sum write 8
 FLOP_PER_PAIR = 10.0             # 2 sub, d^2 (2 mul + 1 add), 1 reciprocal, 2 FMA
+
+
+def flop_per_pair(model):
+    """Repulsion FLOP per pair under the (a, r) model: 2 sub, d^2 (3), the
+    power d^(r-1) from d^2, 2 FMA (4).  r = -1 (any a) takes one reciprocal;
+    other r |h| multiplications by d^2 (h = floor((r-1)/2)), a reciprocal
+    when h < 0, and a square root and a multiplication when r - 1 is odd."""
+    if model[1] == -1:
+        return FLOP_PER_PAIR
+    k = model[1] - 1
+    h = k >> 1
+    return 9.0 + abs(h) + (1.0 if h < 0 else 0.0) + (2.0 if k & 1 else 0.0)
 # HBM bytes per launch of a workload's dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (FETCH_SIZE scaled by 2.0, the factor a plain copy of known size shows; WRITE_SIZE by 1.0).
 # Valid only while the kernel's source file is the one the counters were taken on.
@@ -193,6 +205,7 @@ def main():
     ap.add_argument("--no-greedy", action="store_true", help="skip the greedy-initialisation report")
     ap.add_argument("--no-quality", action="store_true", help="skip the layout-quality report")
     ap.add_argument("--precision", default="fp32_kahan")
+    ap.add_argument("--model", default="2,-1", help="exact mode: the (a, r) energy model, e.g. 1,-1")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -224,9 +237,10 @@ def main():
         return bench_served(args, api, reqs)
     w = workload(args.config)
     g = w["graph"]
+    model = tuple(int(v) for v in args.model.split(","))
     steps = args.steps if args.steps is not None else w["iterations"]
     p = api.params(batch_size=w["batch_size"], iterations=steps, mode=w["mode"],
-                   theta=w["theta"] if w["mode"] == "bh" else 1.2, precision=args.precision)
+                   theta=w["theta"] if w["mode"] == "bh" else 1.2, precision=args.precision, model=model)
 
     # inputs resident on the device before the timed region
     dev = api.Graph(g, p)
@@ -248,7 +262,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": 1e3 * wall / max(steps, 1), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
-           "config": describe(w, steps)}
+           "config": dict(describe(w, steps), model=list(model))}
 
     if not args.no_profile:
         # per-kernel hipEvent timing in a separate run from the same start (its
@@ -295,15 +309,15 @@ def main():
             if "steps_kernel" in kern:   # the run's steps as one persistent launch
                 dom_name = "steps_kernel"
                 dom = kern[dom_name]
-                flop_per_launch = FLOP_PER_PAIR * persistent_pairs(g.n, w["batch_size"], psteps) / dom["launches"]
+                flop_per_launch = flop_per_pair(model) * persistent_pairs(g.n, w["batch_size"], psteps) / dom["launches"]
             elif "step_kernel" in kern:
                 dom_name = "step_kernel"
                 dom = kern[dom_name]
-                flop_per_launch = FLOP_PER_PAIR * float(g.n) * w["batch_size"]
+                flop_per_launch = flop_per_pair(model) * float(g.n) * w["batch_size"]
             else:   # small graph: the whole run is one launch of the one-workgroup kernel
                 dom_name = "exact_graph_kernel"
                 dom = kern[dom_name]
-                flop_per_launch = FLOP_PER_PAIR * float(g.n) * g.n * psteps / dom["launches"]
+                flop_per_launch = flop_per_pair(model) * float(g.n) * g.n * psteps / dom["launches"]
             dom["achieved_TFLOPs"] = flop_per_launch / (dom["avg_us"] * 1e-6) / 1e12
             dom["flop_per_launch"] = flop_per_launch
             peak = FP32_VALU_PEAK_TFLOPS if args.precision != "fp64" else FP64_VALU_PEAK_TFLOPS

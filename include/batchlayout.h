@@ -99,7 +99,15 @@ typedef struct {
                                 layout is the one after iteration k and
                                 stats.iters_run counts the iterations done.
                                 Not with a stop batch, nor in the server.       */
-    int32_t reserved[4];     /* must be zero                                     */
+    int32_t model_a;         /* the (a, r)-energy model of Sec. 2.2: attraction   */
+    int32_t model_r;         /* magnitude d^a / K, repulsion magnitude R K^2 d^r
+                                (r read as the power of d in the force, so the
+                                default (2, -1) is Fruchterman-Reingold).
+                                Integers, -8 <= r < a <= 8.  Other models than
+                                (2, -1) run in exact mode through bl_layout,
+                                bl_forces and bl_graph_* only; Barnes-Hut,
+                                bl_layout_batch and the server reject them.     */
+    int32_t reserved[2];     /* must be zero                                     */
 } bl_params;
 
 typedef struct {

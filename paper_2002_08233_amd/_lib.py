@@ -45,7 +45,8 @@ class Params(C.Structure):
                 ("mode", C.c_int32), ("precision", C.c_int32), ("repulse_adjacent", C.c_int32),
                 ("step0", C.c_double), ("step_decay", C.c_double), ("K", C.c_double),
                 ("R", C.c_double), ("theta", C.c_double), ("flags", C.c_uint32),
-                ("reserved0", C.c_int32), ("conv_tol", C.c_double), ("reserved", C.c_int32 * 4)]
+                ("reserved0", C.c_int32), ("conv_tol", C.c_double), ("model_a", C.c_int32),
+                ("model_r", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Stats(C.Structure):

@@ -20,7 +20,7 @@ MODES = {"exact": BL_EXACT, "bh": BL_BH}
 
 def params(batch_size=256, iterations=600, start_iter=0, mode="exact", precision="fp32_kahan",
            repulse_adjacent=True, step0=1.0, step_decay=0.999, K=1.0, R=1.0, theta=1.2,
-           validate=False, snapshot_leaves=False, multi_wg=False, conv_tol=0.0) -> Params:
+           validate=False, snapshot_leaves=False, multi_wg=False, conv_tol=0.0, model=(2, -1)) -> Params:
     p = Params()
     check(load().bl_params_init(C.byref(p)))
     p.batch_size = int(batch_size)
@@ -31,6 +31,7 @@ def params(batch_size=256, iterations=600, start_iter=0, mode="exact", precision
     p.repulse_adjacent = 1 if repulse_adjacent else 0
     p.step0, p.step_decay, p.K, p.R, p.theta = step0, step_decay, K, R, theta
     p.conv_tol = conv_tol
+    p.model_a, p.model_r = int(model[0]), int(model[1])
     p.flags = ((BL_VALIDATE if validate else 0) | (BL_BH_SNAPSHOT_LEAVES if snapshot_leaves else 0) |
                (BL_EXACT_MULTI_WG if multi_wg else 0))
     return p

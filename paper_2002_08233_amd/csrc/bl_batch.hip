@@ -120,6 +120,8 @@ extern "C" int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const dou
         if (params[q]->flags & BL_DEVICE_PTRS)
             return fail_code(BL_E_INVAL, "bl_layout_batch takes host arrays only");
         BL_TRY(params_check(params[q]));
+        if (model_general(*params[q]))
+            return fail_code(BL_E_INVAL, "bl_layout_batch runs the (2, -1) model only");
     }
     BatchState B;
     BL_HIP(hipStreamCreate(&B.s_ex));

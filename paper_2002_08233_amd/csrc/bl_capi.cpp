@@ -72,8 +72,12 @@ int check_params(const bl_params *p) {
         return fail(BL_E_INVAL, "unknown flags 0x%x", p->flags);
     if (!(p->conv_tol >= 0) || !std::isfinite(p->conv_tol)) return fail(BL_E_INVAL, "conv_tol must be >= 0");
     if (p->reserved0) return fail(BL_E_INVAL, "reserved fields must be zero");
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 2; ++q)
         if (p->reserved[q]) return fail(BL_E_INVAL, "reserved fields must be zero");
+    if (!(p->model_r < p->model_a) || p->model_r < -8 || p->model_a > 8)
+        return fail(BL_E_INVAL, "the (a, r) model needs integers -8 <= r < a <= 8");
+    if (p->mode == BL_BH && model_general(*p))
+        return fail(BL_E_INVAL, "Barnes-Hut mode runs the (2, -1) model only");
     return BL_OK;
 }
 
@@ -180,6 +184,8 @@ int bl_params_init(bl_params *p) {
     p->K = 1.0;
     p->R = 1.0;
     p->theta = 1.2;
+    p->model_a = 2;
+    p->model_r = -1;
     p->flags = 0;
     return BL_OK;
 }

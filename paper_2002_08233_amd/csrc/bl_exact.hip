@@ -117,6 +117,64 @@ struct EntryTerms {
     }
 };
 
+// The (a, r) model of Sec. 2.2 for integer exponents: |c_j - c_i|^k with
+// k = a - 1 (attraction) or r - 1 (repulsion kernel), from d^2 by k/2
+// multiplications (or their reciprocal: the hardware one in FP32, as in the
+// (2, -1) terms) and one square root for odd k; 0 for a coincident pair.  k
+// is uniform across the launch.
+template <typename T>
+__device__ __forceinline__ T dpow(T dx, T dy, int k) {
+    const T d2 = fma(dx, dx, dy * dy);
+    if (d2 == (T)0) return (T)0;
+    const int h = k >> 1;   // floor(k / 2)
+    const int m = h < 0 ? -h : h;
+    T p = 1;
+    for (int q = 0; q < m; ++q) p *= d2;
+    if (h < 0) {
+        if constexpr (sizeof(T) == 4) p = __builtin_amdgcn_rcpf(p);
+        else p = 1.0 / p;
+    }
+    if (k & 1) p *= sqrt(d2);
+    return p;
+}
+
+// Pair terms for model M: 0 = (2, -1) (Fruchterman-Reingold, the paths above
+// unchanged), 1 = the general integer (a, r) of the view, 2 = general a with
+// r = -1 (the repulsion of the (2, -1) paths, e.g. (1, -1) and (0, -1)).
+template <int M, typename T, typename T2>
+__device__ __forceinline__ void rep_pair(int kr, T xi, T yi, T2 pj, T &px, T &py) {
+    if constexpr (M != 1) {
+        rep_term(xi, yi, pj, px, py);
+    } else {
+        const T dx = pj.x - xi, dy = pj.y - yi;
+        const T f = dpow(dx, dy, kr);
+        px = fma(dx, f, px);
+        py = fma(dy, f, py);
+    }
+}
+template <int M, typename T, typename T2>
+__device__ __forceinline__ void ent_att(int ka, T xi, T yi, T2 pj, T &tx, T &ty) {
+    if constexpr (M == 0) {
+        EntryTerms::att(xi, yi, pj, tx, ty);
+    } else {
+        const T dx = pj.x - xi, dy = pj.y - yi;
+        const T f = dpow(dx, dy, ka);
+        tx = f * dx;
+        ty = f * dy;
+    }
+}
+template <int M, typename T, typename T2>
+__device__ __forceinline__ void ent_rep(int kr, T xi, T yi, T2 pj, T &ux, T &uy) {
+    if constexpr (M != 1) {
+        EntryTerms::rep(xi, yi, pj, ux, uy);
+    } else {
+        const T dx = pj.x - xi, dy = pj.y - yi;
+        const T f = dpow(dx, dy, kr);
+        ux = dx * f;
+        uy = dy * f;
+    }
+}
+
 // Four interleaved repulsion partials of one row.
 template <typename T>
 struct Rep4 {
@@ -157,6 +215,7 @@ template <typename T>
 struct GView {
     using T2 = typename V2<T>::type;
     int n, BS, nb, literal;
+    int ka, kr;   // (a, r) model: the terms are d^(a-1) and d^(r-1) times (c_j - c_i)
     T invK, negRK2;
     const int *rowptr, *colidx;
     const int2 *segs;
@@ -318,7 +377,7 @@ __device__ __forceinline__ T ld_agent(const T *p) {
 
 // COH: the column batch was moved by another workgroup of the same launch
 // (persistent run), so its coordinates are read with agent-scope loads.
-template <typename T, int L, bool COH = false>
+template <typename T, int L, bool COH = false, int M = 0>
 __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool active, bool lead, int i, T xi, T yi,
                                                int s, int send, typename V2<T>::type *cols, T &qx, T &qy,
                                                bool &used) {
@@ -349,13 +408,13 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
         int k = k0;
         for (; k + 2 <= k1; k += 2) {
 #pragma unroll
-            for (int t = 0; t < A; ++t) rep_term(xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
+            for (int t = 0; t < A; ++t) rep_pair<M>(G.kr, xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
 #pragma unroll
-            for (int t = 0; t < A; ++t) rep_term(xi, yi, cols[4 * k + 4 + h + L * t], px[t], py[t]);
+            for (int t = 0; t < A; ++t) rep_pair<M>(G.kr, xi, yi, cols[4 * k + 4 + h + L * t], px[t], py[t]);
         }
         if (k < k1) {
 #pragma unroll
-            for (int t = 0; t < A; ++t) rep_term(xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
+            for (int t = 0; t < A; ++t) rep_pair<M>(G.kr, xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
         }
     };
     for (int t0 = c0; t0 < c1; t0 += kTile) {
@@ -394,7 +453,7 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
 #pragma unroll
             for (int t = 0; t < A; ++t) {
                 const int q = 4 * groups + h + L * t;
-                if (q < m) rep_term(xi, yi, cols[q], px[t], py[t]);
+                if (q < m) rep_pair<M>(G.kr, xi, yi, cols[q], px[t], py[t]);
             }
         }
     }
@@ -430,11 +489,11 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
         if (lead && u < cnt) {
             T tx, ty;
             const T2 pj = pos(j);
-            EntryTerms::att(xi, yi, pj, tx, ty);
+            ent_att<M>(G.ka, xi, yi, pj, tx, ty);
             ax += tx;
             ay += ty;
             if (G.literal) {
-                EntryTerms::rep(xi, yi, pj, tx, ty);
+                ent_rep<M>(G.kr, xi, yi, pj, tx, ty);
                 lx += tx;
                 ly += ty;
             }
@@ -469,8 +528,8 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
                 const int e = e0 + lane;
                 const T2 pj = pos(e < ct ? jj[k] : c0);
                 T tx, ty, ux = 0, uy = 0;
-                EntryTerms::att(rxi, ryi, pj, tx, ty);
-                if (G.literal) EntryTerms::rep(rxi, ryi, pj, ux, uy);
+                ent_att<M>(G.ka, rxi, ryi, pj, tx, ty);
+                if (G.literal) ent_rep<M>(G.kr, rxi, ryi, pj, ux, uy);
                 const int mcount = min(kWave, ct - e0);
                 lt[lane] = T2{tx, ty};
                 if (G.literal) lu[lane] = T2{ux, uy};
@@ -499,7 +558,7 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
 
 // rows_block with L lanes per row (workgroups of kRows * L; rows
 // [first, first + kRows)).
-template <typename T, bool KAHAN, int L>
+template <typename T, bool KAHAN, int L, int M = 0>
 __device__ __forceinline__ void rows_blockL(const GView<T> &G, int first, int row1, int from_own, int p, int clear_other,
                                             typename V2<T>::type *cols) {
     using T2 = typename V2<T>::type;
@@ -523,7 +582,7 @@ __device__ __forceinline__ void rows_blockL(const GView<T> &G, int first, int ro
         const bool use = in && (!from_own || bb >= bi);
         T qx, qy;
         bool used;
-        batch_contribL<T, L>(G, bb, use, lead, i, xi, yi, s, send, cols, qx, qy, used);
+        batch_contribL<T, L, false, M>(G, bb, use, lead, i, xi, yi, s, send, cols, qx, qy, used);
         if (use) {
             if (lead) acc_add<T, KAHAN>(acc, cc, qx, qy);
             if (used) ++s;
@@ -540,11 +599,11 @@ __device__ __forceinline__ void rows_blockL(const GView<T> &G, int first, int ro
     }
 }
 
-template <typename T, bool KAHAN, int L>
+template <typename T, bool KAHAN, int L, int M>
 __global__ __launch_bounds__(kRows * L) void rows_kernel(GView<T> G, int row0, int row1, int from_own, int p,
                                                          int clear_other) {
     __shared__ typename V2<T>::type cols[kTile];
-    rows_blockL<T, KAHAN, L>(G, row0 + blockIdx.x * kRows, row1, from_own, p, clear_other, cols);
+    rows_blockL<T, KAHAN, L, M>(G, row0 + blockIdx.x * kRows, row1, from_own, p, clear_other, cols);
 }
 
 // The panel of column batch c for the rows [first, first + blockDim): rows of
@@ -596,7 +655,7 @@ __device__ __forceinline__ void panel_rows(const GView<T> &G, int first, int c, 
 // panel_rows with L lanes per row (workgroups of kRows * L, rows [first,
 // first + kRows)); the completed sum of a row of batch `fin` lands in the
 // lead lane's (fx, fy).
-template <typename T, bool KAHAN, int L, bool COH = false>
+template <typename T, bool KAHAN, int L, bool COH = false, int M = 0>
 __device__ __forceinline__ void panel_rowsL(const GView<T> &G, int first, int c, int pc, int do_next, int fin,
                                             typename V2<T>::type *cols, T &xi, T &yi, T &fx, T &fy) {
     using T2 = typename V2<T>::type;
@@ -622,7 +681,7 @@ __device__ __forceinline__ void panel_rowsL(const GView<T> &G, int first, int c,
     }
     T qx, qy;
     bool used;
-    batch_contribL<T, L, COH>(G, c, act, lead, i, xi, yi, s, send, cols, qx, qy, used);
+    batch_contribL<T, L, COH, M>(G, c, act, lead, i, xi, yi, s, send, cols, qx, qy, used);
     if (act && lead) {
         acc_add<T, KAHAN>(acc, cc, qx, qy);
         if (bi == fin) {
@@ -832,7 +891,7 @@ __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T
 // Panel of column batch c (moved in an iteration of parity pc) over all rows,
 // fused with the finish of batch fa.fin (whose last contribution is this
 // panel's).  Needs nb > 1: the finished rows are read by no other workgroup.
-template <typename T, bool KAHAN, int L>
+template <typename T, bool KAHAN, int L, int M>
 __global__ __launch_bounds__(kRows * L) void step_kernel(GView<T> G, int c, int pc, int do_next, FinArgs<T> fa) {
     if (halted_run(fa.conv_tol, fa.halted)) return;   // the energy stopping rule ended the run
     __shared__ typename V2<T>::type cols[kTile];
@@ -845,7 +904,7 @@ __global__ __launch_bounds__(kRows * L) void step_kernel(GView<T> G, int c, int 
     const bool fin_row = fa.fin >= 0 && bi == fa.fin;
     if (!__syncthreads_or(work || fin_row)) return;
     T xi = 0, yi = 0, fx = 0, fy = 0;
-    panel_rowsL<T, KAHAN, L>(G, first, c, pc, do_next, fa.fin, cols, xi, yi, fx, fy);
+    panel_rowsL<T, KAHAN, L, false, M>(G, first, c, pc, do_next, fa.fin, cols, xi, yi, fx, fy);
     if (fa.fin >= 0 && __syncthreads_or(fin_row)) finish_chunkL<T, KAHAN, L>(G, fa, first, xi, yi, fx, fy, e2, ws);
 }
 
@@ -888,7 +947,7 @@ __device__ __forceinline__ int batch_chunks(int b, int BS, int n) {
     return (b1 - 1) / kRows - b0 / kRows + 1;
 }
 
-template <typename T, bool KAHAN, int L>
+template <typename T, bool KAHAN, int L, int M>
 __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs A, FinArgs<T> fa0) {
     __shared__ typename V2<T>::type cols[kTile];
     __shared__ double ws[kRows * L / kWave];
@@ -932,7 +991,7 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
                 T xi = 0, yi = 0, fx = 0, fy = 0;
                 // the rows every workgroup waits for next go first on their SIMDs
                 if (is_fin) __builtin_amdgcn_s_setprio(3);
-                panel_rowsL<T, KAHAN, L, true>(G, first, c, pk & 1, do_next, fin, cols, xi, yi, fx, fy);
+                panel_rowsL<T, KAHAN, L, true, M>(G, first, c, pk & 1, do_next, fin, cols, xi, yi, fx, fy);
                 if (is_fin) {
                     FinArgs<T> fa = fa0;
                     fa.fin = fin;
@@ -1003,6 +1062,8 @@ __global__ __launch_bounds__(NT) void exact_graph_kernel(const ExactJob *__restr
     G.BS = J0.BS;
     G.nb = J0.nb;
     G.literal = J0.literal;
+    G.ka = 1;    // this kernel runs the (2, -1) model only
+    G.kr = -2;
     G.invK = (T)J0.invK;
     G.negRK2 = (T)J0.negRK2;
     G.rowptr = J0.rowptr;
@@ -1098,7 +1159,7 @@ __global__ __launch_bounds__(NT) void exact_graph_kernel(const ExactJob *__restr
     if (bad) atomicAdd(nonfinite, bad);
 }
 
-template <typename T, bool KAHAN>
+template <typename T, bool KAHAN, int M>
 struct ExactOps {
     using T2 = typename V2<T>::type;
 
@@ -1108,6 +1169,8 @@ struct ExactOps {
         G.BS = g->p.batch_size;
         G.nb = g->nb;
         G.literal = g->p.repulse_adjacent ? 0 : 1;
+        G.ka = g->p.model_a - 1;
+        G.kr = g->p.model_r - 1;
         G.invK = (T)(1.0 / g->p.K);
         G.negRK2 = (T)(-g->p.R * g->p.K * g->p.K);
         G.rowptr = g->rowptr;
@@ -1145,13 +1208,13 @@ struct ExactOps {
         BL_TRY(prof_begin(g, PK_ROWS, &slot));
         const int L = lanes(g, row1 - row0);
         if (L == 1)
-            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 1>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), row0,
+            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 1, M>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), row0,
                                row1, from_own, parity, clear_other);
         else if (L == 2)
-            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 2>), dim3(blocks), dim3(kRows * 2), 0, g->stream, view(g),
+            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 2, M>), dim3(blocks), dim3(kRows * 2), 0, g->stream, view(g),
                                row0, row1, from_own, parity, clear_other);
         else
-            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 4>), dim3(blocks), dim3(kRows * 4), 0, g->stream, view(g),
+            hipLaunchKernelGGL((rows_kernel<T, KAHAN, 4, M>), dim3(blocks), dim3(kRows * 4), 0, g->stream, view(g),
                                row0, row1, from_own, parity, clear_other);
         BL_HIP(hipGetLastError());
         return prof_end(g, slot);
@@ -1186,13 +1249,13 @@ struct ExactOps {
         BL_TRY(prof_begin(g, PK_PANEL, &slot));
         const int L = lanes(g, g->n);
         if (L == 1)
-            hipLaunchKernelGGL((step_kernel<T, KAHAN, 1>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), c, pc,
+            hipLaunchKernelGGL((step_kernel<T, KAHAN, 1, M>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), c, pc,
                                do_next, fa);
         else if (L == 2)
-            hipLaunchKernelGGL((step_kernel<T, KAHAN, 2>), dim3(blocks), dim3(kRows * 2), 0, g->stream, view(g), c,
+            hipLaunchKernelGGL((step_kernel<T, KAHAN, 2, M>), dim3(blocks), dim3(kRows * 2), 0, g->stream, view(g), c,
                                pc, do_next, fa);
         else
-            hipLaunchKernelGGL((step_kernel<T, KAHAN, 4>), dim3(blocks), dim3(kRows * 4), 0, g->stream, view(g), c,
+            hipLaunchKernelGGL((step_kernel<T, KAHAN, 4, M>), dim3(blocks), dim3(kRows * 4), 0, g->stream, view(g), c,
                                pc, do_next, fa);
         BL_HIP(hipGetLastError());
         return prof_end(g, slot);
@@ -1204,8 +1267,8 @@ struct ExactOps {
     static int steps(bl_graph *g, int e0, int e1, int start, int lastk, int &launched) {
         launched = 0;
         const int L = lanes(g, g->n);
-        const void *f = L == 1 ? (const void *)steps_kernel<T, KAHAN, 1>
-                               : (L == 2 ? (const void *)steps_kernel<T, KAHAN, 2> : (const void *)steps_kernel<T, KAHAN, 4>);
+        const void *f = L == 1 ? (const void *)steps_kernel<T, KAHAN, 1, M>
+                               : (L == 2 ? (const void *)steps_kernel<T, KAHAN, 2, M> : (const void *)steps_kernel<T, KAHAN, 4, M>);
         int dev = 0, cus = 0, per_cu = 0;
         BL_HIP(hipGetDevice(&dev));
         BL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1444,8 +1507,10 @@ size_t exact_footprint(int n, int64_t nnz, int BS, bool fp64) {
 
 // Small graphs run in the one-workgroup kernel (one workgroup per graph); it
 // computes the same bits as the multi-workgroup kernels.
+// It runs the (2, -1) model only; other (a, r) models take the multi-workgroup path.
 static bool use_one_wg(const bl_graph *g, int stop_batch) {
-    return stop_batch < 0 && !(g->p.flags & BL_EXACT_MULTI_WG) && (long long)g->n * g->p.batch_size <= kOneWGPairs;
+    return stop_batch < 0 && !(g->p.flags & BL_EXACT_MULTI_WG) && !model_general(g->p) &&
+           (long long)g->n * g->p.batch_size <= kOneWGPairs;
 }
 
 int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch) {
@@ -1456,15 +1521,35 @@ int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch) {
         BL_TRY(exact_graph_launch(&g, 1, nt, g->stream, g->ex.d_job, iters, start_iter));
         return prof_end(g, slot);
     }
-    if (g->fp64) return ExactOps<double, false>::run(g, iters, start_iter, stop_batch);
-    if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false>::run(g, iters, start_iter, stop_batch);
-    return ExactOps<float, true>::run(g, iters, start_iter, stop_batch);
+    if (model_general(g->p) && g->p.model_r == -1) {
+        if (g->fp64) return ExactOps<double, false, 2>::run(g, iters, start_iter, stop_batch);
+        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 2>::run(g, iters, start_iter, stop_batch);
+        return ExactOps<float, true, 2>::run(g, iters, start_iter, stop_batch);
+    }
+    if (model_general(g->p)) {
+        if (g->fp64) return ExactOps<double, false, 1>::run(g, iters, start_iter, stop_batch);
+        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 1>::run(g, iters, start_iter, stop_batch);
+        return ExactOps<float, true, 1>::run(g, iters, start_iter, stop_batch);
+    }
+    if (g->fp64) return ExactOps<double, false, 0>::run(g, iters, start_iter, stop_batch);
+    if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 0>::run(g, iters, start_iter, stop_batch);
+    return ExactOps<float, true, 0>::run(g, iters, start_iter, stop_batch);
 }
 
 int exact_forces(bl_graph *g, int batch) {
-    if (g->fp64) return ExactOps<double, false>::forces(g, batch);
-    if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false>::forces(g, batch);
-    return ExactOps<float, true>::forces(g, batch);
+    if (model_general(g->p) && g->p.model_r == -1) {
+        if (g->fp64) return ExactOps<double, false, 2>::forces(g, batch);
+        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 2>::forces(g, batch);
+        return ExactOps<float, true, 2>::forces(g, batch);
+    }
+    if (model_general(g->p)) {
+        if (g->fp64) return ExactOps<double, false, 1>::forces(g, batch);
+        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 1>::forces(g, batch);
+        return ExactOps<float, true, 1>::forces(g, batch);
+    }
+    if (g->fp64) return ExactOps<double, false, 0>::forces(g, batch);
+    if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 0>::forces(g, batch);
+    return ExactOps<float, true, 0>::forces(g, batch);
 }
 
 }  // namespace bl

@@ -167,6 +167,8 @@ int check_csr_host(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, boo
 // The same checks on a graph given in host or (BL_DEVICE_PTRS) device memory.
 int check_csr(const bl_csr *g, uint32_t flags, hipStream_t s);
 int params_check(const bl_params *p);
+// The (a, r) model is not Fruchterman-Reingold's (2, -1).
+inline bool model_general(const bl_params &p) { return p.model_a != 2 || p.model_r != -1; }
 int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds);
 
 // exact mode (bl_exact.hip)

@@ -173,3 +173,23 @@ def test_quality_rejects_bad_arguments(lib):
     csr2 = api._csr(bad, keep)
     assert lib.bl_quality_eval(C.byref(csr2), x.ctypes.data, x.ctypes.data, 0, None, 1.0, 0, None, C.byref(q)) == -1
     assert lib.bl_last_error()
+
+
+@pytest.mark.parametrize("a,r", [(1, 1), (-1, 2), (9, -1), (2, -9), (0, 0)])
+def test_model_out_of_range_rejected(lib, a, r):
+    from paper_2002_08233_amd import api, inputs
+    p = api.params(iterations=1, model=(a, r))
+    assert _call_layout(lib, inputs.path(5), p) == -1
+    assert b"model" in lib.bl_last_error()
+
+
+def test_general_model_only_in_single_graph_exact_mode(lib):
+    """(a, r) other than (2, -1): Barnes-Hut and the batched path reject it on the host."""
+    from paper_2002_08233_amd import _lib, api, inputs
+    p = api.params()
+    assert (p.model_a, p.model_r) == (2, -1)
+    assert _call_layout(lib, inputs.path(5), api.params(iterations=1, mode="bh", model=(1, -1))) == -1
+    g = inputs.path(6)
+    x = np.zeros(6)
+    with pytest.raises(_lib.BLError, match="model"):
+        api.layout_batch([g], [x], [x], [api.params(iterations=1, model=(1, -1))])
