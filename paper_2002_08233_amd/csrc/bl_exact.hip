@@ -215,7 +215,6 @@ template <typename T>
 struct GView {
     using T2 = typename V2<T>::type;
     int n, BS, nb, literal;
-    int ka, kr;   // (a, r) model: the terms are d^(a-1) and d^(r-1) times (c_j - c_i)
     T invK, negRK2;
     const int *rowptr, *colidx;
     const int2 *segs;
@@ -224,6 +223,7 @@ struct GView {
     T *x, *y;
     T2 *accS[2];
     float2 *accC[2];
+    int ka, kr;   // (a, r) model: the terms are d^(a-1) and d^(r-1) times (c_j - c_i)
     // by parity, without dynamic indexing (keeps a local view out of scratch)
     __device__ __forceinline__ T2 *S(int par) const { return par ? accS[1] : accS[0]; }
     __device__ __forceinline__ float2 *C(int par) const { return par ? accC[1] : accC[0]; }
