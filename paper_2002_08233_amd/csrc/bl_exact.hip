@@ -1405,6 +1405,33 @@ __global__ void seg_fill_kernel(int n, int BS, const int *__restrict__ rowptr, c
 
 }  // namespace
 
+#ifdef BL_EXACT_MODELS_TU
+// Runs and force calls under (a, r) models other than (2, -1).  They are
+// instantiated in a translation unit of their own: next to the (2, -1)
+// kernels in one code object they slowed those by about 3% (placement).
+int exact_run_model(bl_graph *g, int iters, int start_iter, int stop_batch) {
+    if (g->p.model_r == -1) {
+        if (g->fp64) return ExactOps<double, false, 2>::run(g, iters, start_iter, stop_batch);
+        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 2>::run(g, iters, start_iter, stop_batch);
+        return ExactOps<float, true, 2>::run(g, iters, start_iter, stop_batch);
+    }
+    if (g->fp64) return ExactOps<double, false, 1>::run(g, iters, start_iter, stop_batch);
+    if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 1>::run(g, iters, start_iter, stop_batch);
+    return ExactOps<float, true, 1>::run(g, iters, start_iter, stop_batch);
+}
+
+int exact_forces_model(bl_graph *g, int batch) {
+    if (g->p.model_r == -1) {
+        if (g->fp64) return ExactOps<double, false, 2>::forces(g, batch);
+        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 2>::forces(g, batch);
+        return ExactOps<float, true, 2>::forces(g, batch);
+    }
+    if (g->fp64) return ExactOps<double, false, 1>::forces(g, batch);
+    if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 1>::forces(g, batch);
+    return ExactOps<float, true, 1>::forces(g, batch);
+}
+#else
+
 // Launch one workgroup per graph for a group of exact-mode graphs that share
 // a precision.  threads: 256, 512 or 1024 (the result does not depend on it).
 int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override,
@@ -1521,35 +1548,19 @@ int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch) {
         BL_TRY(exact_graph_launch(&g, 1, nt, g->stream, g->ex.d_job, iters, start_iter));
         return prof_end(g, slot);
     }
-    if (model_general(g->p) && g->p.model_r == -1) {
-        if (g->fp64) return ExactOps<double, false, 2>::run(g, iters, start_iter, stop_batch);
-        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 2>::run(g, iters, start_iter, stop_batch);
-        return ExactOps<float, true, 2>::run(g, iters, start_iter, stop_batch);
-    }
-    if (model_general(g->p)) {
-        if (g->fp64) return ExactOps<double, false, 1>::run(g, iters, start_iter, stop_batch);
-        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 1>::run(g, iters, start_iter, stop_batch);
-        return ExactOps<float, true, 1>::run(g, iters, start_iter, stop_batch);
-    }
+    if (model_general(g->p)) return exact_run_model(g, iters, start_iter, stop_batch);
     if (g->fp64) return ExactOps<double, false, 0>::run(g, iters, start_iter, stop_batch);
     if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 0>::run(g, iters, start_iter, stop_batch);
     return ExactOps<float, true, 0>::run(g, iters, start_iter, stop_batch);
 }
 
 int exact_forces(bl_graph *g, int batch) {
-    if (model_general(g->p) && g->p.model_r == -1) {
-        if (g->fp64) return ExactOps<double, false, 2>::forces(g, batch);
-        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 2>::forces(g, batch);
-        return ExactOps<float, true, 2>::forces(g, batch);
-    }
-    if (model_general(g->p)) {
-        if (g->fp64) return ExactOps<double, false, 1>::forces(g, batch);
-        if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 1>::forces(g, batch);
-        return ExactOps<float, true, 1>::forces(g, batch);
-    }
+    if (model_general(g->p)) return exact_forces_model(g, batch);
     if (g->fp64) return ExactOps<double, false, 0>::forces(g, batch);
     if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 0>::forces(g, batch);
     return ExactOps<float, true, 0>::forces(g, batch);
 }
+
+#endif  // BL_EXACT_MODELS_TU
 
 }  // namespace bl

@@ -176,6 +176,9 @@ int exact_alloc(bl_graph *g);
 int exact_prepare(bl_graph *g);   // after the CSR upload
 int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch);
 int exact_forces(bl_graph *g, int batch);
+// The same under (a, r) models other than (2, -1) (bl_exact_models.hip).
+int exact_run_model(bl_graph *g, int iters, int start_iter, int stop_batch);
+int exact_forces_model(bl_graph *g, int batch);
 int exact_graph_launch(bl_graph *const *gs, int G, int threads, hipStream_t s, void *d_jobs, int iters_override,
                        int start_override = -1);
 size_t exact_job_size();
