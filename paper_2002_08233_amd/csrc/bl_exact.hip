@@ -480,8 +480,50 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
         if constexpr (COH) return T2{ld_agent(G.x + j), ld_agent(G.y + j)};
         else return T2{G.x[j], G.y[j]};
     };
-    // entries 0..15, held by the row's lanes (entry u in lane u % L, slot u / L)
+    // entries 0..15, held by the row's lanes (entry u in lane u % L, slot
+    // u / L).  FP32: four entries per round, each lane forms the terms of its
+    // own entries of the round, then the lead lane adds them in entry order.
+    // FP64 (whose registers this would cost occupancy): the lead lane forms
+    // and adds each entry's terms in turn.  Both add in entry order.
     const int base_lane = lane & ~(L - 1);
+    constexpr int KB = 4 / L;   // slots per round
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k0 = 0; k0 < NP; k0 += KB) {
+        if (!__ballot(lead && L * k0 < cnt)) break;
+        T tax[KB], tay[KB], tlx[KB], tly[KB];
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            tax[q] = tay[q] = tlx[q] = tly[q] = 0;
+            if (h + L * (k0 + q) < cnt) {
+                const T2 pj = pos(pre[k0 + q]);
+                ent_att<M>(G.ka, xi, yi, pj, tax[q], tay[q]);
+                if (G.literal) ent_rep<M>(G.kr, xi, yi, pj, tlx[q], tly[q]);
+            }
+        }
+#pragma unroll
+        for (int u = L * k0; u < L * (k0 + KB); ++u) {
+            const int q = u / L - k0;
+            T vx = tax[q], vy = tay[q], wx = tlx[q], wy = tly[q];
+            if constexpr (L > 1) {
+                vx = __shfl(vx, base_lane + (u % L), kWave);
+                vy = __shfl(vy, base_lane + (u % L), kWave);
+                if (G.literal) {
+                    wx = __shfl(wx, base_lane + (u % L), kWave);
+                    wy = __shfl(wy, base_lane + (u % L), kWave);
+                }
+            }
+            if (lead && u < cnt) {
+                ax += vx;
+                ay += vy;
+                if (G.literal) {
+                    lx += wx;
+                    ly += wy;
+                }
+            }
+        }
+    }
+    } else {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         if (!__ballot(lead && u < cnt)) break;
@@ -498,6 +540,7 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
                 ly += ty;
             }
         }
+    }
     }
     // entries 16.. of long segments (hub rows), one row at a time: every lane
     // of the wave forms one entry's terms, the row's lead lane adds them in
@@ -535,10 +578,26 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
                 if (G.literal) lu[lane] = T2{ux, uy};
                 __builtin_amdgcn_wave_barrier();
                 if (lane == src) {
-                    for (int u = 0; u < mcount; ++u) {
-                        const T2 v = lt[u];
-                        ax += v.x;
-                        ay += v.y;
+                    if (sizeof(T) == 4 && mcount == kWave) {
+                        // a full group (FP32): the 64 terms are read eight
+                        // at a time ahead of their additions (same order)
+#pragma unroll
+                        for (int u0 = 0; u0 < kWave; u0 += 8) {
+                            T2 v[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) v[q] = lt[u0 + q];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                ax += v[q].x;
+                                ay += v[q].y;
+                            }
+                        }
+                    } else {
+                        for (int u = 0; u < mcount; ++u) {
+                            const T2 v = lt[u];
+                            ax += v.x;
+                            ay += v.y;
+                        }
                     }
                     if (G.literal) {
                         for (int u = 0; u < mcount; ++u) {
