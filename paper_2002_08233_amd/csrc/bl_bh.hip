@@ -1094,7 +1094,7 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, P po
                 }
                 const float dx = xj[q] - px[r], dy = yj[q] - py[r];
                 if (((unsigned)w[q] & 0x80000000u) == 0u) {
-                    const float d = sqrtf(dx * dx + dy * dy) * invK;
+                    const float d = sqrtf(fmaf(dx, dx, dy * dy)) * invK;
                     ax = fmaf(d, dx, ax);
                     ay = fmaf(d, dy, ay);
                 } else {
@@ -1406,7 +1406,27 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         const int key0 = e0 < e1 ? (int)(ce[0] >> 32) : -1 - tid;   // row of the run's first entry
         gptr<const unsigned long long> lst = J.ent + S.mb[b & 15] + S.mo[b & 15];
         if (wave_busy) {
-            if (use_win)
+            if (chunk == 1 && use_win) {
+                // one entry per run: run_sum's arithmetic without its loop
+                firstp = float2{0.f, 0.f};
+                if (e0 < e1) {
+                    const int r = (int)(ce[0] >> 32);
+                    const float dx = xj[0] - S.px[slot][r], dy = yj[0] - S.py[slot][r];
+                    float ax, ay;
+                    if (((unsigned)ce[0] & 0x80000000u) == 0u) {
+                        const float d = sqrtf(fmaf(dx, dx, dy * dy)) * invK;
+                        ax = fmaf(d, dx, 0.f);
+                        ay = fmaf(d, dy, 0.f);
+                    } else {
+                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+                        const float inv = __builtin_amdgcn_rcpf(d2) * negRK2;
+                        ax = fmaf(dx, inv, 0.f);
+                        ay = fmaf(dy, inv, 0.f);
+                    }
+                    if (S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1) S.sum[r] = float2{ax, ay};
+                    else firstp = float2{ax, ay};
+                }
+            } else if (use_win)
                 run_sum<kEnt>(lst, pl, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl,
                               invK, negRK2);
             else
