@@ -299,6 +299,7 @@ def main():
                                "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
             nb = (g.n + w["batch_size"] - 1) // w["batch_size"]
             out["bh"] = {"node_visits_per_vertex": visits / rows, "cell_tests_per_vertex": tests / rows,
+                         "node_visits_per_s": visits / rows * g.n * steps / wall,
                          "late_entries_per_vertex": late / rows,
                          "old_entries_per_vertex": old_e / rows, "recent_entries_per_vertex": recent_e / rows,
                          "late_overflow": st["late_overflow"],
