@@ -1469,7 +1469,8 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
                 } else {
                     e_iter += f2;
                     if (f2 > 0.0) {
-                        const float sc = step / sqrtf(fx * fx + fy * fy);
+                        // step / |f| with the hardware reciprocal square root (about 1 ulp)
+                        const float sc = step * __builtin_amdgcn_rsqf(fx * fx + fy * fy);
                         np = float2{x + sc * fx, y + sc * fy};
                         st<float2>(J.pos, i, np);
                     }
