@@ -263,6 +263,78 @@ def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=
     return x, y, e[:iters], vt.value
 
 
+_M64 = (1 << 64) - 1
+_SM_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64(state: int) -> int:
+    """SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014) of
+    one state word: xor-shift 30, multiply, xor-shift 27, multiply,
+    xor-shift 31.  The t-th output (t >= 1) of a stream seeded with s is
+    splitmix64(s + t * gamma)."""
+    z = state & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def batch_permutation(n: int, seed: int, k: int) -> np.ndarray:
+    """The vertex order of iteration k under batch randomisation (Sec. 4.2;
+    the paper fixes no generator, so this is the library's documented one):
+    Durstenfeld's Fisher-Yates shuffle of 0..n-1, for i = n-1 down to 1
+    swapping positions i and u mod (i+1), u = the (c+1)-th SplitMix64 output
+    of seed for the counter c = k * 2^32 + i.  Pure Python (small n)."""
+    perm = list(range(n))
+    for i in range(n - 1, 0, -1):
+        c = (k << 32) + i
+        u = splitmix64(seed + (c + 1) * _SM_GAMMA)
+        j = u % (i + 1)
+        perm[i], perm[j] = perm[j], perm[i]
+    return np.array(perm, dtype=np.int64)
+
+
+def _relabel(rowptr, colidx, perm):
+    """The graph with vertex perm[q] renamed q (rows sorted again)."""
+    rp = np.asarray(rowptr, dtype=np.int64)
+    ci = np.asarray(colidx, dtype=np.int64)
+    n = len(rp) - 1
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    rows = [np.sort(inv[ci[rp[v]:rp[v + 1]]]) for v in perm]
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    rp2[1:] = np.cumsum([len(r) for r in rows])
+    ci2 = np.concatenate(rows) if len(ci) else np.zeros(0, dtype=np.int64)
+    return rp2.astype(np.int32), ci2.astype(np.int32)
+
+
+def layout_shuffled(rowptr, colidx, x0, y0, bs, iters, seed, start_iter=0, mode="exact", conv_tol=0.0,
+                    **kw):
+    """BatchLayout with randomised minibatches (Sec. 4.2): iteration k takes
+    its batches as consecutive runs of batch_permutation(n, seed, k).  Written
+    as the ordinary run of one iteration (layout_exact or layout_bh, with the
+    iteration's own step length) on the graph relabelled so that those runs
+    are the id ranges; the coordinates are mapped back after each iteration.
+    Returns (x, y, energy per iteration)."""
+    x = _f64(x0).copy()
+    y = _f64(y0).copy()
+    n = len(x)
+    es = []
+    for t in range(iters):
+        k = start_iter + t
+        perm = batch_permutation(n, seed, k)
+        rp2, ci2 = _relabel(rowptr, colidx, perm)
+        if mode == "exact":
+            xs, ys, e = layout_exact(rp2, ci2, x[perm], y[perm], bs, 1, k, **kw)
+        else:
+            xs, ys, e, _ = layout_bh(rp2, ci2, x[perm], y[perm], bs, 1, k, **kw)
+        x[perm] = xs
+        y[perm] = ys
+        es.append(e[0])
+        if _converged(es, conv_tol):
+            break
+    return x, y, np.array(es)
+
+
 def edge_energy(rowptr, colidx, x, y, K=1.0) -> float:
     """Sum over undirected edges of d^3/(3K), the attractive potential."""
     rp, ci = _csr(rowptr, colidx)
