@@ -187,6 +187,27 @@ def greedy_report(api, w, p, steps, energy_random):
     return rep
 
 
+def shuffle_report(api, w, p, steps, seed=2020):
+    """Randomised minibatches (Sec. 4.2) for `steps` iterations from the
+    workload's start through bl_layout_shuffled, which relabels and uploads
+    the graph every iteration, beside bl_layout from the same host arrays for
+    the same iterations (both end to end, host arrays in and out)."""
+    g = w["graph"]
+    q = api.Params.from_buffer_copy(p)
+    q.iterations = steps
+    t0 = time.perf_counter()
+    _, _, es, st = api.layout_shuffled(g, w["x0"], w["y0"], q, seed=seed)
+    ts = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, eu, _ = api.layout(g, w["x0"], w["y0"], q)
+    tu = time.perf_counter() - t0
+    return {"steps": steps, "seed": seed, "force_updates_per_s": g.n * steps / ts, "seconds": ts,
+            "device_seconds": st["seconds"], "device_force_updates_per_s": g.n * steps / max(st["seconds"], 1e-12),
+            "sequential_end_to_end_force_updates_per_s": g.n * steps / tu,
+            "energy_last": float(es[-1]) if len(es) else None,
+            "energy_last_sequential": float(eu[-1]) if len(eu) else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +226,8 @@ def main():
     ap.add_argument("--no-greedy", action="store_true", help="skip the greedy-initialisation report")
     ap.add_argument("--no-quality", action="store_true", help="skip the layout-quality report")
     ap.add_argument("--precision", default="fp32_kahan")
+    ap.add_argument("--shuffle-steps", type=int, default=0,
+                    help="also run this many iterations with randomised minibatches (0: off)")
     ap.add_argument("--model", default="2,-1", help="exact mode: the (a, r) energy model, e.g. 1,-1")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -342,6 +365,8 @@ def main():
         out["end_to_end"] = {"force_updates_per_s": g.n * steps / e2e, "seconds": e2e,
                              "note": "bl_layout from host arrays: CSR and coordinates uploaded, "
                                      "device state built, the run, coordinates back"}
+    if args.shuffle_steps > 0:
+        out["shuffled"] = shuffle_report(api, w, p, args.shuffle_steps)
     if not args.no_quality:
         out["quality"] = quality_report(api, g, xf, yf)
     if not args.no_greedy:

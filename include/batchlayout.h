@@ -144,6 +144,26 @@ int bl_layout(const bl_csr *g, const double *x0, const double *y0, const bl_para
               void *hip_stream, double *x_out, double *y_out, double *energy_out,
               bl_stats *stats);
 
+/* ------------------------------------------- randomised minibatches
+ * bl_layout with the batch randomisation of Sec. 4.2: in iteration k the
+ * minibatches are the consecutive runs of p->batch_size entries of a
+ * permutation pi_k of the vertex ids (the last run may be shorter), processed
+ * in that order, each with the usual Jacobi-within / Gauss-Seidel-across
+ * semantics; the step length is p->step0 * p->step_decay^k as in bl_layout.
+ * pi_k is Durstenfeld's Fisher-Yates shuffle of the identity, for i = n-1
+ * down to 1 swapping positions i and (u mod (i+1)), where u is SplitMix64's
+ * output function (Steele, Lea and Flood 2014) applied to the state
+ * seed + (c+1) * 0x9E3779B97F4A7C15 with c = k * 2^32 + i; so pi_k depends on
+ * (seed, k) only.  The paper gives no generator; this one is the library's.
+ * Host arrays only (BL_DEVICE_PTRS in p->flags is BL_E_INVAL); exact and
+ * Barnes-Hut modes; conv_tol applies between iterations as in bl_layout.
+ * Each iteration relabels the graph on the host and uploads it, the
+ * reshuffling cost the paper notes.  stats->seconds sums the device time of
+ * the iterations (host relabelling excluded).  Errors as bl_layout. */
+int bl_layout_shuffled(const bl_csr *g, const double *x0, const double *y0, const bl_params *p,
+                       uint64_t seed, void *hip_stream, double *x_out, double *y_out,
+                       double *energy_out, bl_stats *stats);
+
 /* ------------------------------------------------ greedy initial layout
  * The greedy initialisation of Sec. 3.6 (Algorithm 3): `start` is placed at
  * (0, 0) and pushed on a stack; each popped vertex U places every neighbour

@@ -27,6 +27,7 @@ EXPORTED = [
     "bl_graph_destroy", "bl_graph_profile", "bl_graph_profile_read", "bl_layout_batch",
     "bl_server_create", "bl_server_submit", "bl_server_poll", "bl_server_wait", "bl_server_fetch",
     "bl_server_release", "bl_server_destroy", "bl_greedy_init", "bl_quality_eval",
+    "bl_layout_shuffled",
 ]
 
 
@@ -90,6 +91,7 @@ def load():
     lib.bl_footprint_bytes.argtypes = [i32, i64, P(Params)]
     lib.bl_footprint_bytes.restype = C.c_size_t
     lib.bl_layout.argtypes = [P(CSR), vp, vp, P(Params), vp, vp, vp, vp, P(Stats)]
+    lib.bl_layout_shuffled.argtypes = [P(CSR), vp, vp, P(Params), C.c_uint64, vp, vp, vp, vp, P(Stats)]
     lib.bl_forces.argtypes = [P(CSR), vp, vp, vp, vp, i32, P(Params), vp, vp, vp]
     lib.bl_greedy_init.argtypes = [P(CSR), i32, vp, vp]
     lib.bl_quality_eval.argtypes = [P(CSR), vp, vp, i32, vp, dbl, C.c_uint32, vp, P(Quality)]

@@ -122,6 +122,25 @@ def layout(graph, x0, y0, p: Params, stream=None, energy=True):
     return xo, yo, en[:st.iters_run], st.as_dict()
 
 
+def layout_shuffled(graph, x0, y0, p: Params, seed: int, stream=None):
+    """Run p.iterations with randomised minibatches (Sec. 4.2): in iteration k
+    the batches are consecutive runs of a permutation drawn from (seed, k).
+    Host arrays only.  Returns (x, y, energy, stats)."""
+    lib = load()
+    keep = _Keep()
+    if _device(graph.rowptr, x0, y0):
+        raise ValueError("layout_shuffled takes host arrays")
+    csr = _csr(graph, keep)
+    xo = np.empty(csr.n)
+    yo = np.empty(csr.n)
+    en = np.zeros(max(p.iterations, 1))
+    st = Stats()
+    check(lib.bl_layout_shuffled(C.byref(csr), keep.ptr(x0, np.float64), keep.ptr(y0, np.float64), C.byref(p),
+                                 int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream), xo.ctypes.data, yo.ctypes.data,
+                                 en.ctypes.data, C.byref(st)))
+    return xo, yo, en[:st.iters_run], st.as_dict()
+
+
 def greedy_init(graph, start, x=None, y=None):
     """Greedy initial layout (Sec. 3.6, Algorithm 3) from vertex `start` at (0, 0).
 

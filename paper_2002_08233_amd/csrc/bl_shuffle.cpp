@@ -1,0 +1,122 @@
+// Randomised minibatches (Sec. 4.2, batch randomisation), a host driver of the
+// library around the ordinary single-graph path.
+//
+// In iteration k the minibatches are consecutive runs of BS vertices of a
+// permutation pi_k of the vertex ids instead of consecutive id ranges.  The
+// force kernels need no change for this: giving vertex pi_k[q] the label q
+// makes the permuted batches the ordinary ones, so each iteration relabels the
+// graph and the coordinates on the host, runs one iteration of the resident
+// path (start_iter = k, so the step length is the run's own), and scatters the
+// coordinates back.  The relabelling is the reshuffling cost the paper notes;
+// it is O(n + m) host work and one graph upload per iteration.
+//
+// pi_k is drawn with Durstenfeld's form of the Fisher-Yates shuffle, for
+// i = n-1 down to 1 swapping positions i and u mod (i+1), where u is the
+// SplitMix64 output (Steele, Lea and Flood, OOPSLA 2014) for the counter
+// c = k * 2^32 + i: the mix of the state seed + (c + 1) * 0x9E3779B97F4A7C15,
+// which is the (c+1)-th output of a SplitMix64 stream seeded with `seed`.
+// Every u depends only on (seed, k, i), so a run restarted at start_iter
+// draws the same batches.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "bl_internal.hpp"
+
+namespace {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+uint64_t splitmix_out(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// perm[q] = the vertex that gets label q in iteration k.
+void draw_perm(uint64_t seed, int64_t k, int n, std::vector<int32_t> &perm) {
+    perm.resize(n);
+    for (int q = 0; q < n; ++q) perm[q] = q;
+    for (int i = n - 1; i >= 1; --i) {
+        const uint64_t c = ((uint64_t)k << 32) + (uint64_t)i;
+        const uint64_t u = splitmix_out(seed + (c + 1) * kGamma);
+        const int j = (int)(u % (uint64_t)(i + 1));
+        std::swap(perm[i], perm[j]);
+    }
+}
+
+}  // namespace
+
+using namespace bl;
+
+int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, const bl_params *p, uint64_t seed,
+                       void *hip_stream, double *x_out, double *y_out, double *energy_out, bl_stats *st) {
+    if (!x0 || !y0 || !x_out || !y_out) return fail_code(BL_E_INVAL, "coordinate arrays are NULL");
+    if (!p) return fail_code(BL_E_INVAL, "params is NULL");
+    BL_TRY(params_check(p));
+    if (p->flags & BL_DEVICE_PTRS) return fail_code(BL_E_INVAL, "bl_layout_shuffled takes host arrays");
+    if (!csr) return fail_code(BL_E_INVAL, "graph is NULL");
+    BL_TRY(check_csr(csr, p->flags, (hipStream_t)hip_stream));
+    const int n = csr->n;
+    const int32_t *rp = csr->rowptr, *ci = csr->colidx;
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(x0[i]) || !std::isfinite(y0[i]))
+            return fail_code(BL_E_INVAL, "a start coordinate is not finite");
+
+    std::vector<double> x(x0, x0 + n), y(y0, y0 + n), xs(n), ys(n);
+    std::vector<int32_t> perm, inv(n), rp2(n + 1), cur(n), ci2(std::max<int64_t>(csr->nnz, 1));
+    bl_params q = *p;
+    q.iterations = 1;
+    q.conv_tol = 0.0;
+    bl_stats acc{};
+    std::vector<double> es;
+    int rc = BL_OK;
+    for (int t = 0; t < p->iterations; ++t) {
+        const int k = p->start_iter + t;
+        draw_perm(seed, k, n, perm);
+        for (int l = 0; l < n; ++l) inv[perm[l]] = l;
+        // Row l of the relabelled graph is old row perm[l]; its entries are
+        // filled column by column in increasing new label, which leaves every
+        // row sorted with no sort (this reads the graph through its
+        // transpose, which is the graph itself: the CSR is symmetric).
+        rp2[0] = 0;
+        for (int l = 0; l < n; ++l) {
+            const int v = perm[l];
+            rp2[l + 1] = rp2[l] + (rp[v + 1] - rp[v]);
+            cur[l] = rp2[l];
+            xs[l] = x[v];
+            ys[l] = y[v];
+        }
+        for (int c = 0; c < n; ++c) {
+            const int v = perm[c];
+            for (int e = rp[v]; e < rp[v + 1]; ++e) ci2[cur[inv[ci[e]]]++] = c;
+        }
+        const bl_csr g2{n, csr->nnz, rp2.data(), ci2.data()};
+        q.start_iter = k;
+        q.flags = p->flags & ~(uint32_t)BL_VALIDATE;   // the relabelled graph is valid if the input is
+        bl_stats s1{};
+        rc = bl_layout(&g2, xs.data(), ys.data(), &q, hip_stream, xs.data(), ys.data(), nullptr, &s1);
+        if (rc != BL_OK && rc != BL_E_NONFINITE) return rc;
+        for (int l = 0; l < n; ++l) {
+            x[perm[l]] = xs[l];
+            y[perm[l]] = ys[l];
+        }
+        acc.iters_run += s1.iters_run;
+        acc.late_overflow = std::max(acc.late_overflow, s1.late_overflow);
+        acc.seconds += s1.seconds;
+        acc.node_visits += s1.node_visits;
+        acc.nonfinite_events += s1.nonfinite_events;
+        acc.energy_last = s1.energy_last;
+        es.push_back(s1.energy_last);
+        if (energy_out) energy_out[t] = s1.energy_last;
+        if (rc == BL_E_NONFINITE) break;
+        const size_t ne = es.size();
+        if (p->conv_tol > 0 && ne >= 2 && std::fabs(es[ne - 1] - es[ne - 2]) <= p->conv_tol * es[ne - 2]) break;
+    }
+    std::memcpy(x_out, x.data(), 8 * (size_t)n);
+    std::memcpy(y_out, y.data(), 8 * (size_t)n);
+    if (st) *st = acc;
+    return rc;
+}

@@ -193,3 +193,32 @@ def test_general_model_only_in_single_graph_exact_mode(lib):
     x = np.zeros(6)
     with pytest.raises(_lib.BLError, match="model"):
         api.layout_batch([g], [x], [x], [api.params(iterations=1, model=(1, -1))])
+
+
+def test_shuffled_layout_host_checks(lib):
+    """bl_layout_shuffled: bad arguments are rejected before any device work;
+    zero iterations return the start layout."""
+    from paper_2002_08233_amd import api, inputs, _lib
+    g = inputs.path(6)
+    keep = api._Keep()
+    csr = api._csr(g, keep)
+    x = np.linspace(0.0, 1.0, 6)
+    y = np.zeros(6)
+    xo, yo = np.empty(6), np.empty(6)
+
+    def call(p, xa=x, ya=y, graph=C.byref(csr)):
+        return lib.bl_layout_shuffled(graph, xa.ctypes.data, ya.ctypes.data, C.byref(p), 7, None,
+                                      xo.ctypes.data, yo.ctypes.data, None, None)
+    dev = api.params(iterations=1)
+    dev.flags |= _lib.BL_DEVICE_PTRS
+    assert call(dev) == -1
+    assert call(api.params(batch_size=0)) == -1
+    assert call(api.params(iterations=1), graph=None) == -1
+    bad = x.copy()
+    bad[2] = np.nan
+    assert call(api.params(iterations=1), xa=bad) == -1
+    assert lib.bl_last_error()
+    st = _lib.Stats()
+    assert lib.bl_layout_shuffled(C.byref(csr), x.ctypes.data, y.ctypes.data, C.byref(api.params(iterations=0)),
+                                  7, None, xo.ctypes.data, yo.ctypes.data, None, C.byref(st)) == 0
+    assert np.array_equal(xo, x) and np.array_equal(yo, y) and st.iters_run == 0
