@@ -263,6 +263,40 @@ def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=
     return x, y, e[:iters], vt.value
 
 
+def hu_step_update(step, progress, e, e_prev, t):
+    """One update of Hu's adaptive step (Hu 2005, the scheme Sec. 4.1 cites):
+    an energy drop advances a progress count, and the fifth in a row resets
+    it and grows the step by 1/t; any other outcome resets the count and
+    shrinks the step by t.  Returns (step, progress)."""
+    if e < e_prev:
+        progress += 1
+        if progress >= 5:
+            return step / t, 0
+        return step, progress
+    return step * t, 0
+
+
+def layout_adaptive(rowptr, colidx, x0, y0, bs, iters, step0=1.0, t=0.9, mode="exact", conv_tol=0.0, **kw):
+    """BatchLayout with Hu's adaptive step instead of the fixed decay:
+    iteration k runs at step s_k (s_0 = step0, E_{-1} = +inf), then
+    hu_step_update gives s_{k+1}.  Returns (x, y, energy, steps)."""
+    x, y = _f64(x0).copy(), _f64(y0).copy()
+    step, progress, e_prev = step0, 0, float("inf")
+    es, steps = [], []
+    for k in range(iters):
+        steps.append(step)
+        if mode == "exact":
+            x, y, e = layout_exact(rowptr, colidx, x, y, bs, 1, 0, step0=step, decay=1.0, **kw)
+        else:
+            x, y, e, _ = layout_bh(rowptr, colidx, x, y, bs, 1, 0, step0=step, decay=1.0, **kw)
+        es.append(e[0])
+        if _converged(es, conv_tol):
+            break
+        step, progress = hu_step_update(step, progress, e[0], e_prev, t)
+        e_prev = e[0]
+    return x, y, np.array(es), np.array(steps)
+
+
 _M64 = (1 << 64) - 1
 _SM_GAMMA = 0x9E3779B97F4A7C15
 

@@ -1,4 +1,5 @@
-"""Pins of the batch-randomisation oracle (Sec. 4.2): the generator against
+"""Pins of the batch-randomisation oracle (Sec. 4.2) and of Hu's adaptive step
+(cited in Sec. 4.1).  Batch order: the generator against
 published outputs, the shuffle's uniformity, and the shuffled run against a
 brute-force statement of randomised minibatches on the original labels."""
 import collections
@@ -130,3 +131,47 @@ def test_shuffled_bh_run_is_randomised_minibatches(bs):
         step *= 0.999
     xs, ys, es = oracle.layout_shuffled(g.rowptr, g.colidx, x0, y0, bs, 3, seed=11, mode="bh", theta=1.2)
     assert np.allclose(xs, x, atol=1e-10) and np.allclose(ys, y, atol=1e-10) and np.allclose(es, er, rtol=1e-10)
+
+
+# ------------------------------------------------------- Hu's adaptive step
+
+def test_hu_update_worked_sequence():
+    """Hu's rule worked by hand for t = 0.5 on a scripted energy sequence:
+    five drops grow the step once; a rise shrinks it and restarts the count."""
+    energies = [10, 9, 8, 7, 6, 5, 4, 6, 5, 4, 3, 2, 1, 0.5]
+    # step used by each iteration, from 1.0
+    want = [1, 1, 1, 1, 1, 2, 2, 2, 1, 1, 1, 1, 1, 2]
+    step, prog, prev, got = 1.0, 0, float("inf"), []
+    for e in energies:
+        got.append(step)
+        step, prog = oracle.hu_step_update(step, prog, e, prev, 0.5)
+        prev = e
+    assert got == want
+
+
+def test_adaptive_with_unit_factor_is_the_fixed_step_run():
+    g = random_graph(30, 0.15, 51)
+    x0, y0 = I.uniform_coords(30, 52)
+    x, y, e, steps = oracle.layout_adaptive(g.rowptr, g.colidx, x0, y0, 7, 6, step0=0.3, t=1.0)
+    xf, yf, ef = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 7, 6, step0=0.3, decay=1.0)
+    assert np.array_equal(x, xf) and np.array_equal(y, yf) and np.array_equal(e, ef)
+    assert np.all(steps == 0.3)
+
+
+def test_adaptive_steps_follow_the_energies():
+    """The recorded steps obey the rule against the run's own energies, and
+    the run equals the fixed-step iterations replayed with those steps."""
+    g = random_graph(30, 0.15, 53)
+    x0, y0 = I.uniform_coords(30, 54)
+    x, y, e, steps = oracle.layout_adaptive(g.rowptr, g.colidx, x0, y0, 8, 25, step0=0.5, t=0.9)
+    assert len(set(np.round(steps, 12))) > 2             # the step moved both ways or more than once
+    prev, prog, s = float("inf"), 0, 0.5
+    xr, yr = x0, y0
+    for k in range(25):
+        assert steps[k] == s
+        xr, yr, ek = oracle.layout_exact(g.rowptr, g.colidx, xr, yr, 8, 1, step0=steps[k], decay=1.0)
+        assert ek[0] == e[k]
+        s, prog = (s / 0.9, 0) if (e[k] < prev and prog + 1 >= 5) else \
+                  ((s, prog + 1) if e[k] < prev else (s * 0.9, 0))
+        prev = e[k]
+    assert np.array_equal(x, xr) and np.array_equal(y, yr)
