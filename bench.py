@@ -208,6 +208,30 @@ def shuffle_report(api, w, p, steps, seed=2020):
             "energy_last_sequential": float(eu[-1]) if len(eu) else None}
 
 
+def adaptive_report(api, w, p, steps, t=0.9):
+    """Hu's adaptive step for `steps` iterations from the workload's start
+    (one device run per iteration on the resident graph), beside the fixed
+    decay, both through bl_layout from host arrays."""
+    g = w["graph"]
+    q = api.Params.from_buffer_copy(p)
+    q.iterations = steps
+    a = api.Params.from_buffer_copy(q)
+    a.step_decay = t
+    a.flags |= api.BL_ADAPTIVE_STEP
+    t0 = time.perf_counter()
+    _, _, ea, st = api.layout(g, w["x0"], w["y0"], a)
+    ta = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, ef, sf = api.layout(g, w["x0"], w["y0"], q)
+    tf = time.perf_counter() - t0
+    return {"steps": steps, "t": t, "force_updates_per_s": g.n * steps / ta, "seconds": ta,
+            "device_seconds": st["seconds"], "device_force_updates_per_s": g.n * steps / max(st["seconds"], 1e-12),
+            "fixed_decay_end_to_end_force_updates_per_s": g.n * steps / tf,
+            "fixed_decay_device_seconds": sf["seconds"],
+            "energy_last": float(ea[-1]) if len(ea) else None,
+            "energy_last_fixed_decay": float(ef[-1]) if len(ef) else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +250,8 @@ def main():
     ap.add_argument("--no-greedy", action="store_true", help="skip the greedy-initialisation report")
     ap.add_argument("--no-quality", action="store_true", help="skip the layout-quality report")
     ap.add_argument("--precision", default="fp32_kahan")
+    ap.add_argument("--adaptive-steps", type=int, default=0,
+                    help="also run this many iterations with Hu's adaptive step (0: off)")
     ap.add_argument("--shuffle-steps", type=int, default=0,
                     help="also run this many iterations with randomised minibatches (0: off)")
     ap.add_argument("--model", default="2,-1", help="exact mode: the (a, r) energy model, e.g. 1,-1")
@@ -367,6 +393,8 @@ def main():
                                      "device state built, the run, coordinates back"}
     if args.shuffle_steps > 0:
         out["shuffled"] = shuffle_report(api, w, p, args.shuffle_steps)
+    if args.adaptive_steps > 0:
+        out["adaptive"] = adaptive_report(api, w, p, args.adaptive_steps)
     if not args.no_quality:
         out["quality"] = quality_report(api, g, xf, yf)
     if not args.no_greedy:

@@ -64,6 +64,9 @@ extern "C" {
 #define BL_EXACT_MULTI_WG     8u  /* exact mode: always use the multi-workgroup
                                      step kernels (small graphs otherwise run in
                                      one workgroup); the result is the same bits */
+#define BL_ADAPTIVE_STEP     16u  /* bl_layout only: the adaptive step of Hu
+                                     (2005), cited in Sec. 4.1, replaces the
+                                     fixed decay (see bl_layout)                */
 
 typedef struct {
     int32_t n;               /* vertices, >= 1                                   */
@@ -90,7 +93,8 @@ typedef struct {
     double K;                /* > 0, optimal spring length                       */
     double R;                /* > 0, relative strength of repulsion              */
     double theta;            /* >= 0, BH acceptance: side < theta * distance     */
-    uint32_t flags;          /* BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG */
+    uint32_t flags;          /* BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG
+                                | BL_ADAPTIVE_STEP                               */
     int32_t reserved0;       /* must be zero                                     */
     double conv_tol;         /* >= 0; 0 = off.  The energy stopping rule of
                                 Sec. 4.3 read as a relative change: after an
@@ -139,7 +143,15 @@ size_t bl_footprint_bytes(int32_t n, int64_t nnz, const bl_params *p);
  * energy_out (may be NULL) receives p->iterations values, the energy
  * sum_i |f_i|^2 of each iteration (Sec. 2.2), reduced in FP64 on the GPU.
  * stats may be NULL.  Errors: BL_E_INVAL for bad sizes/params/NULL arrays,
- * BL_E_NONFINITE if a net force was NaN/Inf (coordinates are still written). */
+ * BL_E_NONFINITE if a net force was NaN/Inf (coordinates are still written).
+ * With BL_ADAPTIVE_STEP in p->flags the step length follows Hu's adaptive
+ * rule instead of step0 * step_decay^k, with t = p->step_decay (Hu uses 0.9):
+ * iteration 0 takes p->step0; after each iteration k, if E_k < E_{k-1}
+ * (E_{-1} = +inf) a progress count goes up by one and on reaching 5 is reset
+ * while the step is divided by t; otherwise the count is reset and the step
+ * multiplied by t.  p->start_iter must be 0; each iteration is then its own
+ * device run on the resident graph.  The graph API, bl_layout_shuffled,
+ * bl_layout_batch and the server reject the flag. */
 int bl_layout(const bl_csr *g, const double *x0, const double *y0, const bl_params *p,
               void *hip_stream, double *x_out, double *y_out, double *energy_out,
               bl_stats *stats);

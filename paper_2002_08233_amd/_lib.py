@@ -19,7 +19,7 @@ BL_OK, BL_E_INVAL, BL_E_NOMEM, BL_E_HIP, BL_E_NOTREADY, BL_E_REJECTED, BL_E_NONF
     0, -1, -2, -3, -4, -5, -6, -7
 BL_EXACT, BL_BH = 0, 1
 BL_FP32_KAHAN, BL_FP32_PLAIN, BL_FP64 = 0, 1, 2
-BL_DEVICE_PTRS, BL_VALIDATE, BL_BH_SNAPSHOT_LEAVES, BL_EXACT_MULTI_WG = 1, 2, 4, 8
+BL_DEVICE_PTRS, BL_VALIDATE, BL_BH_SNAPSHOT_LEAVES, BL_EXACT_MULTI_WG, BL_ADAPTIVE_STEP = 1, 2, 4, 8, 16
 
 EXPORTED = [
     "bl_params_init", "bl_last_error", "bl_version", "bl_footprint_bytes", "bl_layout", "bl_forces",

@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib as L
-from ._lib import (BL_BH, BL_BH_SNAPSHOT_LEAVES, BL_DEVICE_PTRS, BL_EXACT, BL_EXACT_MULTI_WG, BL_FP32_KAHAN,
+from ._lib import (BL_ADAPTIVE_STEP, BL_BH, BL_BH_SNAPSHOT_LEAVES, BL_DEVICE_PTRS, BL_EXACT, BL_EXACT_MULTI_WG, BL_FP32_KAHAN,
                    BL_FP32_PLAIN, BL_FP64, BL_VALIDATE, BLError, Params, Stats, check, load)
 
 PRECISIONS = {"fp32_kahan": BL_FP32_KAHAN, "fp32": BL_FP32_PLAIN, "fp32_plain": BL_FP32_PLAIN,
@@ -20,7 +20,8 @@ MODES = {"exact": BL_EXACT, "bh": BL_BH}
 
 def params(batch_size=256, iterations=600, start_iter=0, mode="exact", precision="fp32_kahan",
            repulse_adjacent=True, step0=1.0, step_decay=0.999, K=1.0, R=1.0, theta=1.2,
-           validate=False, snapshot_leaves=False, multi_wg=False, conv_tol=0.0, model=(2, -1)) -> Params:
+           validate=False, snapshot_leaves=False, multi_wg=False, conv_tol=0.0, model=(2, -1),
+           adaptive_step=False) -> Params:
     p = Params()
     check(load().bl_params_init(C.byref(p)))
     p.batch_size = int(batch_size)
@@ -33,7 +34,7 @@ def params(batch_size=256, iterations=600, start_iter=0, mode="exact", precision
     p.conv_tol = conv_tol
     p.model_a, p.model_r = int(model[0]), int(model[1])
     p.flags = ((BL_VALIDATE if validate else 0) | (BL_BH_SNAPSHOT_LEAVES if snapshot_leaves else 0) |
-               (BL_EXACT_MULTI_WG if multi_wg else 0))
+               (BL_EXACT_MULTI_WG if multi_wg else 0) | (BL_ADAPTIVE_STEP if adaptive_step else 0))
     return p
 
 

@@ -122,6 +122,8 @@ extern "C" int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const dou
         BL_TRY(params_check(params[q]));
         if (model_general(*params[q]))
             return fail_code(BL_E_INVAL, "bl_layout_batch runs the (2, -1) model only");
+        if (params[q]->flags & BL_ADAPTIVE_STEP)
+            return fail_code(BL_E_INVAL, "BL_ADAPTIVE_STEP is a bl_layout option");
     }
     BatchState B;
     BL_HIP(hipStreamCreate(&B.s_ex));

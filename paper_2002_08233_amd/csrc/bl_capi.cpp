@@ -68,7 +68,7 @@ int check_params(const bl_params *p) {
     if (!(p->K > 0) || !std::isfinite(p->K)) return fail(BL_E_INVAL, "K must be > 0");
     if (!(p->R > 0) || !std::isfinite(p->R)) return fail(BL_E_INVAL, "R must be > 0");
     if (!(p->theta >= 0) || !std::isfinite(p->theta)) return fail(BL_E_INVAL, "theta must be >= 0");
-    if (p->flags & ~(BL_DEVICE_PTRS | BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG))
+    if (p->flags & ~(BL_DEVICE_PTRS | BL_VALIDATE | BL_BH_SNAPSHOT_LEAVES | BL_EXACT_MULTI_WG | BL_ADAPTIVE_STEP))
         return fail(BL_E_INVAL, "unknown flags 0x%x", p->flags);
     if (!(p->conv_tol >= 0) || !std::isfinite(p->conv_tol)) return fail(BL_E_INVAL, "conv_tol must be >= 0");
     if (p->reserved0) return fail(BL_E_INVAL, "reserved fields must be zero");
@@ -219,6 +219,7 @@ int bl::graph_create_ex(const bl_csr *csr, const bl_params *p, hipStream_t s, bo
     if (!out) return fail(BL_E_INVAL, "out is NULL");
     *out = nullptr;
     BL_TRY(check_params(p));
+    if (p->flags & BL_ADAPTIVE_STEP) return fail(BL_E_INVAL, "BL_ADAPTIVE_STEP is a bl_layout option");
     BL_TRY(check_csr(csr, p->flags, s));
     bl_graph *g = new bl_graph();
     g->async_mem = async_mem;
@@ -434,15 +435,66 @@ int bl_graph_profile_read(bl_graph *g, const char *kernel, double *total_ms, int
     return fail(BL_E_INVAL, "unknown kernel name '%s'", kernel);
 }
 
+// Hu's adaptive step (Hu 2005, the scheme Sec. 4.1 cites): one device run
+// per iteration on the resident graph, the step of the next iteration set
+// from the energies of the last two.
+static int run_adaptive(bl_graph *g, const bl_params *p, double *energy_out, bl_stats *st) {
+    const double t = p->step_decay;
+    double step = p->step0, e_prev = HUGE_VAL;
+    int progress = 0;
+    bl_stats acc{};
+    int rc = BL_OK;
+    for (int k = 0; k < p->iterations; ++k) {
+        g->p.step0 = step;                 // step_decay is 1 on this graph: iteration k runs at `step`
+        bl_stats s1{};
+        double e = 0.0;
+        rc = run_impl(g, 1, k, -1, &e, nullptr, nullptr, &s1);
+        if (rc != BL_OK && rc != BL_E_NONFINITE) return rc;
+        acc.iters_run += s1.iters_run;
+        acc.late_overflow = std::max(acc.late_overflow, s1.late_overflow);
+        acc.seconds += s1.seconds;
+        acc.node_visits += s1.node_visits;
+        acc.nonfinite_events += s1.nonfinite_events;
+        acc.energy_last = e;
+        if (energy_out) energy_out[k] = e;
+        if (st) *st = acc;
+        if (rc == BL_E_NONFINITE) return rc;
+        if (p->conv_tol > 0 && k >= 1 && std::fabs(e - e_prev) <= p->conv_tol * e_prev) break;
+        if (e < e_prev) {
+            if (++progress >= 5) {
+                progress = 0;
+                step /= t;
+            }
+        } else {
+            progress = 0;
+            step *= t;
+        }
+        e_prev = e;
+    }
+    if (st) *st = acc;
+    return BL_OK;
+}
+
 int bl_layout(const bl_csr *csr, const double *x0, const double *y0, const bl_params *p,
               void *hip_stream, double *x_out, double *y_out, double *energy_out, bl_stats *st) {
     if (!x0 || !y0 || !x_out || !y_out) return fail(BL_E_INVAL, "coordinate arrays are NULL");
+    if (!p) return fail(BL_E_INVAL, "params is NULL");
+    const bool adaptive = (p->flags & BL_ADAPTIVE_STEP) != 0;
+    if (adaptive && p->start_iter != 0) return fail(BL_E_INVAL, "BL_ADAPTIVE_STEP needs start_iter 0");
+    bl_params q = *p;
+    if (adaptive) {
+        q.flags &= ~(uint32_t)BL_ADAPTIVE_STEP;
+        q.step_decay = 1.0;
+        q.conv_tol = 0.0;
+    }
     bl_graph *g = nullptr;
-    BL_TRY(bl_graph_create(csr, p, hip_stream, &g));
+    BL_TRY(bl_graph_create(csr, &q, hip_stream, &g));
     const uint32_t cf = p->flags & BL_DEVICE_PTRS;
     int rc = bl_graph_set_coords(g, x0, y0, cf);
     int rc_run = BL_OK;
-    if (rc == BL_OK) rc_run = bl_graph_run(g, p->iterations, p->start_iter, -1, energy_out, nullptr, nullptr, st);
+    if (rc == BL_OK)
+        rc_run = adaptive ? run_adaptive(g, p, energy_out, st)
+                          : bl_graph_run(g, p->iterations, p->start_iter, -1, energy_out, nullptr, nullptr, st);
     if (rc == BL_OK && (rc_run == BL_OK || rc_run == BL_E_NONFINITE)) rc = bl_graph_get_coords(g, x_out, y_out, cf);
     char saved[512];
     std::strncpy(saved, g_err, sizeof saved);

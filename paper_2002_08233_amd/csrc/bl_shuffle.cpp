@@ -57,6 +57,7 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
     if (!p) return fail_code(BL_E_INVAL, "params is NULL");
     BL_TRY(params_check(p));
     if (p->flags & BL_DEVICE_PTRS) return fail_code(BL_E_INVAL, "bl_layout_shuffled takes host arrays");
+    if (p->flags & BL_ADAPTIVE_STEP) return fail_code(BL_E_INVAL, "BL_ADAPTIVE_STEP is a bl_layout option");
     if (!csr) return fail_code(BL_E_INVAL, "graph is NULL");
     BL_TRY(check_csr(csr, p->flags, (hipStream_t)hip_stream));
     const int n = csr->n;
