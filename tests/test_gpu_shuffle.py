@@ -90,3 +90,33 @@ def test_small_and_ragged(n, bs):
     xg, yg, eg, _ = api.layout_shuffled(g, x0, y0, p, seed=1)
     xo, yo, eo = oracle.layout_shuffled(g.rowptr, g.colidx, x0, y0, bs, 5, seed=1)
     assert np.allclose(xg, xo, atol=1e-9) and np.allclose(yg, yo, atol=1e-9) and np.allclose(eg, eo, rtol=1e-9)
+
+
+@pytest.mark.parametrize("mode", ["bh", "exact"])
+def test_full_size_rmat17_relabel(mode):
+    """rmat17 at its benchmark batch size: two shuffled iterations equal, bit
+    for bit, two ordinary one-iteration runs on the graph relabelled here with
+    numpy by the same permutations (drawn by the oracle's generator)."""
+    w = I.workload_rmat17(mode="bh")
+    g = w["graph"]
+    kw = dict(batch_size=256, mode=mode, theta=1.2)
+    xs, ys, es, st = api.layout_shuffled(g, w["x0"], w["y0"], api.params(iterations=2, **kw), seed=31)
+    x, y = w["x0"].copy(), w["y0"].copy()
+    rp = np.asarray(g.rowptr, np.int64)
+    ci = np.asarray(g.colidx, np.int64)
+    deg = np.diff(rp)
+    rows = np.repeat(np.arange(g.n), deg)
+    er = []
+    for k in range(2):
+        perm = oracle.batch_permutation(g.n, 31, k)
+        inv = np.empty(g.n, np.int64)
+        inv[perm] = np.arange(g.n)
+        r2, c2 = inv[rows], inv[ci]
+        order = np.lexsort((c2, r2))
+        g2 = I.Graph(g.n, np.concatenate([[0], np.cumsum(np.bincount(r2, minlength=g.n))]).astype(np.int32),
+                     c2[order].astype(np.int32))
+        xk, yk, ek, _ = api.layout(g2, x[perm], y[perm], api.params(iterations=1, start_iter=k, **kw))
+        x[perm], y[perm] = xk, yk
+        er.append(ek[0])
+    assert np.array_equal(xs, x) and np.array_equal(ys, y) and np.array_equal(es, np.array(er))
+    assert st["iters_run"] == 2 and st["nonfinite_events"] == 0
