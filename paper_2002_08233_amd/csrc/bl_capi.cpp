@@ -444,12 +444,16 @@ static int run_adaptive(bl_graph *g, const bl_params *p, double *energy_out, bl_
     int progress = 0;
     bl_stats acc{};
     int rc = BL_OK;
+    g->keep_next = true;   // exact mode: each run leaves the next one's prologue done
     for (int k = 0; k < p->iterations; ++k) {
         g->p.step0 = step;                 // step_decay is 1 on this graph: iteration k runs at `step`
         bl_stats s1{};
         double e = 0.0;
         rc = run_impl(g, 1, k, -1, &e, nullptr, nullptr, &s1);
-        if (rc != BL_OK && rc != BL_E_NONFINITE) return rc;
+        if (rc != BL_OK && rc != BL_E_NONFINITE) {
+            g->keep_next = false;
+            return rc;
+        }
         acc.iters_run += s1.iters_run;
         acc.late_overflow = std::max(acc.late_overflow, s1.late_overflow);
         acc.seconds += s1.seconds;
@@ -458,7 +462,10 @@ static int run_adaptive(bl_graph *g, const bl_params *p, double *energy_out, bl_
         acc.energy_last = e;
         if (energy_out) energy_out[k] = e;
         if (st) *st = acc;
-        if (rc == BL_E_NONFINITE) return rc;
+        if (rc == BL_E_NONFINITE) {
+            g->keep_next = false;
+            return rc;
+        }
         if (p->conv_tol > 0 && k >= 1 && std::fabs(e - e_prev) <= p->conv_tol * e_prev) break;
         if (e < e_prev) {
             if (++progress >= 5) {
@@ -471,6 +478,7 @@ static int run_adaptive(bl_graph *g, const bl_params *p, double *energy_out, bl_
         }
         e_prev = e;
     }
+    g->keep_next = false;
     if (st) *st = acc;
     return BL_OK;
 }

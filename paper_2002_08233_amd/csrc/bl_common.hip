@@ -53,6 +53,7 @@ double step_at(const bl_params &p, int k) {
 }
 
 int convert_coords_in(bl_graph *g, const double *x, const double *y) {
+    g->cont_iter = -1;
     const int blocks = (g->n + 255) / 256;
     if (g->aos)
         hipLaunchKernelGGL(coords_in_aos_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n, x, y, (float2 *)g->x);

@@ -1382,7 +1382,12 @@ struct ExactOps {
         const long long total = (stop_batch >= 0) ? (long long)(iters - 1) * nb + stop_batch + 1
                                                   : (long long)iters * nb;
         const int lastk = start + iters - 1;
-        BL_TRY(rows(g, 0, g->n, 1, start & 1, 1));
+        const bool cont = g->cont_iter == start;
+        g->cont_iter = -1;
+        // keep: the last iteration's panels also count toward iteration lastk+1
+        const bool keep = g->keep_next && stop_batch < 0 && g->p.conv_tol == 0;
+        const int next_bound = keep ? lastk + 1 : lastk;
+        if (!cont) BL_TRY(rows(g, 0, g->n, 1, start & 1, 1));
         auto fin_of = [&](long long e) {
             const int k = start + (int)(e / nb), b = (int)(e % nb);
             const bool probe = stop_batch >= 0 && e == total - 1;
@@ -1393,12 +1398,12 @@ struct ExactOps {
         // the rest as one persistent launch where the device may be held
         if (stop_batch < 0 && nb > 1 && total > 1 && total < (1ll << 30) && g->coop && !getenv("BL_EXACT_STEPWISE")) {
             int launched = 0;
-            BL_TRY(steps(g, 1, (int)total, start, lastk, launched));
-            if (launched) return BL_OK;
+            BL_TRY(steps(g, 1, (int)total, start, next_bound, launched));
+            if (launched) return keep ? keep_last_panel(g, lastk) : BL_OK;
         }
         for (long long e = 1; e < total; ++e) {
             const int pk = start + (int)((e - 1) / nb), pb = (int)((e - 1) % nb);
-            const int do_next = pk < lastk ? 1 : 0;
+            const int do_next = pk < next_bound ? 1 : 0;
             if (nb > 1) {
                 BL_TRY(step(g, pb, pk & 1, do_next, fin_of(e)));
             } else {
@@ -1406,6 +1411,15 @@ struct ExactOps {
                 BL_TRY(finalize(g, fin_of(e)));
             }
         }
+        return keep ? keep_last_panel(g, lastk) : BL_OK;
+    }
+
+    // The panel of the last batch moved in iteration lastk, added toward
+    // iteration lastk+1 (the step a longer run would take next, without its
+    // finish); the next run may then start at lastk+1 without its prologue.
+    static int keep_last_panel(bl_graph *g, int lastk) {
+        BL_TRY(step(g, g->nb - 1, lastk & 1, 1, no_fin()));
+        g->cont_iter = lastk + 1;
         return BL_OK;
     }
 
@@ -1601,6 +1615,7 @@ static bool use_one_wg(const bl_graph *g, int stop_batch) {
 
 int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch) {
     if (iters > 0 && use_one_wg(g, stop_batch)) {
+        g->cont_iter = -1;
         const int nt = g->n >= 1024 ? 1024 : (g->n >= 512 ? 512 : 256);
         int slot;
         BL_TRY(prof_begin(g, PK_GRAPH, &slot));
@@ -1614,6 +1629,7 @@ int exact_run(bl_graph *g, int iters, int start_iter, int stop_batch) {
 }
 
 int exact_forces(bl_graph *g, int batch) {
+    g->cont_iter = -1;
     if (model_general(g->p)) return exact_forces_model(g, batch);
     if (g->fp64) return ExactOps<double, false, 0>::forces(g, batch);
     if (g->p.precision == BL_FP32_PLAIN) return ExactOps<float, false, 0>::forces(g, batch);

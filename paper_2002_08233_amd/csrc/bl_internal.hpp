@@ -139,6 +139,13 @@ struct bl_graph {
     void *x = nullptr;          // device coordinates: float/double x[n] (exact), or float2 xy[n] (BH)
     void *y = nullptr;          // y[n] (exact mode only)
     double *erow = nullptr;     // [n] per-vertex |f|^2 of the current iteration
+    // Exact mode, multi-workgroup path: a run that ends with keep_next set
+    // also adds the last iteration's panels toward the next iteration, and
+    // cont_iter records that iteration, so a run starting there skips its
+    // prologue (the same sums, already in place).  Anything else that runs
+    // or writes coordinates resets cont_iter to -1.
+    int cont_iter = -1;
+    bool keep_next = false;
     double *energy = nullptr;   // [energy_cap] per-iteration energies
     int energy_cap = 0;
     double *fout = nullptr;     // [2 * BS] forces of a stopped batch (FP64)

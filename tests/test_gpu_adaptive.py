@@ -68,3 +68,21 @@ def test_unit_factor_is_the_fixed_step_run():
                                                      adaptive_step=True))
     xb, yb, eb, _ = api.layout(g, x0, y0, api.params(batch_size=128, iterations=8, step0=0.2, step_decay=1.0))
     assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
+
+
+@pytest.mark.parametrize("precision,model,bs,stepwise", [
+    ("fp32_kahan", (2, -1), 96, False), ("fp32", (2, -1), 96, False), ("fp64", (2, -1), 96, False),
+    ("fp32_kahan", (1, -1), 96, False), ("fp32_kahan", (2, -1), 96, True), ("fp32_kahan", (2, -1), 2048, False)])
+def test_multi_wg_runs_chain_bitwise(monkeypatch, precision, model, bs, stepwise):
+    """The multi-workgroup exact path: with t = 1 the adaptive driver's chain
+    of one-iteration runs (each leaving the next one's prologue in place)
+    gives the bits of one 6-iteration run.  Ragged batches (1600 = 16 x 96 +
+    64), FP32 and FP64, a general model, the step-by-step path, one batch."""
+    if stepwise:
+        monkeypatch.setenv("BL_EXACT_STEPWISE", "1")
+    g = I.grid(40, 40)
+    x0, y0 = near_grid_init(40, 40)
+    kw = dict(batch_size=bs, step0=0.2, step_decay=1.0, multi_wg=True, precision=precision, model=model)
+    xa, ya, ea, _ = api.layout(g, x0, y0, api.params(iterations=6, adaptive_step=True, **kw))
+    xb, yb, eb, _ = api.layout(g, x0, y0, api.params(iterations=6, **kw))
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
