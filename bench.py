@@ -188,7 +188,7 @@ def greedy_report(api, w, p, steps, energy_random):
 
 
 def shuffle_report(api, w, p, steps, seed=2020):
-    """Randomised minibatches (Sec. 4.2) for `steps` iterations from the
+    """Randomised minibatches (Sec. 4.3.3) for `steps` iterations from the
     workload's start through bl_layout_shuffled, which relabels and uploads
     the graph every iteration, beside bl_layout from the same host arrays for
     the same iterations (both end to end, host arrays in and out)."""

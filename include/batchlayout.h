@@ -65,7 +65,7 @@ extern "C" {
                                      step kernels (small graphs otherwise run in
                                      one workgroup); the result is the same bits */
 #define BL_ADAPTIVE_STEP     16u  /* bl_layout only: the adaptive step of Hu
-                                     (2005), cited in Sec. 4.1, replaces the
+                                     (2005), cited in Sec. 4.3.5, replaces the
                                      fixed decay (see bl_layout)                */
 
 typedef struct {
@@ -157,7 +157,7 @@ int bl_layout(const bl_csr *g, const double *x0, const double *y0, const bl_para
               bl_stats *stats);
 
 /* ------------------------------------------- randomised minibatches
- * bl_layout with the batch randomisation of Sec. 4.2: in iteration k the
+ * bl_layout with the batch randomisation of Sec. 4.3.3: in iteration k the
  * minibatches are the consecutive runs of p->batch_size entries of a
  * permutation pi_k of the vertex ids (the last run may be shorter), processed
  * in that order, each with the usual Jacobi-within / Gauss-Seidel-across

@@ -264,7 +264,7 @@ def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=
 
 
 def hu_step_update(step, progress, e, e_prev, t):
-    """One update of Hu's adaptive step (Hu 2005, the scheme Sec. 4.1 cites):
+    """One update of Hu's adaptive step (Hu 2005, the scheme Sec. 4.3.5 cites):
     an energy drop advances a progress count, and the fifth in a row resets
     it and grows the step by 1/t; any other outcome resets the count and
     shrinks the step by t.  Returns (step, progress)."""
@@ -313,7 +313,7 @@ def splitmix64(state: int) -> int:
 
 
 def batch_permutation(n: int, seed: int, k: int) -> np.ndarray:
-    """The vertex order of iteration k under batch randomisation (Sec. 4.2;
+    """The vertex order of iteration k under batch randomisation (Sec. 4.3.3;
     the paper fixes no generator, so this is the library's documented one):
     Durstenfeld's Fisher-Yates shuffle of 0..n-1, for i = n-1 down to 1
     swapping positions i and u mod (i+1), u = the (c+1)-th SplitMix64 output
@@ -343,7 +343,7 @@ def _relabel(rowptr, colidx, perm):
 
 def layout_shuffled(rowptr, colidx, x0, y0, bs, iters, seed, start_iter=0, mode="exact", conv_tol=0.0,
                     **kw):
-    """BatchLayout with randomised minibatches (Sec. 4.2): iteration k takes
+    """BatchLayout with randomised minibatches (Sec. 4.3.3): iteration k takes
     its batches as consecutive runs of batch_permutation(n, seed, k).  Written
     as the ordinary run of one iteration (layout_exact or layout_bh, with the
     iteration's own step length) on the graph relabelled so that those runs

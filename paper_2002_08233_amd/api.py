@@ -124,7 +124,7 @@ def layout(graph, x0, y0, p: Params, stream=None, energy=True):
 
 
 def layout_shuffled(graph, x0, y0, p: Params, seed: int, stream=None):
-    """Run p.iterations with randomised minibatches (Sec. 4.2): in iteration k
+    """Run p.iterations with randomised minibatches (Sec. 4.3.3): in iteration k
     the batches are consecutive runs of a permutation drawn from (seed, k).
     Host arrays only.  Returns (x, y, energy, stats)."""
     lib = load()

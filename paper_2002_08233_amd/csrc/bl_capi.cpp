@@ -435,7 +435,7 @@ int bl_graph_profile_read(bl_graph *g, const char *kernel, double *total_ms, int
     return fail(BL_E_INVAL, "unknown kernel name '%s'", kernel);
 }
 
-// Hu's adaptive step (Hu 2005, the scheme Sec. 4.1 cites): one device run
+// Hu's adaptive step (Hu 2005, the scheme Sec. 4.3.5 cites): one device run
 // per iteration on the resident graph, the step of the next iteration set
 // from the energies of the last two.
 static int run_adaptive(bl_graph *g, const bl_params *p, double *energy_out, bl_stats *st) {

@@ -1,4 +1,4 @@
-// Randomised minibatches (Sec. 4.2, batch randomisation), a host driver of the
+// Randomised minibatches (Sec. 4.3.3, batch randomisation), a host driver of the
 // library around the ordinary single-graph path.
 //
 // In iteration k the minibatches are consecutive runs of BS vertices of a

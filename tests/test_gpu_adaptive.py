@@ -1,4 +1,4 @@
-"""Hu's adaptive step (cited in Sec. 4.1) on the GPU against the oracle.  The
+"""Hu's adaptive step (cited in Sec. 4.3.5) on the GPU against the oracle.  The
 step decisions compare consecutive energies; every case here keeps them at
 least 0.5% apart in the oracle's run, far above FP32 rounding, so both sides
 take the same decisions."""

@@ -1,4 +1,4 @@
-"""Randomised minibatches (Sec. 4.2) on the GPU against the oracle's
+"""Randomised minibatches (Sec. 4.3.3) on the GPU against the oracle's
 shuffled run: the same permutations drawn on both sides from (seed, k)."""
 import numpy as np
 import pytest

@@ -1,5 +1,5 @@
-"""Pins of the batch-randomisation oracle (Sec. 4.2) and of Hu's adaptive step
-(cited in Sec. 4.1).  Batch order: the generator against
+"""Pins of the batch-randomisation oracle (Sec. 4.3.3) and of Hu's adaptive step
+(cited in Sec. 4.3.5).  Batch order: the generator against
 published outputs, the shuffle's uniformity, and the shuffled run against a
 brute-force statement of randomised minibatches on the original labels."""
 import collections
