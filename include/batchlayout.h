@@ -97,7 +97,7 @@ typedef struct {
                                 | BL_ADAPTIVE_STEP                               */
     int32_t reserved0;       /* must be zero                                     */
     double conv_tol;         /* >= 0; 0 = off.  The energy stopping rule of
-                                Sec. 4.3 read as a relative change: after an
+                                Sec. 4.5 read as a relative change: after an
                                 iteration k that is not the run's first, stop
                                 when |E_k - E_{k-1}| <= conv_tol * E_{k-1}; the
                                 layout is the one after iteration k and

@@ -33,7 +33,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C, no fast-math, no FMA contraction)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
                                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -54,6 +54,9 @@ def _load():
     lib.orc_layout_exact_ar.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
                                         C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
                                         C.c_int, C.c_int, C.c_int, _f64p]
+    lib.orc_layout_exact_ord.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
+                                         C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                         C.c_int, C.c_int, C.c_int, C.c_void_p, _f64p]
     lib.orc_step_at.argtypes = [C.c_double, C.c_double, C.c_int]
     lib.orc_step_at.restype = C.c_double
     lib.orc_layout_exact.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
@@ -71,6 +74,13 @@ def _load():
     lib.orc_forces_bh.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_void_p, C.c_int, C.c_int,
                                   C.c_double, C.c_double, C.c_double, C.c_int,
                                   _f64p, _f64p, _f64p, _f64p, _f64p, _i64p, _i32p]
+    lib.orc_forces_bh_ar.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_void_p, C.c_int, C.c_int,
+                                     C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                     _f64p, _f64p, _f64p, _f64p, _f64p, _i64p, _i32p]
+    lib.orc_layout_bh_ord.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
+                                      C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _f64p,
+                                      C.c_void_p, C.c_void_p, C.POINTER(C.c_long)]
     lib.orc_layout_bh.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_int, C.c_int,
                                   C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.c_int, C.c_int, _f64p, C.c_void_p, C.c_void_p,
@@ -82,9 +92,23 @@ def _load():
     lib.orc_stress.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_void_p,
                                C.POINTER(C.c_double)]
     lib.orc_stress.restype = C.c_double
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_get_threads.restype = C.c_int
     lib.orc_greedy_init.argtypes = [C.c_int, _i32p, _i32p, C.c_int, _f64p, _f64p, _f64p, _f64p, _i32p]
     _lib = lib
     return lib
+
+
+def set_threads(t: int) -> int:
+    """Threads for the oracle's parallel loops (t <= 0: one per host core).
+    Results do not depend on it.  Returns the count now in effect."""
+    lib = _load()
+    lib.orc_set_threads(int(t))
+    return lib.orc_get_threads()
+
+
+def threads() -> int:
+    return _load().orc_get_threads()
 
 
 def _csr(rowptr, colidx):
@@ -135,23 +159,34 @@ def forces_exact(rowptr, colidx, x, y, i0, i1, K=1.0, R=1.0, repulse_adjacent=Tr
 
 
 def _converged(e, conv_tol):
-    """The energy stopping rule (Sec. 4.3), read as a relative change: after
+    """The energy stopping rule (Sec. 4.5), read as a relative change: after
     an iteration that is not the run's first, stop when |E_k - E_{k-1}| <=
     conv_tol * E_{k-1}."""
     return conv_tol > 0 and len(e) >= 2 and abs(e[-1] - e[-2]) <= conv_tol * e[-2]
 
 
+def _order_arg(order, n):
+    if order is None:
+        return None, None
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    if len(o) != n or not np.array_equal(np.sort(o), np.arange(n)):
+        raise ValueError("order must be a permutation of 0..n-1")
+    return o, o.ctypes.data_as(C.c_void_p)
+
+
 def layout_exact(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=0.999,
-                 K=1.0, R=1.0, repulse_adjacent=True, stop_batch=-1, conv_tol=0.0, model=(2, -1)):
+                 K=1.0, R=1.0, repulse_adjacent=True, stop_batch=-1, conv_tol=0.0, model=(2, -1),
+                 order=None):
     """Exact BatchLayout (Alg. 2 semantics) with the (a, r) model of Sec. 2.2.
-    Returns (x, y, energy per iteration); with conv_tol > 0 the run ends where
-    the energy stopping rule holds."""
+    order: a permutation whose runs of bs entries are the batches (default:
+    consecutive ids).  Returns (x, y, energy per iteration); with conv_tol > 0
+    the run ends where the energy stopping rule holds."""
     if conv_tol > 0:
         assert stop_batch < 0
         x, y, es = x0, y0, []
         for t in range(iters):
             x, y, e = layout_exact(rowptr, colidx, x, y, bs, 1, start_iter + t, step0, decay, K, R,
-                                   repulse_adjacent, model=model)
+                                   repulse_adjacent, model=model, order=order)
             es.append(e[0])
             if _converged(es, conv_tol):
                 break
@@ -162,8 +197,9 @@ def layout_exact(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, dec
     x = _f64(x0).copy()
     y = _f64(y0).copy()
     e = np.zeros(max(iters, 1))
-    rc = lib.orc_layout_exact_ar(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R,
-                                 int(repulse_adjacent), int(model[0]), int(model[1]), stop_batch, e)
+    keep, optr = _order_arg(order, n)
+    rc = lib.orc_layout_exact_ord(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R,
+                                  int(repulse_adjacent), int(model[0]), int(model[1]), stop_batch, optr, e)
     if rc != 0:
         raise ValueError("orc_layout_exact failed (%d)" % rc)
     return x, y, e[:iters]
@@ -208,8 +244,10 @@ class Tree:
 
 
 def forces_bh(rowptr, colidx, x, y, tree: Tree, i0, i1, K=1.0, R=1.0, theta=1.2,
-              leaf_live=True) -> Forces:
-    """Barnes-Hut forces on [i0, i1): CSR attraction + tree repulsion (Alg. S2, S3)."""
+              leaf_live=True, model=(2, -1)) -> Forces:
+    """Barnes-Hut forces on [i0, i1): CSR attraction + tree repulsion (Alg. S2,
+    S3) under the (a, r) model of Sec. 2.2 (an accepted cell adds count times
+    the repulsion from its centroid)."""
     lib = _load()
     rp, ci = _csr(rowptr, colidx)
     n = len(rp) - 1
@@ -217,16 +255,18 @@ def forces_bh(rowptr, colidx, x, y, tree: Tree, i0, i1, K=1.0, R=1.0, theta=1.2,
     out = [np.zeros(max(m, 1)) for _ in range(5)]
     vis = np.zeros(max(m, 1), np.int64)
     tie = np.zeros(max(m, 1), np.int32)
-    rc = lib.orc_forces_bh(n, rp, ci, _f64(x), _f64(y), tree.h, i0, i1, K, R, theta,
-                           int(leaf_live), *out, vis, tie)
+    rc = lib.orc_forces_bh_ar(n, rp, ci, _f64(x), _f64(y), tree.h, i0, i1, K, R, theta,
+                              int(leaf_live), int(model[0]), int(model[1]), *out, vis, tie)
     if rc != 0:
         raise ValueError("orc_forces_bh: bad arguments")
     return Forces(*[o[:m] for o in out], visits=vis[:m], near_tie=tie[:m].astype(bool))
 
 
 def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=0.999,
-              K=1.0, R=1.0, theta=1.2, leaf_live=True, stop_batch=-1, want_snapshot=False, conv_tol=0.0):
-    """BatchLayoutBH (Alg. S3 with the step decay of Alg. 2).
+              K=1.0, R=1.0, theta=1.2, leaf_live=True, stop_batch=-1, want_snapshot=False, conv_tol=0.0,
+              model=(2, -1), order=None):
+    """BatchLayoutBH (Alg. S3 with the step decay of Alg. 2) under the (a, r)
+    model; order as in layout_exact.
 
     Returns (x, y, energy, visits) or, with want_snapshot, also the snapshot
     (sx, sy) taken at the start of the last iteration.  With conv_tol > 0 the
@@ -236,7 +276,7 @@ def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=
         x, y, es, vt = x0, y0, [], 0
         for t in range(iters):
             x, y, e, v = layout_bh(rowptr, colidx, x, y, bs, 1, start_iter + t, step0, decay, K, R, theta,
-                                   leaf_live)
+                                   leaf_live, model=model, order=order)
             es.append(e[0])
             vt += v
             if _converged(es, conv_tol):
@@ -251,11 +291,12 @@ def layout_bh(rowptr, colidx, x0, y0, bs, iters, start_iter=0, step0=1.0, decay=
     sx = np.zeros(n)
     sy = np.zeros(n)
     vt = C.c_long(0)
-    rc = lib.orc_layout_bh(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R, theta,
-                           int(leaf_live), stop_batch, e,
-                           sx.ctypes.data_as(C.c_void_p) if want_snapshot else None,
-                           sy.ctypes.data_as(C.c_void_p) if want_snapshot else None,
-                           C.byref(vt))
+    keep, optr = _order_arg(order, n)
+    rc = lib.orc_layout_bh_ord(n, rp, ci, x, y, bs, iters, start_iter, step0, decay, K, R, theta,
+                               int(leaf_live), int(model[0]), int(model[1]), stop_batch, optr, e,
+                               sx.ctypes.data_as(C.c_void_p) if want_snapshot else None,
+                               sy.ctypes.data_as(C.c_void_p) if want_snapshot else None,
+                               C.byref(vt))
     if rc != 0:
         raise ValueError("orc_layout_bh failed (%d)" % rc)
     if want_snapshot:
@@ -327,28 +368,13 @@ def batch_permutation(n: int, seed: int, k: int) -> np.ndarray:
     return np.array(perm, dtype=np.int64)
 
 
-def _relabel(rowptr, colidx, perm):
-    """The graph with vertex perm[q] renamed q (rows sorted again)."""
-    rp = np.asarray(rowptr, dtype=np.int64)
-    ci = np.asarray(colidx, dtype=np.int64)
-    n = len(rp) - 1
-    inv = np.empty(n, dtype=np.int64)
-    inv[perm] = np.arange(n)
-    rows = [np.sort(inv[ci[rp[v]:rp[v + 1]]]) for v in perm]
-    rp2 = np.zeros(n + 1, dtype=np.int64)
-    rp2[1:] = np.cumsum([len(r) for r in rows])
-    ci2 = np.concatenate(rows) if len(ci) else np.zeros(0, dtype=np.int64)
-    return rp2.astype(np.int32), ci2.astype(np.int32)
-
-
 def layout_shuffled(rowptr, colidx, x0, y0, bs, iters, seed, start_iter=0, mode="exact", conv_tol=0.0,
                     **kw):
     """BatchLayout with randomised minibatches (Sec. 4.3.3): iteration k takes
-    its batches as consecutive runs of batch_permutation(n, seed, k).  Written
-    as the ordinary run of one iteration (layout_exact or layout_bh, with the
-    iteration's own step length) on the graph relabelled so that those runs
-    are the id ranges; the coordinates are mapped back after each iteration.
-    Returns (x, y, energy per iteration)."""
+    its batches as the consecutive runs of bs entries of
+    batch_permutation(n, seed, k), on the original labels, with the usual
+    Jacobi-within and Gauss-Seidel-across semantics and the iteration's own
+    step length.  Returns (x, y, energy per iteration)."""
     x = _f64(x0).copy()
     y = _f64(y0).copy()
     n = len(x)
@@ -356,13 +382,10 @@ def layout_shuffled(rowptr, colidx, x0, y0, bs, iters, seed, start_iter=0, mode=
     for t in range(iters):
         k = start_iter + t
         perm = batch_permutation(n, seed, k)
-        rp2, ci2 = _relabel(rowptr, colidx, perm)
         if mode == "exact":
-            xs, ys, e = layout_exact(rp2, ci2, x[perm], y[perm], bs, 1, k, **kw)
+            x, y, e = layout_exact(rowptr, colidx, x, y, bs, 1, k, order=perm, **kw)
         else:
-            xs, ys, e, _ = layout_bh(rp2, ci2, x[perm], y[perm], bs, 1, k, **kw)
-        x[perm] = xs
-        y[perm] = ys
+            x, y, e, _ = layout_bh(rowptr, colidx, x, y, bs, 1, k, order=perm, **kw)
         es.append(e[0])
         if _converged(es, conv_tol):
             break

@@ -33,13 +33,41 @@
  *    traversal from a start vertex at (0, 0); each popped vertex places its
  *    unvisited neighbours on the unit circle around itself, at angles that
  *    advance by 360 / degree degrees, with the paper's constant 3.1416 for pi.
+ *
+ * Threads: the per-vertex force loops of a batch and the per-pivot BFS of the
+ * stress run on OpenMP threads (orc_set_threads).  Every vertex's sum, and
+ * every pivot's partial sums, keep their one sequential order, and pivot
+ * partials are added in pivot order, so the results are the same bits at any
+ * thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_LEVELS 16
+
+/* Threads for the parallel loops (<= 0: the OpenMP default). */
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(t > 0 ? t : omp_get_num_procs());
+#else
+    (void)t;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------- pair terms
  * The (a,r)-energy model of Sec. 2.2: attraction magnitude d^a / K and
@@ -84,11 +112,6 @@ static void pair_repulsion_ar(double dx, double dy, double K, double R, int r, d
     *ty = f * dy / d;
 }
 
-static void pair_repulsion(double dx, double dy, double K, double R, double *tx, double *ty)
-{
-    pair_repulsion_ar(dx, dy, K, R, -1, tx, ty);
-}
-
 /* ------------------------------------------------------------- exact forces
  * Net force on vertex i from the current coordinates (Sec. 2.2, the combined
  * force f(i,c); Algorithm 2 walks j = 0..n-1 and the sorted CSR row in step).
@@ -129,6 +152,7 @@ int orc_forces_exact_ar(int n, const int *rowptr, const int *colidx,
                         double *ax, double *ay, double *rx, double *ry, double *scale)
 {
     if (n < 1 || i0 < 0 || i1 > n || i0 > i1) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int i = i0; i < i1; ++i)
         force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent, a, r,
                         &ax[i - i0], &ay[i - i0], &rx[i - i0], &ry[i - i0],
@@ -146,21 +170,32 @@ int orc_forces_exact(int n, const int *rowptr, const int *colidx,
 }
 
 /* Move the vertices of one batch along their normalised net forces
- * (Algorithm 2, the update loop after the parallel force loop). */
-static double move_batch(int i0, int i1, double *x, double *y,
+ * (Algorithm 2, the update loop after the parallel force loop).  The batch
+ * is members[0..m) (consecutive ids, or a run of a permutation). */
+static double move_batch(const int *members, int m, double *x, double *y,
                          const double *fx, const double *fy, double step)
 {
     double energy = 0.0;
-    for (int i = i0; i < i1; ++i) {
-        double f2 = fx[i - i0] * fx[i - i0] + fy[i - i0] * fy[i - i0];
+    for (int q = 0; q < m; ++q) {
+        int i = members[q];
+        double f2 = fx[q] * fx[q] + fy[q] * fy[q];
         double norm = sqrt(f2);
         if (norm > 0.0) {
-            x[i] += step * fx[i - i0] / norm;
-            y[i] += step * fy[i - i0] / norm;
+            x[i] += step * fx[q] / norm;
+            y[i] += step * fy[q] / norm;
         }
         energy += f2;
     }
     return energy;
+}
+
+/* The members of batch b: order[b*bs ...] when an order is given (batch
+ * randomisation, Sec. 4.3.3), else the id range [b*bs, min((b+1)*bs, n)). */
+static int batch_members(int n, int bs, int b, const int *order, int *members)
+{
+    int i0 = b * bs, i1 = i0 + bs < n ? i0 + bs : n;
+    for (int q = i0; q < i1; ++q) members[q - i0] = order ? order[q] : q;
+    return i1 - i0;
 }
 
 /* Step length at iteration k: Step_0 multiplied by the decay once per
@@ -175,36 +210,49 @@ double orc_step_at(double step0, double decay, int k)
 /* Exact BatchLayout (Algorithm 2 without the cache blocking).
  * Runs iterations [start_iter, start_iter + iters).  When stop_batch >= 0 the
  * last iteration stops after that many batches (used to dump a mid-iteration
- * state).  energy[t] receives the energy of iteration start_iter + t. */
-int orc_layout_exact_ar(int n, const int *rowptr, const int *colidx,
-                        double *x, double *y, int bs, int iters, int start_iter,
-                        double step0, double decay, double K, double R,
-                        int repulse_adjacent, int a, int r, int stop_batch, double *energy)
+ * state).  energy[t] receives the energy of iteration start_iter + t.
+ * order (may be NULL): a permutation of the ids whose consecutive runs of bs
+ * entries are the batches of every iteration run by this call. */
+int orc_layout_exact_ord(int n, const int *rowptr, const int *colidx,
+                         double *x, double *y, int bs, int iters, int start_iter,
+                         double step0, double decay, double K, double R,
+                         int repulse_adjacent, int a, int r, int stop_batch,
+                         const int *order, double *energy)
 {
     if (n < 1 || bs < 1 || iters < 0) return -1;
     int nb = (n + bs - 1) / bs;
     double *fx = malloc(sizeof(double) * bs), *fy = malloc(sizeof(double) * bs);
-    double *ax = malloc(sizeof(double) * bs), *ay = malloc(sizeof(double) * bs);
-    if (!fx || !fy || !ax || !ay) { free(fx); free(fy); free(ax); free(ay); return -2; }
+    int *mem = malloc(sizeof(int) * bs);
+    if (!fx || !fy || !mem) { free(fx); free(fy); free(mem); return -2; }
     for (int t = 0; t < iters; ++t) {
         double step = orc_step_at(step0, decay, start_iter + t);
         double e = 0.0;
         int last = (t == iters - 1 && stop_batch >= 0) ? stop_batch : nb;
         for (int b = 0; b < last; ++b) {
-            int i0 = b * bs, i1 = i0 + bs < n ? i0 + bs : n;
-            for (int i = i0; i < i1; ++i) {
-                double rx, ry;
-                force_exact_one(n, rowptr, colidx, x, y, i, K, R, repulse_adjacent, a, r,
-                                &ax[i - i0], &ay[i - i0], &rx, &ry, NULL);
-                fx[i - i0] = ax[i - i0] + rx;
-                fy[i - i0] = ay[i - i0] + ry;
+            int m = batch_members(n, bs, b, order, mem);
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int q = 0; q < m; ++q) {
+                double ax, ay, rx, ry;
+                force_exact_one(n, rowptr, colidx, x, y, mem[q], K, R, repulse_adjacent, a, r,
+                                &ax, &ay, &rx, &ry, NULL);
+                fx[q] = ax + rx;
+                fy[q] = ay + ry;
             }
-            e += move_batch(i0, i1, x, y, fx, fy, step);
+            e += move_batch(mem, m, x, y, fx, fy, step);
         }
         if (energy) energy[t] = e;
     }
-    free(fx); free(fy); free(ax); free(ay);
+    free(fx); free(fy); free(mem);
     return 0;
+}
+
+int orc_layout_exact_ar(int n, const int *rowptr, const int *colidx,
+                        double *x, double *y, int bs, int iters, int start_iter,
+                        double step0, double decay, double K, double R,
+                        int repulse_adjacent, int a, int r, int stop_batch, double *energy)
+{
+    return orc_layout_exact_ord(n, rowptr, colidx, x, y, bs, iters, start_iter, step0, decay, K, R,
+                                repulse_adjacent, a, r, stop_batch, NULL, energy);
 }
 
 int orc_layout_exact(int n, const int *rowptr, const int *colidx,
@@ -419,6 +467,7 @@ typedef struct {
     int i, posi;
     double xi, yi;
     double K, R, theta;
+    int r;            /* repulsion exponent of the (a, r) model */
     int leaf_live;
     double rx, ry, scale;
     long visits;
@@ -428,7 +477,7 @@ typedef struct {
 static void add_rep(walk_ctx *w, double px, double py, double mult)
 {
     double tx, ty;
-    pair_repulsion(px - w->xi, py - w->yi, w->K, w->R, &tx, &ty);
+    pair_repulsion_ar(px - w->xi, py - w->yi, w->K, w->R, w->r, &tx, &ty);
     w->rx += mult * tx;
     w->ry += mult * ty;
     w->scale += mult * sqrt(tx * tx + ty * ty);
@@ -469,66 +518,90 @@ static void walk(walk_ctx *w, int id)
     for (int c = 0; c < nd->nchild; ++c) walk(w, nd->child[c]);
 }
 
-/* Barnes-Hut forces for vertices [i0, i1) (Algorithm S3, force loop):
- * attraction over CSR neighbours with live coordinates, repulsion through the
- * tree of the snapshot.  leaf_live = 1 makes leaves use live coordinates. */
+/* Barnes-Hut force on vertex i (Algorithm S3, force loop): attraction over
+ * its CSR neighbours with live coordinates, repulsion through the tree of
+ * the snapshot, under the (a, r) model (an accepted cell adds count times the
+ * repulsion from its centroid).  leaf_live = 1 makes leaves use live
+ * coordinates. */
+static void force_bh_one(const int *rowptr, const int *colidx, const double *x, const double *y,
+                         const otree *t, int i, double K, double R, double theta, int leaf_live,
+                         int a, int r, double *ax, double *ay, double *rx, double *ry,
+                         double *scale, long *visits, int *near_tie)
+{
+    double sax = 0, say = 0, s = 0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        int j = colidx[k];
+        double tx, ty;
+        pair_attraction_ar(x[j] - x[i], y[j] - y[i], K, a, &tx, &ty);
+        sax += tx; say += ty;
+        s += sqrt(tx * tx + ty * ty);
+    }
+    walk_ctx w;
+    memset(&w, 0, sizeof w);
+    w.t = t; w.x = x; w.y = y; w.i = i; w.posi = t->pos[i];
+    w.xi = x[i]; w.yi = y[i];
+    w.K = K; w.R = R; w.theta = theta; w.r = r; w.leaf_live = leaf_live;
+    walk(&w, 0);
+    *ax = sax; *ay = say;
+    *rx = w.rx; *ry = w.ry;
+    if (scale) *scale = s + w.scale;
+    if (visits) *visits = w.visits;
+    if (near_tie) *near_tie = w.near_tie;
+}
+
+/* Barnes-Hut forces for vertices [i0, i1) under the (a, r) model. */
+int orc_forces_bh_ar(int n, const int *rowptr, const int *colidx,
+                     const double *x, const double *y, void *tp, int i0, int i1,
+                     double K, double R, double theta, int leaf_live, int a, int r,
+                     double *ax, double *ay, double *rx, double *ry, double *scale,
+                     long *visits, int *near_tie)
+{
+    otree *t = (otree *)tp;
+    if (!t || t->n != n || i0 < 0 || i1 > n || i0 > i1) return -1;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = i0; i < i1; ++i)
+        force_bh_one(rowptr, colidx, x, y, t, i, K, R, theta, leaf_live, a, r,
+                     &ax[i - i0], &ay[i - i0], &rx[i - i0], &ry[i - i0],
+                     scale ? &scale[i - i0] : NULL, visits ? &visits[i - i0] : NULL,
+                     near_tie ? &near_tie[i - i0] : NULL);
+    return 0;
+}
+
 int orc_forces_bh(int n, const int *rowptr, const int *colidx,
                   const double *x, const double *y, void *tp, int i0, int i1,
                   double K, double R, double theta, int leaf_live,
                   double *ax, double *ay, double *rx, double *ry, double *scale,
                   long *visits, int *near_tie)
 {
-    otree *t = (otree *)tp;
-    if (!t || t->n != n || i0 < 0 || i1 > n || i0 > i1) return -1;
-    for (int i = i0; i < i1; ++i) {
-        double sax = 0, say = 0, s = 0;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            int j = colidx[k];
-            double tx, ty;
-            pair_attraction_ar(x[j] - x[i], y[j] - y[i], K, 2, &tx, &ty);
-            sax += tx; say += ty;
-            s += sqrt(tx * tx + ty * ty);
-        }
-        walk_ctx w;
-        memset(&w, 0, sizeof w);
-        w.t = t; w.x = x; w.y = y; w.i = i; w.posi = t->pos[i];
-        w.xi = x[i]; w.yi = y[i];
-        w.K = K; w.R = R; w.theta = theta; w.leaf_live = leaf_live;
-        walk(&w, 0);
-        ax[i - i0] = sax; ay[i - i0] = say;
-        rx[i - i0] = w.rx; ry[i - i0] = w.ry;
-        if (scale) scale[i - i0] = s + w.scale;
-        if (visits) visits[i - i0] = w.visits;
-        if (near_tie) near_tie[i - i0] = w.near_tie;
-    }
-    return 0;
+    return orc_forces_bh_ar(n, rowptr, colidx, x, y, tp, i0, i1, K, R, theta, leaf_live, 2, -1,
+                            ax, ay, rx, ry, scale, visits, near_tie);
 }
 
-/* BatchLayoutBH (Algorithm S3) with the step decay of Algorithm 2.
- * When snap_x/snap_y are given they receive the snapshot of the last
- * (possibly partial, see stop_batch) iteration.  visits_total accumulates
- * the node visits of all force evaluations. */
-int orc_layout_bh(int n, const int *rowptr, const int *colidx,
-                  double *x, double *y, int bs, int iters, int start_iter,
-                  double step0, double decay, double K, double R, double theta,
-                  int leaf_live, int stop_batch, double *energy,
-                  double *snap_x, double *snap_y, long *visits_total)
+/* BatchLayoutBH (Algorithm S3) with the step decay of Algorithm 2, under the
+ * (a, r) model.  When snap_x/snap_y are given they receive the snapshot of
+ * the last (possibly partial, see stop_batch) iteration.  visits_total
+ * accumulates the node visits of all force evaluations.  order (may be
+ * NULL): a permutation whose runs of bs entries are the batches. */
+int orc_layout_bh_ord(int n, const int *rowptr, const int *colidx,
+                      double *x, double *y, int bs, int iters, int start_iter,
+                      double step0, double decay, double K, double R, double theta,
+                      int leaf_live, int a, int r, int stop_batch, const int *order, double *energy,
+                      double *snap_x, double *snap_y, long *visits_total)
 {
     if (n < 1 || bs < 1 || iters < 0 || theta < 0) return -1;
     int nb = (n + bs - 1) / bs;
-    double *ax = malloc(sizeof(double) * bs), *ay = malloc(sizeof(double) * bs);
-    double *rx = malloc(sizeof(double) * bs), *ry = malloc(sizeof(double) * bs);
     double *fx = malloc(sizeof(double) * bs), *fy = malloc(sizeof(double) * bs);
     long *vis = malloc(sizeof(long) * bs);
-    if (!ax || !ay || !rx || !ry || !fx || !fy || !vis) {
-        free(ax); free(ay); free(rx); free(ry); free(fx); free(fy); free(vis);
+    int *mem = malloc(sizeof(int) * bs);
+    if (!fx || !fy || !vis || !mem) {
+        free(fx); free(fy); free(vis); free(mem);
         return -2;
     }
     long vt = 0;
     int rc = 0;
     for (int t = 0; t < iters && rc == 0; ++t) {
         double step = orc_step_at(step0, decay, start_iter + t);
-        void *tree = orc_tree_build(n, x, y);
+        otree *tree = orc_tree_build(n, x, y);
         if (!tree) { rc = -2; break; }
         if (t == iters - 1 && snap_x && snap_y) {
             memcpy(snap_x, x, sizeof(double) * n);
@@ -537,22 +610,34 @@ int orc_layout_bh(int n, const int *rowptr, const int *colidx,
         double e = 0.0;
         int last = (t == iters - 1 && stop_batch >= 0) ? stop_batch : nb;
         for (int b = 0; b < last; ++b) {
-            int i0 = b * bs, i1 = i0 + bs < n ? i0 + bs : n;
-            orc_forces_bh(n, rowptr, colidx, x, y, tree, i0, i1, K, R, theta, leaf_live,
-                          ax, ay, rx, ry, NULL, vis, NULL);
-            for (int i = i0; i < i1; ++i) {
-                fx[i - i0] = ax[i - i0] + rx[i - i0];
-                fy[i - i0] = ay[i - i0] + ry[i - i0];
-                vt += vis[i - i0];
+            int m = batch_members(n, bs, b, order, mem);
+#pragma omp parallel for schedule(dynamic, 8)
+            for (int q = 0; q < m; ++q) {
+                double ax, ay, rx, ry;
+                force_bh_one(rowptr, colidx, x, y, tree, mem[q], K, R, theta, leaf_live, a, r,
+                             &ax, &ay, &rx, &ry, NULL, &vis[q], NULL);
+                fx[q] = ax + rx;
+                fy[q] = ay + ry;
             }
-            e += move_batch(i0, i1, x, y, fx, fy, step);
+            for (int q = 0; q < m; ++q) vt += vis[q];
+            e += move_batch(mem, m, x, y, fx, fy, step);
         }
         if (energy) energy[t] = e;
         orc_tree_free(tree);
     }
     if (visits_total) *visits_total = vt;
-    free(ax); free(ay); free(rx); free(ry); free(fx); free(fy); free(vis);
+    free(fx); free(fy); free(vis); free(mem);
     return rc;
+}
+
+int orc_layout_bh(int n, const int *rowptr, const int *colidx,
+                  double *x, double *y, int bs, int iters, int start_iter,
+                  double step0, double decay, double K, double R, double theta,
+                  int leaf_live, int stop_batch, double *energy,
+                  double *snap_x, double *snap_y, long *visits_total)
+{
+    return orc_layout_bh_ord(n, rowptr, colidx, x, y, bs, iters, start_iter, step0, decay, K, R, theta,
+                             leaf_live, 2, -1, stop_batch, NULL, energy, snap_x, snap_y, visits_total);
 }
 
 /* ------------------------------------------------------- quality measures */
@@ -608,33 +693,52 @@ double orc_stress(int n, const int *rowptr, const int *colidx,
                   const double *x, const double *y, int npivots, const int *pivots,
                   double *scale_out)
 {
-    int *dist = malloc(sizeof(int) * n), *queue = malloc(sizeof(int) * n);
-    if (!dist || !queue) { free(dist); free(queue); return -1.0; }
-    double A = 0.0, B = 0.0, N = 0.0;
     int np = pivots ? npivots : n;
-    for (int q = 0; q < np; ++q) {
-        int p = pivots ? pivots[q] : q;
-        for (int i = 0; i < n; ++i) dist[i] = -1;
-        int head = 0, tail = 0;
-        dist[p] = 0; queue[tail++] = p;
-        while (head < tail) {
-            int u = queue[head++];
-            for (int k = rowptr[u]; k < rowptr[u + 1]; ++k) {
-                int v = colidx[k];
-                if (dist[v] < 0) { dist[v] = dist[u] + 1; queue[tail++] = v; }
+    /* per-pivot partial sums, added in pivot order below */
+    double *pA = calloc(np > 0 ? np : 1, sizeof(double));
+    double *pB = calloc(np > 0 ? np : 1, sizeof(double));
+    double *pN = calloc(np > 0 ? np : 1, sizeof(double));
+    int failed = 0;
+    if (!pA || !pB || !pN) { free(pA); free(pB); free(pN); return -1.0; }
+#pragma omp parallel
+    {
+        int *dist = malloc(sizeof(int) * n), *queue = malloc(sizeof(int) * n);
+        if (!dist || !queue) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int q = 0; q < np; ++q) {
+            if (!dist || !queue) continue;
+            int p = pivots ? pivots[q] : q;
+            for (int i = 0; i < n; ++i) dist[i] = -1;
+            int head = 0, tail = 0;
+            dist[p] = 0; queue[tail++] = p;
+            while (head < tail) {
+                int u = queue[head++];
+                for (int k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+                    int v = colidx[k];
+                    if (dist[v] < 0) { dist[v] = dist[u] + 1; queue[tail++] = v; }
+                }
             }
+            double A = 0.0, B = 0.0, N = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (j == p || dist[j] <= 0) continue;
+                if (!pivots && j < p) continue;
+                double dij = dist[j];
+                double g = hypot(x[j] - x[p], y[j] - y[p]);
+                A += g / dij;
+                B += g * g / (dij * dij);
+                N += 1.0;
+            }
+            pA[q] = A; pB[q] = B; pN[q] = N;
         }
-        for (int j = 0; j < n; ++j) {
-            if (j == p || dist[j] <= 0) continue;
-            if (!pivots && j < p) continue;
-            double dij = dist[j];
-            double g = hypot(x[j] - x[p], y[j] - y[p]);
-            A += g / dij;
-            B += g * g / (dij * dij);
-            N += 1.0;
-        }
+        free(dist); free(queue);
     }
-    free(dist); free(queue);
+    double A = 0.0, B = 0.0, N = 0.0;
+    for (int q = 0; q < np; ++q) { A += pA[q]; B += pB[q]; N += pN[q]; }
+    free(pA); free(pB); free(pN);
+    if (failed) return -1.0;
     if (B == 0.0) { if (scale_out) *scale_out = 0.0; return N; }
     if (scale_out) *scale_out = A / B;
     return N - A * A / B;

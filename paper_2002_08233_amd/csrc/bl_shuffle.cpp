@@ -62,6 +62,19 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
     BL_TRY(check_csr(csr, p->flags, (hipStream_t)hip_stream));
     const int n = csr->n;
     const int32_t *rp = csr->rowptr, *ci = csr->colidx;
+    // The relabelling below reads the graph through its transpose and sizes
+    // each relabelled row by the old row's length.  That is the graph itself
+    // only for a symmetric CSR (BL_VALIDATE checks it in full); whatever the
+    // flags, every vertex's in-degree must equal its row length, so that the
+    // relabelled rows are filled exactly and never overrun.
+    {
+        std::vector<int64_t> indeg(n, 0);
+        for (int64_t e = 0; e < csr->nnz; ++e) ++indeg[ci[e]];
+        for (int i = 0; i < n; ++i)
+            if (indeg[i] != rp[i + 1] - rp[i])
+                return fail_code(BL_E_INVAL, "bl_layout_shuffled needs a symmetric CSR "
+                                             "(a vertex's in-degree differs from its row length)");
+    }
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(x0[i]) || !std::isfinite(y0[i]))
             return fail_code(BL_E_INVAL, "a start coordinate is not finite");

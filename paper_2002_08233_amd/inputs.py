@@ -200,6 +200,22 @@ def to_f32_representable(x: np.ndarray) -> np.ndarray:
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
 
+def stress_pivots(n: int, count: int = 1024, seed: int = 10):
+    """BFS sources of a sampled stress (reading R23): `count` ids drawn
+    uniformly with repetition from one seeded generator, or None (all pairs)
+    when n <= 65536 and no count is forced."""
+    return rng(seed).integers(0, n, count).astype(np.int32)
+
+
+def ulp_perturbed(x: np.ndarray, seed: int):
+    """A copy of x with one entry, chosen by the seed, moved up by one
+    float32 ulp (a start that differs from x in one coordinate by one ulp)."""
+    xp = np.array(x, dtype=np.float64, copy=True)
+    i = int(rng(seed).integers(0, len(xp)))
+    xp[i] = float(np.nextafter(np.float32(xp[i]), np.float32(np.inf)))
+    return xp, i
+
+
 # --------------------------------------------------------------------------
 # Workload recipes.  Each returns a dict with graph, x0, y0 and run knobs.
 

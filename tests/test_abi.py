@@ -224,6 +224,28 @@ def test_shuffled_layout_host_checks(lib):
     assert np.array_equal(xo, x) and np.array_equal(yo, y) and st.iters_run == 0
 
 
+@pytest.mark.parametrize("rows", [[[1], []], [[1, 2], [0], [0, 1]], [[2], [2], [0]]])
+def test_shuffled_layout_rejects_asymmetric_csr(lib, rows):
+    """An asymmetric CSR whose ids are in range (so the always-on checks pass)
+    is rejected by bl_layout_shuffled before any device work, with or without
+    BL_VALIDATE: its relabelling reads the graph through the transpose and
+    would otherwise write past the relabelled rows."""
+    from paper_2002_08233_amd import api, inputs, _lib
+    n = len(rows)
+    g = inputs.Graph(n, np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32),
+                     np.array(sum(rows, []), np.int32))
+    keep = api._Keep()
+    csr = api._csr(g, keep)
+    x = np.linspace(0.0, 1.0, n)
+    xo, yo = np.empty(n), np.empty(n)
+    for flags in (0, _lib.BL_VALIDATE):
+        p = api.params(iterations=1, batch_size=1)
+        p.flags |= flags
+        assert lib.bl_layout_shuffled(C.byref(csr), x.ctypes.data, x.ctypes.data, C.byref(p), 3, None,
+                                      xo.ctypes.data, yo.ctypes.data, None, None) == -1
+        assert "symmetric" in lib.bl_last_error().decode()
+
+
 def test_adaptive_step_is_a_layout_option(lib):
     """BL_ADAPTIVE_STEP: start_iter must be 0; the graph API, the batched call
     and the shuffled layout reject it (all before any device work)."""

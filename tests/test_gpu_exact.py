@@ -265,7 +265,7 @@ def test_hub_rows_one_workgroup_and_multi_workgroup_bitwise(precision, lit):
 @pytest.mark.parametrize("path", ["one_workgroup", "persistent", "stepwise"])
 def test_energy_stopping_rule(monkeypatch, path):
     """conv_tol ends the run where the energy's relative change first falls to
-    the tolerance (Sec. 4.3): the same iteration as the oracle, and the same
+    the tolerance (Sec. 4.5): the same iteration as the oracle, and the same
     bits as a plain run of that many iterations, on every exact path."""
     g = _rand_graph(900, 8.0 / 900, 77)
     x0, y0 = I.uniform_coords(g.n, 78)

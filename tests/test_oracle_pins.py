@@ -406,9 +406,10 @@ def test_bh_coincident_far_cell_is_k_times_single():
     assert single.rx[0] == pytest.approx(-10.0 / 125.0, rel=1e-14)
 
 
-def _py_bh_force(x, y, i, theta, K=1.0, R=1.0):
+def _py_bh_force(x, y, i, theta, K=1.0, R=1.0, r=-1):
     """Independent Barnes-Hut walk: cells found by recursive geometric
-    subdivision of the bounding square (no Morton keys)."""
+    subdivision of the bounding square (no Morton keys); repulsion magnitude
+    R K^2 d^r, an accepted cell counting once per member."""
     xs = x.astype(np.float32).astype(np.float64)
     ys = y.astype(np.float32).astype(np.float64)
     x0, y0 = xs.min(), ys.min()
@@ -417,8 +418,11 @@ def _py_bh_force(x, y, i, theta, K=1.0, R=1.0):
 
     def rep(px, py, mult):
         dx, dy = px - x[i], py - y[i]
-        d2 = dx * dx + dy * dy
-        return (-mult * R * K * K * dx / d2, -mult * R * K * K * dy / d2) if d2 > 0 else (0.0, 0.0)
+        d = math.hypot(dx, dy)
+        if d == 0:
+            return 0.0, 0.0
+        m = mult * R * K * K * d ** r
+        return (-m * dx / d, -m * dy / d)
 
     def walk(members, cx0, cy0, side, level):
         nonlocal fx, fy
@@ -565,7 +569,7 @@ def _first_stop(e, tol):
 
 @pytest.mark.parametrize("mode", ["exact", "bh"])
 def test_energy_stopping_rule(mode):
-    """Sec. 4.3's energy stopping rule read as a relative change (R11): the run
+    """Sec. 4.5's energy stopping rule read as a relative change (R11): the run
     stops at the first iteration (not the run's first) whose relative energy
     change is at or below the tolerance, and its layout is the plain run's
     layout after that many iterations.  Tolerances taken from the plain run's
@@ -793,3 +797,69 @@ def test_ar_mpmath_bruteforce(a, r):
     x1, y1, e = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, bs, 1, K=K, R=R, model=(a, r))
     for i in range(n):
         assert x1[i] == pytest.approx(float(X[i]), abs=1e-12) and y1[i] == pytest.approx(float(Y[i]), abs=1e-12)
+
+
+# ------------------------------------------- (a, r) models in Barnes-Hut mode
+
+@pytest.mark.parametrize("a,r", AR_MODELS)
+def test_ar_bh_theta_zero_is_exact(a, r):
+    """theta = 0 opens every cell, so the Barnes-Hut force under (a, r) is the
+    exact one (up to summation order), per step and over whole runs."""
+    g = random_graph(70, 0.08, 301)
+    x, y = I.uniform_coords(70, 302)
+    fe = oracle.forces_exact(g.rowptr, g.colidx, x, y, 0, 70, model=(a, r))
+    fb = oracle.forces_bh(g.rowptr, g.colidx, x, y, oracle.Tree(x, y), 0, 70, theta=0.0, model=(a, r))
+    assert np.all(np.abs(fe.fx - fb.fx) <= 1e-12 * fe.scale) and np.all(np.abs(fe.fy - fb.fy) <= 1e-12 * fe.scale)
+    assert np.allclose(fe.scale, fb.scale, rtol=1e-12)
+    for bs in (1, 9, 70):
+        xe, ye, ee = oracle.layout_exact(g.rowptr, g.colidx, x, y, bs, 2, step0=0.05, model=(a, r))
+        xb, yb, eb, _ = oracle.layout_bh(g.rowptr, g.colidx, x, y, bs, 2, step0=0.05, theta=0.0, model=(a, r))
+        assert np.allclose(xe, xb, atol=1e-10) and np.allclose(ye, yb, atol=1e-10) and np.allclose(ee, eb, rtol=1e-10)
+
+
+@pytest.mark.parametrize("a,r", AR_MODELS)
+def test_ar_bh_two_vertex_closed_form(a, r):
+    """Two vertices: the other vertex is a leaf at any theta, so the force is
+    (d^a/K - R K^2 d^r) along the unit vector, as in exact mode."""
+    g = I.path(2)
+    K, R = 0.8, 1.3
+    d, ang = 1.7, 0.4
+    x = np.array([0.1, 0.1 + d * math.cos(ang)])
+    y = np.array([-0.2, -0.2 + d * math.sin(ang)])
+    f = oracle.forces_bh(g.rowptr, g.colidx, x, y, oracle.Tree(x, y), 0, 2, K=K, R=R, theta=5.0, model=(a, r))
+    mag = d ** a / K - R * K * K * d ** r
+    tol = 1e-12 * (d ** a / K + R * K * K * d ** r)
+    assert f.fx[0] == pytest.approx(mag * math.cos(ang), abs=tol)
+    assert f.fy[0] == pytest.approx(mag * math.sin(ang), abs=tol)
+    assert f.fx[1] == pytest.approx(-mag * math.cos(ang), abs=tol)
+
+
+@pytest.mark.parametrize("a,r", AR_MODELS)
+def test_ar_bh_far_cell_is_count_times_single(a, r):
+    """k coincident vertices far away form one accepted cell whose repulsion
+    is k times a single vertex's, R K^2 d^r away from it."""
+    k = 5
+    x = np.array([0.0] + [12.0] * k)
+    y = np.array([0.0] + [-9.0] * k)
+    g = I.csr_from_edges(len(x), np.array([], np.int64), np.array([], np.int64))
+    f = oracle.forces_bh(g.rowptr, g.colidx, x, y, oracle.Tree(x, y), 0, 1, theta=1.2, model=(a, r))
+    assert f.visits[0] < 4
+    d = 15.0
+    assert f.rx[0] == pytest.approx(-k * d ** r * 12.0 / d, rel=1e-13)
+    assert f.ry[0] == pytest.approx(k * d ** r * 9.0 / d, rel=1e-13)
+
+
+@pytest.mark.parametrize("a,r", [(1, -1), (0, -2), (3, 0)])
+@pytest.mark.parametrize("theta", [0.7, 1.2])
+def test_ar_bh_matches_independent_geometric_walk(a, r, theta):
+    """The repulsion under (a, r) against the independent recursive walk."""
+    rr = I.rng(303)
+    n = 50
+    x = rr.uniform(-1, 1, n).astype(np.float32).astype(np.float64)
+    y = rr.uniform(-1, 1, n).astype(np.float32).astype(np.float64)
+    g = I.csr_from_edges(n, np.array([], np.int64), np.array([], np.int64))
+    f = oracle.forces_bh(g.rowptr, g.colidx, x, y, oracle.Tree(x, y), 0, n, theta=theta, model=(a, r))
+    for i in range(n):
+        fx, fy = _py_bh_force(x, y, i, theta, r=r)
+        assert f.rx[i] == pytest.approx(fx, abs=1e-11 * f.scale[i])
+        assert f.ry[i] == pytest.approx(fy, abs=1e-11 * f.scale[i])

@@ -133,6 +133,42 @@ def test_shuffled_bh_run_is_randomised_minibatches(bs):
     assert np.allclose(xs, x, atol=1e-10) and np.allclose(ys, y, atol=1e-10) and np.allclose(es, er, rtol=1e-10)
 
 
+def _relabel(rowptr, colidx, perm):
+    """The graph with vertex perm[q] renamed q (rows sorted again)."""
+    rp = np.asarray(rowptr, dtype=np.int64)
+    ci = np.asarray(colidx, dtype=np.int64)
+    n = len(rp) - 1
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    rows = [np.sort(inv[ci[rp[v]:rp[v + 1]]]) for v in perm]
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    rp2[1:] = np.cumsum([len(r) for r in rows])
+    ci2 = np.concatenate(rows) if len(ci) else np.zeros(0, dtype=np.int64)
+    return rp2.astype(np.int32), ci2.astype(np.int32)
+
+
+@pytest.mark.parametrize("mode,bs", [("exact", 6), ("exact", 13), ("bh", 6)])
+def test_shuffled_run_is_invariant_under_relabelling(mode, bs):
+    """Renaming vertex pi_k[q] to q turns the permutation's runs into id
+    ranges; one ordinary iteration on the renamed graph, mapped back, is the
+    shuffled iteration (same arithmetic up to summation order)."""
+    g = random_graph(45, 0.12, 311)
+    x, y = I.uniform_coords(45, 312)
+    kw = dict(theta=1.2) if mode == "bh" else {}
+    xs, ys, es = oracle.layout_shuffled(g.rowptr, g.colidx, x, y, bs, 3, seed=21, mode=mode, **kw)
+    xr, yr, er = x.copy(), y.copy(), []
+    for k in range(3):
+        perm = oracle.batch_permutation(45, 21, k)
+        rp2, ci2 = _relabel(g.rowptr, g.colidx, perm)
+        if mode == "exact":
+            xk, yk, ek = oracle.layout_exact(rp2, ci2, xr[perm], yr[perm], bs, 1, k)
+        else:
+            xk, yk, ek, _ = oracle.layout_bh(rp2, ci2, xr[perm], yr[perm], bs, 1, k, **kw)
+        xr[perm], yr[perm] = xk, yk
+        er.append(ek[0])
+    assert np.allclose(xs, xr, atol=1e-10) and np.allclose(ys, yr, atol=1e-10) and np.allclose(es, er, rtol=1e-10)
+
+
 # ------------------------------------------------------- Hu's adaptive step
 
 def test_hu_update_worked_sequence():
