@@ -92,6 +92,9 @@ def _load():
     lib.orc_stress.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_void_p,
                                C.POINTER(C.c_double)]
     lib.orc_stress.restype = C.c_double
+    lib.orc_neighborhood_preservation.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, C.c_void_p,
+                                                  C.POINTER(C.c_long)]
+    lib.orc_neighborhood_preservation.restype = C.c_double
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_get_threads.restype = C.c_int
     lib.orc_greedy_init.argtypes = [C.c_int, _i32p, _i32p, C.c_int, _f64p, _f64p, _f64p, _f64p, _i32p]
@@ -415,6 +418,25 @@ def stress(rowptr, colidx, x, y, pivots=None):
         v = _load().orc_stress(len(rp) - 1, rp, ci, _f64(x), _f64(y), len(pv),
                                pv.ctypes.data_as(C.c_void_p), C.byref(s))
     return v, s.value
+
+
+def neighborhood_preservation(rowptr, colidx, x, y, sample=None):
+    """Neighbourhood preservation (Sec. 3.7): the mean over vertices with
+    k = deg > 0 of the Jaccard index of their graph neighbours and their k
+    nearest vertices in the layout (FP64 squared distances, ties by id).
+    sample: vertices to average over (repeats count again), default all.
+    Returns (np, vertices counted)."""
+    rp, ci = _csr(rowptr, colidx)
+    cnt = C.c_long(0)
+    if sample is None:
+        v = _load().orc_neighborhood_preservation(len(rp) - 1, rp, ci, _f64(x), _f64(y), 0, None, C.byref(cnt))
+    else:
+        sv = np.ascontiguousarray(sample, dtype=np.int32)
+        v = _load().orc_neighborhood_preservation(len(rp) - 1, rp, ci, _f64(x), _f64(y), len(sv),
+                                                  sv.ctypes.data_as(C.c_void_p), C.byref(cnt))
+    if v < 0:
+        raise MemoryError("orc_neighborhood_preservation")
+    return v, cnt.value
 
 
 def greedy_init(rowptr, colidx, start, xr=None, yr=None):

@@ -744,6 +744,74 @@ double orc_stress(int n, const int *rowptr, const int *colidx,
     return N - A * A / B;
 }
 
+/* Neighbourhood preservation (Sec. 3.7, the measure tsNET and Maxent use),
+ * read as the mean over vertices i with deg(i) = k > 0 of the Jaccard index
+ * |N(i) & L(i)| / |N(i) | L(i)|, N(i) the graph neighbours of i and L(i) the k
+ * vertices nearest to i in the layout (squared Euclidean distance in FP64,
+ * computed without fused operations; equal distances ordered by vertex id).
+ * With sample != NULL only the listed vertices are averaged (repeats count
+ * again); isolated vertices are skipped.  *counted receives the number of
+ * vertices averaged.  Returns 0 when none is counted. */
+typedef struct { double d2; int v; } ord_dv;
+
+static int cmp_dv(const void *a, const void *b)
+{
+    const ord_dv *p = (const ord_dv *)a, *q = (const ord_dv *)b;
+    if (p->d2 != q->d2) return p->d2 < q->d2 ? -1 : 1;
+    return p->v < q->v ? -1 : (p->v > q->v);
+}
+
+double orc_neighborhood_preservation(int n, const int *rowptr, const int *colidx,
+                                     const double *x, const double *y,
+                                     int nsample, const int *sample, long *counted)
+{
+    int ns = sample ? nsample : n;
+    double *jac = calloc(ns > 0 ? ns : 1, sizeof(double));
+    char *use = calloc(ns > 0 ? ns : 1, 1);
+    int failed = 0;
+    if (!jac || !use) { free(jac); free(use); return -1.0; }
+#pragma omp parallel
+    {
+        ord_dv *buf = malloc(sizeof(ord_dv) * (n > 1 ? n - 1 : 1));
+        char *near = calloc(n, 1);
+        if (!buf || !near) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int q = 0; q < ns; ++q) {
+            if (!buf || !near) continue;
+            int i = sample ? sample[q] : q;
+            int k = rowptr[i + 1] - rowptr[i];
+            if (k == 0) continue;
+            int m = 0;
+            for (int v = 0; v < n; ++v) {
+                if (v == i) continue;
+                double dx = x[v] - x[i], dy = y[v] - y[i];
+                buf[m].d2 = dx * dx + dy * dy;
+                buf[m].v = v;
+                ++m;
+            }
+            qsort(buf, m, sizeof(ord_dv), cmp_dv);
+            for (int t = 0; t < k; ++t) near[buf[t].v] = 1;
+            int both = 0;
+            for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) both += near[colidx[e]];
+            for (int t = 0; t < k; ++t) near[buf[t].v] = 0;
+            jac[q] = (double)both / (double)(2 * k - both);
+            use[q] = 1;
+        }
+        free(buf); free(near);
+    }
+    double sum = 0.0;
+    long cnt = 0;
+    for (int q = 0; q < ns; ++q)
+        if (use[q]) { sum += jac[q]; ++cnt; }
+    free(jac); free(use);
+    if (counted) *counted = cnt;
+    if (failed) return -1.0;
+    return cnt ? sum / (double)cnt : 0.0;
+}
+
 /* ------------------------------------------------- greedy initialisation */
 
 /* Greedy initialisation, Sec. 3.6 and Algorithm 3.  The start vertex sits at

@@ -863,3 +863,63 @@ def test_ar_bh_matches_independent_geometric_walk(a, r, theta):
         fx, fy = _py_bh_force(x, y, i, theta, r=r)
         assert f.rx[i] == pytest.approx(fx, abs=1e-11 * f.scale[i])
         assert f.ry[i] == pytest.approx(fy, abs=1e-11 * f.scale[i])
+
+
+# ------------------------------------------------- neighbourhood preservation
+
+def test_np_metric_layouts_preserve_every_neighbourhood():
+    """A path at unit spacing on a line, a cycle on a regular polygon and a
+    grid at unit spacing: each vertex's deg nearest vertices are exactly its
+    neighbours, so the measure is 1 over all vertices."""
+    n = 12
+    g = I.path(n)
+    v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, np.arange(n, dtype=float), np.zeros(n))
+    assert v == 1.0 and c == n
+    g = I.cycle(9)
+    t = 2 * np.pi * np.arange(9) / 9
+    v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, np.cos(t), np.sin(t))
+    assert v == 1.0 and c == 9
+    g = I.grid(4, 5)
+    v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, (np.arange(20) % 5).astype(float),
+                                            (np.arange(20) // 5).astype(float))
+    assert v == 1.0 and c == 20
+
+
+def test_np_crossed_matching_is_zero():
+    """Edges (0,2), (1,3), (4,6), (5,7) with vertex v at x = v: every vertex's
+    nearest other vertex (ties to the lower id) is not its partner."""
+    src = np.array([0, 1, 4, 5])
+    dst = np.array([2, 3, 6, 7])
+    g = I.csr_from_edges(8, src, dst)
+    v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, np.arange(8, dtype=float), np.zeros(8))
+    assert v == 0.0 and c == 8
+
+
+def test_np_worked_example_with_ties_and_isolated_vertex():
+    """Star 0-{1,2,3} and an isolated vertex 4, worked by hand:
+    vertex 0 at the origin, degree 3: nearest 4 (d^2 .25), then 1 and 2 (d^2 1):
+    2 of 3 neighbours, Jaccard 2/4; vertex 1 at (1,0): nearest 4, a miss;
+    vertex 2 at (0,1): nearest 0, a hit; vertex 3 at (5,5): 1 and 2 tie at
+    d^2 41, the lower id 1 is taken, a miss; vertex 4 is isolated and skipped.
+    Mean (0.5 + 0 + 1 + 0) / 4."""
+    g = I.csr_from_edges(5, np.array([0, 0, 0]), np.array([1, 2, 3]))
+    x = np.array([0.0, 1.0, 0.0, 5.0, 0.5])
+    y = np.array([0.0, 0.0, 1.0, 5.0, 0.0])
+    v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, x, y)
+    assert v == 0.375 and c == 4
+    v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, x, y, sample=[0, 0, 2, 4])
+    assert v == pytest.approx(2.0 / 3.0, rel=1e-15) and c == 3
+    v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, x, y, sample=[4])
+    assert v == 0.0 and c == 0
+
+
+def test_np_invariant_under_similarity_transforms():
+    """Translation by a dyadic offset, scaling by 2 and a 90 degree rotation
+    keep every distance order, so the measure is unchanged."""
+    g = random_graph(80, 0.06, 321)
+    x, y = dyadic_coords(80, 322)
+    v0, c0 = oracle.neighborhood_preservation(g.rowptr, g.colidx, x, y)
+    assert 0.0 < v0 < 1.0
+    for xs, ys in [(x + 0.5, y - 0.25), (2 * x, 2 * y), (-y, x)]:
+        v, c = oracle.neighborhood_preservation(g.rowptr, g.colidx, xs, ys)
+        assert v == v0 and c == c0
