@@ -229,6 +229,27 @@ int bl_quality_eval(const bl_csr *g, const double *x, const double *y, int32_t n
                     const int32_t *pivots, double K, uint32_t flags, void *hip_stream,
                     bl_quality *out);
 
+/* bl_quality_eval for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same results, bit for bit, with every work buffer in
+ * one static device array of the library (about 11.9 MiB per GPU, reserved
+ * from the first use on that GPU until the process ends) instead of device
+ * memory allocated per call.  No hipMalloc, hipFree or other allocation.
+ *  - flags must be exactly BL_DEVICE_PTRS: g's arrays, x and y are device
+ *    memory the caller owns; pivots (npivots of them, or NULL for all pairs)
+ *    stay host memory and are copied into the array.
+ *  - Limits: 1 <= n <= 262144 vertices, npivots <= 65536 (BL_E_INVAL above).
+ *  - The CSR is checked on the device (rowptr from 0 to nnz, non-decreasing,
+ *    colidx in [0, n)); BL_VALIDATE's full checks are not available here.
+ *  - Calls on one GPU share its array: calls that overlap in time on one GPU
+ *    (from several host threads or streams) race and give wrong results; the
+ *    caller serialises them.  Each call starts from cleared state, so a call
+ *    never depends on the previous one.
+ * Errors: as bl_quality_eval, plus BL_E_INVAL for the limits above. */
+int bl_quality_eval_noalloc(const bl_csr *g, const double *x, const double *y, int32_t npivots,
+                            const int32_t *pivots, double K, uint32_t flags, void *hip_stream,
+                            bl_quality *out);
+
 /* --------------------------------------------------------- one minibatch
  * Net forces (attraction + repulsion, no update) on the vertices of batch
  * `batch_index` (ids [b*BS, min((b+1)*BS, n))) from coordinates (x, y)

@@ -182,6 +182,23 @@ def quality(graph, x, y, pivots=None, K=1.0, stream=None):
     return q.as_dict()
 
 
+def quality_noalloc(graph, x, y, pivots=None, K=1.0, stream=None):
+    """quality() through bl_quality_eval_noalloc: the graph (a Graph whose
+    rowptr/colidx are device tensors) and x, y must be device tensors; the
+    library uses its static device work array instead of allocating."""
+    lib = load()
+    keep = _Keep()
+    if not _device(graph.rowptr, x, y):
+        raise ValueError("quality_noalloc takes device tensors only")
+    csr = _csr(graph, keep)
+    piv = None if pivots is None else np.ascontiguousarray(pivots, dtype=np.int32)
+    q = L.Quality()
+    check(lib.bl_quality_eval_noalloc(C.byref(csr), keep.ptr(x, np.float64), keep.ptr(y, np.float64),
+                                      0 if piv is None else len(piv), None if piv is None else piv.ctypes.data,
+                                      float(K), BL_DEVICE_PTRS, _stream(stream), C.byref(q)))
+    return q.as_dict()
+
+
 def forces(graph, x, y, batch_index, p: Params, snapshot=None, stream=None):
     """Net forces on one batch from (x, y); BH tree from `snapshot` (sx, sy) if given."""
     lib = load()

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "bl_device.hpp"
@@ -323,6 +324,229 @@ struct QBuffers {
     }
 };
 
+// Where one evaluation's kernels read and write: the graph and coordinates
+// (device copies or the caller's device arrays) and the work buffers.
+struct QWork {
+    const int *rp, *ci;
+    const double *dx, *dy;
+    const int *src;           // device pivots (NULL: all pairs)
+    const int *heavy;         // rows longer than kHeavyDeg, ascending
+    int nheavy;
+    double2 *p;
+    u64 *seen, *fr[2];
+    Sums *S;
+    double *tot;
+    u64 *cnt, *newc;
+};
+
+// The edge passes and the BFS passes of bl_quality_eval on prepared buffers.
+int quality_compute(int n, int64_t nnz, int npivots, double K, const QWork &w, hipStream_t s, bl_quality *out) {
+    const int vb = (n + 255) / 256;
+    hipLaunchKernelGGL(pos_kernel, dim3(vb), dim3(256), 0, s, n, w.dx, w.dy, w.p);
+
+    // edge energy and uniformity: two passes over the entries
+    double h[4];
+    u64 hc[2];
+    hipLaunchKernelGGL(edge_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, n, nnz, w.rp, w.ci, w.p, K, 0, 0.0, w.S);
+    hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, w.S, w.tot, w.cnt);
+    BL_HIP(hipMemcpyAsync(h, w.tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    BL_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(u64), hipMemcpyDeviceToHost, s));
+    BL_HIP(hipStreamSynchronize(s));
+    const u64 m = hc[0];
+    out->edges = (int64_t)m;
+    out->edge_energy = h[0];
+    if (m > 0) {
+        const double mean = h[1] / (double)m;
+        hipLaunchKernelGGL(edge_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, n, nnz, w.rp, w.ci, w.p, K, 1, mean,
+                           w.S);
+        hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, w.S, w.tot, w.cnt);
+        BL_HIP(hipMemcpyAsync(h, w.tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+        BL_HIP(hipStreamSynchronize(s));
+        out->edge_uniformity = mean > 0 ? std::sqrt(h[0] / ((double)m * mean * mean)) : 0.0;
+    }
+
+    // stress: sources in passes of 64
+    hipLaunchKernelGGL(sums_clear_kernel, dim3((kQBlocks + 255) / 256), dim3(256), 0, s, w.S);
+    const int nsrc_total = npivots > 0 ? npivots : n;
+    int levels = 0;
+    for (int base = 0; base < nsrc_total; base += kSrc) {
+        const int ns = std::min(kSrc, nsrc_total - base);
+        const int *sp = w.src ? w.src + base : nullptr;
+        hipLaunchKernelGGL(bfs_clear_kernel, dim3(vb), dim3(256), 0, s, n, w.seen, w.fr[0]);
+        hipLaunchKernelGGL(bfs_sources_kernel, dim3(1), dim3(kSrc), 0, s, sp, base, ns, w.seen, w.fr[0]);
+        int cur = 0;
+        for (int level = 1; level < n + 1; level += kLevelGroup) {
+            hipLaunchKernelGGL(counters_clear_kernel, dim3(1), dim3(kLevelGroup), 0, s, w.newc, kLevelGroup);
+            for (int q = 0; q < kLevelGroup; ++q) {
+                BfsArgs a;
+                a.n = n;
+                a.ns = ns;
+                a.all_pairs = npivots > 0 ? 0 : 1;
+                a.level = level + q;
+                a.rp = w.rp;
+                a.ci = w.ci;
+                a.src = sp;
+                a.base = base;
+                a.p = w.p;
+                a.fin = w.fr[cur];
+                a.fout = w.fr[cur ^ 1];
+                a.seen = w.seen;
+                a.newcount = w.newc + q;
+                a.heavy = w.heavy;
+                a.nheavy = w.nheavy;
+                a.S = w.S;
+                hipLaunchKernelGGL(bfs_light_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, a);
+                if (w.nheavy)
+                    hipLaunchKernelGGL(bfs_heavy_kernel, dim3(std::min(w.nheavy, kQBlocks)), dim3(kQThreads), 0, s,
+                                       a);
+                cur ^= 1;
+            }
+            u64 nc[kLevelGroup];
+            BL_HIP(hipMemcpyAsync(nc, w.newc, sizeof nc, hipMemcpyDeviceToHost, s));
+            BL_HIP(hipStreamSynchronize(s));
+            levels += kLevelGroup;
+            bool done = false;
+            for (int q = 0; q < kLevelGroup; ++q) done = done || nc[q] == 0;
+            if (done) break;
+        }
+    }
+    hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, w.S, w.tot, w.cnt);
+    BL_HIP(hipMemcpyAsync(h, w.tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    BL_HIP(hipMemcpyAsync(hc, w.cnt, sizeof(u64), hipMemcpyDeviceToHost, s));
+    BL_HIP(hipStreamSynchronize(s));
+    BL_HIP(hipGetLastError());
+    const double A = h[0], Bs = h[1], N = (double)hc[0];
+    out->pairs = (int64_t)hc[0];
+    out->bfs_levels = levels;
+    if (Bs == 0.0) {
+        out->stress = N;
+        out->scale = 0.0;
+    } else {
+        out->stress = N - A * A / Bs;
+        out->scale = A / Bs;
+    }
+    return BL_OK;
+}
+
+// Argument checks shared by both entry points (the CSR itself is checked
+// separately).
+int quality_args(const double *x, const double *y, int32_t npivots, const int32_t *pivots, double K,
+                 bl_quality *out) {
+    if (!out) return fail_code(BL_E_INVAL, "out is NULL");
+    std::memset(out, 0, sizeof *out);
+    if (!x || !y) return fail_code(BL_E_INVAL, "coordinate arrays are NULL");
+    if (!(K > 0) || !std::isfinite(K)) return fail_code(BL_E_INVAL, "K must be > 0");
+    if (npivots < 0 || (npivots > 0 && !pivots)) return fail_code(BL_E_INVAL, "bad pivot list");
+    return BL_OK;
+}
+
+// ------------------------------------------------ allocation-free variant
+//
+// bl_quality_eval_noalloc keeps its work buffers in one static device array
+// of fixed size instead of allocating them.  Its layout, for at most
+// kNoAllocMaxN vertices and kNoAllocMaxPivots pivots:
+//   p (double2 per vertex), seen and two frontier words (u64 per vertex),
+//   the heavy-row list (int per vertex), the block slots, the totals and
+//   counters, the pivots, and two ints (CSR check flag, heavy-row count);
+// each piece starts on a 256-byte boundary.
+constexpr int kNoAllocMaxN = 1 << 18;
+constexpr int kNoAllocMaxPivots = 1 << 16;
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kScrP = 0;
+constexpr size_t kScrSeen = kScrP + al256(sizeof(double2) * kNoAllocMaxN);
+constexpr size_t kScrFr0 = kScrSeen + al256(sizeof(u64) * kNoAllocMaxN);
+constexpr size_t kScrFr1 = kScrFr0 + al256(sizeof(u64) * kNoAllocMaxN);
+constexpr size_t kScrHeavy = kScrFr1 + al256(sizeof(u64) * kNoAllocMaxN);
+constexpr size_t kScrSums = kScrHeavy + al256(sizeof(int) * kNoAllocMaxN);
+constexpr size_t kScrTot = kScrSums + al256(sizeof(Sums));
+constexpr size_t kScrCnt = kScrTot + al256(sizeof(double) * 4);
+constexpr size_t kScrNewc = kScrCnt + al256(sizeof(u64) * 2);
+constexpr size_t kScrSrc = kScrNewc + al256(sizeof(u64) * kLevelGroup);
+constexpr size_t kScrFlags = kScrSrc + al256(sizeof(int) * kNoAllocMaxPivots);
+constexpr size_t kScratchBytes = kScrFlags + al256(sizeof(int) * 2);
+
+}  // namespace
+}  // namespace bl
+
+// One copy per device, held until the process ends.  Host code never uses
+// this name as an address: kernels get the pointer hipGetSymbolAddress gave
+// for the current device.
+static __device__ __align__(256) unsigned char scratch[bl::kScratchBytes];
+
+namespace bl {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_address(unsigned char **out) {
+    int dev = 0;
+    BL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail_code(BL_E_INVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail_code(BL_E_HIP, "hipGetSymbolAddress of the quality scratch array failed");
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned char *)g_scratch_ptr[dev];
+    return BL_OK;
+}
+
+__global__ void flags_clear_kernel(int *f) {
+    if (threadIdx.x < 2) f[threadIdx.x] = 0;
+}
+
+// The CSR checks of check_csr without BL_VALIDATE, on device arrays:
+// rowptr[0] = 0, rowptr non-decreasing, rowptr[n] = nnz, colidx in [0, n).
+// Any failure sets *bad.
+__global__ void csr_check_kernel(int n, int64_t nnz, const int *__restrict__ rp, const int *__restrict__ ci,
+                                 int *bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool b = false;
+    if (t == 0) b = rp[0] != 0 || (int64_t)rp[n] != nnz;
+    for (int64_t i = t; i < n; i += stride) b = b || rp[i + 1] < rp[i];
+    for (int64_t e = t; e < nnz; e += stride) {
+        const int j = ci[e];
+        b = b || j < 0 || j >= n;
+    }
+    if (b) atomicOr(bad, 1);
+}
+
+// Rows with more than kHeavyDeg entries, ascending, in one workgroup of
+// kQThreads threads (the list bl_quality_eval builds on the host).
+__global__ __launch_bounds__(kQThreads) void heavy_list_kernel(int n, const int *__restrict__ rp, int *heavy,
+                                                               int *count) {
+    __shared__ int wtot[kQThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int carry = 0;
+    for (int base = 0; base < n; base += kQThreads) {
+        const int v = base + threadIdx.x;
+        const bool f = v < n && rp[v + 1] - rp[v] > kHeavyDeg;
+        const u64 bal = __ballot(f);
+        const int below = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wtot[w] = __popcll(bal);
+        __syncthreads();
+        int off = carry, tot = 0;
+        for (int q = 0; q < kQThreads / kWave; ++q) {
+            if (q < w) off += wtot[q];
+            tot += wtot[q];
+        }
+        if (f) heavy[off + below] = v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
 }  // namespace
 }  // namespace bl
 
@@ -330,12 +554,8 @@ extern "C" int bl_quality_eval(const bl_csr *g, const double *x, const double *y
                                const int32_t *pivots, double K, uint32_t flags, void *hip_stream,
                                bl_quality *out) {
     using namespace bl;
-    if (!out) return fail_code(BL_E_INVAL, "out is NULL");
-    std::memset(out, 0, sizeof *out);
-    if (!x || !y) return fail_code(BL_E_INVAL, "coordinate arrays are NULL");
+    BL_TRY(quality_args(x, y, npivots, pivots, K, out));
     if (flags & ~BL_DEVICE_PTRS) return fail_code(BL_E_INVAL, "unknown flags");
-    if (!(K > 0) || !std::isfinite(K)) return fail_code(BL_E_INVAL, "K must be > 0");
-    if (npivots < 0 || (npivots > 0 && !pivots)) return fail_code(BL_E_INVAL, "bad pivot list");
     hipStream_t s = (hipStream_t)hip_stream;
     BL_TRY(check_csr(g, flags, s));
     const int n = g->n;
@@ -346,24 +566,21 @@ extern "C" int bl_quality_eval(const bl_csr *g, const double *x, const double *y
     const hipMemcpyKind h2d = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
 
     QBuffers B;
-    int *rp, *ci, *src = nullptr;
-    double *dx, *dy, *tot;
-    double2 *p;
-    u64 *seen, *fr[2], *cnt, *newc;
-    int *heavy;
-    Sums *S;
+    QWork w{};
+    int *rp, *ci, *src = nullptr, *heavy;
+    double *dx, *dy;
     BL_TRY(B.alloc((void **)&rp, sizeof(int) * (size_t)(n + 1)));
     BL_TRY(B.alloc((void **)&ci, sizeof(int) * (size_t)nnz));
     BL_TRY(B.alloc((void **)&dx, sizeof(double) * (size_t)n));
     BL_TRY(B.alloc((void **)&dy, sizeof(double) * (size_t)n));
-    BL_TRY(B.alloc((void **)&p, sizeof(double2) * (size_t)n));
-    BL_TRY(B.alloc((void **)&seen, sizeof(u64) * (size_t)n));
-    BL_TRY(B.alloc((void **)&fr[0], sizeof(u64) * (size_t)n));
-    BL_TRY(B.alloc((void **)&fr[1], sizeof(u64) * (size_t)n));
-    BL_TRY(B.alloc((void **)&S, sizeof(Sums)));
-    BL_TRY(B.alloc((void **)&tot, sizeof(double) * 4));
-    BL_TRY(B.alloc((void **)&cnt, sizeof(u64) * 2));
-    BL_TRY(B.alloc((void **)&newc, sizeof(u64) * kLevelGroup));
+    BL_TRY(B.alloc((void **)&w.p, sizeof(double2) * (size_t)n));
+    BL_TRY(B.alloc((void **)&w.seen, sizeof(u64) * (size_t)n));
+    BL_TRY(B.alloc((void **)&w.fr[0], sizeof(u64) * (size_t)n));
+    BL_TRY(B.alloc((void **)&w.fr[1], sizeof(u64) * (size_t)n));
+    BL_TRY(B.alloc((void **)&w.S, sizeof(Sums)));
+    BL_TRY(B.alloc((void **)&w.tot, sizeof(double) * 4));
+    BL_TRY(B.alloc((void **)&w.cnt, sizeof(u64) * 2));
+    BL_TRY(B.alloc((void **)&w.newc, sizeof(u64) * kLevelGroup));
     if (npivots > 0) {
         BL_TRY(B.alloc((void **)&src, sizeof(int) * (size_t)npivots));
         BL_HIP(hipMemcpyAsync(src, pivots, sizeof(int) * (size_t)npivots, hipMemcpyHostToDevice, s));
@@ -386,88 +603,66 @@ extern "C" int bl_quality_eval(const bl_csr *g, const double *x, const double *y
         if (rpv[v + 1] - rpv[v] > kHeavyDeg) hv.push_back(v);
     BL_TRY(B.alloc((void **)&heavy, sizeof(int) * std::max<size_t>(hv.size(), 1)));
     if (!hv.empty()) BL_HIP(hipMemcpyAsync(heavy, hv.data(), sizeof(int) * hv.size(), hipMemcpyHostToDevice, s));
-    const int nheavy = (int)hv.size();
-    const int vb = (n + 255) / 256;
-    hipLaunchKernelGGL(pos_kernel, dim3(vb), dim3(256), 0, s, n, dx, dy, p);
+    w.rp = rp;
+    w.ci = ci;
+    w.dx = dx;
+    w.dy = dy;
+    w.src = src;
+    w.heavy = heavy;
+    w.nheavy = (int)hv.size();
+    return quality_compute(n, nnz, npivots, K, w, s, out);
+}
 
-    // edge energy and uniformity: two passes over the entries
-    double h[4];
-    u64 hc[2];
-    hipLaunchKernelGGL(edge_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, n, nnz, rp, ci, p, K, 0, 0.0, S);
-    hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, S, tot, cnt);
-    BL_HIP(hipMemcpyAsync(h, tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
-    BL_HIP(hipMemcpyAsync(hc, cnt, sizeof(u64), hipMemcpyDeviceToHost, s));
+extern "C" int bl_quality_eval_noalloc(const bl_csr *g, const double *x, const double *y, int32_t npivots,
+                                       const int32_t *pivots, double K, uint32_t flags, void *hip_stream,
+                                       bl_quality *out) {
+    using namespace bl;
+    BL_TRY(quality_args(x, y, npivots, pivots, K, out));
+    if (flags != BL_DEVICE_PTRS) return fail_code(BL_E_INVAL, "flags must be exactly BL_DEVICE_PTRS");
+    if (!g) return fail_code(BL_E_INVAL, "graph is NULL");
+    if (g->n < 1) return fail_code(BL_E_INVAL, "n must be >= 1");
+    if (g->n > kNoAllocMaxN) return fail_code(BL_E_INVAL, "n exceeds the scratch limit of 262144 vertices");
+    if (npivots > kNoAllocMaxPivots) return fail_code(BL_E_INVAL, "more than 65536 pivots");
+    if (g->nnz < 0 || g->nnz > 0x7fffffffLL) return fail_code(BL_E_INVAL, "nnz out of range");
+    if (!g->rowptr || (g->nnz > 0 && !g->colidx)) return fail_code(BL_E_INVAL, "CSR arrays are NULL");
+    const int n = g->n;
+    const int64_t nnz = g->nnz;
+    for (int q = 0; q < npivots; ++q)
+        if (pivots[q] < 0 || pivots[q] >= n) return fail_code(BL_E_INVAL, "pivot out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned char *base = nullptr;
+    BL_TRY(scratch_address(&base));
+    int *fl = (int *)(base + kScrFlags);
+    int hf[2] = {0, 0};
+    hipLaunchKernelGGL(flags_clear_kernel, dim3(1), dim3(64), 0, s, fl);
+    hipLaunchKernelGGL(csr_check_kernel, dim3(256), dim3(256), 0, s, n, nnz, g->rowptr, g->colidx, fl);
+    BL_HIP(hipMemcpyAsync(hf, fl, sizeof(int), hipMemcpyDeviceToHost, s));
     BL_HIP(hipStreamSynchronize(s));
-    const u64 m = hc[0];
-    out->edges = (int64_t)m;
-    out->edge_energy = h[0];
-    if (m > 0) {
-        const double mean = h[1] / (double)m;
-        hipLaunchKernelGGL(edge_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, n, nnz, rp, ci, p, K, 1, mean, S);
-        hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, S, tot, cnt);
-        BL_HIP(hipMemcpyAsync(h, tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
-        BL_HIP(hipStreamSynchronize(s));
-        out->edge_uniformity = mean > 0 ? std::sqrt(h[0] / ((double)m * mean * mean)) : 0.0;
-    }
+    if (hf[0]) return fail_code(BL_E_INVAL, "malformed CSR (rowptr not monotone from 0 to nnz, or colidx out of range)");
 
-    // stress: sources in passes of 64
-    hipLaunchKernelGGL(sums_clear_kernel, dim3((kQBlocks + 255) / 256), dim3(256), 0, s, S);
-    const int nsrc_total = npivots > 0 ? npivots : n;
-    int levels = 0;
-    for (int base = 0; base < nsrc_total; base += kSrc) {
-        const int ns = std::min(kSrc, nsrc_total - base);
-        const int *sp = src ? src + base : nullptr;
-        hipLaunchKernelGGL(bfs_clear_kernel, dim3(vb), dim3(256), 0, s, n, seen, fr[0]);
-        hipLaunchKernelGGL(bfs_sources_kernel, dim3(1), dim3(kSrc), 0, s, sp, base, ns, seen, fr[0]);
-        int cur = 0;
-        for (int level = 1; level < n + 1; level += kLevelGroup) {
-            hipLaunchKernelGGL(counters_clear_kernel, dim3(1), dim3(kLevelGroup), 0, s, newc, kLevelGroup);
-            for (int q = 0; q < kLevelGroup; ++q) {
-                BfsArgs a;
-                a.n = n;
-                a.ns = ns;
-                a.all_pairs = npivots > 0 ? 0 : 1;
-                a.level = level + q;
-                a.rp = rp;
-                a.ci = ci;
-                a.src = sp;
-                a.base = base;
-                a.p = p;
-                a.fin = fr[cur];
-                a.fout = fr[cur ^ 1];
-                a.seen = seen;
-                a.newcount = newc + q;
-                a.heavy = heavy;
-                a.nheavy = nheavy;
-                a.S = S;
-                hipLaunchKernelGGL(bfs_light_kernel, dim3(kQBlocks), dim3(kQThreads), 0, s, a);
-                if (nheavy)
-                    hipLaunchKernelGGL(bfs_heavy_kernel, dim3(std::min(nheavy, kQBlocks)), dim3(kQThreads), 0, s, a);
-                cur ^= 1;
-            }
-            u64 nc[kLevelGroup];
-            BL_HIP(hipMemcpyAsync(nc, newc, sizeof nc, hipMemcpyDeviceToHost, s));
-            BL_HIP(hipStreamSynchronize(s));
-            levels += kLevelGroup;
-            bool done = false;
-            for (int q = 0; q < kLevelGroup; ++q) done = done || nc[q] == 0;
-            if (done) break;
-        }
+    QWork w{};
+    w.rp = g->rowptr;
+    w.ci = g->colidx;
+    w.dx = x;
+    w.dy = y;
+    w.p = (double2 *)(base + kScrP);
+    w.seen = (u64 *)(base + kScrSeen);
+    w.fr[0] = (u64 *)(base + kScrFr0);
+    w.fr[1] = (u64 *)(base + kScrFr1);
+    w.S = (Sums *)(base + kScrSums);
+    w.tot = (double *)(base + kScrTot);
+    w.cnt = (u64 *)(base + kScrCnt);
+    w.newc = (u64 *)(base + kScrNewc);
+    int *heavy = (int *)(base + kScrHeavy);
+    if (npivots > 0) {
+        int *src = (int *)(base + kScrSrc);
+        BL_HIP(hipMemcpyAsync(src, pivots, sizeof(int) * (size_t)npivots, hipMemcpyHostToDevice, s));
+        w.src = src;
     }
-    hipLaunchKernelGGL(sums_total_kernel, dim3(1), dim3(1), 0, s, S, tot, cnt);
-    BL_HIP(hipMemcpyAsync(h, tot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
-    BL_HIP(hipMemcpyAsync(hc, cnt, sizeof(u64), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(heavy_list_kernel, dim3(1), dim3(kQThreads), 0, s, n, g->rowptr, heavy, fl + 1);
+    BL_HIP(hipMemcpyAsync(hf + 1, fl + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     BL_HIP(hipStreamSynchronize(s));
-    BL_HIP(hipGetLastError());
-    const double A = h[0], Bs = h[1], N = (double)hc[0];
-    out->pairs = (int64_t)hc[0];
-    out->bfs_levels = levels;
-    if (Bs == 0.0) {
-        out->stress = N;
-        out->scale = 0.0;
-    } else {
-        out->stress = N - A * A / Bs;
-        out->scale = A / Bs;
-    }
-    return BL_OK;
+    w.heavy = heavy;
+    w.nheavy = hf[1];
+    return quality_compute(n, nnz, npivots, K, w, s, out);
 }
