@@ -229,6 +229,27 @@ int bl_quality_eval(const bl_csr *g, const double *x, const double *y, int32_t n
                     const int32_t *pivots, double K, uint32_t flags, void *hip_stream,
                     bl_quality *out);
 
+/* Neighbourhood preservation (Sec. 3.7, the measure of tsNET and Maxent):
+ * the mean, over vertices i with k = deg(i) > 0, of the Jaccard index
+ * |N(i) & L(i)| / |N(i) | L(i)| of i's graph neighbours N(i) and the k
+ * vertices L(i) nearest to i in the layout.  The paper names the measure but
+ * not its neighbourhood size; k = deg(i) is the reading used here.  Distances
+ * are squared Euclidean in FP64 without fused multiply-add, equal distances
+ * ordered by vertex id, so every membership decision is exact.
+ * nsample = 0: over all vertices; otherwise over the vertices of the host
+ * array sample[nsample] (repeats count again).  Isolated vertices are
+ * skipped; *counted (may be NULL) receives how many vertices were averaged
+ * and *np_out the mean (0 when none).  With BL_DEVICE_PTRS in flags, g, x and
+ * y are device pointers (sample stays host memory).  Coordinates must be
+ * finite.  One workgroup per sampled vertex runs a radix selection over all
+ * n vertices.  Temporary device memory is allocated and freed inside; the
+ * same inputs give the same bits.
+ * Errors: BL_E_INVAL (NULL arrays, bad CSR, a sample vertex out of range),
+ * BL_E_NOMEM, BL_E_HIP. */
+int bl_neighborhood_preservation(const bl_csr *g, const double *x, const double *y, int32_t nsample,
+                                 const int32_t *sample, uint32_t flags, void *hip_stream,
+                                 double *np_out, int64_t *counted);
+
 /* bl_quality_eval for callers that cannot allocate device memory (code under
  * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same kernels and the same results, bit for bit, with every work buffer in

@@ -27,7 +27,7 @@ EXPORTED = [
     "bl_graph_destroy", "bl_graph_profile", "bl_graph_profile_read", "bl_layout_batch",
     "bl_server_create", "bl_server_submit", "bl_server_poll", "bl_server_wait", "bl_server_fetch",
     "bl_server_release", "bl_server_destroy", "bl_greedy_init", "bl_quality_eval",
-    "bl_layout_shuffled", "bl_quality_eval_noalloc",
+    "bl_layout_shuffled", "bl_quality_eval_noalloc", "bl_neighborhood_preservation",
 ]
 
 
@@ -95,6 +95,7 @@ def load():
     lib.bl_forces.argtypes = [P(CSR), vp, vp, vp, vp, i32, P(Params), vp, vp, vp]
     lib.bl_greedy_init.argtypes = [P(CSR), i32, vp, vp]
     lib.bl_quality_eval.argtypes = [P(CSR), vp, vp, i32, vp, dbl, C.c_uint32, vp, P(Quality)]
+    lib.bl_neighborhood_preservation.argtypes = [P(CSR), vp, vp, i32, vp, C.c_uint32, vp, P(dbl), P(i64)]
     lib.bl_quality_eval_noalloc.argtypes = [P(CSR), vp, vp, i32, vp, dbl, C.c_uint32, vp, P(Quality)]
     lib.bl_graph_create.argtypes = [P(CSR), P(Params), vp, P(vp)]
     lib.bl_graph_set_coords.argtypes = [vp, vp, vp, C.c_uint32]

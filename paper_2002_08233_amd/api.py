@@ -182,6 +182,24 @@ def quality(graph, x, y, pivots=None, K=1.0, stream=None):
     return q.as_dict()
 
 
+def neighborhood_preservation(graph, x, y, sample=None, stream=None):
+    """Neighbourhood preservation (Sec. 3.7) of the layout (x, y) on the GPU:
+    mean Jaccard index of each vertex's graph neighbours and its deg nearest
+    layout vertices.  sample=None: all vertices.  Returns (np, counted)."""
+    lib = load()
+    keep = _Keep()
+    dev = _device(graph.rowptr, x, y)
+    csr = _csr(graph, keep)
+    smp = None if sample is None else np.ascontiguousarray(sample, dtype=np.int32)
+    v = C.c_double(0.0)
+    cnt = C.c_int64(0)
+    check(lib.bl_neighborhood_preservation(C.byref(csr), keep.ptr(x, np.float64), keep.ptr(y, np.float64),
+                                           0 if smp is None else len(smp), None if smp is None else smp.ctypes.data,
+                                           BL_DEVICE_PTRS if dev else 0, _stream(stream), C.byref(v),
+                                           C.byref(cnt)))
+    return v.value, cnt.value
+
+
 def quality_noalloc(graph, x, y, pivots=None, K=1.0, stream=None):
     """quality() through bl_quality_eval_noalloc: the graph (a Graph whose
     rowptr/colidx are device tensors) and x, y must be device tensors; the

@@ -547,6 +547,155 @@ __global__ __launch_bounds__(kQThreads) void heavy_list_kernel(int n, const int 
     if (threadIdx.x == 0) *count = carry;
 }
 
+// ------------------------------------------------ neighbourhood preservation
+//
+// For a vertex i with k = deg(i) > 0: L(i) = the k vertices v != i nearest
+// to i in the layout, ordered by the squared distance (FP64, no fused
+// multiply-add) and then by id; the vertex's score is the Jaccard index
+// |N(i) & L(i)| / |N(i) | L(i)| = both / (2k - both).
+//
+// One workgroup per sampled vertex finds the k-th smallest key (d2, id) by
+// radix selection: eight 8-bit passes over the bits of d2 (non-negative
+// doubles order like their bit patterns), then, if the k-th place falls
+// inside a run of equal distances, four 8-bit passes over the ids of that
+// run.  Each pass histograms, in LDS, the vertices whose key agrees with the
+// prefix found so far.  A neighbour j is then in L(i) iff its key is at most
+// the k-th key.  Every decision is on exact integers and bit patterns.
+constexpr int kNpThreads = 512;
+
+__device__ __forceinline__ u64 d2_bits(double2 a, double2 b) {
+#pragma clang fp contract(off)
+    const double dx = b.x - a.x, dy = b.y - a.y;
+    const double d2 = dx * dx + dy * dy;
+    return (u64)__double_as_longlong(d2);
+}
+
+// The bin of hist[256] holding the need-th (1-based) of the counted keys;
+// need becomes the rank inside that bin and *cnt the bin's count.  Thread 0
+// scans; the result is broadcast through sh[3].  Returns -1 when fewer than
+// need keys were counted.
+__device__ int np_pick(const int *hist, int *sh, int &need, int &cnt) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int below = 0, b = -1;
+        for (int q = 0; q < 256; ++q) {
+            const int c = hist[q];
+            if (below + c >= need) {
+                b = q;
+                break;
+            }
+            below += c;
+        }
+        sh[0] = b;
+        sh[1] = b >= 0 ? need - below : need;
+        sh[2] = b >= 0 ? hist[b] : 0;
+    }
+    __syncthreads();
+    const int b = sh[0];
+    need = sh[1];
+    cnt = sh[2];
+    __syncthreads();
+    return b;
+}
+
+__global__ __launch_bounds__(kNpThreads) void np_kernel(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                        const double2 *__restrict__ p, int ns,
+                                                        const int *__restrict__ sample, int2 *res) {
+    __shared__ int hist[256];
+    __shared__ int sh[4];
+    for (int q = blockIdx.x; q < ns; q += gridDim.x) {   // uniform over the block
+        const int i = sample ? sample[q] : q;
+        const int k = rp[i + 1] - rp[i];
+        if (k == 0) {
+            if (threadIdx.x == 0) res[q] = int2{0, 0};
+            continue;
+        }
+        const double2 pi = p[i];
+        u64 tau = ~0ull;
+        int id_thr = 0x7fffffff;
+        if (k <= n - 1) {
+            // d2 bits, most significant byte first
+            u64 pre = 0, msk = 0;
+            int need = k, cnt = 0;
+            for (int sft = 56; sft >= 0; sft -= 8) {
+                if (threadIdx.x < 256) hist[threadIdx.x] = 0;
+                __syncthreads();
+                for (int v = threadIdx.x; v < n; v += blockDim.x) {
+                    if (v == i) continue;
+                    const u64 kb = d2_bits(pi, p[v]);
+                    if ((kb & msk) == pre) atomicAdd(&hist[(int)((kb >> sft) & 255ull)], 1);
+                }
+                const int b = np_pick(hist, sh, need, cnt);
+                pre |= (u64)b << sft;
+                msk |= 255ull << sft;
+            }
+            tau = pre;
+            if (need < cnt) {
+                // only the `need` smallest ids of the run with d2 == tau are in L(i)
+                int ipre = 0, imsk = 0;
+                for (int sft = 24; sft >= 0; sft -= 8) {
+                    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
+                    __syncthreads();
+                    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+                        if (v == i || (v & imsk) != ipre) continue;
+                        if (d2_bits(pi, p[v]) == tau) atomicAdd(&hist[(v >> sft) & 255], 1);
+                    }
+                    const int b = np_pick(hist, sh, need, cnt);
+                    ipre |= b << sft;
+                    imsk |= 255 << sft;
+                }
+                id_thr = ipre;
+            }
+        }
+        // neighbours inside L(i)
+        if (threadIdx.x == 0) sh[3] = 0;
+        __syncthreads();
+        int both = 0;
+        for (int e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) {
+            const int j = ci[e];
+            const u64 kb = d2_bits(pi, p[j]);
+            both += (kb < tau || (kb == tau && j <= id_thr)) ? 1 : 0;
+        }
+        both = wave_sum(both);
+        if ((threadIdx.x & (kWave - 1)) == 0 && both) atomicAdd(&sh[3], both);
+        __syncthreads();
+        if (threadIdx.x == 0) res[q] = int2{sh[3], k};
+        __syncthreads();
+    }
+}
+
+// Mean of the per-vertex Jaccard indices over vertices with k > 0, in a fixed
+// order: thread t sums its contiguous share in order, then thread 0 adds the
+// shares in thread order.  out[0] = sum, cnt[0] = vertices counted.
+__global__ __launch_bounds__(256) void np_sum_kernel(int ns, const int2 *__restrict__ res, double *out, u64 *cnt) {
+    __shared__ double ps[256];
+    __shared__ u64 pc[256];
+    const int per = (ns + 255) / 256;
+    const int q0 = threadIdx.x * per, q1 = min(ns, q0 + per);
+    double sum = 0.0;
+    u64 c = 0;
+    for (int q = q0; q < q1; ++q) {
+        const int2 r = res[q];
+        if (r.y > 0) {
+            sum += (double)r.x / (double)(2 * r.y - r.x);
+            ++c;
+        }
+    }
+    ps[threadIdx.x] = sum;
+    pc[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        u64 tc = 0;
+        for (int q = 0; q < 256; ++q) {
+            t += ps[q];
+            tc += pc[q];
+        }
+        out[0] = t;
+        cnt[0] = tc;
+    }
+}
+
 }  // namespace
 }  // namespace bl
 
@@ -665,4 +814,60 @@ extern "C" int bl_quality_eval_noalloc(const bl_csr *g, const double *x, const d
     w.heavy = heavy;
     w.nheavy = hf[1];
     return quality_compute(n, nnz, npivots, K, w, s, out);
+}
+
+extern "C" int bl_neighborhood_preservation(const bl_csr *g, const double *x, const double *y, int32_t nsample,
+                                            const int32_t *sample, uint32_t flags, void *hip_stream,
+                                            double *np_out, int64_t *counted) {
+    using namespace bl;
+    if (!np_out) return fail_code(BL_E_INVAL, "np_out is NULL");
+    *np_out = 0.0;
+    if (counted) *counted = 0;
+    if (!x || !y) return fail_code(BL_E_INVAL, "coordinate arrays are NULL");
+    if (flags & ~BL_DEVICE_PTRS) return fail_code(BL_E_INVAL, "unknown flags");
+    if (nsample < 0 || (nsample > 0 && !sample)) return fail_code(BL_E_INVAL, "bad sample list");
+    hipStream_t s = (hipStream_t)hip_stream;
+    BL_TRY(check_csr(g, flags, s));
+    const int n = g->n;
+    const int64_t nnz = g->nnz;
+    for (int q = 0; q < nsample; ++q)
+        if (sample[q] < 0 || sample[q] >= n) return fail_code(BL_E_INVAL, "sample vertex out of range");
+    const bool dev = (flags & BL_DEVICE_PTRS) != 0;
+    const hipMemcpyKind h2d = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const int ns = nsample > 0 ? nsample : n;
+
+    QBuffers B;
+    int *rp, *ci, *smp = nullptr;
+    double *dx, *dy, *sum;
+    double2 *p;
+    int2 *res;
+    u64 *cnt;
+    BL_TRY(B.alloc((void **)&rp, sizeof(int) * (size_t)(n + 1)));
+    BL_TRY(B.alloc((void **)&ci, sizeof(int) * (size_t)nnz));
+    BL_TRY(B.alloc((void **)&dx, sizeof(double) * (size_t)n));
+    BL_TRY(B.alloc((void **)&dy, sizeof(double) * (size_t)n));
+    BL_TRY(B.alloc((void **)&p, sizeof(double2) * (size_t)n));
+    BL_TRY(B.alloc((void **)&res, sizeof(int2) * (size_t)ns));
+    BL_TRY(B.alloc((void **)&sum, sizeof(double)));
+    BL_TRY(B.alloc((void **)&cnt, sizeof(u64)));
+    if (nsample > 0) {
+        BL_TRY(B.alloc((void **)&smp, sizeof(int) * (size_t)nsample));
+        BL_HIP(hipMemcpyAsync(smp, sample, sizeof(int) * (size_t)nsample, hipMemcpyHostToDevice, s));
+    }
+    BL_HIP(hipMemcpyAsync(rp, g->rowptr, sizeof(int) * (size_t)(n + 1), h2d, s));
+    if (nnz) BL_HIP(hipMemcpyAsync(ci, g->colidx, sizeof(int) * (size_t)nnz, h2d, s));
+    BL_HIP(hipMemcpyAsync(dx, x, sizeof(double) * (size_t)n, h2d, s));
+    BL_HIP(hipMemcpyAsync(dy, y, sizeof(double) * (size_t)n, h2d, s));
+    hipLaunchKernelGGL(pos_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, dx, dy, p);
+    hipLaunchKernelGGL(np_kernel, dim3(std::min(ns, 4096)), dim3(kNpThreads), 0, s, n, rp, ci, p, ns, smp, res);
+    hipLaunchKernelGGL(np_sum_kernel, dim3(1), dim3(256), 0, s, ns, res, sum, cnt);
+    double h = 0.0;
+    u64 c = 0;
+    BL_HIP(hipMemcpyAsync(&h, sum, sizeof h, hipMemcpyDeviceToHost, s));
+    BL_HIP(hipMemcpyAsync(&c, cnt, sizeof c, hipMemcpyDeviceToHost, s));
+    BL_HIP(hipStreamSynchronize(s));
+    BL_HIP(hipGetLastError());
+    *np_out = c ? h / (double)c : 0.0;
+    if (counted) *counted = (int64_t)c;
+    return BL_OK;
 }
