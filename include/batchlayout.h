@@ -107,10 +107,10 @@ typedef struct {
     int32_t model_r;         /* magnitude d^a / K, repulsion magnitude R K^2 d^r
                                 (r read as the power of d in the force, so the
                                 default (2, -1) is Fruchterman-Reingold).
-                                Integers, -8 <= r < a <= 8.  Other models than
-                                (2, -1) run in exact mode through bl_layout,
-                                bl_forces and bl_graph_* only; Barnes-Hut,
-                                bl_layout_batch and the server reject them.     */
+                                Integers, -8 <= r < a <= 8, in exact and
+                                Barnes-Hut mode, on every path (an accepted
+                                Barnes-Hut cell adds count times the repulsion
+                                at its centroid).                                */
     int32_t reserved[2];     /* must be zero                                     */
 } bl_params;
 

@@ -120,8 +120,6 @@ extern "C" int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const dou
         if (params[q]->flags & BL_DEVICE_PTRS)
             return fail_code(BL_E_INVAL, "bl_layout_batch takes host arrays only");
         BL_TRY(params_check(params[q]));
-        if (model_general(*params[q]))
-            return fail_code(BL_E_INVAL, "bl_layout_batch runs the (2, -1) model only");
         if (params[q]->flags & BL_ADAPTIVE_STEP)
             return fail_code(BL_E_INVAL, "BL_ADAPTIVE_STEP is a bl_layout option");
     }
@@ -149,7 +147,7 @@ extern "C" int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const dou
     for (int q = 0; q < G; ++q) {
         bl_graph *g = B.gs[q];
         if (g->p.mode == BL_BH) bhs.push_back(g);
-        else if (g->n <= kWGMaxN) {
+        else if (g->n <= kWGMaxN && !model_general(g->p)) {   // the one-workgroup kernel runs (2, -1)
             wg[g->p.precision].push_back(g);
             wg_idx[g->p.precision].push_back(q);
         } else big.push_back(g);

@@ -73,6 +73,8 @@ static_assert(kMaxChainRows <= 1024, "batch_offsets_kernel takes one row per thr
 struct BHJob {
     int n, BS, nb, tiles, sblocks;
     float theta2, negRK2, invK;
+    int ka, kr;                 // (a, r) model of Sec. 2.2: attraction d^ka, repulsion d^kr times (c_j - c_i)
+    int general;                // 1 unless (a, r) = (2, -1): the kernels' general-model instantiations run it
     int snapshot_leaves;        // leaves use the snapshot (no late lists)
     int all_live;               // one-shot force call: every leaf and neighbour is live
     int first_batch, last_batch, stop_batch;
@@ -650,13 +652,21 @@ struct WalkArgs {
     gptr<const int2> nodeB;
     gptr<const int> leafpos;
     float theta2, negRK2, invK;
+    int kr;
 };
 
-// Repulsion kernel term (c_j - c_i)/|c_j - c_i|^2 times `mult`, compensated.
-__device__ __forceinline__ void rep_add(float dx, float dy, float mult, float &sx, float &cx,
+// Repulsion kernel term (c_j - c_i)/|c_j - c_i|^2 times `mult`, compensated;
+// under a general model (GM) the kernel is |c_j - c_i|^kr (c_j - c_i).
+template <bool GM>
+__device__ __forceinline__ void rep_add(float dx, float dy, float mult, int kr, float &sx, float &cx,
                                         float &sy, float &cy) {
-    const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-    const float inv = __builtin_amdgcn_rcpf(d2) * mult;
+    float inv;
+    if constexpr (GM) {
+        inv = dpow(dx, dy, kr) * mult;
+    } else {
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+        inv = __builtin_amdgcn_rcpf(d2) * mult;
+    }
     kahan_add(sx, cx, dx * inv);
     kahan_add(sy, cy, dy * inv);
 }
@@ -665,6 +675,7 @@ __device__ __forceinline__ void rep_add(float dx, float dy, float mult, float &s
 // live == nullptr: far-field mode -- leaves of vertices j with id < late_below
 // (already moved this iteration) are appended to late[] instead of summed.
 // live != nullptr: every leaf uses live coordinates.
+template <bool GM>
 __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_below,
                        gptr<const float2> live, float4 &acc, gptr<int> late, int &nlate, int cap,
                        int *tests = nullptr) {
@@ -682,12 +693,12 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
             if (j != i) {
                 if (live) {
                     const float2 pj = ld<float2>(live, j);
-                    rep_add(pj.x - xi, pj.y - yi, 1.f, sx, cx, sy, cy);
+                    rep_add<GM>(pj.x - xi, pj.y - yi, 1.f, a.kr, sx, cx, sy, cy);
                 } else if (j < late_below) {
                     if (nlate < cap) late[nlate] = j;
                     ++nlate;
                 } else {
-                    rep_add(A.x - xi, A.y - yi, 1.f, sx, cx, sy, cy);
+                    rep_add<GM>(A.x - xi, A.y - yi, 1.f, a.kr, sx, cx, sy, cy);
                 }
             }
             ++v;
@@ -701,7 +712,7 @@ __device__ int bh_walk(const WalkArgs &a, int i, float xi, float yi, int late_be
             const float dx = (A.x - xi) + lox, dy = (A.y - yi) + loy;
             const float d2 = dx * dx + dy * dy;
             if (A.z < a.theta2 * d2) {
-                rep_add(dx, dy, (float)(-B.y), sx, cx, sy, cy);
+                rep_add<GM>(dx, dy, (float)(-B.y), a.kr, sx, cx, sy, cy);
                 v = B.x;
             } else {
                 ++v;
@@ -724,11 +735,16 @@ __device__ __forceinline__ WalkArgs walk_args(const BHJob &J) {
     w.theta2 = J.theta2;
     w.negRK2 = J.negRK2;
     w.invK = J.invK;
+    w.kr = J.kr;
     return w;
 }
 
+// GM: this instantiation serves the jobs with J.general == GM (the other
+// instantiation's jobs leave at once).
+template <bool GM>
 __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
+    if (J.general != (int)GM) return;
     const WalkArgs a = walk_args(J);
     const int p = jb.local * blockDim.x + threadIdx.x;
     int visits = 0, ovf = 0, lat = 0, tests = 0;
@@ -738,8 +754,8 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
         float4 acc;
         int nlate = 0;
         const float2 pi = ld<float2>(J.pos, i);
-        visits = bh_walk(a, i, pi.x, pi.y, late_below, nullptr, acc, J.late_ids + (size_t)i * kLateCap, nlate,
-                         kLateCap, &tests);
+        visits = bh_walk<GM>(a, i, pi.x, pi.y, late_below, nullptr, acc, J.late_ids + (size_t)i * kLateCap, nlate,
+                             kLateCap, &tests);
         st<float4>(J.far, i, acc);
         J.late_cnt[i] = nlate;
         ovf = nlate > kLateCap;
@@ -804,7 +820,7 @@ __global__ void late_prefix_kernel(BH_KERNEL_ARGS) {
 // Light rows: 8 lanes per row.
 // Attraction terms of one lane's entries e, e + S, e + 2S, ... below e1, in
 // that order; U entries' loads are issued before their terms are added.
-template <int U, int S>
+template <int U, int S, bool GM>
 __device__ __forceinline__ void att_run(const BHJob &J, int e, int e1, float2 pi, float invK, float &ax, float &ay) {
     for (; e < e1; e += U * S) {
         int c[U];
@@ -818,7 +834,9 @@ __device__ __forceinline__ void att_run(const BHJob &J, int e, int e1, float2 pi
         for (int u = 0; u < U; ++u) {
             if (c[u] >= 0) {
                 const float dx = pj[u].x - pi.x, dy = pj[u].y - pi.y;
-                const float d = sqrtf(dx * dx + dy * dy) * invK;
+                float d;
+                if constexpr (GM) d = dpow(dx, dy, J.ka) * invK;   // d^(a-1) / K
+                else d = sqrtf(dx * dx + dy * dy) * invK;
                 ax = fmaf(d, dx, ax);
                 ay = fmaf(d, dy, ay);
             }
@@ -826,8 +844,10 @@ __device__ __forceinline__ void att_run(const BHJob &J, int e, int e1, float2 pi
     }
 }
 
+template <bool GM>
 __global__ __launch_bounds__(256) void att_early_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
+    if (J.general != (int)GM) return;
     const int i = (jb.local * blockDim.x + threadIdx.x) >> 3;
     const int sub = threadIdx.x & 7;
     if (i >= J.n) return;
@@ -836,15 +856,17 @@ __global__ __launch_bounds__(256) void att_early_kernel(BH_KERNEL_ARGS) {
     const float2 pi = ld<float2>(J.pos, i);
     const float invK = J.invK;
     float ax = 0.f, ay = 0.f;
-    att_run<4, 8>(J, e0 + sub, e1, pi, invK, ax, ay);
+    att_run<4, 8, GM>(J, e0 + sub, e1, pi, invK, ax, ay);
     ax = group_sum<8>(ax);
     ay = group_sum<8>(ay);
     if (sub == 0) st<float2>(J.atte, i, float2{ax, ay});
 }
 
 // Heavy rows: one workgroup per row, reduced in a fixed order.
+template <bool GM>
 __global__ __launch_bounds__(256) void att_heavy_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
+    if (J.general != (int)GM) return;
     __shared__ float wsx[4], wsy[4];
     const int nh = *J.nheavy;
     const float invK = J.invK;
@@ -853,7 +875,7 @@ __global__ __launch_bounds__(256) void att_heavy_kernel(BH_KERNEL_ARGS) {
         const int e0 = J.rowptr[i] + J.late_att[i], e1 = J.rowptr[i + 1];
         const float2 pi = ld<float2>(J.pos, i);
         float ax = 0.f, ay = 0.f;
-        att_run<8, 256>(J, e0 + (int)threadIdx.x, e1, pi, invK, ax, ay);
+        att_run<8, 256, GM>(J, e0 + (int)threadIdx.x, e1, pi, invK, ax, ay);
         ax = wave_sum(ax);
         ay = wave_sum(ay);
         if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -1053,11 +1075,34 @@ struct PosL {
     __device__ __forceinline__ float2 operator()(int j) const { return w[j - base]; }
 };
 
-template <int KE, typename P>
+// Under a general model (GM) the terms are d^ka delta / K and -R K^2 d^kr delta.
+template <bool GM>
+__device__ __forceinline__ void entry_term(unsigned long long w, float dx, float dy, float invK, float negRK2,
+                                           int ka, int kr, float &ax, float &ay) {
+    if ((((unsigned)w) & 0x80000000u) == 0u) {
+        float d;
+        if constexpr (GM) d = dpow(dx, dy, ka) * invK;
+        else d = sqrtf(fmaf(dx, dx, dy * dy)) * invK;
+        ax = fmaf(d, dx, ax);
+        ay = fmaf(d, dy, ay);
+    } else {
+        float inv;
+        if constexpr (GM) {
+            inv = dpow(dx, dy, kr) * negRK2;
+        } else {
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+            inv = __builtin_amdgcn_rcpf(d2) * negRK2;
+        }
+        ax = fmaf(dx, inv, ax);
+        ay = fmaf(dy, inv, ay);
+    }
+}
+
+template <int KE, typename P, bool GM>
 __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, P pos, int e0, int e1,
                                         unsigned long long (&w)[KE], float (&xj)[KE], float (&yj)[KE],
                                         const int *off, const float *px, const float *py, float2 *sum,
-                                        float2 &first, float2 *cl, float invK, float negRK2) {
+                                        float2 &first, float2 *cl, float invK, float negRK2, int ka, int kr) {
     first = float2{0.f, 0.f};
     if (e0 >= e1) return;
     const int tid = threadIdx.x;
@@ -1093,16 +1138,7 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, P po
                     r = rq;
                 }
                 const float dx = xj[q] - px[r], dy = yj[q] - py[r];
-                if (((unsigned)w[q] & 0x80000000u) == 0u) {
-                    const float d = sqrtf(fmaf(dx, dx, dy * dy)) * invK;
-                    ax = fmaf(d, dx, ax);
-                    ay = fmaf(d, dy, ay);
-                } else {
-                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-                    const float inv = __builtin_amdgcn_rcpf(d2) * negRK2;
-                    ax = fmaf(dx, inv, ax);
-                    ay = fmaf(dy, inv, ay);
-                }
+                entry_term<GM>(w[q], dx, dy, invK, negRK2, ka, kr, ax, ay);
             }
         }
     }
@@ -1200,8 +1236,10 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
 // position is final.  The range's entries are split into equal runs, summed
 // per row with live positions, the runs' partial rows combined by the carry
 // scan; each row's total goes to oldsum.
+template <bool GM>
 __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     BH_JOB();
+    if (J.general != (int)GM) return;
     __shared__ int off[kMaxChainRows + 1];
     __shared__ float px[kMaxChainRows], py[kMaxChainRows];
     __shared__ float2 sum[kMaxChainRows];
@@ -1251,7 +1289,8 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     __syncthreads();
     const int key0 = e0 < e1 ? (int)(w[0] >> 32) : -1 - tid;
     float2 firstp;
-    run_sum<kEntH>(J.ent + base, PosG{J.pos}, e0, e1, w, xj, yj, off, px, py, sum, firstp, cl, J.invK, J.negRK2);
+    run_sum<kEntH, PosG, GM>(J.ent + base, PosG{J.pos}, e0, e1, w, xj, yj, off, px, py, sum, firstp, cl, J.invK,
+                             J.negRK2, J.ka, J.kr);
     carry_scan_wave(firstp, key0, loc, keys, wv, wk, wkf);
     __syncthreads();
     for (int r = rlo + tid; r < rhi; r += 256)
@@ -1273,8 +1312,10 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
 // a dependent load of them.  The step length of iteration k is step0 times
 // decay k times (the host uses the same product), k is read from and advanced
 // in device memory.
+template <bool GM>
 __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, int seg) {
     BH_JOB();
+    if (J.general != (int)GM) return;
     __shared__ ChainShared S;
     extern __shared__ float2 win[];   // dynamic: the segment's moved positions
     const int tid = threadIdx.x;
@@ -1412,26 +1453,17 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
                 if (e0 < e1) {
                     const int r = (int)(ce[0] >> 32);
                     const float dx = xj[0] - S.px[slot][r], dy = yj[0] - S.py[slot][r];
-                    float ax, ay;
-                    if (((unsigned)ce[0] & 0x80000000u) == 0u) {
-                        const float d = sqrtf(fmaf(dx, dx, dy * dy)) * invK;
-                        ax = fmaf(d, dx, 0.f);
-                        ay = fmaf(d, dy, 0.f);
-                    } else {
-                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-                        const float inv = __builtin_amdgcn_rcpf(d2) * negRK2;
-                        ax = fmaf(dx, inv, 0.f);
-                        ay = fmaf(dy, inv, 0.f);
-                    }
+                    float ax = 0.f, ay = 0.f;
+                    entry_term<GM>(ce[0], dx, dy, invK, negRK2, J.ka, J.kr, ax, ay);
                     if (S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1) S.sum[r] = float2{ax, ay};
                     else firstp = float2{ax, ay};
                 }
             } else if (use_win)
-                run_sum<kEnt>(lst, pl, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl,
-                              invK, negRK2);
+                run_sum<kEnt, PosL, GM>(lst, pl, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum,
+                                        firstp, S.cl, invK, negRK2, J.ka, J.kr);
             else
-                run_sum<kEnt>(lst, pg, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum, firstp, S.cl,
-                              invK, negRK2);
+                run_sum<kEnt, PosG, GM>(lst, pg, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum,
+                                        firstp, S.cl, invK, negRK2, J.ka, J.kr);
             carry_scan_wave(firstp, key0, S.scan, S.skey, S.wv, S.wk, S.wkf);
         }
         if (tid == 0) S.ovf[slot ^ 1] = 0;   // last read in the previous step
@@ -1454,7 +1486,7 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
             if (S.ovf[slot] && J.late_cnt[i] > kLateCap) {
                 float4 fr;
                 int dummy = 0;
-                (void)bh_walk(wa, i, x, y, 0, J.pos, fr, nullptr, dummy, 0);
+                (void)bh_walk<GM>(wa, i, x, y, 0, J.pos, fr, nullptr, dummy, 0);
                 fx += negRK2 * (fr.x - fr.z);
                 fy += negRK2 * (fr.y - fr.w);
             }
@@ -1540,6 +1572,7 @@ struct BHEngine {
     bool ev_used[2] = {false, false};
     int total[PT_COUNT] = {};
     int nseg = 1;                       // most chain segments of any job
+    int nkind[2] = {0, 0};              // jobs of the (2, -1) model, jobs of other (a, r) models
     size_t win_bytes = 0;               // chain window: the largest segment of any job
     hipGraph_t graph = nullptr;         // one captured iteration of the current set
     hipGraphExec_t exec = nullptr;
@@ -1567,12 +1600,14 @@ int bh_engine_create(hipStream_t s, BHEngine **out) {
         }
     }
     // the chain's window is dynamic LDS beyond the 64 KB default
-    hipError_t r = hipFuncSetAttribute((const void *)chain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(float2) * kWindow));
-    if (r != hipSuccess) {
-        bh_engine_destroy(e);
-        set_error("hipFuncSetAttribute(chain_kernel) failed: %s", hipGetErrorString(r));
-        return BL_E_HIP;
+    for (int kind = 0; kind < 2; ++kind) {
+        hipError_t r = hipFuncSetAttribute(kind ? (const void *)chain_kernel<true> : (const void *)chain_kernel<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float2) * kWindow));
+        if (r != hipSuccess) {
+            bh_engine_destroy(e);
+            set_error("hipFuncSetAttribute(chain_kernel) failed: %s", hipGetErrorString(r));
+            return BL_E_HIP;
+        }
     }
     *out = e;
     return BL_OK;
@@ -1604,6 +1639,9 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->theta2 = (decltype(J->theta2))((float)(g->p.theta * g->p.theta));
     J->negRK2 = (decltype(J->negRK2))((float)(-g->p.R * g->p.K * g->p.K));
     J->invK = (decltype(J->invK))((float)(1.0 / g->p.K));
+    J->ka = (decltype(J->ka))(g->p.model_a - 1);
+    J->kr = (decltype(J->kr))(g->p.model_r - 1);
+    J->general = (decltype(J->general))(model_general(g->p) ? 1 : 0);
     J->snapshot_leaves = (decltype(J->snapshot_leaves))((g->p.flags & BL_BH_SNAPSHOT_LEAVES) ? 1 : 0);
     J->all_live = (decltype(J->all_live))(spec.all_live);
     J->first_batch = (decltype(J->first_batch))(spec.first_batch);
@@ -1708,8 +1746,10 @@ int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
     }
     e->nseg = 1;
     e->win_bytes = 0;
+    e->nkind[0] = e->nkind[1] = 0;
     for (int j = 0; j < G; ++j) {
         const BHJob &J = jobs[j];
+        ++e->nkind[J.general ? 1 : 0];
         e->nseg = std::max(e->nseg, (int)J.nseg);
         if (!J.all_live)
             e->win_bytes = std::max(e->win_bytes, sizeof(float2) * (size_t)J.BS * ((J.nb + J.nseg - 1) / J.nseg));
@@ -1730,6 +1770,14 @@ int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
         if (e->total[type] > 0)                                                                     \
             hipLaunchKernelGGL(kernel, dim3(e->total[type]), dim3(threads), 0, e->stream, jobs,     \
                                e->d_pre[e->cur] + (type) * (e->cap + 1), e->G, ##__VA_ARGS__);      \
+    } while (0)
+
+// A kernel with an instantiation per model kind: each kind present in the
+// set gets its launch (the other kind's workgroups leave at once).
+#define BH_LAUNCH_M(kernel, type, threads, ...)                  \
+    do {                                                         \
+        if (e->nkind[0]) BH_LAUNCH(kernel<false>, type, threads, ##__VA_ARGS__); \
+        if (e->nkind[1]) BH_LAUNCH(kernel<true>, type, threads, ##__VA_ARGS__);  \
     } while (0)
 
 // Once per job set: lengths of the moved-neighbour CSR prefixes, heavy rows.
@@ -1765,10 +1813,10 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     BH_LAUNCH(emit_kernel, PT_VERT, 256);
     if (prof) BL_TRY(prof_end(prof, slot));
     if (prof) BL_TRY(prof_begin(prof, PK_FAR, &slot));
-    BH_LAUNCH(far_kernel, PT_VERT, 256);
+    BH_LAUNCH_M(far_kernel, PT_VERT, 256);
     if (prof) BL_TRY(prof_end(prof, slot));
-    BH_LAUNCH(att_early_kernel, PT_VERT8, 256);
-    BH_LAUNCH(att_heavy_kernel, PT_HEAVY, 256);
+    BH_LAUNCH_M(att_early_kernel, PT_VERT8, 256);
+    BH_LAUNCH_M(att_heavy_kernel, PT_HEAVY, 256);
     BH_LAUNCH(batch_offsets_kernel, PT_BATCH, 1024);
     BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 2);
     BH_LAUNCH(late_fill_kernel, PT_VERT8, 256);
@@ -1776,13 +1824,15 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     for (int seg = 0; seg < e->nseg; ++seg) {
         if (e->total[PT_SEG] > 0) {
             if (prof) BL_TRY(prof_begin(prof, PK_OLDSUM, &slot));
-            BH_LAUNCH(old_sum_kernel, PT_SEG, 256, seg);
+            BH_LAUNCH_M(old_sum_kernel, PT_SEG, 256, seg);
             if (prof) BL_TRY(prof_end(prof, slot));
         }
         if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
-        if (e->total[PT_ONE] > 0)
-            hipLaunchKernelGGL(chain_kernel, dim3(e->total[PT_ONE]), dim3(kChainThreads), e->win_bytes, e->stream,
-                               jobs, e->d_pre[e->cur] + PT_ONE * (e->cap + 1), e->G, seg);
+        for (int kind = 0; kind < 2; ++kind)
+            if (e->total[PT_ONE] > 0 && e->nkind[kind])
+                hipLaunchKernelGGL(kind ? chain_kernel<true> : chain_kernel<false>, dim3(e->total[PT_ONE]),
+                                   dim3(kChainThreads), e->win_bytes, e->stream, jobs,
+                                   e->d_pre[e->cur] + PT_ONE * (e->cap + 1), e->G, seg);
         if (prof) BL_TRY(prof_end(prof, slot));
     }
     BL_HIP(hipGetLastError());

@@ -76,8 +76,6 @@ int check_params(const bl_params *p) {
         if (p->reserved[q]) return fail(BL_E_INVAL, "reserved fields must be zero");
     if (!(p->model_r < p->model_a) || p->model_r < -8 || p->model_a > 8)
         return fail(BL_E_INVAL, "the (a, r) model needs integers -8 <= r < a <= 8");
-    if (p->mode == BL_BH && model_general(*p))
-        return fail(BL_E_INVAL, "Barnes-Hut mode runs the (2, -1) model only");
     return BL_OK;
 }
 

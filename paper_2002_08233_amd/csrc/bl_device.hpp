@@ -130,4 +130,25 @@ __device__ __forceinline__ double block_sum_fixed(double v, double *ws) {
     return r;
 }
 
+// The (a, r) model of Sec. 2.2 for integer exponents: |c_j - c_i|^k with
+// k = a - 1 (attraction) or r - 1 (repulsion kernel), from d^2 by k/2
+// multiplications (or their reciprocal: the hardware one in FP32, as in the
+// (2, -1) terms) and one square root for odd k; 0 for a coincident pair.  k
+// is uniform across the workgroup.
+template <typename T>
+__device__ __forceinline__ T dpow(T dx, T dy, int k) {
+    const T d2 = fma(dx, dx, dy * dy);
+    if (d2 == (T)0) return (T)0;
+    const int h = k >> 1;   // floor(k / 2)
+    const int m = h < 0 ? -h : h;
+    T p = 1;
+    for (int q = 0; q < m; ++q) p *= d2;
+    if (h < 0) {
+        if constexpr (sizeof(T) == 4) p = __builtin_amdgcn_rcpf(p);
+        else p = 1.0 / p;
+    }
+    if (k & 1) p *= sqrt(d2);
+    return p;
+}
+
 }  // namespace bl

@@ -359,7 +359,6 @@ int bl_server_submit(bl_server *s, const bl_csr *g, const double *x0, const doub
     BL_TRY(params_check(p));
     if (p->flags & BL_DEVICE_PTRS) return fail_code(BL_E_INVAL, "bl_server_submit takes host arrays only");
     if (p->conv_tol > 0) return fail_code(BL_E_INVAL, "the server runs a fixed number of iterations (conv_tol must be 0)");
-    if (model_general(*p)) return fail_code(BL_E_INVAL, "the server runs the (2, -1) model only");
     if (p->flags & BL_ADAPTIVE_STEP) return fail_code(BL_E_INVAL, "BL_ADAPTIVE_STEP is a bl_layout option");
     if (g->n < 1 || g->nnz < 0 || !g->rowptr || (g->nnz > 0 && !g->colidx))
         return fail_code(BL_E_INVAL, "bad graph");

@@ -183,16 +183,14 @@ def test_model_out_of_range_rejected(lib, a, r):
     assert b"model" in lib.bl_last_error()
 
 
-def test_general_model_only_in_single_graph_exact_mode(lib):
-    """(a, r) other than (2, -1): Barnes-Hut and the batched path reject it on the host."""
-    from paper_2002_08233_amd import _lib, api, inputs
+def test_default_model_is_fruchterman_reingold(lib):
+    """bl_params_init gives the (2, -1) model; a model outside -8 <= r < a <= 8
+    is rejected on the host in Barnes-Hut mode as in exact mode."""
+    from paper_2002_08233_amd import api, inputs
     p = api.params()
     assert (p.model_a, p.model_r) == (2, -1)
-    assert _call_layout(lib, inputs.path(5), api.params(iterations=1, mode="bh", model=(1, -1))) == -1
-    g = inputs.path(6)
-    x = np.zeros(6)
-    with pytest.raises(_lib.BLError, match="model"):
-        api.layout_batch([g], [x], [x], [api.params(iterations=1, model=(1, -1))])
+    assert _call_layout(lib, inputs.path(5), api.params(iterations=1, mode="bh", model=(1, 2))) == -1
+    assert b"model" in lib.bl_last_error()
 
 
 def test_shuffled_layout_host_checks(lib):

@@ -101,12 +101,3 @@ def test_default_model_is_fruchterman_reingold(ragged):
     a = api.layout(g, x, y, api.params(batch_size=96, iterations=3))
     b = api.layout(g, x, y, api.params(batch_size=96, iterations=3, model=(2, -1)))
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
-
-
-def test_server_rejects_other_models():
-    from paper_2002_08233_amd._lib import BLError
-    g = I.path(10)
-    x, y = I.uniform_coords(10, 1)
-    with api.Server(1 << 30) as s:
-        with pytest.raises(BLError, match="model"):
-            s.submit(g, x, y, api.params(iterations=5, model=(1, -1)))
