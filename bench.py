@@ -30,13 +30,12 @@ HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 FLOP (FMA) x 2.4 GHz, non-packed FP32
 FP64_VALU_PEAK_TFLOPS = 78.6     # MI355X vector FP64
 # Algorithmic work per unit (bytes a kernel must move, or FLOP it must do, per unit of work):
-BYTES_PER_VISIT = 24.0           # float4 (centroid hi, side^2, centroid lo) + int2 (skip, vertex or count) per node visit
+BYTES_PER_VISIT = 24.0           # a tree-node visit: centroid and side (16) + skip link and count or vertex (8)
 BYTES_PER_WALK_VERTEX = 32.0     # order id 4 + own x,y 8 + far-field sum 16 + late count 4
-BYTES_PER_LIST_WORD = 8.0        # late-list entry: row in batch << 32 | vertex (bit 31: leaf)
-BYTES_PER_GATHER = 8.0           # x,y of the vertex an entry refers to
-BYTES_PER_CHAIN_ROW = 56.0       # list offset 4 + leaf count 4 + x,y 8 + far sum 16 + early attraction 8
-                                 # + old sum 8 + x,y write 8 (recent gathers come from the LDS window)
-BYTES_PER_OLD_ROW = 20.0         # list offset 4 + x,y 8 + old sum write 8
+BYTES_PER_ENTRY = 12.0           # a CSR or moved-leaf entry: its id 4 + the x,y it gathers 8
+BYTES_PER_UPDATE = 16.0          # a vertex update: x,y read 8 + x,y written 8
+BYTES_PER_TREE_VERTEX = 200.0    # quadtree build per vertex and iteration: keys 8, four radix passes x 16,
+                                 # about two 24-byte nodes, their reads
 FLOP_PER_PAIR = 10.0             # 2 sub, d^2 (2 mul + 1 add), 1 reciprocal, 2 FMA
 
 
@@ -111,23 +110,10 @@ def describe(w, iters):
         "iterations": iters, "init": "seeded uniform [-1,1]^2 (float32-representable)"}
 
 
-def cpu_baseline(w, budget_s, quality_layout=None):
-    """The FP64 oracle, single-threaded, on the host: as many whole iterations of
-    the same workload as fit in the budget (at least one).  Also times, under
-    "other", the oracle's greedy initialisation of the graph and its stress
-    evaluator per BFS source (16 sources) on `quality_layout` when given."""
+def _oracle_iterations(w, budget_s):
+    """Whole iterations of the workload's oracle run from its start until the
+    budget is spent (at least one); returns (iterations, seconds)."""
     import oracle
-    g0 = w["graph"]
-    other = {}
-    t0 = time.perf_counter()
-    oracle.greedy_init(g0.rowptr, g0.colidx, 0, w["x0"], w["y0"])
-    other["greedy_init_seconds"] = time.perf_counter() - t0
-    if quality_layout is not None:
-        from paper_2002_08233_amd import inputs as I
-        sp = I.rng(11).integers(0, g0.n, 16).astype(np.int32)
-        t0 = time.perf_counter()
-        oracle.stress(g0.rowptr, g0.colidx, quality_layout[0], quality_layout[1], sp)
-        other["stress_seconds_per_source"] = (time.perf_counter() - t0) / len(sp)
     g = w["graph"]
     x, y = w["x0"].copy(), w["y0"].copy()
     done = 0
@@ -141,10 +127,40 @@ def cpu_baseline(w, budget_s, quality_layout=None):
         done += 1
         el = time.perf_counter() - t0
         if el >= budget_s or el / done * (done + 1) > 2.5 * budget_s:
-            break
-    return {"value": g.n * done / el, "unit": "force-updates/s", "cores": 1, "kind": "oracle",
+            return done, el
+
+
+def cpu_baseline(w, budget_s, quality_layout=None):
+    """The FP64 oracle on the host: as many whole iterations of the same
+    workload as fit in the budget (at least one), on the oracle's OpenMP
+    threads (OMP_NUM_THREADS, else one per host core; results do not depend
+    on the count), and again on one thread.  Also times, under "other", the
+    oracle's greedy initialisation of the graph and its stress evaluator per
+    BFS source (16 sources) on `quality_layout` when given."""
+    import oracle
+    g0 = w["graph"]
+    other = {}
+    nthreads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+    t0 = time.perf_counter()
+    oracle.greedy_init(g0.rowptr, g0.colidx, 0, w["x0"], w["y0"])
+    other["greedy_init_seconds"] = time.perf_counter() - t0
+    if quality_layout is not None:
+        from paper_2002_08233_amd import inputs as I
+        sp = I.rng(11).integers(0, g0.n, 16).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.stress(g0.rowptr, g0.colidx, quality_layout[0], quality_layout[1], sp)
+        other["stress_seconds_per_source"] = (time.perf_counter() - t0) / len(sp)
+    g = w["graph"]
+    done, el = _oracle_iterations(w, budget_s)
+    oracle.set_threads(1)
+    done1, el1 = _oracle_iterations(w, budget_s)
+    oracle.set_threads(nthreads)
+    return {"value": g.n * done / el, "unit": "force-updates/s", "cores": nthreads, "kind": "oracle",
             "sample": "%d of %d iterations of the same workload from the same start, FP64 C oracle, "
-                      "1 thread, %.1f s" % (done, w["iterations"], el), "other": other}
+                      "%d OpenMP threads, %.1f s" % (done, w["iterations"], nthreads, el),
+            "one_thread": {"value": g.n * done1 / el1, "unit": "force-updates/s", "cores": 1,
+                           "sample": "%d iterations, 1 thread, %.1f s" % (done1, el1)},
+            "other": other}
 
 
 QUALITY_PIVOTS = 1024             # BFS pivots of the stress sample at 131072 vertices
@@ -232,72 +248,30 @@ def adaptive_report(api, w, p, steps, t=0.9):
             "energy_last_fixed_decay": float(ef[-1]) if len(ef) else None}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2-bh", choices=["c2-bh", "c2-exact", "c1", "c3", "c4", "c5"])
-    ap.add_argument("--batch-count", type=int, default=512, help="c4: graphs in the batch")
-    ap.add_argument("--plain-every", type=int, default=8, help="c4: run every k-th graph alone for the plain rate")
-    ap.add_argument("--serve-seconds", type=float, default=6.0, help="c5: length of the arrival window")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="c5: arrivals per second")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel hipEvent timing")
-    ap.add_argument("--profile-steps", type=int, default=100, help="iterations of the per-kernel timing run")
-    ap.add_argument("--no-end-to-end", action="store_true", help="skip the run through host arrays")
-    ap.add_argument("--no-greedy", action="store_true", help="skip the greedy-initialisation report")
-    ap.add_argument("--no-quality", action="store_true", help="skip the layout-quality report")
-    ap.add_argument("--precision", default="fp32_kahan")
-    ap.add_argument("--adaptive-steps", type=int, default=0,
-                    help="also run this many iterations with Hu's adaptive step (0: off)")
-    ap.add_argument("--shuffle-steps", type=int, default=0,
-                    help="also run this many iterations with randomised minibatches (0: off)")
-    ap.add_argument("--model", default="2,-1", help="exact mode: the (a, r) energy model, e.g. 1,-1")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
-                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs the layout of a graph on a single "
-              "MI355X; --gpus %d is not supported." % args.gpus, file=sys.stderr)
-        return 2
-
-    if args.copy_probe:
-        return copy_probe(args.copy_probe)
-    reqs = None
-    if args.config == "c5":
-        # request graphs are generated before anything touches the GPU
-        import multiprocessing as mp
-        from paper_2002_08233_amd import inputs as I
-        stream = I.served_stream(rate=args.serve_rate, duration=args.serve_seconds)
-        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 4)) as pool:
-            reqs = pool.map(_served_request, stream)
-
+def bench_single(args, api, config, steps=None, warmup=None, precision=None, extras=True):
+    """One workload's timed run on resident device buffers (the benchmark
+    step = one iteration of the whole path), with its per-kernel timing and,
+    when `extras`, the reports beside it.  Returns the JSON-ready dict."""
     import torch
-    from paper_2002_08233_amd import api
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    if args.config == "c4":
-        return bench_batched(args, api)
-    if args.config == "c5":
-        return bench_served(args, api, reqs)
-    w = workload(args.config)
+    w = workload(config)
+    if steps is None:
+        steps = args.steps if args.steps is not None else w["iterations"]
+    if warmup is None:
+        warmup = args.warmup
+    if precision is None:
+        precision = args.precision
     g = w["graph"]
     model = tuple(int(v) for v in args.model.split(","))
-    steps = args.steps if args.steps is not None else w["iterations"]
     p = api.params(batch_size=w["batch_size"], iterations=steps, mode=w["mode"],
-                   theta=w["theta"] if w["mode"] == "bh" else 1.2, precision=args.precision, model=model)
+                   theta=w["theta"] if w["mode"] == "bh" else 1.2, precision=precision, model=model)
 
     # inputs resident on the device before the timed region
     dev = api.Graph(g, p)
     x0 = torch.as_tensor(w["x0"], device="cuda")
     y0 = torch.as_tensor(w["y0"], device="cuda")
     dev.set_coords(x0, y0)
-    if args.warmup > 0:
-        dev.run(args.warmup)
+    if warmup > 0:
+        dev.run(warmup)
     dev.set_coords(x0, y0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -308,9 +282,9 @@ def main():
 
     value = g.n * steps / wall
     out = {"metric": METRIC, "value": value, "unit": "force-updates/s", "n_gpus": 1, "steps": steps,
-           "warmup": args.warmup, "ms_per_step": 1e3 * wall / max(steps, 1), "higher_is_better": True,
+           "warmup": warmup, "ms_per_step": 1e3 * wall / max(steps, 1), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+           "dtype": "f64" if precision == "fp64" else "f32", "data": "synthetic",
            "config": dict(describe(w, steps), model=list(model))}
 
     if not args.no_profile:
@@ -334,8 +308,8 @@ def main():
             tests = dev.profile_read("cell_tests")[1]
             rows = float(g.n) * psteps   # every row once per iteration in each kernel below
             work = {"far_kernel": BYTES_PER_VISIT * visits + BYTES_PER_WALK_VERTEX * rows,
-                    "chain_kernel": BYTES_PER_CHAIN_ROW * rows + BYTES_PER_LIST_WORD * recent_e,
-                    "old_sum_kernel": BYTES_PER_OLD_ROW * rows + (BYTES_PER_LIST_WORD + BYTES_PER_GATHER) * old_e}
+                    "chain_kernel": BYTES_PER_UPDATE * rows + BYTES_PER_ENTRY * recent_e,
+                    "old_sum_kernel": BYTES_PER_ENTRY * old_e}
             for k, total in work.items():
                 if k in kern:
                     kern[k]["bytes_per_launch"] = total / kern[k]["launches"]
@@ -344,7 +318,7 @@ def main():
             dom = kern[dom_name]
             out["roofline"] = {"bound": "hbm", "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": dom["achieved_GBs"] / HBM_PEAK_GBS,
-                               "traffic": measured_traffic(args.config, dom_name), "kernel": dom_name,
+                               "traffic": measured_traffic(config, dom_name), "kernel": dom_name,
                                "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
             nb = (g.n + w["batch_size"] - 1) // w["batch_size"]
             out["bh"] = {"node_visits_per_vertex": visits / rows, "cell_tests_per_vertex": tests / rows,
@@ -353,6 +327,16 @@ def main():
                          "old_entries_per_vertex": old_e / rows, "recent_entries_per_vertex": recent_e / rows,
                          "late_overflow": st["late_overflow"],
                          "chain_us_per_batch": 1e3 * kern["chain_kernel"]["total_ms"] / (nb * psteps)}
+            # the whole Barnes-Hut iteration on the same units: walks, every CSR
+            # entry's attraction, moved leaves, updates and the tree build
+            path_bytes = (BYTES_PER_VISIT * visits / psteps + BYTES_PER_ENTRY * (g.nnz + late / psteps)
+                          + (BYTES_PER_UPDATE + BYTES_PER_TREE_VERTEX) * g.n)
+            path_gbs = path_bytes / (1e-3 * out["ms_per_step"]) / 1e9
+            out["bh"]["path"] = {"algorithmic_bytes_per_iteration": path_bytes, "achieved_GBs": path_gbs,
+                                 "frac_of_hbm_peak": path_gbs / HBM_PEAK_GBS,
+                                 "note": "24 B per node visit, 12 B per CSR or moved-leaf entry, 16 B per "
+                                         "update and 200 B per vertex of tree build, over the timed "
+                                         "iteration time"}
         else:
             nb = (g.n + w["batch_size"] - 1) // w["batch_size"]
             pairs = float(g.n) * g.n * steps
@@ -370,18 +354,18 @@ def main():
                 flop_per_launch = flop_per_pair(model) * float(g.n) * g.n * psteps / dom["launches"]
             dom["achieved_TFLOPs"] = flop_per_launch / (dom["avg_us"] * 1e-6) / 1e12
             dom["flop_per_launch"] = flop_per_launch
-            peak = FP32_VALU_PEAK_TFLOPS if args.precision != "fp64" else FP64_VALU_PEAK_TFLOPS
+            peak = FP32_VALU_PEAK_TFLOPS if precision != "fp64" else FP64_VALU_PEAK_TFLOPS
             out["roofline"] = {"bound": "alu", "achieved": dom["achieved_TFLOPs"], "peak": peak,
                                "unit": "TFLOP/s", "frac": dom["achieved_TFLOPs"] / peak,
-                               "traffic": measured_traffic(args.config, dom_name.split("<")[0]), "kernel": dom_name,
+                               "traffic": measured_traffic(config, dom_name.split("<")[0]), "kernel": dom_name,
                                "frac_of_packed_fp32_peak": (dom["achieved_TFLOPs"] / 157.3
-                                                            if args.precision != "fp64" else None)}
+                                                            if precision != "fp64" else None)}
             out["exact"] = {"pairs_per_s": pairs / wall, "batches_per_iteration": nb}
         out["kernels"] = kern
         dev.profile(False)   # (this also clears the totals just read)
     out["energy_last"] = float(energy[-1]) if len(energy) else None
 
-    if not args.no_end_to_end:
+    if extras and not args.no_end_to_end:
         # the same run through the host-array boundary: graph and coordinates
         # uploaded, the run, coordinates copied back (never the headline value)
         torch.cuda.synchronize()
@@ -391,19 +375,121 @@ def main():
         out["end_to_end"] = {"force_updates_per_s": g.n * steps / e2e, "seconds": e2e,
                              "note": "bl_layout from host arrays: CSR and coordinates uploaded, "
                                      "device state built, the run, coordinates back"}
-    if args.shuffle_steps > 0:
+    if extras and args.shuffle_steps > 0:
         out["shuffled"] = shuffle_report(api, w, p, args.shuffle_steps)
-    if args.adaptive_steps > 0:
+    if extras and args.adaptive_steps > 0:
         out["adaptive"] = adaptive_report(api, w, p, args.adaptive_steps)
-    if not args.no_quality:
+    if extras and not args.no_quality:
         out["quality"] = quality_report(api, g, xf, yf)
-    if not args.no_greedy:
+    if extras and not args.no_greedy:
         out["greedy_init"] = greedy_report(api, w, p, steps, float(energy[-1]) if len(energy) else None)
-    if args.config == "c3" and args.precision == "fp32_kahan":
-        out["precision"] = precision_report(api, w, dev, x0, y0, min(steps, 20))
-    if not args.no_cpu_baseline:
+    if extras and config == "c3" and precision == "fp32_kahan" and not args.no_precision:
+        out["precision"] = precision_report(api, w, x0, y0, w["iterations"])
+    if extras and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, None if args.no_quality else (xf, yf))
     dev.close()
+    return out
+
+
+def other_configs(args, api, reqs):
+    """Compact measurements of the other workloads, for the default line:
+    rgg64k exact (all 300 iterations, with the three-precision comparison
+    against the oracle's full runs), rmat17 exact, grid32 exact, the 512
+    uneven graphs batched against the same graphs alone, and a short served
+    stream against its requests alone."""
+    keep = ("value", "unit", "steps", "ms_per_step", "dtype", "config", "roofline", "exact", "precision",
+            "energy_last")
+    res = {}
+    for name in ("c3", "c2-exact", "c1"):
+        t0 = time.perf_counter()
+        # rgg64k and grid32 run all their iterations (under two seconds); rmat17
+        # exact the timed iterations of the line (6 ms each)
+        steps = workload(name)["iterations"] if name != "c2-exact" else (args.steps if args.steps is not None else 20)
+        r = bench_single(args, api, name, steps=steps, warmup=1, precision="fp32_kahan", extras=False)
+        if name == "c3" and not args.no_precision:
+            import torch
+            w = workload(name)
+            x0 = torch.as_tensor(w["x0"], device="cuda")
+            y0 = torch.as_tensor(w["y0"], device="cuda")
+            r["precision"] = precision_report(api, w, x0, y0, w["iterations"])
+        r = {k: v for k, v in r.items() if k in keep}
+        r["wall_seconds"] = time.perf_counter() - t0
+        res[name] = r
+    t0 = time.perf_counter()
+    res["c4"] = {k: v for k, v in bench_batched(args, api).items() if k != "metric"}
+    res["c4"]["wall_seconds"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res["c5"] = {k: v for k, v in bench_served(args, api, reqs, window=args.compact_serve_seconds).items()
+                 if k != "metric"}
+    res["c5"]["wall_seconds"] = time.perf_counter() - t0
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2-bh", choices=["c2-bh", "c2-exact", "c1", "c3", "c4", "c5"])
+    ap.add_argument("--batch-count", type=int, default=512, help="c4: graphs in the batch")
+    ap.add_argument("--plain-every", type=int, default=8, help="c4: run every k-th graph alone for the plain rate")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="c5: length of the arrival window")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="c5: arrivals per second")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel hipEvent timing")
+    ap.add_argument("--profile-steps", type=int, default=100, help="iterations of the per-kernel timing run")
+    ap.add_argument("--no-end-to-end", action="store_true", help="skip the run through host arrays")
+    ap.add_argument("--no-greedy", action="store_true", help="skip the greedy-initialisation report")
+    ap.add_argument("--no-quality", action="store_true", help="skip the layout-quality report")
+    ap.add_argument("--precision", default="fp32_kahan")
+    ap.add_argument("--adaptive-steps", type=int, default=0,
+                    help="also run this many iterations with Hu's adaptive step (0: off)")
+    ap.add_argument("--shuffle-steps", type=int, default=0,
+                    help="also run this many iterations with randomised minibatches (0: off)")
+    ap.add_argument("--model", default="2,-1", help="exact mode: the (a, r) energy model, e.g. 1,-1")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="default run: skip the compact measurements of the other workloads")
+    ap.add_argument("--compact-serve-seconds", type=float, default=6.0,
+                    help="default run: arrival window of the compact served measurement")
+    ap.add_argument("--no-precision", action="store_true", help="c3: skip the three-precision comparison")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the layout of a graph on a single "
+              "MI355X; --gpus %d is not supported." % args.gpus, file=sys.stderr)
+        return 2
+
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
+    reqs = None
+    if args.config == "c5" or (args.config == "c2-bh" and not args.no_other_configs):
+        # request graphs are generated before anything touches the GPU
+        import multiprocessing as mp
+        from paper_2002_08233_amd import inputs as I
+        secs = args.serve_seconds if args.config == "c5" else args.compact_serve_seconds
+        stream = I.served_stream(rate=args.serve_rate, duration=secs)
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 4)) as pool:
+            reqs = pool.map(_served_request, stream)
+
+    import torch
+    from paper_2002_08233_amd import api
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.config == "c4":
+        print(json.dumps(bench_batched(args, api)))
+        return 0
+    if args.config == "c5":
+        print(json.dumps(bench_served(args, api, reqs)))
+        return 0
+    if args.config == "c2-bh" and not args.no_other_configs:
+        out = bench_single(args, api, "c2-bh")
+        out["other_configs"] = other_configs(args, api, reqs)
+    else:
+        out = bench_single(args, api, args.config)
     print(json.dumps(out))
     return 0
 
@@ -430,12 +516,17 @@ def edge_energy(g, x, y):
     return float(np.sum(d ** 3) / 3.0)
 
 
-def precision_report(api, w, dev, x0, y0, iters):
+def precision_report(api, w, x0, y0, iters):
     """The same iterations in FP32 with compensated sums, plain FP32 and FP64
-    on the GPU: throughput of each, and the FP32 results' deviation from the
-    FP64 run (final edge energy, per-iteration energy, coordinates)."""
+    on the GPU: throughput of each; the final layout's stress (Sec. 3.7, 1024
+    seeded pivots) and edge energy, from the GPU evaluator, against the FP64
+    oracle's full run of the workload and the spread of its one-ulp-perturbed
+    runs (tests/golden/fullrun_<workload>.json, written by the oracle alone)
+    when the run is the full one; and the FP32 runs' deviation from the FP64
+    run on the GPU (per-iteration energy, coordinates)."""
     import numpy as np
     import torch
+    from paper_2002_08233_amd import inputs as I
     g = w["graph"]
     res = {}
     for prec in ("fp32_kahan", "fp32", "fp64"):
@@ -449,19 +540,36 @@ def precision_report(api, w, dev, x0, y0, iters):
             dt = time.perf_counter() - t0
             x, y = h.get_coords()
         res[prec] = dict(x=x, y=y, en=en, fu_s=g.n * iters / dt)
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "fullrun_%s.json" % w["name"].split("-")[0])
+    if iters == w["iterations"] and os.path.exists(gpath):
+        with open(gpath) as f:
+            gold = json.load(f)
+    piv = I.stress_pivots(g.n) if g.n > 65536 or gold is not None else None
     ref = res["fp64"]
     ext = max(np.ptp(ref["x"]), np.ptp(ref["y"]))
-    ee64 = edge_energy(g, ref["x"], ref["y"])
-    out = {"iterations": iters, "reference": "fp64 on the GPU"}
+    out = {"iterations": iters, "reference": "fp64 on the GPU; oracle full run when the run is the full one",
+           "stress_sources": "all pairs" if piv is None else "%d pivots" % len(piv)}
+    if gold is not None:
+        out["oracle"] = {k: {"run": gold["runs"][0][k], "min": min(r[k] for r in gold["runs"]),
+                             "max": max(r[k] for r in gold["runs"]), "spread": gold["spread"][k]}
+                         for k in ("stress", "edge_energy")}
     for prec in ("fp32_kahan", "fp32", "fp64"):
         r = res[prec]
-        out[prec] = {"force_updates_per_s": r["fu_s"]}
+        q = api.quality(g, r["x"], r["y"], piv)
+        o = {"force_updates_per_s": r["fu_s"], "stress": q["stress"], "edge_energy": q["edge_energy"]}
+        if gold is not None:
+            for k in ("stress", "edge_energy"):
+                o[k + "_dev_from_oracle"] = o[k] / gold["runs"][0][k] - 1
+                lo = min(x[k] for x in gold["runs"]) * 0.99
+                hi = max(x[k] for x in gold["runs"]) * 1.01
+                o[k + "_within_1pct_of_oracle_range"] = bool(lo <= o[k] <= hi)
         if prec != "fp64":
-            out[prec].update({
-                "edge_energy_rel_dev": abs(edge_energy(g, r["x"], r["y"]) / ee64 - 1),
-                "energy_rel_dev_max": float(np.max(np.abs(r["en"] / ref["en"] - 1))),
-                "coord_rms_dev_over_extent": float(np.sqrt(np.mean((r["x"] - ref["x"]) ** 2 +
-                                                                   (r["y"] - ref["y"]) ** 2)) / ext)})
+            o.update({
+                "energy_rel_dev_from_fp64_max": float(np.max(np.abs(r["en"] / ref["en"] - 1))),
+                "coord_rms_dev_from_fp64_over_extent": float(np.sqrt(np.mean((r["x"] - ref["x"]) ** 2 +
+                                                                             (r["y"] - ref["y"]) ** 2)) / ext)})
+        out[prec] = o
     return out
 
 
@@ -507,8 +615,7 @@ def bench_batched(args, api):
                      "note": "each sampled graph alone through bl_layout, device time summed"},
            "speedup_vs_plain": value / plain, "equal_stress": "bitwise-identical layouts" if same else "MISMATCH",
            "roofline": None}
-    print(json.dumps(out))
-    return 0
+    return out
 
 
 def _served_request(args):
@@ -518,7 +625,7 @@ def _served_request(args):
     return t, r["graph"], r["x0"], r["y0"]
 
 
-def bench_served(args, api, reqs):
+def bench_served(args, api, reqs, window=None):
     """Served stream: Poisson arrivals, each an RMAT graph (edge factor 8, n
     log-uniform in [2^10, 2^20]), Barnes-Hut theta 1.2, batch 256, 300
     iterations, submitted to the continuous-batching server at its arrival
@@ -565,15 +672,14 @@ def bench_served(args, api, reqs):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "served: Poisson %.0f requests/s for %.0f s (%d requests), RMAT edge factor 8, "
                                   "n log-uniform in [2^10, 2^20], Barnes-Hut theta 1.2, batch 256, 300 iterations"
-                                  % (args.serve_rate, args.serve_seconds, len(reqs)),
+                                  % (args.serve_rate, window or args.serve_seconds, len(reqs)),
                       "requests": len(reqs), "vertices": int(sum(g.n for _, g, _, _ in reqs))},
            "served": {"latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
                       "latency_max_s": float(lat.max()), "span_s": span},
            "plain": {"force_updates_per_s": pf / ps, "sample_requests": int(len(sample)),
                      "note": "sampled requests alone through bl_layout, device time summed"},
            "speedup_vs_plain": (fu / span) / (pf / ps), "roofline": None}
-    print(json.dumps(out))
-    return 0
+    return out
 
 
 if __name__ == "__main__":
