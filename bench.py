@@ -453,6 +453,7 @@ def main():
     ap.add_argument("--compact-serve-seconds", type=float, default=6.0,
                     help="default run: arrival window of the compact served measurement")
     ap.add_argument("--no-precision", action="store_true", help="c3: skip the three-precision comparison")
+    ap.add_argument("--no-bs-study", action="store_true", help="c4: skip the minibatch-size study")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -615,7 +616,47 @@ def bench_batched(args, api):
                      "note": "each sampled graph alone through bl_layout, device time summed"},
            "speedup_vs_plain": value / plain, "equal_stress": "bitwise-identical layouts" if same else "MISMATCH",
            "roofline": None}
+    if not args.no_bs_study:
+        out["minibatch_study"] = minibatch_study(api, jobs)
     return out
+
+
+MINIBATCH_CANDIDATES = (64, 128, 256, 512)
+
+
+def minibatch_study(api, jobs, count=24, ref_bs=128, tol=0.01):
+    """The minibatch size at equal stress (Sec. 4.3.2): a size-stratified
+    sample of the batched graphs is laid out in one bl_layout_batch call per
+    candidate batch size; each layout's stress (all pairs, on the GPU) is
+    compared with the same graph's at the configured size.  The pick is the
+    fastest candidate whose mean stress ratio lies within `tol` of 1.  Batch
+    size changes the layout, so the parity path keeps the configured 128; the
+    pick is reported, not applied."""
+    import numpy as np
+    order = np.argsort([j["graph"].n for j in jobs])
+    sample = [jobs[q] for q in order[np.linspace(0, len(order) - 1, min(count, len(order))).astype(int)]]
+    graphs = [j["graph"] for j in sample]
+    fu = float(sum(g.n * j["iterations"] for g, j in zip(graphs, sample)))
+    res = {}
+    for bs in MINIBATCH_CANDIDATES:
+        plist = [api.params(batch_size=bs, iterations=j["iterations"], mode=j["mode"],
+                            theta=j["theta"] if j["mode"] == "bh" else 1.2) for j in sample]
+        outs, stats = api.layout_batch(graphs, [j["x0"] for j in sample], [j["y0"] for j in sample], plist)
+        stress = [api.quality(g, o[0], o[1])["stress"] for g, o in zip(graphs, outs)]
+        res[bs] = dict(force_updates_per_s=fu / stats[0]["seconds"], stress=stress)
+    ref = np.array(res[ref_bs]["stress"])
+    rows = {}
+    for bs, r in res.items():
+        ratio = np.array(r["stress"]) / ref
+        rows[str(bs)] = {"force_updates_per_s": r["force_updates_per_s"],
+                         "stress_ratio_mean": float(ratio.mean()), "stress_ratio_min": float(ratio.min()),
+                         "stress_ratio_max": float(ratio.max())}
+    ok = [bs for bs in res if abs(rows[str(bs)]["stress_ratio_mean"] - 1) <= tol]
+    pick = max(ok, key=lambda bs: res[bs]["force_updates_per_s"])
+    return {"graphs": len(sample), "reference_batch_size": ref_bs, "tolerance": tol, "candidates": rows,
+            "pick_at_equal_stress": pick,
+            "note": "batched throughput per candidate batch size on a size-stratified sample; equal stress = "
+                    "mean stress ratio to the reference size within the tolerance (all pairs, GPU evaluator)"}
 
 
 def _served_request(args):
