@@ -99,10 +99,15 @@ struct BHJob {
     gptr<int> late_cnt, late_ids, late_att, old_att, heavy, nheavy;
     gptr<float2> atte;
     gptr<int> roff, roff_old, bbase, bold;
-    gptr<float2> oldsum;        // per vertex: sum of its old entries
+    gptr<float4> rec;           // per vertex, for the chain: x, y and the force apart from recent entries
+    gptr<int2> rmeta;           // per vertex: offset in its batch's recent list, late-leaf count
     gptr<int> osplit;           // per batch: kOldSplit + 1 row bounds splitting its old part
     gptr<unsigned long long> ent;
     size_t ent_cap;
+    gptr<int> pstart;           // per vertex: first slot of its row's run within its batch's slots
+    gptr<int> pbase;            // [nb + 1] slot count of each batch, then (scanned) its first slot
+    gptr<unsigned long long> slots;   // the batches' slot plans (chain2_kernel)
+    gptr<int> povf;             // [nb] a row of the batch overflowed its leaf list
     gptr<double> energy;        // one value per iteration of the run
     gptr<double> fout;
     Counters *ctr;
@@ -355,11 +360,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(BH_KERNEL_A
 
 // Exclusive scan in place by one workgroup per job.  which: 0 radix
 // histogram (256 * tiles), 1 cell-count tile sums (sblocks), 2 batch list
-// sizes (nb + 1).
+// sizes (nb + 1), 3 batch slot counts (nb + 1).
 __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(BH_KERNEL_ARGS, int which) {
     BH_JOB();
     __shared__ int ws[16];
-    gptr<int> data = which == 0 ? J.hist : (which == 1 ? J.scan_part : J.bbase);
+    gptr<int> data = which == 0 ? J.hist : (which == 1 ? J.scan_part : (which == 2 ? J.bbase : J.pbase));
     const int len = which == 0 ? 256 * J.tiles : (which == 1 ? J.sblocks : J.nb + 1);
     int running = 0;
     for (int b0 = 0; b0 < len; b0 += kScanTile) {
@@ -1016,47 +1021,6 @@ __global__ __launch_bounds__(256) void late_fill_heavy_kernel(BH_KERNEL_ARGS) {
 }
 
 // ---------------------------------------------------------------- chain
-// Per-row data of a step, requested one step ahead.
-struct ChainRow {
-    int o0;              // start of the row's entries in its batch list
-    int lc;              // late-leaf count; above kLateCap the list overflowed: walk the whole tree live
-    float x, y;
-    float4 far;
-    float2 atte;
-    float2 old;          // sum of the row's old entries (segment kernel)
-};
-
-__device__ __forceinline__ ChainRow chain_row(const BHJob &J, int b, int r) {
-    ChainRow d;
-    const int i = b * J.BS + r;
-    d.o0 = J.roff[i];
-    d.lc = J.late_cnt[i];
-    const float2 pi = ld<float2>(J.pos, i);
-    d.x = pi.x;
-    d.y = pi.y;
-    d.far = ld<float4>(J.far, i);
-    d.atte = J.all_live ? float2{0.f, 0.f} : ld<float2>(J.atte, i);
-    d.old = J.nseg <= 1 ? float2{0.f, 0.f} : ld<float2>(J.oldsum, i);
-    return d;
-}
-
-struct ChainShared {
-    int off[2][kMaxChainRows + 1];    // row offsets in the batch list, by step parity
-    float px[2][kMaxChainRows];       // row positions, by step parity
-    float py[2][kMaxChainRows];
-    float2 base[2][kMaxChainRows];    // row forces apart from the late entries: old sum, early attraction, far field
-    int ovf[2];                       // a row of the step takes the full walk
-    float2 sum[kMaxChainRows];        // rows complete inside one thread's run
-    float2 scan[kChainThreads];       // first (partial) rows of the threads' runs, scanned within waves
-    int skey[kChainThreads];          // their rows
-    float2 cl[kChainThreads];         // last (partial) row of each thread's run
-    float2 wv[kChainThreads / kWave]; // carry scan: per-wave totals and keys
-    int wk[kChainThreads / kWave], wkf[kChainThreads / kWave];
-    int mb[16], mo[16];               // list starts and old-part lengths of batches b .. b + 15
-    double wsd[16];
-    double step;
-};
-
 // A thread's run [e0, e1) of a batch list (entries ordered by row): rows
 // wholly inside the run go to sum[r], the run's first and last (cut) rows to
 // cf/cl[thread].  The first min(KE, e1 - e0) entry words and their gathered
@@ -1235,7 +1199,7 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
 // to lies in an earlier segment, so it has moved in this iteration and its
 // position is final.  The range's entries are split into equal runs, summed
 // per row with live positions, the runs' partial rows combined by the carry
-// scan; each row's total goes to oldsum.
+// scan; each row's total is added to the row's base force in its record.
 template <bool GM>
 __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
     BH_JOB();
@@ -1293,35 +1257,375 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
                              J.negRK2, J.ka, J.kr);
     carry_scan_wave(firstp, key0, loc, keys, wv, wk, wkf);
     __syncthreads();
-    for (int r = rlo + tid; r < rhi; r += 256)
-        st<float2>(J.oldsum, b * BS + r,
-                   row_total(r, off[r] - E0, off[r + 1] - E0, chunk, sum, cl, loc, keys, wv, wk, wkf));
+    for (int r = rlo + tid; r < rhi; r += 256) {
+        const float2 t = row_total(r, off[r] - E0, off[r + 1] - E0, chunk, sum, cl, loc, keys, wv, wk, wkf);
+        float4 rc = ld<float4>(J.rec, b * BS + r);
+        rc.z += t.x;
+        rc.w += t.y;
+        st<float4>(J.rec, b * BS + r, rc);
+    }
 }
 
-// The minibatch chain: one workgroup per job walks its batches in order.
-// Per step b:
-//   - each thread gathers the live positions of the first late entries of its
-//     run (entry words were loaded one step ahead), then requests the next
-//     step's row data and entry words (they do not depend on this step's
-//     moves), then sums its run row by row;
-//   - rows cut by thread boundaries are completed from per-thread carries in
-//     thread order; early attraction and the far field are added, and the
-//     thread owning the row moves it (Alg. 2 update loop; Jacobi within the
-//     batch because every gather of the batch precedes the barrier).
-// The list starts of the next 16 batches are kept in LDS, so no step waits on
-// a dependent load of them.  The step length of iteration k is step0 times
-// decay k times (the host uses the same product), k is read from and advanced
-// in device memory.
-template <bool GM>
-__global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, int seg) {
+// ------------------------------------------------ chain over a slot plan
+// Before the chain, the recent entries of each batch are laid out as "slots",
+// one per lane: a row takes min(max(cr, 1), kRunLanes) consecutive lanes (cr
+// its recent entries) inside one 16-lane row of a wave, lane j holding entry
+// j (and j + kRunLanes, j + 2 kRunLanes, ... when cr > kRunLanes).  A chain
+// step then needs no communication across waves before the update: each lane
+// forms its entry's term, a DPP suffix sum inside the 16-lane row brings the
+// run's sum to the run's first lane, and that lane completes and moves the
+// row.  One barrier per step makes the moved positions visible to the next.
+constexpr int kRunLanes = 16;
+constexpr int kMoreLoads = 8;         // list words a lane of a long row loads at once
+// Slot word: bits 0-31 the entry word's low half (vertex | leaf bit 31),
+// 32-41 the row in its batch, 42-45 lanes after this one in the row's run,
+// 46 holds an entry, 47 first lane of the run (moves the row), 48 the row has
+// more than kRunLanes entries, 49 padding (no row).
+constexpr unsigned long long kSlotHas = 1ull << 46, kSlotLead = 1ull << 47, kSlotMore = 1ull << 48,
+                             kSlotPad = 1ull << 49;
+static_assert(kMaxChainRows <= 1024, "slot words hold the row in 10 bits");
+
+// Recent entries of row r of batch b (R rows); bbase holds list starts.
+__device__ __forceinline__ int recent_count(const BHJob &J, int b, int r, int R) {
+    const int i = b * J.BS + r;
+    const int rend = (r + 1 < R) ? J.roff[i + 1] : (J.bbase[b + 1] - J.bbase[b] - J.bold[b]);
+    return rend - J.roff[i];
+}
+__device__ __forceinline__ int run_lanes(int cr) { return min(max(cr, 1), kRunLanes); }
+
+// One workgroup per batch: each row's first slot, runs packed in row order
+// so that none crosses a 16-lane row; pbase[b] = the batch's slot count.
+__global__ __launch_bounds__(1024) void plan_count_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
-    if (J.general != (int)GM) return;
-    __shared__ ChainShared S;
-    extern __shared__ float2 win[];   // dynamic: the segment's moved positions
+    __shared__ unsigned char lanes[kMaxChainRows];
+    __shared__ int start[kMaxChainRows];
+    const int b = jb.local, r = (int)threadIdx.x;
+    const int R = min(J.BS, J.n - b * J.BS);
+    __shared__ int any_ovf;
+    if (r == 0) any_ovf = 0;
+    __syncthreads();
+    if (r < R) {
+        lanes[r] = (unsigned char)run_lanes(recent_count(J, b, r, R));
+        if (J.late_cnt[b * J.BS + r] > kLateCap) any_ovf = 1;
+    }
+    __syncthreads();
+    if (r == 0) J.povf[b] = any_ovf;
+    if (r == 0) {
+        int pos = 0;
+        for (int q = 0; q < R; ++q) {
+            const int l = lanes[q];
+            if ((pos & (kRunLanes - 1)) + l > kRunLanes) pos = (pos + kRunLanes - 1) & ~(kRunLanes - 1);
+            start[q] = pos;
+            pos += l;
+        }
+        J.pbase[b] = (pos + kRunLanes - 1) & ~(kRunLanes - 1);
+        if (b == 0) J.pbase[J.nb] = 0;
+    }
+    __syncthreads();
+    if (r < R) J.pstart[b * J.BS + r] = start[r];
+}
+
+// One thread per row: its run's slot words and the padding up to the next run.
+__global__ __launch_bounds__(256) void plan_fill_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    const int i = jb.local * blockDim.x + threadIdx.x;
+    if (i >= J.n) return;
+    const int b = i / J.BS, r = i - b * J.BS, R = min(J.BS, J.n - b * J.BS);
+    const int cr = recent_count(J, b, r, R);
+    const int l = run_lanes(cr);
+    const int s0 = J.pstart[i];
+    const int s1 = (r + 1 < R) ? J.pstart[i + 1] : (J.pbase[b + 1] - J.pbase[b]);
+    const size_t base = (size_t)J.pbase[b];
+    const size_t list = (size_t)J.bbase[b] + J.bold[b] + J.roff[i];
+    const unsigned long long rb = (unsigned long long)r << 32;
+    for (int j = 0; j < l; ++j) {
+        unsigned long long w = rb | ((unsigned long long)(l - 1 - j) << 42);
+        if (j < cr) w |= kSlotHas | (J.ent[list + j] & 0xffffffffull);
+        if (j == 0) w |= kSlotLead;
+        if (cr > kRunLanes) w |= kSlotMore;
+        J.slots[base + s0 + j] = w;
+    }
+    for (int q = s0 + l; q < s1; ++q) J.slots[base + q] = kSlotPad;
+    // the row's record: position at the iteration's start, and its force apart
+    // from recent entries -- early attraction and far field (a row whose leaf
+    // list overflowed takes its far field from a full walk when it moves); the
+    // segment kernel adds the old entries
+    const int lc = J.late_cnt[i];
+    const float2 p = ld<float2>(J.pos, i);
+    float2 bs = J.all_live ? float2{0.f, 0.f} : ld<float2>(J.atte, i);
+    if (lc <= kLateCap) {
+        const float4 fr = ld<float4>(J.far, i);
+        bs.x += J.negRK2 * (fr.x - fr.z);
+        bs.y += J.negRK2 * (fr.y - fr.w);
+    }
+    st<float4>(J.rec, i, float4{p.x, p.y, bs.x, bs.y});
+    st<int2>(J.rmeta, i, int2{J.roff[i], lc});
+}
+
+struct Chain2Shared {
+    int off[2][kMaxChainRows + 1];    // row offsets in the batch's recent list, by step parity
+    float4 rec[2][kMaxChainRows];     // rows' x, y and force apart from recent entries, by step parity
+    int meta[4][8];                   // batches b .. b + 3 (by b mod 4): kMeta* fields
+    double wsd[16];
+    double step;
+};
+
+// Fields of a batch's metadata: its first slot and the next batch's, its list
+// start, old-part length and the next batch's list start, and whether a row
+// of it overflowed its leaf list (its full walk reads moved positions from
+// memory).
+enum { kMetaPb0 = 0, kMetaPb1, kMetaBb, kMetaBo, kMetaBn, kMetaOvf, kMetaFields };
+
+// Barrier for LDS traffic only: every wave's LDS stores are complete and
+// visible after it, while global loads and stores stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Sum of v over this lane and the `rem` lanes after it in its 16-lane row
+// (a Hillis-Steele suffix sum whose steps stay inside the lane's run).
+__device__ __forceinline__ float run_suffix_sum(float v, int rem) {
+#define BL_RUN_STEP(O)                                                                                            \
+    {                                                                                                             \
+        const float t = __builtin_bit_cast(                                                                       \
+            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x100 + (O), 0xf, 0xf, false));     \
+        if ((O) <= rem) v += t;                                                                                   \
+    }
+    BL_RUN_STEP(1)
+    BL_RUN_STEP(2)
+    BL_RUN_STEP(4)
+    BL_RUN_STEP(8)
+#undef BL_RUN_STEP
+    return v;
+}
+
+// The minibatch chain over the slot plan: one workgroup per job walks its
+// batches in order.  Step b writes batch b + 1's rows to LDS (loaded in step
+// b - 1), issues the loads later steps need (batch b + 1's pass-0 slot words,
+// batch b + 2's row records, batch b + 4's metadata by lanes of the first
+// wave), stores the positions moved in step b - 1, then runs batch b's slots;
+// a barrier on LDS traffic alone ends the step, so those loads and stores
+// stay in flight across it.  The rows' terms use the positions their batch
+// sees: moved ones from the LDS window of the segment (WIN; Jacobi within the
+// batch, Gauss-Seidel across batches) or from memory (one-shot force calls,
+// where nothing moves), the rows' own from LDS.
+template <bool GM, bool WIN>
+__device__ __forceinline__ void chain2_run(const BHJob &J, Chain2Shared &S, float2 *win, int first, int last,
+                                           int wbase, bool first_launch, bool last_launch) {
     const int tid = threadIdx.x;
     const int BS = J.BS, n = J.n;
-    // this launch's batches: segment `seg` of the run's range (a one-shot
-    // force call runs whole in segment 0)
+    const PosL pl{win, wbase};
+    const PosG pg{J.pos};
+    auto gather = [&](int j) -> float2 {
+        if constexpr (WIN) return pl(j);
+        else return pg(j);
+    };
+    const float invK = J.invK, negRK2 = J.negRK2;
+    const WalkArgs wa = walk_args(J);
+    const int k_it = J.kiter[0];
+    auto nrows = [&](int b) { return min(BS, n - b * BS); };
+    // lane f < kMetaFields of the first wave: field f of batch q's metadata
+    // (one load per lane, from the array and index the field names)
+    const gptr<const int> p_pbase = J.pbase, p_bbase = J.bbase, p_bold = J.bold, p_povf = J.povf;
+    const gptr<const int> meta_src = tid <= kMetaPb1 ? p_pbase
+                                     : (tid == kMetaBo ? p_bold : (tid == kMetaOvf ? p_povf : p_bbase));
+    const int meta_add = (tid == kMetaPb1 || tid == kMetaBn) ? 1 : 0;
+    auto meta_field = [&](int q) -> int { return meta_src[q + meta_add]; };
+    auto M = [&](int b, int f) -> int { return S.meta[b & 3][f]; };
+    // pass-0 slot word of batch b for this lane (padding past its slots)
+    auto slot_word = [&](int b) -> unsigned long long {
+        const int pb0 = M(b, kMetaPb0);
+        return tid < M(b, kMetaPb1) - pb0 ? J.slots[(size_t)pb0 + tid] : kSlotPad;
+    };
+    struct Row {
+        float4 rec;
+        int2 meta;
+    };
+    auto load_row = [&](int b, Row &rd) {
+        if (tid < nrows(b)) {
+            rd.rec = ld<float4>(J.rec, (size_t)b * BS + tid);
+            rd.meta = ld<int2>(J.rmeta, (size_t)b * BS + tid);
+        }
+    };
+    auto write_lds = [&](int b, int slot, const Row &rd) {
+        const int R = nrows(b);
+        if (tid < R) {
+            S.off[slot][tid] = rd.meta.x;
+            S.rec[slot][tid] = rd.rec;
+        }
+        if (tid == 0) S.off[slot][R] = M(b, kMetaBn) - M(b, kMetaBb) - M(b, kMetaBo);
+    };
+
+    // prologue: metadata of the first three batches in LDS, of the fourth in
+    // registers; the first batch's rows and slot words, the second's rows
+    if (tid == 0) {
+        double st = J.step0;
+        for (int t = 0; t < k_it; ++t) st *= J.decay;
+        S.step = st;
+    }
+    for (int q = 0; q < 3; ++q)
+        if (tid < kMetaFields && first + q <= last) S.meta[(first + q) & 3][tid] = meta_field(first + q);
+    int mreg = 0;
+    if (tid < kMetaFields && first + 3 <= last) mreg = meta_field(first + 3);
+    if (WIN)   // batches of the segment moved before this launch
+        for (int v = wbase + tid; v < first * BS; v += kChainThreads) win[v - wbase] = ld<float2>(J.pos, v);
+    __syncthreads();
+    Row rdA{}, rdB{};
+    load_row(first, rdA);
+    write_lds(first, first & 1, rdA);
+    unsigned long long wA = slot_word(first), wB = kSlotPad;
+    if (first + 1 <= last) load_row(first + 1, rdA);
+    __syncthreads();
+    const float step = (float)S.step;
+
+    double e_iter = 0.0;
+    unsigned long long bad = 0;
+    // position of the row this thread moved as a lead lane of the last step's
+    // first pass, stored one step later (i < 0: none)
+    int pend_i = -1;
+    float2 pend_p{0.f, 0.f};
+
+    // Terms of one slot, the run's suffix sum, and the row's move by its lead lane.
+    auto do_slot = [&](int b, int slot, unsigned long long w, bool stop, bool defer) {
+        const bool pad = (w & kSlotPad) != 0;
+        if (!__any(!pad)) return;   // a wave of padding only
+        const int r = pad ? 0 : (int)((w >> 32) & 1023u);
+        const int rem = (int)((w >> 42) & 15u);
+        float ax = 0.f, ay = 0.f;
+        const float4 rc = S.rec[slot][r];
+        if (!pad) {
+            if (w & kSlotHas) {
+                const float2 pj = gather((int)((unsigned)w & 0x7fffffffu));
+                entry_term<GM>(w, pj.x - rc.x, pj.y - rc.y, invK, negRK2, J.ka, J.kr, ax, ay);
+            }
+            if (w & kSlotMore) {
+                // every kRunLanes-th further entry of the row, from the batch
+                // list, kMoreLoads list words in flight at a time
+                const int jl = (kRunLanes - 1) - rem;
+                const size_t lst = (size_t)M(b, kMetaBb) + M(b, kMetaBo);
+                const int o0 = S.off[slot][r], o1 = S.off[slot][r + 1];
+                for (int e0 = o0 + jl + kRunLanes; e0 < o1; e0 += kMoreLoads * kRunLanes) {
+                    unsigned long long we[kMoreLoads];
+#pragma unroll
+                    for (int u = 0; u < kMoreLoads; ++u) {
+                        const int e = e0 + u * kRunLanes;
+                        we[u] = e < o1 ? J.ent[lst + e] : 0ull;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kMoreLoads; ++u) {
+                        if (e0 + u * kRunLanes < o1) {
+                            const float2 pj = gather((int)((unsigned)we[u] & 0x7fffffffu));
+                            entry_term<GM>(we[u], pj.x - rc.x, pj.y - rc.y, invK, negRK2, J.ka, J.kr, ax, ay);
+                        }
+                    }
+                }
+            }
+        }
+        if (__any(!pad && rem > 0)) {
+            ax = run_suffix_sum(ax, rem);
+            ay = run_suffix_sum(ay, rem);
+        }
+        if (pad || !(w & kSlotLead)) return;
+        const int i = b * BS + r;
+        float fx = ax + rc.z, fy = ay + rc.w;
+        if (M(b, kMetaOvf) && J.late_cnt[i] > kLateCap) {
+            float4 fr;
+            int dummy = 0;
+            (void)bh_walk<GM>(wa, i, rc.x, rc.y, 0, J.pos, fr, nullptr, dummy, 0);
+            fx += negRK2 * (fr.x - fr.z);
+            fy += negRK2 * (fr.y - fr.w);
+        }
+        if (stop) {
+            J.fout[2 * r] = (double)fx;
+            J.fout[2 * r + 1] = (double)fy;
+            return;
+        }
+        float2 np{rc.x, rc.y};
+        const double f2 = (double)fx * fx + (double)fy * fy;
+        if (!isfinite(f2)) {
+            ++bad;
+        } else {
+            e_iter += f2;
+            if (f2 > 0.0) {
+                // step / |f| with the hardware reciprocal square root (about 1 ulp)
+                const float sc = step * __builtin_amdgcn_rsqf(fx * fx + fy * fy);
+                np = float2{rc.x + sc * fx, rc.y + sc * fy};
+                if (defer) {
+                    pend_i = i;
+                    pend_p = np;
+                } else {
+                    st<float2>(J.pos, i, np);
+                }
+            }
+        }
+        if (WIN) win[i - wbase] = np;
+    };
+
+    // step b: w_cur holds batch b's pass-0 slot word, rd1 batch b + 1's rows;
+    // w_nx receives batch b + 1's slot word, rd2 batch b + 2's rows.
+    auto chain_step = [&](int b, unsigned long long w_cur, const Row &rd1, unsigned long long &w_nx, Row &rd2) {
+        const int slot = b & 1;
+        const bool stop = (b == J.stop_batch);
+        const bool more = b + 1 <= last;
+        // The loads and stores of the previous step are complete here (one
+        // explicit wait, so that no later use of what they loaded waits for
+        // this step's loads); then this step's loads are issued.
+        __builtin_amdgcn_s_waitcnt(0);
+        if (tid < kMetaFields && b + 3 <= last) S.meta[(b + 3) & 3][tid] = mreg;   // batch b - 1's entry is free
+        if (more) write_lds(b + 1, slot ^ 1, rd1);
+        const unsigned long long w0 = w_cur;
+        const bool walk_next = more && M(b + 1, kMetaOvf);
+        if (more) w_nx = slot_word(b + 1);
+        if (b + 2 <= last) load_row(b + 2, rd2);
+        if (tid < kMetaFields && b + 4 <= last) mreg = meta_field(b + 4);
+        if (pend_i >= 0) st<float2>(J.pos, pend_i, pend_p);
+        pend_i = -1;
+        do_slot(b, slot, w0, stop, true);
+        const int sc = M(b, kMetaPb1) - M(b, kMetaPb0);
+        for (int p = 1; p * kChainThreads < sc; ++p) {   // batches with more slots than lanes
+            const int sidx = p * kChainThreads + tid;
+            const unsigned long long w = sidx < sc ? J.slots[(size_t)M(b, kMetaPb0) + sidx] : kSlotPad;
+            do_slot(b, slot, w, stop, false);
+        }
+        if (walk_next) {
+            // a row of the next batch walks the tree over positions in memory
+            if (pend_i >= 0) st<float2>(J.pos, pend_i, pend_p);
+            pend_i = -1;
+            __syncthreads();
+        } else {
+            lds_barrier();
+        }
+    };
+    for (int b = first; b <= last; b += 2) {
+        chain_step(b, wA, rdA, wB, rdB);
+        if (b + 1 <= last) chain_step(b + 1, wB, rdB, wA, rdA);
+    }
+    if (pend_i >= 0) st<float2>(J.pos, pend_i, pend_p);
+    if (bad) atomicAdd(&J.ctr->nonfinite, bad);
+    const double e = block_sum_fixed(e_iter, S.wsd);
+    if (tid == 0 && J.stop_batch < 0) {
+        // segments add their energies in order; the last one ends the iteration
+        const int slot_e = k_it - J.kiter[1];
+        const double ek = first_launch ? e : J.energy[slot_e] + e;
+        J.energy[slot_e] = ek;
+        if (last_launch) {
+            J.kiter[0] = k_it + 1;
+            if (J.conv_tol > 0 && slot_e >= 1) {
+                const double ep = J.energy[slot_e - 1];
+                if (fabs(ek - ep) <= J.conv_tol * ep) J.ctr->halted = (unsigned long long)(slot_e + 1);
+            }
+        }
+    }
+}
+
+template <bool GM>
+__global__ __launch_bounds__(kChainThreads) void chain2_kernel(BH_KERNEL_ARGS, int seg) {
+    BH_JOB();
+    if (J.general != (int)GM) return;
+    __shared__ Chain2Shared S;
+    extern __shared__ float2 win[];   // dynamic: the segment's moved positions
     int first = J.first_batch, last = J.last_batch;
     if (J.nseg <= 1) {
         if (seg != 0) return;
@@ -1332,207 +1636,11 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS, in
         if (first > last) return;
     }
     const bool first_launch = (first == J.first_batch), last_launch = (last == J.last_batch);
-    // one-shot force calls gather from global memory; runs from the window,
-    // which starts at the segment's first vertex
-    const bool use_win = !J.all_live;
-    const int wbase = (J.nseg <= 1 ? 0 : seg * seg_len(J)) * BS;
-    const PosL pl{win, wbase};
-    const PosG pg{J.pos};
-    const float invK = J.invK, negRK2 = J.negRK2;
-    const WalkArgs wa = walk_args(J);
-    static_assert(kMaxChainRows == kChainThreads, "one row per thread");
-    const size_t entmax = J.ent_cap - 1;
-    const int k_it = J.kiter[0];
-    if (tid == 0) {
-        double st = J.step0;
-        for (int t = 0; t < k_it; ++t) st *= J.decay;
-        S.step = st;
-    }
-    auto nrows = [&](int b) { return min(BS, n - b * BS); };
-    auto run_of = [&](int E, int &e0, int &e1) {
-        const int chunk = max(kMinRun, (E + kChainThreads - 1) / kChainThreads);
-        e0 = min(tid * chunk, E);
-        e1 = min(e0 + chunk, E);
-        return chunk;
-    };
-    if (tid < 16) {
-        const int q = first + tid;
-        if (q <= J.nb) S.mb[q & 15] = J.bbase[q];
-        if (q < J.nb) S.mo[q & 15] = J.bold[q];
-    }
-    if (tid < 2) S.ovf[tid] = 0;
-    if (use_win)   // batches of the segment moved before this launch
-        for (int v = wbase + tid; v < first * BS; v += kChainThreads) win[v - wbase] = ld<float2>(J.pos, v);
-    __syncthreads();
-
-    // The next batch's row records are loaded during a step and moved to LDS
-    // at its end; its first entries stay in registers, double-buffered (the
-    // loop is unrolled by two) so that they are loaded before this batch's
-    // gathers are waited for.
-    ChainRow rd;
-    unsigned long long pA[kEnt], pB[kEnt];
-    auto fetch_regs = [&](int b, ChainRow &rd, unsigned long long (&pe)[kEnt]) {
-        const int R = nrows(b);
-        const int Eo = S.mo[b & 15], E = S.mb[(b + 1) & 15] - S.mb[b & 15] - Eo;
-        if (tid < R) rd = chain_row(J, b, tid);
-        int e0, e1;
-        run_of(E, e0, e1);
-        const size_t gb = (size_t)S.mb[b & 15] + Eo;
-#pragma unroll
-        for (int q = 0; q < kEnt; ++q)
-            if (e0 + q < e1) pe[q] = J.ent[min(gb + (size_t)(e0 + q), entmax)];
-    };
-    auto fetch_lds = [&](int b, int slot, const ChainRow &rd) {
-        const int R = nrows(b);
-        if (tid < R) {
-            S.off[slot][tid] = rd.o0;
-            S.px[slot][tid] = rd.x;
-            S.py[slot][tid] = rd.y;
-            // a row whose leaf list overflowed gets its far field from a
-            // full walk when it moves
-            const bool ov = rd.lc > kLateCap;
-            float2 bs{rd.old.x + rd.atte.x, rd.old.y + rd.atte.y};
-            if (!ov) {
-                bs.x += negRK2 * (rd.far.x - rd.far.z);
-                bs.y += negRK2 * (rd.far.y - rd.far.w);
-            } else {
-                S.ovf[slot] = 1;
-            }
-            S.base[slot][tid] = bs;
-        }
-        if (tid == 0) S.off[slot][R] = S.mb[(b + 1) & 15] - S.mb[b & 15] - S.mo[b & 15];
-    };
-    fetch_regs(first, rd, pA);
-    fetch_lds(first, first & 1, rd);
-    __syncthreads();
-    const float step = (float)S.step;
-
-    double e_iter = 0.0;
-    unsigned long long bad = 0;
-    auto chain_step = [&](int b, unsigned long long (&ce)[kEnt], unsigned long long (&ne)[kEnt]) {
-        const int slot = b & 1;
-        const int R = nrows(b);
-        const int E = S.off[slot][R];
-        int e0, e1;
-        const int chunk = run_of(E, e0, e1);
-
-        // gathers of the first pass (only real entries: every lane's gather
-        // costs a cache-line lookup in this CU's address unit)
-        const int m0 = min(kEnt, e1 - e0);
-        float xj[kEnt], yj[kEnt];
-        // waves past the last thread with entries have nothing to sum (the
-        // row totals read carries of earlier waves only)
-        const bool wave_busy = __builtin_amdgcn_readfirstlane(tid & ~(kWave - 1)) * chunk < E;
-#pragma unroll
-        for (int q = 0; q < kEnt; ++q) {
-            xj[q] = 0.f;
-            yj[q] = 0.f;
-            if (q < m0) {
-                const int j = (int)((unsigned)ce[q] & 0x7fffffffu);
-                const float2 pj = use_win ? pl(j) : pg(j);
-                xj[q] = pj.x;
-                yj[q] = pj.y;
-            }
-        }
-        // next step's data (clamped to the last batch on the final step),
-        // and the list start of batch b + 16
-        fetch_regs(min(b + 1, last), rd, ne);
-        int meta = 0, meta_o = 0;
-        if (tid == 0) {
-            if (b + 16 <= J.nb) meta = J.bbase[b + 16];
-            if (b + 16 < J.nb) meta_o = J.bold[b + 16];
-        }
-
-        float2 firstp;
-        const int key0 = e0 < e1 ? (int)(ce[0] >> 32) : -1 - tid;   // row of the run's first entry
-        gptr<const unsigned long long> lst = J.ent + S.mb[b & 15] + S.mo[b & 15];
-        if (wave_busy) {
-            if (chunk == 1 && use_win) {
-                // one entry per run: run_sum's arithmetic without its loop
-                firstp = float2{0.f, 0.f};
-                if (e0 < e1) {
-                    const int r = (int)(ce[0] >> 32);
-                    const float dx = xj[0] - S.px[slot][r], dy = yj[0] - S.py[slot][r];
-                    float ax = 0.f, ay = 0.f;
-                    entry_term<GM>(ce[0], dx, dy, invK, negRK2, J.ka, J.kr, ax, ay);
-                    if (S.off[slot][r] >= e0 && S.off[slot][r + 1] <= e1) S.sum[r] = float2{ax, ay};
-                    else firstp = float2{ax, ay};
-                }
-            } else if (use_win)
-                run_sum<kEnt, PosL, GM>(lst, pl, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum,
-                                        firstp, S.cl, invK, negRK2, J.ka, J.kr);
-            else
-                run_sum<kEnt, PosG, GM>(lst, pg, e0, e1, ce, xj, yj, S.off[slot], S.px[slot], S.py[slot], S.sum,
-                                        firstp, S.cl, invK, negRK2, J.ka, J.kr);
-            carry_scan_wave(firstp, key0, S.scan, S.skey, S.wv, S.wk, S.wkf);
-        }
-        if (tid == 0) S.ovf[slot ^ 1] = 0;   // last read in the previous step
-        __syncthreads();
-        if (tid == 0) {   // the slot of batch b now holds batch b + 16
-            S.mb[b & 15] = meta;
-            S.mo[b & 15] = meta_o;
-        }
-
-        // complete the row of batch b, add early attraction and far field,
-        // move it
-        const bool stop = (b == J.stop_batch);
-        if (tid < R) {
-            const float2 sm = row_total(tid, S.off[slot][tid], S.off[slot][tid + 1], chunk, S.sum, S.cl, S.scan, S.skey,
-                                        S.wv, S.wk, S.wkf);
-            const int i = b * BS + tid;
-            const float2 bs = S.base[slot][tid];
-            const float x = S.px[slot][tid], y = S.py[slot][tid];
-            float fx = sm.x + bs.x, fy = sm.y + bs.y;
-            if (S.ovf[slot] && J.late_cnt[i] > kLateCap) {
-                float4 fr;
-                int dummy = 0;
-                (void)bh_walk<GM>(wa, i, x, y, 0, J.pos, fr, nullptr, dummy, 0);
-                fx += negRK2 * (fr.x - fr.z);
-                fy += negRK2 * (fr.y - fr.w);
-            }
-            if (stop) {
-                J.fout[2 * tid] = (double)fx;
-                J.fout[2 * tid + 1] = (double)fy;
-            } else {
-                float2 np{x, y};
-                const double f2 = (double)fx * fx + (double)fy * fy;
-                if (!isfinite(f2)) {
-                    ++bad;
-                } else {
-                    e_iter += f2;
-                    if (f2 > 0.0) {
-                        // step / |f| with the hardware reciprocal square root (about 1 ulp)
-                        const float sc = step * __builtin_amdgcn_rsqf(fx * fx + fy * fy);
-                        np = float2{x + sc * fx, y + sc * fy};
-                        st<float2>(J.pos, i, np);
-                    }
-                }
-                if (use_win) win[i - wbase] = np;
-            }
-        }
-        if (b + 1 <= last) fetch_lds(b + 1, slot ^ 1, rd);
-        __syncthreads();
-    };
-    for (int b = first; b <= last; b += 2) {
-        chain_step(b, pA, pB);
-        if (b + 1 <= last) chain_step(b + 1, pB, pA);
-    }
-    if (bad) atomicAdd(&J.ctr->nonfinite, bad);
-    const double e = block_sum_fixed(e_iter, S.wsd);
-    if (tid == 0 && J.stop_batch < 0) {
-        // segments add their energies in order; the last one ends the iteration
-        const int slot_e = k_it - J.kiter[1];
-        const double ek = first_launch ? e : J.energy[slot_e] + e;
-        J.energy[slot_e] = ek;
-        if (last_launch) {
-            J.kiter[0] = k_it + 1;
-            // energy stopping rule (relative change against the previous iteration of the run)
-            if (J.conv_tol > 0 && slot_e >= 1) {
-                const double ep = J.energy[slot_e - 1];
-                if (fabs(ek - ep) <= J.conv_tol * ep) J.ctr->halted = (unsigned long long)(slot_e + 1);
-            }
-        }
-    }
+    const int wbase = (J.nseg <= 1 ? 0 : seg * seg_len(J)) * J.BS;
+    if (!J.all_live)
+        chain2_run<GM, true>(J, S, win, first, last, wbase, first_launch, last_launch);
+    else
+        chain2_run<GM, false>(J, S, win, first, last, wbase, first_launch, last_launch);
 }
 
 // ------------------------------------------------------------- host side
@@ -1600,9 +1708,10 @@ int bh_engine_create(hipStream_t s, BHEngine **out) {
         }
     }
     // the chain's window is dynamic LDS beyond the 64 KB default
+    const void *chains[2] = {(const void *)chain2_kernel<false>, (const void *)chain2_kernel<true>};
     for (int kind = 0; kind < 2; ++kind) {
-        hipError_t r = hipFuncSetAttribute(kind ? (const void *)chain_kernel<true> : (const void *)chain_kernel<false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float2) * kWindow));
+        hipError_t r = hipFuncSetAttribute(chains[kind], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(sizeof(float2) * kWindow));
         if (r != hipSuccess) {
             bh_engine_destroy(e);
             set_error("hipFuncSetAttribute(chain_kernel) failed: %s", hipGetErrorString(r));
@@ -1698,7 +1807,8 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->old_att = (decltype(J->old_att))(h.old_att);
     J->roff_old = (decltype(J->roff_old))(h.roff_old);
     J->bold = (decltype(J->bold))(h.bold);
-    J->oldsum = (decltype(J->oldsum))(h.oldsum);
+    J->rec = (decltype(J->rec))(h.rec);
+    J->rmeta = (decltype(J->rmeta))(h.rmeta);
     J->osplit = (decltype(J->osplit))(h.osplit);
     J->heavy = (decltype(J->heavy))(h.heavy);
     J->nheavy = (decltype(J->nheavy))(h.nheavy);
@@ -1707,6 +1817,10 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->bbase = (decltype(J->bbase))(h.bbase);
     J->ent = (decltype(J->ent))(h.ent);
     J->ent_cap = (decltype(J->ent_cap))((size_t)g->nnz + (size_t)g->n * kLateCap);
+    J->pstart = (decltype(J->pstart))(h.pstart);
+    J->pbase = (decltype(J->pbase))(h.pbase);
+    J->slots = (decltype(J->slots))(h.slots);
+    J->povf = (decltype(J->povf))(h.povf);
     J->energy = (decltype(J->energy))(g->energy);
     J->fout = (decltype(J->fout))(g->fout);
     J->ctr = (decltype(J->ctr))(g->counters);
@@ -1821,6 +1935,9 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 2);
     BH_LAUNCH(late_fill_kernel, PT_VERT8, 256);
     BH_LAUNCH(late_fill_heavy_kernel, PT_HEAVY, 256);
+    BH_LAUNCH(plan_count_kernel, PT_BATCH, 1024);
+    BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 3);
+    BH_LAUNCH(plan_fill_kernel, PT_VERT, 256);
     for (int seg = 0; seg < e->nseg; ++seg) {
         if (e->total[PT_SEG] > 0) {
             if (prof) BL_TRY(prof_begin(prof, PK_OLDSUM, &slot));
@@ -1828,11 +1945,12 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
             if (prof) BL_TRY(prof_end(prof, slot));
         }
         if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
-        for (int kind = 0; kind < 2; ++kind)
-            if (e->total[PT_ONE] > 0 && e->nkind[kind])
-                hipLaunchKernelGGL(kind ? chain_kernel<true> : chain_kernel<false>, dim3(e->total[PT_ONE]),
-                                   dim3(kChainThreads), e->win_bytes, e->stream, jobs,
-                                   e->d_pre[e->cur] + PT_ONE * (e->cap + 1), e->G, seg);
+        for (int kind = 0; kind < 2; ++kind) {
+            if (e->total[PT_ONE] == 0 || !e->nkind[kind]) continue;
+            const int *pre = e->d_pre[e->cur] + PT_ONE * (e->cap + 1);
+            hipLaunchKernelGGL(kind ? chain2_kernel<true> : chain2_kernel<false>, dim3(e->total[PT_ONE]),
+                               dim3(kChainThreads), e->win_bytes, e->stream, jobs, pre, e->G, seg);
+        }
         if (prof) BL_TRY(prof_end(prof, slot));
     }
     BL_HIP(hipGetLastError());
@@ -1890,7 +2008,8 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
-           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1);
+           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1) +
+           4 * N + 4 * (nb + 1) + 8 * (2 * kRunLanes * N + kRunLanes * nb) + 4 * nb + 16 * N;
 }
 
 int bh_alloc(bl_graph *g) {
@@ -1922,7 +2041,8 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.old_att, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.roff_old, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.bold, 4 * ((size_t)g->nb + 1)));
-    BL_TRY(graph_alloc(g, (void **)&h.oldsum, 8 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.rec, 16 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.rmeta, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.osplit, 4 * (size_t)g->nb * (kOldSplit + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.heavy, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nheavy, 16));
@@ -1930,6 +2050,12 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.roff, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.bbase, 4 * ((size_t)g->nb + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.ent, 8 * ((size_t)g->nnz + N * kLateCap)));
+    // slot plans: a batch's runs (at most kRunLanes lanes per row) packed into
+    // 16-lane rows take fewer than twice their lanes, plus the last row's padding
+    BL_TRY(graph_alloc(g, (void **)&h.pstart, 4 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.pbase, 4 * ((size_t)g->nb + 1)));
+    BL_TRY(graph_alloc(g, (void **)&h.slots, 8 * (2 * kRunLanes * N + (size_t)kRunLanes * g->nb)));
+    BL_TRY(graph_alloc(g, (void **)&h.povf, 4 * (size_t)g->nb));
     BL_TRY(graph_alloc(g, (void **)&h.kiter, 16));
     BL_HIP(hipMemsetAsync(h.bbox, 0, 64, g->stream));
     BL_HIP(hipMemsetAsync(h.kiter, 0, 16, g->stream));

@@ -88,7 +88,8 @@ struct BHBuffers {
     int *old_att;           // [n] its part in earlier chain segments
     int *roff_old;          // [n] offset of each row's old entries within its batch list
     int *bold;              // [nb + 1] length of each batch list's old part
-    float2 *oldsum;         // [n] sum of each vertex's old entries
+    float4 *rec;            // [n] chain row records: x, y, force apart from recent entries
+    int2 *rmeta;            // [n] offset in the batch's recent list, late-leaf count
     int *osplit;            // [nb * 17] row ranges of each batch's old part, one per workgroup
     int *heavy;             // [n] rows with many early neighbours (first *nheavy used)
     int *nheavy;            // [1]
@@ -96,6 +97,10 @@ struct BHBuffers {
     int *roff;              // [n] offset of each row's late entries within its batch list
     int *bbase;             // [nb + 1] start of each batch's late entry list
     unsigned long long *ent;// late entries (row in batch << 32 | vertex, bit 31: leaf)
+    int *pstart;            // [n] first slot of each row's run within its batch's slot plan
+    int *pbase;             // [nb + 1] slot counts, then first slots of the batches' plans
+    unsigned long long *slots;  // the batches' slot plans (one word per lane of the chain)
+    int *povf;              // [nb] a row of the batch overflowed its leaf list
     int *kiter;             // [2] current iteration, first iteration of the run
     int host_kiter[2];      // host staging for kiter
     bool prefix_ready;      // late_att/heavy computed for this job

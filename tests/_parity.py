@@ -33,14 +33,20 @@ def assert_forces(fx, fy, ref, mask=None, what=""):
 
 
 def perturbed_inits(x0, y0, count, seed=123):
-    """(x0, y0) and count-1 copies with one coordinate moved by one float32 ulp."""
+    """(x0, y0) and count-1 copies in which every coordinate moved by one
+    float32 ulp up or down (random signs): rounding-sized changes of the whole
+    state, like those an FP32 run makes at every update."""
     r = np.random.default_rng(seed)
     out = [(x0, y0)]
+
+    def nudge(a):
+        up = r.random(len(a)) < 0.5
+        f = a.astype(np.float32)
+        return np.where(up, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf))).astype(
+            np.float64)
+
     for _ in range(count - 1):
-        xp = x0.copy()
-        i = int(r.integers(0, len(x0)))
-        xp[i] = float(np.nextafter(np.float32(xp[i]), np.float32(np.inf)))
-        out.append((xp, y0))
+        out.append((nudge(x0), nudge(y0)))
     return out
 
 
@@ -48,22 +54,41 @@ def quality(oracle, g, x, y):
     return (oracle.stress(g.rowptr, g.colidx, x, y)[0], oracle.edge_energy(g.rowptr, g.colidx, x, y))
 
 
-def assert_within_oracle_spread(oracle, g, xg, yg, run_oracle, x0, y0, members=8, what=""):
-    """Chaotic runs: from a random start, a one-ulp change of one input
-    coordinate moves the oracle's own final stress by several percent, so the
-    GPU run is checked against the range of an ensemble of such oracle runs,
-    widened by RUN_TOL and by the ensemble's own width (an FP32 run is
-    perturbed at every update, not once)."""
+def assert_within_oracle_spread(oracle, g, xg, yg, run_oracle, x0, y0, members=16, what=""):
+    """Chaotic runs: from a random start, rounding-sized changes of the input
+    move the oracle's own final stress by up to several percent.
+    The GPU run's stress and edge energy must lie within RUN_TOL of the range
+    of an ensemble of such oracle runs, [min * (1 - RUN_TOL), max * (1 +
+    RUN_TOL)]; the ensemble's own spread is reported beside the result, not
+    added to the bound."""
     qs = np.array([quality(oracle, g, *run_oracle(xp, yp)) for xp, yp in perturbed_inits(x0, y0, members)])
     qg = np.array(quality(oracle, g, xg, yg))
-    width = qs.max(axis=0) - qs.min(axis=0)
-    lo = qs.min(axis=0) * (1 - RUN_TOL) - width
-    hi = qs.max(axis=0) * (1 + RUN_TOL) + width
-    spread = width / qs[0]
-    assert np.all((qg >= lo) & (qg <= hi)), "%s: gpu %s outside oracle range %s..%s (spread %s)" % (
-        what, qg, qs.min(axis=0), qs.max(axis=0), spread)
-    return dict(gpu=qg.tolist(), oracle_min=qs.min(axis=0).tolist(), oracle_max=qs.max(axis=0).tolist(),
-                spread=spread.tolist())
+    lo = qs.min(axis=0) * (1 - RUN_TOL)
+    hi = qs.max(axis=0) * (1 + RUN_TOL)
+    spread = (qs.max(axis=0) - qs.min(axis=0)) / qs[0]
+    rep = dict(gpu=qg.tolist(), oracle_min=qs.min(axis=0).tolist(), oracle_max=qs.max(axis=0).tolist(),
+               spread=spread.tolist(), dev_from_oracle_run=(qg / qs[0] - 1).tolist())
+    print(what, "stress, edge energy:", rep)
+    assert np.all((qg >= lo) & (qg <= hi)), "%s: gpu %s outside %s..%s (oracle spread %s)" % (
+        what, qg, lo, hi, spread)
+    return rep
+
+
+# Barnes-Hut: the oracle flags a vertex whose walk met a cell with
+# |side - theta * d| <= 1e-5 theta d, where an FP32 distance may take the
+# other branch of the acceptance test.  Such vertices are left out of the
+# force bar, and there must be few of them.
+NEAR_TIE_MAX_FRAC = 0.02
+
+
+def bh_mask(ref, what=""):
+    """Rows checked against the force bar: all but the oracle's near-tie
+    vertices, whose number is bounded by NEAR_TIE_MAX_FRAC of the rows (at
+    least one allowed)."""
+    ties = int(np.sum(ref.near_tie))
+    rows = len(ref.near_tie)
+    assert ties <= max(1, NEAR_TIE_MAX_FRAC * rows), "%s: %d of %d rows are near ties" % (what, ties, rows)
+    return ~ref.near_tie
 
 
 # A schedule whose runs settle: total travel step0 / (1 - decay) ~ 1.7 edge

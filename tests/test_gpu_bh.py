@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_2002_08233_amd import api, inputs as I
-from _parity import (RUN_TOL, SETTLING, assert_forces, assert_within_oracle_spread, near_grid_init, quality,
+from _parity import (bh_mask, RUN_TOL, SETTLING, assert_forces, assert_within_oracle_spread, near_grid_init, quality,
                      stop_tolerance)
 
 pytestmark = pytest.mark.gpu
@@ -30,7 +30,7 @@ def test_one_shot_forces(grid32, theta, batch):
     fx, fy = api.forces(g, x, y, batch, p)
     ref = oracle.forces_bh(g.rowptr, g.colidx, x, y, oracle.Tree(x, y), batch * 128, batch * 128 + 128,
                            theta=theta)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie, what="theta=%g" % theta)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref), what="theta=%g" % theta)
     if theta == 0.0:
         ex = oracle.forces_exact(g.rowptr, g.colidx, x, y, batch * 128, batch * 128 + 128)
         assert_forces(fx, fy, ex, what="theta=0 vs exact")
@@ -50,7 +50,7 @@ def test_pipeline_step_forces(grid32, iters, stop, snapshot_leaves):
         xs, ys = h.get_coords()
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(sx, sy), stop * 128, stop * 128 + 128,
                            theta=1.2, leaf_live=not snapshot_leaves)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref))
 
 
 def test_rmat_hubs_and_snapshot_argument():
@@ -65,14 +65,14 @@ def test_rmat_hubs_and_snapshot_argument():
         _, st, fx, fy = h.run(1, stop_batch=9)
         xs, ys = h.get_coords()
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), 9 * 256, 10 * 256, theta=1.2)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie, what="pipeline")
+    assert_forces(fx, fy, ref, mask=bh_mask(ref), what="pipeline")
     fx2, fy2 = api.forces(g, xs, ys, 9, p, snapshot=(x0, y0))
-    assert_forces(fx2, fy2, ref, mask=~ref.near_tie, what="one-shot with snapshot")
+    assert_forces(fx2, fy2, ref, mask=bh_mask(ref), what="one-shot with snapshot")
     for b in (0, 15):    # hub rows sit at low ids
         fx3, fy3 = api.forces(g, xs, ys, b, p, snapshot=(x0, y0))
         ref3 = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), b * 256, b * 256 + 256,
                                 theta=1.2)
-        assert_forces(fx3, fy3, ref3, mask=~ref3.near_tie, what="batch %d" % b)
+        assert_forces(fx3, fy3, ref3, mask=bh_mask(ref3), what="batch %d" % b)
 
 
 def test_late_list_overflow_falls_back_to_full_walk():
@@ -92,7 +92,7 @@ def test_late_list_overflow_falls_back_to_full_walk():
         xs, ys = h.get_coords()
     assert st["late_overflow"] > 0
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), 6 * 256, 7 * 256, theta=0.3)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref))
 
 
 @pytest.mark.parametrize("n,bs", [(1, 4), (2, 1), (3, 2), (600, 100), (777, 1024)])
@@ -108,7 +108,7 @@ def test_small_and_ragged(n, bs):
         _, _, fx, fy = h.run(1, stop_batch=nb - 1)
         xs, ys = h.get_coords()
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), (nb - 1) * bs, n, theta=1.0)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref))
 
 
 def test_coincident_points_bucket():
@@ -123,7 +123,7 @@ def test_coincident_points_bucket():
     p = api.params(batch_size=64, iterations=1, mode="bh", theta=1.2)
     fx, fy = api.forces(g, x0, y0, 0, p)
     ref = oracle.forces_bh(g.rowptr, g.colidx, x0, y0, oracle.Tree(x0, y0), 0, 64, theta=1.2)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref))
 
 
 def test_full_run_settling_schedule_within_one_percent():
@@ -183,7 +183,7 @@ def test_segmented_chain_ragged(iters, stop):
         xs, ys = h.get_coords()
     r1 = min(n, stop * 64 + 64)
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(sx, sy), stop * 64, r1, theta=1.2)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie, what="stop %d" % stop)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref), what="stop %d" % stop)
 
 
 @pytest.mark.parametrize("stop", [25, 29])
@@ -205,7 +205,7 @@ def test_window_forces_segments_at_big_batches(stop):
         xs, ys = h.get_coords()
     r1 = min(n, stop * 1024 + 1024)
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), stop * 1024, r1, theta=1.2)
-    assert_forces(fx, fy, ref, mask=~ref.near_tie, what="stop %d" % stop)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref), what="stop %d" % stop)
 
 
 @pytest.mark.parametrize("n,bs", [(3000, 128), (12783, 64)])
