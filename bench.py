@@ -53,7 +53,6 @@ def flop_per_pair(model):
 # (FETCH_SIZE scaled by 2.0, the factor a plain copy of known size shows; WRITE_SIZE by 1.0).
 # Valid only while the kernel's source file is the one the counters were taken on.
 MEASURED_TRAFFIC = {
-    ("c2-bh", "chain_kernel"): (626138.7, "bl_bh.hip", "b4e961fb7f770662"),
 }
 
 
@@ -296,7 +295,7 @@ def bench_single(args, api, config, steps=None, warmup=None, precision=None, ext
         _, st = dev.run(psteps)
         out["profiled_steps"] = psteps
         kern = {}
-        for name in ("tree_build", "far_kernel", "old_sum_kernel", "chain_kernel", "rows_kernel", "step_kernel",
+        for name in ("tree_build", "far_kernel", "old_sum_kernel", "chain2_kernel", "rows_kernel", "step_kernel",
                      "steps_kernel", "finalize_kernel", "exact_graph_kernel"):
             ms, cnt = dev.profile_read(name)
             if cnt:
@@ -308,7 +307,7 @@ def bench_single(args, api, config, steps=None, warmup=None, precision=None, ext
             tests = dev.profile_read("cell_tests")[1]
             rows = float(g.n) * psteps   # every row once per iteration in each kernel below
             work = {"far_kernel": BYTES_PER_VISIT * visits + BYTES_PER_WALK_VERTEX * rows,
-                    "chain_kernel": BYTES_PER_UPDATE * rows + BYTES_PER_ENTRY * recent_e,
+                    "chain2_kernel": BYTES_PER_UPDATE * rows + BYTES_PER_ENTRY * recent_e,
                     "old_sum_kernel": BYTES_PER_ENTRY * old_e}
             for k, total in work.items():
                 if k in kern:
@@ -326,7 +325,7 @@ def bench_single(args, api, config, steps=None, warmup=None, precision=None, ext
                          "late_entries_per_vertex": late / rows,
                          "old_entries_per_vertex": old_e / rows, "recent_entries_per_vertex": recent_e / rows,
                          "late_overflow": st["late_overflow"],
-                         "chain_us_per_batch": 1e3 * kern["chain_kernel"]["total_ms"] / (nb * psteps)}
+                         "chain_us_per_batch": 1e3 * kern["chain2_kernel"]["total_ms"] / (nb * psteps)}
             # the whole Barnes-Hut iteration on the same units: walks, every CSR
             # entry's attraction, moved leaves, updates and the tree build
             path_bytes = (BYTES_PER_VISIT * visits / psteps + BYTES_PER_ENTRY * (g.nnz + late / psteps)
@@ -473,7 +472,12 @@ def main():
         secs = args.serve_seconds if args.config == "c5" else args.compact_serve_seconds
         stream = I.served_stream(rate=args.serve_rate, duration=secs)
         with mp.get_context("fork").Pool(min(16, os.cpu_count() or 4)) as pool:
-            reqs = pool.map(_served_request, stream)
+            reqs = []
+            for r in pool.imap(_served_request, stream, chunksize=4):
+                reqs.append(r)
+                if len(reqs) % 200 == 0:
+                    print("served stream: %d of %d request graphs generated" % (len(reqs), len(stream)),
+                          file=sys.stderr, flush=True)
 
     import torch
     from paper_2002_08233_amd import api
@@ -685,6 +689,9 @@ def bench_served(args, api, reqs, window=None):
             if delay > 0:
                 time.sleep(delay)
             ids[q] = srv.submit(g, x0, y0, p)
+            if (q + 1) % 100 == 0:
+                print("served stream: %d requests submitted at %.1f s" % (q + 1, time.perf_counter() - t_start),
+                      file=sys.stderr, flush=True)
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -694,6 +701,9 @@ def bench_served(args, api, reqs, window=None):
         srv.wait(ids[q], 3600.0)
         _, _, st = srv.fetch(ids[q])
         lat.append(st["seconds"])
+        if (q + 1) % 100 == 0:
+            print("served stream: %d requests done at %.1f s" % (q + 1, time.perf_counter() - t_start),
+                  file=sys.stderr, flush=True)
     t_end = time.perf_counter()
     srv.close()
     fu = float(sum(g.n * 300 for _, g, _, _ in reqs))

@@ -320,7 +320,7 @@ int bl_graph_profile(bl_graph *h, int32_t enable);
 /* Totals since the last bl_graph_profile(h, 1) for one kernel: "rows_kernel",
  * "step_kernel", "finalize_kernel", "exact_graph_kernel", "steps_kernel" (exact mode),
  * "tree_build" (the whole quadtree build sequence, one entry per iteration),
- * "far_kernel", "old_sum_kernel", "chain_kernel" (Barnes-Hut, one entry per
+ * "far_kernel", "old_sum_kernel", "chain2_kernel" (Barnes-Hut, one entry per
  * launch).  Counts instead of times, returned in *launches: "late_entries"
  * (moved-leaf entries the far-field walks listed), "old_entries" and
  * "recent_entries" (moved-neighbour and moved-leaf entries summed by the

@@ -24,12 +24,15 @@
 //   9. late lists      per batch: the moved neighbours and listed moved leaves,
 //                      split into entries that refer to earlier chain segments
 //                      ("old") and to the batch's own segment ("recent")
-//  10. per segment     old_sum_kernel (full chip) sums the segment's old
-//                      entries; chain_kernel (one workgroup per job) then walks
-//                      the segment's batches in order: the recent entries with
-//                      live coordinates from an LDS window of the segment's
-//                      moved vertices, then the batch update (Alg. 2 update
-//                      loop)
+//  10. slot plan       the recent entries laid out one per lane, each row's
+//                      run inside one 16-lane DPP row; one record per row
+//                      (start position, force apart from recent entries)
+//  11. per segment     old_sum_kernel (full chip) adds the segment's old
+//                      entries into the row records; chain2_kernel (one
+//                      workgroup per job) then walks the segment's batches in
+//                      order: the recent entries with live coordinates from an
+//                      LDS window of the segment's moved vertices, then the
+//                      batch update (Alg. 2 update loop)
 #include <algorithm>
 #include <cfloat>
 #include <cstring>
@@ -1714,7 +1717,7 @@ int bh_engine_create(hipStream_t s, BHEngine **out) {
                                            (int)(sizeof(float2) * kWindow));
         if (r != hipSuccess) {
             bh_engine_destroy(e);
-            set_error("hipFuncSetAttribute(chain_kernel) failed: %s", hipGetErrorString(r));
+            set_error("hipFuncSetAttribute(chain2_kernel) failed: %s", hipGetErrorString(r));
             return BL_E_HIP;
         }
     }

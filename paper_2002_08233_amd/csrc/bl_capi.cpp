@@ -379,7 +379,7 @@ int bl_graph_run(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t st
 }
 
 static const char *kProfNames[PK_COUNT] = {"rows_kernel", "step_kernel",        "finalize_kernel",
-                                           "tree_build",  "far_kernel",         "chain_kernel",
+                                           "tree_build",  "far_kernel",         "chain2_kernel",
                                            "exact_graph_kernel", "old_sum_kernel", "steps_kernel"};
 
 int bl_graph_profile(bl_graph *g, int32_t enable) {
