@@ -103,7 +103,7 @@ struct BHJob {
     gptr<float2> atte;
     gptr<int> roff, roff_old, bbase, bold;
     gptr<float4> rec;           // per vertex, for the chain: x, y and the force apart from recent entries
-    gptr<int2> rmeta;           // per vertex: offset in its batch's recent list, late-leaf count
+    gptr<int2> rmeta;           // per vertex: its recent entries' range [x, y) in its batch's recent list
     gptr<int> osplit;           // per batch: kOldSplit + 1 row bounds splitting its old part
     gptr<unsigned long long> ent;
     size_t ent_cap;
@@ -111,6 +111,8 @@ struct BHJob {
     gptr<int> pbase;            // [nb + 1] slot count of each batch, then (scanned) its first slot
     gptr<unsigned long long> slots;   // the batches' slot plans (chain2_kernel)
     gptr<int> povf;             // [nb] a row of the batch overflowed its leaf list
+    gptr<int4> bmeta;           // [nb] first slot, slot count, recent-list start, overflow flag
+    gptr<float2> sink;          // [kChainThreads] chain stores of lanes without a moved position
     gptr<double> energy;        // one value per iteration of the run
     gptr<double> fout;
     Counters *ctr;
@@ -844,7 +846,7 @@ __device__ __forceinline__ void att_run(const BHJob &J, int e, int e1, float2 pi
                 const float dx = pj[u].x - pi.x, dy = pj[u].y - pi.y;
                 float d;
                 if constexpr (GM) d = dpow(dx, dy, J.ka) * invK;   // d^(a-1) / K
-                else d = sqrtf(dx * dx + dy * dy) * invK;
+                else d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy) * invK;   // hardware sqrt, about 1 ulp
                 ax = fmaf(d, dx, ax);
                 ay = fmaf(d, dy, ay);
             }
@@ -1049,7 +1051,7 @@ __device__ __forceinline__ void entry_term(unsigned long long w, float dx, float
     if ((((unsigned)w) & 0x80000000u) == 0u) {
         float d;
         if constexpr (GM) d = dpow(dx, dy, ka) * invK;
-        else d = sqrtf(fmaf(dx, dx, dy * dy)) * invK;
+        else d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) * invK;   // hardware sqrt, about 1 ulp
         ax = fmaf(d, dx, ax);
         ay = fmaf(d, dy, ay);
     } else {
@@ -1280,12 +1282,15 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
 // row.  One barrier per step makes the moved positions visible to the next.
 constexpr int kRunLanes = 16;
 constexpr int kMoreLoads = 8;         // list words a lane of a long row loads at once
+constexpr int kPassChunk = 2;         // further passes of a batch whose loads the chain issues together
 // Slot word: bits 0-31 the entry word's low half (vertex | leaf bit 31),
 // 32-41 the row in its batch, 42-45 lanes after this one in the row's run,
 // 46 holds an entry, 47 first lane of the run (moves the row), 48 the row has
-// more than kRunLanes entries, 49 padding (no row).
+// more than kRunLanes entries, 49 padding (no row), 50 the row's late-leaf
+// list overflowed (its far field comes from a full walk when it moves).  A
+// batch's plan ends with at least one padding slot.
 constexpr unsigned long long kSlotHas = 1ull << 46, kSlotLead = 1ull << 47, kSlotMore = 1ull << 48,
-                             kSlotPad = 1ull << 49;
+                             kSlotPad = 1ull << 49, kSlotWalk = 1ull << 50;
 static_assert(kMaxChainRows <= 1024, "slot words hold the row in 10 bits");
 
 // Recent entries of row r of batch b (R rows); bbase holds list starts.
@@ -1321,7 +1326,7 @@ __global__ __launch_bounds__(1024) void plan_count_kernel(BH_KERNEL_ARGS) {
             start[q] = pos;
             pos += l;
         }
-        J.pbase[b] = (pos + kRunLanes - 1) & ~(kRunLanes - 1);
+        J.pbase[b] = (pos + kRunLanes) & ~(kRunLanes - 1);   // at least one padding slot last
         if (b == 0) J.pbase[J.nb] = 0;
     }
     __syncthreads();
@@ -1344,7 +1349,7 @@ __global__ __launch_bounds__(256) void plan_fill_kernel(BH_KERNEL_ARGS) {
     for (int j = 0; j < l; ++j) {
         unsigned long long w = rb | ((unsigned long long)(l - 1 - j) << 42);
         if (j < cr) w |= kSlotHas | (J.ent[list + j] & 0xffffffffull);
-        if (j == 0) w |= kSlotLead;
+        if (j == 0) w |= kSlotLead | (J.late_cnt[i] > kLateCap ? kSlotWalk : 0ull);
         if (cr > kRunLanes) w |= kSlotMore;
         J.slots[base + s0 + j] = w;
     }
@@ -1362,22 +1367,15 @@ __global__ __launch_bounds__(256) void plan_fill_kernel(BH_KERNEL_ARGS) {
         bs.y += J.negRK2 * (fr.y - fr.w);
     }
     st<float4>(J.rec, i, float4{p.x, p.y, bs.x, bs.y});
-    st<int2>(J.rmeta, i, int2{J.roff[i], lc});
+    st<int2>(J.rmeta, i, int2{J.roff[i], J.roff[i] + cr});
+    if (r == 0)
+        st<int4>(J.bmeta, b, int4{J.pbase[b], J.pbase[b + 1] - J.pbase[b], J.bbase[b] + J.bold[b], J.povf[b]});
 }
 
 struct Chain2Shared {
-    int off[2][kMaxChainRows + 1];    // row offsets in the batch's recent list, by step parity
-    float4 rec[2][kMaxChainRows];     // rows' x, y and force apart from recent entries, by step parity
-    int meta[4][8];                   // batches b .. b + 3 (by b mod 4): kMeta* fields
     double wsd[16];
     double step;
 };
-
-// Fields of a batch's metadata: its first slot and the next batch's, its list
-// start, old-part length and the next batch's list start, and whether a row
-// of it overflowed its leaf list (its full walk reads moved positions from
-// memory).
-enum { kMetaPb0 = 0, kMetaPb1, kMetaBb, kMetaBo, kMetaBn, kMetaOvf, kMetaFields };
 
 // Barrier for LDS traffic only: every wave's LDS stores are complete and
 // visible after it, while global loads and stores stay in flight.
@@ -1404,19 +1402,99 @@ __device__ __forceinline__ float run_suffix_sum(float v, int rem) {
     return v;
 }
 
-// The minibatch chain over the slot plan: one workgroup per job walks its
-// batches in order.  Step b writes batch b + 1's rows to LDS (loaded in step
-// b - 1), issues the loads later steps need (batch b + 1's pass-0 slot words,
-// batch b + 2's row records, batch b + 4's metadata by lanes of the first
-// wave), stores the positions moved in step b - 1, then runs batch b's slots;
-// a barrier on LDS traffic alone ends the step, so those loads and stores
-// stay in flight across it.  The rows' terms use the positions their batch
-// sees: moved ones from the LDS window of the segment (WIN; Jacobi within the
-// batch, Gauss-Seidel across batches) or from memory (one-shot force calls,
-// where nothing moves), the rows' own from LDS.
+// Uniform loads through the scalar unit (the address is the same for every
+// lane): the chain's per-batch records (first slot, slot count, recent-list
+// start, overflow flag).
+__device__ __forceinline__ int4 sld4(gptr<const int4> p, int i) {
+    using B = RawBits<16>::type;
+    return __builtin_bit_cast(int4, ((const __attribute__((address_space(4))) B *)p)[__builtin_amdgcn_readfirstlane(i)]);
+}
+__device__ __forceinline__ int2 sld2(gptr<const int4> p, int i) {   // the first two fields
+    using B = RawBits<8>::type;
+    return __builtin_bit_cast(int2,
+                              ((const __attribute__((address_space(4))) B *)p)[2 * __builtin_amdgcn_readfirstlane(i)]);
+}
+
+// Two paths of the chain off its common case: the terms of a long row's
+// recent entries [o0, o1) past its first kRunLanes (every kRunLanes-th from
+// lane position jl, kMoreLoads list words in flight at a time), and the far
+// field of a row whose late-leaf list overflowed, from a full walk over the
+// live positions.  The walk reads its job fields through a pointer that an
+// empty asm statement hands it inside the branch, so that the compiler cannot
+// hoist those reads into the hot loop's scalar registers.
+using JobC = const __attribute__((address_space(4))) BHJob *;
+__device__ __forceinline__ JobC launder(const BHJob *p) {
+    JobC q = (JobC)p;
+    asm volatile("" : "+s"(q));
+    return q;
+}
+
 template <bool GM, bool WIN>
-__device__ __forceinline__ void chain2_run(const BHJob &J, Chain2Shared &S, float2 *win, int first, int last,
-                                           int wbase, bool first_launch, bool last_launch) {
+__device__ __forceinline__ float2 long_row_terms(gptr<const unsigned long long> ent, const float2 *win, int wbase,
+                                                 gptr<const float2> pos, size_t lst, int o0, int o1, int jl, float x,
+                                                 float y, float invK, float negRK2, int ka, int kr) {
+    float ax = 0.f, ay = 0.f;
+    for (int e0 = o0 + jl + kRunLanes; e0 < o1; e0 += kMoreLoads * kRunLanes) {
+        unsigned long long we[kMoreLoads];
+#pragma unroll
+        for (int u = 0; u < kMoreLoads; ++u) {
+            const int e = e0 + u * kRunLanes;
+            we[u] = e < o1 ? ent[lst + e] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kMoreLoads; ++u) {
+            if (e0 + u * kRunLanes < o1) {
+                const int j = (int)((unsigned)we[u] & 0x7fffffffu);
+                const float2 pj = WIN ? win[j - wbase] : ld<float2>(pos, j);
+                entry_term<GM>(we[u], pj.x - x, pj.y - y, invK, negRK2, ka, kr, ax, ay);
+            }
+        }
+    }
+    return float2{ax, ay};
+}
+
+template <bool GM>
+__device__ __forceinline__ float2 overflow_far(JobC Jp, int i, float x, float y) {
+    WalkArgs wa;
+    wa.n = Jp->n;
+    wa.BS = Jp->BS;
+    wa.total = Jp->nnodes;
+    wa.nodeA = Jp->nodeA;
+    wa.nodeB = Jp->nodeB;
+    wa.leafpos = Jp->leafpos;
+    wa.theta2 = Jp->theta2;
+    wa.negRK2 = Jp->negRK2;
+    wa.invK = Jp->invK;
+    wa.kr = Jp->kr;
+    float4 fr;
+    int dummy = 0;
+    (void)bh_walk<GM>(wa, i, x, y, 0, Jp->pos, fr, nullptr, dummy, 0);
+    return float2{wa.negRK2 * (fr.x - fr.z), wa.negRK2 * (fr.y - fr.w)};
+}
+
+// Wait until at most three vector memory operations of this wave are
+// outstanding (s_waitcnt vmcnt(3); the LDS/scalar and export counters are
+// left alone).
+__device__ __forceinline__ void wait_vm3() { __builtin_amdgcn_s_waitcnt(0x0F73); }
+
+// The minibatch chain over the slot plan: one workgroup per job walks its
+// batches in order, one step per batch.  A lane's slot word is loaded four
+// steps before its batch comes up and its row's record two steps before (the
+// record's address is the slot word's row); batch metadata comes through the
+// scalar unit a step ahead.  Every step issues three vector memory operations
+// in a fixed order -- the record two batches ahead, the store of the position
+// moved in the previous step (lanes without one store to a per-job sink), the
+// slot word four batches ahead -- and only steps with long rows, overflowed
+// rows or more slots than lanes add others in between.  Waiting at the start
+// of a step until at most three are outstanding therefore completes every
+// operation of the steps before the previous one and leaves the previous
+// step's loads in flight.  A barrier on LDS traffic alone ends the step.  The
+// rows' terms use the positions their batch sees: moved ones from the LDS
+// window of the segment (WIN; Jacobi within the batch, Gauss-Seidel across
+// batches) or from memory (one-shot force calls, where nothing moves).
+template <bool GM, bool WIN>
+__device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chain2Shared &S, float2 *win, int first,
+                                           int last, int wbase, bool first_launch, bool last_launch) {
     const int tid = threadIdx.x;
     const int BS = J.BS, n = J.n;
     const PosL pl{win, wbase};
@@ -1426,119 +1504,99 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, Chain2Shared &S, floa
         else return pg(j);
     };
     const float invK = J.invK, negRK2 = J.negRK2;
-    const WalkArgs wa = walk_args(J);
     const int k_it = J.kiter[0];
-    auto nrows = [&](int b) { return min(BS, n - b * BS); };
-    // lane f < kMetaFields of the first wave: field f of batch q's metadata
-    // (one load per lane, from the array and index the field names)
-    const gptr<const int> p_pbase = J.pbase, p_bbase = J.bbase, p_bold = J.bold, p_povf = J.povf;
-    const gptr<const int> meta_src = tid <= kMetaPb1 ? p_pbase
-                                     : (tid == kMetaBo ? p_bold : (tid == kMetaOvf ? p_povf : p_bbase));
-    const int meta_add = (tid == kMetaPb1 || tid == kMetaBn) ? 1 : 0;
-    auto meta_field = [&](int q) -> int { return meta_src[q + meta_add]; };
-    auto M = [&](int b, int f) -> int { return S.meta[b & 3][f]; };
-    // pass-0 slot word of batch b for this lane (padding past its slots)
-    auto slot_word = [&](int b) -> unsigned long long {
-        const int pb0 = M(b, kMetaPb0);
-        return tid < M(b, kMetaPb1) - pb0 ? J.slots[(size_t)pb0 + tid] : kSlotPad;
+    const gptr<const int4> p_bmeta = J.bmeta;
+    const gptr<const unsigned long long> p_slots = J.slots, p_ent = J.ent;
+    const gptr<const float4> p_rec = J.rec;
+    const gptr<const int2> p_rmeta = J.rmeta;
+    const gptr<float2> p_pos = J.pos, p_sink = J.sink;
+    // this lane's slot word of a batch with first slot pb0 and sc slots
+    // (lanes past the last slot read the last one, which is padding)
+    auto slot_load = [&](int pb0, int sc) -> unsigned long long {
+        return p_slots[(size_t)pb0 + min(tid, sc - 1)];
     };
-    struct Row {
-        float4 rec;
-        int2 meta;
+    auto rec_load = [&](int b, unsigned long long w) -> float4 {
+        return ld<float4>(p_rec, (size_t)b * BS + (int)((w >> 32) & 1023u));
     };
-    auto load_row = [&](int b, Row &rd) {
-        if (tid < nrows(b)) {
-            rd.rec = ld<float4>(J.rec, (size_t)b * BS + tid);
-            rd.meta = ld<int2>(J.rmeta, (size_t)b * BS + tid);
-        }
-    };
-    auto write_lds = [&](int b, int slot, const Row &rd) {
-        const int R = nrows(b);
-        if (tid < R) {
-            S.off[slot][tid] = rd.meta.x;
-            S.rec[slot][tid] = rd.rec;
-        }
-        if (tid == 0) S.off[slot][R] = M(b, kMetaBn) - M(b, kMetaBb) - M(b, kMetaBo);
+    // a long row's recent-entry range (lanes of other rows: none)
+    auto range_load = [&](int b, unsigned long long w) -> int2 {
+        return (w & kSlotMore) ? ld<int2>(p_rmeta, (size_t)b * BS + (int)((w >> 32) & 1023u)) : int2{0, 0};
     };
 
-    // prologue: metadata of the first three batches in LDS, of the fourth in
-    // registers; the first batch's rows and slot words, the second's rows
     if (tid == 0) {
         double st = J.step0;
         for (int t = 0; t < k_it; ++t) st *= J.decay;
         S.step = st;
     }
-    for (int q = 0; q < 3; ++q)
-        if (tid < kMetaFields && first + q <= last) S.meta[(first + q) & 3][tid] = meta_field(first + q);
-    int mreg = 0;
-    if (tid < kMetaFields && first + 3 <= last) mreg = meta_field(first + 3);
     if (WIN)   // batches of the segment moved before this launch
         for (int v = wbase + tid; v < first * BS; v += kChainThreads) win[v - wbase] = ld<float2>(J.pos, v);
-    __syncthreads();
-    Row rdA{}, rdB{};
-    load_row(first, rdA);
-    write_lds(first, first & 1, rdA);
-    unsigned long long wA = slot_word(first), wB = kSlotPad;
-    if (first + 1 <= last) load_row(first + 1, rdA);
+    // prologue: slot words of the first four batches, records of the first two
+    auto bq = [&](int q) { return min(q, last); };
+    unsigned long long W0, W1, W2, W3;
+    float4 R0{}, R1{}, R2{}, R3{};
+    int2 O0{}, O1{}, O2{}, O3{};
+    {
+        int2 q = sld2(p_bmeta, bq(first));
+        W0 = slot_load(q.x, q.y);
+        q = sld2(p_bmeta, bq(first + 1));
+        W1 = slot_load(q.x, q.y);
+        q = sld2(p_bmeta, bq(first + 2));
+        W2 = slot_load(q.x, q.y);
+        q = sld2(p_bmeta, bq(first + 3));
+        W3 = slot_load(q.x, q.y);
+        R0 = rec_load(bq(first), W0);
+        R1 = rec_load(bq(first + 1), W1);
+        O0 = range_load(bq(first), W0);
+        O1 = range_load(bq(first + 1), W1);
+    }
+    // scalar state: this batch's record, batch b + 4's first slot and slot count
+    int4 bm = sld4(p_bmeta, first);
+    int2 q4 = sld2(p_bmeta, bq(first + 4));
     __syncthreads();
     const float step = (float)S.step;
 
     double e_iter = 0.0;
     unsigned long long bad = 0;
     // position of the row this thread moved as a lead lane of the last step's
-    // first pass, stored one step later (i < 0: none)
+    // first pass, stored one step later (i < 0: none; its store goes to the
+    // lane's sink word)
+    const gptr<float2> sink_lane = p_sink + tid;
     int pend_i = -1;
+    gptr<float2> pend_a = sink_lane;
     float2 pend_p{0.f, 0.f};
 
     // Terms of one slot, the run's suffix sum, and the row's move by its lead lane.
-    auto do_slot = [&](int b, int slot, unsigned long long w, bool stop, bool defer) {
+    auto do_slot = [&](int b, unsigned long long w, const float4 &rc, const int2 &om, bool stop, bool defer)
+                       __attribute__((always_inline)) {
         const bool pad = (w & kSlotPad) != 0;
         if (!__any(!pad)) return;   // a wave of padding only
-        const int r = pad ? 0 : (int)((w >> 32) & 1023u);
-        const int rem = (int)((w >> 42) & 15u);
+        const int r = (int)((w >> 32) & 1023u);
+        const int rem = pad ? 0 : (int)((w >> 42) & 15u);
         float ax = 0.f, ay = 0.f;
-        const float4 rc = S.rec[slot][r];
         if (!pad) {
             if (w & kSlotHas) {
                 const float2 pj = gather((int)((unsigned)w & 0x7fffffffu));
                 entry_term<GM>(w, pj.x - rc.x, pj.y - rc.y, invK, negRK2, J.ka, J.kr, ax, ay);
             }
             if (w & kSlotMore) {
-                // every kRunLanes-th further entry of the row, from the batch
-                // list, kMoreLoads list words in flight at a time
-                const int jl = (kRunLanes - 1) - rem;
-                const size_t lst = (size_t)M(b, kMetaBb) + M(b, kMetaBo);
-                const int o0 = S.off[slot][r], o1 = S.off[slot][r + 1];
-                for (int e0 = o0 + jl + kRunLanes; e0 < o1; e0 += kMoreLoads * kRunLanes) {
-                    unsigned long long we[kMoreLoads];
-#pragma unroll
-                    for (int u = 0; u < kMoreLoads; ++u) {
-                        const int e = e0 + u * kRunLanes;
-                        we[u] = e < o1 ? J.ent[lst + e] : 0ull;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kMoreLoads; ++u) {
-                        if (e0 + u * kRunLanes < o1) {
-                            const float2 pj = gather((int)((unsigned)we[u] & 0x7fffffffu));
-                            entry_term<GM>(we[u], pj.x - rc.x, pj.y - rc.y, invK, negRK2, J.ka, J.kr, ax, ay);
-                        }
-                    }
-                }
+                const float2 t = long_row_terms<GM, WIN>(p_ent, win, wbase, p_pos, (size_t)bm.z, om.x, om.y,
+                                                         (kRunLanes - 1) - rem, rc.x, rc.y, invK, negRK2, J.ka,
+                                                         J.kr);
+                ax += t.x;
+                ay += t.y;
             }
         }
-        if (__any(!pad && rem > 0)) {
+        if (__any(rem > 0)) {
             ax = run_suffix_sum(ax, rem);
             ay = run_suffix_sum(ay, rem);
         }
         if (pad || !(w & kSlotLead)) return;
         const int i = b * BS + r;
         float fx = ax + rc.z, fy = ay + rc.w;
-        if (M(b, kMetaOvf) && J.late_cnt[i] > kLateCap) {
-            float4 fr;
-            int dummy = 0;
-            (void)bh_walk<GM>(wa, i, rc.x, rc.y, 0, J.pos, fr, nullptr, dummy, 0);
-            fx += negRK2 * (fr.x - fr.z);
-            fy += negRK2 * (fr.y - fr.w);
+        if (w & kSlotWalk) {
+            const float2 t = overflow_far<GM>(launder(Jg), i, rc.x, rc.y);
+            fx += t.x;
+            fy += t.y;
         }
         if (stop) {
             J.fout[2 * r] = (double)fx;
@@ -1557,55 +1615,73 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, Chain2Shared &S, floa
                 np = float2{rc.x + sc * fx, rc.y + sc * fy};
                 if (defer) {
                     pend_i = i;
+                    pend_a = p_pos + i;
                     pend_p = np;
                 } else {
-                    st<float2>(J.pos, i, np);
+                    st<float2>(p_pos, i, np);
                 }
             }
         }
         if (WIN) win[i - wbase] = np;
     };
 
-    // step b: w_cur holds batch b's pass-0 slot word, rd1 batch b + 1's rows;
-    // w_nx receives batch b + 1's slot word, rd2 batch b + 2's rows.
-    auto chain_step = [&](int b, unsigned long long w_cur, const Row &rd1, unsigned long long &w_nx, Row &rd2) {
-        const int slot = b & 1;
+    // step b: wc / rc / oc hold batch b's slot word, record and long-row
+    // range; w2 holds batch b + 2's slot word, and r2 / o2 receive its record
+    // and range; wc receives batch b + 4's slot word.
+    auto chain_step = [&](int b, unsigned long long &wc, const float4 &rc, const int2 &oc,
+                          const unsigned long long &w2, float4 &r2, int2 &o2) __attribute__((always_inline)) {
         const bool stop = (b == J.stop_batch);
-        const bool more = b + 1 <= last;
-        // The loads and stores of the previous step are complete here (one
-        // explicit wait, so that no later use of what they loaded waits for
-        // this step's loads); then this step's loads are issued.
-        __builtin_amdgcn_s_waitcnt(0);
-        if (tid < kMetaFields && b + 3 <= last) S.meta[(b + 3) & 3][tid] = mreg;   // batch b - 1's entry is free
-        if (more) write_lds(b + 1, slot ^ 1, rd1);
-        const unsigned long long w0 = w_cur;
-        const bool walk_next = more && M(b + 1, kMetaOvf);
-        if (more) w_nx = slot_word(b + 1);
-        if (b + 2 <= last) load_row(b + 2, rd2);
-        if (tid < kMetaFields && b + 4 <= last) mreg = meta_field(b + 4);
-        if (pend_i >= 0) st<float2>(J.pos, pend_i, pend_p);
+        wait_vm3();
+        // next step's scalar state (its loads complete at this step's barrier)
+        const int4 bmn = sld4(p_bmeta, bq(b + 1));
+        const int2 q5 = sld2(p_bmeta, bq(b + 5));
+        r2 = rec_load(bq(b + 2), w2);
+        o2 = range_load(bq(b + 2), w2);
+        st<float2>(pend_a, 0, pend_p);   // the position this lane moved in the previous step, or the sink
         pend_i = -1;
-        do_slot(b, slot, w0, stop, true);
-        const int sc = M(b, kMetaPb1) - M(b, kMetaPb0);
-        for (int p = 1; p * kChainThreads < sc; ++p) {   // batches with more slots than lanes
-            const int sidx = p * kChainThreads + tid;
-            const unsigned long long w = sidx < sc ? J.slots[(size_t)M(b, kMetaPb0) + sidx] : kSlotPad;
-            do_slot(b, slot, w, stop, false);
+        pend_a = sink_lane;
+        do_slot(b, wc, rc, oc, stop, true);
+        // batches with more slots than lanes: further passes, kPassChunk at a
+        // time with their loads issued together
+        const int pb = bm.x, sc = bm.y;
+        for (int p0 = 1; p0 * kChainThreads < sc; p0 += kPassChunk) {
+            unsigned long long wq[kPassChunk];
+            float4 rq[kPassChunk];
+            int2 oq[kPassChunk];
+#pragma unroll
+            for (int u = 0; u < kPassChunk; ++u)
+                wq[u] = (p0 + u) * kChainThreads < sc
+                            ? p_slots[(size_t)pb + min((p0 + u) * kChainThreads + tid, sc - 1)]
+                            : kSlotPad;
+#pragma unroll
+            for (int u = 0; u < kPassChunk; ++u) {
+                rq[u] = rec_load(b, wq[u]);
+                oq[u] = range_load(b, wq[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kPassChunk; ++u)
+                if ((p0 + u) * kChainThreads < sc) do_slot(b, wq[u], rq[u], oq[u], stop, false);
         }
-        if (walk_next) {
+        wc = slot_load(q4.x, q4.y);
+        if (b + 1 <= last && bmn.w) {
             // a row of the next batch walks the tree over positions in memory
-            if (pend_i >= 0) st<float2>(J.pos, pend_i, pend_p);
+            if (pend_i >= 0) st<float2>(p_pos, pend_i, pend_p);
             pend_i = -1;
+            pend_a = sink_lane;
             __syncthreads();
         } else {
             lds_barrier();
         }
+        bm = bmn;
+        q4 = q5;
     };
-    for (int b = first; b <= last; b += 2) {
-        chain_step(b, wA, rdA, wB, rdB);
-        if (b + 1 <= last) chain_step(b + 1, wB, rdB, wA, rdA);
+    for (int b = first; b <= last; b += 4) {
+        chain_step(b, W0, R0, O0, W2, R2, O2);
+        if (b + 1 <= last) chain_step(b + 1, W1, R1, O1, W3, R3, O3);
+        if (b + 2 <= last) chain_step(b + 2, W2, R2, O2, W0, R0, O0);
+        if (b + 3 <= last) chain_step(b + 3, W3, R3, O3, W1, R1, O1);
     }
-    if (pend_i >= 0) st<float2>(J.pos, pend_i, pend_p);
+    if (pend_i >= 0) st<float2>(p_pos, pend_i, pend_p);
     if (bad) atomicAdd(&J.ctr->nonfinite, bad);
     const double e = block_sum_fixed(e_iter, S.wsd);
     if (tid == 0 && J.stop_batch < 0) {
@@ -1641,9 +1717,9 @@ __global__ __launch_bounds__(kChainThreads) void chain2_kernel(BH_KERNEL_ARGS, i
     const bool first_launch = (first == J.first_batch), last_launch = (last == J.last_batch);
     const int wbase = (J.nseg <= 1 ? 0 : seg * seg_len(J)) * J.BS;
     if (!J.all_live)
-        chain2_run<GM, true>(J, S, win, first, last, wbase, first_launch, last_launch);
+        chain2_run<GM, true>(J, jb.J, S, win, first, last, wbase, first_launch, last_launch);
     else
-        chain2_run<GM, false>(J, S, win, first, last, wbase, first_launch, last_launch);
+        chain2_run<GM, false>(J, jb.J, S, win, first, last, wbase, first_launch, last_launch);
 }
 
 // ------------------------------------------------------------- host side
@@ -1824,6 +1900,8 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->pbase = (decltype(J->pbase))(h.pbase);
     J->slots = (decltype(J->slots))(h.slots);
     J->povf = (decltype(J->povf))(h.povf);
+    J->sink = (decltype(J->sink))(h.sink);
+    J->bmeta = (decltype(J->bmeta))(h.bmeta);
     J->energy = (decltype(J->energy))(g->energy);
     J->fout = (decltype(J->fout))(g->fout);
     J->ctr = (decltype(J->ctr))(g->counters);
@@ -2012,7 +2090,8 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
            8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1) +
-           4 * N + 4 * (nb + 1) + 8 * (2 * kRunLanes * N + kRunLanes * nb) + 4 * nb + 16 * N;
+           4 * N + 4 * (nb + 1) + 8 * (2 * kRunLanes * N + 2 * kRunLanes * nb) + 4 * nb + 16 * N +
+           8 * (size_t)kChainThreads + 16 * nb;
 }
 
 int bh_alloc(bl_graph *g) {
@@ -2057,8 +2136,10 @@ int bh_alloc(bl_graph *g) {
     // 16-lane rows take fewer than twice their lanes, plus the last row's padding
     BL_TRY(graph_alloc(g, (void **)&h.pstart, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.pbase, 4 * ((size_t)g->nb + 1)));
-    BL_TRY(graph_alloc(g, (void **)&h.slots, 8 * (2 * kRunLanes * N + (size_t)kRunLanes * g->nb)));
+    BL_TRY(graph_alloc(g, (void **)&h.slots, 8 * (2 * kRunLanes * N + 2 * (size_t)kRunLanes * g->nb)));
     BL_TRY(graph_alloc(g, (void **)&h.povf, 4 * (size_t)g->nb));
+    BL_TRY(graph_alloc(g, (void **)&h.sink, 8 * (size_t)kChainThreads));
+    BL_TRY(graph_alloc(g, (void **)&h.bmeta, 16 * (size_t)g->nb));
     BL_TRY(graph_alloc(g, (void **)&h.kiter, 16));
     BL_HIP(hipMemsetAsync(h.bbox, 0, 64, g->stream));
     BL_HIP(hipMemsetAsync(h.kiter, 0, 16, g->stream));
