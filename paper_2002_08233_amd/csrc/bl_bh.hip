@@ -110,8 +110,8 @@ struct BHJob {
     gptr<int> pstart;           // per vertex: first slot of its row's run within its batch's slots
     gptr<int> pbase;            // [nb + 1] slot count of each batch, then (scanned) its first slot
     gptr<unsigned long long> slots;   // the batches' slot plans (chain2_kernel)
-    gptr<int> povf;             // [nb] a row of the batch overflowed its leaf list
-    gptr<int4> bmeta;           // [nb] first slot, slot count, recent-list start, overflow flag
+    gptr<int> pflag;            // [nb] batch flags of the slot plan (kFlag*)
+    gptr<int4> bmeta;           // [nb] first slot, slot count, recent-list start, batch flags
     gptr<float2> sink;          // [kChainThreads] chain stores of lanes without a moved position
     gptr<double> energy;        // one value per iteration of the run
     gptr<double> fout;
@@ -1273,24 +1273,36 @@ __global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
 
 // ------------------------------------------------ chain over a slot plan
 // Before the chain, the recent entries of each batch are laid out as "slots",
-// one per lane: a row takes min(max(cr, 1), kRunLanes) consecutive lanes (cr
-// its recent entries) inside one 16-lane row of a wave, lane j holding entry
-// j (and j + kRunLanes, j + 2 kRunLanes, ... when cr > kRunLanes).  A chain
-// step then needs no communication across waves before the update: each lane
-// forms its entry's term, a DPP suffix sum inside the 16-lane row brings the
-// run's sum to the run's first lane, and that lane completes and moves the
-// row.  One barrier per step makes the moved positions visible to the next.
+// one per lane of the chain's workgroup, and a batch never takes more than one
+// pass of the workgroup's lanes.  With k entries per lane (the smallest k for
+// which the batch fits), a row with cr recent entries takes
+// l = max(1, ceil(cr / k)) lanes: lane j holds entries j, j + l, j + 2l, ...
+// When l <= kRunLanes the lanes are one run inside a 16-lane row of a wave
+// (the row's slots rounded up to a power of two, so that runs stay inside
+// 16-lane rows); a longer row is split into 16-lane runs (its lane count
+// rounded up to a multiple of 16).  A step then forms each lane's terms, a DPP suffix sum
+// inside each run brings the run's sum to its first lane, and that lane
+// completes and moves the row; the first run of a split row adds the other
+// runs' sums, which they leave in LDS, in run order after a second barrier.
+// With k = 1 every entry is in its slot word, loaded steps ahead; with k > 1
+// the lane reads its entries from the batch list.  One barrier per step
+// (two with split rows) makes the moved positions visible to the next.
 constexpr int kRunLanes = 16;
-constexpr int kMoreLoads = 8;         // list words a lane of a long row loads at once
-constexpr int kPassChunk = 2;         // further passes of a batch whose loads the chain issues together
-// Slot word: bits 0-31 the entry word's low half (vertex | leaf bit 31),
-// 32-41 the row in its batch, 42-45 lanes after this one in the row's run,
-// 46 holds an entry, 47 first lane of the run (moves the row), 48 the row has
-// more than kRunLanes entries, 49 padding (no row), 50 the row's late-leaf
-// list overflowed (its far field comes from a full walk when it moves).  A
-// batch's plan ends with at least one padding slot.
-constexpr unsigned long long kSlotHas = 1ull << 46, kSlotLead = 1ull << 47, kSlotMore = 1ull << 48,
-                             kSlotPad = 1ull << 49, kSlotWalk = 1ull << 50;
+constexpr int kMoreLoads = 8;         // list words a lane with several entries loads at once
+// Slot word: bits 0-31 the entry word's low half (vertex | leaf bit 31), or
+// for a lane with several entries its lane index in the row (bits 0-15) and
+// the row's lane count (bits 16-31); 32-41 the row in its batch; 42-45 lanes
+// after this one in its run; 46 holds one entry; 47 first lane of a run; 48
+// several entries from the list; 49 padding (no row); 50 the row's late-leaf
+// list overflowed (its far field comes from a full walk when it moves); 51
+// first lane of the row (moves it); 52-57 the row's further runs.
+constexpr unsigned long long kSlotHas = 1ull << 46, kSlotLead = 1ull << 47, kSlotMulti = 1ull << 48,
+                             kSlotPad = 1ull << 49, kSlotWalk = 1ull << 50, kSlotRow = 1ull << 51;
+constexpr int kSlotRunsShift = 52;
+// Batch flags (pflag): bit 0 a row overflowed its leaf list, bit 1 the batch
+// has split rows, bits 8-15 the index of its entries per lane in kPlanK, bits
+// 16 and up the slots its rows use.
+constexpr int kFlagOvf = 1, kFlagSplit = 2, kFlagKShift = 8, kFlagUsedShift = 16;
 static_assert(kMaxChainRows <= 1024, "slot words hold the row in 10 bits");
 
 // Recent entries of row r of batch b (R rows); bbase holds list starts.
@@ -1299,61 +1311,152 @@ __device__ __forceinline__ int recent_count(const BHJob &J, int b, int r, int R)
     const int rend = (r + 1 < R) ? J.roff[i + 1] : (J.bbase[b + 1] - J.bbase[b] - J.bold[b]);
     return rend - J.roff[i];
 }
-__device__ __forceinline__ int run_lanes(int cr) { return min(max(cr, 1), kRunLanes); }
+// Lanes a row with cr recent entries takes at k entries per lane.
+__device__ __forceinline__ int row_lanes(int cr, int k) {
+    const int l = max(1, (cr + k - 1) / k);
+    return l > kRunLanes ? (l + kRunLanes - 1) & ~(kRunLanes - 1) : l;
+}
+// Slot capacity of a batch of R rows (a row alone never needs more than
+// 2 kRunLanes lanes at k = cr).
+__device__ __host__ __forceinline__ int plan_cap(int R) { return min(kChainThreads, 2 * kRunLanes * R + kRunLanes); }
 
-// One workgroup per batch: each row's first slot, runs packed in row order
-// so that none crosses a 16-lane row; pbase[b] = the batch's slot count.
-__global__ __launch_bounds__(1024) void plan_count_kernel(BH_KERNEL_ARGS) {
-    BH_JOB();
-    __shared__ unsigned char lanes[kMaxChainRows];
-    __shared__ int start[kMaxChainRows];
-    const int b = jb.local, r = (int)threadIdx.x;
-    const int R = min(J.BS, J.n - b * J.BS);
-    __shared__ int any_ovf;
-    if (r == 0) any_ovf = 0;
-    __syncthreads();
-    if (r < R) {
-        lanes[r] = (unsigned char)run_lanes(recent_count(J, b, r, R));
-        if (J.late_cnt[b * J.BS + r] > kLateCap) any_ovf = 1;
-    }
-    __syncthreads();
-    if (r == 0) J.povf[b] = any_ovf;
-    if (r == 0) {
-        int pos = 0;
-        for (int q = 0; q < R; ++q) {
-            const int l = lanes[q];
-            if ((pos & (kRunLanes - 1)) + l > kRunLanes) pos = (pos + kRunLanes - 1) & ~(kRunLanes - 1);
-            start[q] = pos;
-            pos += l;
-        }
-        J.pbase[b] = (pos + kRunLanes) & ~(kRunLanes - 1);   // at least one padding slot last
-        if (b == 0) J.pbase[J.nb] = 0;
-    }
-    __syncthreads();
-    if (r < R) J.pstart[b * J.BS + r] = start[r];
+// Entries per lane the planner may choose.
+__constant__ int kPlanK[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128, 192, 256, 384, 512, 1 << 30};
+constexpr int kPlanKs = 23;
+
+// Lanes a row's slots occupy: its lane count rounded up to a power of two
+// when it is one run, as it is when split.
+__device__ __forceinline__ int row_span(int l) {
+    return l > kRunLanes ? l : (l == 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)(l - 1))));
 }
 
-// One thread per row: its run's slot words and the padding up to the next run.
+// Sum over the workgroup (1024 threads) of v, returned to every thread.
+__device__ __forceinline__ int plan_block_sum(int v, int *wsum) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();   // wsum free from the previous sum
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = v;
+    __syncthreads();
+    int s = 0;
+    for (int w = 0; w < kChainThreads / kWave; ++w) s += wsum[w];
+    return s;
+}
+// Number of earlier threads (in thread order) with pred set, and the total.
+__device__ __forceinline__ int plan_block_rank(bool pred, int *wsum, int &total) {
+    const unsigned long long m = __ballot(pred);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int in_wave = __popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    total = 0;
+    for (int q = 0; q < kChainThreads / kWave; ++q) {
+        before += q < w ? wsum[q] : 0;
+        total += wsum[q];
+    }
+    return before + in_wave;
+}
+
+// One workgroup per batch (1024 threads, one row each): the batch's entries
+// per lane k -- the first of kPlanK whose plan fits the batch's slot capacity,
+// found by bisection (a row's span does not grow with k, and the last k, one
+// lane per row, always fits) -- and each row's first slot.  The plan places
+// split rows first, then one-run rows by span (16, 8, 4, 2, 1 lanes), each
+// group in row order, so that every position is a prefix count and no run
+// crosses a 16-lane row.  pbase[b] gets the batch's slot count (a padding
+// slot last unless the slots fill whole passes), pflag[b] its flags, the
+// index of k and the slots its rows use.
+__global__ __launch_bounds__(1024) void plan_count_kernel(BH_KERNEL_ARGS) {
+    BH_JOB();
+    __shared__ int wsum[kChainThreads / kWave];
+    const int b = jb.local, r = (int)threadIdx.x;
+    const int R = min(J.BS, J.n - b * J.BS);
+    const bool row = r < R;
+    const int cr = row ? recent_count(J, b, r, R) : 0;
+    const int ovf = plan_block_sum(row && J.late_cnt[b * J.BS + r] > kLateCap ? 1 : 0, wsum) > 0;
+    const int cap = plan_cap(R);
+    auto total_at = [&](int c) {
+        const int pos = plan_block_sum(row ? row_span(row_lanes(cr, kPlanK[c])) : 0, wsum);
+        return (pos % kChainThreads) == 0 ? pos : (pos + kRunLanes) & ~(kRunLanes - 1);
+    };
+    int lo = 0, hi = kPlanKs - 1;
+    if (total_at(0) <= cap) hi = 0;
+    else lo = 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (total_at(mid) <= cap) hi = mid;
+        else lo = mid + 1;
+    }
+    const int c = lo, k = kPlanK[c];
+    const int l = row ? row_lanes(cr, k) : 0;
+    const int span = row ? row_span(l) : 0;
+    // split rows first: an exclusive scan of their spans (multiples of 16)
+    int start = 0, base = 0, split = 0;
+    {
+        const int v = row && l > kRunLanes ? span : 0;
+        int x = v;
+        const int lane = r & (kWave - 1), w = r / kWave;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        __syncthreads();
+        if (lane == kWave - 1) wsum[w] = x;
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int q = 0; q < kChainThreads / kWave; ++q) {
+            before += q < w ? wsum[q] : 0;
+            tot += wsum[q];
+        }
+        if (v) start = before + x - v;
+        base = tot;
+        split = tot > 0;
+    }
+    for (int s = kRunLanes; s >= 1; s >>= 1) {
+        int cnt = 0;
+        const int rk = plan_block_rank(row && l <= kRunLanes && span == s, wsum, cnt);
+        if (row && l <= kRunLanes && span == s) start = base + rk * s;
+        base += cnt * s;
+    }
+    if (row) J.pstart[b * J.BS + r] = start;
+    if (r == 0) {
+        const int total = (base % kChainThreads) == 0 ? base : (base + kRunLanes) & ~(kRunLanes - 1);
+        J.pbase[b] = total;
+        J.pflag[b] = (ovf ? kFlagOvf : 0) | (split ? kFlagSplit : 0) | (c << kFlagKShift) | (base << kFlagUsedShift);
+        if (b == 0) J.pbase[J.nb] = 0;
+    }
+}
+
+// One thread per row: its slot words (padding to its span), and for the
+// batch's first row the padding after the last row's slots.
 __global__ __launch_bounds__(256) void plan_fill_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     const int i = jb.local * blockDim.x + threadIdx.x;
     if (i >= J.n) return;
     const int b = i / J.BS, r = i - b * J.BS, R = min(J.BS, J.n - b * J.BS);
     const int cr = recent_count(J, b, r, R);
-    const int l = run_lanes(cr);
+    const int flags = J.pflag[b];
+    const int k = kPlanK[(flags >> kFlagKShift) & 255];
+    const int l = row_lanes(cr, k);
+    const bool split = l > kRunLanes;
     const int s0 = J.pstart[i];
-    const int s1 = (r + 1 < R) ? J.pstart[i + 1] : (J.pbase[b + 1] - J.pbase[b]);
     const size_t base = (size_t)J.pbase[b];
     const size_t list = (size_t)J.bbase[b] + J.bold[b] + J.roff[i];
     const unsigned long long rb = (unsigned long long)r << 32;
+    const unsigned long long rowlead = kSlotRow | (J.late_cnt[i] > kLateCap ? kSlotWalk : 0ull) |
+                                       ((unsigned long long)(split ? l / kRunLanes - 1 : 0) << kSlotRunsShift);
     for (int j = 0; j < l; ++j) {
-        unsigned long long w = rb | ((unsigned long long)(l - 1 - j) << 42);
-        if (j < cr) w |= kSlotHas | (J.ent[list + j] & 0xffffffffull);
-        if (j == 0) w |= kSlotLead | (J.late_cnt[i] > kLateCap ? kSlotWalk : 0ull);
-        if (cr > kRunLanes) w |= kSlotMore;
+        const int rem = split ? (kRunLanes - 1) - (j & (kRunLanes - 1)) : l - 1 - j;
+        unsigned long long w = rb | ((unsigned long long)rem << 42);
+        if (k > 1) w |= kSlotMulti | (unsigned long long)j | ((unsigned long long)l << 16);
+        else if (j < cr) w |= kSlotHas | (J.ent[list + j] & 0xffffffffull);
+        if (split ? (j & (kRunLanes - 1)) == 0 : j == 0) w |= kSlotLead;
+        if (j == 0) w |= rowlead;
         J.slots[base + s0 + j] = w;
     }
-    for (int q = s0 + l; q < s1; ++q) J.slots[base + q] = kSlotPad;
+    for (int q = l; q < row_span(l); ++q) J.slots[base + s0 + q] = kSlotPad;
+    if (r == 0)
+        for (int q = flags >> kFlagUsedShift; q < J.pbase[b + 1] - J.pbase[b]; ++q) J.slots[base + q] = kSlotPad;
     // the row's record: position at the iteration's start, and its force apart
     // from recent entries -- early attraction and far field (a row whose leaf
     // list overflowed takes its far field from a full walk when it moves); the
@@ -1369,10 +1472,11 @@ __global__ __launch_bounds__(256) void plan_fill_kernel(BH_KERNEL_ARGS) {
     st<float4>(J.rec, i, float4{p.x, p.y, bs.x, bs.y});
     st<int2>(J.rmeta, i, int2{J.roff[i], J.roff[i] + cr});
     if (r == 0)
-        st<int4>(J.bmeta, b, int4{J.pbase[b], J.pbase[b + 1] - J.pbase[b], J.bbase[b] + J.bold[b], J.povf[b]});
+        st<int4>(J.bmeta, b, int4{J.pbase[b], J.pbase[b + 1] - J.pbase[b], J.bbase[b] + J.bold[b], flags});
 }
 
 struct Chain2Shared {
+    float2 xpart[kChainThreads / kRunLanes];   // run totals of split rows' later runs
     double wsd[16];
     double step;
 };
@@ -1415,13 +1519,13 @@ __device__ __forceinline__ int2 sld2(gptr<const int4> p, int i) {   // the first
                               ((const __attribute__((address_space(4))) B *)p)[2 * __builtin_amdgcn_readfirstlane(i)]);
 }
 
-// Two paths of the chain off its common case: the terms of a long row's
-// recent entries [o0, o1) past its first kRunLanes (every kRunLanes-th from
-// lane position jl, kMoreLoads list words in flight at a time), and the far
-// field of a row whose late-leaf list overflowed, from a full walk over the
-// live positions.  The walk reads its job fields through a pointer that an
-// empty asm statement hands it inside the branch, so that the compiler cannot
-// hoist those reads into the hot loop's scalar registers.
+// Two paths of the chain off its common case: the terms of a lane with
+// several entries (list entries e0, e0 + stride, ... below e1 from base,
+// kMoreLoads list words in flight at a time), and the far field of a row
+// whose late-leaf list overflowed, from a full walk over the live positions.
+// The walk reads its job fields through a pointer that an empty asm statement
+// hands it inside the branch, so that the compiler cannot hoist those reads
+// into the hot loop's scalar registers.
 using JobC = const __attribute__((address_space(4))) BHJob *;
 __device__ __forceinline__ JobC launder(const BHJob *p) {
     JobC q = (JobC)p;
@@ -1430,20 +1534,17 @@ __device__ __forceinline__ JobC launder(const BHJob *p) {
 }
 
 template <bool GM, bool WIN>
-__device__ __forceinline__ float2 long_row_terms(gptr<const unsigned long long> ent, const float2 *win, int wbase,
-                                                 gptr<const float2> pos, size_t lst, int o0, int o1, int jl, float x,
-                                                 float y, float invK, float negRK2, int ka, int kr) {
+__device__ __forceinline__ float2 lane_terms(gptr<const unsigned long long> ent, const float2 *win, int wbase,
+                                             gptr<const float2> pos, size_t base, int e0, int e1, int stride, float x,
+                                             float y, float invK, float negRK2, int ka, int kr) {
     float ax = 0.f, ay = 0.f;
-    for (int e0 = o0 + jl + kRunLanes; e0 < o1; e0 += kMoreLoads * kRunLanes) {
+    for (int e = e0; e < e1; e += kMoreLoads * stride) {
         unsigned long long we[kMoreLoads];
 #pragma unroll
-        for (int u = 0; u < kMoreLoads; ++u) {
-            const int e = e0 + u * kRunLanes;
-            we[u] = e < o1 ? ent[lst + e] : 0ull;
-        }
+        for (int u = 0; u < kMoreLoads; ++u) we[u] = e + u * stride < e1 ? ent[base + e + u * stride] : 0ull;
 #pragma unroll
         for (int u = 0; u < kMoreLoads; ++u) {
-            if (e0 + u * kRunLanes < o1) {
+            if (e + u * stride < e1) {
                 const int j = (int)((unsigned)we[u] & 0x7fffffffu);
                 const float2 pj = WIN ? win[j - wbase] : ld<float2>(pos, j);
                 entry_term<GM>(we[u], pj.x - x, pj.y - y, invK, negRK2, ka, kr, ax, ay);
@@ -1518,9 +1619,10 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
     auto rec_load = [&](int b, unsigned long long w) -> float4 {
         return ld<float4>(p_rec, (size_t)b * BS + (int)((w >> 32) & 1023u));
     };
-    // a long row's recent-entry range (lanes of other rows: none)
+    // the recent-entry range of the row of a lane with several entries
+    // (other lanes: none)
     auto range_load = [&](int b, unsigned long long w) -> int2 {
-        return (w & kSlotMore) ? ld<int2>(p_rmeta, (size_t)b * BS + (int)((w >> 32) & 1023u)) : int2{0, 0};
+        return (w & kSlotMulti) ? ld<int2>(p_rmeta, (size_t)b * BS + (int)((w >> 32) & 1023u)) : int2{0, 0};
     };
 
     if (tid == 0) {
@@ -1565,23 +1667,23 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
     gptr<float2> pend_a = sink_lane;
     float2 pend_p{0.f, 0.f};
 
-    // Terms of one slot, the run's suffix sum, and the row's move by its lead lane.
-    auto do_slot = [&](int b, unsigned long long w, const float4 &rc, const int2 &om, bool stop, bool defer)
-                       __attribute__((always_inline)) {
+    // The terms of this lane's slot and its run's suffix sum (the run's total
+    // at its first lane).
+    auto run_total = [&](unsigned long long w, const float4 &rc, const int2 &om, int lst)
+                         __attribute__((always_inline)) -> float2 {
         const bool pad = (w & kSlotPad) != 0;
-        if (!__any(!pad)) return;   // a wave of padding only
-        const int r = (int)((w >> 32) & 1023u);
-        const int rem = pad ? 0 : (int)((w >> 42) & 15u);
         float ax = 0.f, ay = 0.f;
+        if (!__any(!pad)) return float2{ax, ay};   // a wave of padding only
+        const int rem = pad ? 0 : (int)((w >> 42) & 15u);
         if (!pad) {
             if (w & kSlotHas) {
                 const float2 pj = gather((int)((unsigned)w & 0x7fffffffu));
                 entry_term<GM>(w, pj.x - rc.x, pj.y - rc.y, invK, negRK2, J.ka, J.kr, ax, ay);
             }
-            if (w & kSlotMore) {
-                const float2 t = long_row_terms<GM, WIN>(p_ent, win, wbase, p_pos, (size_t)bm.z, om.x, om.y,
-                                                         (kRunLanes - 1) - rem, rc.x, rc.y, invK, negRK2, J.ka,
-                                                         J.kr);
+            if (w & kSlotMulti) {
+                const float2 t = lane_terms<GM, WIN>(p_ent, win, wbase, p_pos, (size_t)lst + om.x,
+                                                     (int)(w & 0xffffu), om.y - om.x, (int)((w >> 16) & 0xffffu),
+                                                     rc.x, rc.y, invK, negRK2, J.ka, J.kr);
                 ax += t.x;
                 ay += t.y;
             }
@@ -1590,9 +1692,14 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
             ax = run_suffix_sum(ax, rem);
             ay = run_suffix_sum(ay, rem);
         }
-        if (pad || !(w & kSlotLead)) return;
+        return float2{ax, ay};
+    };
+    // The row's move by its first lane, from the total of its recent entries.
+    auto move_row = [&](int b, unsigned long long w, const float4 &rc, float2 f, bool stop)
+                        __attribute__((always_inline)) {
+        const int r = (int)((w >> 32) & 1023u);
         const int i = b * BS + r;
-        float fx = ax + rc.z, fy = ay + rc.w;
+        float fx = f.x + rc.z, fy = f.y + rc.w;
         if (w & kSlotWalk) {
             const float2 t = overflow_far<GM>(launder(Jg), i, rc.x, rc.y);
             fx += t.x;
@@ -1613,21 +1720,17 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
                 // step / |f| with the hardware reciprocal square root (about 1 ulp)
                 const float sc = step * __builtin_amdgcn_rsqf(fx * fx + fy * fy);
                 np = float2{rc.x + sc * fx, rc.y + sc * fy};
-                if (defer) {
-                    pend_i = i;
-                    pend_a = p_pos + i;
-                    pend_p = np;
-                } else {
-                    st<float2>(p_pos, i, np);
-                }
+                pend_i = i;
+                pend_a = p_pos + i;
+                pend_p = np;
             }
         }
         if (WIN) win[i - wbase] = np;
     };
 
-    // step b: wc / rc / oc hold batch b's slot word, record and long-row
-    // range; w2 holds batch b + 2's slot word, and r2 / o2 receive its record
-    // and range; wc receives batch b + 4's slot word.
+    // step b: wc / rc / oc hold batch b's slot word, record and row range; w2
+    // holds batch b + 2's slot word, and r2 / o2 receive its record and range;
+    // wc receives batch b + 4's slot word.
     auto chain_step = [&](int b, unsigned long long &wc, const float4 &rc, const int2 &oc,
                           const unsigned long long &w2, float4 &r2, int2 &o2) __attribute__((always_inline)) {
         const bool stop = (b == J.stop_batch);
@@ -1640,30 +1743,25 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
         st<float2>(pend_a, 0, pend_p);   // the position this lane moved in the previous step, or the sink
         pend_i = -1;
         pend_a = sink_lane;
-        do_slot(b, wc, rc, oc, stop, true);
-        // batches with more slots than lanes: further passes, kPassChunk at a
-        // time with their loads issued together
-        const int pb = bm.x, sc = bm.y;
-        for (int p0 = 1; p0 * kChainThreads < sc; p0 += kPassChunk) {
-            unsigned long long wq[kPassChunk];
-            float4 rq[kPassChunk];
-            int2 oq[kPassChunk];
-#pragma unroll
-            for (int u = 0; u < kPassChunk; ++u)
-                wq[u] = (p0 + u) * kChainThreads < sc
-                            ? p_slots[(size_t)pb + min((p0 + u) * kChainThreads + tid, sc - 1)]
-                            : kSlotPad;
-#pragma unroll
-            for (int u = 0; u < kPassChunk; ++u) {
-                rq[u] = rec_load(b, wq[u]);
-                oq[u] = range_load(b, wq[u]);
+        float2 f = run_total(wc, rc, oc, bm.z);
+        const bool lead = !(wc & kSlotPad) && (wc & kSlotLead);
+        const bool first = lead && (wc & kSlotRow);
+        if (bm.w & kFlagSplit) {
+            // split rows: the later runs' totals through LDS, added in run order
+            if (lead && !first) S.xpart[tid / kRunLanes] = f;
+            lds_barrier();
+            if (first) {
+                const int runs = (int)((wc >> kSlotRunsShift) & 63u);
+                for (int q = 1; q <= runs; ++q) {
+                    const float2 t = S.xpart[tid / kRunLanes + q];
+                    f.x += t.x;
+                    f.y += t.y;
+                }
             }
-#pragma unroll
-            for (int u = 0; u < kPassChunk; ++u)
-                if ((p0 + u) * kChainThreads < sc) do_slot(b, wq[u], rq[u], oq[u], stop, false);
         }
+        if (first) move_row(b, wc, rc, f, stop);
         wc = slot_load(q4.x, q4.y);
-        if (b + 1 <= last && bmn.w) {
+        if (b + 1 <= last && (bmn.w & kFlagOvf)) {
             // a row of the next batch walks the tree over positions in memory
             if (pend_i >= 0) st<float2>(p_pos, pend_i, pend_p);
             pend_i = -1;
@@ -1899,7 +1997,7 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->pstart = (decltype(J->pstart))(h.pstart);
     J->pbase = (decltype(J->pbase))(h.pbase);
     J->slots = (decltype(J->slots))(h.slots);
-    J->povf = (decltype(J->povf))(h.povf);
+    J->pflag = (decltype(J->pflag))(h.pflag);
     J->sink = (decltype(J->sink))(h.sink);
     J->bmeta = (decltype(J->bmeta))(h.bmeta);
     J->energy = (decltype(J->energy))(g->energy);
@@ -2090,7 +2188,7 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
            8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1) +
-           4 * N + 4 * (nb + 1) + 8 * (2 * kRunLanes * N + 2 * kRunLanes * nb) + 4 * nb + 16 * N +
+           4 * N + 4 * (nb + 1) + 8 * nb * (size_t)plan_cap(BS) + 4 * nb + 16 * N +
            8 * (size_t)kChainThreads + 16 * nb;
 }
 
@@ -2136,8 +2234,8 @@ int bh_alloc(bl_graph *g) {
     // 16-lane rows take fewer than twice their lanes, plus the last row's padding
     BL_TRY(graph_alloc(g, (void **)&h.pstart, 4 * N));
     BL_TRY(graph_alloc(g, (void **)&h.pbase, 4 * ((size_t)g->nb + 1)));
-    BL_TRY(graph_alloc(g, (void **)&h.slots, 8 * (2 * kRunLanes * N + 2 * (size_t)kRunLanes * g->nb)));
-    BL_TRY(graph_alloc(g, (void **)&h.povf, 4 * (size_t)g->nb));
+    BL_TRY(graph_alloc(g, (void **)&h.slots, 8 * (size_t)g->nb * plan_cap(g->p.batch_size)));
+    BL_TRY(graph_alloc(g, (void **)&h.pflag, 4 * (size_t)g->nb));
     BL_TRY(graph_alloc(g, (void **)&h.sink, 8 * (size_t)kChainThreads));
     BL_TRY(graph_alloc(g, (void **)&h.bmeta, 16 * (size_t)g->nb));
     BL_TRY(graph_alloc(g, (void **)&h.kiter, 16));

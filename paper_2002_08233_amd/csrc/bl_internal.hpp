@@ -100,9 +100,9 @@ struct BHBuffers {
     int *pstart;            // [n] first slot of each row's run within its batch's slot plan
     int *pbase;             // [nb + 1] slot counts, then first slots of the batches' plans
     unsigned long long *slots;  // the batches' slot plans (one word per lane of the chain)
-    int *povf;              // [nb] a row of the batch overflowed its leaf list
+    int *pflag;             // [nb] batch flags of the chain's slot plan
     float2 *sink;           // [1024] chain stores of lanes without a moved position
-    int4 *bmeta;            // [nb] per batch: first slot, slot count, recent-list start, overflow flag
+    int4 *bmeta;            // [nb] per batch: first slot, slot count, recent-list start, flags
     int *kiter;             // [2] current iteration, first iteration of the run
     int host_kiter[2];      // host staging for kiter
     bool prefix_ready;      // late_att/heavy computed for this job
