@@ -295,7 +295,7 @@ def bench_single(args, api, config, steps=None, warmup=None, precision=None, ext
         _, st = dev.run(psteps)
         out["profiled_steps"] = psteps
         kern = {}
-        for name in ("tree_build", "far_kernel", "old_sum_kernel", "chain2_kernel", "rows_kernel", "step_kernel",
+        for name in ("tree_build", "far_kernel", "chain_kernel", "rows_kernel", "step_kernel",
                      "steps_kernel", "finalize_kernel", "exact_graph_kernel"):
             ms, cnt = dev.profile_read(name)
             if cnt:
@@ -307,8 +307,7 @@ def bench_single(args, api, config, steps=None, warmup=None, precision=None, ext
             tests = dev.profile_read("cell_tests")[1]
             rows = float(g.n) * psteps   # every row once per iteration in each kernel below
             work = {"far_kernel": BYTES_PER_VISIT * visits + BYTES_PER_WALK_VERTEX * rows,
-                    "chain2_kernel": BYTES_PER_UPDATE * rows + BYTES_PER_ENTRY * recent_e,
-                    "old_sum_kernel": BYTES_PER_ENTRY * old_e}
+                    "chain_kernel": BYTES_PER_UPDATE * rows + BYTES_PER_ENTRY * (recent_e + old_e)}
             for k, total in work.items():
                 if k in kern:
                     kern[k]["bytes_per_launch"] = total / kern[k]["launches"]
@@ -325,7 +324,7 @@ def bench_single(args, api, config, steps=None, warmup=None, precision=None, ext
                          "late_entries_per_vertex": late / rows,
                          "old_entries_per_vertex": old_e / rows, "recent_entries_per_vertex": recent_e / rows,
                          "late_overflow": st["late_overflow"],
-                         "chain_us_per_batch": 1e3 * kern["chain2_kernel"]["total_ms"] / (nb * psteps)}
+                         "chain_us_per_batch": 1e3 * kern["chain_kernel"]["total_ms"] / (nb * psteps)}
             # the whole Barnes-Hut iteration on the same units: walks, every CSR
             # entry's attraction, moved leaves, updates and the tree build
             path_bytes = (BYTES_PER_VISIT * visits / psteps + BYTES_PER_ENTRY * (g.nnz + late / psteps)

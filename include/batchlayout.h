@@ -320,12 +320,13 @@ int bl_graph_profile(bl_graph *h, int32_t enable);
 /* Totals since the last bl_graph_profile(h, 1) for one kernel: "rows_kernel",
  * "step_kernel", "finalize_kernel", "exact_graph_kernel", "steps_kernel" (exact mode),
  * "tree_build" (the whole quadtree build sequence, one entry per iteration),
- * "far_kernel", "old_sum_kernel", "chain2_kernel" (Barnes-Hut, one entry per
- * launch).  Counts instead of times, returned in *launches: "late_entries"
- * (moved-leaf entries the far-field walks listed), "old_entries" and
- * "recent_entries" (moved-neighbour and moved-leaf entries summed by the
- * segment kernel and by the chain), "cell_tests" (cells the far-field walks
- * tested with the acceptance criterion). */
+ * "far_kernel", "chain_kernel" (Barnes-Hut, one entry per launch; the chain
+ * launch holds the chain and its helper workgroups).  Counts instead of times,
+ * returned in *launches: "late_entries" (moved-leaf entries the far-field
+ * walks listed), "old_entries" and "recent_entries" (moved-neighbour and
+ * moved-leaf entries summed by the chain's helpers and by the chain itself),
+ * "cell_tests" (cells the far-field walks tested with the acceptance
+ * criterion). */
 int bl_graph_profile_read(bl_graph *h, const char *kernel, double *total_ms, int64_t *launches);
 
 /* -------------------------------------------------- many graphs at once

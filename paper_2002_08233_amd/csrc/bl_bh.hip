@@ -27,12 +27,12 @@
 //  10. slot plan       the recent entries laid out one per lane, each row's
 //                      run inside one 16-lane DPP row; one record per row
 //                      (start position, force apart from recent entries)
-//  11. per segment     old_sum_kernel (full chip) adds the segment's old
-//                      entries into the row records; chain2_kernel (one
-//                      workgroup per job) then walks the segment's batches in
-//                      order: the recent entries with live coordinates from an
-//                      LDS window of the segment's moved vertices, then the
-//                      batch update (Alg. 2 update loop)
+//  11. chain_kernel    one launch: per job, one workgroup walks the batches
+//                      in order -- the recent entries (the last `lag`
+//                      batches) with live coordinates from an LDS ring, then
+//                      the batch update (Alg. 2 update loop) -- while helper
+//                      workgroups sum the older entries of later batches as
+//                      soon as the batches they refer to have moved
 #include <algorithm>
 #include <cfloat>
 #include <cstring>
@@ -56,20 +56,25 @@ constexpr int kLateHeavyRow = 256;    // moved neighbours above which a whole wo
 constexpr int kMaxChainRows = 1024;   // batch-size limit of the Barnes-Hut chain
 constexpr int kEnt = 3;               // late entries per thread per pass (held in registers)
 constexpr int kMinRun = 1;            // entries per thread at least (packs a step's entries into fewer waves)
-// An iteration's chain runs in up to kMaxSegments launches (one per
-// kSegBatches batches).  Before the launch of a segment, a full-chip kernel
-// sums, for every row of the segment, the late entries that refer to
-// vertices of earlier segments ("old": all moved, and final, by then); the
-// chain itself gathers only the entries that refer to its own segment.
-constexpr int kMaxSegments = 16;
-constexpr int kSegBatches = 32;
-constexpr int kMinSegChain = 192;
-constexpr int kEntH = 8;              // old entries per thread per pass in the segment kernel
-constexpr int kOldSplit = 16;         // most workgroups per batch in the segment kernel
-// The chain keeps the positions its segment has moved in an LDS window (the
-// recent entries refer to those vertices only); a segment spans at most
-// kWindow vertices.
-constexpr int kWindow = 10240;
+// An iteration's chain runs in one launch.  A row's late entries that refer
+// to batches more than `lag` batches before its own ("old") are summed by
+// helper workgroups of the same launch as soon as the chain has moved those
+// batches; the chain gathers only the entries that refer to the last `lag`
+// batches ("recent"), from an LDS ring holding the last lag + 1 batches'
+// positions (kRing vertices at most).
+constexpr int kLag = 14;
+constexpr int kRelease = 4;           // the chain copies out and publishes its progress every kRelease steps
+constexpr int kMinLag = kRelease + 5; // progress goes out every kRelease steps; old sums are waited for 2 steps ahead
+constexpr int kRing = 16384;
+constexpr int kHelpers = 32;          // helper workgroups per job, at most
+constexpr int kEntH = 8;              // old entries per thread per pass in the helpers
+// A batch's old list is cut into parts of whole rows, one helper item each: a
+// row belongs to the part whose window of kPartEnt entries holds its first
+// entry (so a part holds fewer than kPartEnt entries plus one row).
+constexpr int kPartEnt = 4096;
+// Per-job progress words of the chain launch: batches moved, helper batches
+// claimed, then one ready flag per batch.
+constexpr int kSyncMoved = 0, kSyncTicket = 1, kSyncReady = 2;
 static_assert(kMaxChainRows <= 1024, "batch_offsets_kernel takes one row per thread");
 
 // Device descriptor of one job (all pointers are device memory).
@@ -81,8 +86,9 @@ struct BHJob {
     int snapshot_leaves;        // leaves use the snapshot (no late lists)
     int all_live;               // one-shot force call: every leaf and neighbour is live
     int first_batch, last_batch, stop_batch;
-    int nseg;                   // chain segments per iteration (1: no old part)
-    int nsplit;                 // segment-kernel workgroups per batch (<= kOldSplit)
+    int lag;                    // batches whose positions the chain gathers itself (its LDS ring)
+    int helpers;                // helper workgroups of the chain launch, at most (set with the job set)
+    long long spin_limit;       // polls before a wait of the chain launch gives up
     double step0, decay;
     gptr<int> kiter;            // [2]: current iteration, first iteration of the run
     gptr<const int> rowptr, colidx;
@@ -104,15 +110,17 @@ struct BHJob {
     gptr<int> roff, roff_old, bbase, bold;
     gptr<float4> rec;           // per vertex, for the chain: x, y and the force apart from recent entries
     gptr<int2> rmeta;           // per vertex: its recent entries' range [x, y) in its batch's recent list
-    gptr<int> osplit;           // per batch: kOldSplit + 1 row bounds splitting its old part
+    gptr<float2> oldf;          // per vertex: the sum of its old entries (helpers -> chain)
+    gptr<int> sync;             // [kSyncReady + nb] progress words of the chain launch
+    gptr<int> hbase;            // [nb + 1] helper parts per batch, then (scanned) the first part's item
+    gptr<int2> hitem;           // helper items: (batch, part)
     gptr<unsigned long long> ent;
     size_t ent_cap;
     gptr<int> pstart;           // per vertex: first slot of its row's run within its batch's slots
     gptr<int> pbase;            // [nb + 1] slot count of each batch, then (scanned) its first slot
-    gptr<unsigned long long> slots;   // the batches' slot plans (chain2_kernel)
+    gptr<unsigned long long> slots;   // the batches' slot plans (chain_kernel)
     gptr<int> pflag;            // [nb] batch flags of the slot plan (kFlag*)
     gptr<int4> bmeta;           // [nb] first slot, slot count, recent-list start, batch flags
-    gptr<float2> sink;          // [kChainThreads] chain stores of lanes without a moved position
     gptr<double> energy;        // one value per iteration of the run
     gptr<double> fout;
     Counters *ctr;
@@ -365,30 +373,38 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(BH_KERNEL_A
 
 // Exclusive scan in place by one workgroup per job.  which: 0 radix
 // histogram (256 * tiles), 1 cell-count tile sums (sblocks), 2 batch list
-// sizes (nb + 1), 3 batch slot counts (nb + 1).
+// sizes (nb + 1), 3 batch slot counts and helper part counts (nb + 1 each).
 __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(BH_KERNEL_ARGS, int which) {
     BH_JOB();
     __shared__ int ws[16];
-    gptr<int> data = which == 0 ? J.hist : (which == 1 ? J.scan_part : (which == 2 ? J.bbase : J.pbase));
-    const int len = which == 0 ? 256 * J.tiles : (which == 1 ? J.sblocks : J.nb + 1);
-    int running = 0;
-    for (int b0 = 0; b0 < len; b0 += kScanTile) {
-        int v[kScanItems];
-        int s = 0;
-        const int p0 = b0 + threadIdx.x * kScanItems;
+    auto scan = [&](gptr<int> data, int len) {
+        int running = 0;
+        for (int b0 = 0; b0 < len; b0 += kScanTile) {
+            int v[kScanItems];
+            int s = 0;
+            const int p0 = b0 + threadIdx.x * kScanItems;
 #pragma unroll
-        for (int q = 0; q < kScanItems; ++q) {
-            v[q] = (p0 + q < len) ? data[p0 + q] : 0;
-            s += v[q];
-        }
-        int total;
-        int pre_ = block_excl_scan(s, ws, &total) + running;
+            for (int q = 0; q < kScanItems; ++q) {
+                v[q] = (p0 + q < len) ? data[p0 + q] : 0;
+                s += v[q];
+            }
+            int total;
+            int pre_ = block_excl_scan(s, ws, &total) + running;
 #pragma unroll
-        for (int q = 0; q < kScanItems; ++q) {
-            if (p0 + q < len) data[p0 + q] = pre_;
-            pre_ += v[q];
+            for (int q = 0; q < kScanItems; ++q) {
+                if (p0 + q < len) data[p0 + q] = pre_;
+                pre_ += v[q];
+            }
+            running += total;
         }
-        running += total;
+    };
+    if (which == 0) scan(J.hist, 256 * J.tiles);
+    else if (which == 1) scan(J.scan_part, J.sblocks);
+    else if (which == 2) scan(J.bbase, J.nb + 1);
+    else {
+        scan(J.pbase, J.nb + 1);
+        __syncthreads();
+        scan(J.hbase, J.nb + 1);
     }
 }
 
@@ -788,13 +804,15 @@ __global__ __launch_bounds__(256) void far_kernel(BH_KERNEL_ARGS) {
 // so their attraction terms (Sec. 2.2, a = 2: d * delta / K) can be summed
 // for all vertices at once from the snapshot.  Sorted CSR rows make the moved
 // ("late") neighbours a prefix of each row; its length is fixed per job.
-// Batches per chain segment, and the first vertex of batch b's segment:
-// entries of batch b that refer to vertices below it are "old".
-__device__ __forceinline__ int seg_len(const BHJob &J) { return (J.nb + J.nseg - 1) / J.nseg; }
+// The first vertex of batch b - lag: entries of batch b that refer to vertices
+// below it are "old" (none in one-shot force calls, where nothing moves).
 __device__ __forceinline__ int old_limit(const BHJob &J, int b) {
-    if (J.nseg <= 1) return 0;
-    const int L = seg_len(J);
-    return (b / L) * L * J.BS;
+    return J.all_live ? 0 : max(0, b - J.lag) * J.BS;
+}
+// Where the chain's LDS ring keeps vertex j's position.
+__device__ __forceinline__ unsigned ring_index(const BHJob &J, int j) {
+    const int bj = j / J.BS;
+    return (unsigned)((bj % (J.lag + 1)) * J.BS + (j - bj * J.BS));
 }
 
 __global__ void heavy_reset_kernel(BH_KERNEL_ARGS) {
@@ -910,9 +928,7 @@ __device__ __forceinline__ int late_leaf_count(int lc) { return lc > kLateCap ? 
 // Per batch: the list holds first the old entries of all its rows, then the
 // others, each part row by row.  Counts of each row -> exclusive offsets
 // within each part; bold[b] = old part length, bbase[b] = list length (a scan
-// turns bbase into list starts).  The old part is also cut into J.nsplit
-// row ranges of about equal entry counts: bound k is the first row that
-// starts at or after entry floor(k * bold / J.nsplit).
+// turns bbase into list starts).
 __global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     __shared__ int ws[16];
@@ -937,20 +953,6 @@ __global__ __launch_bounds__(1024) void batch_offsets_kernel(BH_KERNEL_ARGS) {
     if (r < R) {
         J.roff_old[b * BS + r] = off_o;
         J.roff[b * BS + r] = off_r;
-    }
-    if (J.nseg > 1) {
-        gptr<int> sp = J.osplit + (size_t)b * (kOldSplit + 1);
-        const int S = J.nsplit;
-        for (int k = 1; k < S; ++k) {
-            const int t = (int)(((long long)k * tot_o) / S);
-            // the row whose entries (off_o, off_o + co] hold t ends range k - 1
-            if (r < R && co > 0 && off_o < t && t <= off_o + co) sp[k] = r + 1;
-            if (r == 0 && t == 0) sp[k] = 0;
-        }
-        if (r == 0) {
-            sp[0] = 0;
-            sp[S] = R;
-        }
     }
     if (r == 0) {
         atomicAdd(&J.ctr->old_total, (unsigned long long)tot_o);
@@ -977,7 +979,10 @@ __global__ __launch_bounds__(256) void late_fill_kernel(BH_KERNEL_ARGS) {
     const bool heavy = !J.all_live && la > kLateHeavyRow;   // copied by late_fill_heavy_kernel
     if (in && !heavy) {
         for (int k = sub; k < oa; k += 8) ent[bo + k] = rbits | (unsigned)J.colidx[rs + k];
-        for (int k = oa + sub; k < la; k += 8) ent[br + (k - oa)] = rbits | (unsigned)J.colidx[rs + k];
+        for (int k = oa + sub; k < la; k += 8) {
+            const int c = J.colidx[rs + k];
+            ent[br + (k - oa)] = rbits | (J.all_live ? (unsigned)c : ring_index(J, c));
+        }
     }
     // leaves: stable split by the ballot of this row's eight lanes
     const int ll = in ? late_leaf_count(J.late_cnt[ii]) : 0;
@@ -998,9 +1003,8 @@ __global__ __launch_bounds__(256) void late_fill_kernel(BH_KERNEL_ARGS) {
         const unsigned below = (1u << sub) - 1u;
         const int ro = __popc(mo & below), rr = __popc(mh & ~mo & below);
         if (have) {
-            const unsigned long long wd = rbits | 0x80000000u | (unsigned)v;
-            if (isold) ent[bo + oa + no + ro] = wd;
-            else ent[br + (la - oa) + nr + rr] = wd;
+            if (isold) ent[bo + oa + no + ro] = rbits | 0x80000000u | (unsigned)v;
+            else ent[br + (la - oa) + nr + rr] = rbits | 0x80000000u | (J.all_live ? (unsigned)v : ring_index(J, v));
         }
         no += __popc(mo);
         nr += __popc(mh & ~mo);
@@ -1020,8 +1024,10 @@ __global__ __launch_bounds__(256) void late_fill_heavy_kernel(BH_KERNEL_ARGS) {
         const size_t br = (size_t)J.bbase[b] + J.bold[b] + J.roff[i];
         const int rs = J.rowptr[i], la = J.late_att[i], oa = J.old_att[i];
 #pragma unroll 4
-        for (int k = threadIdx.x; k < la; k += 256)
-            J.ent[k < oa ? bo + k : br + (k - oa)] = rbits | (unsigned)J.colidx[rs + k];
+        for (int k = threadIdx.x; k < la; k += 256) {
+            const int c = J.colidx[rs + k];
+            J.ent[k < oa ? bo + k : br + (k - oa)] = rbits | (k < oa ? (unsigned)c : ring_index(J, c));
+        }
     }
 }
 
@@ -1068,14 +1074,14 @@ __device__ __forceinline__ void entry_term(unsigned long long w, float dx, float
 }
 
 template <int KE, typename P, bool GM>
-__device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, P pos, int e0, int e1,
+__device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, P pos, int e0, int e1, int rbase,
                                         unsigned long long (&w)[KE], float (&xj)[KE], float (&yj)[KE],
                                         const int *off, const float *px, const float *py, float2 *sum,
                                         float2 &first, float2 *cl, float invK, float negRK2, int ka, int kr) {
     first = float2{0.f, 0.f};
     if (e0 >= e1) return;
     const int tid = threadIdx.x;
-    int r = (int)(w[0] >> 32);
+    int r = (int)(w[0] >> 32) - rbase;
     float ax = 0.f, ay = 0.f;
     bool firstseg = true;
     for (int base = e0; base < e1; base += KE) {
@@ -1096,7 +1102,7 @@ __device__ __forceinline__ void run_sum(gptr<const unsigned long long> src, P po
 #pragma unroll
         for (int q = 0; q < KE; ++q) {
             if (q < m) {
-                const int rq = (int)(w[q] >> 32);
+                const int rq = (int)(w[q] >> 32) - rbase;
                 if (rq != r) {
                     const bool full = off[r] >= e0 && off[r + 1] <= e1;
                     if (full) sum[r] = float2{ax, ay};
@@ -1197,78 +1203,6 @@ __device__ __forceinline__ float2 row_total(int r, int o0, int o1, int chunk, co
         }
     }
     return sm;
-}
-
-// Old entries of chain segment `seg`, J.nsplit workgroups of 256 per batch,
-// each taking one row range of the batch's old part: every vertex they refer
-// to lies in an earlier segment, so it has moved in this iteration and its
-// position is final.  The range's entries are split into equal runs, summed
-// per row with live positions, the runs' partial rows combined by the carry
-// scan; each row's total is added to the row's base force in its record.
-template <bool GM>
-__global__ __launch_bounds__(256) void old_sum_kernel(BH_KERNEL_ARGS, int seg) {
-    BH_JOB();
-    if (J.general != (int)GM) return;
-    __shared__ int off[kMaxChainRows + 1];
-    __shared__ float px[kMaxChainRows], py[kMaxChainRows];
-    __shared__ float2 sum[kMaxChainRows];
-    __shared__ float2 cl[256], loc[256];
-    __shared__ int keys[256];
-    __shared__ float2 wv[256 / kWave];
-    __shared__ int wk[256 / kWave], wkf[256 / kWave];
-    if (J.nseg <= 1) return;
-    const int b = seg * seg_len(J) + jb.local / J.nsplit, part = jb.local % J.nsplit;
-    if (b >= J.nb) return;
-    const int tid = threadIdx.x, BS = J.BS;
-    const int R = min(BS, J.n - b * BS);
-    gptr<const int> sp = J.osplit + (size_t)b * (kOldSplit + 1);
-    const int rlo = sp[part], rhi = sp[part + 1];
-    if (rlo >= rhi) return;
-    gptr<const int> ro = J.roff_old + (size_t)b * BS;
-    const int Eo = J.bold[b];
-    const int E0 = ro[rlo], E1 = rhi < R ? ro[rhi] : Eo;
-    const size_t base = (size_t)J.bbase[b];
-    const int chunk = max(1, (E1 - E0 + 255) / 256);
-    const int e0 = min(E0 + tid * chunk, E1), e1 = min(e0 + chunk, E1);
-    unsigned long long w[kEntH];
-    float xj[kEntH], yj[kEntH];
-    const int m0 = min(kEntH, e1 - e0);
-#pragma unroll
-    for (int q = 0; q < kEntH; ++q) {
-        w[q] = 0;
-        xj[q] = 0.f;
-        yj[q] = 0.f;
-        if (q < m0) w[q] = J.ent[base + e0 + q];
-    }
-    for (int r = rlo + tid; r < rhi; r += 256) {
-        off[r] = ro[r];
-        const float2 p = ld<float2>(J.pos, b * BS + r);
-        px[r] = p.x;
-        py[r] = p.y;
-    }
-    if (tid == 0) off[rhi] = E1;
-#pragma unroll
-    for (int q = 0; q < kEntH; ++q) {
-        if (q < m0) {
-            const float2 pj = ld<float2>(J.pos, (int)((unsigned)w[q] & 0x7fffffffu));
-            xj[q] = pj.x;
-            yj[q] = pj.y;
-        }
-    }
-    __syncthreads();
-    const int key0 = e0 < e1 ? (int)(w[0] >> 32) : -1 - tid;
-    float2 firstp;
-    run_sum<kEntH, PosG, GM>(J.ent + base, PosG{J.pos}, e0, e1, w, xj, yj, off, px, py, sum, firstp, cl, J.invK,
-                             J.negRK2, J.ka, J.kr);
-    carry_scan_wave(firstp, key0, loc, keys, wv, wk, wkf);
-    __syncthreads();
-    for (int r = rlo + tid; r < rhi; r += 256) {
-        const float2 t = row_total(r, off[r] - E0, off[r + 1] - E0, chunk, sum, cl, loc, keys, wv, wk, wkf);
-        float4 rc = ld<float4>(J.rec, b * BS + r);
-        rc.z += t.x;
-        rc.w += t.y;
-        st<float4>(J.rec, b * BS + r, rc);
-    }
 }
 
 // ------------------------------------------------ chain over a slot plan
@@ -1419,6 +1353,20 @@ __global__ __launch_bounds__(1024) void plan_count_kernel(BH_KERNEL_ARGS) {
         base += cnt * s;
     }
     if (row) J.pstart[b * J.BS + r] = start;
+    // the chain launch's progress words for this iteration, and the batch's
+    // helper parts (batches above lag in the launch's range; the ready word
+    // counts the parts done up from 1 - parts, ready at 1)
+    if (r == 0) {
+        const bool helped = !J.all_live && b >= max(J.first_batch, J.lag + 1) && b <= J.last_batch;
+        const int parts = helped ? max(1, (J.bold[b] + kPartEnt - 1) / kPartEnt) : 0;
+        J.hbase[b] = parts;
+        J.sync[kSyncReady + b] = 1 - parts;
+        if (b == 0) {
+            J.sync[kSyncMoved] = J.first_batch;
+            J.sync[kSyncTicket] = 0;
+            J.hbase[J.nb] = 0;
+        }
+    }
     if (r == 0) {
         const int total = (base % kChainThreads) == 0 ? base : (base + kRunLanes) & ~(kRunLanes - 1);
         J.pbase[b] = total;
@@ -1471,14 +1419,30 @@ __global__ __launch_bounds__(256) void plan_fill_kernel(BH_KERNEL_ARGS) {
     }
     st<float4>(J.rec, i, float4{p.x, p.y, bs.x, bs.y});
     st<int2>(J.rmeta, i, int2{J.roff[i], J.roff[i] + cr});
-    if (r == 0)
+    if (r == 0) {
         st<int4>(J.bmeta, b, int4{J.pbase[b], J.pbase[b + 1] - J.pbase[b], J.bbase[b] + J.bold[b], flags});
+        for (int q = J.hbase[b]; q < J.hbase[b + 1]; ++q) st<int2>(J.hitem, q, int2{b, q - J.hbase[b]});
+    }
 }
 
-struct Chain2Shared {
+struct ChainShared {
     float2 xpart[kChainThreads / kRunLanes];   // run totals of split rows' later runs
     double wsd[16];
     double step;
+    int go;                                    // 0: a bounded wait ran out, leave
+};
+
+// The helpers' workspace: one batch's old entries summed by runs of equal
+// length, the runs' cut rows combined by a carry scan.
+struct HelperShared {
+    int off[kMaxChainRows + 1];
+    float px[kMaxChainRows], py[kMaxChainRows];
+    float2 sum[kMaxChainRows];
+    float2 cl[kChainThreads], loc[kChainThreads];
+    int keys[kChainThreads];
+    float2 wv[kChainThreads / kWave];
+    int wk[kChainThreads / kWave], wkf[kChainThreads / kWave];
+    int item, go;
 };
 
 // Barrier for LDS traffic only: every wave's LDS stores are complete and
@@ -1508,7 +1472,7 @@ __device__ __forceinline__ float run_suffix_sum(float v, int rem) {
 
 // Uniform loads through the scalar unit (the address is the same for every
 // lane): the chain's per-batch records (first slot, slot count, recent-list
-// start, overflow flag).
+// start, flags).
 __device__ __forceinline__ int4 sld4(gptr<const int4> p, int i) {
     using B = RawBits<16>::type;
     return __builtin_bit_cast(int4, ((const __attribute__((address_space(4))) B *)p)[__builtin_amdgcn_readfirstlane(i)]);
@@ -1517,6 +1481,42 @@ __device__ __forceinline__ int2 sld2(gptr<const int4> p, int i) {   // the first
     using B = RawBits<8>::type;
     return __builtin_bit_cast(int2,
                               ((const __attribute__((address_space(4))) B *)p)[2 * __builtin_amdgcn_readfirstlane(i)]);
+}
+
+// Values that workgroups of one launch exchange across the chip: positions
+// the chain moves, the helpers' old sums, the progress counters.  A writer
+// stores plainly, waits for its stores, and raises a counter with an
+// agent-scope release (which writes its die's L2 back); a reader polls the
+// counter and reads the values with agent-scope loads, which bypass its own
+// die's L2.
+__device__ __forceinline__ float2 ld_coh(gptr<const float2> p, size_t i) {
+    const unsigned long long v =
+        __hip_atomic_load((gptr<unsigned long long>)(p + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, v);
+}
+__device__ __forceinline__ int ld_flag(gptr<int> p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+struct PosC {
+    gptr<const float2> p;
+    __device__ __forceinline__ float2 operator()(int j) const { return ld_coh(p, j); }
+};
+
+// Thread 0: wait until *flag >= need.  Returns 0 when the launch is being
+// abandoned (this wait or another one ran out of polls).
+__device__ __forceinline__ int bh_wait(gptr<int> flag, int need, gptr<unsigned long long> abort, long long limit) {
+    for (long long it = 0;; ++it) {
+        if (ld_flag(flag) >= need) return 1;
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0;
+        if (it >= limit) {
+            __hip_atomic_store(abort, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // (complete here: a store left in flight would cost the chain's
+            // loads their completion count)
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // Two paths of the chain off its common case: the terms of a lane with
@@ -1534,7 +1534,7 @@ __device__ __forceinline__ JobC launder(const BHJob *p) {
 }
 
 template <bool GM, bool WIN>
-__device__ __forceinline__ float2 lane_terms(gptr<const unsigned long long> ent, const float2 *win, int wbase,
+__device__ __forceinline__ float2 lane_terms(gptr<const unsigned long long> ent, const float2 *win,
                                              gptr<const float2> pos, size_t base, int e0, int e1, int stride, float x,
                                              float y, float invK, float negRK2, int ka, int kr) {
     float ax = 0.f, ay = 0.f;
@@ -1546,7 +1546,7 @@ __device__ __forceinline__ float2 lane_terms(gptr<const unsigned long long> ent,
         for (int u = 0; u < kMoreLoads; ++u) {
             if (e + u * stride < e1) {
                 const int j = (int)((unsigned)we[u] & 0x7fffffffu);
-                const float2 pj = WIN ? win[j - wbase] : ld<float2>(pos, j);
+                const float2 pj = WIN ? win[j] : ld<float2>(pos, j);
                 entry_term<GM>(we[u], pj.x - x, pj.y - y, invK, negRK2, ka, kr, ax, ay);
             }
         }
@@ -1573,44 +1573,125 @@ __device__ __forceinline__ float2 overflow_far(JobC Jp, int i, float x, float y)
     return float2{wa.negRK2 * (fr.x - fr.z), wa.negRK2 * (fr.y - fr.w)};
 }
 
-// Wait until at most three vector memory operations of this wave are
-// outstanding (s_waitcnt vmcnt(3); the LDS/scalar and export counters are
-// left alone).
-__device__ __forceinline__ void wait_vm3() { __builtin_amdgcn_s_waitcnt(0x0F73); }
 
-// The minibatch chain over the slot plan: one workgroup per job walks its
-// batches in order, one step per batch.  A lane's slot word is loaded four
-// steps before its batch comes up and its row's record two steps before (the
-// record's address is the slot word's row); batch metadata comes through the
-// scalar unit a step ahead.  Every step issues three vector memory operations
-// in a fixed order -- the record two batches ahead, the store of the position
-// moved in the previous step (lanes without one store to a per-job sink), the
-// slot word four batches ahead -- and only steps with long rows, overflowed
-// rows or more slots than lanes add others in between.  Waiting at the start
-// of a step until at most three are outstanding therefore completes every
-// operation of the steps before the previous one and leaves the previous
-// step's loads in flight.  A barrier on LDS traffic alone ends the step.  The
-// rows' terms use the positions their batch sees: moved ones from the LDS
-// window of the segment (WIN; Jacobi within the batch, Gauss-Seidel across
-// batches) or from memory (one-shot force calls, where nothing moves).
+// A helper workgroup: items (batch b, part p) of the chain, claimed in order.
+// Once the chain has moved the batches below b - lag, the helper sums the old
+// entries of the part's rows with their final positions -- the part's list
+// split into equal runs, summed per row, the runs' cut rows combined by the
+// carry scan -- stores the sums in oldf and counts the part done in the
+// batch's ready word.
+template <bool GM>
+__device__ __forceinline__ void chain_helper(const BHJob &J, HelperShared &H) {
+    const int tid = threadIdx.x, BS = J.BS;
+    const int items = J.hbase[J.nb];
+    for (;;) {
+        if (tid == 0) H.item = __hip_atomic_fetch_add(J.sync + kSyncTicket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        // (scalar copies: the loop's barriers stay in uniform control flow)
+        const int t = __builtin_amdgcn_readfirstlane(H.item);
+        if (t >= items) return;
+        const int2 it = ld<int2>(J.hitem, t);
+        const int b = __builtin_amdgcn_readfirstlane(it.x), part = __builtin_amdgcn_readfirstlane(it.y);
+        // What does not depend on moves is loaded before the wait: the part's
+        // rows and list words, and the batch's own positions (its rows move
+        // only at step b).
+        const int R = min(BS, J.n - b * BS);
+        gptr<const int> ro = J.roff_old + (size_t)b * BS;
+        const int E = J.bold[b];
+        const int parts = J.hbase[b + 1] - J.hbase[b];
+        const int myoff = tid < R ? ro[tid] : E;
+        const int mypart = tid < R ? min(myoff / kPartEnt, parts - 1) : parts;
+        const int r_lo = __syncthreads_count(mypart < part);
+        const int r_hi = __syncthreads_count(mypart <= part);
+        const int E0 = r_lo < R ? ro[r_lo] : E, E1 = r_hi < R ? ro[r_hi] : E;
+        const int len = E1 - E0, nr = r_hi - r_lo;
+        const size_t base = (size_t)J.bbase[b] + E0;
+        const int chunk = max(1, (len + kChainThreads - 1) / kChainThreads);
+        const int e0 = min(tid * chunk, len), e1 = min(e0 + chunk, len);
+        unsigned long long w[kEntH];
+        float xj[kEntH], yj[kEntH];
+        const int m0 = min(kEntH, e1 - e0);
+#pragma unroll
+        for (int q = 0; q < kEntH; ++q) {
+            w[q] = 0;
+            xj[q] = 0.f;
+            yj[q] = 0.f;
+            if (q < m0) w[q] = J.ent[base + e0 + q];
+        }
+        if (tid >= r_lo && tid < r_hi) {
+            H.off[tid - r_lo] = myoff - E0;
+            const float2 p = ld<float2>(J.pos, b * BS + tid);
+            H.px[tid - r_lo] = p.x;
+            H.py[tid - r_lo] = p.y;
+        }
+        if (tid == 0) {
+            H.off[nr] = len;
+            H.go = bh_wait(J.sync + kSyncMoved, b - J.lag, (gptr<unsigned long long>)&J.ctr->wait_abort, J.spin_limit);
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(H.go)) return;
+        const PosC pc{J.pos};
+#pragma unroll
+        for (int q = 0; q < kEntH; ++q) {
+            if (q < m0) {
+                const float2 pj = pc((int)((unsigned)w[q] & 0x7fffffffu));
+                xj[q] = pj.x;
+                yj[q] = pj.y;
+            }
+        }
+        const int key0 = e0 < e1 ? (int)(w[0] >> 32) - r_lo : -1 - tid;
+        float2 firstp;
+        run_sum<kEntH, PosC, GM>(J.ent + base, pc, e0, e1, r_lo, w, xj, yj, H.off, H.px, H.py, H.sum, firstp, H.cl,
+                                 J.invK, J.negRK2, J.ka, J.kr);
+        carry_scan_wave(firstp, key0, H.loc, H.keys, H.wv, H.wk, H.wkf);
+        __syncthreads();
+        for (int j = tid; j < nr; j += kChainThreads) {
+            const float2 s2 = row_total(j, H.off[j], H.off[j + 1], chunk, H.sum, H.cl, H.loc, H.keys, H.wv, H.wk,
+                                        H.wkf);
+            st<float2>(J.oldf, (size_t)b * BS + r_lo + j, s2);
+        }
+        // every wave's sums complete, then their release with the count
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
+            (void)__hip_atomic_fetch_add(J.sync + kSyncReady + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// The minibatch chain: one workgroup per job walks the job's batches in
+// order, one step per batch, over the slot plan.  A lane's slot word is
+// loaded four steps before its batch comes up and its row's record and old
+// sum two steps before (their address is the slot word's row); batch records
+// come through the scalar unit a step ahead.  A step loads the ready flag of
+// the batch whose old sums the next step loads, the record and the old sum two
+// batches ahead and the slot word four batches ahead, and stores nothing to
+// memory: moved positions go to the ring, and a copy every kRelease steps
+// takes them to memory and waits for its stores.  (A store in flight among
+// loads leaves the compiler no count of the loads that have completed, so that
+// it would wait for all of them where a loaded value is used.)  A barrier on
+// LDS traffic alone ends the step.  The rows' terms use the positions their batch sees:
+// moved ones from an LDS ring of the last lag + 1 batches (WIN; Jacobi within
+// the batch, Gauss-Seidel across batches) or from memory (one-shot force
+// calls, where nothing moves).  The chain publishes how many batches it has
+// moved for the helpers, and waits for a batch's old sums before loading
+// them.
 template <bool GM, bool WIN>
-__device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chain2Shared &S, float2 *win, int first,
-                                           int last, int wbase, bool first_launch, bool last_launch) {
+__device__ __forceinline__ void chain_run(const BHJob &J, const BHJob *Jg, ChainShared &S, float2 *win) {
     const int tid = threadIdx.x;
-    const int BS = J.BS, n = J.n;
-    const PosL pl{win, wbase};
-    const PosG pg{J.pos};
-    auto gather = [&](int j) -> float2 {
-        if constexpr (WIN) return pl(j);
-        else return pg(j);
-    };
+    const int BS = J.BS, first = J.first_batch, last = J.last_batch, lag = J.lag;
     const float invK = J.invK, negRK2 = J.negRK2;
     const int k_it = J.kiter[0];
     const gptr<const int4> p_bmeta = J.bmeta;
     const gptr<const unsigned long long> p_slots = J.slots, p_ent = J.ent;
     const gptr<const float4> p_rec = J.rec;
+    const gptr<const float2> p_oldf = J.oldf;
     const gptr<const int2> p_rmeta = J.rmeta;
-    const gptr<float2> p_pos = J.pos, p_sink = J.sink;
+    const gptr<float2> p_pos = J.pos;
+    const gptr<int> p_sync = J.sync;
+    const bool helped = !J.all_live && last > lag;   // batches above lag have old entries
     // this lane's slot word of a batch with first slot pb0 and sc slots
     // (lanes past the last slot read the last one, which is padding)
     auto slot_load = [&](int pb0, int sc) -> unsigned long long {
@@ -1619,23 +1700,47 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
     auto rec_load = [&](int b, unsigned long long w) -> float4 {
         return ld<float4>(p_rec, (size_t)b * BS + (int)((w >> 32) & 1023u));
     };
+    // the old-entry sum of the lane's row (batches up to lag have none: the
+    // load is issued all the same, so that every step has the same loads, and
+    // its value is dropped where it is used)
+    auto old_load = [&](int b, unsigned long long w) -> float2 {
+        if (!helped) return float2{0.f, 0.f};
+        return ld_coh(p_oldf, (size_t)b * BS + (int)((w >> 32) & 1023u));
+    };
     // the recent-entry range of the row of a lane with several entries
     // (other lanes: none)
     auto range_load = [&](int b, unsigned long long w) -> int2 {
         return (w & kSlotMulti) ? ld<int2>(p_rmeta, (size_t)b * BS + (int)((w >> 32) & 1023u)) : int2{0, 0};
+    };
+    auto bq = [&](int q) { return min(q, last); };
+    // the old sums of batch q are there (or the launch is being left)
+    auto needs = [&](int q) { return helped && q > lag && q <= last; };
+    auto ready = [&](int q) -> int {
+        return !needs(q) || bh_wait(p_sync + kSyncReady + q, 1, (gptr<unsigned long long>)&J.ctr->wait_abort, J.spin_limit);
     };
 
     if (tid == 0) {
         double st = J.step0;
         for (int t = 0; t < k_it; ++t) st *= J.decay;
         S.step = st;
+        S.go = ready(first) && ready(first + 1);
     }
-    if (WIN)   // batches of the segment moved before this launch
-        for (int v = wbase + tid; v < first * BS; v += kChainThreads) win[v - wbase] = ld<float2>(J.pos, v);
-    // prologue: slot words of the first four batches, records of the first two
-    auto bq = [&](int q) { return min(q, last); };
+    if (WIN)   // the ring's batches moved before this launch
+        for (int v = max(0, first - lag) * BS + tid; v < first * BS; v += kChainThreads)
+            win[((v / BS) % (lag + 1)) * BS + v % BS] = ld<float2>(J.pos, v);
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(S.go)) return;
+    // every wave's copy of the ready flag of the batch whose old sums the next
+    // step loads (it checks it itself; a wait that gives up clears S.go,
+    // which all waves read after each group of four steps).  It is loaded
+    // ahead of the prologue's other loads, as each step loads it ahead of its
+    // others, so that the step's partial wait covers it on the first step too.
+    int fl = helped ? ld_flag(p_sync + kSyncReady + bq(first + 2)) : 1;
+    // prologue: slot words of the first four batches, records, old sums and
+    // ranges of the first two
     unsigned long long W0, W1, W2, W3;
     float4 R0{}, R1{}, R2{}, R3{};
+    float2 F0{}, F1{}, F2{}, F3{};
     int2 O0{}, O1{}, O2{}, O3{};
     {
         int2 q = sld2(p_bmeta, bq(first));
@@ -1648,24 +1753,43 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
         W3 = slot_load(q.x, q.y);
         R0 = rec_load(bq(first), W0);
         R1 = rec_load(bq(first + 1), W1);
+        F0 = old_load(bq(first), W0);
+        F1 = old_load(bq(first + 1), W1);
         O0 = range_load(bq(first), W0);
         O1 = range_load(bq(first + 1), W1);
     }
-    // scalar state: this batch's record, batch b + 4's first slot and slot count
+    // scalar state: this batch's record, batch b + 4's first slot and slot
+    // count, the ring slot of this batch
     int4 bm = sld4(p_bmeta, first);
     int2 q4 = sld2(p_bmeta, bq(first + 4));
-    __syncthreads();
+    static_assert(kRelease % 4 == 0, "the step loop takes four steps at a time");
+    int ring = first % (lag + 1);
     const float step = (float)S.step;
 
     double e_iter = 0.0;
     unsigned long long bad = 0;
-    // position of the row this thread moved as a lead lane of the last step's
-    // first pass, stored one step later (i < 0: none; its store goes to the
-    // lane's sink word)
-    const gptr<float2> sink_lane = p_sink + tid;
-    int pend_i = -1;
-    gptr<float2> pend_a = sink_lane;
-    float2 pend_p{0.f, 0.f};
+    // Moved positions stay in the ring; every kRelease steps the workgroup
+    // copies the batches moved since the last copy to memory (cp: the first
+    // batch not copied yet), with agent-scope stores that the helpers' loads
+    // see, and waits for them, so that the steps in between store nothing.
+    int cp = first;
+    // the old value the last progress update returned, used by the next one
+    // (an update that returns a value is a load for the compiler's counter
+    // waits, and a store in flight would cost the chain's loads their count)
+    int relv = 0;
+    auto copy_out = [&](int c1) __attribute__((always_inline)) {   // batches cp .. c1
+        const int cnt = (c1 - cp + 1) * BS;
+        for (int t = tid; t < cnt; t += kChainThreads) {
+            const int q = t / BS, r = t - q * BS;
+            const int v = (cp + q) * BS + r;
+            if (v < J.n) {
+                const float2 pv = win[((cp + q) % (lag + 1)) * BS + r];
+                __hip_atomic_store((gptr<unsigned long long>)(p_pos + v), __builtin_bit_cast(unsigned long long, pv),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        cp = c1 + 1;
+    };
 
     // The terms of this lane's slot and its run's suffix sum (the run's total
     // at its first lane).
@@ -1677,13 +1801,14 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
         const int rem = pad ? 0 : (int)((w >> 42) & 15u);
         if (!pad) {
             if (w & kSlotHas) {
-                const float2 pj = gather((int)((unsigned)w & 0x7fffffffu));
+                const int j = (int)((unsigned)w & 0x7fffffffu);
+                const float2 pj = WIN ? win[j] : ld<float2>(p_pos, j);
                 entry_term<GM>(w, pj.x - rc.x, pj.y - rc.y, invK, negRK2, J.ka, J.kr, ax, ay);
             }
             if (w & kSlotMulti) {
-                const float2 t = lane_terms<GM, WIN>(p_ent, win, wbase, p_pos, (size_t)lst + om.x,
-                                                     (int)(w & 0xffffu), om.y - om.x, (int)((w >> 16) & 0xffffu),
-                                                     rc.x, rc.y, invK, negRK2, J.ka, J.kr);
+                const float2 t = lane_terms<GM, WIN>(p_ent, win, p_pos, (size_t)lst + om.x, (int)(w & 0xffffu),
+                                                     om.y - om.x, (int)((w >> 16) & 0xffffu), rc.x, rc.y, invK,
+                                                     negRK2, J.ka, J.kr);
                 ax += t.x;
                 ay += t.y;
             }
@@ -1708,6 +1833,8 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
         if (stop) {
             J.fout[2 * r] = (double)fx;
             J.fout[2 * r + 1] = (double)fy;
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // no store left in flight among the chain's loads
+            if (WIN) win[ring * BS + r] = float2{rc.x, rc.y};   // unmoved (the ring is copied out)
             return;
         }
         float2 np{rc.x, rc.y};
@@ -1720,37 +1847,48 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
                 // step / |f| with the hardware reciprocal square root (about 1 ulp)
                 const float sc = step * __builtin_amdgcn_rsqf(fx * fx + fy * fy);
                 np = float2{rc.x + sc * fx, rc.y + sc * fy};
-                pend_i = i;
-                pend_a = p_pos + i;
-                pend_p = np;
             }
         }
-        if (WIN) win[i - wbase] = np;
+        if (WIN) win[ring * BS + r] = np;
+        else st<float2>(p_pos, i, np);
     };
 
-    // step b: wc / rc / oc hold batch b's slot word, record and row range; w2
-    // holds batch b + 2's slot word, and r2 / o2 receive its record and range;
-    // wc receives batch b + 4's slot word.
-    auto chain_step = [&](int b, unsigned long long &wc, const float4 &rc, const int2 &oc,
-                          const unsigned long long &w2, float4 &r2, int2 &o2) __attribute__((always_inline)) {
+    // step b: wc / rc / fc / oc hold batch b's slot word, record, old sum and
+    // row range; w2 holds batch b + 2's slot word, and r2 / f2 / o2 receive its
+    // record, old sum and range; wc receives batch b + 4's slot word.
+    auto chain_step = [&](int b, unsigned long long &wc, const float4 &rc, const float2 &fc, const int2 &oc,
+                          const unsigned long long &w2, float4 &r2, float2 &f2, int2 &o2)
+                          __attribute__((always_inline)) {
         const bool stop = (b == J.stop_batch);
-        wait_vm3();
+        // Every kRelease steps the batches moved since the last copy go from
+        // the ring to memory (the last step's barrier completed the ring).
+        // The earlier steps' loads are complete first, so that the stores in
+        // flight leave the compiler no loaded value to wait for in this step;
+        // the stores complete at its end, and the helpers get the batches.
+        const bool copy = WIN && helped && b > first && ((b - first) & (kRelease - 1)) == 0;
+        if (copy) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            copy_out(b - 1);
+        }
+        // the old sums this step loads (batch b + 2): the flag loaded a step ago
+        // (their helper needs batches below b + 2 - lag, published by now as
+        // lag >= kMinLag)
+        if (__any(fl < 1) && needs(b + 2) && !ready(b + 2)) S.go = 0;
         // next step's scalar state (its loads complete at this step's barrier)
         const int4 bmn = sld4(p_bmeta, bq(b + 1));
         const int2 q5 = sld2(p_bmeta, bq(b + 5));
+        if (helped) fl = ld_flag(p_sync + kSyncReady + bq(b + 3));
         r2 = rec_load(bq(b + 2), w2);
+        f2 = old_load(bq(b + 2), w2);
         o2 = range_load(bq(b + 2), w2);
-        st<float2>(pend_a, 0, pend_p);   // the position this lane moved in the previous step, or the sink
-        pend_i = -1;
-        pend_a = sink_lane;
         float2 f = run_total(wc, rc, oc, bm.z);
         const bool lead = !(wc & kSlotPad) && (wc & kSlotLead);
-        const bool first = lead && (wc & kSlotRow);
+        const bool first_lane = lead && (wc & kSlotRow);
         if (bm.w & kFlagSplit) {
             // split rows: the later runs' totals through LDS, added in run order
-            if (lead && !first) S.xpart[tid / kRunLanes] = f;
+            if (lead && !first_lane) S.xpart[tid / kRunLanes] = f;
             lds_barrier();
-            if (first) {
+            if (first_lane) {
                 const int runs = (int)((wc >> kSlotRunsShift) & 63u);
                 for (int q = 1; q <= runs; ++q) {
                     const float2 t = S.xpart[tid / kRunLanes + q];
@@ -1759,71 +1897,88 @@ __device__ __forceinline__ void chain2_run(const BHJob &J, const BHJob *Jg, Chai
                 }
             }
         }
-        if (first) move_row(b, wc, rc, f, stop);
+        if (first_lane) {
+            if (helped && b > lag) {   // the row's old entries, once
+                f.x += fc.x;
+                f.y += fc.y;
+            }
+            move_row(b, wc, rc, f, stop);
+        }
+        if (copy) {
+            // every wave's copy stores are complete after the barrier
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __builtin_amdgcn_s_barrier();
+            if (tid == 0)
+                relv = __hip_atomic_fetch_max(p_sync + kSyncMoved, relv < 0 ? relv : cp, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        }
         wc = slot_load(q4.x, q4.y);
-        if (b + 1 <= last && (bmn.w & kFlagOvf)) {
+        if (WIN && b + 1 <= last && (bmn.w & kFlagOvf)) {
             // a row of the next batch walks the tree over positions in memory
-            if (pend_i >= 0) st<float2>(p_pos, pend_i, pend_p);
-            pend_i = -1;
-            pend_a = sink_lane;
+            lds_barrier();
+            copy_out(b);
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             __syncthreads();
         } else {
             lds_barrier();
         }
         bm = bmn;
         q4 = q5;
+        ring = ring == lag ? 0 : ring + 1;
     };
-    for (int b = first; b <= last; b += 4) {
-        chain_step(b, W0, R0, O0, W2, R2, O2);
-        if (b + 1 <= last) chain_step(b + 1, W1, R1, O1, W3, R3, O3);
-        if (b + 2 <= last) chain_step(b + 2, W2, R2, O2, W0, R0, O0);
-        if (b + 3 <= last) chain_step(b + 3, W3, R3, O3, W1, R1, O1);
+    bool go = true;
+    for (int b = first; b <= last && go; b += 4) {
+        chain_step(b, W0, R0, F0, O0, W2, R2, F2, O2);
+        if (b + 1 <= last) chain_step(b + 1, W1, R1, F1, O1, W3, R3, F3, O3);
+        if (b + 2 <= last) chain_step(b + 2, W2, R2, F2, O2, W0, R0, F0, O0);
+        if (b + 3 <= last) chain_step(b + 3, W3, R3, F3, O3, W1, R1, F1, O1);
+        go = __builtin_amdgcn_readfirstlane(S.go) != 0;
     }
-    if (pend_i >= 0) st<float2>(p_pos, pend_i, pend_p);
+    if (!go) return;
+    if (WIN) copy_out(last);   // the last step's barrier made the ring complete
     if (bad) atomicAdd(&J.ctr->nonfinite, bad);
     const double e = block_sum_fixed(e_iter, S.wsd);
     if (tid == 0 && J.stop_batch < 0) {
-        // segments add their energies in order; the last one ends the iteration
         const int slot_e = k_it - J.kiter[1];
-        const double ek = first_launch ? e : J.energy[slot_e] + e;
-        J.energy[slot_e] = ek;
-        if (last_launch) {
-            J.kiter[0] = k_it + 1;
-            if (J.conv_tol > 0 && slot_e >= 1) {
-                const double ep = J.energy[slot_e - 1];
-                if (fabs(ek - ep) <= J.conv_tol * ep) J.ctr->halted = (unsigned long long)(slot_e + 1);
-            }
+        J.energy[slot_e] = e;
+        J.kiter[0] = k_it + 1;
+        if (J.conv_tol > 0 && slot_e >= 1) {
+            const double ep = J.energy[slot_e - 1];
+            if (fabs(e - ep) <= J.conv_tol * ep) J.ctr->halted = (unsigned long long)(slot_e + 1);
         }
     }
 }
 
+// One launch per iteration: per job, workgroup 0 runs the chain and the
+// others are its helpers.
 template <bool GM>
-__global__ __launch_bounds__(kChainThreads) void chain2_kernel(BH_KERNEL_ARGS, int seg) {
+__global__ __launch_bounds__(kChainThreads) void chain_kernel(BH_KERNEL_ARGS) {
     BH_JOB();
     if (J.general != (int)GM) return;
-    __shared__ Chain2Shared S;
-    extern __shared__ float2 win[];   // dynamic: the segment's moved positions
-    int first = J.first_batch, last = J.last_batch;
-    if (J.nseg <= 1) {
-        if (seg != 0) return;
-    } else {
-        const int L = seg_len(J);
-        first = max(first, seg * L);
-        last = min(last, seg * L + L - 1);
-        if (first > last) return;
+    extern __shared__ double lds_raw[];
+    if (jb.local > 0) {
+        chain_helper<GM>(J, *reinterpret_cast<HelperShared *>(lds_raw));
+        return;
     }
-    const bool first_launch = (first == J.first_batch), last_launch = (last == J.last_batch);
-    const int wbase = (J.nseg <= 1 ? 0 : seg * seg_len(J)) * J.BS;
+    ChainShared &S = *reinterpret_cast<ChainShared *>(lds_raw);
+    float2 *win = reinterpret_cast<float2 *>(lds_raw + (sizeof(ChainShared) + 7) / 8);
     if (!J.all_live)
-        chain2_run<GM, true>(J, jb.J, S, win, first, last, wbase, first_launch, last_launch);
+        chain_run<GM, true>(J, jb.J, S, win);
     else
-        chain2_run<GM, false>(J, jb.J, S, win, first, last, wbase, first_launch, last_launch);
+        chain_run<GM, false>(J, jb.J, S, win);
 }
 
 // ------------------------------------------------------------- host side
 namespace {
 
-enum PreType { PT_BBOX = 0, PT_VERT, PT_SORT, PT_ONE, PT_MARK, PT_SCAN, PT_VERT8, PT_HEAVY, PT_BATCH, PT_SEG, PT_COUNT };
+enum PreType { PT_BBOX = 0, PT_VERT, PT_SORT, PT_ONE, PT_MARK, PT_SCAN, PT_VERT8, PT_HEAVY, PT_BATCH, PT_CHAIN, PT_COUNT };
+
+// Helper workgroups of a job's chain launch: none in one-shot force calls or
+// when no batch of the run has old entries.
+int chain_helpers(const BHJob &J) {
+    if (J.all_live || J.last_batch <= J.lag) return 0;
+    return std::min(J.helpers, J.last_batch - std::max(J.first_batch, J.lag + 1) + 1);
+}
 
 int blocks_for(int type, const BHJob &J) {
     const int n = J.n;
@@ -1837,7 +1992,7 @@ int blocks_for(int type, const BHJob &J) {
         case PT_VERT8: return (n + 31) / 32;
         case PT_HEAVY: return std::max(16, std::min(256, n / 512));
         case PT_BATCH: return J.nb;
-        case PT_SEG: return J.nseg > 1 ? J.nsplit * ((J.nb + J.nseg - 1) / J.nseg) : 0;
+        case PT_CHAIN: return 1 + chain_helpers(J);
     }
     return 0;
 }
@@ -1856,12 +2011,17 @@ struct BHEngine {
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool ev_used[2] = {false, false};
     int total[PT_COUNT] = {};
-    int nseg = 1;                       // most chain segments of any job
     int nkind[2] = {0, 0};              // jobs of the (2, -1) model, jobs of other (a, r) models
-    size_t win_bytes = 0;               // chain window: the largest segment of any job
+    size_t lds_bytes = 0;               // dynamic LDS of the chain launch
     hipGraph_t graph = nullptr;         // one captured iteration of the current set
     hipGraphExec_t exec = nullptr;
 };
+
+// Dynamic LDS of the chain launch for a ring of `ring` vertices: the chain's
+// shared block and ring, or the helpers' workspace, whichever is larger.
+static size_t chain_lds_bytes(size_t ring) {
+    return std::max((sizeof(ChainShared) + 7) / 8 * 8 + sizeof(float2) * ring, sizeof(HelperShared));
+}
 
 // Drop the captured iteration (after the stream has drained).
 static void engine_drop_graph(BHEngine *e) {
@@ -1885,13 +2045,13 @@ int bh_engine_create(hipStream_t s, BHEngine **out) {
         }
     }
     // the chain's window is dynamic LDS beyond the 64 KB default
-    const void *chains[2] = {(const void *)chain2_kernel<false>, (const void *)chain2_kernel<true>};
+    const void *chains[2] = {(const void *)chain_kernel<false>, (const void *)chain_kernel<true>};
     for (int kind = 0; kind < 2; ++kind) {
         hipError_t r = hipFuncSetAttribute(chains[kind], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(sizeof(float2) * kWindow));
+                                           (int)chain_lds_bytes(kRing));
         if (r != hipSuccess) {
             bh_engine_destroy(e);
-            set_error("hipFuncSetAttribute(chain2_kernel) failed: %s", hipGetErrorString(r));
+            set_error("hipFuncSetAttribute(chain_kernel) failed: %s", hipGetErrorString(r));
             return BL_E_HIP;
         }
     }
@@ -1934,24 +2094,16 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->last_batch = (decltype(J->last_batch))(spec.last_batch);
     J->stop_batch = (decltype(J->stop_batch))(spec.stop_batch);
     {
-        // enough segments for the window, and for chains of kMinSegChain
-        // batches or more one per kSegBatches batches (up to kMaxSegments) to
-        // move old entries off the chain (shorter chains gain less than the
-        // segment launches cost)
-        int ns = 1;
-        if (!spec.all_live) {
-            const int nb = (int)g->nb, lmax = kWindow / (int)g->p.batch_size;
-            if (lmax < 1) {
-                set_error("batch size %d above the chain window", (int)g->p.batch_size);
-                return BL_E_INVAL;
-            }
-            const int want = nb < kMinSegChain ? 1 : std::max(1, std::min(kMaxSegments, nb / kSegBatches));
-            ns = std::max(want, (nb + lmax - 1) / lmax);
+        // the chain's LDS ring holds lag + 1 batches
+        const int lmax = kRing / (int)g->p.batch_size - 1;
+        if (lmax < kMinLag) {
+            set_error("batch size %d above the chain's ring", (int)g->p.batch_size);
+            return BL_E_INVAL;
         }
-        J->nseg = (decltype(J->nseg))ns;
-        // about 256 expected old entries or more per segment-kernel workgroup
-        const double per_batch = (double)g->p.batch_size * (double)g->nnz / std::max(1, g->n);
-        J->nsplit = (decltype(J->nsplit))std::max(1, std::min(kOldSplit, (int)(per_batch / 256.0)));
+        J->lag = (decltype(J->lag))std::min(kLag, lmax);
+        long long limit = 1ll << 18;   // polls of a microsecond or two each
+        if (const char *v = getenv("BL_BH_SPIN_LIMIT")) limit = atoll(v);
+        J->spin_limit = (decltype(J->spin_limit))limit;
     }
     J->step0 = (decltype(J->step0))(g->p.step0);
     J->decay = (decltype(J->decay))(g->p.step_decay);
@@ -1986,7 +2138,10 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->bold = (decltype(J->bold))(h.bold);
     J->rec = (decltype(J->rec))(h.rec);
     J->rmeta = (decltype(J->rmeta))(h.rmeta);
-    J->osplit = (decltype(J->osplit))(h.osplit);
+    J->oldf = (decltype(J->oldf))(h.oldf);
+    J->sync = (decltype(J->sync))(h.sync);
+    J->hbase = (decltype(J->hbase))(h.hbase);
+    J->hitem = (decltype(J->hitem))(h.hitem);
     J->heavy = (decltype(J->heavy))(h.heavy);
     J->nheavy = (decltype(J->nheavy))(h.nheavy);
     J->atte = (decltype(J->atte))(h.atte);
@@ -1998,7 +2153,6 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->pbase = (decltype(J->pbase))(h.pbase);
     J->slots = (decltype(J->slots))(h.slots);
     J->pflag = (decltype(J->pflag))(h.pflag);
-    J->sink = (decltype(J->sink))(h.sink);
     J->bmeta = (decltype(J->bmeta))(h.bmeta);
     J->energy = (decltype(J->energy))(g->energy);
     J->fout = (decltype(J->fout))(g->fout);
@@ -2031,21 +2185,21 @@ int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
         e->ev_used[0] = e->ev_used[1] = false;
     }
     std::memcpy(e->h_jobs[s], jobs, sizeof(BHJob) * G);
+    // helpers: up to kHelpers per job, fewer when many jobs share the chip
+    // (every job keeps one)
+    for (int j = 0; j < G; ++j) e->h_jobs[s][j].helpers = std::max(1, std::min(kHelpers, 512 / std::max(1, G) - 1));
     for (int t = 0; t < PT_COUNT; ++t) {
         int *pre = e->h_pre[s] + t * (e->cap + 1);
         pre[0] = 0;
-        for (int j = 0; j < G; ++j) pre[j + 1] = pre[j] + blocks_for(t, jobs[j]);
+        for (int j = 0; j < G; ++j) pre[j + 1] = pre[j] + blocks_for(t, e->h_jobs[s][j]);
         e->total[t] = pre[G];
     }
-    e->nseg = 1;
-    e->win_bytes = 0;
+    e->lds_bytes = sizeof(HelperShared);
     e->nkind[0] = e->nkind[1] = 0;
     for (int j = 0; j < G; ++j) {
         const BHJob &J = jobs[j];
         ++e->nkind[J.general ? 1 : 0];
-        e->nseg = std::max(e->nseg, (int)J.nseg);
-        if (!J.all_live)
-            e->win_bytes = std::max(e->win_bytes, sizeof(float2) * (size_t)J.BS * ((J.nb + J.nseg - 1) / J.nseg));
+        e->lds_bytes = std::max(e->lds_bytes, chain_lds_bytes((size_t)J.BS * (J.all_live ? 0 : J.lag + 1)));
     }
     BL_HIP(hipMemcpyAsync(e->d_jobs[s], e->h_jobs[s], sizeof(BHJob) * G, hipMemcpyHostToDevice, e->stream));
     BL_HIP(hipMemcpyAsync(e->d_pre[s], e->h_pre[s], sizeof(int) * PT_COUNT * (e->cap + 1),
@@ -2117,21 +2271,14 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     BH_LAUNCH(plan_count_kernel, PT_BATCH, 1024);
     BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 3);
     BH_LAUNCH(plan_fill_kernel, PT_VERT, 256);
-    for (int seg = 0; seg < e->nseg; ++seg) {
-        if (e->total[PT_SEG] > 0) {
-            if (prof) BL_TRY(prof_begin(prof, PK_OLDSUM, &slot));
-            BH_LAUNCH_M(old_sum_kernel, PT_SEG, 256, seg);
-            if (prof) BL_TRY(prof_end(prof, slot));
-        }
-        if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
-        for (int kind = 0; kind < 2; ++kind) {
-            if (e->total[PT_ONE] == 0 || !e->nkind[kind]) continue;
-            const int *pre = e->d_pre[e->cur] + PT_ONE * (e->cap + 1);
-            hipLaunchKernelGGL(kind ? chain2_kernel<true> : chain2_kernel<false>, dim3(e->total[PT_ONE]),
-                               dim3(kChainThreads), e->win_bytes, e->stream, jobs, pre, e->G, seg);
-        }
-        if (prof) BL_TRY(prof_end(prof, slot));
+    if (prof) BL_TRY(prof_begin(prof, PK_CHAIN, &slot));
+    for (int kind = 0; kind < 2; ++kind) {
+        if (e->total[PT_CHAIN] == 0 || !e->nkind[kind]) continue;
+        const int *pre = e->d_pre[e->cur] + PT_CHAIN * (e->cap + 1);
+        hipLaunchKernelGGL(kind ? chain_kernel<true> : chain_kernel<false>, dim3(e->total[PT_CHAIN]),
+                           dim3(kChainThreads), e->lds_bytes, e->stream, jobs, pre, e->G);
     }
+    if (prof) BL_TRY(prof_end(prof, slot));
     BL_HIP(hipGetLastError());
     return BL_OK;
 }
@@ -2179,6 +2326,10 @@ int bh_engine_run(BHEngine *e, int iters, bool use_graph) {
     return BL_OK;
 }
 
+// Helper items of an iteration at most: a part per batch, and one more per
+// kPartEnt entries of the old lists (at most every list entry).
+static size_t help_items(size_t nb, size_t ent) { return nb + ent / kPartEnt + 1; }
+
 size_t bh_footprint(int n, int64_t nnz, int BS) {
     const size_t N = (size_t)n;
     const size_t tiles = (N + kSortTile - 1) / kSortTile;
@@ -2187,9 +2338,9 @@ size_t bh_footprint(int n, int64_t nnz, int BS) {
     return 64 + 16 * kBBoxBlocks + 16 * N + 4 * 256 * tiles + 4 * N + 4 * (N + 1) + 4 * (sblocks + 1) +
            32 * (N + 1) + 32 * (sblocks + 1) + 2 * N * (16 + 8) + 4 * N + 16 + 16 * N + 4 * N +
            4 * N * kLateCap + 8 * N + 8 * (size_t)BS + 4 * N + 4 * N + 16 + 8 * N + 4 * N + 4 * (nb + 1) +
-           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 4 * nb * (kOldSplit + 1) +
-           4 * N + 4 * (nb + 1) + 8 * nb * (size_t)plan_cap(BS) + 4 * nb + 16 * N +
-           8 * (size_t)kChainThreads + 16 * nb;
+           8 * ((size_t)nnz + N * kLateCap) + 64 + 4 * N + 16 * N + 4 * (nb + 1) + 8 * N + 4 * (nb + kSyncReady) +
+           4 * N + 4 * (nb + 1) + 8 * nb * (size_t)plan_cap(BS) + 4 * nb + 16 * N + 16 * nb + 4 * (nb + 1) +
+           8 * help_items(nb, (size_t)nnz + N * kLateCap);
 }
 
 int bh_alloc(bl_graph *g) {
@@ -2223,7 +2374,10 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.bold, 4 * ((size_t)g->nb + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.rec, 16 * N));
     BL_TRY(graph_alloc(g, (void **)&h.rmeta, 8 * N));
-    BL_TRY(graph_alloc(g, (void **)&h.osplit, 4 * (size_t)g->nb * (kOldSplit + 1)));
+    BL_TRY(graph_alloc(g, (void **)&h.oldf, 8 * N));
+    BL_TRY(graph_alloc(g, (void **)&h.sync, 4 * ((size_t)g->nb + kSyncReady)));
+    BL_TRY(graph_alloc(g, (void **)&h.hbase, 4 * ((size_t)g->nb + 1)));
+    BL_TRY(graph_alloc(g, (void **)&h.hitem, 8 * help_items(g->nb, (size_t)g->nnz + N * kLateCap)));
     BL_TRY(graph_alloc(g, (void **)&h.heavy, 8 * N));
     BL_TRY(graph_alloc(g, (void **)&h.nheavy, 16));
     BL_TRY(graph_alloc(g, (void **)&h.atte, 8 * N));
@@ -2236,7 +2390,6 @@ int bh_alloc(bl_graph *g) {
     BL_TRY(graph_alloc(g, (void **)&h.pbase, 4 * ((size_t)g->nb + 1)));
     BL_TRY(graph_alloc(g, (void **)&h.slots, 8 * (size_t)g->nb * plan_cap(g->p.batch_size)));
     BL_TRY(graph_alloc(g, (void **)&h.pflag, 4 * (size_t)g->nb));
-    BL_TRY(graph_alloc(g, (void **)&h.sink, 8 * (size_t)kChainThreads));
     BL_TRY(graph_alloc(g, (void **)&h.bmeta, 16 * (size_t)g->nb));
     BL_TRY(graph_alloc(g, (void **)&h.kiter, 16));
     BL_HIP(hipMemsetAsync(h.bbox, 0, 64, g->stream));

@@ -158,7 +158,7 @@ int stats_fill(bl_graph *g, bl_stats *st, int iters_run, double seconds) {
         st->nonfinite_events = (int64_t)c.nonfinite;
         st->late_overflow = (int32_t)c.late_overflow;
     }
-    if (c.wait_abort) return fail(BL_E_TIMEOUT, "a device wait of the persistent exact kernel ran out");
+    if (c.wait_abort) return fail(BL_E_TIMEOUT, "a bounded device wait ran out (the launch left early)");
     return c.nonfinite ? BL_E_NONFINITE : BL_OK;
 }
 
@@ -368,7 +368,7 @@ static int run_impl(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t
         st->nonfinite_events = (int64_t)c.nonfinite;
         st->late_overflow = (int32_t)c.late_overflow;
     }
-    if (c.wait_abort) return fail(BL_E_TIMEOUT, "a device wait of the persistent exact kernel ran out");
+    if (c.wait_abort) return fail(BL_E_TIMEOUT, "a bounded device wait ran out (the launch left early)");
     if (c.nonfinite) return fail(BL_E_NONFINITE, "%llu non-finite net forces", c.nonfinite);
     return BL_OK;
 }
@@ -379,8 +379,8 @@ int bl_graph_run(bl_graph *g, int32_t iterations, int32_t start_iter, int32_t st
 }
 
 static const char *kProfNames[PK_COUNT] = {"rows_kernel", "step_kernel",        "finalize_kernel",
-                                           "tree_build",  "far_kernel",         "chain2_kernel",
-                                           "exact_graph_kernel", "old_sum_kernel", "steps_kernel"};
+                                           "tree_build",  "far_kernel",         "chain_kernel",
+                                           "exact_graph_kernel", "steps_kernel"};
 
 int bl_graph_profile(bl_graph *g, int32_t enable) {
     if (!g) return fail(BL_E_INVAL, "graph is NULL");

@@ -46,7 +46,7 @@ struct Counters {
 
 // Per-kernel device time, measured with hipEvents around launches when a
 // job's profiling is on.
-enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_GRAPH, PK_OLDSUM, PK_STEPS, PK_COUNT };
+enum ProfKernel { PK_ROWS = 0, PK_PANEL, PK_FINALIZE, PK_TREE, PK_FAR, PK_CHAIN, PK_GRAPH, PK_STEPS, PK_COUNT };
 constexpr int kProfPool = 8192;
 struct Prof {
     bool on = false;
@@ -90,7 +90,10 @@ struct BHBuffers {
     int *bold;              // [nb + 1] length of each batch list's old part
     float4 *rec;            // [n] chain row records: x, y, force apart from recent entries
     int2 *rmeta;            // [n] offset in the batch's recent list, late-leaf count
-    int *osplit;            // [nb * 17] row ranges of each batch's old part, one per workgroup
+    float2 *oldf;           // [n] old-entry sums, from the helpers to the chain
+    int *sync;              // [nb + 2] progress words of the chain launch
+    int *hbase;             // [nb + 1] helper parts per batch, then (scanned) the first part's item
+    int2 *hitem;            // helper items: (batch, part)
     int *heavy;             // [n] rows with many early neighbours (first *nheavy used)
     int *nheavy;            // [1]
     float2 *atte;           // [n] early attraction (neighbours not yet moved)
@@ -101,7 +104,6 @@ struct BHBuffers {
     int *pbase;             // [nb + 1] slot counts, then first slots of the batches' plans
     unsigned long long *slots;  // the batches' slot plans (one word per lane of the chain)
     int *pflag;             // [nb] batch flags of the chain's slot plan
-    float2 *sink;           // [1024] chain stores of lanes without a moved position
     int4 *bmeta;            // [nb] per batch: first slot, slot count, recent-list start, flags
     int *kiter;             // [2] current iteration, first iteration of the run
     int host_kiter[2];      // host staging for kiter

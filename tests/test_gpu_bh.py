@@ -162,9 +162,9 @@ def test_repeat_runs_bitwise(grid32):
 
 @pytest.mark.parametrize("iters,stop", [(1, 40), (1, 199), (2, 170)])
 def test_segmented_chain_ragged(iters, stop):
-    """A chain long enough to be cut into segments (200 batches of 64 rows,
-    ragged last batch and last segment): forces at stop batches inside later
-    segments, where most moved entries come from earlier segments."""
+    """A long chain (200 batches of 64 rows, ragged last batch): forces at stop
+    batches where most moved entries lie more than the chain's lag behind
+    (summed by its helper workgroups), the rest in its LDS ring."""
     g = I.rmat(14, 8, seed=23)
     n = 200 * 64 - 17
     keep = (g.colidx < n)
@@ -188,9 +188,9 @@ def test_segmented_chain_ragged(iters, stop):
 
 @pytest.mark.parametrize("stop", [25, 29])
 def test_window_forces_segments_at_big_batches(stop):
-    """Batch 1024: the chain's LDS window holds 10 batches, so a 30-batch
-    chain is cut into 3 segments even though it is short; forces in the
-    last segment, including the ragged last batch."""
+    """Batch 1024: the chain's LDS ring holds 15 batches (lag 14), so even a
+    30-batch chain has old entries for its helpers; forces in the last
+    batches, including the ragged last batch."""
     g = I.rmat(15, 8, seed=29)
     n = 29 * 1024 + 300
     rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
@@ -206,6 +206,25 @@ def test_window_forces_segments_at_big_batches(stop):
     r1 = min(n, stop * 1024 + 1024)
     ref = oracle.forces_bh(g.rowptr, g.colidx, xs, ys, oracle.Tree(x0, y0), stop * 1024, r1, theta=1.2)
     assert_forces(fx, fy, ref, mask=bh_mask(ref), what="stop %d" % stop)
+
+
+def test_chain_wait_limit_reports_timeout(monkeypatch):
+    """A spin limit of zero makes the first wait of the chain launch that is
+    not already met give up (a helper polling for batches the chain has not
+    moved yet): every workgroup leaves, the run reports BL_E_TIMEOUT, and a
+    new run is unaffected."""
+    g = I.rmat(14, 8, seed=23)
+    x0, y0 = I.uniform_coords(g.n, 24)
+    x0, y0 = _f32(x0), _f32(y0)
+    p = api.params(batch_size=64, iterations=2, mode="bh", theta=1.2)
+    monkeypatch.setenv("BL_BH_SPIN_LIMIT", "0")
+    with pytest.raises(api.BLError) as err:
+        api.layout(g, x0, y0, p)
+    assert err.value.code == -7
+    monkeypatch.delenv("BL_BH_SPIN_LIMIT")
+    xa, ya, ea, _ = api.layout(g, x0, y0, p)
+    xb, yb, eb, _ = api.layout(g, x0, y0, p)
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
 
 
 @pytest.mark.parametrize("n,bs", [(3000, 128), (12783, 64)])
