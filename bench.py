@@ -53,6 +53,7 @@ def flop_per_pair(model):
 # (FETCH_SIZE scaled by 2.0, the factor a plain copy of known size shows; WRITE_SIZE by 1.0).
 # Valid only while the kernel's source file is the one the counters were taken on.
 MEASURED_TRAFFIC = {
+    ("c2-bh", "chain_kernel"): (33953631.3, "bl_bh.hip", "c992386a699a55cf"),
 }
 
 
@@ -452,6 +453,8 @@ def main():
                     help="default run: arrival window of the compact served measurement")
     ap.add_argument("--no-precision", action="store_true", help="c3: skip the three-precision comparison")
     ap.add_argument("--no-bs-study", action="store_true", help="c4: skip the minibatch-size study")
+    ap.add_argument("--rcp-probe", action="store_true",
+                    help="measure the FMA and reciprocal issue rates and the exact kernel's pair ceiling")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -463,6 +466,8 @@ def main():
 
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.rcp_probe:
+        return rcp_probe()
     reqs = None
     if args.config == "c5" or (args.config == "c2-bh" and not args.no_other_configs):
         # request graphs are generated before anything touches the GPU
@@ -494,6 +499,33 @@ def main():
         out["other_configs"] = other_configs(args, api, reqs)
     else:
         out = bench_single(args, api, args.config)
+    print(json.dumps(out))
+    return 0
+
+
+def rcp_probe():
+    """Issue rates of v_fma_f32, v_rcp_f32 and their repulsion-term mix (one
+    reciprocal to six multiply-adds) through the library's probe, and the
+    instruction-bound ceiling of the exact kernel's repulsion pairs that
+    follows: a pair takes six FMA-class instructions and one reciprocal."""
+    import ctypes as C
+    from paper_2002_08233_amd import _lib
+    lib = _lib.load()
+    blocks, iters = 256 * 16, 4096
+    res = {}
+    for op, name in ((0, "fma"), (1, "rcp"), (2, "rep_mix")):
+        ms, ops = C.c_double(), C.c_double()
+        rc = lib.bl_probe_issue_rate(op, blocks, iters, None, C.byref(ms), C.byref(ops))
+        if rc != 0:
+            raise RuntimeError("bl_probe_issue_rate(%d) failed: %d" % (op, rc))
+        res[name] = {"ms": ms.value, "lane_ops_per_s": ops.value / (ms.value * 1e-3)}
+    lanes_clk = 256 * 64 * 2.4e9   # lanes of the chip's SIMDs per second at 2.4 GHz
+    fma = res["fma"]["lane_ops_per_s"]
+    out = {"rcp_probe": res,
+           "fma_fraction_of_2p4GHz_issue": fma / lanes_clk,
+           "rcp_rate_vs_fma": res["rcp"]["lane_ops_per_s"] / fma,
+           "pair_ceiling_per_s": res["rep_mix"]["lane_ops_per_s"] / 7.0,
+           "flop_ceiling_tflops": 10.0 * res["rep_mix"]["lane_ops_per_s"] / 7.0 / 1e12}
     print(json.dumps(out))
     return 0
 

@@ -329,6 +329,21 @@ int bl_graph_profile(bl_graph *h, int32_t enable);
  * criterion). */
 int bl_graph_profile_read(bl_graph *h, const char *kernel, double *total_ms, int64_t *launches);
 
+/* -------------------------------------------------- diagnostics
+ * Instruction issue rate of the device, for stating the exact kernel's
+ * instruction-bound ceiling (no part of the layout path).  Runs `blocks`
+ * workgroups of 256 threads, each thread `iters` rounds over 8 independent
+ * chains of: op 0, one FP32 fused multiply-add (v_fma_f32); op 1, one
+ * hardware reciprocal (v_rcp_f32); op 2, one reciprocal and six multiply-adds
+ * of other chains (the repulsion term's mix).  One untimed launch, then one
+ * timed with hipEvents on hip_stream (NULL: the default stream).  *ms gets
+ * the timed launch's duration; *lane_ops (may be NULL) the instructions it
+ * issued, counted per lane.  The probe allocates and frees its own 1 KiB per
+ * workgroup of device memory.  Errors: BL_E_INVAL (op not 0..2, blocks or
+ * iters not positive, ms NULL), BL_E_NOMEM, BL_E_HIP. */
+int bl_probe_issue_rate(int32_t op, int32_t blocks, int32_t iters, void *hip_stream, double *ms,
+                        double *lane_ops);
+
 /* -------------------------------------------------- many graphs at once
  * Lay out G independent graphs; graph i uses params[i] (iterations, batch
  * size, mode, theta may differ).  Graphs small enough for one workgroup run

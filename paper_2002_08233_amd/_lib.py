@@ -28,6 +28,7 @@ EXPORTED = [
     "bl_server_create", "bl_server_submit", "bl_server_poll", "bl_server_wait", "bl_server_fetch",
     "bl_server_release", "bl_server_destroy", "bl_greedy_init", "bl_quality_eval",
     "bl_layout_shuffled", "bl_quality_eval_noalloc", "bl_neighborhood_preservation",
+    "bl_probe_issue_rate",
 ]
 
 
@@ -104,6 +105,7 @@ def load():
     lib.bl_graph_destroy.argtypes = [vp]
     lib.bl_graph_profile.argtypes = [vp, i32]
     lib.bl_graph_profile_read.argtypes = [vp, C.c_char_p, P(dbl), P(i64)]
+    lib.bl_probe_issue_rate.argtypes = [i32, i32, i32, vp, P(dbl), P(dbl)]
     if hasattr(lib, "bl_layout_batch"):
         lib.bl_layout_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp]
     if hasattr(lib, "bl_server_create"):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbatchlayout.so")
 SOURCES = ["bl_capi.cpp", "bl_common.hip", "bl_exact.hip", "bl_bh.hip", "bl_batch.hip", "bl_server.cpp",
-           "bl_init.cpp", "bl_quality.hip", "bl_exact_models.hip", "bl_shuffle.cpp"]
+           "bl_init.cpp", "bl_quality.hip", "bl_exact_models.hip", "bl_shuffle.cpp", "bl_probe.hip"]
 ARCH = os.environ.get("BL_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

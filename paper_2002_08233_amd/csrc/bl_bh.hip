@@ -2094,13 +2094,18 @@ int bh_fill_job(bl_graph *g, BHJob *J, const BHRunSpec &spec) {
     J->last_batch = (decltype(J->last_batch))(spec.last_batch);
     J->stop_batch = (decltype(J->stop_batch))(spec.stop_batch);
     {
-        // the chain's LDS ring holds lag + 1 batches
+        // The chain's LDS ring holds lag + 1 batches.  A chain the ring holds
+        // whole needs no helpers (no entry refers to a batch more than lag
+        // back); a longer one keeps the last kLag batches and hands the rest
+        // to helpers.  BL_BH_LAG caps the lag (tests, measurements).
         const int lmax = kRing / (int)g->p.batch_size - 1;
         if (lmax < kMinLag) {
             set_error("batch size %d above the chain's ring", (int)g->p.batch_size);
             return BL_E_INVAL;
         }
-        J->lag = (decltype(J->lag))std::min(kLag, lmax);
+        int lag = (int)g->nb - 1 <= lmax ? std::max(1, (int)g->nb - 1) : std::min(kLag, lmax);
+        if (const char *v = getenv("BL_BH_LAG")) lag = std::min(lag, std::max(kMinLag, atoi(v)));
+        J->lag = (decltype(J->lag))lag;
         long long limit = 1ll << 18;   // polls of a microsecond or two each
         if (const char *v = getenv("BL_BH_SPIN_LIMIT")) limit = atoll(v);
         J->spin_limit = (decltype(J->spin_limit))limit;

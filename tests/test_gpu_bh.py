@@ -160,11 +160,14 @@ def test_repeat_runs_bitwise(grid32):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
-@pytest.mark.parametrize("iters,stop", [(1, 40), (1, 199), (2, 170)])
-def test_segmented_chain_ragged(iters, stop):
+@pytest.mark.parametrize("iters,stop,lag", [(1, 40, 14), (1, 199, 14), (2, 170, 14), (1, 199, None), (2, 170, None)])
+def test_segmented_chain_ragged(iters, stop, lag, monkeypatch):
     """A long chain (200 batches of 64 rows, ragged last batch): forces at stop
-    batches where most moved entries lie more than the chain's lag behind
-    (summed by its helper workgroups), the rest in its LDS ring."""
+    batches.  With the lag capped at 14, most moved entries lie more than the
+    chain's lag behind (summed by its helper workgroups), the rest in its LDS
+    ring; by default the ring holds the whole chain and no helper runs."""
+    if lag is not None:
+        monkeypatch.setenv("BL_BH_LAG", str(lag))
     g = I.rmat(14, 8, seed=23)
     n = 200 * 64 - 17
     keep = (g.colidx < n)
@@ -217,6 +220,7 @@ def test_chain_wait_limit_reports_timeout(monkeypatch):
     x0, y0 = I.uniform_coords(g.n, 24)
     x0, y0 = _f32(x0), _f32(y0)
     p = api.params(batch_size=64, iterations=2, mode="bh", theta=1.2)
+    monkeypatch.setenv("BL_BH_LAG", "14")   # (the ring would hold this chain whole: no helpers, no waits)
     monkeypatch.setenv("BL_BH_SPIN_LIMIT", "0")
     with pytest.raises(api.BLError) as err:
         api.layout(g, x0, y0, p)
@@ -227,11 +231,13 @@ def test_chain_wait_limit_reports_timeout(monkeypatch):
     assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(ea, eb)
 
 
-@pytest.mark.parametrize("n,bs", [(3000, 128), (12783, 64)])
-def test_energy_stopping_rule(n, bs):
-    """conv_tol on the Barnes-Hut engine (one segment, and a segmented chain):
-    the run stops at the same iteration as the oracle and equals a plain run
-    of that many iterations bitwise."""
+@pytest.mark.parametrize("n,bs,lag", [(3000, 128, None), (12783, 64, 14)])
+def test_energy_stopping_rule(n, bs, lag, monkeypatch):
+    """conv_tol on the Barnes-Hut engine (a chain the ring holds whole, and a
+    chain with helpers): the run stops at the same iteration as the oracle and
+    equals a plain run of that many iterations bitwise."""
+    if lag is not None:
+        monkeypatch.setenv("BL_BH_LAG", str(lag))
     g = I.rmat(14, 8, seed=31)
     rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
     sel = (g.colidx < n) & (rows < n)
