@@ -24,9 +24,9 @@
 // attraction (and, in literal mode, the neighbour repulsion) of the row's
 // CSR entries inside the batch in entry order, combined into one partial,
 // then one compensated (Kahan) add into the row's sum.  Energy: per batch,
-// each 256-row chunk (aligned to absolute row ids) is summed by wave
-// butterflies and then its four wave sums in order; the chunk sums are added
-// in row order; iteration energies add the batch sums in batch order.
+// each kRows-row chunk (aligned to absolute row ids) is summed by wave
+// butterflies and then its wave sums in order; the chunk sums are added in
+// row order; iteration energies add the batch sums in batch order.
 //
 // Kernels: rows_kernel (whole-column-batch sums: the prologue of a run and
 // the one-shot force call), steps_kernel (all steps of a run in one
@@ -61,7 +61,8 @@ struct V2<double> {
     using type = double2;
 };
 
-constexpr int kRows = 256;     // rows per workgroup of the multi-workgroup kernels (= energy chunk)
+constexpr int kRows = 128;     // rows per workgroup of the multi-workgroup kernels (= energy chunk)
+constexpr int kChunkWaves = kRows / kWave;   // waves of one energy chunk at one lane per row
 constexpr int kTile = 1024;    // columns staged in LDS per pass
 constexpr int kSimds = 256 * 4;   // SIMDs of the chip (256 compute units x 4)
 constexpr int kPre = 4;        // CSR entries of a row prefetched per column batch
@@ -778,9 +779,9 @@ __device__ __forceinline__ double finish_row(const GView<T> &G, int i, int r, T 
     return f2;
 }
 
-// Sum over one 256-row chunk held by 4 consecutive waves: wave butterflies,
-// then the four wave sums in order.  `ws` is LDS of one double per wave;
-// `w0` the chunk's first wave.  Valid in the chunk's first thread; all
+// Sum over one kRows-row chunk held by kChunkWaves consecutive waves: wave
+// butterflies, then the wave sums in order.  `ws` is LDS of one double per
+// wave; `w0` the chunk's first wave.  Valid in the chunk's first thread; all
 // threads of the workgroup call it.
 __device__ __forceinline__ double chunk_sum(double e, double *ws, int w0) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -789,7 +790,11 @@ __device__ __forceinline__ double chunk_sum(double e, double *ws, int w0) {
     if (lane == 0) ws[w] = e;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == w0 * kWave) r = ((ws[w0] + ws[w0 + 1]) + ws[w0 + 2]) + ws[w0 + 3];
+    if (threadIdx.x == w0 * kWave) {
+        r = ws[w0];
+#pragma unroll
+        for (int q = 1; q < kChunkWaves; ++q) r += ws[w0 + q];
+    }
     __syncthreads();
     return r;
 }
@@ -827,7 +832,7 @@ __device__ __forceinline__ bool halted_run(double conv_tol, const unsigned long 
 }
 
 // Finishing of batch a.fin by the workgroup holding rows [first, first +
-// 256): each row's force (already in (fx, fy) when `have`, else from
+// kRows): each row's force (already in (fx, fy) when `have`, else from
 // memory), the move, and the batch energy, combined over the batch's chunks
 // by the last workgroup to finish.
 template <typename T, bool KAHAN>
@@ -878,7 +883,7 @@ __device__ __forceinline__ void finish_chunk(const GView<T> &G, const FinArgs<T>
 }
 
 // finish_chunk for the lead lanes of a kRows * L workgroup: the rows' |f|^2
-// go through LDS to the first 256 threads, which sum them with the same tree
+// go through LDS to the first kRows threads, which sum them with the same tree
 // as finish_chunk.
 template <typename T, bool KAHAN, int L, bool COH = false>
 __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T> &a, int first, T xi, T yi, T fx,
@@ -948,7 +953,7 @@ __global__ __launch_bounds__(kRows * L) void step_kernel(GView<T> G, int c, int 
 
 // ------------------------------------------------- persistent whole run
 // A run as one launch of co-resident workgroups (cooperative launch).  Each
-// workgroup owns fixed 256-row chunks and walks the steps in order; a step
+// workgroup owns fixed kRows-row chunks and walks the steps in order; a step
 // waits only until the batch whose columns it adds has moved, and the
 // workgroups holding the next batch's rows move them and count the move.
 // Every wait is for an earlier step, so the launch always progresses; a wait
@@ -1068,7 +1073,7 @@ __global__ __launch_bounds__(kRows) void finalize_kernel(GView<T> G, FinArgs<T> 
 // ------------------------------------------------- one workgroup per graph
 // Many small graphs in one launch: each workgroup runs the whole layout of
 // one graph, the steps in order with workgroup barriers between them, in
-// passes of NT rows aligned to absolute row ids (so waves and 256-row chunks
+// passes of NT rows aligned to absolute row ids (so waves and kRows-row chunks
 // cover the same rows as in the multi-workgroup kernels, and the result is
 // the same bitwise).
 struct ExactJob {
@@ -1149,7 +1154,9 @@ __global__ __launch_bounds__(NT) void exact_graph_kernel(const ExactJob *__restr
                 for (int ch = 0; ch < NT / kRows; ++ch) {
                     const int cf = first + ch * kRows;
                     if (cf + kRows <= b0 || cf >= b1) continue;
-                    const double cs = ((ws[4 * ch] + ws[4 * ch + 1]) + ws[4 * ch + 2]) + ws[4 * ch + 3];
+                    double cs = ws[kChunkWaves * ch];
+#pragma unroll
+                    for (int q = 1; q < kChunkWaves; ++q) cs += ws[kChunkWaves * ch + q];
                     bs = (cf <= b0) ? cs : bs + cs;
                 }
                 s_batch = bs;
