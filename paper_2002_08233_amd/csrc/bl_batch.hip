@@ -124,8 +124,10 @@ extern "C" int bl_layout_batch(int32_t G, const bl_csr *const *graphs, const dou
             return fail_code(BL_E_INVAL, "BL_ADAPTIVE_STEP is a bl_layout option");
     }
     BatchState B;
-    BL_HIP(hipStreamCreate(&B.s_ex));
-    BL_HIP(hipStreamCreate(&B.s_bh));
+    // non-blocking: the legacy stream of other threads does not wait for them
+    // (nor for the graph captured on s_bh)
+    BL_HIP(hipStreamCreateWithFlags(&B.s_ex, hipStreamNonBlocking));
+    BL_HIP(hipStreamCreateWithFlags(&B.s_bh, hipStreamNonBlocking));
     hipStream_t user = (hipStream_t)hip_stream;
     BL_HIP(hipStreamSynchronize(user));
     B.gs.assign(G, nullptr);

@@ -181,7 +181,10 @@ int launch(Lane &L) {
             BL_TRY(bh_engine_setup(L.eng));
             L.set_dirty = false;
         }
-        BL_TRY(bh_engine_run(L.eng, q, q > 1));
+        // (launched directly, not replayed from a captured graph: a capture in
+        // progress on this thread would make legacy-stream calls of other
+        // threads of the process fail)
+        BL_TRY(bh_engine_run(L.eng, q, false));
     }
     for (auto &j : ex) BL_TRY(exact_run(j->g, q, j->p.start_iter + j->done_iters, -1));
     BL_HIP(hipEventRecord(L.done, L.stream));
