@@ -885,10 +885,10 @@ __device__ __forceinline__ void finish_chunk(const GView<T> &G, const FinArgs<T>
 // finish_chunk for the lead lanes of a kRows * L workgroup: the rows' |f|^2
 // go through LDS to the first kRows threads, which sum them with the same tree
 // as finish_chunk.
-template <typename T, bool KAHAN, int L, bool COH = false>
-__device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T> &a, int first, T xi, T yi, T fx,
-                                              T fy, double *e2, double *ws) {
-    __shared__ int s_last;
+// The rows' moves and the chunk's energy sum (valid in thread 0).
+template <typename T, bool KAHAN, int L>
+__device__ __forceinline__ double finish_rowsL(const GView<T> &G, const FinArgs<T> &a, int first, T xi, T yi, T fx,
+                                               T fy, double *e2, double *ws) {
     const bool lead = (threadIdx.x & (L - 1)) == 0;
     const int r = threadIdx.x / L;
     const int i = first + r;
@@ -898,7 +898,15 @@ __device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T
     if (lead) e2[r] = mine ? finish_row<T>(G, i, i - b0, xi, yi, fx, fy, a.step, a.update, a.fout, bad) : 0.0;
     if (bad) atomicAdd(a.nonfinite_count, bad);
     __syncthreads();
-    const double cs = chunk_sum(threadIdx.x < kRows ? e2[threadIdx.x] : 0.0, ws, 0);
+    return chunk_sum(threadIdx.x < kRows ? e2[threadIdx.x] : 0.0, ws, 0);
+}
+
+template <typename T, bool KAHAN, int L, bool COH = false>
+__device__ __forceinline__ void finish_chunkL(const GView<T> &G, const FinArgs<T> &a, int first, T xi, T yi, T fx,
+                                              T fy, double *e2, double *ws) {
+    __shared__ int s_last;
+    const int b0 = a.fin * G.BS, b1 = min(b0 + G.BS, G.n);
+    const double cs = finish_rowsL<T, KAHAN, L>(G, a, first, xi, yi, fx, fy, e2, ws);
     if (!a.energy_k) return;
     const int ch0 = b0 / kRows, ch1 = (b1 - 1) / kRows, nch = ch1 - ch0 + 1;
     // (COH: the running energy was written by another workgroup of the
@@ -968,7 +976,51 @@ struct StepsArgs {
     unsigned *moved;       // [nb] chunk moves of each batch since the run started
     unsigned long long *abort;
     long long spin_limit;  // polls before a wait gives up
+    // energies combined after the release (no stopping rule): per iteration
+    // parity, chunk sums [nb][maxch], batch sums [nb], tickets [nb + 1]
+    int deferred, maxch;
+    double *echunk, *ebatch;
+    unsigned *eticket;
 };
+
+// The iteration energy off the chain's critical path (thread 0 of a
+// finishing workgroup, after its release): the chunk sum goes to its slot;
+// the batch's last chunk adds the batch's chunk sums in order; the last
+// batch's, once every batch of the iteration has its sum, adds the batch sums
+// in batch order.  The same additions in the same order as the finish that
+// combines them before the release.  Batch 0 of the run's first iteration was
+// finished before the launch, its sum already in energy_k.
+__device__ __forceinline__ void energy_deferred(const StepsArgs &A, int nb, int BS, int n, int fin, int kf, int first,
+                                                double cs, double *energy_k) {
+    const int p = kf & 1;
+    const int b0 = fin * BS, b1 = min(b0 + BS, n);
+    const int ch0 = b0 / kRows, nch = (b1 - 1) / kRows - ch0 + 1;
+    double *ec = A.echunk + ((size_t)p * nb + fin) * A.maxch;
+    unsigned *tk = A.eticket + (size_t)p * (nb + 1);
+    ec[first / kRows - ch0] = cs;
+    if (__hip_atomic_fetch_add(tk + fin, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)(nch - 1)) return;
+    double bs = ec[0];   // (after the acquire above)
+    for (int q = 1; q < nch; ++q) bs += ec[q];
+    __hip_atomic_store(tk + fin, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    A.ebatch[(size_t)p * nb + fin] = bs;
+    const unsigned need = (kf == A.start) ? (unsigned)(nb - 1) : (unsigned)nb;
+    if (__hip_atomic_fetch_add(tk + nb, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == need) {
+        // (after the acquire above, plain loads see every batch's sum; eight
+        // in flight at a time, added in batch order)
+        const double *eb = A.ebatch + (size_t)p * nb;
+        double ek = (kf == A.start) ? *energy_k : eb[0];
+        for (int b = 1; b < nb; b += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = b + u < nb ? eb[b + u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (b + u < nb) ek += v[u];
+        }
+        *energy_k = ek;
+        __hip_atomic_store(tk + nb, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // Thread 0: wait until *cnt >= need (the caller then acquires).  Returns 0
 // when the launch is being abandoned.
@@ -1041,13 +1093,17 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
                     fa.pf = kf & 1;
                     fa.step = (T)st_cur;
                     fa.energy_k = A.energy + (kf - A.start);
-                    finish_chunkL<T, KAHAN, L, true>(G, fa, first, xi, yi, fx, fy, e2, ws);
+                    double cs = 0.0;
+                    if (A.deferred) cs = finish_rowsL<T, KAHAN, L>(G, fa, first, xi, yi, fx, fy, e2, ws);
+                    else finish_chunkL<T, KAHAN, L, true>(G, fa, first, xi, yi, fx, fy, e2, ws);
                     // every wave's stores complete, then one release of them and the count
                     __builtin_amdgcn_s_waitcnt(0);
                     __syncthreads();
                     if (threadIdx.x == 0)
                         __hip_atomic_fetch_add(A.moved + fin, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     __builtin_amdgcn_s_setprio(0);
+                    if (A.deferred && threadIdx.x == 0 && fa.energy_k)
+                        energy_deferred(A, nb, G.BS, G.n, fin, kf, first, cs, fa.energy_k);
                 }
             }
         }
@@ -1056,8 +1112,9 @@ __global__ __launch_bounds__(kRows * L) void steps_kernel(GView<T> G, StepsArgs 
 
 // Move counters of a persistent run: batch 0 of its first iteration was
 // finished before the launch.
-__global__ void moved_init_kernel(unsigned *moved, int nb, unsigned first_chunks) {
+__global__ void moved_init_kernel(unsigned *moved, int nb, unsigned first_chunks, unsigned *eticket) {
     for (int b = threadIdx.x; b < nb; b += blockDim.x) moved[b] = b == 0 ? first_chunks : 0u;
+    for (int q = threadIdx.x; q < 2 * (nb + 1); q += blockDim.x) eticket[q] = 0u;
 }
 
 
@@ -1234,7 +1291,10 @@ struct ExactOps {
 
     // Lanes per row of the multi-workgroup kernels: enough waves per SIMD to
     // hide latency, as few lanes as that allows (each lane's loop overhead is
-    // shared by more pairs).  The result does not depend on it.
+    // shared by more pairs).  Two lanes from two one-lane waves per SIMD up:
+    // with fewer, the workgroups that finish a batch -- the chain's critical
+    // path -- run on too few waves (rgg64k, 1024 one-lane waves: 1.49 ms per
+    // iteration at four lanes, 1.67 at two).  The result does not depend on it.
     static int lanes(bl_graph *g, int rows) {
         if (const char *e = getenv("BL_EXACT_LANES")) {
             const int v = atoi(e);
@@ -1242,7 +1302,7 @@ struct ExactOps {
         }
         const long long waves1 = ((long long)rows + kWave - 1) / kWave;   // waves at one lane per row
         if (waves1 >= 8LL * kSimds) return 1;
-        if (waves1 >= kSimds) return 2;
+        if (waves1 >= 2LL * kSimds) return 2;
         return 4;
     }
 
@@ -1325,7 +1385,8 @@ struct ExactOps {
         if (const char *v = getenv("BL_EXACT_SPIN_LIMIT")) limit = atoll(v);
         const int BS = g->p.batch_size;
         const unsigned first_chunks = (unsigned)((std::min(BS, g->n) - 1) / kRows + 1);
-        hipLaunchKernelGGL(moved_init_kernel, dim3(1), dim3(256), 0, g->stream, g->ex.moved, g->nb, first_chunks);
+        hipLaunchKernelGGL(moved_init_kernel, dim3(1), dim3(256), 0, g->stream, g->ex.moved, g->nb, first_chunks,
+                           g->ex.eticket);
         BL_HIP(hipGetLastError());
         StepsArgs A;
         A.e0 = e0;
@@ -1338,6 +1399,11 @@ struct ExactOps {
         A.moved = g->ex.moved;
         A.abort = &g->counters->wait_abort;
         A.spin_limit = limit;
+        A.deferred = g->p.conv_tol > 0 ? 0 : 1;   // (the stopping rule needs each energy before the next step)
+        A.maxch = BS / kRows + 2;
+        A.echunk = g->ex.echunk;
+        A.ebatch = g->ex.ebatch;
+        A.eticket = g->ex.eticket;
         FinArgs<T> fa0 = fin_args(g, 0, start, nullptr, nullptr, 1);
         GView<T> G = view(g);
         void *args[] = {&G, &A, &fa0};
@@ -1556,6 +1622,9 @@ int exact_alloc(bl_graph *g) {
     }
     BL_TRY(graph_alloc(g, (void **)&g->ex.epart, sizeof(double) * (size_t)(BS / kRows + 2)));
     BL_TRY(graph_alloc(g, (void **)&g->ex.ticket, 256));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.echunk, sizeof(double) * 2 * (size_t)g->nb * (size_t)(BS / kRows + 2)));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.ebatch, sizeof(double) * 2 * (size_t)g->nb));
+    BL_TRY(graph_alloc(g, (void **)&g->ex.eticket, sizeof(unsigned) * 2 * ((size_t)g->nb + 1)));
     BL_TRY(graph_alloc(g, &g->ex.d_job, sizeof(ExactJob)));
     BL_TRY(graph_alloc(g, (void **)&g->ex.moved, sizeof(unsigned) * (size_t)g->nb));
     BL_HIP(hipMemsetAsync(g->ex.ticket, 0, 256, g->stream));
@@ -1588,7 +1657,8 @@ size_t exact_footprint(int n, int64_t nnz, int BS, bool fp64) {
     const size_t N = (size_t)n, T2 = fp64 ? 16 : 8;
     const size_t nb = (N + BS - 1) / BS;
     return 2 * (T2 * N + 8 * N) + 8 * (size_t)(BS / kRows + 2) + 256 + sizeof(ExactJob) + 4 * nb + 4 * (N + 1) + 4 * N +
-           8 * (size_t)std::max<int64_t>(nnz, 1) + 4 * 256;
+           8 * (size_t)std::max<int64_t>(nnz, 1) + 4 * 256 + 16 * nb * (size_t)(BS / kRows + 2) + 16 * nb +
+           8 * (nb + 1);
 }
 
 // Small graphs run in the one-workgroup kernel (one workgroup per graph); it

@@ -126,8 +126,11 @@ struct ExactBuffers {
                             // neighbours that fall in one batch, rows in order
     int *segoff;            // [n + 1] first segment of each row
     int *cursor;            // [n] next segment of each row in the column-batch cycle
-    double *epart;          // energy partials of the 256-row chunks of one batch
+    double *epart;          // energy partials of the row chunks of one batch
     unsigned *ticket;       // last-workgroup counter of the batch finalize
+    double *echunk;         // persistent run: [2][nb][BS / kRows + 2] chunk energies by iteration parity
+    double *ebatch;         // persistent run: [2][nb] batch energies by iteration parity
+    unsigned *eticket;      // persistent run: [2][nb + 1] chunks combined per batch, then batches combined
     void *d_job;            // one-job table of the one-workgroup kernel
     unsigned *moved;        // [nb] chunk moves of each batch in the current persistent run
 };
