@@ -264,3 +264,13 @@ def test_adaptive_step_is_a_layout_option(lib):
     ppp = (C.c_void_p * 1)(C.addressof(pp))
     assert lib.bl_layout_batch(1, gp, xp, xp, ppp, None, xp, xp, None) == -1
     assert "ADAPTIVE" in lib.bl_last_error().decode()
+
+
+@pytest.mark.parametrize("op,blocks,iters,null_ms", [(3, 1, 1, False), (-1, 1, 1, False), (0, 0, 1, False),
+                                                     (1, 1, 0, False), (2, 1, 1, True)])
+def test_issue_probe_rejects_bad_arguments(lib, op, blocks, iters, null_ms):
+    """The issue-rate probe checks its arguments before touching the device."""
+    ms, ops = C.c_double(), C.c_double()
+    rc = lib.bl_probe_issue_rate(op, blocks, iters, None, None if null_ms else C.byref(ms), C.byref(ops))
+    assert rc == -1
+    assert b"bl_probe_issue_rate" in lib.bl_last_error()

@@ -282,3 +282,17 @@ def test_energy_stopping_rule(monkeypatch, path):
     assert np.array_equal(xs, xp) and np.array_equal(ys, yp) and np.array_equal(es, ep)
     _, _, eo = oracle.layout_exact(g.rowptr, g.colidx, x0, y0, 128, 14, step0=0.05, decay=0.97, conv_tol=tol)
     assert len(eo) == want
+
+
+@pytest.mark.gpu
+def test_issue_probe_counts_and_times():
+    """The issue-rate probe times each op and counts the instructions it
+    issued: blocks x 256 threads x iters x 8 chains (x 7 for the mix)."""
+    import ctypes as C
+    from paper_2002_08233_amd import _lib
+    lib = _lib.load()
+    for op, per in ((0, 1), (1, 1), (2, 7)):
+        ms, ops = C.c_double(), C.c_double()
+        assert lib.bl_probe_issue_rate(op, 64, 128, None, C.byref(ms), C.byref(ops)) == 0
+        assert ms.value > 0
+        assert ops.value == 64 * 256 * 128 * 8 * per
