@@ -213,6 +213,18 @@ int bl_graph_create(const bl_csr *csr, const bl_params *p, void *hip_stream, bl_
 
 }  // extern "C"
 
+int bl::graph_reload_csr(bl_graph *g, const int32_t *rowptr, const int32_t *colidx) {
+    const size_t N = (size_t)g->n;
+    BL_HIP(hipMemcpyAsync(g->rowptr, rowptr, 4 * (N + 1), hipMemcpyHostToDevice, g->stream));
+    if (g->nnz) BL_HIP(hipMemcpyAsync(g->colidx, colidx, 4 * (size_t)g->nnz, hipMemcpyHostToDevice, g->stream));
+    g->cont_iter = -1;
+    g->keep_next = false;
+    if (g->p.mode == BL_EXACT) BL_TRY(exact_prepare(g));   // CSR segments by column batch
+    else g->bh.prefix_ready = false;                       // moved-neighbour prefixes, heavy rows
+    BL_HIP(hipStreamSynchronize(g->stream));
+    return BL_OK;
+}
+
 int bl::graph_create_ex(const bl_csr *csr, const bl_params *p, hipStream_t s, bool async_mem, bl_graph **out) {
     if (!out) return fail(BL_E_INVAL, "out is NULL");
     *out = nullptr;

@@ -1645,7 +1645,10 @@ int exact_prepare(bl_graph *g) {
     int nseg = 0;
     BL_HIP(hipMemcpyAsync(&nseg, g->ex.segoff + n, sizeof(int), hipMemcpyDeviceToHost, g->stream));
     BL_HIP(hipStreamSynchronize(g->stream));
-    BL_TRY(graph_alloc(g, (void **)&g->ex.segs, sizeof(int2) * (size_t)std::max(nseg, 1)));
+    if (!g->ex.segs || g->ex.segs_cap < (size_t)std::max(nseg, 1)) {   // (a reloaded CSR reuses the room)
+        BL_TRY(graph_alloc(g, (void **)&g->ex.segs, sizeof(int2) * (size_t)std::max<int64_t>(std::max(nseg, 1), g->nnz)));
+        g->ex.segs_cap = (size_t)std::max<int64_t>(std::max(nseg, 1), g->nnz);
+    }
     hipLaunchKernelGGL(seg_fill_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n, BS, g->rowptr, g->colidx,
                        g->ex.segoff, g->ex.segs);
     BL_HIP(hipGetLastError());

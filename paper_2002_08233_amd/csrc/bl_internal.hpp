@@ -124,6 +124,7 @@ struct ExactBuffers {
     float2 *accC[2];        // [n] Kahan compensation (FP32 Kahan only)
     int2 *segs;             // CSR segments: (column batch, first entry) of each run of a row's
                             // neighbours that fall in one batch, rows in order
+    size_t segs_cap;        // segments segs holds room for (kept across CSR reloads)
     int *segoff;            // [n + 1] first segment of each row
     int *cursor;            // [n] next segment of each row in the column-batch cycle
     double *epart;          // energy partials of the row chunks of one batch
@@ -179,6 +180,10 @@ int graph_alloc(bl_graph *g, void **ptr, size_t bytes);
 // bl_graph_create with stream-ordered device memory when async_mem (nothing
 // in create or destroy then waits for other streams).
 int graph_create_ex(const bl_csr *csr, const bl_params *p, hipStream_t s, bool async_mem, bl_graph **out);
+// Replace g's CSR by another of the same n and nnz (host arrays, already
+// checked) and rebuild what the layout derives from it; the next run starts
+// with its prologue.
+int graph_reload_csr(bl_graph *g, const int32_t *rowptr, const int32_t *colidx);
 int fail_code(int code, const char *msg);
 // Host CSR checks: sizes, monotone rowptr, colidx in range; with `full` also
 // sorted rows, no self-loops or duplicates, symmetry.

@@ -8,7 +8,8 @@
 // graph and the coordinates on the host, runs one iteration of the resident
 // path (start_iter = k, so the step length is the run's own), and scatters the
 // coordinates back.  The relabelling is the reshuffling cost the paper notes;
-// it is O(n + m) host work and one graph upload per iteration.
+// it is O(n + m) host work and one CSR upload per iteration into one resident
+// device graph (what the layout derives from the CSR is rebuilt each time).
 //
 // pi_k is drawn with Durstenfeld's form of the Fisher-Yates shuffle, for
 // i = n-1 down to 1 swapping positions i and u mod (i+1), where u is the
@@ -87,6 +88,17 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
     bl_stats acc{};
     std::vector<double> es;
     int rc = BL_OK;
+    bl_graph *g = nullptr;   // the relabelled graph, resident across iterations
+    auto done = [&](int code) {
+        if (g) {
+            char saved[512];
+            std::strncpy(saved, bl_last_error(), sizeof saved - 1);
+            saved[sizeof saved - 1] = 0;
+            bl_graph_destroy(g);
+            if (code != BL_OK) set_error("%s", saved);
+        }
+        return code;
+    };
     for (int t = 0; t < p->iterations; ++t) {
         const int k = p->start_iter + t;
         draw_perm(seed, k, n, perm);
@@ -107,12 +119,23 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
             const int v = perm[c];
             for (int e = rp[v]; e < rp[v + 1]; ++e) ci2[cur[inv[ci[e]]]++] = c;
         }
-        const bl_csr g2{n, csr->nnz, rp2.data(), ci2.data()};
         q.start_iter = k;
         q.flags = p->flags & ~(uint32_t)BL_VALIDATE;   // the relabelled graph is valid if the input is
+        if (!g) {
+            const bl_csr g2{n, csr->nnz, rp2.data(), ci2.data()};
+            rc = bl_graph_create(&g2, &q, hip_stream, &g);
+            if (rc != BL_OK) return done(rc);
+        } else {
+            rc = graph_reload_csr(g, rp2.data(), ci2.data());
+            if (rc != BL_OK) return done(rc);
+        }
         bl_stats s1{};
-        rc = bl_layout(&g2, xs.data(), ys.data(), &q, hip_stream, xs.data(), ys.data(), nullptr, &s1);
-        if (rc != BL_OK && rc != BL_E_NONFINITE) return rc;
+        rc = bl_graph_set_coords(g, xs.data(), ys.data(), 0);
+        if (rc != BL_OK) return done(rc);
+        rc = bl_graph_run(g, 1, k, -1, nullptr, nullptr, nullptr, &s1);
+        if (rc != BL_OK && rc != BL_E_NONFINITE) return done(rc);
+        const int rc_get = bl_graph_get_coords(g, xs.data(), ys.data(), 0);
+        if (rc_get != BL_OK) return done(rc_get);
         for (int l = 0; l < n; ++l) {
             x[perm[l]] = xs[l];
             y[perm[l]] = ys[l];
@@ -132,5 +155,5 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
     std::memcpy(x_out, x.data(), 8 * (size_t)n);
     std::memcpy(y_out, y.data(), 8 * (size_t)n);
     if (st) *st = acc;
-    return rc;
+    return done(rc);
 }
