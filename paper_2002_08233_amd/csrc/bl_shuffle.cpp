@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "bl_internal.hpp"
@@ -46,6 +47,21 @@ void draw_perm(uint64_t seed, int64_t k, int n, std::vector<int32_t> &perm) {
         const int j = (int)(u % (uint64_t)(i + 1));
         std::swap(perm[i], perm[j]);
     }
+}
+
+// f(lo, hi) over [0, n) in contiguous parts on up to 16 host threads (one
+// when the work is small).
+template <typename F>
+void parallel_range(int64_t n, int64_t work, F f) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = work < (1 << 18) ? 1 : (int)std::min<unsigned>(16u, hw);
+    if (T == 1 || n < 2 * T) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) th.emplace_back(f, n * t / T, n * (t + 1) / T);
+    for (auto &x : th) x.join();
 }
 
 }  // namespace
@@ -81,7 +97,7 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
             return fail_code(BL_E_INVAL, "a start coordinate is not finite");
 
     std::vector<double> x(x0, x0 + n), y(y0, y0 + n), xs(n), ys(n);
-    std::vector<int32_t> perm, inv(n), rp2(n + 1), cur(n), ci2(std::max<int64_t>(csr->nnz, 1));
+    std::vector<int32_t> perm, inv(n), rp2(n + 1), ci2(std::max<int64_t>(csr->nnz, 1));
     bl_params q = *p;
     q.iterations = 1;
     q.conv_tol = 0.0;
@@ -103,22 +119,21 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
         const int k = p->start_iter + t;
         draw_perm(seed, k, n, perm);
         for (int l = 0; l < n; ++l) inv[perm[l]] = l;
-        // Row l of the relabelled graph is old row perm[l]; its entries are
-        // filled column by column in increasing new label, which leaves every
-        // row sorted with no sort (this reads the graph through its
-        // transpose, which is the graph itself: the CSR is symmetric).
+        // Row l of the relabelled graph is old row perm[l] with every
+        // neighbour u renamed inv[u], in increasing new label: each row is
+        // gathered and sorted on its own, rows in parallel.
         rp2[0] = 0;
-        for (int l = 0; l < n; ++l) {
-            const int v = perm[l];
-            rp2[l + 1] = rp2[l] + (rp[v + 1] - rp[v]);
-            cur[l] = rp2[l];
-            xs[l] = x[v];
-            ys[l] = y[v];
-        }
-        for (int c = 0; c < n; ++c) {
-            const int v = perm[c];
-            for (int e = rp[v]; e < rp[v + 1]; ++e) ci2[cur[inv[ci[e]]]++] = c;
-        }
+        for (int l = 0; l < n; ++l) rp2[l + 1] = rp2[l] + (rp[perm[l] + 1] - rp[perm[l]]);
+        parallel_range(n, csr->nnz, [&](int64_t l0, int64_t l1) {
+            for (int64_t l = l0; l < l1; ++l) {
+                const int v = perm[l];
+                int32_t *row = ci2.data() + rp2[l];
+                for (int e = rp[v]; e < rp[v + 1]; ++e) row[e - rp[v]] = inv[ci[e]];
+                std::sort(row, row + (rp[v + 1] - rp[v]));
+                xs[l] = x[v];
+                ys[l] = y[v];
+            }
+        });
         q.start_iter = k;
         q.flags = p->flags & ~(uint32_t)BL_VALIDATE;   // the relabelled graph is valid if the input is
         if (!g) {
@@ -136,10 +151,12 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
         if (rc != BL_OK && rc != BL_E_NONFINITE) return done(rc);
         const int rc_get = bl_graph_get_coords(g, xs.data(), ys.data(), 0);
         if (rc_get != BL_OK) return done(rc_get);
-        for (int l = 0; l < n; ++l) {
-            x[perm[l]] = xs[l];
-            y[perm[l]] = ys[l];
-        }
+        parallel_range(n, csr->nnz, [&](int64_t l0, int64_t l1) {
+            for (int64_t l = l0; l < l1; ++l) {
+                x[perm[l]] = xs[l];
+                y[perm[l]] = ys[l];
+            }
+        });
         acc.iters_run += s1.iters_run;
         acc.late_overflow = std::max(acc.late_overflow, s1.late_overflow);
         acc.seconds += s1.seconds;
