@@ -209,6 +209,100 @@ struct GView {
     __device__ __forceinline__ float2 *C(int par) const { return par ? accC[1] : accC[0]; }
 };
 
+// Order of the CSR terms of one row in one column batch.  Entries 0..15 are
+// added one after another, in entry order.  Entries 16.. (hub rows) are
+// dealt round a wave: "lane" l in [0, 64) sums the terms of entries
+// 16 + l, 16 + l + 64, 16 + l + 128, ... in that order, the 64 lane sums
+// meet in a balanced pairwise tree over the lanes in order ((l0 + l1) +
+// (l2 + l3)) + ..., and the tree's total is added last.  On a wave the tree
+// is four data-parallel-primitive exchanges inside each 16-lane row (pairs at
+// distance 1 and 2, then the row's half and whole mirror images, which pair
+// equal quads and equal octets) and the four row totals read into scalars;
+// the paths that take a row's entries one lane at a time evaluate the same
+// tree with lane_tree.
+template <typename T>
+struct Sum4 {
+    T ax, ay, lx, ly;
+};
+// The pairwise tree's total of leaf(0..63) (a 2-vector) evaluated by one
+// lane: a stack of one subtree per level pairs each finished subtree with its
+// left sibling.
+template <typename T2, typename F>
+__device__ __forceinline__ T2 lane_tree(const F &leaf) {
+    T2 stk[6];
+    T2 v{0, 0};
+    for (int i = 0; i < kWave; ++i) {
+        v = leaf(i);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int low = (1 << k) - 1;
+            if ((i & low) != low) continue;   // a lower level kept the subtree
+            if ((i >> k) & 1) {
+#pragma clang fp contract(off)
+                v = T2{stk[k].x + v.x, stk[k].y + v.y};
+            } else {
+                stk[k] = v;
+            }
+        }
+    }
+    return v;
+}
+
+// v + (v of the lane that DPP control CTRL selects), every lane active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_pair(float v) {
+    const int o = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false);
+    float r;
+    {
+#pragma clang fp contract(off)
+        r = v + __builtin_bit_cast(float, o);
+    }
+    return r;
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_pair(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const long long ob = ((long long)hi << 32) | (long long)(unsigned)lo;
+    double r;
+    {
+#pragma clang fp contract(off)
+        r = v + __builtin_bit_cast(double, ob);
+    }
+    return r;
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// The pairwise tree's total of the wave's 64 values (all lanes active; the
+// result is uniform).  quad_perm [1,0,3,2] and [2,3,0,1] pair lanes at
+// distance 1 and 2; once quads hold equal values the row half mirror pairs
+// quad 0 with quad 1 of each octet, and once octets do the row mirror pairs
+// the two octets of a row.  Each pair's two lanes add the same two values,
+// so they hold the same bits.
+template <typename T>
+__device__ __forceinline__ T wave_tree(T v) {
+    v = dpp_pair<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = dpp_pair<0x4E>(v);    // quad_perm [2,3,0,1]
+    v = dpp_pair<0x141>(v);   // row_half_mirror
+    v = dpp_pair<0x140>(v);   // row_mirror
+    const T r0 = lane_read(v, 0), r1 = lane_read(v, 16), r2 = lane_read(v, 32), r3 = lane_read(v, 48);
+    T t;
+    {
+#pragma clang fp contract(off)
+        t = (r0 + r1) + (r2 + r3);
+    }
+    return t;
+}
+
 // Contribution of column batch c = [c0, c1) to row i (all threads of the
 // workgroup call it; `active` rows compute).  `s` is the row's candidate
 // segment (its next unconsumed CSR run), `send` the row's segment end.  On
@@ -270,13 +364,45 @@ __device__ __forceinline__ void batch_contrib(const GView<T> &G, int c, bool act
 #pragma unroll
         for (int u = 0; u < kPre; ++u)
             if (u < cnt) one(pre[u]);
-        for (int u = kPre; u < cnt; u += 4) {
+        const int c16 = min(cnt, 16);
+        for (int u = kPre; u < c16; u += 4) {
             int jj[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) jj[v] = (u + v < cnt) ? G.colidx[sg.y + u + v] : 0;
+            for (int v = 0; v < 4; ++v) jj[v] = (u + v < c16) ? G.colidx[sg.y + u + v] : 0;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (u + v < cnt) one(jj[v]);
+                if (u + v < c16) one(jj[v]);
+        }
+        if (cnt > 16) {
+            // entries 16.., one lane's share at a time, in the lanes' tree
+            // (the attraction, then the literal repulsion in a second pass)
+            const int st = sg.y;
+            auto share = [&](bool rep_term) {
+                return lane_tree<T2>([&](int l) {
+                    T2 q{0, 0};
+                    for (int e = 16 + l; e < cnt; e += kWave) {
+                        const int j = G.colidx[st + e];
+                        const T2 pj = in_lds ? cols[j - c0] : T2{G.x[j], G.y[j]};
+                        T tx, ty;
+                        if (rep_term) EntryTerms::rep(xi, yi, pj, tx, ty);
+                        else EntryTerms::att(xi, yi, pj, tx, ty);
+                        {
+#pragma clang fp contract(off)
+                            q.x += tx;
+                            q.y += ty;
+                        }
+                    }
+                    return q;
+                });
+            };
+            const T2 ta = share(false);
+            ax += ta.x;
+            ay += ta.y;
+            if (G.literal) {
+                const T2 tl = share(true);
+                lx += tl.x;
+                ly += tl.y;
+            }
         }
     }
     const T rx = (P.x0 + P.x1) + (P.x2 + P.x3);
@@ -346,8 +472,9 @@ __device__ __forceinline__ void rows_block(const GView<T> &G, int first, int row
 // the lead lane's entry-order sum of the CSR segment make the bits those of
 // batch_contrib.  The column loop runs on a wave-uniform counter.  The
 // segment's first 16 entries are prefetched by the row's lanes halfway
-// through the first tile; longer segments (hub rows) are formed by all lanes
-// of the wave, one row at a time, and added by the lead lane in order.
+// through the first tile and added by the lead lane in entry order; entries
+// 16.. of longer segments (hub rows) are summed by all lanes of the wave, one
+// row at a time, in the lane-sum and pairwise-tree order defined above.
 // A coordinate that another workgroup of a running launch may have written:
 // an agent-scope load, coherent across the chip's L2 caches.
 template <typename T>
@@ -522,21 +649,20 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
         }
     }
     }
-    // entries 16.. of long segments (hub rows), one row at a time: every lane
-    // of the wave forms one entry's terms, the row's lead lane adds them in
-    // entry order
+    // entries 16.. of long segments (hub rows), one row at a time: lane l of
+    // the wave sums the terms of entries 16 + l + 64 g in order of g, the
+    // lane sums meet in the wave's pairwise tree, and the row's lead lane adds
+    // the total
     unsigned long long longm = __ballot(lead && cnt > 16);
     bool first_long = true;
-    // per-wave staging of one group's terms (at most 16 waves per workgroup)
-    __shared__ T2 s_att[16][kWave], s_lrep[16][kWave];
-    T2 *lt = s_att[threadIdx.x / kWave], *lu = s_lrep[threadIdx.x / kWave];
     while (longm) {
         const int src = __ffsll((long long)longm) - 1;
         longm &= longm - 1;
-        const int st = __shfl(sg.y, src, kWave), ct = __shfl(cnt, src, kWave);
-        const T rxi = __shfl(xi, src, kWave), ryi = __shfl(yi, src, kWave);
+        const int st = lane_read(sg.y, src), ct = lane_read(cnt, src);
+        const T rxi = lane_read(xi, src), ryi = lane_read(yi, src);
         const bool have = first_long && src == src0;
         first_long = false;
+        Sum4<T> q{0, 0, 0, 0};
         for (int b = 16; b < ct; b += 4 * kWave) {
             int jj[4];
 #pragma unroll
@@ -546,49 +672,35 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int e0 = b + kWave * k;
-                if (e0 >= ct) break;
-                const int e = e0 + lane;
-                const T2 pj = pos(e < ct ? jj[k] : c0);
-                T tx, ty, ux = 0, uy = 0;
-                ent_att<M>(G.ka, rxi, ryi, pj, tx, ty);
-                if (G.literal) ent_rep<M>(G.kr, rxi, ryi, pj, ux, uy);
-                const int mcount = min(kWave, ct - e0);
-                lt[lane] = T2{tx, ty};
-                if (G.literal) lu[lane] = T2{ux, uy};
-                __builtin_amdgcn_wave_barrier();
-                if (lane == src) {
-                    if (sizeof(T) == 4 && mcount == kWave) {
-                        // a full group (FP32): the 64 terms are read eight
-                        // at a time ahead of their additions (same order)
-#pragma unroll
-                        for (int u0 = 0; u0 < kWave; u0 += 8) {
-                            T2 v[8];
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) v[q] = lt[u0 + q];
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) {
-                                ax += v[q].x;
-                                ay += v[q].y;
-                            }
-                        }
-                    } else {
-                        for (int u = 0; u < mcount; ++u) {
-                            const T2 v = lt[u];
-                            ax += v.x;
-                            ay += v.y;
-                        }
-                    }
-                    if (G.literal) {
-                        for (int u = 0; u < mcount; ++u) {
-                            const T2 v = lu[u];
-                            lx += v.x;
-                            ly += v.y;
+                const int e = b + lane + kWave * k;
+                if (e < ct) {
+                    const T2 pj = pos(jj[k]);
+                    T tx, ty, ux = 0, uy = 0;
+                    ent_att<M>(G.ka, rxi, ryi, pj, tx, ty);
+                    if (G.literal) ent_rep<M>(G.kr, rxi, ryi, pj, ux, uy);
+                    {
+#pragma clang fp contract(off)
+                        q.ax += tx;
+                        q.ay += ty;
+                        if (G.literal) {
+                            q.lx += ux;
+                            q.ly += uy;
                         }
                     }
                 }
-                __builtin_amdgcn_wave_barrier();   // the next group overwrites the staging
             }
+        }
+        const T sx = wave_tree(q.ax), sy = wave_tree(q.ay);
+        T ux = 0, uy = 0;
+        if (G.literal) {
+            ux = wave_tree(q.lx);
+            uy = wave_tree(q.ly);
+        }
+        if (lane == src) {
+            ax += sx;
+            ay += sy;
+            lx += ux;
+            ly += uy;
         }
     }
     qx = G.invK * ax + G.negRK2 * (rx - lx);

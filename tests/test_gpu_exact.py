@@ -245,9 +245,9 @@ def test_persistent_wait_limit_reports_timeout(monkeypatch):
 @pytest.mark.parametrize("lit", [True, False])
 def test_hub_rows_one_workgroup_and_multi_workgroup_bitwise(precision, lit):
     """Rows with far more than 16 neighbours in one column batch take the
-    long-segment path (terms formed across the wave, added by the row's lead
-    lane in entry order); the one-workgroup kernel adds the same terms in the
-    same order one lane per row."""
+    long-segment path (entries 16.. dealt round the wave's 64 lanes, the lane
+    sums met in a pairwise tree of cross-lane exchanges); the one-workgroup
+    kernel evaluates the same tree one lane per row."""
     r = I.rng(91)
     n = 2000
     src = np.concatenate([np.zeros(900, np.int64), np.full(600, 7), r.integers(0, n, 3000)])
