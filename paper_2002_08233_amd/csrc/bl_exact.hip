@@ -1596,19 +1596,27 @@ struct ExactOps {
 };
 
 // CSR segments: per row, the runs of neighbours that fall in one column batch.
-__global__ void seg_count_kernel(int n, int BS, const int *__restrict__ rowptr, const int *__restrict__ colidx,
-                                 int *__restrict__ cnt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int c = 0, last = -1;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        const int b = colidx[e] / BS;
-        if (b != last) {
-            ++c;
-            last = b;
-        }
+// One wave per row (rows are sorted, so a run starts where the column batch
+// changes); lane l looks at entries rowptr[i] + l + 64 k, so a hub row costs
+// its length / 64 rounds.
+constexpr int kSegRowsPerBlock = 4;   // waves (rows) per 256-thread workgroup
+
+__device__ __forceinline__ bool seg_start(const int *__restrict__ colidx, int BS, int e0, int e) {
+    return e == e0 || colidx[e] / BS != colidx[e - 1] / BS;
+}
+
+__global__ __launch_bounds__(256) void seg_count_kernel(int n, int BS, const int *__restrict__ rowptr,
+                                                        const int *__restrict__ colidx, int *__restrict__ cnt) {
+    const int i = blockIdx.x * kSegRowsPerBlock + (int)(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (i >= n) return;   // the whole wave
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    int c = 0;
+    for (int b0 = e0; b0 < e1; b0 += kWave) {
+        const int e = b0 + lane;
+        c += __popcll(__ballot(e < e1 && seg_start(colidx, BS, e0, e)));
     }
-    cnt[i] = c;
+    if (lane == 0) cnt[i] = c;
 }
 
 // Exclusive scan of cnt[0..n) into off[0..n] by one workgroup of 1024.
@@ -1626,17 +1634,21 @@ __global__ __launch_bounds__(1024) void seg_scan_kernel(int n, const int *__rest
     if (threadIdx.x == 0) off[n] = base;
 }
 
-__global__ void seg_fill_kernel(int n, int BS, const int *__restrict__ rowptr, const int *__restrict__ colidx,
-                                const int *__restrict__ off, int2 *__restrict__ segs) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int s = off[i], last = -1;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        const int b = colidx[e] / BS;
-        if (b != last) {
-            segs[s++] = make_int2(b, e);
-            last = b;
-        }
+__global__ __launch_bounds__(256) void seg_fill_kernel(int n, int BS, const int *__restrict__ rowptr,
+                                                       const int *__restrict__ colidx, const int *__restrict__ off,
+                                                       int2 *__restrict__ segs) {
+    const int i = blockIdx.x * kSegRowsPerBlock + (int)(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (i >= n) return;   // the whole wave
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    const unsigned long long below = (1ull << lane) - 1;
+    int s = off[i];
+    for (int b0 = e0; b0 < e1; b0 += kWave) {
+        const int e = b0 + lane;
+        const bool start = e < e1 && seg_start(colidx, BS, e0, e);
+        const unsigned long long m = __ballot(start);
+        if (start) segs[s + __popcll(m & below)] = make_int2(colidx[e] / BS, e);
+        s += __popcll(m);
     }
 }
 
@@ -1749,7 +1761,7 @@ int exact_alloc(bl_graph *g) {
 int exact_prepare(bl_graph *g) {
     const size_t n = (size_t)g->n;
     const int BS = g->p.batch_size;
-    const int blocks = (g->n + 255) / 256;
+    const int blocks = (g->n + kSegRowsPerBlock - 1) / kSegRowsPerBlock;
     hipLaunchKernelGGL(seg_count_kernel, dim3(blocks), dim3(256), 0, g->stream, g->n, BS, g->rowptr, g->colidx,
                        g->ex.cursor);
     hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, g->stream, g->n, g->ex.cursor, g->ex.segoff);
