@@ -750,11 +750,18 @@ __device__ __forceinline__ void rows_blockL(const GView<T> &G, int first, int ro
     }
 }
 
+// Chunks of kRows rows; with `pair` (the run prologue, where chunk c sums the
+// batches from its own on, so the work falls with c) workgroup b takes chunk b
+// and chunk nblk - 1 - b, which evens out the workgroups' work.  A row's sums
+// do not depend on which workgroup forms them.
 template <typename T, bool KAHAN, int L, int M>
 __global__ __launch_bounds__(kRows * L) void rows_kernel(GView<T> G, int row0, int row1, int from_own, int p,
-                                                         int clear_other) {
+                                                         int clear_other, int nblk, int pair) {
     __shared__ typename V2<T>::type cols[kTile];
-    rows_blockL<T, KAHAN, L, M>(G, row0 + blockIdx.x * kRows, row1, from_own, p, clear_other, cols);
+    const int c = blockIdx.x;
+    rows_blockL<T, KAHAN, L, M>(G, row0 + c * kRows, row1, from_own, p, clear_other, cols);
+    if (pair && nblk - 1 - c > c)
+        rows_blockL<T, KAHAN, L, M>(G, row0 + (nblk - 1 - c) * kRows, row1, from_own, p, clear_other, cols);
 }
 
 // The panel of column batch c for the rows [first, first + blockDim): rows of
@@ -1420,19 +1427,21 @@ struct ExactOps {
 
     static int rows(bl_graph *g, int row0, int row1, int from_own, int parity, int clear_other) {
         if (row1 <= row0) return BL_OK;
-        const int blocks = (row1 - row0 + kRows - 1) / kRows;
+        const int nblk = (row1 - row0 + kRows - 1) / kRows;
+        const int pair = from_own ? 1 : 0;
+        const int blocks = pair ? (nblk + 1) / 2 : nblk;
         int slot;
         BL_TRY(prof_begin(g, PK_ROWS, &slot));
         const int L = lanes(g, row1 - row0);
         if (L == 1)
             hipLaunchKernelGGL((rows_kernel<T, KAHAN, 1, M>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), row0,
-                               row1, from_own, parity, clear_other);
+                               row1, from_own, parity, clear_other, nblk, pair);
         else if (L == 2)
             hipLaunchKernelGGL((rows_kernel<T, KAHAN, 2, M>), dim3(blocks), dim3(kRows * 2), 0, g->stream, view(g),
-                               row0, row1, from_own, parity, clear_other);
+                               row0, row1, from_own, parity, clear_other, nblk, pair);
         else
             hipLaunchKernelGGL((rows_kernel<T, KAHAN, 4, M>), dim3(blocks), dim3(kRows * 4), 0, g->stream, view(g),
-                               row0, row1, from_own, parity, clear_other);
+                               row0, row1, from_own, parity, clear_other, nblk, pair);
         BL_HIP(hipGetLastError());
         return prof_end(g, slot);
     }
