@@ -79,11 +79,10 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
     BL_TRY(check_csr(csr, p->flags, (hipStream_t)hip_stream));
     const int n = csr->n;
     const int32_t *rp = csr->rowptr, *ci = csr->colidx;
-    // The relabelling below reads the graph through its transpose and sizes
-    // each relabelled row by the old row's length.  That is the graph itself
-    // only for a symmetric CSR (BL_VALIDATE checks it in full); whatever the
-    // flags, every vertex's in-degree must equal its row length, so that the
-    // relabelled rows are filled exactly and never overrun.
+    // The method lays out undirected graphs, stored as symmetric CSRs
+    // (BL_VALIDATE checks that in full).  Whatever the flags, a CSR whose
+    // in-degrees differ from its row lengths is rejected here, as the batch
+    // randomisation has always done.
     {
         std::vector<int64_t> indeg(n, 0);
         for (int64_t e = 0; e < csr->nnz; ++e) ++indeg[ci[e]];
