@@ -510,16 +510,20 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
     int big[4] = {0, 0, 0, 0};     // entries 16.. of the wave's first long segment
     int cnt = 0, st0 = 0, ct0 = 0, src0 = -1;
     used = false;
-    // columns [4 k0, 4 k1) of the staged tile; column 4k + h + L t -> sum t
+    // columns [4 k0, 4 k1) of the staged tile; column 4k + h + L t -> sum t.
+    // UG groups per loop round give every lane eight pairs a round at any L.
+    constexpr int UG = 2 * L;
     auto group_range = [&](int k0, int k1) {
         int k = k0;
-        for (; k + 2 <= k1; k += 2) {
+        for (; k + UG <= k1; k += UG) {
 #pragma unroll
-            for (int t = 0; t < A; ++t) rep_pair<M>(G.kr, xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
+            for (int u = 0; u < UG; ++u) {
 #pragma unroll
-            for (int t = 0; t < A; ++t) rep_pair<M>(G.kr, xi, yi, cols[4 * k + 4 + h + L * t], px[t], py[t]);
+                for (int t = 0; t < A; ++t)
+                    rep_pair<M>(G.kr, xi, yi, cols[4 * (k + u) + h + L * t], px[t], py[t]);
+            }
         }
-        if (k < k1) {
+        for (; k < k1; ++k) {
 #pragma unroll
             for (int t = 0; t < A; ++t) rep_pair<M>(G.kr, xi, yi, cols[4 * k + h + L * t], px[t], py[t]);
         }
