@@ -48,6 +48,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;     // 2048 keys per tile
 constexpr int kScanThreads = 1024;
+// Up to this many sort tiles per job, each radix scatter workgroup forms its
+// digit offsets from the raw histogram itself (256 x tiles reads), with no
+// scan launch in between.
+constexpr int kFuseTiles = 128;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 values per tile
 constexpr int kChainThreads = 1024;
@@ -316,6 +320,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(BH_KERNEL_ARGS
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(BH_KERNEL_ARGS, int pass) {
     BH_JOB();
     __shared__ int cnt[4][256];
+    __shared__ int s_ws[kSortThreads / kWave];
     gptr<const unsigned> kin = (pass & 1) ? J.key1 : J.key0;
     gptr<const int> vin = (pass & 1) ? J.val1 : J.val0;
     gptr<unsigned> kout = (pass & 1) ? J.key0 : J.key1;
@@ -343,11 +348,25 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(BH_KERNEL_A
         if (valid && (__ffsll((long long)m) - 1) == lane) cnt[w][d] += __popcll(m);
     }
     __syncthreads();
-    // per-wave starting offsets: tile base from the scanned histogram, then
-    // earlier waves of this tile
+    // per-wave starting offsets: the tile's base for digit d (keys of lower
+    // digits in every tile, then of digit d in earlier tiles), then earlier
+    // waves of this tile
     {
         const int d = threadIdx.x;
-        int run = J.hist[d * tiles + jb.local];
+        int run;
+        if (tiles <= kFuseTiles) {   // the raw histogram (job-uniform branch)
+            int before = 0, all = 0;
+#pragma unroll 8
+            for (int t = 0; t < tiles; ++t) {
+                const int c = J.hist[d * tiles + t];
+                all += c;
+                before += t < jb.local ? c : 0;
+            }
+            int tot;
+            run = block_excl_scan(all, s_ws, &tot) + before;
+        } else {   // scanned in place by scan_single_kernel
+            run = J.hist[d * tiles + jb.local];
+        }
         for (int q = 0; q < 4; ++q) {
             const int c = cnt[q][d];
             cnt[q][d] = run;
@@ -398,7 +417,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_single_kernel(BH_KERNEL_ARG
             running += total;
         }
     };
-    if (which == 0) scan(J.hist, 256 * J.tiles);
+    if (which == 0) {
+        if (J.tiles > kFuseTiles) scan(J.hist, 256 * J.tiles);   // else the scatter reads it raw
+    }
     else if (which == 1) scan(J.scan_part, J.sblocks);
     else if (which == 2) scan(J.bbase, J.nb + 1);
     else {
@@ -2012,6 +2033,7 @@ struct BHEngine {
     bool ev_used[2] = {false, false};
     int total[PT_COUNT] = {};
     int nkind[2] = {0, 0};              // jobs of the (2, -1) model, jobs of other (a, r) models
+    int sort_scans = 0;                 // jobs with more than kFuseTiles sort tiles
     size_t lds_bytes = 0;               // dynamic LDS of the chain launch
     hipGraph_t graph = nullptr;         // one captured iteration of the current set
     hipGraphExec_t exec = nullptr;
@@ -2201,9 +2223,11 @@ int bh_engine_set(BHEngine *e, const BHJob *jobs, int G) {
     }
     e->lds_bytes = sizeof(HelperShared);
     e->nkind[0] = e->nkind[1] = 0;
+    e->sort_scans = 0;
     for (int j = 0; j < G; ++j) {
         const BHJob &J = jobs[j];
         ++e->nkind[J.general ? 1 : 0];
+        if (J.tiles > kFuseTiles) ++e->sort_scans;
         e->lds_bytes = std::max(e->lds_bytes, chain_lds_bytes((size_t)J.BS * (J.all_live ? 0 : J.lag + 1)));
     }
     BL_HIP(hipMemcpyAsync(e->d_jobs[s], e->h_jobs[s], sizeof(BHJob) * G, hipMemcpyHostToDevice, e->stream));
@@ -2252,7 +2276,7 @@ int bh_engine_iteration(BHEngine *e, bl_graph *prof) {
     BH_LAUNCH(morton_kernel, PT_VERT, 256);
     for (int pass = 0; pass < 4; ++pass) {
         BH_LAUNCH(radix_hist_kernel, PT_SORT, kSortThreads, pass);
-        BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 0);
+        if (e->sort_scans) BH_LAUNCH(scan_single_kernel, PT_ONE, kScanThreads, 0);
         BH_LAUNCH(radix_scatter_kernel, PT_SORT, kSortThreads, pass);
     }
     BH_LAUNCH(mark_kernel, PT_MARK, 256);
