@@ -1436,7 +1436,8 @@ struct ExactOps {
         const int blocks = pair ? (nblk + 1) / 2 : nblk;
         int slot;
         BL_TRY(prof_begin(g, PK_ROWS, &slot));
-        const int L = lanes(g, row1 - row0);
+        // paired chunks: half as many workgroups hold the rows at a time
+        const int L = lanes(g, pair ? blocks * kRows : row1 - row0);
         if (L == 1)
             hipLaunchKernelGGL((rows_kernel<T, KAHAN, 1, M>), dim3(blocks), dim3(kRows), 0, g->stream, view(g), row0,
                                row1, from_own, parity, clear_other, nblk, pair);
