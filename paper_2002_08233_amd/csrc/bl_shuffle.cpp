@@ -96,7 +96,17 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
             return fail_code(BL_E_INVAL, "a start coordinate is not finite");
 
     std::vector<double> x(x0, x0 + n), y(y0, y0 + n), xs(n), ys(n);
-    std::vector<int32_t> perm, inv(n), rp2(n + 1), ci2(std::max<int64_t>(csr->nnz, 1));
+    std::vector<int32_t> perm, inv(n), rp2(n + 1), ci2;
+    // the relabelled column ids, uploaded every iteration: pinned host memory
+    // when it can be had (the copy then goes straight to DMA), else pageable
+    const size_t ci_bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(csr->nnz, 1);
+    int32_t *ci_pin = nullptr;
+    if (hipHostMalloc((void **)&ci_pin, ci_bytes, hipHostMallocDefault) != hipSuccess) {
+        ci_pin = nullptr;
+        (void)hipGetLastError();
+        ci2.resize((size_t)std::max<int64_t>(csr->nnz, 1));
+    }
+    int32_t *const ci_out = ci_pin ? ci_pin : ci2.data();
     bl_params q = *p;
     q.iterations = 1;
     q.conv_tol = 0.0;
@@ -112,6 +122,7 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
             bl_graph_destroy(g);
             if (code != BL_OK) set_error("%s", saved);
         }
+        if (ci_pin) (void)hipHostFree(ci_pin);   // every copy from it has completed
         return code;
     };
     for (int t = 0; t < p->iterations; ++t) {
@@ -126,7 +137,7 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
         parallel_range(n, csr->nnz, [&](int64_t l0, int64_t l1) {
             for (int64_t l = l0; l < l1; ++l) {
                 const int v = perm[l];
-                int32_t *row = ci2.data() + rp2[l];
+                int32_t *row = ci_out + rp2[l];
                 for (int e = rp[v]; e < rp[v + 1]; ++e) row[e - rp[v]] = inv[ci[e]];
                 std::sort(row, row + (rp[v + 1] - rp[v]));
                 xs[l] = x[v];
@@ -136,11 +147,11 @@ int bl_layout_shuffled(const bl_csr *csr, const double *x0, const double *y0, co
         q.start_iter = k;
         q.flags = p->flags & ~(uint32_t)BL_VALIDATE;   // the relabelled graph is valid if the input is
         if (!g) {
-            const bl_csr g2{n, csr->nnz, rp2.data(), ci2.data()};
+            const bl_csr g2{n, csr->nnz, rp2.data(), ci_out};
             rc = bl_graph_create(&g2, &q, hip_stream, &g);
             if (rc != BL_OK) return done(rc);
         } else {
-            rc = graph_reload_csr(g, rp2.data(), ci2.data());
+            rc = graph_reload_csr(g, rp2.data(), ci_out);
             if (rc != BL_OK) return done(rc);
         }
         bl_stats s1{};
