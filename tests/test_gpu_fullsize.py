@@ -116,3 +116,21 @@ def test_rgg64k_precision_stress(rgg64k, precision):
     assert r["ok"], r
     if precision == "fp64":
         assert r["normwise"] < 1e-10
+
+
+@pytest.mark.parametrize("b", [0, 1000, 1171])
+def test_sort_above_fused_tile_limit_one_shot(b):
+    """300,000 vertices (a 600 x 500 grid, random start) is above 128 sort
+    tiles of 2048 keys, where the radix scatter reads scanned histogram
+    offsets instead of forming them from the raw counts: one-shot forces of
+    the first, a middle and the last (ragged) batch against the oracle's walk
+    of its own tree, theta 1.2."""
+    g = I.grid(600, 500)
+    x0, y0 = I.uniform_coords(g.n, 23)
+    x0, y0 = I.to_f32_representable(x0), I.to_f32_representable(y0)
+    assert g.n > 128 * 2048
+    p = api.params(batch_size=256, iterations=1, mode="bh", theta=1.2)
+    fx, fy = api.forces(g, x0, y0, b, p)
+    ref = oracle.forces_bh(g.rowptr, g.colidx, x0, y0, oracle.Tree(x0, y0), b * 256, min(b * 256 + 256, g.n),
+                           theta=1.2)
+    assert_forces(fx, fy, ref, mask=bh_mask(ref), what="grid 600x500 one-shot batch %d" % b)
