@@ -22,7 +22,9 @@
 // bitwise).  Per row and column batch: the repulsion of the batch's columns
 // in four interleaved partial sums (column q to sum q mod 4, ascending), the
 // attraction (and, in literal mode, the neighbour repulsion) of the row's
-// CSR entries inside the batch in entry order, combined into one partial,
+// CSR entries inside the batch in a fixed order (four round-robin partials
+// for entries 0..15, a pairwise tree over 64 lane sums for the rest),
+// combined into one partial,
 // then one compensated (Kahan) add into the row's sum.  Energy: per batch,
 // each kRows-row chunk (aligned to absolute row ids) is summed by wave
 // butterflies and then its wave sums in order; the chunk sums are added in
@@ -92,7 +94,7 @@ __device__ __forceinline__ void rep_term(double xi, double yi, double2 pj, doubl
 }
 
 // One CSR entry's terms, each rounded on its own so that they can be formed
-// in any lane and then added in entry order: the attraction d * (c_j - c_i)
+// in any lane and then added in the fixed order: the attraction d * (c_j - c_i)
 // without its factor 1/K (Sec. 2.2 with a = 2: magnitude d^2 / K along the
 // unit vector), and the repulsion kernel (c_j - c_i) / d^2 that literal mode
 // takes back out for a neighbour.
@@ -209,8 +211,9 @@ struct GView {
     __device__ __forceinline__ float2 *C(int par) const { return par ? accC[1] : accC[0]; }
 };
 
-// Order of the CSR terms of one row in one column batch.  Entries 0..15 are
-// added one after another, in entry order.  Entries 16.. (hub rows) are
+// Order of the CSR terms of one row in one column batch.  Entry u of 0..15
+// goes to partial u % 4; each partial adds its entries in order and the four
+// meet as (V0 + V1) + (V2 + V3).  Entries 16.. (hub rows) are
 // dealt round a wave: "lane" l in [0, 64) sums the terms of entries
 // 16 + l, 16 + l + 64, 16 + l + 128, ... in that order, the 64 lane sums
 // meet in a balanced pairwise tree over the lanes in order ((l0 + l1) +
@@ -349,21 +352,26 @@ __device__ __forceinline__ void batch_contrib(const GView<T> &G, int c, bool act
     T ax = 0, ay = 0, lx = 0, ly = 0;
     if (active && cnt > 0) {
         const bool in_lds = (c1 - c0) <= kTile;   // the whole batch is staged
-        auto one = [&](int j) {
+        // entries 0..15: entry u into partial u % 4, met as (V0 + V1) + (V2 + V3)
+        Sum4<T> V[4] = {};
+        auto one = [&](int j, int t) {
             const T2 pj = in_lds ? cols[j - c0] : T2{G.x[j], G.y[j]};
-            T tx, ty;
+            T tx, ty, ux = 0, uy = 0;
             EntryTerms::att(xi, yi, pj, tx, ty);
-            ax += tx;
-            ay += ty;
-            if (G.literal) {
-                EntryTerms::rep(xi, yi, pj, tx, ty);
-                lx += tx;
-                ly += ty;
+            if (G.literal) EntryTerms::rep(xi, yi, pj, ux, uy);
+            {
+#pragma clang fp contract(off)
+                V[t].ax += tx;
+                V[t].ay += ty;
+                if (G.literal) {
+                    V[t].lx += ux;
+                    V[t].ly += uy;
+                }
             }
         };
 #pragma unroll
         for (int u = 0; u < kPre; ++u)
-            if (u < cnt) one(pre[u]);
+            if (u < cnt) one(pre[u], u & 3);
         const int c16 = min(cnt, 16);
         for (int u = kPre; u < c16; u += 4) {
             int jj[4];
@@ -371,7 +379,14 @@ __device__ __forceinline__ void batch_contrib(const GView<T> &G, int c, bool act
             for (int v = 0; v < 4; ++v) jj[v] = (u + v < c16) ? G.colidx[sg.y + u + v] : 0;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (u + v < c16) one(jj[v]);
+                if (u + v < c16) one(jj[v], v);   // u is a multiple of 4
+        }
+        {
+#pragma clang fp contract(off)
+            ax = (V[0].ax + V[1].ax) + (V[2].ax + V[3].ax);
+            ay = (V[0].ay + V[1].ay) + (V[2].ay + V[3].ay);
+            lx = (V[0].lx + V[1].lx) + (V[2].lx + V[3].lx);
+            ly = (V[0].ly + V[1].ly) + (V[2].ly + V[3].ly);
         }
         if (cnt > 16) {
             // entries 16.., one lane's share at a time, in the lanes' tree
@@ -469,10 +484,10 @@ __device__ __forceinline__ void rows_block(const GView<T> &G, int first, int row
 // The same contribution with L lanes per row (L = 1, 2 or 4 consecutive
 // lanes; lane h holds the partial sums m = h, h + L, ... and the lead lane
 // h = 0 gets the combined partial).  The combine (P0 + P1) + (P2 + P3) and
-// the lead lane's entry-order sum of the CSR segment make the bits those of
+// the CSR segment's order defined above make the bits those of
 // batch_contrib.  The column loop runs on a wave-uniform counter.  The
 // segment's first 16 entries are prefetched by the row's lanes halfway
-// through the first tile and added by the lead lane in entry order; entries
+// through the first tile and summed in the four round-robin partials; entries
 // 16.. of longer segments (hub rows) are summed by all lanes of the wave, one
 // row at a time, in the lane-sum and pairwise-tree order defined above.
 // A coordinate that another workgroup of a running launch may have written:
@@ -592,66 +607,57 @@ __device__ __forceinline__ void batch_contribL(const GView<T> &G, int c, bool ac
         else return T2{G.x[j], G.y[j]};
     };
     // entries 0..15, held by the row's lanes (entry u in lane u % L, slot
-    // u / L).  FP32: four entries per round, each lane forms the terms of its
-    // own entries of the round, then the lead lane adds them in entry order.
-    // FP64 (whose registers this would cost occupancy): the lead lane forms
-    // and adds each entry's terms in turn.  Both add in entry order.
-    const int base_lane = lane & ~(L - 1);
-    constexpr int KB = 4 / L;   // slots per round
-    if constexpr (sizeof(T) == 4) {
+    // u / L): entry u goes to partial u % 4, which lane h = u % L holds as its
+    // partial t = (u / L) % A, as the repulsion's partials are held.  Each
+    // partial adds its entries in order; the partials meet as (V0 + V1) +
+    // (V2 + V3) by the repulsion's combine.
+    Sum4<T> V[A];
 #pragma unroll
-    for (int k0 = 0; k0 < NP; k0 += KB) {
+    for (int t = 0; t < A; ++t) V[t] = Sum4<T>{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < NP; k0 += A) {
         if (!__ballot(lead && L * k0 < cnt)) break;
-        T tax[KB], tay[KB], tlx[KB], tly[KB];
 #pragma unroll
-        for (int q = 0; q < KB; ++q) {
-            tax[q] = tay[q] = tlx[q] = tly[q] = 0;
+        for (int q = 0; q < A; ++q) {
             if (h + L * (k0 + q) < cnt) {
                 const T2 pj = pos(pre[k0 + q]);
-                ent_att<M>(G.ka, xi, yi, pj, tax[q], tay[q]);
-                if (G.literal) ent_rep<M>(G.kr, xi, yi, pj, tlx[q], tly[q]);
-            }
-        }
-#pragma unroll
-        for (int u = L * k0; u < L * (k0 + KB); ++u) {
-            const int q = u / L - k0;
-            T vx = tax[q], vy = tay[q], wx = tlx[q], wy = tly[q];
-            if constexpr (L > 1) {
-                vx = __shfl(vx, base_lane + (u % L), kWave);
-                vy = __shfl(vy, base_lane + (u % L), kWave);
-                if (G.literal) {
-                    wx = __shfl(wx, base_lane + (u % L), kWave);
-                    wy = __shfl(wy, base_lane + (u % L), kWave);
-                }
-            }
-            if (lead && u < cnt) {
-                ax += vx;
-                ay += vy;
-                if (G.literal) {
-                    lx += wx;
-                    ly += wy;
+                T tx, ty, ux = 0, uy = 0;
+                ent_att<M>(G.ka, xi, yi, pj, tx, ty);
+                if (G.literal) ent_rep<M>(G.kr, xi, yi, pj, ux, uy);
+                {
+#pragma clang fp contract(off)
+                    V[q].ax += tx;
+                    V[q].ay += ty;
+                    if (G.literal) {
+                        V[q].lx += ux;
+                        V[q].ly += uy;
+                    }
                 }
             }
         }
     }
-    } else {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        if (!__ballot(lead && u < cnt)) break;
-        const int j = (L == 1) ? pre[u] : __shfl(pre[u / L], base_lane + (u % L), kWave);
-        if (lead && u < cnt) {
-            T tx, ty;
-            const T2 pj = pos(j);
-            ent_att<M>(G.ka, xi, yi, pj, tx, ty);
-            ax += tx;
-            ay += ty;
-            if (G.literal) {
-                ent_rep<M>(G.kr, xi, yi, pj, tx, ty);
-                lx += tx;
-                ly += ty;
+    auto meet = [&](auto get) -> T {
+        T r;
+        {
+#pragma clang fp contract(off)
+            if constexpr (L == 1) {
+                r = (get(V[0]) + get(V[1])) + (get(V[2]) + get(V[3]));
+            } else if constexpr (L == 2) {
+                const T a0 = get(V[0]) + __shfl_xor(get(V[0]), 1, kWave);
+                const T a1 = get(V[1]) + __shfl_xor(get(V[1]), 1, kWave);
+                r = a0 + a1;
+            } else {
+                r = get(V[0]) + __shfl_xor(get(V[0]), 1, kWave);
+                r += __shfl_xor(r, 2, kWave);
             }
         }
-    }
+        return r;
+    };
+    ax = meet([](const Sum4<T> &v) { return v.ax; });
+    ay = meet([](const Sum4<T> &v) { return v.ay; });
+    if (G.literal) {
+        lx = meet([](const Sum4<T> &v) { return v.lx; });
+        ly = meet([](const Sum4<T> &v) { return v.ly; });
     }
     // entries 16.. of long segments (hub rows), one row at a time: lane l of
     // the wave sums the terms of entries 16 + l + 64 g in order of g, the
