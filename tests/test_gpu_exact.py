@@ -152,9 +152,11 @@ def test_device_pointer_path(grid32):
 
 @pytest.mark.parametrize("precision", ["fp32_kahan", "fp32", "fp64"])
 @pytest.mark.parametrize("n,bs,lit", [(1024, 128, True), (700, 96, False), (300, 512, True), (257, 256, True)])
-def test_one_workgroup_and_multi_workgroup_paths_agree_bitwise(precision, n, bs, lit):
-    """Small graphs run in one workgroup unless forced onto the step kernels;
-    both compute the same bits (energies, coordinates), resumed or not."""
+def test_one_workgroup_and_multi_workgroup_paths_agree_bitwise(monkeypatch, precision, n, bs, lit):
+    """The one-workgroup kernel (forced with BL_EXACT_ONE_WG=1 above its
+    default size) and the step kernels compute the same bits (energies,
+    coordinates), resumed or not."""
+    monkeypatch.setenv("BL_EXACT_ONE_WG", "1")
     g = I.grid(32, 32) if n == 1024 else _rand_graph(n, 8.0 / n, n + 3)
     x0, y0 = I.uniform_coords(g.n, 12)
     x0, y0 = _f32(x0), _f32(y0)
@@ -243,11 +245,12 @@ def test_persistent_wait_limit_reports_timeout(monkeypatch):
 
 @pytest.mark.parametrize("precision", ["fp32_kahan", "fp64"])
 @pytest.mark.parametrize("lit", [True, False])
-def test_hub_rows_one_workgroup_and_multi_workgroup_bitwise(precision, lit):
+def test_hub_rows_one_workgroup_and_multi_workgroup_bitwise(monkeypatch, precision, lit):
     """Rows with far more than 16 neighbours in one column batch take the
     long-segment path (entries 16.. dealt round the wave's 64 lanes, the lane
     sums met in a pairwise tree of cross-lane exchanges); the one-workgroup
     kernel evaluates the same tree one lane per row."""
+    monkeypatch.setenv("BL_EXACT_ONE_WG", "1")
     r = I.rng(91)
     n = 2000
     src = np.concatenate([np.zeros(900, np.int64), np.full(600, 7), r.integers(0, n, 3000)])
@@ -271,6 +274,8 @@ def test_energy_stopping_rule(monkeypatch, path):
     x0, y0 = I.uniform_coords(g.n, 78)
     x0, y0 = _f32(x0), _f32(y0)
     multi = path != "one_workgroup"
+    if path == "one_workgroup":
+        monkeypatch.setenv("BL_EXACT_ONE_WG", "1")
     if path == "stepwise":
         monkeypatch.setenv("BL_EXACT_STEPWISE", "1")
     kw = dict(batch_size=128, step0=0.05, step_decay=0.97, multi_wg=multi)
