@@ -71,7 +71,7 @@ constexpr int kPre = 4;        // CSR entries of a row prefetched per column bat
 // Graphs with n * BS up to this many pairs per step run alone in the
 // one-workgroup kernel: one compute unit finishes such a step faster than
 // a chain of full-chip launches.
-constexpr long long kOneWGPairs = 1LL << 15;      // pairs per step up to which a graph runs in one workgroup
+constexpr long long kOneWGPairs = 3LL << 13;      // pairs per step up to which a graph runs in one workgroup
 constexpr long long kOneWGMaxPairs = 1LL << 18;   // ... and up to which BL_EXACT_ONE_WG=1 may force it
 
 // Repulsion kernel term without its constant factor -R K^2:
@@ -1811,9 +1811,10 @@ size_t exact_footprint(int n, int64_t nnz, int BS, bool fp64) {
 
 // Small graphs run in the one-workgroup kernel (one workgroup per graph); it
 // computes the same bits as the multi-workgroup kernels.  One compute unit
-// forms a step's n * BS pairs, so above a few tens of thousands of pairs the
-// persistent multi-workgroup run is faster (grid32, 131072 pairs per step:
-// 0.042 against 0.082 ms per iteration); BL_EXACT_ONE_WG=1 forces it up to
+// forms a step's n * BS pairs, so from about 24576 pairs on the persistent
+// multi-workgroup run is faster (16384 pairs: 0.022 against 0.025 ms per
+// iteration in one workgroup; 32768: 0.013 against 0.016; grid32, 131072:
+// 0.042 against 0.082); BL_EXACT_ONE_WG=1 forces it up to
 // kOneWGMaxPairs (tests of the kernel, measurements).
 // It runs the (2, -1) model only; other (a, r) models take the multi-workgroup path.
 static bool use_one_wg(const bl_graph *g, int stop_batch) {
