@@ -62,8 +62,10 @@ extern "C" {
 #define BL_BH_SNAPSHOT_LEAVES 4u  /* BH leaves use the per-iteration snapshot
                                      instead of live coordinates                */
 #define BL_EXACT_MULTI_WG     8u  /* exact mode: always use the multi-workgroup
-                                     step kernels (small graphs otherwise run in
-                                     one workgroup); the result is the same bits */
+                                     step kernels (graphs of at most 24,576
+                                     pairs per step, n * batch_size, otherwise
+                                     run in one workgroup); the result is the
+                                     same bits                                   */
 #define BL_ADAPTIVE_STEP     16u  /* bl_layout only: the adaptive step of Hu
                                      (2005), cited in Sec. 4.3.5, replaces the
                                      fixed decay (see bl_layout)                */
